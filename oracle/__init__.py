@@ -1,0 +1,188 @@
+"""CPU oracle of the Segment Linking hot path -- TEST INFRASTRUCTURE.
+
+Plain, slow C (``lst_oracle.c`` + ``cuts.inc``) loaded through ctypes.  Only the
+test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package; the HIP library never does, and the two
+share no code.  Inputs are the synthetic geometry, hits and the primary
+parameter vector; every derived constant, the module map and every cut value
+is computed here independently.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = [os.path.join(_HERE, f) for f in ("lst_oracle.c", "cuts.inc", "lst_oracle.h")]
+
+# primary parameter vector (same order as ORC_P_* in lst_oracle.h)
+PARAM_NAMES = ("bfield", "ptmin", "z0max", "sigu", "sigv", "nsig", "epsk", "epsa", "d0max",
+               "xrphi", "xrz", "w", "map_dphi", "map_dl")
+N_PARAMS = len(PARAM_NAMES)
+MD, SEG, T3, T5, T5_KEPT = 0, 1, 2, 3, 4
+WIDTH = {MD: 2, SEG: 4, T3: 6, T5: 10, T5_KEPT: 10}
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (FP32 strict: no contraction, no fast-math)."""
+    if force or not os.path.exists(_SO):
+        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-o", _SO, os.path.join(_HERE, "lst_oracle.c"), "-lm"]
+        subprocess.run(cmd, check=True)
+    return _SO
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build()
+    lib = ctypes.CDLL(_SO)
+    P = ctypes.c_void_p
+    lib.orc_create.restype = P
+    lib.orc_create.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P]
+    lib.orc_destroy.argtypes = [P]
+    lib.orc_map_edges.restype = ctypes.c_int64
+    lib.orc_map_edges.argtypes = [P]
+    lib.orc_map.argtypes = [P, P, P]
+    lib.orc_run.restype = ctypes.c_int
+    lib.orc_run.argtypes = [P, ctypes.c_int32, P, P, P, P, P]
+    lib.orc_count.restype = ctypes.c_int64
+    lib.orc_count.argtypes = [P, ctypes.c_int]
+    lib.orc_tuples.argtypes = [P, ctypes.c_int, P]
+    lib.orc_cands.argtypes = [P, P]
+    lib.orc_t5_scores.argtypes = [P, P]
+    lib.orc_t5_keep.argtypes = [P, P]
+    lib.orc_t3_curv.argtypes = [P, P]
+    lib.orc_near_count.restype = ctypes.c_int64
+    lib.orc_near_count.argtypes = [P, ctypes.c_int]
+    lib.orc_near.argtypes = [P, ctypes.c_int, P, P, P]
+    for f in ("orc_eval_md",):
+        getattr(lib, f).restype = ctypes.c_int
+        getattr(lib, f).argtypes = [P, ctypes.c_int, P, P, P]
+    for f in ("orc_eval_seg", "orc_eval_t3", "orc_eval_t5"):
+        getattr(lib, f).restype = ctypes.c_int
+        getattr(lib, f).argtypes = [P, P, P, P]
+    lib.orc_consts.argtypes = [P, P]
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass
+class Result:
+    tuples: dict            # kind -> int32 [n, width]
+    t5_scores: np.ndarray
+    t5_keep: np.ndarray
+    t3_curv: np.ndarray
+    cands: np.ndarray       # int64 [4]
+    near: dict              # kind -> (tuples, margins, decisions)
+
+
+class Oracle:
+    """One geometry + parameter set; ``run(event)`` evaluates one event."""
+
+    def __init__(self, params: np.ndarray, geo_f32: np.ndarray, geo_i32: np.ndarray):
+        lib = _load()
+        self._params = np.ascontiguousarray(params, dtype=np.float64)
+        self._f32 = np.ascontiguousarray(geo_f32, dtype=np.float32)
+        self._i32 = np.ascontiguousarray(geo_i32, dtype=np.int32)
+        self.n_mod = int(self._f32.shape[1])
+        h = lib.orc_create(_ptr(self._params), len(self._params), self.n_mod,
+                           _ptr(self._f32), _ptr(self._i32))
+        if not h:
+            raise ValueError("oracle: bad geometry or parameters")
+        self._h = ctypes.c_void_p(h)
+        self._lib = lib
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and self._lib is not None:
+            self._lib.orc_destroy(self._h)
+            self._h = None
+
+    def module_map(self):
+        n_e = self._lib.orc_map_edges(self._h)
+        ptr = np.zeros(self.n_mod + 1, np.int32)
+        col = np.zeros(max(n_e, 1), np.int32)
+        self._lib.orc_map(self._h, _ptr(ptr), _ptr(col))
+        return ptr, col[:n_e]
+
+    def consts(self):
+        out = np.zeros(7, np.float32)
+        self._lib.orc_consts(self._h, _ptr(out))
+        return dict(zip(("kmax", "klim", "kh", "tolu", "tolv", "tolkc", "epsak"), out))
+
+    def run(self, x, y, z, module, sensor) -> Result:
+        x = np.ascontiguousarray(x, np.float32); y = np.ascontiguousarray(y, np.float32)
+        z = np.ascontiguousarray(z, np.float32)
+        module = np.ascontiguousarray(module, np.int32)
+        sensor = np.ascontiguousarray(sensor, np.uint8)
+        rc = self._lib.orc_run(self._h, int(x.shape[0]), _ptr(x), _ptr(y), _ptr(z),
+                               _ptr(module), _ptr(sensor))
+        if rc != 0:
+            raise ValueError("oracle: invalid hits")
+        return self._collect()
+
+    def run_event(self, ev) -> Result:
+        return self.run(ev.x, ev.y, ev.z, ev.module, ev.sensor)
+
+    def _collect(self) -> Result:
+        lib, h = self._lib, self._h
+        tuples = {}
+        for kind in (MD, SEG, T3, T5, T5_KEPT):
+            n = lib.orc_count(h, kind)
+            out = np.zeros((max(n, 1), WIDTH[kind]), np.int32)
+            lib.orc_tuples(h, kind, _ptr(out))
+            tuples[kind] = out[:n]
+        n5 = lib.orc_count(h, T5)
+        sc = np.zeros(max(n5, 1), np.float32); lib.orc_t5_scores(h, _ptr(sc))
+        kp = np.zeros(max(n5, 1), np.uint8); lib.orc_t5_keep(h, _ptr(kp))
+        n3 = lib.orc_count(h, T3)
+        k3 = np.zeros(max(n3, 1), np.float32); lib.orc_t3_curv(h, _ptr(k3))
+        cands = np.zeros(4, np.int64); lib.orc_cands(h, _ptr(cands))
+        near = {}
+        for kind in (MD, SEG, T3, T5):
+            nn = lib.orc_near_count(h, kind)
+            tt = np.zeros((max(nn, 1), WIDTH[kind]), np.int32)
+            mg = np.zeros(max(nn, 1), np.float64)
+            dc = np.zeros(max(nn, 1), np.uint8)
+            lib.orc_near(h, kind, _ptr(tt), _ptr(mg), _ptr(dc))
+            near[kind] = (tt[:nn], mg[:nn], dc[:nn])
+        return Result(tuples=tuples, t5_scores=sc[:n5], t5_keep=kp[:n5].astype(bool),
+                      t3_curv=k3[:n3], cands=cands, near=near)
+
+    # -- single-candidate evaluation (closed-form checks) -------------------
+    def eval_md(self, module: int, lo3, up3):
+        lo = np.ascontiguousarray(lo3, np.float32); up = np.ascontiguousarray(up3, np.float32)
+        out = np.zeros(8)
+        p = self._lib.orc_eval_md(self._h, int(module), _ptr(lo), _ptr(up), _ptr(out))
+        return bool(p), out
+
+    def _eval(self, fn, n, mods, hits, nout):
+        mods = np.ascontiguousarray(mods, np.int32)
+        hits = np.ascontiguousarray(hits, np.float32).reshape(-1)
+        assert mods.shape[0] == n and hits.shape[0] == 6 * n
+        out = np.zeros(nout)
+        p = fn(self._h, _ptr(mods), _ptr(hits), _ptr(out))
+        return bool(p), out
+
+    def eval_seg(self, mods, hits):
+        return self._eval(self._lib.orc_eval_seg, 2, mods, hits, 13)
+
+    def eval_t3(self, mods, hits):
+        return self._eval(self._lib.orc_eval_t3, 3, mods, hits, 7)
+
+    def eval_t5(self, mods, hits):
+        return self._eval(self._lib.orc_eval_t5, 5, mods, hits, 18)

@@ -1,0 +1,89 @@
+/* CPU oracle of the Segment Linking hot path (arXiv:2209.13711).
+ *
+ * TEST INFRASTRUCTURE.  This is the slow, plain reference the HIP library is
+ * checked against.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it; the library never does.  It shares no
+ * source with the library: the geometry, the hits and the primary parameter
+ * vector are its only common inputs.
+ *
+ * Stages, in the paper's order (Sec. 2.1 and the kernel-flow figure of
+ * Sec. 3): compatibility map of modules -> mini-doublets (stubs) ->
+ * segments -> triplets (T3) -> quintuplets (T5) -> removal of T5s that share
+ * hits (Sec. 2.1, "objects do not share any hits").  Decisions are FP32; every
+ * decision also gets its FP64 margin so that near-threshold cases can be told
+ * apart from real disagreements.
+ */
+#ifndef LST_ORACLE_H
+#define LST_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* primary parameters (double); the oracle derives its own FP32 constants */
+enum {
+    ORC_P_BFIELD = 0, /* T */
+    ORC_P_PTMIN,      /* GeV, threshold p_T (0.8) */
+    ORC_P_Z0MAX,      /* cm, luminous-region half length used by the pointing cuts */
+    ORC_P_SIGU,       /* cm, precise-axis resolution */
+    ORC_P_SIGV,       /* cm, coarse-axis resolution */
+    ORC_P_NSIG,       /* window width in resolution units */
+    ORC_P_EPSK,       /* relative curvature margin on the threshold */
+    ORC_P_EPSA,       /* curvature agreement slack, fraction of kappa_max */
+    ORC_P_D0MAX,      /* cm, transverse impact parameter allowed by the beam-line cut */
+    ORC_P_XRPHI,      /* chi2 limit, r-phi, 2 dof */
+    ORC_P_XRZ,        /* chi2 limit, r-z, 3 dof */
+    ORC_P_W,          /* window scale */
+    ORC_P_MAP_DPHI,   /* rad, azimuthal margin of the module map */
+    ORC_P_MAP_DL,     /* cm, length margin of the module map */
+    ORC_N_PARAMS
+};
+
+enum { ORC_MD = 0, ORC_SEG = 1, ORC_T3 = 2, ORC_T5 = 3, ORC_T5_KEPT = 4 };
+
+typedef struct orc orc;
+
+/* geometry: mod_f32 is [21][n_mod] float SoA, mod_i32 is [4][n_mod] int SoA
+ * (layouts in synth/geometry.py).  Returns NULL on bad input. */
+orc *orc_create(const double *params, int n_params, int n_mod, const float *mod_f32,
+                const int32_t *mod_i32);
+void orc_destroy(orc *o);
+
+int64_t orc_map_edges(const orc *o);
+void orc_map(const orc *o, int32_t *row_ptr, int32_t *col);
+
+/* one event; hits in the caller's order (tuples refer to these indices) */
+int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float *z,
+            const int32_t *module, const uint8_t *sensor);
+
+int64_t orc_count(const orc *o, int kind);
+/* tuples of kind (width 2, 4, 6, 10, 10) in caller hit indices */
+void orc_tuples(const orc *o, int kind, int32_t *out);
+/* algorithmic candidate counts: MD pairs, segment pairs, T3 pairs, T5 pairs */
+void orc_cands(const orc *o, int64_t *out4);
+void orc_t5_scores(const orc *o, float *out);
+void orc_t5_keep(const orc *o, uint8_t *out);
+void orc_t3_curv(const orc *o, float *out);
+
+/* candidates whose FP64 margin is below 1e-5 (relative): tuple, margin and
+ * the FP32 decision; kind 0..3 */
+int64_t orc_near_count(const orc *o, int kind);
+void orc_near(const orc *o, int kind, int32_t *tuples, double *margins, uint8_t *decision);
+
+/* single-candidate evaluation for closed-form checks: each builds the MDs of
+ * the given (module, lower hit, upper hit) triples without applying the MD
+ * cut and fills `out` with the intermediate quantities listed in the source;
+ * returns the FP32 decision */
+int orc_eval_md(const orc *o, int module, const float *lo3, const float *up3, double *out);
+int orc_eval_seg(const orc *o, const int32_t *mods2, const float *hits12, double *out);
+int orc_eval_t3(const orc *o, const int32_t *mods3, const float *hits18, double *out);
+int orc_eval_t5(const orc *o, const int32_t *mods5, const float *hits30, double *out);
+
+/* derived FP32 constants (for inspection): kmax, klim, kh, tolu, tolv, tolkc, epsak */
+void orc_consts(const orc *o, float *out7);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
