@@ -1,0 +1,179 @@
+/* lst.h -- C ABI of the MI355X Segment Linking (Line Segment Tracking) library.
+ *
+ * Method: arXiv:2209.13711, "Segment Linking: A Highly Parallelizable Track
+ * Reconstruction Algorithm for HL-LHC".  The library runs the data-parallel,
+ * module-local part of the method on one GPU: stubs (mini-doublets, Sec. 2),
+ * segments, triplets and quintuplets built from every candidate combination
+ * under geometric and kinematic requirements (Sec. 2.1), and removal of
+ * quintuplets that share hits (Sec. 2.1, cross-cleaning rule that objects do
+ * not share any hits).
+ *
+ * Conventions
+ *  - Every function returns LST_OK (0) or a negative LST_E_* code; the message
+ *    of the last failure is returned by lst_last_error.  Nothing throws.
+ *  - Pointers are plain host or device pointers; the caller keeps ownership of
+ *    everything it passes in (the library copies what it keeps).  Device
+ *    memory for per-event work is the caller's arena (lst_attach_arena).
+ *  - "stream" is a hipStream_t passed as void* (NULL = default stream).  Stage
+ *    calls are asynchronous on it; kernel-side errors and capacity overflow
+ *    surface at the next synchronising call (lst_get_counts / lst_get_objects).
+ *  - A context is not thread safe; separate contexts are independent.
+ *  - Output hit indices are the caller's per-event indices (position of the
+ *    hit inside its event in the arrays given to lst_load_hits).  Tuples are
+ *    in canonical order: mini-doublets inner to outer, each as (lower-sensor
+ *    hit, upper-sensor hit).
+ */
+#ifndef LST_H
+#define LST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LST_OK 0
+#define LST_E_INVALID (-1)  /* bad argument or input value */
+#define LST_E_STATE (-2)    /* call out of order (no geometry, no arena, no hits) */
+#define LST_E_CAPACITY (-3) /* an output did not fit its capacity; counts report the need */
+#define LST_E_HIP (-4)      /* HIP runtime error */
+#define LST_E_NOMEM (-5)    /* host or device allocation failed */
+
+/* object kinds and their tuple widths (hit indices per object) */
+enum lst_kind {
+    LST_MD = 0,      /* width 2  */
+    LST_SEG = 1,     /* width 4  */
+    LST_T3 = 2,      /* width 6  */
+    LST_T5 = 3,      /* width 10 */
+    LST_T5_KEPT = 4  /* width 10: quintuplets surviving duplicate removal */
+};
+
+/* primary parameter vector (double), in this order.  The library derives
+ * all of its FP32 constants from these values. */
+enum lst_param {
+    LST_P_BFIELD = 0, /* solenoid field, T (3.8) */
+    LST_P_PTMIN,      /* threshold transverse momentum, GeV (0.8, Sec. 2) */
+    LST_P_Z0MAX,      /* half length of the luminous region, cm */
+    LST_P_SIGU,       /* hit resolution along the precise module axis, cm */
+    LST_P_SIGV,       /* hit resolution along the coarse module axis, cm */
+    LST_P_NSIG,       /* window half width in resolution units */
+    LST_P_EPSK,       /* relative curvature margin above the threshold curvature */
+    LST_P_EPSA,       /* curvature agreement slack, fraction of the threshold curvature */
+    LST_P_D0MAX,      /* transverse impact parameter allowed by the beam-line cut, cm */
+    LST_P_XRPHI,      /* r-phi chi2 limit of quintuplets (2 dof) */
+    LST_P_XRZ,        /* r-z chi2 limit of quintuplets (3 dof) */
+    LST_P_W,          /* window scale applied to every cut */
+    LST_P_MAP_DPHI,   /* azimuthal margin of the module map, rad */
+    LST_P_MAP_DL,     /* length margin of the module map, cm */
+    LST_N_PARAMS
+};
+
+/* module table layout: module_f32 is [LST_MOD_NF][n_modules] float SoA with
+ * rows cx cy cz ux uy uz vx vy vz wx wy wz hu hv gap rmin rmax zmin zmax phi dphi
+ * (centre between the sensors; u precise axis, v coarse axis, w sensor normal
+ * away from the interaction point; half sizes; sensor gap; extents of the
+ * module in r, z and azimuth).  module_i32 is [LST_MOD_NI][n_modules] int SoA
+ * with rows layer (barrel 1..6, +z disks 7..11, -z disks 12..16),
+ * subdetector (0 barrel, 1 endcap), side (0, +1, -1), type (0 PS, 1 2S). */
+#define LST_MOD_NF 21
+#define LST_MOD_NI 4
+
+typedef struct lst_ctx lst_ctx;
+
+/* capacities of one arena (totals over all events of a batch) */
+typedef struct {
+    int32_t events; /* events per batch */
+    int64_t hits;
+    int64_t md;
+    int64_t seg;
+    int64_t t3;
+    int64_t t5;
+} lst_caps;
+
+/* per-event result summary.  n_* are the numbers of objects required, also
+ * when they exceeded capacity; cand_* are the algorithmic candidate counts
+ * (pairs evaluated by each stage).  overflow_mask bit k = stage k (MD, SEG,
+ * T3, T5) ran out of capacity; error_flags bit 0 = a hit with an invalid
+ * module or sensor id was skipped. */
+typedef struct {
+    int64_t n_hits, n_md, n_seg, n_t3, n_t5, n_t5_kept;
+    int64_t cand_md, cand_seg, cand_t3, cand_t5;
+    int32_t overflow_mask, error_flags;
+} lst_counts;
+
+/* Create a context on HIP device `device`.  params: LST_N_PARAMS doubles. */
+int lst_create(lst_ctx **out, int device, const double *params, int32_t n_params);
+void lst_destroy(lst_ctx *ctx);
+const char *lst_last_error(const lst_ctx *ctx);
+
+/* Load the detector description (host arrays, copied) and build the module
+ * compatibility map (Sec. 2.1: modules on the next logical layer reachable by
+ * +-q helices of threshold p_T from the luminous region).  Synchronous. */
+int lst_load_geometry(lst_ctx *ctx, int32_t n_modules, const float *module_f32,
+                      const int32_t *module_i32);
+
+/* Stateless, host only (no device needed): the module map lst_load_geometry
+ * would build for this geometry and parameter vector.  row_ptr [n_modules+1],
+ * col [cap_col]; *n_edges is set even when cap_col is too small (then
+ * LST_E_CAPACITY). */
+int lst_build_map(const double *params, int32_t n_params, int32_t n_modules,
+                  const float *module_f32, const int32_t *module_i32, int32_t *row_ptr,
+                  int32_t *col, int64_t cap_col, int64_t *n_edges);
+
+/* Copy the map out: row_ptr [n_modules+1], col [cap_col]; *n_edges is set even
+ * when cap_col is too small (then LST_E_CAPACITY). */
+int lst_get_map(lst_ctx *ctx, int32_t *row_ptr, int32_t *col, int64_t cap_col,
+                int64_t *n_edges);
+
+/* Device bytes an arena needs for the given capacities (geometry loaded). */
+int lst_arena_bytes(const lst_ctx *ctx, const lst_caps *caps, size_t *bytes);
+
+/* Hand the library a device buffer (e.g. a framework-allocated tensor) to
+ * carve its per-event arrays from.  The caller keeps ownership and must keep
+ * it alive while the context uses it. */
+int lst_attach_arena(lst_ctx *ctx, void *dev_ptr, size_t bytes, const lst_caps *caps);
+
+/* Load a batch of n_events events: hits of event e are [hit_offsets[e],
+ * hit_offsets[e+1]) of x, y, z (cm), module (0..n_modules-1), sensor (0 lower,
+ * 1 upper).  hit_offsets is a host array; the hit arrays are host pointers
+ * (on_device = 0) or device pointers (on_device = 1).  Copies are enqueued on
+ * `stream`; host arrays must stay valid until the stream reaches them. */
+int lst_load_hits(lst_ctx *ctx, int32_t n_events, const int32_t *hit_offsets, const float *x,
+                  const float *y, const float *z, const int32_t *module, const uint8_t *sensor,
+                  int on_device, void *stream);
+
+/* Stages (asynchronous on `stream`), each requiring the previous one:
+ * lst_run_sort      hits grouped by (event, module, sensor)
+ * lst_run_md        mini-doublets (stubs), Sec. 2
+ * lst_run_segments  segments over map edges, Sec. 2.1
+ * lst_run_triplets  triplets: segment pairs sharing a mini-doublet, Sec. 2.1
+ * lst_run_quintuplets quintuplets: triplet pairs sharing a mini-doublet, then
+ *                   removal of quintuplets sharing hits, Sec. 2.1
+ * lst_run_chain     all of the above in one call. */
+int lst_run_sort(lst_ctx *ctx, void *stream);
+int lst_run_md(lst_ctx *ctx, void *stream);
+int lst_run_segments(lst_ctx *ctx, void *stream);
+int lst_run_triplets(lst_ctx *ctx, void *stream);
+int lst_run_quintuplets(lst_ctx *ctx, void *stream);
+int lst_run_chain(lst_ctx *ctx, void *stream);
+
+/* Synchronise `stream`, then report event `event` (0..n_events-1).  Returns
+ * LST_E_CAPACITY when any stage overflowed (counts still filled). */
+int lst_get_counts(lst_ctx *ctx, int32_t event, lst_counts *out, void *stream);
+
+/* Synchronise `stream` and copy the objects of `kind` of `event` to out_host
+ * (int32, width per lst_kind, capacity cap_tuples tuples).  *n_tuples is set
+ * even when the capacity is too small (then LST_E_CAPACITY). */
+int lst_get_objects(lst_ctx *ctx, int32_t event, int32_t kind, int32_t *out_host,
+                    int64_t cap_tuples, int64_t *n_tuples, void *stream);
+
+/* Quintuplet scores (chi2_rphi + chi2_rz) of `event`, in the order of
+ * lst_get_objects(LST_T5). */
+int lst_get_t5_scores(lst_ctx *ctx, int32_t event, float *out_host, int64_t cap,
+                      int64_t *n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

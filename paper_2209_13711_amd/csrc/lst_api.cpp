@@ -1,0 +1,626 @@
+// Host side of liblst: the C ABI declared in include/lst.h.
+//
+// Owns the geometry on the device, carves the per-batch arrays out of the
+// caller's arena, enqueues the stage kernels on the caller's stream and
+// converts device objects into per-event hit-index tuples on request.
+#include "../../include/lst.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lst_internal.hpp"
+
+namespace lst {
+void build_module_map(int n, const float *f32, const int32_t *i32, const double *params,
+                      std::vector<int32_t> &row_ptr, std::vector<int32_t> &col);
+}
+
+using namespace lst;
+
+struct lst_ctx {
+    int device = 0;
+    double params[LST_N_PARAMS];
+    Consts K;
+    std::string err;
+    // geometry
+    int n_mod = 0;
+    std::vector<float> mod_f32;
+    std::vector<int32_t> mod_i32;
+    std::vector<int32_t> map_ptr, map_col;
+    void *geo_dev = nullptr;
+    ModDev M{};
+    // arena
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    lst_caps caps{};
+    EvDev E{};
+    void *zero_base = nullptr;
+    size_t zero_bytes = 0;
+    // batch
+    int n_events = 0;
+    std::vector<int32_t> hit_off;
+    int stage = 0;  // 0 nothing, 1 hits loaded, 2 sorted, 3 md, 4 seg, 5 t3, 6 t5+dedup
+};
+
+static int fail(lst_ctx *c, int code, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(c, call)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) return fail((c), LST_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// FP32 constants, each computed once in FP64 from the primary parameters and
+// rounded once.
+static void derive(const double *p, Consts &K)
+{
+    const double kmax = (0.0029979245800 * p[LST_P_BFIELD]) / p[LST_P_PTMIN];
+    const double klim = kmax * (1.0 + p[LST_P_EPSK]);
+    K.kmax = (float)kmax;
+    K.klim = (float)klim;
+    K.kh = (float)(0.5 * klim);
+    K.tolu = (float)(p[LST_P_NSIG] * std::sqrt(2.0) * p[LST_P_SIGU]);
+    K.tolv = (float)(p[LST_P_NSIG] * std::sqrt(2.0) * p[LST_P_SIGV]);
+    K.tolkc = (float)(p[LST_P_NSIG] * 8.0 * std::sqrt(1.5));
+    K.epsak = (float)(p[LST_P_EPSA] * kmax);
+    K.z0max = (float)p[LST_P_Z0MAX];
+    K.sigu = (float)p[LST_P_SIGU];
+    K.sigv = (float)p[LST_P_SIGV];
+    K.nsig = (float)p[LST_P_NSIG];
+    K.d0max = (float)p[LST_P_D0MAX];
+    K.w = (float)p[LST_P_W];
+    K.w2 = (float)(p[LST_P_W] * p[LST_P_W]);
+    K.xrphi = (float)p[LST_P_XRPHI];
+    K.xrz = (float)p[LST_P_XRZ];
+}
+
+// ---------------------------------------------------------------- arena
+namespace {
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(char *b) : base(b) {}
+    template <class T>
+    T *take(size_t n)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += sizeof(T) * std::max<size_t>(n, 1);
+        return p;
+    }
+};
+
+bool caps_ok(const lst_caps *k)
+{
+    return k && k->events > 0 && k->hits >= 0 && k->md >= 0 && k->seg >= 0 && k->t3 >= 0 &&
+           k->t5 >= 0 && k->hits < (1ll << 31) && k->md < (1ll << 31) &&
+           k->seg < (1ll << 31) && k->t3 < (1ll << 31) && k->t5 < (1ll << 31);
+}
+
+// Lay the arrays out; with base == nullptr only the size is computed.
+size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_base,
+             size_t *zero_bytes)
+{
+    Carver cv(base);
+    const int64_t slots = (int64_t)k.events * c->n_mod;
+    const int64_t keys = 2 * slots;
+    E = EvDev{};
+    E.n_slots = (int32_t)slots;
+    E.n_keys = (int32_t)keys;
+    E.cap_hits = k.hits;
+    E.cap_md = k.md;
+    E.cap_seg = k.seg;
+    E.cap_t3 = k.t3;
+    E.cap_t5 = k.t5;
+    // region cleared at the start of every chain
+    size_t z0 = (cv.off + 255) & ~(size_t)255;
+    E.gc = cv.take<int32_t>(GC_COUNT);
+    E.evc = cv.take<unsigned long long>((size_t)k.events * EC_COUNT * NSHARD);
+    E.bcnt = cv.take<uint32_t>(keys);
+    size_t z1 = (cv.off + 255) & ~(size_t)255;
+    if (zero_base) *zero_base = base ? base + z0 : nullptr;
+    if (zero_bytes) *zero_bytes = z1 - z0;
+    // inputs
+    E.x = cv.take<float>(k.hits);
+    E.y = cv.take<float>(k.hits);
+    E.z = cv.take<float>(k.hits);
+    E.module = cv.take<int32_t>(k.hits);
+    E.sensor = cv.take<uint8_t>(k.hits);
+    E.hit_off = cv.take<int32_t>(k.events + 1);
+    // grouping
+    E.boff = cv.take<uint32_t>(keys + 1);
+    E.bsum = cv.take<uint32_t>((keys + 1023) / 1024 + 1);
+    E.sx = cv.take<float>(k.hits);
+    E.sy = cv.take<float>(k.hits);
+    E.sz = cv.take<float>(k.hits);
+    E.sorig = cv.take<int32_t>(k.hits);
+    E.hmin = cv.take<uint32_t>(k.hits);
+    E.htie = cv.take<int32_t>(k.hits);
+    // MD
+    E.md_hlo = cv.take<int32_t>(k.md);
+    E.md_hup = cv.take<int32_t>(k.md);
+    E.md_slot = cv.take<int32_t>(k.md);
+    E.md_x = cv.take<float>(k.md);
+    E.md_y = cv.take<float>(k.md);
+    E.md_z = cv.take<float>(k.md);
+    E.md_r = cv.take<float>(k.md);
+    E.md_a = cv.take<float>(k.md);
+    E.md_ca = cv.take<float>(k.md);
+    E.md_dx = cv.take<float>(k.md);
+    E.md_dy = cv.take<float>(k.md);
+    E.md_dn = cv.take<float>(k.md);
+    E.md_bend = cv.take<float>(k.md);
+    E.md_sv = cv.take<float>(k.md);
+    E.md_bar = cv.take<uint8_t>(k.md);
+    E.md_start = cv.take<int32_t>(slots);
+    E.md_cnt = cv.take<int32_t>(slots);
+    // segments
+    E.seg_in = cv.take<int32_t>(k.seg);
+    E.seg_out = cv.take<int32_t>(k.seg);
+    E.seg_start = cv.take<int32_t>(k.md);
+    E.seg_cnt = cv.take<int32_t>(k.md);
+    // triplets
+    E.t3_a = cv.take<int32_t>(k.t3);
+    E.t3_b = cv.take<int32_t>(k.t3);
+    E.t3_c = cv.take<int32_t>(k.t3);
+    E.t3_k = cv.take<float>(k.t3);
+    E.t3_start = cv.take<int32_t>(k.md);
+    E.t3_cnt = cv.take<int32_t>(k.md);
+    // quintuplets
+    E.t5_md0 = cv.take<int32_t>(k.t5);
+    E.t5_md1 = cv.take<int32_t>(k.t5);
+    E.t5_md2 = cv.take<int32_t>(k.t5);
+    E.t5_md3 = cv.take<int32_t>(k.t5);
+    E.t5_md4 = cv.take<int32_t>(k.t5);
+    E.t5_score = cv.take<float>(k.t5);
+    E.t5_keep = cv.take<uint8_t>(k.t5);
+    return (cv.off + 255) & ~(size_t)255;
+}
+}  // namespace
+
+template <class T>
+static int d2h(lst_ctx *c, std::vector<T> &v, const T *src, size_t n)
+{
+    v.resize(std::max<size_t>(n, 1));
+    if (n) HIPCHK(c, hipMemcpy(v.data(), src, sizeof(T) * n, hipMemcpyDeviceToHost));
+    return LST_OK;
+}
+
+extern "C" {
+
+int lst_create(lst_ctx **out, int device, const double *params, int32_t n_params)
+{
+    if (!out) return LST_E_INVALID;
+    *out = nullptr;
+    if (!params || n_params < LST_N_PARAMS) return LST_E_INVALID;
+    for (int i = 0; i < LST_N_PARAMS; ++i)
+        if (!std::isfinite(params[i])) return LST_E_INVALID;
+    if (params[LST_P_BFIELD] <= 0 || params[LST_P_PTMIN] <= 0 || params[LST_P_W] <= 0)
+        return LST_E_INVALID;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return LST_E_HIP;
+    lst_ctx *c = new (std::nothrow) lst_ctx();
+    if (!c) return LST_E_NOMEM;
+    c->device = device;
+    std::memcpy(c->params, params, sizeof(c->params));
+    derive(c->params, c->K);
+    *out = c;
+    return LST_OK;
+}
+
+void lst_destroy(lst_ctx *c)
+{
+    if (!c) return;
+    if (c->geo_dev) {
+        (void)hipSetDevice(c->device);
+        (void)hipFree(c->geo_dev);
+    }
+    delete c;
+}
+
+const char *lst_last_error(const lst_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+int lst_load_geometry(lst_ctx *c, int32_t n, const float *f32, const int32_t *i32)
+{
+    if (!c) return LST_E_INVALID;
+    if (n <= 0 || !f32 || !i32) return fail(c, LST_E_INVALID, "empty geometry");
+    for (int m = 0; m < n; ++m) {
+        int layer = i32[m], sub = i32[n + m];
+        if (layer < 1 || layer > 16 || sub < 0 || sub > 1)
+            return fail(c, LST_E_INVALID, "module %d: bad layer/subdetector", m);
+        for (int f = 0; f < LST_MOD_NF; ++f)
+            if (!std::isfinite(f32[(size_t)f * n + m]))
+                return fail(c, LST_E_INVALID, "module %d: non-finite field %d", m, f);
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    c->n_mod = n;
+    c->mod_f32.assign(f32, f32 + (size_t)LST_MOD_NF * n);
+    c->mod_i32.assign(i32, i32 + (size_t)LST_MOD_NI * n);
+    build_module_map(n, f32, i32, c->params, c->map_ptr, c->map_col);
+
+    // device geometry: 11 float rows, barrel flags, map
+    std::vector<float> rows((size_t)11 * n);
+    std::vector<int32_t> barrel(n);
+    const int src[10] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 14};  // cx..vz, gap
+    for (int r = 0; r < 10; ++r)
+        std::memcpy(&rows[(size_t)r * n], &f32[(size_t)src[r] * n], sizeof(float) * n);
+    for (int m = 0; m < n; ++m) {
+        const float cx = f32[m], cy = f32[n + m], wx = f32[9 * n + m], wy = f32[10 * n + m];
+        const float g = f32[14 * n + m];
+        rows[(size_t)10 * n + m] = ((cx * wx) + (cy * wy)) - (0.5f * g);  // lower-sensor apothem
+        barrel[m] = i32[n + m] == 0 ? 1 : 0;
+    }
+    const size_t nf = rows.size() * sizeof(float);
+    const size_t nb = sizeof(int32_t) * n;
+    const size_t np = sizeof(int32_t) * (n + 1);
+    const size_t nc = sizeof(int32_t) * std::max<size_t>(c->map_col.size(), 1);
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t total = al(nf) + al(nb) + al(np) + al(nc);
+    if (c->geo_dev) {
+        HIPCHK(c, hipFree(c->geo_dev));
+        c->geo_dev = nullptr;
+    }
+    HIPCHK(c, hipMalloc(&c->geo_dev, total));
+    char *p = (char *)c->geo_dev;
+    float *drows = (float *)p;
+    int32_t *dbar = (int32_t *)(p + al(nf));
+    int32_t *dptr = (int32_t *)(p + al(nf) + al(nb));
+    int32_t *dcol = (int32_t *)(p + al(nf) + al(nb) + al(np));
+    HIPCHK(c, hipMemcpy(drows, rows.data(), nf, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(dbar, barrel.data(), nb, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(dptr, c->map_ptr.data(), np, hipMemcpyHostToDevice));
+    if (!c->map_col.empty())
+        HIPCHK(c, hipMemcpy(dcol, c->map_col.data(), c->map_col.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice));
+    ModDev &M = c->M;
+    float *r[11];
+    for (int i = 0; i < 11; ++i) r[i] = drows + (size_t)i * n;
+    M.cx = r[0]; M.cy = r[1]; M.cz = r[2]; M.ux = r[3]; M.uy = r[4]; M.uz = r[5];
+    M.vx = r[6]; M.vy = r[7]; M.vz = r[8]; M.g = r[9]; M.rl = r[10];
+    M.barrel = dbar;
+    M.map_ptr = dptr;
+    M.map_col = dcol;
+    M.n_mod = n;
+    c->arena = nullptr;  // a new geometry invalidates the arena layout
+    c->stage = 0;
+    return LST_OK;
+}
+
+int lst_build_map(const double *params, int32_t n_params, int32_t n, const float *f32,
+                  const int32_t *i32, int32_t *row_ptr, int32_t *col, int64_t cap_col,
+                  int64_t *n_edges)
+{
+    if (!params || n_params < LST_N_PARAMS || n <= 0 || !f32 || !i32) return LST_E_INVALID;
+    std::vector<int32_t> ptr, cl;
+    build_module_map(n, f32, i32, params, ptr, cl);
+    if (n_edges) *n_edges = (int64_t)cl.size();
+    if (row_ptr) std::memcpy(row_ptr, ptr.data(), sizeof(int32_t) * (n + 1));
+    if ((int64_t)cl.size() > cap_col) return LST_E_CAPACITY;
+    if (col && !cl.empty()) std::memcpy(col, cl.data(), sizeof(int32_t) * cl.size());
+    return LST_OK;
+}
+
+int lst_get_map(lst_ctx *c, int32_t *row_ptr, int32_t *col, int64_t cap_col, int64_t *n_edges)
+{
+    if (!c) return LST_E_INVALID;
+    if (!c->n_mod) return fail(c, LST_E_STATE, "no geometry loaded");
+    if (n_edges) *n_edges = (int64_t)c->map_col.size();
+    if (row_ptr) std::memcpy(row_ptr, c->map_ptr.data(), sizeof(int32_t) * (c->n_mod + 1));
+    if ((int64_t)c->map_col.size() > cap_col)
+        return fail(c, LST_E_CAPACITY, "map has %zu edges", c->map_col.size());
+    if (col && !c->map_col.empty())
+        std::memcpy(col, c->map_col.data(), sizeof(int32_t) * c->map_col.size());
+    return LST_OK;
+}
+
+// ---------------------------------------------------------------- arena
+
+int lst_arena_bytes(const lst_ctx *cc, const lst_caps *caps, size_t *bytes)
+{
+    lst_ctx *c = const_cast<lst_ctx *>(cc);
+    if (!c || !bytes) return LST_E_INVALID;
+    if (!c->n_mod) return fail(c, LST_E_STATE, "no geometry loaded");
+    if (!caps_ok(caps)) return fail(c, LST_E_INVALID, "bad capacities");
+    if ((int64_t)caps->events * c->n_mod * 2 >= (1ll << 31))
+        return fail(c, LST_E_INVALID, "too many events for one arena");
+    EvDev E;
+    *bytes = carve(c, nullptr, *caps, E, nullptr, nullptr);
+    return LST_OK;
+}
+
+int lst_attach_arena(lst_ctx *c, void *dev_ptr, size_t bytes, const lst_caps *caps)
+{
+    if (!c) return LST_E_INVALID;
+    size_t need = 0;
+    int rc = lst_arena_bytes(c, caps, &need);
+    if (rc != LST_OK) return rc;
+    if (!dev_ptr) return fail(c, LST_E_INVALID, "null arena");
+    if (((uintptr_t)dev_ptr & 255) != 0) return fail(c, LST_E_INVALID, "arena not 256-byte aligned");
+    if (bytes < need) return fail(c, LST_E_CAPACITY, "arena needs %zu bytes, got %zu", need, bytes);
+    c->arena = (char *)dev_ptr;
+    c->arena_bytes = bytes;
+    c->caps = *caps;
+    carve(c, c->arena, *caps, c->E, &c->zero_base, &c->zero_bytes);
+    c->stage = 0;
+    c->n_events = 0;
+    return LST_OK;
+}
+
+int lst_load_hits(lst_ctx *c, int32_t n_events, const int32_t *hit_offsets, const float *x,
+                  const float *y, const float *z, const int32_t *module, const uint8_t *sensor,
+                  int on_device, void *stream)
+{
+    if (!c) return LST_E_INVALID;
+    if (!c->n_mod) return fail(c, LST_E_STATE, "no geometry loaded");
+    if (!c->arena) return fail(c, LST_E_STATE, "no arena attached");
+    if (n_events <= 0 || n_events > c->caps.events || !hit_offsets)
+        return fail(c, LST_E_INVALID, "n_events %d outside 1..%d", n_events, c->caps.events);
+    if (hit_offsets[0] != 0) return fail(c, LST_E_INVALID, "hit_offsets[0] must be 0");
+    for (int e = 0; e < n_events; ++e)
+        if (hit_offsets[e + 1] < hit_offsets[e]) return fail(c, LST_E_INVALID, "hit_offsets not sorted");
+    const int64_t n = hit_offsets[n_events];
+    if (n > c->caps.hits) return fail(c, LST_E_CAPACITY, "%lld hits exceed capacity %lld",
+                                      (long long)n, (long long)c->caps.hits);
+    if (n > 0 && (!x || !y || !z || !module || !sensor))
+        return fail(c, LST_E_INVALID, "null hit array");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    EvDev &E = c->E;
+    if (n > 0) {
+        HIPCHK(c, hipMemcpyAsync(E.x, x, sizeof(float) * n, kind, s));
+        HIPCHK(c, hipMemcpyAsync(E.y, y, sizeof(float) * n, kind, s));
+        HIPCHK(c, hipMemcpyAsync(E.z, z, sizeof(float) * n, kind, s));
+        HIPCHK(c, hipMemcpyAsync(E.module, module, sizeof(int32_t) * n, kind, s));
+        HIPCHK(c, hipMemcpyAsync(E.sensor, sensor, n, kind, s));
+    }
+    c->hit_off.assign(hit_offsets, hit_offsets + n_events + 1);
+    HIPCHK(c, hipMemcpyAsync(E.hit_off, c->hit_off.data(), sizeof(int32_t) * (n_events + 1),
+                             hipMemcpyHostToDevice, s));
+    c->n_events = n_events;
+    E.n_ev = n_events;
+    E.n_slots = n_events * c->n_mod;
+    E.n_keys = 2 * E.n_slots;
+    E.n_hits = (int32_t)n;
+    c->stage = 1;
+    return LST_OK;
+}
+
+// ---------------------------------------------------------------- stages
+static int need_stage(lst_ctx *c, int s, const char *what)
+{
+    if (!c) return LST_E_INVALID;
+    if (c->stage < s) return fail(c, LST_E_STATE, "%s called out of order", what);
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, LST_E_HIP, "hipSetDevice");
+    return LST_OK;
+}
+
+int lst_run_sort(lst_ctx *c, void *stream)
+{
+    int rc = need_stage(c, 1, "lst_run_sort");
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, s));
+    HIPCHK(c, launch_sort(c->E, c->M, s));
+    c->stage = 2;
+    return LST_OK;
+}
+
+int lst_run_md(lst_ctx *c, void *stream)
+{
+    int rc = need_stage(c, 2, "lst_run_md");
+    if (rc) return rc;
+    HIPCHK(c, launch_md(c->E, c->M, c->K, (hipStream_t)stream));
+    c->stage = 3;
+    return LST_OK;
+}
+
+int lst_run_segments(lst_ctx *c, void *stream)
+{
+    int rc = need_stage(c, 3, "lst_run_segments");
+    if (rc) return rc;
+    HIPCHK(c, launch_seg(c->E, c->M, c->K, (hipStream_t)stream));
+    c->stage = 4;
+    return LST_OK;
+}
+
+int lst_run_triplets(lst_ctx *c, void *stream)
+{
+    int rc = need_stage(c, 4, "lst_run_triplets");
+    if (rc) return rc;
+    HIPCHK(c, launch_t3(c->E, c->M, c->K, (hipStream_t)stream));
+    c->stage = 5;
+    return LST_OK;
+}
+
+int lst_run_quintuplets(lst_ctx *c, void *stream)
+{
+    int rc = need_stage(c, 5, "lst_run_quintuplets");
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, launch_t5(c->E, c->M, c->K, s));
+    HIPCHK(c, launch_dedup(c->E, c->M, s));
+    c->stage = 6;
+    return LST_OK;
+}
+
+int lst_run_chain(lst_ctx *c, void *stream)
+{
+    int rc;
+    if ((rc = lst_run_sort(c, stream))) return rc;
+    if ((rc = lst_run_md(c, stream))) return rc;
+    if ((rc = lst_run_segments(c, stream))) return rc;
+    if ((rc = lst_run_triplets(c, stream))) return rc;
+    return lst_run_quintuplets(c, stream);
+}
+
+// ---------------------------------------------------------------- results
+static int sync_stream(lst_ctx *c, void *stream)
+{
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    HIPCHK(c, hipGetLastError());
+    return LST_OK;
+}
+
+int lst_get_counts(lst_ctx *c, int32_t event, lst_counts *out, void *stream)
+{
+    if (!c || !out) return LST_E_INVALID;
+    if (c->stage < 2) return fail(c, LST_E_STATE, "no chain has run");
+    if (event < 0 || event >= c->n_events) return fail(c, LST_E_INVALID, "event %d", event);
+    int rc = sync_stream(c, stream);
+    if (rc) return rc;
+    int32_t gc[GC_COUNT];
+    std::vector<unsigned long long> ev((size_t)EC_COUNT * NSHARD);
+    HIPCHK(c, hipMemcpy(gc, c->E.gc, sizeof(gc), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(ev.data(), c->E.evc + (size_t)event * EC_COUNT * NSHARD,
+                        ev.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    int64_t v[EC_COUNT];
+    for (int k = 0; k < EC_COUNT; ++k) {
+        unsigned long long s = 0;
+        for (int j = 0; j < NSHARD; ++j) s += ev[(size_t)k * NSHARD + j];
+        v[k] = (int64_t)s;
+    }
+    std::memset(out, 0, sizeof(*out));
+    out->n_hits = c->hit_off[event + 1] - c->hit_off[event];
+    out->n_md = v[EC_N_MD];
+    out->n_seg = v[EC_N_SEG];
+    out->n_t3 = v[EC_N_T3];
+    out->n_t5 = v[EC_N_T5];
+    out->n_t5_kept = v[EC_N_KEPT];
+    out->cand_md = v[EC_CAND_MD];
+    out->cand_seg = v[EC_CAND_SEG];
+    out->cand_t3 = v[EC_CAND_T3];
+    out->cand_t5 = v[EC_CAND_T5];
+    out->overflow_mask = gc[GC_OVERFLOW];
+    out->error_flags = gc[GC_ERROR];
+    if (gc[GC_OVERFLOW])
+        return fail(c, LST_E_CAPACITY, "capacity overflow (mask %d): MD %d SEG %d T3 %d T5 %d needed",
+                    gc[GC_OVERFLOW], gc[GC_MD], gc[GC_SEG], gc[GC_T3], gc[GC_T5]);
+    return LST_OK;
+}
+
+
+int lst_get_objects(lst_ctx *c, int32_t event, int32_t kind, int32_t *out, int64_t cap,
+                    int64_t *n_tuples, void *stream)
+{
+    if (!c) return LST_E_INVALID;
+    if (kind < LST_MD || kind > LST_T5_KEPT) return fail(c, LST_E_INVALID, "kind %d", kind);
+    if (event < 0 || event >= c->n_events) return fail(c, LST_E_INVALID, "event %d", event);
+    const int need = kind == LST_MD ? 3 : kind == LST_SEG ? 4 : kind == LST_T3 ? 5 : 6;
+    if (c->stage < need) return fail(c, LST_E_STATE, "stage for kind %d has not run", kind);
+    int rc = sync_stream(c, stream);
+    if (rc) return rc;
+    const EvDev &E = c->E;
+    int32_t gc[GC_COUNT];
+    HIPCHK(c, hipMemcpy(gc, E.gc, sizeof(gc), hipMemcpyDeviceToHost));
+    if (gc[GC_OVERFLOW]) return fail(c, LST_E_CAPACITY, "capacity overflow (mask %d)", gc[GC_OVERFLOW]);
+    const size_t n_sorted = (size_t)gc[GC_N_SORTED];
+    const size_t nmd = (size_t)std::min<int64_t>(gc[GC_MD], E.cap_md);
+    std::vector<int32_t> sorig, hlo, hup, slot;
+    if ((rc = d2h(c, sorig, E.sorig, n_sorted))) return rc;
+    if ((rc = d2h(c, hlo, E.md_hlo, nmd))) return rc;
+    if ((rc = d2h(c, hup, E.md_hup, nmd))) return rc;
+    if ((rc = d2h(c, slot, E.md_slot, nmd))) return rc;
+    const int lo_slot = event * c->n_mod, hi_slot = (event + 1) * c->n_mod;
+    auto in_ev = [&](int32_t md) { return slot[md] >= lo_slot && slot[md] < hi_slot; };
+    std::vector<int32_t> tup;
+    int width = 2;
+    if (kind == LST_MD) {
+        for (size_t i = 0; i < nmd; ++i)
+            if (in_ev((int32_t)i)) { tup.push_back(sorig[hlo[i]]); tup.push_back(sorig[hup[i]]); }
+    } else if (kind == LST_SEG) {
+        width = 4;
+        const size_t n = (size_t)std::min<int64_t>(gc[GC_SEG], E.cap_seg);
+        std::vector<int32_t> a, b;
+        if ((rc = d2h(c, a, E.seg_in, n)) || (rc = d2h(c, b, E.seg_out, n))) return rc;
+        for (size_t i = 0; i < n; ++i) {
+            if (!in_ev(a[i])) continue;
+            for (int32_t m : {a[i], b[i]}) { tup.push_back(sorig[hlo[m]]); tup.push_back(sorig[hup[m]]); }
+        }
+    } else if (kind == LST_T3) {
+        width = 6;
+        const size_t n = (size_t)std::min<int64_t>(gc[GC_T3], E.cap_t3);
+        std::vector<int32_t> a, b, d;
+        if ((rc = d2h(c, a, E.t3_a, n)) || (rc = d2h(c, b, E.t3_b, n)) || (rc = d2h(c, d, E.t3_c, n)))
+            return rc;
+        for (size_t i = 0; i < n; ++i) {
+            if (!in_ev(a[i])) continue;
+            for (int32_t m : {a[i], b[i], d[i]}) { tup.push_back(sorig[hlo[m]]); tup.push_back(sorig[hup[m]]); }
+        }
+    } else {
+        width = 10;
+        const size_t n = (size_t)std::min<int64_t>(gc[GC_T5], E.cap_t5);
+        std::vector<int32_t> m0, m1, m2, m3, m4;
+        std::vector<uint8_t> keep;
+        if ((rc = d2h(c, m0, E.t5_md0, n)) || (rc = d2h(c, m1, E.t5_md1, n)) ||
+            (rc = d2h(c, m2, E.t5_md2, n)) || (rc = d2h(c, m3, E.t5_md3, n)) ||
+            (rc = d2h(c, m4, E.t5_md4, n)) || (rc = d2h(c, keep, E.t5_keep, n)))
+            return rc;
+        for (size_t i = 0; i < n; ++i) {
+            if (!in_ev(m0[i])) continue;
+            if (kind == LST_T5_KEPT && !keep[i]) continue;
+            for (int32_t m : {m0[i], m1[i], m2[i], m3[i], m4[i]}) {
+                tup.push_back(sorig[hlo[m]]);
+                tup.push_back(sorig[hup[m]]);
+            }
+        }
+    }
+    const int64_t nt = (int64_t)tup.size() / width;
+    if (n_tuples) *n_tuples = nt;
+    if (nt > cap) return fail(c, LST_E_CAPACITY, "%lld tuples, capacity %lld", (long long)nt, (long long)cap);
+    if (out && nt) std::memcpy(out, tup.data(), sizeof(int32_t) * tup.size());
+    return LST_OK;
+}
+
+int lst_get_t5_scores(lst_ctx *c, int32_t event, float *out, int64_t cap, int64_t *n_out,
+                      void *stream)
+{
+    if (!c) return LST_E_INVALID;
+    if (event < 0 || event >= c->n_events) return fail(c, LST_E_INVALID, "event %d", event);
+    if (c->stage < 6) return fail(c, LST_E_STATE, "quintuplets have not run");
+    int rc = sync_stream(c, stream);
+    if (rc) return rc;
+    const EvDev &E = c->E;
+    int32_t gc[GC_COUNT];
+    HIPCHK(c, hipMemcpy(gc, E.gc, sizeof(gc), hipMemcpyDeviceToHost));
+    if (gc[GC_OVERFLOW]) return fail(c, LST_E_CAPACITY, "capacity overflow (mask %d)", gc[GC_OVERFLOW]);
+    const size_t n = (size_t)std::min<int64_t>(gc[GC_T5], E.cap_t5);
+    const size_t nmd = (size_t)std::min<int64_t>(gc[GC_MD], E.cap_md);
+    std::vector<int32_t> m0, slot;
+    std::vector<float> sc;
+    if ((rc = d2h(c, m0, E.t5_md0, n)) || (rc = d2h(c, sc, E.t5_score, n)) ||
+        (rc = d2h(c, slot, E.md_slot, nmd)))
+        return rc;
+    const int lo_slot = event * c->n_mod, hi_slot = (event + 1) * c->n_mod;
+    int64_t k = 0;
+    for (size_t i = 0; i < n; ++i) {
+        if (slot[m0[i]] < lo_slot || slot[m0[i]] >= hi_slot) continue;
+        if (out && k < cap) out[k] = sc[i];
+        ++k;
+    }
+    if (n_out) *n_out = k;
+    if (k > cap) return fail(c, LST_E_CAPACITY, "%lld scores, capacity %lld", (long long)k, (long long)cap);
+    return LST_OK;
+}
+
+}  // extern "C"

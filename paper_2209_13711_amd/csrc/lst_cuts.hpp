@@ -1,0 +1,291 @@
+// Device-side cut arithmetic of the Segment Linking chain (gfx950).
+//
+// The paper (arXiv:2209.13711) prints no formula; these are this project's
+// readings of its rules: a stub window equivalent to p_T >= 0.8 GeV (Sec. 2);
+// links along +-q helices of threshold p_T from the centre and a relative
+// angle between linked objects (Sec. 2.1); triplets and quintuplets from
+// objects sharing a stub (Sec. 2.1).
+//
+// Every expression is parenthesised in the operation order that defines the
+// FP32 result.  The library is built with -ffp-contract=off (no FMA
+// contraction) and HIP's default correctly rounded division and square root,
+// so each operation rounds exactly once and the result is reproducible
+// bit for bit on any IEEE-754 binary32 implementation.  min/max are the
+// ternaries below and every cut is "lhs <= rhs", so NaN fails.
+#pragma once
+
+#include "lst_internal.hpp"
+
+namespace lst {
+
+__device__ __forceinline__ float mn(float a, float b) { return a < b ? a : b; }
+__device__ __forceinline__ float mx(float a, float b) { return a > b ? a : b; }
+
+// asin(x)/x at x^2 = x2 (x2 clamped to 0.81): Maclaurin series to x^10 with
+// the remaining tail bounded by c6 x^12 / (1 - x^2).
+__device__ __forceinline__ float asinx(float x2)
+{
+    const float A1 = 1.0f / 6.0f, A2 = 3.0f / 40.0f, A3 = 5.0f / 112.0f;
+    const float A4 = 35.0f / 1152.0f, A5 = 63.0f / 2816.0f, A6 = 231.0f / 13312.0f;
+    float y = mn(x2, 0.81f);
+    return 1.0f + y * (A1 + y * (A2 + y * (A3 + y * (A4 + y * (A5 + y * (A6 / (1.0f - y)))))));
+}
+
+// transverse arc length of chord c on a circle of curvature k
+__device__ __forceinline__ float arc(float c, float k)
+{
+    float x = (0.5f * k) * c;
+    return c * asinx(x * x);
+}
+
+struct ModF {
+    float cx, cy, cz, ux, uy, uz, vx, vy, vz, g, rl;
+    int barrel;
+};
+
+struct MdOut {
+    float r, a, ca, bend, sv;
+};
+
+// Mini-doublet (stub) window for lower hit L and upper hit U of a module.
+__device__ __forceinline__ bool md_accept(const Consts &K, const ModF &m, float xL, float yL,
+                                          float zL, float xU, float yU, float zU, MdOut &o)
+{
+    float uL = (((xL - m.cx) * m.ux) + ((yL - m.cy) * m.uy)) + ((zL - m.cz) * m.uz);
+    float vL = (((xL - m.cx) * m.vx) + ((yL - m.cy) * m.vy)) + ((zL - m.cz) * m.vz);
+    float uU = (((xU - m.cx) * m.ux) + ((yU - m.cy) * m.uy)) + ((zU - m.cz) * m.uz);
+    float vU = (((xU - m.cx) * m.vx) + ((yU - m.cy) * m.vy)) + ((zU - m.cz) * m.vz);
+    float du = uU - uL;
+    float dv = vU - vL;
+    float rL = sqrtf((xL * xL) + (yL * yL));
+    float a = mn(rL * K.kh, 0.999f);
+    float ca = sqrtf(1.0f - (a * a));
+    float g = m.g;
+    float hi, lo, zc, hz, sv;
+    if (m.barrel) {
+        // bend along u over the gap: g tan(psi +- alpha)
+        float ta = a / ca;
+        float tp = uL / m.rl;
+        hi = g * ((tp + ta) / (1.0f - (tp * ta)));
+        lo = g * ((tp - ta) / (1.0f + (tp * ta)));
+        float dxy = sqrtf((du * du) + (g * g));
+        zc = dxy * (zL / rL);
+        hz = (dxy * (K.z0max / rL)) + K.tolv;
+        sv = 0.0f;
+    } else {
+        // transverse step between the sensors, precise component sin(delta +- alpha)
+        float sz = fabsf(zL);
+        float Dlo = g * (rL / (sz + K.z0max));
+        float Dhi = g * ((rL * asinx(a * a)) / (sz - K.z0max));
+        float sp = uL / rL;
+        float cp = ((xL * m.vx) + (yL * m.vy)) / rL;
+        float Sp = (sp * ca) + (cp * a);
+        float Sm = (sp * ca) - (cp * a);
+        hi = mx(Dlo * Sp, Dhi * Sp);
+        lo = mn(Dlo * Sm, Dhi * Sm);
+        zc = (0.5f * (Dlo + Dhi)) * cp;
+        hz = (0.5f * (Dhi - Dlo)) + K.tolv;
+        sv = sp;
+    }
+    float c0 = 0.5f * (hi + lo);
+    float h0 = (0.5f * (hi - lo)) + K.tolu;
+    o.r = rL;
+    o.a = a;
+    o.ca = ca;
+    o.bend = (du - c0) / h0;
+    o.sv = sv;
+    return (fabsf(du - c0) <= K.w * h0) && (fabsf(dv - zc) <= K.w * hz);
+}
+
+// A mini-doublet as the later stages see it (anchor = lower hit).
+struct MdV {
+    float x, y, z, r, a, ca, dx, dy, dn, sv;
+    int barrel;
+};
+
+__device__ __forceinline__ MdV load_md(const EvDev &E, int32_t i)
+{
+    MdV v;
+    v.x = E.md_x[i]; v.y = E.md_y[i]; v.z = E.md_z[i]; v.r = E.md_r[i];
+    v.a = E.md_a[i]; v.ca = E.md_ca[i]; v.dx = E.md_dx[i]; v.dy = E.md_dy[i];
+    v.dn = E.md_dn[i]; v.sv = E.md_sv[i];
+    v.barrel = E.md_bar[i];
+    return v;
+}
+
+// Segment I -> O: azimuthal window (S2), pointing along the prompt circle
+// (S1), relative angle of each barrel MD direction to the chord (S3).
+__device__ __forceinline__ bool seg_accept(const Consts &K, const MdV &I, const MdV &O)
+{
+    float rr = I.r * O.r;
+    float crs = (I.x * O.y) - (I.y * O.x);
+    float C = ((I.x * O.x) + (I.y * O.y)) / rr;
+    float S = crs / rr;
+    float sphi = (O.a * I.ca) - (I.a * O.ca);
+    float tphi = (K.tolu * ((1.0f / I.r) + (1.0f / O.r))) +
+                 (K.tolv * ((fabsf(I.sv) / I.r) + (fabsf(O.sv) / O.r)));
+    if (!((-C <= 0.0f) && (fabsf(S) <= K.w * (sphi + tphi)))) return false;
+    float qx = O.x - I.x, qy = O.y - I.y;
+    float ql = sqrtf((qx * qx) + (qy * qy));
+    float kO = (2.0f * crs) / (rr * ql);
+    float si = arc(I.r, kO);
+    float so = arc(O.r, kO);
+    float ds = so - si;
+    float z0 = ((I.z * so) - (O.z * si)) / ds;
+    float sl = (O.z - I.z) / ds;
+    float szi = I.barrel ? K.sigv : (fabsf(sl) * K.sigv);
+    float szo = O.barrel ? K.sigv : (fabsf(sl) * K.sigv);
+    float tolz = K.nsig * (((so * szi) + (si * szo)) / ds);
+    if (!(fabsf(z0) <= K.w * (K.z0max + tolz))) return false;
+    if (I.barrel) {
+        float sa = ((I.dx * qy) - (I.dy * qx)) / (I.dn * ql);
+        if (!(fabsf(sa - S) <= K.w * (K.tolu / I.dn))) return false;
+    }
+    if (O.barrel) {
+        float sb = ((qx * O.dy) - (qy * O.dx)) / (ql * O.dn);
+        if (!(fabsf(sb - S) <= K.w * (K.tolu / O.dn))) return false;
+    }
+    return true;
+}
+
+// variance of an anchor along the track normal
+__device__ __forceinline__ float perp_var(const Consts &K, const MdV &P, float hk)
+{
+    float su2 = K.sigu * K.sigu;
+    float t = P.sv + (hk * P.r);
+    float e = K.sigv * t;
+    return P.barrel ? su2 : (su2 + (e * e));
+}
+
+// Triplet A-B-C: curvature bound (T1), beam-line circle (T2), r-z line (T3).
+__device__ __forceinline__ bool t3_accept(const Consts &K, const MdV &A, const MdV &B,
+                                          const MdV &C, float &k_out)
+{
+    float xab = B.x - A.x, yab = B.y - A.y;
+    float xbc = C.x - B.x, ybc = C.y - B.y;
+    float xac = C.x - A.x, yac = C.y - A.y;
+    float lab = sqrtf((xab * xab) + (yab * yab));
+    float lbc = sqrtf((xbc * xbc) + (ybc * ybc));
+    float lac = sqrtf((xac * xac) + (yac * yac));
+    float crs = (xab * yac) - (yab * xac);
+    float k = (2.0f * crs) / ((lab * lbc) * lac);
+    k_out = k;
+    float l2 = lac * lac;
+    float hk = 0.5f * k;
+    float e2 = mx(mx(perp_var(K, A, hk), perp_var(K, B, hk)), perp_var(K, C, hk));
+    float tk = (K.tolkc * sqrtf(e2)) / l2;
+    if (!(fabsf(k) <= K.w * (K.klim + tk))) return false;
+    float kO = (2.0f * ((A.x * C.y) - (A.y * C.x))) / ((A.r * C.r) * lac);
+    if (!(fabsf(k - kO) <= K.w * (tk + ((2.0f * K.d0max) / (A.r * C.r))))) return false;
+    float sab = arc(lab, k);
+    float sbc = arc(lbc, k);
+    float st = sab + sbc;
+    float f = sab / st;
+    float sl = (C.z - A.z) / st;
+    float dz = B.z - (A.z + ((C.z - A.z) * f));
+    float se = mx(fabsf(sl), 0.05f) * K.sigv;
+    float sza = A.barrel ? K.sigv : se;
+    float szb = B.barrel ? K.sigv : se;
+    float szc = C.barrel ? K.sigv : se;
+    float g1 = (1.0f - f) * sza;
+    float g2 = f * szc;
+    return fabsf(dz) <= K.w * (K.nsig * sqrtf(((szb * szb) + (g1 * g1)) + (g2 * g2)));
+}
+
+// signed distance of P from the circle through A, C, E
+__device__ __forceinline__ float circ_res(float xa, float ya, float xc, float yc, float xe,
+                                         float ye, float xp, float yp, float crs, float den)
+{
+    float Ax = xa - xp, Ay = ya - yp;
+    float Cx = xc - xp, Cy = yc - yp;
+    float Ex = xe - xp, Ey = ye - yp;
+    float la = (Ax * Ax) + (Ay * Ay);
+    float lc = (Cx * Cx) + (Cy * Cy);
+    float le = (Ex * Ex) + (Ey * Ey);
+    float det = ((Ax * ((Cy * le) - (lc * Ey))) - (Ay * ((Cx * le) - (lc * Ex)))) +
+                (la * ((Cx * Ey) - (Cy * Ex)));
+    float sd = (crs >= 0.0f) ? -det : det;
+    return sd / den;
+}
+
+// Quintuplet P0..P4 from triplets (P0,P1,P2) and (P2,P3,P4): curvature
+// agreement with the bridge circle (Q1), bridge curvature bound (Q2), r-phi
+// chi2 of P1 and P3 (Q3), r-z chi2 of P1..P3 (Q4).  score = chi2 sum.
+__device__ __forceinline__ bool t5_accept(const Consts &K, const MdV &A, const MdV &B,
+                                          const MdV &C, const MdV &D, const MdV &Ee, float kin,
+                                          float kout, float &score)
+{
+    float xac = C.x - A.x, yac = C.y - A.y;
+    float xce = Ee.x - C.x, yce = Ee.y - C.y;
+    float xae = Ee.x - A.x, yae = Ee.y - A.y;
+    float lac = sqrtf((xac * xac) + (yac * yac));
+    float lce = sqrtf((xce * xce) + (yce * yce));
+    float lae = sqrtf((xae * xae) + (yae * yae));
+    float crs = (xac * yae) - (yac * xae);
+    float den = (lac * lce) * lae;
+    float kbr = (2.0f * crs) / den;
+    float hk = 0.5f * kbr;
+    float v0 = perp_var(K, A, hk), v1 = perp_var(K, B, hk), v2 = perp_var(K, C, hk);
+    float v3 = perp_var(K, D, hk), v4 = perp_var(K, Ee, hk);
+    float ein = mx(mx(v0, v1), v2);
+    float eout = mx(mx(v2, v3), v4);
+    if (!(fabsf(kin - kbr) <= K.w * (((K.tolkc * sqrtf(ein)) / (lac * lac)) + K.epsak))) return false;
+    if (!(fabsf(kout - kbr) <= K.w * (((K.tolkc * sqrtf(eout)) / (lce * lce)) + K.epsak))) return false;
+    if (!(fabsf(kbr) <= K.w * K.klim)) return false;
+    float resb = circ_res(A.x, A.y, C.x, C.y, Ee.x, Ee.y, B.x, B.y, crs, den);
+    float resd = circ_res(A.x, A.y, C.x, C.y, Ee.x, Ee.y, D.x, D.y, crs, den);
+    float xab = B.x - A.x, yab = B.y - A.y;
+    float xbc = C.x - B.x, ybc = C.y - B.y;
+    float xcd = D.x - C.x, ycd = D.y - C.y;
+    float xde = Ee.x - D.x, yde = Ee.y - D.y;
+    float s1 = arc(sqrtf((xab * xab) + (yab * yab)), kbr);
+    float s2 = arc(sqrtf((xbc * xbc) + (ybc * ybc)), kbr);
+    float s3 = arc(sqrtf((xcd * xcd) + (ycd * ycd)), kbr);
+    float s4 = arc(sqrtf((xde * xde) + (yde * yde)), kbr);
+    float S1 = s1, S2 = S1 + s2, S3 = S2 + s3, S4 = S3 + s4;
+    float Lab = ((S1 - S2) * (S1 - S4)) / (S2 * S4);
+    float Lcb = (S1 * (S1 - S4)) / (S2 * (S2 - S4));
+    float Leb = (S1 * (S1 - S2)) / (S4 * (S4 - S2));
+    float Lad = ((S3 - S2) * (S3 - S4)) / (S2 * S4);
+    float Lcd = (S3 * (S3 - S4)) / (S2 * (S2 - S4));
+    float Led = (S3 * (S3 - S2)) / (S4 * (S4 - S2));
+    float Vb = (v1 + (((Lab * Lab) * v0) + ((Lcb * Lcb) * v2))) + ((Leb * Leb) * v4);
+    float Vd = (v3 + (((Lad * Lad) * v0) + ((Lcd * Lcd) * v2))) + ((Led * Led) * v4);
+    float chi2p = ((resb * resb) / Vb) + ((resd * resd) / Vd);
+    if (!(chi2p <= K.w2 * K.xrphi)) return false;
+    float sl = (Ee.z - A.z) / S4;
+    float se = mx(fabsf(sl), 0.05f) * K.sigv;
+    float sza = A.barrel ? K.sigv : se;
+    float sze = Ee.barrel ? K.sigv : se;
+    float szb = B.barrel ? K.sigv : se;
+    float szc = C.barrel ? K.sigv : se;
+    float szd = D.barrel ? K.sigv : se;
+    float tb, tc, td;
+    {
+        float f = S1 / S4;
+        float dz = B.z - (A.z + (sl * S1));
+        float g1 = (1.0f - f) * sza, g2 = f * sze;
+        float V = ((szb * szb) + (g1 * g1)) + (g2 * g2);
+        tb = (dz * dz) / V;
+    }
+    {
+        float f = S2 / S4;
+        float dz = C.z - (A.z + (sl * S2));
+        float g1 = (1.0f - f) * sza, g2 = f * sze;
+        float V = ((szc * szc) + (g1 * g1)) + (g2 * g2);
+        tc = (dz * dz) / V;
+    }
+    {
+        float f = S3 / S4;
+        float dz = D.z - (A.z + (sl * S3));
+        float g1 = (1.0f - f) * sza, g2 = f * sze;
+        float V = ((szd * szd) + (g1 * g1)) + (g2 * g2);
+        td = (dz * dz) / V;
+    }
+    float chi2z = (tb + tc) + td;
+    if (!(chi2z <= K.w2 * K.xrz)) return false;
+    score = chi2p + chi2z;
+    return true;
+}
+
+}  // namespace lst

@@ -1,0 +1,92 @@
+// Internal layout shared by the host API and the kernels of liblst.
+//
+// Everything on the device is structure-of-arrays: one array per object
+// property, so that consecutive lanes touch consecutive addresses (the SoA
+// layout of Sec. 3 of the paper).  A batch of events is handled as one big
+// detector with n_events x n_modules "slots": slot = event * n_modules + module,
+// so a single event and a batch of 64 run the same kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lst {
+
+// FP32 constants derived once from the primary parameter vector.
+struct Consts {
+    float kmax, klim, kh, tolu, tolv, tolkc, epsak;
+    float z0max, sigu, sigv, nsig, d0max, w, w2, xrphi, xrz;
+};
+
+// Per-event counters, each spread over NSHARD shards to avoid one hot address.
+enum EvCounter {
+    EC_CAND_MD = 0, EC_CAND_SEG, EC_CAND_T3, EC_CAND_T5,
+    EC_N_MD, EC_N_SEG, EC_N_T3, EC_N_T5, EC_N_KEPT, EC_N_HITS,
+    EC_COUNT
+};
+constexpr int NSHARD = 16;
+
+// Global counters (int32 unless noted).
+enum GlobalCounter {
+    GC_MD = 0, GC_SEG, GC_T3, GC_T5, GC_OVERFLOW, GC_ERROR, GC_N_SORTED, GC_PAD,
+    GC_COUNT
+};
+
+struct ModDev {
+    const float *cx, *cy, *cz, *ux, *uy, *uz, *vx, *vy, *vz, *g, *rl;
+    const int32_t *barrel;   // 1 barrel, 0 endcap
+    const int32_t *map_ptr;  // [n_mod + 1]
+    const int32_t *map_col;  // [n_edges]
+    int32_t n_mod;
+};
+
+struct EvDev {
+    int32_t n_ev, n_slots, n_keys, n_hits;
+    int64_t cap_hits, cap_md, cap_seg, cap_t3, cap_t5;
+    // inputs as loaded
+    float *x, *y, *z;
+    int32_t *module;
+    uint8_t *sensor;
+    int32_t *hit_off;        // [n_ev + 1]
+    // grouping of hits by key = 2 * slot + sensor
+    uint32_t *bcnt;          // [n_keys]     (zeroed at chain start)
+    uint32_t *boff;          // [n_keys + 1]
+    uint32_t *bsum;          // scan partials
+    float *sx, *sy, *sz;     // sorted hits
+    int32_t *sorig;          // per-event index of each sorted hit
+    uint32_t *hmin;          // dedup: smallest quintuplet score bits per sorted hit
+    int32_t *htie;           // dedup: how many quintuplets reach that score
+    // mini-doublets
+    int32_t *md_hlo, *md_hup, *md_slot;
+    float *md_x, *md_y, *md_z, *md_r, *md_a, *md_ca, *md_dx, *md_dy, *md_dn, *md_bend, *md_sv;
+    uint8_t *md_bar;                 // 1 when the MD's module is in the barrel
+    int32_t *md_start, *md_cnt;      // [n_slots]
+    // segments (grouped by inner MD)
+    int32_t *seg_in, *seg_out;
+    int32_t *seg_start, *seg_cnt;    // [cap_md]
+    // triplets (grouped by first MD)
+    int32_t *t3_a, *t3_b, *t3_c;
+    float *t3_k;
+    int32_t *t3_start, *t3_cnt;      // [cap_md]
+    // quintuplets
+    int32_t *t5_md0, *t5_md1, *t5_md2, *t5_md3, *t5_md4;
+    float *t5_score;
+    uint8_t *t5_keep;
+    // counters (zeroed at chain start)
+    int32_t *gc;                     // [GC_COUNT]
+    unsigned long long *evc;         // [n_ev][EC_COUNT][NSHARD]
+};
+
+constexpr int BLOCK = 256;           // 4 waves of 64
+constexpr int WAVES = BLOCK / 64;
+
+// launchers (lst_kernels.hip)
+hipError_t launch_zero(const EvDev &E, void *zero_base, size_t zero_bytes, hipStream_t s);
+hipError_t launch_sort(const EvDev &E, const ModDev &M, hipStream_t s);
+hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s);
+hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s);
+hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s);
+hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s);
+hipError_t launch_dedup(const EvDev &E, const ModDev &M, hipStream_t s);
+
+}  // namespace lst

@@ -1,0 +1,284 @@
+"""ctypes binding of liblst (include/lst.h): same function names, argument
+marshalling only.  PyTorch provides the device arena and the HIP stream; every
+step of the chain runs in the library's kernels.
+
+``import torch`` happens first so that the library binds to the HIP runtime
+torch has already loaded (one runtime per process).  A missing or unloadable
+library raises immediately: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "liblst.so")
+
+LST_OK, LST_E_INVALID, LST_E_STATE, LST_E_CAPACITY, LST_E_HIP, LST_E_NOMEM = 0, -1, -2, -3, -4, -5
+LST_MD, LST_SEG, LST_T3, LST_T5, LST_T5_KEPT = 0, 1, 2, 3, 4
+WIDTH = {LST_MD: 2, LST_SEG: 4, LST_T3: 6, LST_T5: 10, LST_T5_KEPT: 10}
+LST_N_PARAMS = 14
+LST_MOD_NF, LST_MOD_NI = 21, 4
+
+
+class lst_caps(ctypes.Structure):
+    _fields_ = [("events", ctypes.c_int32), ("hits", ctypes.c_int64), ("md", ctypes.c_int64),
+                ("seg", ctypes.c_int64), ("t3", ctypes.c_int64), ("t5", ctypes.c_int64)]
+
+
+class lst_counts(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("n_hits", "n_md", "n_seg", "n_t3", "n_t5",
+                                               "n_t5_kept", "cand_md", "cand_seg", "cand_t3",
+                                               "cand_t5")] + \
+               [("overflow_mask", ctypes.c_int32), ("error_flags", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class LSTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"liblst error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_P = ctypes.c_void_p
+_SIGS = {
+    "lst_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P, ctypes.c_int32]),
+    "lst_destroy": (None, [_P]),
+    "lst_last_error": (ctypes.c_char_p, [_P]),
+    "lst_load_geometry": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    "lst_build_map": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P,
+                                     ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "lst_get_map": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "lst_arena_bytes": (ctypes.c_int, [_P, ctypes.POINTER(lst_caps), ctypes.POINTER(ctypes.c_size_t)]),
+    "lst_attach_arena": (ctypes.c_int, [_P, _P, ctypes.c_size_t, ctypes.POINTER(lst_caps)]),
+    "lst_load_hits": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, ctypes.c_int, _P]),
+    "lst_run_sort": (ctypes.c_int, [_P, _P]),
+    "lst_run_md": (ctypes.c_int, [_P, _P]),
+    "lst_run_segments": (ctypes.c_int, [_P, _P]),
+    "lst_run_triplets": (ctypes.c_int, [_P, _P]),
+    "lst_run_quintuplets": (ctypes.c_int, [_P, _P]),
+    "lst_run_chain": (ctypes.c_int, [_P, _P]),
+    "lst_get_counts": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(lst_counts), _P]),
+    "lst_get_objects": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64,
+                                       ctypes.POINTER(ctypes.c_int64), _P]),
+    "lst_get_t5_scores": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_int64), _P]),
+}
+EXPORTS = tuple(_SIGS)
+
+
+def load_library():
+    """Load liblst.so (built by paper_2209_13711_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"liblst.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def lst_build_map(params, geo_f32, geo_i32):
+    """Module map as (row_ptr, col) through the library's host-only entry point."""
+    lib = load_library()
+    params = np.ascontiguousarray(params, np.float64)
+    f32 = np.ascontiguousarray(geo_f32, np.float32)
+    i32 = np.ascontiguousarray(geo_i32, np.int32)
+    n = f32.shape[1]
+    ptr = np.zeros(n + 1, np.int32)
+    ne = ctypes.c_int64(0)
+    rc = lib.lst_build_map(_np_ptr(params), len(params), n, _np_ptr(f32), _np_ptr(i32),
+                           _np_ptr(ptr), None, 0, ctypes.byref(ne))
+    col = np.zeros(max(ne.value, 1), np.int32)
+    rc = lib.lst_build_map(_np_ptr(params), len(params), n, _np_ptr(f32), _np_ptr(i32),
+                           _np_ptr(ptr), _np_ptr(col), ne.value, ctypes.byref(ne))
+    if rc != LST_OK:
+        raise LSTError(rc, "lst_build_map")
+    return ptr, col[:ne.value]
+
+
+def default_caps(n_events: int, n_hits: int) -> dict:
+    md = max(4096, int(1.5 * n_hits))
+    return dict(events=n_events, hits=max(n_hits, 1), md=md, seg=6 * md, t3=4 * md, t5=4 * md)
+
+
+class Context:
+    """One detector geometry + parameter set on one GPU."""
+
+    def __init__(self, params, geo_f32, geo_i32, device: int = 0):
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblst needs a HIP device")
+        self.device = device
+        self._params = np.ascontiguousarray(params, np.float64)
+        h = _P()
+        rc = self.lib.lst_create(ctypes.byref(h), device, _np_ptr(self._params), len(self._params))
+        if rc != LST_OK:
+            raise LSTError(rc, "lst_create")
+        self.h = h
+        f32 = np.ascontiguousarray(geo_f32, np.float32)
+        i32 = np.ascontiguousarray(geo_i32, np.int32)
+        self.n_mod = f32.shape[1]
+        self._check(self.lib.lst_load_geometry(self.h, self.n_mod, _np_ptr(f32), _np_ptr(i32)))
+        self.arena = None
+        self.caps = None
+        self.n_events = 0
+        self._keep = []
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.lib is not None:
+            self.lib.lst_destroy(self.h)
+            self.h = None
+
+    def _check(self, rc):
+        if rc != LST_OK:
+            raise LSTError(rc, self.lib.lst_last_error(self.h).decode())
+        return rc
+
+    @staticmethod
+    def _stream(stream):
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        return ctypes.c_void_p(stream.cuda_stream)
+
+    # -- memory -------------------------------------------------------------
+    def reserve(self, caps: dict):
+        c = lst_caps(**caps)
+        nbytes = ctypes.c_size_t(0)
+        self._check(self.lib.lst_arena_bytes(self.h, ctypes.byref(c), ctypes.byref(nbytes)))
+        if self.arena is None or self.arena.numel() < nbytes.value:
+            self.arena = None
+            torch.cuda.synchronize(self.device)
+            self.arena = torch.empty(nbytes.value, dtype=torch.uint8, device=f"cuda:{self.device}")
+        self._check(self.lib.lst_attach_arena(self.h, ctypes.c_void_p(self.arena.data_ptr()),
+                                              self.arena.numel(), ctypes.byref(c)))
+        self.caps = dict(caps)
+
+    def module_map(self):
+        ptr = np.zeros(self.n_mod + 1, np.int32)
+        ne = ctypes.c_int64(0)
+        self.lib.lst_get_map(self.h, _np_ptr(ptr), None, 0, ctypes.byref(ne))
+        col = np.zeros(max(ne.value, 1), np.int32)
+        self._check(self.lib.lst_get_map(self.h, _np_ptr(ptr), _np_ptr(col), ne.value, ctypes.byref(ne)))
+        return ptr, col[:ne.value]
+
+    # -- inputs -------------------------------------------------------------
+    def load_hits(self, offsets, x, y, z, module, sensor, stream=None):
+        """Host numpy arrays or device torch tensors (one batch)."""
+        offsets = np.ascontiguousarray(offsets, np.int32)
+        n_ev = len(offsets) - 1
+        n = int(offsets[-1])
+        if self.caps is None or self.caps["events"] < n_ev or self.caps["hits"] < n:
+            self.reserve(default_caps(n_ev, n))
+        if isinstance(x, torch.Tensor):
+            arrs = [x, y, z, module, sensor]
+            for a in arrs:
+                assert a.is_cuda and a.is_contiguous()
+            ptrs = [ctypes.c_void_p(a.data_ptr()) for a in arrs]
+            on_dev = 1
+        else:
+            arrs = [np.ascontiguousarray(x, np.float32), np.ascontiguousarray(y, np.float32),
+                    np.ascontiguousarray(z, np.float32), np.ascontiguousarray(module, np.int32),
+                    np.ascontiguousarray(sensor, np.uint8)]
+            ptrs = [_np_ptr(a) for a in arrs]
+            on_dev = 0
+        self._keep = [offsets] + arrs       # host buffers must outlive the async copies
+        self._check(self.lib.lst_load_hits(self.h, n_ev, _np_ptr(offsets), *ptrs, on_dev,
+                                           self._stream(stream)))
+        self.n_events = n_ev
+
+    # -- stages -------------------------------------------------------------
+    def run_sort(self, stream=None):
+        self._check(self.lib.lst_run_sort(self.h, self._stream(stream)))
+
+    def run_md(self, stream=None):
+        self._check(self.lib.lst_run_md(self.h, self._stream(stream)))
+
+    def run_segments(self, stream=None):
+        self._check(self.lib.lst_run_segments(self.h, self._stream(stream)))
+
+    def run_triplets(self, stream=None):
+        self._check(self.lib.lst_run_triplets(self.h, self._stream(stream)))
+
+    def run_quintuplets(self, stream=None):
+        self._check(self.lib.lst_run_quintuplets(self.h, self._stream(stream)))
+
+    def run_chain(self, stream=None):
+        self._check(self.lib.lst_run_chain(self.h, self._stream(stream)))
+
+    # -- outputs ------------------------------------------------------------
+    def counts(self, event=0, stream=None, check=True) -> dict:
+        c = lst_counts()
+        rc = self.lib.lst_get_counts(self.h, event, ctypes.byref(c), self._stream(stream))
+        if check:
+            self._check(rc)
+        d = c.as_dict()
+        d["rc"] = rc
+        return d
+
+    def objects(self, event, kind, stream=None) -> np.ndarray:
+        n = ctypes.c_int64(0)
+        rc = self.lib.lst_get_objects(self.h, event, kind, None, 0, ctypes.byref(n), self._stream(stream))
+        if rc not in (LST_OK, LST_E_CAPACITY):
+            self._check(rc)
+        out = np.zeros((max(n.value, 1), WIDTH[kind]), np.int32)
+        self._check(self.lib.lst_get_objects(self.h, event, kind, _np_ptr(out), n.value,
+                                             ctypes.byref(n), self._stream(stream)))
+        return out[:n.value]
+
+    def t5_scores(self, event, stream=None) -> np.ndarray:
+        n = ctypes.c_int64(0)
+        rc = self.lib.lst_get_t5_scores(self.h, event, None, 0, ctypes.byref(n), self._stream(stream))
+        if rc not in (LST_OK, LST_E_CAPACITY):
+            self._check(rc)
+        out = np.zeros(max(n.value, 1), np.float32)
+        self._check(self.lib.lst_get_t5_scores(self.h, event, _np_ptr(out), n.value,
+                                               ctypes.byref(n), self._stream(stream)))
+        return out[:n.value]
+
+    def run_batch(self, offsets, x, y, z, module, sensor, stream=None, max_retry=3):
+        """Load, run the chain and grow the arena to the reported need on overflow."""
+        for _ in range(max_retry):
+            self.load_hits(offsets, x, y, z, module, sensor, stream)
+            self.run_chain(stream)
+            c = lst_counts()
+            worst = {"md": 0, "seg": 0, "t3": 0, "t5": 0}
+            ovf = False
+            for e in range(self.n_events):
+                rc = self.lib.lst_get_counts(self.h, e, ctypes.byref(c), self._stream(stream))
+                if rc == LST_E_CAPACITY:
+                    ovf = True
+                elif rc != LST_OK:
+                    self._check(rc)
+            if not ovf:
+                return
+            # totals over the batch: per-event sums
+            tot = {"md": 0, "seg": 0, "t3": 0, "t5": 0}
+            for e in range(self.n_events):
+                self.lib.lst_get_counts(self.h, e, ctypes.byref(c), self._stream(stream))
+                tot["md"] += c.n_md; tot["seg"] += c.n_seg; tot["t3"] += c.n_t3; tot["t5"] += c.n_t5
+            caps = dict(self.caps)
+            for k in worst:
+                caps[k] = max(caps[k], int(tot[k] * 1.25) + 1024)
+            self.reserve(caps)
+        raise LSTError(LST_E_CAPACITY, "capacity still exceeded after growing the arena")
+
+    def run_event(self, ev, stream=None):
+        offs = np.array([0, ev.n_hits], np.int32)
+        self.run_batch(offs, ev.x, ev.y, ev.z, ev.module, ev.sensor, stream)
+        return {k: self.objects(0, k, stream) for k in WIDTH}

@@ -1,0 +1,154 @@
+"""Parity of the HIP chain with the CPU oracle (run with -m gpu on an MI355X).
+
+Object sets are compared as sorted hit-index tuples per stage; the only
+allowed mismatches are decisions whose FP64 margin is below 1e-5 and their
+descendants (none are expected: both sides round every FP32 operation the
+same way).  Candidate counts are integers and must match exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import events as E
+from synth import geometry as G
+from synth import params as PR
+from tests.parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(geo, params):
+    import paper_2209_13711_amd as lst
+    return lst.Context(params, geo.f32, geo.i32, device=0)
+
+
+def _run_both(cid, event=0, n_tracks=None, params=None):
+    cfg = E.CONFIGS[cid]
+    geo = G.get(cfg.geometry)
+    params = PR.make(w=cfg.window) if params is None else params
+    ev = E.generate(cid, event, n_tracks=n_tracks)
+    print(f"case cfg{cid} event {event} hits {ev.n_hits}", flush=True)
+    ctx = _ctx(geo, params)
+    got = ctx.run_event(ev)
+    cnt = ctx.counts(0)
+    ref = oracle.Oracle(params, geo.f32, geo.i32).run_event(ev)
+    return ctx, got, cnt, ref, ev
+
+
+@pytest.mark.parametrize("cid,event,n_tracks", [(1, 0, None), (1, 1, None), (2, 0, 600),
+                                                (2, 0, None), (5, 0, 800)])
+def test_chain_matches_oracle(cid, event, n_tracks):
+    ctx, got, cnt, ref, ev = _run_both(cid, event, n_tracks)
+    assert_parity(got, ref)
+    # algorithmic candidate counts are exact integers
+    assert [cnt["cand_md"], cnt["cand_seg"], cnt["cand_t3"], cnt["cand_t5"]] == ref.cands.tolist()
+    assert cnt["n_t5_kept"] == len(ref.tuples[4])
+
+
+def test_t5_scores_bitwise():
+    ctx, got, cnt, ref, ev = _run_both(2, 1, 1500)
+    s_gpu = ctx.t5_scores(0)
+    t_gpu = ctx.objects(0, 3)
+    gmap = {tuple(t): s for t, s in zip(t_gpu.tolist(), s_gpu.view(np.uint32).tolist())}
+    omap = {tuple(t): s for t, s in zip(ref.tuples[3].tolist(), ref.t5_scores.view(np.uint32).tolist())}
+    assert gmap.keys() == omap.keys()
+    assert all(gmap[k] == omap[k] for k in gmap)
+
+
+def test_batch_of_uneven_events_matches_per_event_oracle():
+    cfg = E.CONFIGS[3]
+    geo = G.get(cfg.geometry)
+    params = PR.make()
+    evs = [E.generate(3, e) for e in range(4)]
+    b = E.concat(evs)
+    print("case batch cfg3 x4 hits", b.offsets.tolist(), flush=True)
+    ctx = _ctx(geo, params)
+    ctx.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+    orc = oracle.Oracle(params, geo.f32, geo.i32)
+    for e, ev in enumerate(evs):
+        got = {k: ctx.objects(e, k) for k in range(5)}
+        ref = orc.run_event(ev)
+        assert_parity(got, ref)
+        cnt = ctx.counts(e)
+        assert [cnt["cand_md"], cnt["cand_seg"], cnt["cand_t3"], cnt["cand_t5"]] == ref.cands.tolist()
+
+
+def test_empty_and_degenerate_events():
+    geo = G.get("barrel_toy")
+    params = PR.make()
+    ctx = _ctx(geo, params)
+    print("case empty", flush=True)
+    z = np.zeros(0, np.float32)
+    ctx.run_batch(np.array([0, 0], np.int32), z, z, z, np.zeros(0, np.int32), np.zeros(0, np.uint8))
+    for k in range(5):
+        assert len(ctx.objects(0, k)) == 0
+    # hits on lower sensors only: no mini-doublet can form
+    ev = E.generate(1, 2)
+    lo = ev.sensor == 0
+    print("case lower-only", flush=True)
+    ctx.run_batch(np.array([0, int(lo.sum())], np.int32), ev.x[lo], ev.y[lo], ev.z[lo],
+                  ev.module[lo], ev.sensor[lo])
+    assert len(ctx.objects(0, 0)) == 0
+    # an event between two empty ones
+    print("case ragged batch", flush=True)
+    offs = np.array([0, 0, ev.n_hits, ev.n_hits], np.int32)
+    ctx.run_batch(offs, ev.x, ev.y, ev.z, ev.module, ev.sensor)
+    ref = oracle.Oracle(params, geo.f32, geo.i32).run_event(ev)
+    assert_parity({k: ctx.objects(1, k) for k in range(5)}, ref)
+    assert len(ctx.objects(0, 0)) == 0 and len(ctx.objects(2, 0)) == 0
+
+
+def test_invalid_hits_are_flagged_and_skipped():
+    geo = G.get("barrel_toy")
+    params = PR.make()
+    ctx = _ctx(geo, params)
+    ev = E.generate(1, 3)
+    mod = ev.module.copy()
+    mod[0] = geo.n_mod + 5          # out of range
+    sen = ev.sensor.copy()
+    sen[1] = 7                       # bad sensor id
+    print("case invalid ids", flush=True)
+    ctx.run_batch(np.array([0, ev.n_hits], np.int32), ev.x, ev.y, ev.z, mod, sen)
+    c = ctx.counts(0)
+    assert c["error_flags"] & 1
+    keep = np.ones(ev.n_hits, bool); keep[:2] = False
+    ref = oracle.Oracle(params, geo.f32, geo.i32).run(ev.x[keep], ev.y[keep], ev.z[keep],
+                                                       ev.module[keep], ev.sensor[keep])
+    # oracle indices refer to the filtered arrays: map them back
+    back = np.nonzero(keep)[0]
+    for k in range(5):
+        ref.tuples[k] = back[ref.tuples[k]] if len(ref.tuples[k]) else ref.tuples[k]
+    for k in range(4):
+        if len(ref.near[k][0]):
+            ref.near[k] = (back[ref.near[k][0]], ref.near[k][1], ref.near[k][2])
+    assert_parity({k: ctx.objects(0, k) for k in range(5)}, ref)
+
+
+def test_capacity_overflow_is_reported_then_recovered():
+    import paper_2209_13711_amd as lst
+    geo = G.get("barrel_toy")
+    params = PR.make()
+    ctx = _ctx(geo, params)
+    ev = E.generate(1, 4)
+    print("case tiny capacity", flush=True)
+    ctx.reserve(dict(events=1, hits=ev.n_hits, md=64, seg=64, t3=64, t5=64))
+    ctx.load_hits(np.array([0, ev.n_hits], np.int32), ev.x, ev.y, ev.z, ev.module, ev.sensor)
+    ctx.run_chain()
+    c = ctx.counts(0, check=False)
+    assert c["rc"] == lst.lst.LST_E_CAPACITY and c["overflow_mask"] & 1
+    assert c["n_md"] > 64
+    with pytest.raises(lst.LSTError):
+        ctx.objects(0, 0)
+    got = ctx.run_event(ev)
+    ref = oracle.Oracle(params, geo.f32, geo.i32).run_event(ev)
+    assert_parity(got, ref)
+
+
+def test_module_map_on_device_context_equals_oracle():
+    geo = G.get("full")
+    params = PR.make()
+    ctx = _ctx(geo, params)
+    ptr, col = ctx.module_map()
+    optr, ocol = oracle.Oracle(params, geo.f32, geo.i32).module_map()
+    np.testing.assert_array_equal(ptr, optr)
+    np.testing.assert_array_equal(col, ocol)
