@@ -91,9 +91,10 @@ typedef struct {
     int64_t t5;
 } lst_caps;
 
-/* per-event result summary.  n_* are the numbers of objects required, also
- * when they exceeded capacity; cand_* are the algorithmic candidate counts
- * (pairs evaluated by each stage).  overflow_mask bit k = stage k (MD, SEG,
+/* per-event result summary.  n_* are the numbers of objects and cand_* the
+ * algorithmic candidate counts (pairs evaluated by each stage).  When a stage
+ * ran out of capacity (LST_E_CAPACITY) the arrays are incomplete and every
+ * event reports instead the batch-wide number of MD/SEG/T3/T5 required.  overflow_mask bit k = stage k (MD, SEG,
  * T3, T5) ran out of capacity; error_flags bit 0 = a hit with an invalid
  * module or sensor id was skipped. */
 typedef struct {
@@ -148,14 +149,17 @@ int lst_load_hits(lst_ctx *ctx, int32_t n_events, const int32_t *hit_offsets, co
  * lst_run_md        mini-doublets (stubs), Sec. 2
  * lst_run_segments  segments over map edges, Sec. 2.1
  * lst_run_triplets  triplets: segment pairs sharing a mini-doublet, Sec. 2.1
- * lst_run_quintuplets quintuplets: triplet pairs sharing a mini-doublet, then
- *                   removal of quintuplets sharing hits, Sec. 2.1
+ * lst_run_quintuplets quintuplets: triplet pairs sharing a mini-doublet, Sec. 2.1
+ * lst_run_dedup     removal of quintuplets sharing hits (Sec. 2.1: objects
+ *                   must not share hits): a quintuplet survives when, for each
+ *                   of its hits, it has the smallest (score, hit tuple) key
  * lst_run_chain     all of the above in one call. */
 int lst_run_sort(lst_ctx *ctx, void *stream);
 int lst_run_md(lst_ctx *ctx, void *stream);
 int lst_run_segments(lst_ctx *ctx, void *stream);
 int lst_run_triplets(lst_ctx *ctx, void *stream);
 int lst_run_quintuplets(lst_ctx *ctx, void *stream);
+int lst_run_dedup(lst_ctx *ctx, void *stream);
 int lst_run_chain(lst_ctx *ctx, void *stream);
 
 /* Synchronise `stream`, then report event `event` (0..n_events-1).  Returns

@@ -46,7 +46,9 @@ struct lst_ctx {
     // batch
     int n_events = 0;
     std::vector<int32_t> hit_off;
-    int stage = 0;  // 0 nothing, 1 hits loaded, 2 sorted, 3 md, 4 seg, 5 t3, 6 t5+dedup
+    std::vector<lst_counts> counts;
+    bool counts_valid = false;
+    int stage = 0;  // 0 nothing, 1 hits loaded, 2 sorted, 3 md, 4 seg, 5 t3, 6 t5, 7 dedup
 };
 
 static int fail(lst_ctx *c, int code, const char *fmt, ...)
@@ -133,7 +135,6 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     // region cleared at the start of every chain
     size_t z0 = (cv.off + 255) & ~(size_t)255;
     E.gc = cv.take<int32_t>(GC_COUNT);
-    E.evc = cv.take<unsigned long long>((size_t)k.events * EC_COUNT * NSHARD);
     E.bcnt = cv.take<uint32_t>(keys);
     size_t z1 = (cv.off + 255) & ~(size_t)255;
     if (zero_base) *zero_base = base ? base + z0 : nullptr;
@@ -154,6 +155,7 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.sorig = cv.take<int32_t>(k.hits);
     E.hmin = cv.take<uint32_t>(k.hits);
     E.htie = cv.take<int32_t>(k.hits);
+    E.hslot = cv.take<int32_t>((size_t)k.hits * TIE_SLOTS);
     // MD
     E.md_hlo = cv.take<int32_t>(k.md);
     E.md_hup = cv.take<int32_t>(k.md);
@@ -410,6 +412,7 @@ static int need_stage(lst_ctx *c, int s, const char *what)
 {
     if (!c) return LST_E_INVALID;
     if (c->stage < s) return fail(c, LST_E_STATE, "%s called out of order", what);
+    c->counts_valid = false;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, LST_E_HIP, "hipSetDevice");
     return LST_OK;
 }
@@ -456,10 +459,17 @@ int lst_run_quintuplets(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 5, "lst_run_quintuplets");
     if (rc) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    HIPCHK(c, launch_t5(c->E, c->M, c->K, s));
-    HIPCHK(c, launch_dedup(c->E, c->M, s));
+    HIPCHK(c, launch_t5(c->E, c->M, c->K, (hipStream_t)stream));
     c->stage = 6;
+    return LST_OK;
+}
+
+int lst_run_dedup(lst_ctx *c, void *stream)
+{
+    int rc = need_stage(c, 6, "lst_run_dedup");
+    if (rc) return rc;
+    HIPCHK(c, launch_dedup(c->E, c->M, (hipStream_t)stream));
+    c->stage = 7;
     return LST_OK;
 }
 
@@ -470,7 +480,8 @@ int lst_run_chain(lst_ctx *c, void *stream)
     if ((rc = lst_run_md(c, stream))) return rc;
     if ((rc = lst_run_segments(c, stream))) return rc;
     if ((rc = lst_run_triplets(c, stream))) return rc;
-    return lst_run_quintuplets(c, stream);
+    if ((rc = lst_run_quintuplets(c, stream))) return rc;
+    return lst_run_dedup(c, stream);
 }
 
 // ---------------------------------------------------------------- results
@@ -482,6 +493,79 @@ static int sync_stream(lst_ctx *c, void *stream)
     return LST_OK;
 }
 
+// Per-event statistics, reduced on the host from the device arrays (the
+// reporting path; the stage kernels carry no statistics atomics).
+static int compute_counts(lst_ctx *c)
+{
+    const EvDev &E = c->E;
+    const int n_ev = c->n_events, nm = c->n_mod;
+    int32_t gc[GC_COUNT];
+    HIPCHK(c, hipMemcpy(gc, E.gc, sizeof(gc), hipMemcpyDeviceToHost));
+    c->counts.assign(n_ev, lst_counts{});
+    for (int e = 0; e < n_ev; ++e) {
+        c->counts[e].n_hits = c->hit_off[e + 1] - c->hit_off[e];
+        c->counts[e].overflow_mask = gc[GC_OVERFLOW];
+        c->counts[e].error_flags = gc[GC_ERROR];
+    }
+    if (gc[GC_OVERFLOW]) {
+        // arrays are incomplete: report the batch-wide requirement instead
+        for (auto &k : c->counts) {
+            k.n_md = gc[GC_MD]; k.n_seg = gc[GC_SEG]; k.n_t3 = gc[GC_T3]; k.n_t5 = gc[GC_T5];
+        }
+        c->counts_valid = true;
+        return LST_OK;
+    }
+    const size_t slots = (size_t)n_ev * nm;
+    std::vector<uint32_t> boff;
+    std::vector<int32_t> mds, mdc, mslot, ss, sc, so, ts, tc, tcc, t50;
+    std::vector<uint8_t> keep;
+    int rc;
+    const size_t nmd = gc[GC_MD], nseg = gc[GC_SEG], nt3 = gc[GC_T3], nt5 = gc[GC_T5];
+    if ((rc = d2h(c, boff, E.boff, 2 * slots + 1)) || (rc = d2h(c, mds, E.md_start, slots)) ||
+        (rc = d2h(c, mdc, E.md_cnt, slots)))
+        return rc;
+    if (c->stage >= 3 && (rc = d2h(c, mslot, E.md_slot, nmd))) return rc;
+    if (c->stage >= 4 && ((rc = d2h(c, ss, E.seg_start, nmd)) || (rc = d2h(c, sc, E.seg_cnt, nmd)) ||
+                          (rc = d2h(c, so, E.seg_out, nseg))))
+        return rc;
+    if (c->stage >= 5 && ((rc = d2h(c, ts, E.t3_start, nmd)) || (rc = d2h(c, tc, E.t3_cnt, nmd)) ||
+                          (rc = d2h(c, tcc, E.t3_c, nt3))))
+        return rc;
+    if (c->stage >= 6 && (rc = d2h(c, t50, E.t5_md0, nt5))) return rc;
+    if (c->stage >= 7 && (rc = d2h(c, keep, E.t5_keep, nt5))) return rc;
+    for (int e = 0; e < n_ev; ++e) {
+        lst_counts &k = c->counts[e];
+        for (int m = 0; m < nm; ++m) {
+            const size_t sl = (size_t)e * nm + m;
+            const int64_t nlo = boff[2 * sl + 1] - boff[2 * sl];
+            const int64_t nup = boff[2 * sl + 2] - boff[2 * sl + 1];
+            k.cand_md += nlo * nup;
+            if (c->stage < 3) continue;
+            k.n_md += mdc[sl];
+            if (mdc[sl] == 0) continue;
+            int64_t outer = 0;
+            for (int32_t q = c->map_ptr[m]; q < c->map_ptr[m + 1]; ++q)
+                outer += mdc[(size_t)e * nm + c->map_col[q]];
+            k.cand_seg += (int64_t)mdc[sl] * outer;
+            for (int32_t a = mds[sl]; a < mds[sl] + mdc[sl]; ++a) {
+                if (c->stage < 4) break;
+                k.n_seg += sc[a];
+                for (int32_t s1 = ss[a]; s1 < ss[a] + sc[a]; ++s1) k.cand_t3 += sc[so[s1]];
+                if (c->stage < 5) continue;
+                k.n_t3 += tc[a];
+                for (int32_t t1 = ts[a]; t1 < ts[a] + tc[a]; ++t1) k.cand_t5 += tc[tcc[t1]];
+            }
+        }
+    }
+    for (size_t t = 0; c->stage >= 6 && t < nt5; ++t) {
+        const int e = mslot[t50[t]] / nm;
+        c->counts[e].n_t5++;
+        if (c->stage >= 7) c->counts[e].n_t5_kept += keep[t];
+    }
+    c->counts_valid = true;
+    return LST_OK;
+}
+
 int lst_get_counts(lst_ctx *c, int32_t event, lst_counts *out, void *stream)
 {
     if (!c || !out) return LST_E_INVALID;
@@ -489,36 +573,14 @@ int lst_get_counts(lst_ctx *c, int32_t event, lst_counts *out, void *stream)
     if (event < 0 || event >= c->n_events) return fail(c, LST_E_INVALID, "event %d", event);
     int rc = sync_stream(c, stream);
     if (rc) return rc;
-    int32_t gc[GC_COUNT];
-    std::vector<unsigned long long> ev((size_t)EC_COUNT * NSHARD);
-    HIPCHK(c, hipMemcpy(gc, c->E.gc, sizeof(gc), hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(ev.data(), c->E.evc + (size_t)event * EC_COUNT * NSHARD,
-                        ev.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
-    int64_t v[EC_COUNT];
-    for (int k = 0; k < EC_COUNT; ++k) {
-        unsigned long long s = 0;
-        for (int j = 0; j < NSHARD; ++j) s += ev[(size_t)k * NSHARD + j];
-        v[k] = (int64_t)s;
-    }
-    std::memset(out, 0, sizeof(*out));
-    out->n_hits = c->hit_off[event + 1] - c->hit_off[event];
-    out->n_md = v[EC_N_MD];
-    out->n_seg = v[EC_N_SEG];
-    out->n_t3 = v[EC_N_T3];
-    out->n_t5 = v[EC_N_T5];
-    out->n_t5_kept = v[EC_N_KEPT];
-    out->cand_md = v[EC_CAND_MD];
-    out->cand_seg = v[EC_CAND_SEG];
-    out->cand_t3 = v[EC_CAND_T3];
-    out->cand_t5 = v[EC_CAND_T5];
-    out->overflow_mask = gc[GC_OVERFLOW];
-    out->error_flags = gc[GC_ERROR];
-    if (gc[GC_OVERFLOW])
-        return fail(c, LST_E_CAPACITY, "capacity overflow (mask %d): MD %d SEG %d T3 %d T5 %d needed",
-                    gc[GC_OVERFLOW], gc[GC_MD], gc[GC_SEG], gc[GC_T3], gc[GC_T5]);
+    if (!c->counts_valid && (rc = compute_counts(c))) return rc;
+    *out = c->counts[event];
+    if (out->overflow_mask)
+        return fail(c, LST_E_CAPACITY, "capacity overflow (mask %d): MD %lld SEG %lld T3 %lld T5 %lld needed",
+                    out->overflow_mask, (long long)out->n_md, (long long)out->n_seg,
+                    (long long)out->n_t3, (long long)out->n_t5);
     return LST_OK;
 }
-
 
 int lst_get_objects(lst_ctx *c, int32_t event, int32_t kind, int32_t *out, int64_t cap,
                     int64_t *n_tuples, void *stream)
@@ -526,7 +588,7 @@ int lst_get_objects(lst_ctx *c, int32_t event, int32_t kind, int32_t *out, int64
     if (!c) return LST_E_INVALID;
     if (kind < LST_MD || kind > LST_T5_KEPT) return fail(c, LST_E_INVALID, "kind %d", kind);
     if (event < 0 || event >= c->n_events) return fail(c, LST_E_INVALID, "event %d", event);
-    const int need = kind == LST_MD ? 3 : kind == LST_SEG ? 4 : kind == LST_T3 ? 5 : 6;
+    const int need = kind == LST_MD ? 3 : kind == LST_SEG ? 4 : kind == LST_T3 ? 5 : kind == LST_T5 ? 6 : 7;
     if (c->stage < need) return fail(c, LST_E_STATE, "stage for kind %d has not run", kind);
     int rc = sync_stream(c, stream);
     if (rc) return rc;

@@ -18,14 +18,6 @@ struct Consts {
     float z0max, sigu, sigv, nsig, d0max, w, w2, xrphi, xrz;
 };
 
-// Per-event counters, each spread over NSHARD shards to avoid one hot address.
-enum EvCounter {
-    EC_CAND_MD = 0, EC_CAND_SEG, EC_CAND_T3, EC_CAND_T5,
-    EC_N_MD, EC_N_SEG, EC_N_T3, EC_N_T5, EC_N_KEPT, EC_N_HITS,
-    EC_COUNT
-};
-constexpr int NSHARD = 16;
-
 // Global counters (int32 unless noted).
 enum GlobalCounter {
     GC_MD = 0, GC_SEG, GC_T3, GC_T5, GC_OVERFLOW, GC_ERROR, GC_N_SORTED, GC_PAD,
@@ -56,6 +48,7 @@ struct EvDev {
     int32_t *sorig;          // per-event index of each sorted hit
     uint32_t *hmin;          // dedup: smallest quintuplet score bits per sorted hit
     int32_t *htie;           // dedup: how many quintuplets reach that score
+    int32_t *hslot;          // dedup: [n_hits][TIE_SLOTS] quintuplets reaching it
     // mini-doublets
     int32_t *md_hlo, *md_hup, *md_slot;
     float *md_x, *md_y, *md_z, *md_r, *md_a, *md_ca, *md_dx, *md_dy, *md_dn, *md_bend, *md_sv;
@@ -74,9 +67,9 @@ struct EvDev {
     uint8_t *t5_keep;
     // counters (zeroed at chain start)
     int32_t *gc;                     // [GC_COUNT]
-    unsigned long long *evc;         // [n_ev][EC_COUNT][NSHARD]
 };
 
+constexpr int TIE_SLOTS = 8;
 constexpr int BLOCK = 256;           // 4 waves of 64
 constexpr int WAVES = BLOCK / 64;
 

@@ -46,11 +46,6 @@ __device__ __forceinline__ int wave_find(uint32_t incl, uint32_t j)
     return lo;
 }
 
-__device__ __forceinline__ void ev_add(const EvDev &E, int ev, int which, unsigned long long v)
-{
-    if (v) atomicAdd(&E.evc[((size_t)ev * EC_COUNT + which) * NSHARD + (blockIdx.x % NSHARD)], v);
-}
-
 // Block-wide reservation: every thread of the block must call it.  Returns
 // the first output index of the calling wave; `ovf` is set for every wave of
 // the block when the block's range does not fit the capacity.
@@ -130,7 +125,6 @@ __global__ void k_hist(EvDev E, int n_mod)
         return;
     }
     atomicAdd(&E.bcnt[key], 1u);
-    ev_add(E, ev, EC_N_HITS, 1);
 }
 
 // exclusive scan of bcnt[0..n) into boff[0..n], three phases over tiles of 1024
@@ -281,9 +275,6 @@ __global__ __launch_bounds__(BLOCK) void k_md(EvDev E, ModDev M, Consts K)
     if (lane == 0) {
         E.md_start[slot] = (int32_t)off;
         E.md_cnt[slot] = ovf ? 0 : (int32_t)cnt;
-        int ev = slot / M.n_mod;
-        ev_add(E, ev, EC_CAND_MD, np);
-        ev_add(E, ev, EC_N_MD, cnt);
     }
     if (ovf || cnt == 0) return;
     uint32_t pos = off;
@@ -398,14 +389,10 @@ __global__ __launch_bounds__(BLOCK) void k_seg(EvDev E, ModDev M, Consts K)
     const bool act = slot < E.n_slots;
     unsigned long long cand = 0;
     uint32_t cnt = act ? seg_slot<false>(E, M, K, slot, 0, &cand) : 0u;
+    (void)cand;
     bool ovf;
     uint32_t off = block_reserve(cnt, &E.gc[GC_SEG], E.cap_seg, E.gc, 1, ovf);
     if (!act) return;
-    if (lane_id() == 0) {
-        int ev = slot / M.n_mod;
-        ev_add(E, ev, EC_CAND_SEG, cand);
-        ev_add(E, ev, EC_N_SEG, cnt);
-    }
     if (ovf) {
         const int32_t sA = E.md_start[slot], nA = E.md_cnt[slot];
         for (int32_t ii = lane_id(); ii < nA; ii += 64) {
@@ -493,14 +480,10 @@ __global__ __launch_bounds__(BLOCK) void k_t3(EvDev E, ModDev M, Consts K)
     const bool act = slot < E.n_slots;
     unsigned long long cand = 0;
     uint32_t cnt = act ? t3_slot<false>(E, K, slot, 0, &cand) : 0u;
+    (void)cand;
     bool ovf;
     uint32_t off = block_reserve(cnt, &E.gc[GC_T3], E.cap_t3, E.gc, 2, ovf);
     if (!act) return;
-    if (lane_id() == 0) {
-        int ev = slot / M.n_mod;
-        ev_add(E, ev, EC_CAND_T3, cand);
-        ev_add(E, ev, EC_N_T3, cnt);
-    }
     if (ovf) {
         const int32_t sA = E.md_start[slot], nA = E.md_cnt[slot];
         for (int32_t ii = lane_id(); ii < nA; ii += 64) {
@@ -593,14 +576,10 @@ __global__ __launch_bounds__(BLOCK) void k_t5(EvDev E, ModDev M, Consts K)
     const bool act = slot < E.n_slots;
     unsigned long long cand = 0;
     uint32_t cnt = act ? t5_slot<false>(E, K, slot, 0, &cand) : 0u;
+    (void)cand;
     bool ovf;
     uint32_t off = block_reserve(cnt, &E.gc[GC_T5], E.cap_t5, E.gc, 3, ovf);
     if (!act) return;
-    if (lane_id() == 0) {
-        int ev = slot / M.n_mod;
-        ev_add(E, ev, EC_CAND_T5, cand);
-        ev_add(E, ev, EC_N_T5, cnt);
-    }
     if (ovf) return;
     t5_slot<true>(E, K, slot, off, nullptr);
 }
@@ -649,6 +628,10 @@ __global__ void k_dedup_min(EvDev E)
     }
 }
 
+// Quintuplets reaching a hit's minimum score are recorded in TIE_SLOTS
+// per-hit slots; exact score ties are common (two quintuplets that differ
+// only in the upper hit of one mini-doublet have the same anchors, hence the
+// same score) and are resolved by the hit tuple.
 __global__ void k_dedup_tie(EvDev E)
 {
     const int32_t n = n_t5(E);
@@ -656,7 +639,10 @@ __global__ void k_dedup_tie(EvDev E)
         uint32_t key = __float_as_uint(E.t5_score[t]);
         for (int j = 0; j < 10; ++j) {
             int32_t h = t5_hit(E, t, j);
-            if (E.hmin[h] == key) atomicAdd(&E.htie[h], 1);
+            if (E.hmin[h] == key) {
+                int k = atomicAdd(&E.htie[h], 1);
+                if (k < TIE_SLOTS) E.hslot[(size_t)h * TIE_SLOTS + k] = t;
+            }
         }
     }
 }
@@ -671,19 +657,27 @@ __device__ __forceinline__ bool tuple_less(const EvDev &E, int32_t u, int32_t t)
     return false;
 }
 
-__global__ void k_dedup_keep(EvDev E, int n_mod)
+__global__ void k_dedup_keep(EvDev E)
 {
     const int32_t n = n_t5(E);
     for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-        uint32_t key = __float_as_uint(E.t5_score[t]);
+        const float sc = E.t5_score[t];
+        const uint32_t key = __float_as_uint(sc);
         bool keep = true;
         for (int j = 0; j < 10 && keep; ++j) {
             int32_t h = t5_hit(E, t, j);
             if (E.hmin[h] != key) { keep = false; break; }
-            if (E.htie[h] > 1) {
-                // rare exact tie in score: the smaller hit tuple wins
+            const int nt = E.htie[h];
+            if (nt <= 1) continue;
+            if (nt <= TIE_SLOTS) {
+                for (int k = 0; k < nt && keep; ++k) {
+                    int32_t u = E.hslot[(size_t)h * TIE_SLOTS + k];
+                    if (u != t && tuple_less(E, u, t)) keep = false;
+                }
+            } else {
+                // more ties than slots: scan every quintuplet (never seen in practice)
                 for (int32_t u = 0; u < n && keep; ++u) {
-                    if (u == t || E.t5_score[u] != E.t5_score[t]) continue;
+                    if (u == t || E.t5_score[u] != sc) continue;
                     bool uses = false;
                     for (int k = 0; k < 10; ++k) uses |= (t5_hit(E, u, k) == h);
                     if (uses && tuple_less(E, u, t)) keep = false;
@@ -691,10 +685,6 @@ __global__ void k_dedup_keep(EvDev E, int n_mod)
             }
         }
         E.t5_keep[t] = keep ? 1 : 0;
-        if (keep) {
-            int ev = E.md_slot[E.t5_md0[t]] / n_mod;
-            atomicAdd(&E.evc[((size_t)ev * EC_COUNT + EC_N_KEPT) * NSHARD + (t % NSHARD)], 1ull);
-        }
     }
 }
 
@@ -703,7 +693,7 @@ hipError_t launch_dedup(const EvDev &E, const ModDev &M, hipStream_t s)
     int blocks = 1024;
     hipLaunchKernelGGL(k_dedup_min, dim3(blocks), dim3(BLOCK), 0, s, E);
     hipLaunchKernelGGL(k_dedup_tie, dim3(blocks), dim3(BLOCK), 0, s, E);
-    hipLaunchKernelGGL(k_dedup_keep, dim3(blocks), dim3(BLOCK), 0, s, E, M.n_mod);
+    hipLaunchKernelGGL(k_dedup_keep, dim3(blocks), dim3(BLOCK), 0, s, E);
     return hipGetLastError();
 }
 

@@ -63,6 +63,7 @@ _SIGS = {
     "lst_run_segments": (ctypes.c_int, [_P, _P]),
     "lst_run_triplets": (ctypes.c_int, [_P, _P]),
     "lst_run_quintuplets": (ctypes.c_int, [_P, _P]),
+    "lst_run_dedup": (ctypes.c_int, [_P, _P]),
     "lst_run_chain": (ctypes.c_int, [_P, _P]),
     "lst_get_counts": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(lst_counts), _P]),
     "lst_get_objects": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64,
@@ -218,6 +219,9 @@ class Context:
     def run_quintuplets(self, stream=None):
         self._check(self.lib.lst_run_quintuplets(self.h, self._stream(stream)))
 
+    def run_dedup(self, stream=None):
+        self._check(self.lib.lst_run_dedup(self.h, self._stream(stream)))
+
     def run_chain(self, stream=None):
         self._check(self.lib.lst_run_chain(self.h, self._stream(stream)))
 
@@ -257,7 +261,6 @@ class Context:
             self.load_hits(offsets, x, y, z, module, sensor, stream)
             self.run_chain(stream)
             c = lst_counts()
-            worst = {"md": 0, "seg": 0, "t3": 0, "t5": 0}
             ovf = False
             for e in range(self.n_events):
                 rc = self.lib.lst_get_counts(self.h, e, ctypes.byref(c), self._stream(stream))
@@ -267,13 +270,11 @@ class Context:
                     self._check(rc)
             if not ovf:
                 return
-            # totals over the batch: per-event sums
-            tot = {"md": 0, "seg": 0, "t3": 0, "t5": 0}
-            for e in range(self.n_events):
-                self.lib.lst_get_counts(self.h, e, ctypes.byref(c), self._stream(stream))
-                tot["md"] += c.n_md; tot["seg"] += c.n_seg; tot["t3"] += c.n_t3; tot["t5"] += c.n_t5
+            # on overflow every event reports the batch-wide requirement
+            self.lib.lst_get_counts(self.h, 0, ctypes.byref(c), self._stream(stream))
+            tot = {"md": c.n_md, "seg": c.n_seg, "t3": c.n_t3, "t5": c.n_t5}
             caps = dict(self.caps)
-            for k in worst:
+            for k in tot:
                 caps[k] = max(caps[k], int(tot[k] * 1.25) + 1024)
             self.reserve(caps)
         raise LSTError(LST_E_CAPACITY, "capacity still exceeded after growing the arena")
