@@ -128,13 +128,16 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.n_slots = (int32_t)slots;
     E.n_keys = (int32_t)keys;
     E.cap_hits = k.hits;
-    E.cap_md = k.md;
-    E.cap_seg = k.seg;
-    E.cap_t3 = k.t3;
-    E.cap_t5 = k.t5;
+    const int64_t caps[OT_COUNT] = {k.md, k.seg, k.t3, k.t5};
+    size_t span[OT_COUNT];
+    for (int t = 0; t < OT_COUNT; ++t) {
+        E.rc[t] = (uint32_t)std::max<int64_t>(1, (caps[t] + NSH - 1) / NSH);
+        span[t] = (size_t)E.rc[t] * NSH;
+    }
+    const size_t nmd = span[OT_MD], nseg = span[OT_SEG], nt3 = span[OT_T3], nt5 = span[OT_T5];
     // region cleared at the start of every chain
     size_t z0 = (cv.off + 255) & ~(size_t)255;
-    E.gc = cv.take<int32_t>(GC_COUNT);
+    E.gc = cv.take<uint32_t>(GC_COUNT);
     E.bcnt = cv.take<uint32_t>(keys);
     size_t z1 = (cv.off + 255) & ~(size_t)255;
     if (zero_base) *zero_base = base ? base + z0 : nullptr;
@@ -157,43 +160,43 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.htie = cv.take<int32_t>(k.hits);
     E.hslot = cv.take<int32_t>((size_t)k.hits * TIE_SLOTS);
     // MD
-    E.md_hlo = cv.take<int32_t>(k.md);
-    E.md_hup = cv.take<int32_t>(k.md);
-    E.md_slot = cv.take<int32_t>(k.md);
-    E.md_x = cv.take<float>(k.md);
-    E.md_y = cv.take<float>(k.md);
-    E.md_z = cv.take<float>(k.md);
-    E.md_r = cv.take<float>(k.md);
-    E.md_a = cv.take<float>(k.md);
-    E.md_ca = cv.take<float>(k.md);
-    E.md_dx = cv.take<float>(k.md);
-    E.md_dy = cv.take<float>(k.md);
-    E.md_dn = cv.take<float>(k.md);
-    E.md_bend = cv.take<float>(k.md);
-    E.md_sv = cv.take<float>(k.md);
-    E.md_bar = cv.take<uint8_t>(k.md);
+    E.md_hlo = cv.take<int32_t>(nmd);
+    E.md_hup = cv.take<int32_t>(nmd);
+    E.md_slot = cv.take<int32_t>(nmd);
+    E.md_x = cv.take<float>(nmd);
+    E.md_y = cv.take<float>(nmd);
+    E.md_z = cv.take<float>(nmd);
+    E.md_r = cv.take<float>(nmd);
+    E.md_a = cv.take<float>(nmd);
+    E.md_ca = cv.take<float>(nmd);
+    E.md_dx = cv.take<float>(nmd);
+    E.md_dy = cv.take<float>(nmd);
+    E.md_dn = cv.take<float>(nmd);
+    E.md_bend = cv.take<float>(nmd);
+    E.md_sv = cv.take<float>(nmd);
+    E.md_bar = cv.take<uint8_t>(nmd);
     E.md_start = cv.take<int32_t>(slots);
     E.md_cnt = cv.take<int32_t>(slots);
     // segments
-    E.seg_in = cv.take<int32_t>(k.seg);
-    E.seg_out = cv.take<int32_t>(k.seg);
-    E.seg_start = cv.take<int32_t>(k.md);
-    E.seg_cnt = cv.take<int32_t>(k.md);
+    E.seg_in = cv.take<int32_t>(nseg);
+    E.seg_out = cv.take<int32_t>(nseg);
+    E.seg_start = cv.take<int32_t>(nmd);
+    E.seg_cnt = cv.take<int32_t>(nmd);
     // triplets
-    E.t3_a = cv.take<int32_t>(k.t3);
-    E.t3_b = cv.take<int32_t>(k.t3);
-    E.t3_c = cv.take<int32_t>(k.t3);
-    E.t3_k = cv.take<float>(k.t3);
-    E.t3_start = cv.take<int32_t>(k.md);
-    E.t3_cnt = cv.take<int32_t>(k.md);
+    E.t3_a = cv.take<int32_t>(nt3);
+    E.t3_b = cv.take<int32_t>(nt3);
+    E.t3_c = cv.take<int32_t>(nt3);
+    E.t3_k = cv.take<float>(nt3);
+    E.t3_start = cv.take<int32_t>(nmd);
+    E.t3_cnt = cv.take<int32_t>(nmd);
     // quintuplets
-    E.t5_md0 = cv.take<int32_t>(k.t5);
-    E.t5_md1 = cv.take<int32_t>(k.t5);
-    E.t5_md2 = cv.take<int32_t>(k.t5);
-    E.t5_md3 = cv.take<int32_t>(k.t5);
-    E.t5_md4 = cv.take<int32_t>(k.t5);
-    E.t5_score = cv.take<float>(k.t5);
-    E.t5_keep = cv.take<uint8_t>(k.t5);
+    E.t5_md0 = cv.take<int32_t>(nt5);
+    E.t5_md1 = cv.take<int32_t>(nt5);
+    E.t5_md2 = cv.take<int32_t>(nt5);
+    E.t5_md3 = cv.take<int32_t>(nt5);
+    E.t5_md4 = cv.take<int32_t>(nt5);
+    E.t5_score = cv.take<float>(nt5);
+    E.t5_keep = cv.take<uint8_t>(nt5);
     return (cv.off + 255) & ~(size_t)255;
 }
 }  // namespace
@@ -493,24 +496,58 @@ static int sync_stream(lst_ctx *c, void *stream)
     return LST_OK;
 }
 
+}  // extern "C"
+
+// Shard counters of every object type, read back from the device.
+struct ShardCounts {
+    uint32_t gc[GC_COUNT];
+    uint32_t rc[OT_COUNT];
+    uint32_t n(int t, int s) const { return std::min(gc[GC_SH + t * NSH + s], rc[t]); }
+    size_t span(int t) const { return (size_t)rc[t] * NSH; }
+    // capacity that would have let every shard fit
+    int64_t required(int t) const
+    {
+        uint32_t m = 0;
+        for (int s = 0; s < NSH; ++s) m = std::max(m, gc[GC_SH + t * NSH + s]);
+        return (int64_t)m * NSH;
+    }
+    int64_t stored(int t) const
+    {
+        int64_t k = 0;
+        for (int s = 0; s < NSH; ++s) k += n(t, s);
+        return k;
+    }
+};
+
+static int read_shards(lst_ctx *c, ShardCounts &S)
+{
+    HIPCHK(c, hipMemcpy(S.gc, c->E.gc, sizeof(S.gc), hipMemcpyDeviceToHost));
+    std::memcpy(S.rc, c->E.rc, sizeof(S.rc));
+    return LST_OK;
+}
+
 // Per-event statistics, reduced on the host from the device arrays (the
 // reporting path; the stage kernels carry no statistics atomics).
 static int compute_counts(lst_ctx *c)
 {
     const EvDev &E = c->E;
     const int n_ev = c->n_events, nm = c->n_mod;
-    int32_t gc[GC_COUNT];
-    HIPCHK(c, hipMemcpy(gc, E.gc, sizeof(gc), hipMemcpyDeviceToHost));
+    ShardCounts S;
+    int rc = read_shards(c, S);
+    if (rc) return rc;
     c->counts.assign(n_ev, lst_counts{});
     for (int e = 0; e < n_ev; ++e) {
         c->counts[e].n_hits = c->hit_off[e + 1] - c->hit_off[e];
-        c->counts[e].overflow_mask = gc[GC_OVERFLOW];
-        c->counts[e].error_flags = gc[GC_ERROR];
+        c->counts[e].overflow_mask = (int32_t)S.gc[GC_OVERFLOW];
+        c->counts[e].error_flags = (int32_t)S.gc[GC_ERROR];
     }
-    if (gc[GC_OVERFLOW]) {
+    if (S.gc[GC_OVERFLOW]) {
         // arrays are incomplete: report the batch-wide requirement instead
         for (auto &k : c->counts) {
-            k.n_md = gc[GC_MD]; k.n_seg = gc[GC_SEG]; k.n_t3 = gc[GC_T3]; k.n_t5 = gc[GC_T5];
+            k.n_md = S.required(OT_MD);
+            k.n_seg = S.required(OT_SEG);
+            k.n_t3 = S.required(OT_T3);
+            k.n_t5 = S.required(OT_T5);
         }
         c->counts_valid = true;
         return LST_OK;
@@ -519,8 +556,7 @@ static int compute_counts(lst_ctx *c)
     std::vector<uint32_t> boff;
     std::vector<int32_t> mds, mdc, mslot, ss, sc, so, ts, tc, tcc, t50;
     std::vector<uint8_t> keep;
-    int rc;
-    const size_t nmd = gc[GC_MD], nseg = gc[GC_SEG], nt3 = gc[GC_T3], nt5 = gc[GC_T5];
+    const size_t nmd = S.span(OT_MD), nseg = S.span(OT_SEG), nt3 = S.span(OT_T3), nt5 = S.span(OT_T5);
     if ((rc = d2h(c, boff, E.boff, 2 * slots + 1)) || (rc = d2h(c, mds, E.md_start, slots)) ||
         (rc = d2h(c, mdc, E.md_cnt, slots)))
         return rc;
@@ -540,15 +576,14 @@ static int compute_counts(lst_ctx *c)
             const int64_t nlo = boff[2 * sl + 1] - boff[2 * sl];
             const int64_t nup = boff[2 * sl + 2] - boff[2 * sl + 1];
             k.cand_md += nlo * nup;
-            if (c->stage < 3) continue;
+            if (c->stage < 3 || mdc[sl] == 0) continue;
             k.n_md += mdc[sl];
-            if (mdc[sl] == 0) continue;
             int64_t outer = 0;
             for (int32_t q = c->map_ptr[m]; q < c->map_ptr[m + 1]; ++q)
                 outer += mdc[(size_t)e * nm + c->map_col[q]];
             k.cand_seg += (int64_t)mdc[sl] * outer;
+            if (c->stage < 4) continue;
             for (int32_t a = mds[sl]; a < mds[sl] + mdc[sl]; ++a) {
-                if (c->stage < 4) break;
                 k.n_seg += sc[a];
                 for (int32_t s1 = ss[a]; s1 < ss[a] + sc[a]; ++s1) k.cand_t3 += sc[so[s1]];
                 if (c->stage < 5) continue;
@@ -557,14 +592,20 @@ static int compute_counts(lst_ctx *c)
             }
         }
     }
-    for (size_t t = 0; c->stage >= 6 && t < nt5; ++t) {
-        const int e = mslot[t50[t]] / nm;
-        c->counts[e].n_t5++;
-        if (c->stage >= 7) c->counts[e].n_t5_kept += keep[t];
+    if (c->stage >= 6) {
+        for (int s = 0; s < NSH; ++s)
+            for (uint32_t q = 0; q < S.n(OT_T5, s); ++q) {
+                const size_t t = (size_t)s * S.rc[OT_T5] + q;
+                const int e = mslot[t50[t]] / nm;
+                c->counts[e].n_t5++;
+                if (c->stage >= 7) c->counts[e].n_t5_kept += keep[t];
+            }
     }
     c->counts_valid = true;
     return LST_OK;
 }
+
+extern "C" {
 
 int lst_get_counts(lst_ctx *c, int32_t event, lst_counts *out, void *stream)
 {
@@ -576,7 +617,8 @@ int lst_get_counts(lst_ctx *c, int32_t event, lst_counts *out, void *stream)
     if (!c->counts_valid && (rc = compute_counts(c))) return rc;
     *out = c->counts[event];
     if (out->overflow_mask)
-        return fail(c, LST_E_CAPACITY, "capacity overflow (mask %d): MD %lld SEG %lld T3 %lld T5 %lld needed",
+        return fail(c, LST_E_CAPACITY,
+                    "capacity overflow (mask %d): MD %lld SEG %lld T3 %lld T5 %lld needed",
                     out->overflow_mask, (long long)out->n_md, (long long)out->n_seg,
                     (long long)out->n_t3, (long long)out->n_t5);
     return LST_OK;
@@ -593,63 +635,61 @@ int lst_get_objects(lst_ctx *c, int32_t event, int32_t kind, int32_t *out, int64
     int rc = sync_stream(c, stream);
     if (rc) return rc;
     const EvDev &E = c->E;
-    int32_t gc[GC_COUNT];
-    HIPCHK(c, hipMemcpy(gc, E.gc, sizeof(gc), hipMemcpyDeviceToHost));
-    if (gc[GC_OVERFLOW]) return fail(c, LST_E_CAPACITY, "capacity overflow (mask %d)", gc[GC_OVERFLOW]);
-    const size_t n_sorted = (size_t)gc[GC_N_SORTED];
-    const size_t nmd = (size_t)std::min<int64_t>(gc[GC_MD], E.cap_md);
+    ShardCounts S;
+    if ((rc = read_shards(c, S))) return rc;
+    if (S.gc[GC_OVERFLOW])
+        return fail(c, LST_E_CAPACITY, "capacity overflow (mask %u)", S.gc[GC_OVERFLOW]);
+    const size_t n_sorted = S.gc[GC_N_SORTED];
+    const size_t nmd = S.span(OT_MD);
     std::vector<int32_t> sorig, hlo, hup, slot;
-    if ((rc = d2h(c, sorig, E.sorig, n_sorted))) return rc;
-    if ((rc = d2h(c, hlo, E.md_hlo, nmd))) return rc;
-    if ((rc = d2h(c, hup, E.md_hup, nmd))) return rc;
-    if ((rc = d2h(c, slot, E.md_slot, nmd))) return rc;
+    if ((rc = d2h(c, sorig, E.sorig, n_sorted)) || (rc = d2h(c, hlo, E.md_hlo, nmd)) ||
+        (rc = d2h(c, hup, E.md_hup, nmd)) || (rc = d2h(c, slot, E.md_slot, nmd)))
+        return rc;
     const int lo_slot = event * c->n_mod, hi_slot = (event + 1) * c->n_mod;
     auto in_ev = [&](int32_t md) { return slot[md] >= lo_slot && slot[md] < hi_slot; };
+    auto put = [&](std::vector<int32_t> &tup, int32_t md) {
+        tup.push_back(sorig[hlo[md]]);
+        tup.push_back(sorig[hup[md]]);
+    };
     std::vector<int32_t> tup;
     int width = 2;
-    if (kind == LST_MD) {
-        for (size_t i = 0; i < nmd; ++i)
-            if (in_ev((int32_t)i)) { tup.push_back(sorig[hlo[i]]); tup.push_back(sorig[hup[i]]); }
-    } else if (kind == LST_SEG) {
+    const int type = kind == LST_MD ? OT_MD : kind == LST_SEG ? OT_SEG : kind == LST_T3 ? OT_T3 : OT_T5;
+    const size_t sp = S.span(type);
+    std::vector<int32_t> a, b, d, e4, f5;
+    std::vector<uint8_t> keep;
+    if (kind == LST_SEG) {
         width = 4;
-        const size_t n = (size_t)std::min<int64_t>(gc[GC_SEG], E.cap_seg);
-        std::vector<int32_t> a, b;
-        if ((rc = d2h(c, a, E.seg_in, n)) || (rc = d2h(c, b, E.seg_out, n))) return rc;
-        for (size_t i = 0; i < n; ++i) {
-            if (!in_ev(a[i])) continue;
-            for (int32_t m : {a[i], b[i]}) { tup.push_back(sorig[hlo[m]]); tup.push_back(sorig[hup[m]]); }
-        }
+        if ((rc = d2h(c, a, E.seg_in, sp)) || (rc = d2h(c, b, E.seg_out, sp))) return rc;
     } else if (kind == LST_T3) {
         width = 6;
-        const size_t n = (size_t)std::min<int64_t>(gc[GC_T3], E.cap_t3);
-        std::vector<int32_t> a, b, d;
-        if ((rc = d2h(c, a, E.t3_a, n)) || (rc = d2h(c, b, E.t3_b, n)) || (rc = d2h(c, d, E.t3_c, n)))
+        if ((rc = d2h(c, a, E.t3_a, sp)) || (rc = d2h(c, b, E.t3_b, sp)) || (rc = d2h(c, d, E.t3_c, sp)))
             return rc;
-        for (size_t i = 0; i < n; ++i) {
-            if (!in_ev(a[i])) continue;
-            for (int32_t m : {a[i], b[i], d[i]}) { tup.push_back(sorig[hlo[m]]); tup.push_back(sorig[hup[m]]); }
-        }
-    } else {
+    } else if (kind >= LST_T5) {
         width = 10;
-        const size_t n = (size_t)std::min<int64_t>(gc[GC_T5], E.cap_t5);
-        std::vector<int32_t> m0, m1, m2, m3, m4;
-        std::vector<uint8_t> keep;
-        if ((rc = d2h(c, m0, E.t5_md0, n)) || (rc = d2h(c, m1, E.t5_md1, n)) ||
-            (rc = d2h(c, m2, E.t5_md2, n)) || (rc = d2h(c, m3, E.t5_md3, n)) ||
-            (rc = d2h(c, m4, E.t5_md4, n)) || (rc = d2h(c, keep, E.t5_keep, n)))
+        if ((rc = d2h(c, a, E.t5_md0, sp)) || (rc = d2h(c, b, E.t5_md1, sp)) ||
+            (rc = d2h(c, d, E.t5_md2, sp)) || (rc = d2h(c, e4, E.t5_md3, sp)) ||
+            (rc = d2h(c, f5, E.t5_md4, sp)) || (rc = d2h(c, keep, E.t5_keep, sp)))
             return rc;
-        for (size_t i = 0; i < n; ++i) {
-            if (!in_ev(m0[i])) continue;
-            if (kind == LST_T5_KEPT && !keep[i]) continue;
-            for (int32_t m : {m0[i], m1[i], m2[i], m3[i], m4[i]}) {
-                tup.push_back(sorig[hlo[m]]);
-                tup.push_back(sorig[hup[m]]);
+    }
+    for (int s = 0; s < NSH; ++s) {
+        for (uint32_t q = 0; q < S.n(type, s); ++q) {
+            const size_t i = (size_t)s * S.rc[type] + q;
+            if (kind == LST_MD) {
+                if (in_ev((int32_t)i)) put(tup, (int32_t)i);
+            } else if (kind == LST_SEG) {
+                if (in_ev(a[i])) { put(tup, a[i]); put(tup, b[i]); }
+            } else if (kind == LST_T3) {
+                if (in_ev(a[i])) { put(tup, a[i]); put(tup, b[i]); put(tup, d[i]); }
+            } else {
+                if (!in_ev(a[i]) || (kind == LST_T5_KEPT && !keep[i])) continue;
+                put(tup, a[i]); put(tup, b[i]); put(tup, d[i]); put(tup, e4[i]); put(tup, f5[i]);
             }
         }
     }
     const int64_t nt = (int64_t)tup.size() / width;
     if (n_tuples) *n_tuples = nt;
-    if (nt > cap) return fail(c, LST_E_CAPACITY, "%lld tuples, capacity %lld", (long long)nt, (long long)cap);
+    if (nt > cap)
+        return fail(c, LST_E_CAPACITY, "%lld tuples, capacity %lld", (long long)nt, (long long)cap);
     if (out && nt) std::memcpy(out, tup.data(), sizeof(int32_t) * tup.size());
     return LST_OK;
 }
@@ -663,25 +703,27 @@ int lst_get_t5_scores(lst_ctx *c, int32_t event, float *out, int64_t cap, int64_
     int rc = sync_stream(c, stream);
     if (rc) return rc;
     const EvDev &E = c->E;
-    int32_t gc[GC_COUNT];
-    HIPCHK(c, hipMemcpy(gc, E.gc, sizeof(gc), hipMemcpyDeviceToHost));
-    if (gc[GC_OVERFLOW]) return fail(c, LST_E_CAPACITY, "capacity overflow (mask %d)", gc[GC_OVERFLOW]);
-    const size_t n = (size_t)std::min<int64_t>(gc[GC_T5], E.cap_t5);
-    const size_t nmd = (size_t)std::min<int64_t>(gc[GC_MD], E.cap_md);
+    ShardCounts S;
+    if ((rc = read_shards(c, S))) return rc;
+    if (S.gc[GC_OVERFLOW])
+        return fail(c, LST_E_CAPACITY, "capacity overflow (mask %u)", S.gc[GC_OVERFLOW]);
     std::vector<int32_t> m0, slot;
     std::vector<float> sc;
-    if ((rc = d2h(c, m0, E.t5_md0, n)) || (rc = d2h(c, sc, E.t5_score, n)) ||
-        (rc = d2h(c, slot, E.md_slot, nmd)))
+    if ((rc = d2h(c, m0, E.t5_md0, S.span(OT_T5))) || (rc = d2h(c, sc, E.t5_score, S.span(OT_T5))) ||
+        (rc = d2h(c, slot, E.md_slot, S.span(OT_MD))))
         return rc;
     const int lo_slot = event * c->n_mod, hi_slot = (event + 1) * c->n_mod;
     int64_t k = 0;
-    for (size_t i = 0; i < n; ++i) {
-        if (slot[m0[i]] < lo_slot || slot[m0[i]] >= hi_slot) continue;
-        if (out && k < cap) out[k] = sc[i];
-        ++k;
-    }
+    for (int s = 0; s < NSH; ++s)
+        for (uint32_t q = 0; q < S.n(OT_T5, s); ++q) {
+            const size_t i = (size_t)s * S.rc[OT_T5] + q;
+            if (slot[m0[i]] < lo_slot || slot[m0[i]] >= hi_slot) continue;
+            if (out && k < cap) out[k] = sc[i];
+            ++k;
+        }
     if (n_out) *n_out = k;
-    if (k > cap) return fail(c, LST_E_CAPACITY, "%lld scores, capacity %lld", (long long)k, (long long)cap);
+    if (k > cap)
+        return fail(c, LST_E_CAPACITY, "%lld scores, capacity %lld", (long long)k, (long long)cap);
     return LST_OK;
 }
 

@@ -18,10 +18,20 @@ struct Consts {
     float z0max, sigu, sigv, nsig, d0max, w, w2, xrphi, xrz;
 };
 
-// Global counters (int32 unless noted).
+// Output reservation is spread over NSH counters per object type ("shards",
+// chosen by blockIdx % NSH); shard s owns indices [s * rc, (s + 1) * rc) of
+// the type's arrays, rc = ceil(capacity / NSH).  One hot counter would
+// serialise every block's reservation across the chip.
+constexpr int NSH = 32;
+enum ObjType { OT_MD = 0, OT_SEG, OT_T3, OT_T5, OT_COUNT };
+
+// Global counters (int32 / uint32).
 enum GlobalCounter {
-    GC_MD = 0, GC_SEG, GC_T3, GC_T5, GC_OVERFLOW, GC_ERROR, GC_N_SORTED, GC_PAD,
-    GC_COUNT
+    GC_OVERFLOW = 0,   // bit k: object type k ran out of its region
+    GC_ERROR,          // bit 0: invalid hit skipped
+    GC_N_SORTED,       // number of grouped hits
+    GC_SH = 8,         // [OT_COUNT][NSH] reservation shards
+    GC_COUNT = GC_SH + OT_COUNT * NSH
 };
 
 struct ModDev {
@@ -34,7 +44,8 @@ struct ModDev {
 
 struct EvDev {
     int32_t n_ev, n_slots, n_keys, n_hits;
-    int64_t cap_hits, cap_md, cap_seg, cap_t3, cap_t5;
+    int64_t cap_hits;
+    uint32_t rc[OT_COUNT];           // region capacity per shard, per object type
     // inputs as loaded
     float *x, *y, *z;
     int32_t *module;
@@ -66,12 +77,14 @@ struct EvDev {
     float *t5_score;
     uint8_t *t5_keep;
     // counters (zeroed at chain start)
-    int32_t *gc;                     // [GC_COUNT]
+    uint32_t *gc;                    // [GC_COUNT]
 };
 
 constexpr int TIE_SLOTS = 8;
 constexpr int BLOCK = 256;           // 4 waves of 64
 constexpr int WAVES = BLOCK / 64;
+constexpr int STAGE = 256;           // accepted objects a wave stages in LDS
+constexpr int GRID_MAX = 2048;       // blocks of a grid-stride stage kernel
 
 // launchers (lst_kernels.hip)
 hipError_t launch_zero(const EvDev &E, void *zero_base, size_t zero_bytes, hipStream_t s);

@@ -1,21 +1,28 @@
 // Stage kernels of the Segment Linking chain for gfx950 (wave64).
 //
-// Structure shared by the object stages: one wavefront owns one "slot"
-// (event x module) and enumerates the slot's candidate combinations 64 at a
-// time, one per lane.  Candidate lists that are concatenations of several
-// groups (map edges, outgoing segments, outgoing triplets) are flattened with
-// a wave-wide inclusive scan of the group sizes; a lane finds its group by a
-// binary search over that scan held in registers (cross-lane reads, no LDS).
-// Accepted objects are compacted with ballot + popcount, no per-object
-// atomics: pass 1 counts, the block reserves its whole range with ONE atomic,
-// pass 2 recomputes the (cheap) predicate and writes each object at its
-// slot-contiguous position.  The output of a stage stays grouped by its inner
-// object, which is exactly the index the next stage needs.
+// Work decomposition of the object stages: one wavefront owns one inner
+// object (a module slot for mini-doublets, an inner mini-doublet for
+// segments, triplets and quintuplets) and evaluates that object's candidate
+// combinations 64 at a time, one per lane.  Candidate lists that are
+// concatenations of several groups (map edges, outgoing segments, outgoing
+// triplets) are flattened with a wave-wide inclusive scan of the group sizes;
+// a lane finds its group by a binary search over that scan held in
+// registers (cross-lane reads, no LDS).  Accepted objects are compacted with
+// ballot + popcount into an LDS staging buffer; the block then reserves its
+// whole output range with one atomic on one of NSH shard counters, and each
+// wave copies its staged objects out.  Kernels are grid-stride over the inner
+// objects, whose number is only known on the device.
+//
+// Why not one global counter: device-scope atomics on one address are
+// serialised across the chip (measured ~0.1 us apiece through 16 counters),
+// so per-object or per-wave atomics on a shared counter cost more than the
+// whole stage.
 #include "lst_cuts.hpp"
 
 namespace lst {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 __device__ __forceinline__ unsigned long long lanes_below()
 {
     return (1ull << lane_id()) - 1ull;
@@ -33,7 +40,8 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
     return v;
 }
 
-// smallest lane e with incl[e] > j (incl non-decreasing, j < incl[63])
+// smallest lane e with incl[e] > j (incl non-decreasing, j < incl[63]);
+// every lane of the wave must take part
 __device__ __forceinline__ int wave_find(uint32_t incl, uint32_t j)
 {
     int lo = 0, hi = 63;
@@ -46,34 +54,82 @@ __device__ __forceinline__ int wave_find(uint32_t incl, uint32_t j)
     return lo;
 }
 
-// Block-wide reservation: every thread of the block must call it.  Returns
-// the first output index of the calling wave; `ovf` is set for every wave of
-// the block when the block's range does not fit the capacity.
-__device__ __forceinline__ uint32_t block_reserve(uint32_t wave_total, int32_t *counter,
-                                                  int64_t cap, int32_t *gc, int stage_bit,
+// ---------------------------------------------------------------- regions
+// Objects of one type live in NSH regions; n_s = min(counter_s, rc) of them
+// in region s.  A wave maps a compact index v in [0, sum n_s) to its array
+// index with a scan of the region sizes held in lanes 0..NSH-1.
+struct Regions {
+    uint32_t incl;   // inclusive prefix of region sizes (this lane's region)
+    uint32_t size;   // this lane's region size
+    uint32_t total;
+    uint32_t rc;
+};
+
+__device__ __forceinline__ Regions load_regions(const EvDev &E, int type)
+{
+    Regions R;
+    R.rc = E.rc[type];
+    uint32_t n = 0;
+    if (lane_id() < NSH) {
+        uint32_t c = E.gc[GC_SH + type * NSH + lane_id()];
+        n = c < R.rc ? c : R.rc;
+    }
+    R.size = n;
+    R.incl = wave_incl_scan(n);
+    R.total = __shfl(R.incl, 63, 64);
+    return R;
+}
+
+// v must be wave-uniform and < R.total
+__device__ __forceinline__ int32_t region_index(const Regions &R, uint32_t v)
+{
+    const int r = wave_find(R.incl, v);
+    const uint32_t ex = __shfl(R.incl, r, 64) - __shfl(R.size, r, 64);
+    return (int32_t)((uint32_t)r * R.rc + (v - ex));
+}
+
+// Block-wide reservation in shard blockIdx % NSH; every thread of the block
+// must call it.  Returns the first output index of the calling wave; `ovf`
+// is set for the whole block when the range does not fit the shard's region.
+__device__ __forceinline__ uint32_t block_reserve(uint32_t wave_total, const EvDev &E, int type,
                                                   bool &ovf)
 {
     __shared__ uint32_t s_cnt[WAVES];
     __shared__ uint32_t s_base;
     __shared__ int s_ovf;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     if (lane_id() == 0) s_cnt[w] = wave_total;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t tot = 0;
         for (int i = 0; i < WAVES; ++i) tot += s_cnt[i];
-        uint32_t base = tot ? atomicAdd((uint32_t *)counter, tot) : 0u;
-        int o = ((uint64_t)base + tot) > (uint64_t)cap;
-        if (o) atomicOr(&gc[GC_OVERFLOW], 1 << stage_bit);
-        s_base = base;
+        const uint32_t shard = blockIdx.x % NSH;
+        const uint32_t rc = E.rc[type];
+        const uint32_t base = tot ? atomicAdd(&E.gc[GC_SH + type * NSH + shard], tot) : 0u;
+        const int o = ((uint64_t)base + tot) > (uint64_t)rc;
+        if (o) atomicOr(&E.gc[GC_OVERFLOW], 1u << type);
+        s_base = shard * rc + base;
         s_ovf = o;
     }
     __syncthreads();
     uint32_t off = s_base;
     for (int i = 0; i < w; ++i) off += s_cnt[i];
     ovf = s_ovf != 0;
+    // the next grid-stride round rewrites s_cnt: every wave must have read it
     __syncthreads();
     return off;
+}
+
+__device__ __forceinline__ bool upstream_overflow(const EvDev &E)
+{
+    return E.gc[GC_OVERFLOW] != 0u;
+}
+
+static int grid_for(uint32_t waves_wanted)
+{
+    uint32_t b = (waves_wanted + WAVES - 1) / WAVES;
+    if (b > (uint32_t)GRID_MAX) b = GRID_MAX;
+    return b < 1 ? 1 : (int)b;
 }
 
 // ---------------------------------------------------------------- zero fill
@@ -88,13 +144,13 @@ hipError_t launch_zero(const EvDev &, void *zero_base, size_t zero_bytes, hipStr
 {
     size_t n16 = zero_bytes / 16;
     int blocks = (int)((n16 + BLOCK - 1) / BLOCK);
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > GRID_MAX) blocks = GRID_MAX;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(BLOCK), 0, s, (uint4 *)zero_base, n16);
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- a0: sort
+// ---------------------------------------------------------------- a0: hit grouping
 __device__ __forceinline__ int event_of(const int32_t *off, int n_ev, int32_t h)
 {
     int lo = 0, hi = n_ev - 1;
@@ -121,7 +177,7 @@ __global__ void k_hist(EvDev E, int n_mod)
     int ev;
     int key = hit_key(E, n_mod, h, ev);
     if (key < 0) {
-        atomicOr(&E.gc[GC_ERROR], 1);
+        atomicOr(&E.gc[GC_ERROR], 1u);
         return;
     }
     atomicAdd(&E.bcnt[key], 1u);
@@ -134,7 +190,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t &total)
 {
     __shared__ uint32_t s_w[WAVES];
     uint32_t incl = wave_incl_scan(v);
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     if (lane_id() == 63) s_w[w] = incl;
     __syncthreads();
     uint32_t before = 0;
@@ -160,7 +216,6 @@ __global__ void k_scan_reduce(const uint32_t *in, int n, uint32_t *bsum)
 
 __global__ void k_scan_top(uint32_t *bsum, int nb)
 {
-    // single block: exclusive scan of nb partials, nb <= 16 * BLOCK
     uint32_t carry = 0;
     for (int b0 = 0; b0 < nb; b0 += BLOCK) {
         int i = b0 + threadIdx.x;
@@ -173,7 +228,7 @@ __global__ void k_scan_top(uint32_t *bsum, int nb)
 }
 
 __global__ void k_scan_down(const uint32_t *in, int n, const uint32_t *bsum, uint32_t *out,
-                            int32_t *gc)
+                            uint32_t *gc)
 {
     int base = blockIdx.x * SCAN_TILE + threadIdx.x * 4;
     uint32_t v[4], s = 0;
@@ -189,7 +244,7 @@ __global__ void k_scan_down(const uint32_t *in, int n, const uint32_t *bsum, uin
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == BLOCK - 1) {
         out[n] = ex;
-        gc[GC_N_SORTED] = (int32_t)ex;
+        gc[GC_N_SORTED] = ex;
     }
 }
 
@@ -229,7 +284,7 @@ hipError_t launch_sort(const EvDev &E, const ModDev &M, hipStream_t s)
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- a1: MD
+// ---------------------------------------------------------------- a1: mini-doublets
 __device__ __forceinline__ ModF load_mod(const ModDev &M, int m)
 {
     ModF f;
@@ -241,234 +296,242 @@ __device__ __forceinline__ ModF load_mod(const ModDev &M, int m)
     return f;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_md(EvDev E, ModDev M, Consts K)
+__device__ __forceinline__ void write_md(const EvDev &E, uint32_t i, int slot, uint32_t hl,
+                                         uint32_t hu, const MdOut &o, int barrel)
 {
-    const int lane = lane_id();
-    const int slot = blockIdx.x * WAVES + (threadIdx.x >> 6);
-    const bool act = slot < E.n_slots;
-    uint32_t lo0 = 0, up0 = 0, nlo = 0, nup = 0;
-    if (act) {
-        lo0 = E.boff[2 * slot];
-        up0 = E.boff[2 * slot + 1];
-        nlo = up0 - lo0;
-        nup = E.boff[2 * slot + 2] - up0;
-    }
-    const uint32_t np = nlo * nup;
-    const int m = act ? slot % M.n_mod : 0;
-    ModF mod;
-    if (np) mod = load_mod(M, m);
+    const float xL = E.sx[hl], yL = E.sy[hl];
+    E.md_hlo[i] = (int32_t)hl;
+    E.md_hup[i] = (int32_t)hu;
+    E.md_slot[i] = slot;
+    E.md_x[i] = xL;
+    E.md_y[i] = yL;
+    E.md_z[i] = E.sz[hl];
+    E.md_r[i] = o.r;
+    E.md_a[i] = o.a;
+    E.md_ca[i] = o.ca;
+    const float dx = E.sx[hu] - xL, dy = E.sy[hu] - yL;
+    E.md_dx[i] = dx;
+    E.md_dy[i] = dy;
+    E.md_dn[i] = sqrtf((dx * dx) + (dy * dy));
+    E.md_bend[i] = o.bend;
+    E.md_sv[i] = o.sv;
+    E.md_bar[i] = (uint8_t)barrel;
+}
+
+// every lower x upper hit pair of one module slot; sink(ok, hl, hu, pos)
+template <class F>
+__device__ __forceinline__ uint32_t enum_md(const EvDev &E, const Consts &K, const ModF &mod,
+                                            uint32_t lo0, uint32_t up0, uint32_t nup,
+                                            uint32_t np, F &&sink)
+{
     uint32_t cnt = 0;
     for (uint32_t b = 0; b < np; b += 64) {
-        uint32_t p = b + lane;
+        const uint32_t p = b + lane_id();
         bool ok = false;
+        uint32_t hl = 0, hu = 0;
         if (p < np) {
-            uint32_t il = p / nup, iu = p - il * nup;
-            uint32_t hl = lo0 + il, hu = up0 + iu;
+            const uint32_t il = p / nup, iu = p - il * nup;
+            hl = lo0 + il;
+            hu = up0 + iu;
             MdOut o;
             ok = md_accept(K, mod, E.sx[hl], E.sy[hl], E.sz[hl], E.sx[hu], E.sy[hu], E.sz[hu], o);
         }
-        cnt += (uint32_t)__popcll(__ballot(ok));
+        const unsigned long long mask = __ballot(ok);
+        sink(ok, hl, hu, cnt + (uint32_t)__popcll(mask & lanes_below()));
+        cnt += (uint32_t)__popcll(mask);
     }
-    bool ovf;
-    uint32_t off = block_reserve(cnt, &E.gc[GC_MD], E.cap_md, E.gc, 0, ovf);
-    if (!act) return;
-    if (lane == 0) {
-        E.md_start[slot] = (int32_t)off;
-        E.md_cnt[slot] = ovf ? 0 : (int32_t)cnt;
-    }
-    if (ovf || cnt == 0) return;
-    uint32_t pos = off;
-    for (uint32_t b = 0; b < np; b += 64) {
-        uint32_t p = b + lane;
-        bool ok = false;
-        uint32_t hl = 0, hu = 0;
-        MdOut o;
-        if (p < np) {
-            uint32_t il = p / nup, iu = p - il * nup;
-            hl = lo0 + il;
-            hu = up0 + iu;
-            ok = md_accept(K, mod, E.sx[hl], E.sy[hl], E.sz[hl], E.sx[hu], E.sy[hu], E.sz[hu], o);
+    return cnt;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_md(EvDev E, ModDev M, Consts K)
+{
+    __shared__ uint32_t s_lo[WAVES][STAGE];
+    __shared__ uint32_t s_up[WAVES][STAGE];
+    const int w = wave_id();
+    for (int base = blockIdx.x * WAVES; base < E.n_slots; base += gridDim.x * WAVES) {
+        const int slot = base + w;
+        const bool act = slot < E.n_slots;
+        uint32_t lo0 = 0, up0 = 0, nup = 0, np = 0;
+        if (act) {
+            lo0 = E.boff[2 * slot];
+            up0 = E.boff[2 * slot + 1];
+            nup = E.boff[2 * slot + 2] - up0;
+            np = (up0 - lo0) * nup;
         }
-        unsigned long long mask = __ballot(ok);
-        if (ok) {
-            uint32_t i = pos + (uint32_t)__popcll(mask & lanes_below());
-            float xL = E.sx[hl], yL = E.sy[hl];
-            E.md_hlo[i] = (int32_t)hl;
-            E.md_hup[i] = (int32_t)hu;
-            E.md_slot[i] = slot;
-            E.md_x[i] = xL;
-            E.md_y[i] = yL;
-            E.md_z[i] = E.sz[hl];
-            E.md_r[i] = o.r;
-            E.md_a[i] = o.a;
-            E.md_ca[i] = o.ca;
-            float dx = E.sx[hu] - xL, dy = E.sy[hu] - yL;
-            E.md_dx[i] = dx;
-            E.md_dy[i] = dy;
-            E.md_dn[i] = sqrtf((dx * dx) + (dy * dy));
-            E.md_bend[i] = o.bend;
-            E.md_sv[i] = o.sv;
-            E.md_bar[i] = (uint8_t)mod.barrel;
+        ModF mod = {};
+        if (np) mod = load_mod(M, slot % M.n_mod);
+        const uint32_t cnt = enum_md(E, K, mod, lo0, up0, nup, np,
+                                     [&](bool ok, uint32_t hl, uint32_t hu, uint32_t pos) {
+                                         if (ok && pos < STAGE) {
+                                             s_lo[w][pos] = hl;
+                                             s_up[w][pos] = hu;
+                                         }
+                                     });
+        bool ovf;
+        const uint32_t off = block_reserve(cnt, E, OT_MD, ovf);
+        if (!act) continue;
+        if (lane_id() == 0) {
+            E.md_start[slot] = (int32_t)off;
+            E.md_cnt[slot] = ovf ? 0 : (int32_t)cnt;
         }
-        pos += (uint32_t)__popcll(mask);
+        if (ovf || cnt == 0) continue;
+        if (cnt <= STAGE) {
+            for (uint32_t k = lane_id(); k < cnt; k += 64) {
+                const uint32_t hl = s_lo[w][k], hu = s_up[w][k];
+                MdOut o;
+                md_accept(K, mod, E.sx[hl], E.sy[hl], E.sz[hl], E.sx[hu], E.sy[hu], E.sz[hu], o);
+                write_md(E, off + k, slot, hl, hu, o, mod.barrel);
+            }
+        } else {
+            enum_md(E, K, mod, lo0, up0, nup, np,
+                    [&](bool ok, uint32_t hl, uint32_t hu, uint32_t pos) {
+                        if (ok) {
+                            MdOut o;
+                            md_accept(K, mod, E.sx[hl], E.sy[hl], E.sz[hl], E.sx[hu], E.sy[hu],
+                                      E.sz[hu], o);
+                            write_md(E, off + pos, slot, hl, hu, o, mod.barrel);
+                        }
+                    });
+        }
     }
 }
 
 hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s)
 {
-    int blocks = (E.n_slots + WAVES - 1) / WAVES;
-    hipLaunchKernelGGL(k_md, dim3(blocks), dim3(BLOCK), 0, s, E, M, K);
+    hipLaunchKernelGGL(k_md, dim3(grid_for(E.n_slots)), dim3(BLOCK), 0, s, E, M, K);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- a2: segments
-// Outer candidates of an inner MD: the MDs of every map edge of its module,
-// in edge order.  Pass 1 counts, pass 2 writes.
-template <bool WRITE>
-__device__ __forceinline__ uint32_t seg_slot(const EvDev &E, const ModDev &M, const Consts &K,
-                                             int slot, uint32_t pos, unsigned long long *cand)
+// Outer candidates of inner MD i: the MDs of every map edge of its module,
+// in edge order.  sink(ok, o, pos)
+template <class F>
+__device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, const Consts &K,
+                                             int32_t i, F &&sink)
 {
     const int lane = lane_id();
-    const int32_t sA = E.md_start[slot];
-    const int32_t nA = E.md_cnt[slot];
+    const MdV I = load_md(E, i);
+    const int slot = E.md_slot[i];
     const int ev = slot / M.n_mod;
     const int m = slot - ev * M.n_mod;
+    const int base_slot = ev * M.n_mod;
     const int32_t e0 = M.map_ptr[m];
     const int32_t ne = M.map_ptr[m + 1] - e0;
-    const int base_slot = ev * M.n_mod;
     uint32_t cnt = 0;
-    for (int32_t ii = 0; ii < nA; ++ii) {
-        const int32_t i = sA + ii;
-        const MdV I = load_md(E, i);
-        const uint32_t pos_i = pos + cnt;
-        for (int32_t ec = 0; ec < ne; ec += 64) {
-            int32_t e = ec + lane;
-            uint32_t bc = 0;
-            int32_t bs = 0;
-            if (e < ne) {
-                int b = base_slot + M.map_col[e0 + e];
-                bs = E.md_start[b];
-                bc = (uint32_t)E.md_cnt[b];
-            }
-            uint32_t incl = wave_incl_scan(bc);
-            uint32_t tot = __shfl(incl, 63, 64);
-            if (!WRITE && ii == 0) *cand += tot;
-            for (uint32_t jc = 0; jc < tot; jc += 64) {
-                uint32_t j = jc + lane;
-                bool ok = false;
-                int32_t o = 0;
-                int src = wave_find(incl, j < tot ? j : tot - 1);
-                uint32_t ex = __shfl(incl, src, 64) - __shfl(bc, src, 64);
-                int32_t obs = __shfl(bs, src, 64);
-                if (j < tot) {
-                    o = obs + (int32_t)(j - ex);
-                    const MdV O = load_md(E, o);
-                    ok = seg_accept(K, I, O);
-                }
-                unsigned long long mask = __ballot(ok);
-                if (WRITE && ok) {
-                    uint32_t at = pos + cnt + (uint32_t)__popcll(mask & lanes_below());
-                    E.seg_in[at] = i;
-                    E.seg_out[at] = o;
-                }
-                cnt += (uint32_t)__popcll(mask);
-            }
+    for (int32_t ec = 0; ec < ne; ec += 64) {
+        const int32_t e = ec + lane;
+        uint32_t bc = 0;
+        int32_t bs = 0;
+        if (e < ne) {
+            const int b = base_slot + M.map_col[e0 + e];
+            bs = E.md_start[b];
+            bc = (uint32_t)E.md_cnt[b];
         }
-        if (WRITE && lane == 0) {
-            E.seg_start[i] = (int32_t)pos_i;
-            E.seg_cnt[i] = (int32_t)(pos + cnt - pos_i);
+        const uint32_t incl = wave_incl_scan(bc);
+        const uint32_t tot = __shfl(incl, 63, 64);
+        for (uint32_t jc = 0; jc < tot; jc += 64) {
+            const uint32_t j = jc + lane;
+            const int src = wave_find(incl, j < tot ? j : tot - 1);
+            const uint32_t ex = __shfl(incl, src, 64) - __shfl(bc, src, 64);
+            const int32_t obs = __shfl(bs, src, 64);
+            bool ok = false;
+            int32_t o = 0;
+            if (j < tot) {
+                o = obs + (int32_t)(j - ex);
+                ok = seg_accept(K, I, load_md(E, o));
+            }
+            const unsigned long long mask = __ballot(ok);
+            sink(ok, o, cnt + (uint32_t)__popcll(mask & lanes_below()));
+            cnt += (uint32_t)__popcll(mask);
         }
     }
-    if (!WRITE && cand) *cand *= (unsigned long long)nA;
     return cnt;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_seg(EvDev E, ModDev M, Consts K)
 {
-    const int slot = blockIdx.x * WAVES + (threadIdx.x >> 6);
-    const bool act = slot < E.n_slots;
-    unsigned long long cand = 0;
-    uint32_t cnt = act ? seg_slot<false>(E, M, K, slot, 0, &cand) : 0u;
-    (void)cand;
-    bool ovf;
-    uint32_t off = block_reserve(cnt, &E.gc[GC_SEG], E.cap_seg, E.gc, 1, ovf);
-    if (!act) return;
-    if (ovf) {
-        const int32_t sA = E.md_start[slot], nA = E.md_cnt[slot];
-        for (int32_t ii = lane_id(); ii < nA; ii += 64) {
-            E.seg_start[sA + ii] = 0;
-            E.seg_cnt[sA + ii] = 0;
+    __shared__ int32_t s_o[WAVES][STAGE];
+    if (upstream_overflow(E)) return;
+    const int w = wave_id();
+    const Regions R = load_regions(E, OT_MD);
+    for (uint32_t base = blockIdx.x * WAVES; base < R.total; base += gridDim.x * WAVES) {
+        const uint32_t v = base + w;
+        const bool act = v < R.total;
+        const int32_t i = region_index(R, act ? v : 0);
+        uint32_t cnt = 0;
+        if (act)
+            cnt = enum_seg(E, M, K, i, [&](bool ok, int32_t o, uint32_t pos) {
+                if (ok && pos < STAGE) s_o[w][pos] = o;
+            });
+        bool ovf;
+        const uint32_t off = block_reserve(cnt, E, OT_SEG, ovf);
+        if (!act) continue;
+        if (lane_id() == 0) {
+            E.seg_start[i] = (int32_t)off;
+            E.seg_cnt[i] = ovf ? 0 : (int32_t)cnt;
         }
-        return;
+        if (ovf || cnt == 0) continue;
+        if (cnt <= STAGE) {
+            for (uint32_t k = lane_id(); k < cnt; k += 64) {
+                E.seg_in[off + k] = i;
+                E.seg_out[off + k] = s_o[w][k];
+            }
+        } else {
+            enum_seg(E, M, K, i, [&](bool ok, int32_t o, uint32_t pos) {
+                if (ok) {
+                    E.seg_in[off + pos] = i;
+                    E.seg_out[off + pos] = o;
+                }
+            });
+        }
     }
-    seg_slot<true>(E, M, K, slot, off, nullptr);
 }
 
 hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s)
 {
-    int blocks = (E.n_slots + WAVES - 1) / WAVES;
-    hipLaunchKernelGGL(k_seg, dim3(blocks), dim3(BLOCK), 0, s, E, M, K);
+    hipLaunchKernelGGL(k_seg, dim3(GRID_MAX), dim3(BLOCK), 0, s, E, M, K);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- a3: triplets
-template <bool WRITE>
-__device__ __forceinline__ uint32_t t3_slot(const EvDev &E, const Consts &K, int slot,
-                                            uint32_t pos, unsigned long long *cand)
+// Candidates of inner MD a: every segment (a->b) followed by every segment
+// (b->c).  sink(ok, b, c, k, pos)
+template <class F>
+__device__ __forceinline__ uint32_t enum_t3(const EvDev &E, const Consts &K, int32_t a, F &&sink)
 {
     const int lane = lane_id();
-    const int32_t sA = E.md_start[slot];
-    const int32_t nA = E.md_cnt[slot];
+    const int32_t ns1 = E.seg_cnt[a];
+    const int32_t s10 = E.seg_start[a];
     uint32_t cnt = 0;
-    for (int32_t ii = 0; ii < nA; ++ii) {
-        const int32_t a = sA + ii;
-        const int32_t ns1 = E.seg_cnt[a];
-        const int32_t s10 = E.seg_start[a];
-        const uint32_t pos_a = pos + cnt;
-        if (ns1 > 0) {
-            const MdV A = load_md(E, a);
-            for (int32_t c1 = 0; c1 < ns1; c1 += 64) {
-                int32_t k = c1 + lane;
-                int32_t b = 0, bs = 0;
-                uint32_t nb = 0;
-                if (k < ns1) {
-                    b = E.seg_out[s10 + k];
-                    bs = E.seg_start[b];
-                    nb = (uint32_t)E.seg_cnt[b];
-                }
-                uint32_t incl = wave_incl_scan(nb);
-                uint32_t tot = __shfl(incl, 63, 64);
-                if (!WRITE) *cand += tot;
-                for (uint32_t jc = 0; jc < tot; jc += 64) {
-                    uint32_t j = jc + lane;
-                    int src = wave_find(incl, j < tot ? j : tot - 1);
-                    uint32_t ex = __shfl(incl, src, 64) - __shfl(nb, src, 64);
-                    int32_t bb = __shfl(b, src, 64);
-                    int32_t bbs = __shfl(bs, src, 64);
-                    bool ok = false;
-                    int32_t c = 0;
-                    float kk = 0.0f;
-                    if (j < tot) {
-                        c = E.seg_out[bbs + (int32_t)(j - ex)];
-                        const MdV B = load_md(E, bb);
-                        const MdV C = load_md(E, c);
-                        ok = t3_accept(K, A, B, C, kk);
-                    }
-                    unsigned long long mask = __ballot(ok);
-                    if (WRITE && ok) {
-                        uint32_t at = pos + cnt + (uint32_t)__popcll(mask & lanes_below());
-                        E.t3_a[at] = a;
-                        E.t3_b[at] = bb;
-                        E.t3_c[at] = c;
-                        E.t3_k[at] = kk;
-                    }
-                    cnt += (uint32_t)__popcll(mask);
-                }
-            }
+    if (ns1 <= 0) return 0;
+    const MdV A = load_md(E, a);
+    for (int32_t c1 = 0; c1 < ns1; c1 += 64) {
+        const int32_t k = c1 + lane;
+        int32_t b = 0, bs = 0;
+        uint32_t nb = 0;
+        if (k < ns1) {
+            b = E.seg_out[s10 + k];
+            bs = E.seg_start[b];
+            nb = (uint32_t)E.seg_cnt[b];
         }
-        if (WRITE && lane == 0) {
-            E.t3_start[a] = (int32_t)pos_a;
-            E.t3_cnt[a] = (int32_t)(pos + cnt - pos_a);
+        const uint32_t incl = wave_incl_scan(nb);
+        const uint32_t tot = __shfl(incl, 63, 64);
+        for (uint32_t jc = 0; jc < tot; jc += 64) {
+            const uint32_t j = jc + lane;
+            const int src = wave_find(incl, j < tot ? j : tot - 1);
+            const uint32_t ex = __shfl(incl, src, 64) - __shfl(nb, src, 64);
+            const int32_t bb = __shfl(b, src, 64);
+            const int32_t bbs = __shfl(bs, src, 64);
+            bool ok = false;
+            int32_t c = 0;
+            float kk = 0.0f;
+            if (j < tot) {
+                c = E.seg_out[bbs + (int32_t)(j - ex)];
+                ok = t3_accept(K, A, load_md(E, bb), load_md(E, c), kk);
+            }
+            const unsigned long long mask = __ballot(ok);
+            sink(ok, bb, c, kk, cnt + (uint32_t)__popcll(mask & lanes_below()));
+            cnt += (uint32_t)__popcll(mask);
         }
     }
     return cnt;
@@ -476,126 +539,175 @@ __device__ __forceinline__ uint32_t t3_slot(const EvDev &E, const Consts &K, int
 
 __global__ __launch_bounds__(BLOCK) void k_t3(EvDev E, ModDev M, Consts K)
 {
-    const int slot = blockIdx.x * WAVES + (threadIdx.x >> 6);
-    const bool act = slot < E.n_slots;
-    unsigned long long cand = 0;
-    uint32_t cnt = act ? t3_slot<false>(E, K, slot, 0, &cand) : 0u;
-    (void)cand;
-    bool ovf;
-    uint32_t off = block_reserve(cnt, &E.gc[GC_T3], E.cap_t3, E.gc, 2, ovf);
-    if (!act) return;
-    if (ovf) {
-        const int32_t sA = E.md_start[slot], nA = E.md_cnt[slot];
-        for (int32_t ii = lane_id(); ii < nA; ii += 64) {
-            E.t3_start[sA + ii] = 0;
-            E.t3_cnt[sA + ii] = 0;
+    __shared__ int32_t s_b[WAVES][STAGE];
+    __shared__ int32_t s_c[WAVES][STAGE];
+    __shared__ float s_k[WAVES][STAGE];
+    if (upstream_overflow(E)) return;
+    const int w = wave_id();
+    const Regions R = load_regions(E, OT_MD);
+    for (uint32_t base = blockIdx.x * WAVES; base < R.total; base += gridDim.x * WAVES) {
+        const uint32_t v = base + w;
+        const bool act = v < R.total;
+        const int32_t a = region_index(R, act ? v : 0);
+        uint32_t cnt = 0;
+        if (act)
+            cnt = enum_t3(E, K, a, [&](bool ok, int32_t b, int32_t c, float k, uint32_t pos) {
+                if (ok && pos < STAGE) {
+                    s_b[w][pos] = b;
+                    s_c[w][pos] = c;
+                    s_k[w][pos] = k;
+                }
+            });
+        bool ovf;
+        const uint32_t off = block_reserve(cnt, E, OT_T3, ovf);
+        if (!act) continue;
+        if (lane_id() == 0) {
+            E.t3_start[a] = (int32_t)off;
+            E.t3_cnt[a] = ovf ? 0 : (int32_t)cnt;
         }
-        return;
+        if (ovf || cnt == 0) continue;
+        if (cnt <= STAGE) {
+            for (uint32_t k = lane_id(); k < cnt; k += 64) {
+                E.t3_a[off + k] = a;
+                E.t3_b[off + k] = s_b[w][k];
+                E.t3_c[off + k] = s_c[w][k];
+                E.t3_k[off + k] = s_k[w][k];
+            }
+        } else {
+            enum_t3(E, K, a, [&](bool ok, int32_t b, int32_t c, float k, uint32_t pos) {
+                if (ok) {
+                    E.t3_a[off + pos] = a;
+                    E.t3_b[off + pos] = b;
+                    E.t3_c[off + pos] = c;
+                    E.t3_k[off + pos] = k;
+                }
+            });
+        }
     }
-    t3_slot<true>(E, K, slot, off, nullptr);
 }
 
 hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s)
 {
-    int blocks = (E.n_slots + WAVES - 1) / WAVES;
-    hipLaunchKernelGGL(k_t3, dim3(blocks), dim3(BLOCK), 0, s, E, M, K);
+    hipLaunchKernelGGL(k_t3, dim3(GRID_MAX), dim3(BLOCK), 0, s, E, M, K);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- a4: quintuplets
-template <bool WRITE>
-__device__ __forceinline__ uint32_t t5_slot(const EvDev &E, const Consts &K, int slot,
-                                            uint32_t pos, unsigned long long *cand)
+// Candidates of inner MD a: every triplet (a,b,c) followed by every triplet
+// (c,d,e).  sink(ok, b, c, d, e, score, pos)
+template <class F>
+__device__ __forceinline__ uint32_t enum_t5(const EvDev &E, const Consts &K, int32_t a, F &&sink)
 {
     const int lane = lane_id();
-    const int32_t sA = E.md_start[slot];
-    const int32_t nA = E.md_cnt[slot];
+    const int32_t nt1 = E.t3_cnt[a];
+    const int32_t t10 = E.t3_start[a];
     uint32_t cnt = 0;
-    for (int32_t ii = 0; ii < nA; ++ii) {
-        const int32_t a = sA + ii;
-        const int32_t nt1 = E.t3_cnt[a];
-        const int32_t t10 = E.t3_start[a];
-        if (nt1 <= 0) continue;
-        const MdV A = load_md(E, a);
-        for (int32_t c1 = 0; c1 < nt1; c1 += 64) {
-            int32_t k = c1 + lane;
-            int32_t t1 = 0, cs = 0;
-            uint32_t nc = 0;
-            if (k < nt1) {
-                t1 = t10 + k;
-                int32_t c = E.t3_c[t1];
-                cs = E.t3_start[c];
-                nc = (uint32_t)E.t3_cnt[c];
+    if (nt1 <= 0) return 0;
+    const MdV A = load_md(E, a);
+    for (int32_t c1 = 0; c1 < nt1; c1 += 64) {
+        const int32_t k = c1 + lane;
+        int32_t t1 = 0, cs = 0;
+        uint32_t nc = 0;
+        if (k < nt1) {
+            t1 = t10 + k;
+            const int32_t c = E.t3_c[t1];
+            cs = E.t3_start[c];
+            nc = (uint32_t)E.t3_cnt[c];
+        }
+        const uint32_t incl = wave_incl_scan(nc);
+        const uint32_t tot = __shfl(incl, 63, 64);
+        for (uint32_t jc = 0; jc < tot; jc += 64) {
+            const uint32_t j = jc + lane;
+            const int src = wave_find(incl, j < tot ? j : tot - 1);
+            const uint32_t ex = __shfl(incl, src, 64) - __shfl(nc, src, 64);
+            const int32_t tt1 = __shfl(t1, src, 64);
+            const int32_t tcs = __shfl(cs, src, 64);
+            bool ok = false;
+            int32_t b = 0, c = 0, d = 0, e = 0;
+            float score = 0.0f;
+            if (j < tot) {
+                const int32_t t2 = tcs + (int32_t)(j - ex);
+                b = E.t3_b[tt1];
+                c = E.t3_c[tt1];
+                d = E.t3_b[t2];
+                e = E.t3_c[t2];
+                ok = t5_accept(K, A, load_md(E, b), load_md(E, c), load_md(E, d), load_md(E, e),
+                               E.t3_k[tt1], E.t3_k[t2], score);
             }
-            uint32_t incl = wave_incl_scan(nc);
-            uint32_t tot = __shfl(incl, 63, 64);
-            if (!WRITE) *cand += tot;
-            for (uint32_t jc = 0; jc < tot; jc += 64) {
-                uint32_t j = jc + lane;
-                int src = wave_find(incl, j < tot ? j : tot - 1);
-                uint32_t ex = __shfl(incl, src, 64) - __shfl(nc, src, 64);
-                int32_t tt1 = __shfl(t1, src, 64);
-                int32_t tcs = __shfl(cs, src, 64);
-                bool ok = false;
-                int32_t b = 0, c = 0, d = 0, e = 0;
-                float score = 0.0f;
-                if (j < tot) {
-                    int32_t t2 = tcs + (int32_t)(j - ex);
-                    b = E.t3_b[tt1];
-                    c = E.t3_c[tt1];
-                    d = E.t3_b[t2];
-                    e = E.t3_c[t2];
-                    float kin = E.t3_k[tt1], kout = E.t3_k[t2];
-                    const MdV B = load_md(E, b);
-                    const MdV C = load_md(E, c);
-                    const MdV D = load_md(E, d);
-                    const MdV Ee = load_md(E, e);
-                    ok = t5_accept(K, A, B, C, D, Ee, kin, kout, score);
-                }
-                unsigned long long mask = __ballot(ok);
-                if (WRITE && ok) {
-                    uint32_t at = pos + cnt + (uint32_t)__popcll(mask & lanes_below());
-                    E.t5_md0[at] = a;
-                    E.t5_md1[at] = b;
-                    E.t5_md2[at] = c;
-                    E.t5_md3[at] = d;
-                    E.t5_md4[at] = e;
-                    E.t5_score[at] = score;
-                    E.t5_keep[at] = 0;
-                }
-                cnt += (uint32_t)__popcll(mask);
-            }
+            const unsigned long long mask = __ballot(ok);
+            sink(ok, b, c, d, e, score, cnt + (uint32_t)__popcll(mask & lanes_below()));
+            cnt += (uint32_t)__popcll(mask);
         }
     }
     return cnt;
 }
 
+__device__ __forceinline__ void write_t5(const EvDev &E, uint32_t at, int32_t a, int32_t b,
+                                         int32_t c, int32_t d, int32_t e, float score)
+{
+    E.t5_md0[at] = a;
+    E.t5_md1[at] = b;
+    E.t5_md2[at] = c;
+    E.t5_md3[at] = d;
+    E.t5_md4[at] = e;
+    E.t5_score[at] = score;
+    E.t5_keep[at] = 0;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_t5(EvDev E, ModDev M, Consts K)
 {
-    const int slot = blockIdx.x * WAVES + (threadIdx.x >> 6);
-    const bool act = slot < E.n_slots;
-    unsigned long long cand = 0;
-    uint32_t cnt = act ? t5_slot<false>(E, K, slot, 0, &cand) : 0u;
-    (void)cand;
-    bool ovf;
-    uint32_t off = block_reserve(cnt, &E.gc[GC_T5], E.cap_t5, E.gc, 3, ovf);
-    if (!act) return;
-    if (ovf) return;
-    t5_slot<true>(E, K, slot, off, nullptr);
+    __shared__ int32_t s_b[WAVES][STAGE], s_c[WAVES][STAGE], s_d[WAVES][STAGE],
+        s_e[WAVES][STAGE];
+    __shared__ float s_s[WAVES][STAGE];
+    if (upstream_overflow(E)) return;
+    const int w = wave_id();
+    const Regions R = load_regions(E, OT_MD);
+    for (uint32_t base = blockIdx.x * WAVES; base < R.total; base += gridDim.x * WAVES) {
+        const uint32_t v = base + w;
+        const bool act = v < R.total;
+        const int32_t a = region_index(R, act ? v : 0);
+        uint32_t cnt = 0;
+        if (act)
+            cnt = enum_t5(E, K, a, [&](bool ok, int32_t b, int32_t c, int32_t d, int32_t e,
+                                       float sc, uint32_t pos) {
+                if (ok && pos < STAGE) {
+                    s_b[w][pos] = b;
+                    s_c[w][pos] = c;
+                    s_d[w][pos] = d;
+                    s_e[w][pos] = e;
+                    s_s[w][pos] = sc;
+                }
+            });
+        bool ovf;
+        const uint32_t off = block_reserve(cnt, E, OT_T5, ovf);
+        if (!act || ovf || cnt == 0) continue;
+        if (cnt <= STAGE) {
+            for (uint32_t k = lane_id(); k < cnt; k += 64)
+                write_t5(E, off + k, a, s_b[w][k], s_c[w][k], s_d[w][k], s_e[w][k], s_s[w][k]);
+        } else {
+            enum_t5(E, K, a, [&](bool ok, int32_t b, int32_t c, int32_t d, int32_t e, float sc,
+                                 uint32_t pos) {
+                if (ok) write_t5(E, off + pos, a, b, c, d, e, sc);
+            });
+        }
+    }
 }
 
 hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s)
 {
-    int blocks = (E.n_slots + WAVES - 1) / WAVES;
-    hipLaunchKernelGGL(k_t5, dim3(blocks), dim3(BLOCK), 0, s, E, M, K);
+    hipLaunchKernelGGL(k_t5, dim3(GRID_MAX), dim3(BLOCK), 0, s, E, M, K);
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- a5: dedup
+// ---------------------------------------------------------------- a5: duplicate removal
 // A quintuplet survives iff for each of its hits it has the smallest key
 // (score, hit tuple) among the quintuplets using that hit.  Scores are
-// non-negative, so their bit patterns order like the floats.
-__device__ __forceinline__ int t5_md(const EvDev &E, int32_t t, int j)
+// non-negative, so their bit patterns order like the floats.  Quintuplets
+// reaching a hit's minimum score are recorded in TIE_SLOTS per-hit slots:
+// exact score ties are common (two quintuplets that differ only in the
+// upper hit of one mini-doublet have the same anchors, hence the same
+// score) and are resolved by the hit tuple.
+__device__ __forceinline__ int32_t t5_md(const EvDev &E, int32_t t, int j)
 {
     switch (j) {
     case 0: return E.t5_md0[t];
@@ -608,41 +720,62 @@ __device__ __forceinline__ int t5_md(const EvDev &E, int32_t t, int j)
 
 __device__ __forceinline__ int32_t t5_hit(const EvDev &E, int32_t t, int j)
 {
-    int32_t md = t5_md(E, t, j >> 1);
+    const int32_t md = t5_md(E, t, j >> 1);
     return (j & 1) ? E.md_hup[md] : E.md_hlo[md];
 }
 
-__device__ __forceinline__ int32_t n_t5(const EvDev &E)
+// Compact index over the stored quintuplets: the block keeps the prefix of
+// the NSH region sizes in LDS; a thread maps v to its array index with a
+// binary search over it.
+__device__ __forceinline__ uint32_t t5_prefix(const EvDev &E, uint32_t *s_pre)
 {
-    int64_t n = E.gc[GC_T5];
-    if (E.gc[GC_OVERFLOW] & 8) n = 0;
-    return (int32_t)(n < E.cap_t5 ? n : E.cap_t5);
+    if (threadIdx.x == 0) {
+        const uint32_t rc = E.rc[OT_T5];
+        uint32_t acc = 0;
+        for (int r = 0; r < NSH; ++r) {
+            s_pre[r] = acc;
+            const uint32_t c = E.gc[GC_SH + OT_T5 * NSH + r];
+            acc += c < rc ? c : rc;
+        }
+        s_pre[NSH] = acc;
+    }
+    __syncthreads();
+    return s_pre[NSH];
 }
 
+__device__ __forceinline__ int32_t t5_at(const EvDev &E, const uint32_t *s_pre, uint32_t v)
+{
+    int lo = 0, hi = NSH - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pre[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return (int32_t)((uint32_t)lo * E.rc[OT_T5] + (v - s_pre[lo]));
+}
+
+// one thread per (quintuplet, hit)
 __global__ void k_dedup_min(EvDev E)
 {
-    const int32_t n = n_t5(E);
-    for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-        uint32_t key = __float_as_uint(E.t5_score[t]);
-        for (int j = 0; j < 10; ++j) atomicMin(&E.hmin[t5_hit(E, t, j)], key);
+    __shared__ uint32_t s_pre[NSH + 1];
+    if (upstream_overflow(E)) return;
+    const uint32_t n = t5_prefix(E, s_pre) * 10u;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int32_t t = t5_at(E, s_pre, v / 10u);
+        atomicMin(&E.hmin[t5_hit(E, t, (int)(v % 10u))], __float_as_uint(E.t5_score[t]));
     }
 }
 
-// Quintuplets reaching a hit's minimum score are recorded in TIE_SLOTS
-// per-hit slots; exact score ties are common (two quintuplets that differ
-// only in the upper hit of one mini-doublet have the same anchors, hence the
-// same score) and are resolved by the hit tuple.
 __global__ void k_dedup_tie(EvDev E)
 {
-    const int32_t n = n_t5(E);
-    for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-        uint32_t key = __float_as_uint(E.t5_score[t]);
-        for (int j = 0; j < 10; ++j) {
-            int32_t h = t5_hit(E, t, j);
-            if (E.hmin[h] == key) {
-                int k = atomicAdd(&E.htie[h], 1);
-                if (k < TIE_SLOTS) E.hslot[(size_t)h * TIE_SLOTS + k] = t;
-            }
+    __shared__ uint32_t s_pre[NSH + 1];
+    if (upstream_overflow(E)) return;
+    const uint32_t n = t5_prefix(E, s_pre) * 10u;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int32_t t = t5_at(E, s_pre, v / 10u);
+        const int32_t h = t5_hit(E, t, (int)(v % 10u));
+        if (E.hmin[h] == __float_as_uint(E.t5_score[t])) {
+            const int k = atomicAdd(&E.htie[h], 1);
+            if (k < TIE_SLOTS) E.hslot[(size_t)h * TIE_SLOTS + k] = t;
         }
     }
 }
@@ -651,35 +784,49 @@ __global__ void k_dedup_tie(EvDev E)
 __device__ __forceinline__ bool tuple_less(const EvDev &E, int32_t u, int32_t t)
 {
     for (int j = 0; j < 10; ++j) {
-        int32_t a = E.sorig[t5_hit(E, u, j)], b = E.sorig[t5_hit(E, t, j)];
+        const int32_t a = E.sorig[t5_hit(E, u, j)], b = E.sorig[t5_hit(E, t, j)];
         if (a != b) return a < b;
     }
     return false;
 }
 
+// one thread per quintuplet; the ten hit lookups are independent loads
 __global__ void k_dedup_keep(EvDev E)
 {
-    const int32_t n = n_t5(E);
-    for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    __shared__ uint32_t s_pre[NSH + 1];
+    if (upstream_overflow(E)) return;
+    const uint32_t n = t5_prefix(E, s_pre);
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int32_t t = t5_at(E, s_pre, v);
         const float sc = E.t5_score[t];
         const uint32_t key = __float_as_uint(sc);
+        int32_t h[10];
+        uint32_t hm[10];
+        int nt[10];
+#pragma unroll
+        for (int j = 0; j < 10; ++j) h[j] = t5_hit(E, t, j);
+#pragma unroll
+        for (int j = 0; j < 10; ++j) {
+            hm[j] = E.hmin[h[j]];
+            nt[j] = E.htie[h[j]];
+        }
         bool keep = true;
+#pragma unroll
+        for (int j = 0; j < 10; ++j) keep = keep && (hm[j] == key);
         for (int j = 0; j < 10 && keep; ++j) {
-            int32_t h = t5_hit(E, t, j);
-            if (E.hmin[h] != key) { keep = false; break; }
-            const int nt = E.htie[h];
-            if (nt <= 1) continue;
-            if (nt <= TIE_SLOTS) {
-                for (int k = 0; k < nt && keep; ++k) {
-                    int32_t u = E.hslot[(size_t)h * TIE_SLOTS + k];
+            if (nt[j] <= 1) continue;
+            if (nt[j] <= TIE_SLOTS) {
+                for (int k = 0; k < nt[j] && keep; ++k) {
+                    const int32_t u = E.hslot[(size_t)h[j] * TIE_SLOTS + k];
                     if (u != t && tuple_less(E, u, t)) keep = false;
                 }
             } else {
-                // more ties than slots: scan every quintuplet (never seen in practice)
-                for (int32_t u = 0; u < n && keep; ++u) {
+                // more tied quintuplets than slots: scan them all (rare)
+                for (uint32_t q = 0; q < n && keep; ++q) {
+                    const int32_t u = t5_at(E, s_pre, q);
                     if (u == t || E.t5_score[u] != sc) continue;
                     bool uses = false;
-                    for (int k = 0; k < 10; ++k) uses |= (t5_hit(E, u, k) == h);
+                    for (int k = 0; k < 10; ++k) uses |= (t5_hit(E, u, k) == h[j]);
                     if (uses && tuple_less(E, u, t)) keep = false;
                 }
             }
@@ -690,7 +837,8 @@ __global__ void k_dedup_keep(EvDev E)
 
 hipError_t launch_dedup(const EvDev &E, const ModDev &M, hipStream_t s)
 {
-    int blocks = 1024;
+    (void)M;
+    const int blocks = 512;
     hipLaunchKernelGGL(k_dedup_min, dim3(blocks), dim3(BLOCK), 0, s, E);
     hipLaunchKernelGGL(k_dedup_tie, dim3(blocks), dim3(BLOCK), 0, s, E);
     hipLaunchKernelGGL(k_dedup_keep, dim3(blocks), dim3(BLOCK), 0, s, E);

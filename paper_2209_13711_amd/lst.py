@@ -255,8 +255,9 @@ class Context:
                                                ctypes.byref(n), self._stream(stream)))
         return out[:n.value]
 
-    def run_batch(self, offsets, x, y, z, module, sensor, stream=None, max_retry=3):
-        """Load, run the chain and grow the arena to the reported need on overflow."""
+    def run_batch(self, offsets, x, y, z, module, sensor, stream=None, max_retry=8):
+        """Load, run the chain and grow the arena to the reported need on overflow
+        (a stage's need is known once its upstream fits: one retry per stage)."""
         for _ in range(max_retry):
             self.load_hits(offsets, x, y, z, module, sensor, stream)
             self.run_chain(stream)
