@@ -96,10 +96,11 @@ def main():
         if events is not None:
             events[-1].record(stream)
 
+    # instrumented timed region: eager stage calls with HIP events between
+    # them on the launch stream -> per-kernel durations for the roofline
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
            for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -107,12 +108,22 @@ def main():
     for k in range(args.steps):
         step(evs[k])
     torch.cuda.synchronize()
+    dt_eager = time.perf_counter() - t0
+
+    # headline timed region: the same chain replayed as one hipGraph per step
+    for _ in range(args.warmup):
+        ctx.run_chain_graph(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ctx.run_chain_graph(stream)
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
     stage_ms = {name: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1])
                                      for k in range(args.steps)]))
                 for i, (name, _) in enumerate(stages)}
-    c2 = ctx.counts(0)
+    c2 = ctx.counts(0)   # after the graph replays
     assert c2["n_t5_kept"] == cnt["n_t5_kept"], "result changed between runs"
 
     abytes = algorithmic_bytes(cnt, n_slots, n_edges_used)
@@ -139,6 +150,7 @@ def main():
                    "events_per_step": 1, "hits": int(ev.n_hits)},
         "candidates_per_s": cands * value,
         "stage_ms": stage_ms,
+        "eager_events_per_s": args.steps / dt_eager,
         "objects": {k: int(cnt[k]) for k in ("n_md", "n_seg", "n_t3", "n_t5", "n_t5_kept")},
         "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -162,6 +162,12 @@ int lst_run_quintuplets(lst_ctx *ctx, void *stream);
 int lst_run_dedup(lst_ctx *ctx, void *stream);
 int lst_run_chain(lst_ctx *ctx, void *stream);
 
+/* The same chain as lst_run_chain, launched as one hipGraph.  The graph is
+ * captured on the first call after lst_attach_arena and replayed afterwards
+ * for any batch that fits the arena (batch sizes are read on the device).
+ * Results are identical to lst_run_chain. */
+int lst_run_chain_graph(lst_ctx *ctx, void *stream);
+
 /* Synchronise `stream`, then report event `event` (0..n_events-1).  Returns
  * LST_E_CAPACITY when any stage overflowed (counts still filled). */
 int lst_get_counts(lst_ctx *ctx, int32_t event, lst_counts *out, void *stream);

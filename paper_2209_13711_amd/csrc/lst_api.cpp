@@ -46,6 +46,12 @@ struct lst_ctx {
     // batch
     int n_events = 0;
     std::vector<int32_t> hit_off;
+    int32_t *stage_host = nullptr;   // pinned: batch descriptor + hit offsets
+    size_t stage_cap = 0;
+    hipEvent_t stage_done = nullptr;
+    bool stage_pending = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
     std::vector<lst_counts> counts;
     bool counts_valid = false;
     int stage = 0;  // 0 nothing, 1 hits loaded, 2 sorted, 3 md, 4 seg, 5 t3, 6 t5, 7 dedup
@@ -125,8 +131,10 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     const int64_t slots = (int64_t)k.events * c->n_mod;
     const int64_t keys = 2 * slots;
     E = EvDev{};
-    E.n_slots = (int32_t)slots;
-    E.n_keys = (int32_t)keys;
+    E.cap_ev = k.events;
+    E.cap_slots = (int32_t)slots;
+    E.cap_keys = (int32_t)keys;
+    E.desc = cv.take<int32_t>(D_COUNT);
     E.cap_hits = k.hits;
     const int64_t caps[OT_COUNT] = {k.md, k.seg, k.t3, k.t5};
     size_t span[OT_COUNT];
@@ -232,13 +240,24 @@ int lst_create(lst_ctx **out, int device, const double *params, int32_t n_params
     return LST_OK;
 }
 
+static void drop_graph(lst_ctx *c)
+{
+    if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+}
+
 void lst_destroy(lst_ctx *c)
 {
     if (!c) return;
-    if (c->geo_dev) {
-        (void)hipSetDevice(c->device);
-        (void)hipFree(c->geo_dev);
-    }
+    (void)hipSetDevice(c->device);
+    drop_graph(c);
+    if (c->stage_done) (void)hipEventSynchronize(c->stage_done);
+    if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+    if (c->stage_host) (void)hipHostFree(c->stage_host);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->geo_dev) (void)hipFree(c->geo_dev);
     delete c;
 }
 
@@ -306,6 +325,7 @@ int lst_load_geometry(lst_ctx *c, int32_t n, const float *f32, const int32_t *i3
     M.map_col = dcol;
     M.n_mod = n;
     c->arena = nullptr;  // a new geometry invalidates the arena layout
+    drop_graph(c);
     c->stage = 0;
     return LST_OK;
 }
@@ -361,6 +381,20 @@ int lst_attach_arena(lst_ctx *c, void *dev_ptr, size_t bytes, const lst_caps *ca
     if (!dev_ptr) return fail(c, LST_E_INVALID, "null arena");
     if (((uintptr_t)dev_ptr & 255) != 0) return fail(c, LST_E_INVALID, "arena not 256-byte aligned");
     if (bytes < need) return fail(c, LST_E_CAPACITY, "arena needs %zu bytes, got %zu", need, bytes);
+    HIPCHK(c, hipSetDevice(c->device));
+    drop_graph(c);
+    if (c->stage_pending) {
+        HIPCHK(c, hipEventSynchronize(c->stage_done));
+        c->stage_pending = false;
+    }
+    const size_t want = (size_t)caps->events + 1 + D_COUNT;
+    if (c->stage_cap < want) {
+        if (c->stage_host) HIPCHK(c, hipHostFree(c->stage_host));
+        c->stage_host = nullptr;
+        HIPCHK(c, hipHostMalloc((void **)&c->stage_host, want * sizeof(int32_t), hipHostMallocDefault));
+        c->stage_cap = want;
+    }
+    if (!c->stage_done) HIPCHK(c, hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming));
     c->arena = (char *)dev_ptr;
     c->arena_bytes = bytes;
     c->caps = *caps;
@@ -399,13 +433,21 @@ int lst_load_hits(lst_ctx *c, int32_t n_events, const int32_t *hit_offsets, cons
         HIPCHK(c, hipMemcpyAsync(E.sensor, sensor, n, kind, s));
     }
     c->hit_off.assign(hit_offsets, hit_offsets + n_events + 1);
-    HIPCHK(c, hipMemcpyAsync(E.hit_off, c->hit_off.data(), sizeof(int32_t) * (n_events + 1),
+    // descriptor + offsets go through a pinned buffer; wait until the copy
+    // of the previous batch has left it
+    if (c->stage_pending) HIPCHK(c, hipEventSynchronize(c->stage_done));
+    int32_t *st = c->stage_host;
+    st[D_NEV] = n_events;
+    st[D_NHITS] = (int32_t)n;
+    st[D_NSLOTS] = n_events * c->n_mod;
+    st[D_NKEYS] = 2 * n_events * c->n_mod;
+    std::memcpy(st + D_COUNT, hit_offsets, sizeof(int32_t) * (n_events + 1));
+    HIPCHK(c, hipMemcpyAsync((void *)E.desc, st, sizeof(int32_t) * D_COUNT, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(E.hit_off, st + D_COUNT, sizeof(int32_t) * (n_events + 1),
                              hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipEventRecord(c->stage_done, s));
+    c->stage_pending = true;
     c->n_events = n_events;
-    E.n_ev = n_events;
-    E.n_slots = n_events * c->n_mod;
-    E.n_keys = 2 * E.n_slots;
-    E.n_hits = (int32_t)n;
     c->stage = 1;
     return LST_OK;
 }
@@ -485,6 +527,48 @@ int lst_run_chain(lst_ctx *c, void *stream)
     if ((rc = lst_run_triplets(c, stream))) return rc;
     if ((rc = lst_run_quintuplets(c, stream))) return rc;
     return lst_run_dedup(c, stream);
+}
+
+// The whole chain as one hipGraph: captured once per arena (kernel grids and
+// arguments depend on the arena only; batch sizes are read on the device)
+// and replayed for every batch.  Only kernel nodes: no memset nodes.
+static int enqueue_chain(lst_ctx *c, hipStream_t s)
+{
+    HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, s));
+    HIPCHK(c, launch_sort(c->E, c->M, s));
+    HIPCHK(c, launch_md(c->E, c->M, c->K, s));
+    HIPCHK(c, launch_seg(c->E, c->M, c->K, s));
+    HIPCHK(c, launch_t3(c->E, c->M, c->K, s));
+    HIPCHK(c, launch_t5(c->E, c->M, c->K, s));
+    HIPCHK(c, launch_dedup(c->E, c->M, s));
+    return LST_OK;
+}
+
+int lst_run_chain_graph(lst_ctx *c, void *stream)
+{
+    int rc = need_stage(c, 1, "lst_run_chain_graph");
+    if (rc) return rc;
+    if (!c->graph) {
+        if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+        rc = enqueue_chain(c, c->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(c, LST_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->graph = nullptr;
+            return fail(c, LST_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+    }
+    HIPCHK(c, hipGraphLaunch(c->graph, (hipStream_t)stream));
+    c->stage = 7;
+    return LST_OK;
 }
 
 // ---------------------------------------------------------------- results

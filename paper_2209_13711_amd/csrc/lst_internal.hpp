@@ -42,8 +42,13 @@ struct ModDev {
     int32_t n_mod;
 };
 
+// Batch descriptor, device resident so that a captured chain stays valid for
+// any batch that fits the arena: [n_events, n_hits, n_slots, n_keys].
+enum { D_NEV = 0, D_NHITS, D_NSLOTS, D_NKEYS, D_COUNT };
+
 struct EvDev {
-    int32_t n_ev, n_slots, n_keys, n_hits;
+    const int32_t *desc;             // [D_COUNT]
+    int32_t cap_ev, cap_slots, cap_keys;
     int64_t cap_hits;
     uint32_t rc[OT_COUNT];           // region capacity per shard, per object type
     // inputs as loaded

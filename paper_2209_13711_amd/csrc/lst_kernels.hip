@@ -161,9 +161,9 @@ __device__ __forceinline__ int event_of(const int32_t *off, int n_ev, int32_t h)
     return lo;
 }
 
-__device__ __forceinline__ int hit_key(const EvDev &E, int n_mod, int32_t h, int &ev)
+__device__ __forceinline__ int hit_key(const EvDev &E, int n_mod, int n_ev, int32_t h, int &ev)
 {
-    ev = event_of(E.hit_off, E.n_ev, h);
+    ev = event_of(E.hit_off, n_ev, h);
     int32_t m = E.module[h];
     uint8_t s = E.sensor[h];
     if (m < 0 || m >= n_mod || s > 1) return -1;
@@ -172,15 +172,14 @@ __device__ __forceinline__ int hit_key(const EvDev &E, int n_mod, int32_t h, int
 
 __global__ void k_hist(EvDev E, int n_mod)
 {
-    int32_t h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= E.n_hits) return;
-    int ev;
-    int key = hit_key(E, n_mod, h, ev);
-    if (key < 0) {
-        atomicOr(&E.gc[GC_ERROR], 1u);
-        return;
+    const int n_ev = E.desc[D_NEV], n_hits = E.desc[D_NHITS];
+    for (int32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < n_hits;
+         h += gridDim.x * blockDim.x) {
+        int ev;
+        const int key = hit_key(E, n_mod, n_ev, h, ev);
+        if (key < 0) atomicOr(&E.gc[GC_ERROR], 1u);
+        else atomicAdd(&E.bcnt[key], 1u);
     }
-    atomicAdd(&E.bcnt[key], 1u);
 }
 
 // exclusive scan of bcnt[0..n) into boff[0..n], three phases over tiles of 1024
@@ -203,8 +202,9 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t &total)
     return before + incl - v;
 }
 
-__global__ void k_scan_reduce(const uint32_t *in, int n, uint32_t *bsum)
+__global__ void k_scan_reduce(const uint32_t *in, const int32_t *np, uint32_t *bsum)
 {
+    const int n = *np;
     int base = blockIdx.x * SCAN_TILE + threadIdx.x * 4;
     uint32_t v = 0;
     for (int k = 0; k < 4; ++k)
@@ -227,9 +227,10 @@ __global__ void k_scan_top(uint32_t *bsum, int nb)
     }
 }
 
-__global__ void k_scan_down(const uint32_t *in, int n, const uint32_t *bsum, uint32_t *out,
-                            uint32_t *gc)
+__global__ void k_scan_down(const uint32_t *in, const int32_t *np, const uint32_t *bsum,
+                            uint32_t *out, uint32_t *gc)
 {
+    const int n = *np;
     int base = blockIdx.x * SCAN_TILE + threadIdx.x * 4;
     uint32_t v[4], s = 0;
     for (int k = 0; k < 4; ++k) {
@@ -239,48 +240,48 @@ __global__ void k_scan_down(const uint32_t *in, int n, const uint32_t *bsum, uin
     uint32_t tot;
     uint32_t ex = block_excl_scan(s, tot) + bsum[blockIdx.x];
     for (int k = 0; k < 4; ++k) {
-        if (base + k < n) out[base + k] = ex;
+        const int idx = base + k;
+        if (idx < n) out[idx] = ex;
+        if (idx == n) {   // the total, written by the thread covering index n
+            out[n] = ex;
+            gc[GC_N_SORTED] = ex;
+        }
         ex += v[k];
-    }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == BLOCK - 1) {
-        out[n] = ex;
-        gc[GC_N_SORTED] = ex;
     }
 }
 
 __global__ void k_scatter(EvDev E, int n_mod)
 {
-    int32_t h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= E.n_hits) return;
-    int ev;
-    int key = hit_key(E, n_mod, h, ev);
-    if (key < 0) return;
-    // positions are taken from the top of the bin down; bcnt ends at zero
-    uint32_t pos = E.boff[key] + atomicSub(&E.bcnt[key], 1u) - 1u;
-    E.sx[pos] = E.x[h];
-    E.sy[pos] = E.y[h];
-    E.sz[pos] = E.z[h];
-    E.sorig[pos] = h - E.hit_off[ev];
-    E.hmin[pos] = 0xffffffffu;
-    E.htie[pos] = 0;
+    const int n_ev = E.desc[D_NEV], n_hits = E.desc[D_NHITS];
+    for (int32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < n_hits;
+         h += gridDim.x * blockDim.x) {
+        int ev;
+        const int key = hit_key(E, n_mod, n_ev, h, ev);
+        if (key < 0) continue;
+        // positions are taken from the top of the bin down; bcnt ends at zero
+        const uint32_t pos = E.boff[key] + atomicSub(&E.bcnt[key], 1u) - 1u;
+        E.sx[pos] = E.x[h];
+        E.sy[pos] = E.y[h];
+        E.sz[pos] = E.z[h];
+        E.sorig[pos] = h - E.hit_off[ev];
+        E.hmin[pos] = 0xffffffffu;
+        E.htie[pos] = 0;
+    }
 }
 
+// grids depend on the arena capacities only, never on the batch
 hipError_t launch_sort(const EvDev &E, const ModDev &M, hipStream_t s)
 {
-    if (E.n_hits > 0) {
-        int blocks = (E.n_hits + BLOCK - 1) / BLOCK;
-        hipLaunchKernelGGL(k_hist, dim3(blocks), dim3(BLOCK), 0, s, E, M.n_mod);
-    }
-    int n = E.n_keys;
-    int nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(BLOCK), 0, s, E.bcnt, n, E.bsum);
+    int hb = (int)((E.cap_hits + BLOCK - 1) / BLOCK);
+    hb = hb < 1 ? 1 : (hb > GRID_MAX ? GRID_MAX : hb);
+    const int32_t *nkeys = E.desc + D_NKEYS;
+    const int nb = (E.cap_keys + 1 + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_hist, dim3(hb), dim3(BLOCK), 0, s, E, M.n_mod);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(BLOCK), 0, s, E.bcnt, nkeys, E.bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, s, E.bsum, nb);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(BLOCK), 0, s, E.bcnt, n, E.bsum, E.boff,
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(BLOCK), 0, s, E.bcnt, nkeys, E.bsum, E.boff,
                        E.gc);
-    if (E.n_hits > 0) {
-        int blocks = (E.n_hits + BLOCK - 1) / BLOCK;
-        hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(BLOCK), 0, s, E, M.n_mod);
-    }
+    hipLaunchKernelGGL(k_scatter, dim3(hb), dim3(BLOCK), 0, s, E, M.n_mod);
     return hipGetLastError();
 }
 
@@ -348,9 +349,10 @@ __global__ __launch_bounds__(BLOCK) void k_md(EvDev E, ModDev M, Consts K)
     __shared__ uint32_t s_lo[WAVES][STAGE];
     __shared__ uint32_t s_up[WAVES][STAGE];
     const int w = wave_id();
-    for (int base = blockIdx.x * WAVES; base < E.n_slots; base += gridDim.x * WAVES) {
+    const int n_slots = E.desc[D_NSLOTS];
+    for (int base = blockIdx.x * WAVES; base < n_slots; base += gridDim.x * WAVES) {
         const int slot = base + w;
-        const bool act = slot < E.n_slots;
+        const bool act = slot < n_slots;
         uint32_t lo0 = 0, up0 = 0, nup = 0, np = 0;
         if (act) {
             lo0 = E.boff[2 * slot];
@@ -398,7 +400,7 @@ __global__ __launch_bounds__(BLOCK) void k_md(EvDev E, ModDev M, Consts K)
 
 hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_md, dim3(grid_for(E.n_slots)), dim3(BLOCK), 0, s, E, M, K);
+    hipLaunchKernelGGL(k_md, dim3(grid_for(E.cap_slots)), dim3(BLOCK), 0, s, E, M, K);
     return hipGetLastError();
 }
 

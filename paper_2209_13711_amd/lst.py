@@ -65,6 +65,7 @@ _SIGS = {
     "lst_run_quintuplets": (ctypes.c_int, [_P, _P]),
     "lst_run_dedup": (ctypes.c_int, [_P, _P]),
     "lst_run_chain": (ctypes.c_int, [_P, _P]),
+    "lst_run_chain_graph": (ctypes.c_int, [_P, _P]),
     "lst_get_counts": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(lst_counts), _P]),
     "lst_get_objects": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64,
                                        ctypes.POINTER(ctypes.c_int64), _P]),
@@ -225,6 +226,9 @@ class Context:
     def run_chain(self, stream=None):
         self._check(self.lib.lst_run_chain(self.h, self._stream(stream)))
 
+    def run_chain_graph(self, stream=None):
+        self._check(self.lib.lst_run_chain_graph(self.h, self._stream(stream)))
+
     # -- outputs ------------------------------------------------------------
     def counts(self, event=0, stream=None, check=True) -> dict:
         c = lst_counts()
@@ -255,12 +259,15 @@ class Context:
                                                ctypes.byref(n), self._stream(stream)))
         return out[:n.value]
 
-    def run_batch(self, offsets, x, y, z, module, sensor, stream=None, max_retry=8):
+    def run_batch(self, offsets, x, y, z, module, sensor, stream=None, max_retry=8, graph=False):
         """Load, run the chain and grow the arena to the reported need on overflow
         (a stage's need is known once its upstream fits: one retry per stage)."""
         for _ in range(max_retry):
             self.load_hits(offsets, x, y, z, module, sensor, stream)
-            self.run_chain(stream)
+            if graph:
+                self.run_chain_graph(stream)
+            else:
+                self.run_chain(stream)
             c = lst_counts()
             ovf = False
             for e in range(self.n_events):
@@ -280,7 +287,7 @@ class Context:
             self.reserve(caps)
         raise LSTError(LST_E_CAPACITY, "capacity still exceeded after growing the arena")
 
-    def run_event(self, ev, stream=None):
+    def run_event(self, ev, stream=None, graph=False):
         offs = np.array([0, ev.n_hits], np.int32)
-        self.run_batch(offs, ev.x, ev.y, ev.z, ev.module, ev.sensor, stream)
+        self.run_batch(offs, ev.x, ev.y, ev.z, ev.module, ev.sensor, stream, graph=graph)
         return {k: self.objects(0, k, stream) for k in WIDTH}

@@ -152,3 +152,30 @@ def test_module_map_on_device_context_equals_oracle():
     optr, ocol = oracle.Oracle(params, geo.f32, geo.i32).module_map()
     np.testing.assert_array_equal(ptr, optr)
     np.testing.assert_array_equal(col, ocol)
+
+
+def test_graph_chain_replays_match_eager_and_oracle():
+    """The captured chain is replayed several times with eager work in
+    between, then fed a batch of a different size; every replay must equal
+    the eager chain and the oracle."""
+    import torch
+    geo = G.get("full")
+    params = PR.make()
+    orc = oracle.Oracle(params, geo.f32, geo.i32)
+    ctx = _ctx(geo, params)
+    ev0, ev1 = E.generate(2, 5, n_tracks=2500), E.generate(2, 6, n_tracks=1200)
+    print("case graph replays", ev0.n_hits, ev1.n_hits, flush=True)
+    eager = ctx.run_event(ev0)
+    ref0 = orc.run_event(ev0)
+    assert_parity(eager, ref0)
+    for rep in range(3):
+        got = ctx.run_event(ev0, graph=True)
+        assert_parity(got, ref0)
+        for k in range(5):
+            assert set(map(tuple, got[k].tolist())) == set(map(tuple, eager[k].tolist()))
+        # eager work on the same stream between replays
+        t = torch.arange(1 << 20, device="cuda", dtype=torch.float32)
+        assert float(t.sum().item()) == float((1 << 20) * ((1 << 20) - 1) / 2)
+        ctx.run_event(ev1)
+    got1 = ctx.run_event(ev1, graph=True)
+    assert_parity(got1, orc.run_event(ev1))
