@@ -23,6 +23,52 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 1 << 30
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_seg_pu200_traffic.txt")
+
+
+def kernel_source_digest():
+    """Digest of the kernel sources; counter figures taken from an older
+    source are not reported."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("lst_kernels.hip", "lst_cuts.hpp", "lst_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2209_13711_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when the summary is absent or was taken from other kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel") != kernel or kv.get("source_digest") != kernel_source_digest():
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def copy_bandwidth(lst, torch, reps=10):
+    """Achievable HBM bandwidth of the library's STREAM-like copy (read+write)."""
+    src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    lst.lst_stream_copy(dst, src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lst.lst_stream_copy(dst, src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * COPY_BYTES / (ms * 1e-3) / 1e9
 
 
 def algorithmic_bytes(c, n_slots, n_edges_used):
@@ -126,6 +172,7 @@ def main():
     c2 = ctx.counts(0)   # after the graph replays
     assert c2["n_t5_kept"] == cnt["n_t5_kept"], "result changed between runs"
 
+    copy_gbs = copy_bandwidth(lst, torch)
     abytes = algorithmic_bytes(cnt, n_slots, n_edges_used)
     dom = max(abytes, key=lambda k: stage_ms[k])
     achieved = abytes[dom] / (stage_ms[dom] * 1e-3) / 1e9
@@ -154,8 +201,11 @@ def main():
         "objects": {k: int(cnt[k]) for k in ("n_md", "n_seg", "n_t3", "n_t5", "n_t5_kept")},
         "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes": int(abytes[dom]),
-                     "duration_us": stage_ms[dom] * 1e3},
+                     "traffic": measured_traffic(f"k_{dom}"),
+                     "algorithmic_bytes": int(abytes[dom]),
+                     "duration_us": stage_ms[dom] * 1e3,
+                     "copy_GBps_measured": copy_gbs,
+                     "frac_vs_copy": achieved / copy_gbs},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(params, geo)

@@ -183,6 +183,12 @@ int lst_get_objects(lst_ctx *ctx, int32_t event, int32_t kind, int32_t *out_host
 int lst_get_t5_scores(lst_ctx *ctx, int32_t event, float *out_host, int64_t cap,
                       int64_t *n, void *stream);
 
+/* Project-written STREAM-like device copy (no context needed): dst = src for
+ * n_bytes (a multiple of 16, 16-byte aligned device pointers), asynchronous
+ * on `stream`.  Used to measure the achievable HBM bandwidth and to
+ * calibrate the FETCH_SIZE / WRITE_SIZE counters against a known byte count. */
+int lst_stream_copy(void *dst, const void *src, size_t n_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

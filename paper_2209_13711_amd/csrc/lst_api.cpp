@@ -580,6 +580,14 @@ static int sync_stream(lst_ctx *c, void *stream)
     return LST_OK;
 }
 
+int lst_stream_copy(void *dst, const void *src, size_t n_bytes, void *stream)
+{
+    if (!dst || !src || (n_bytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
+        return LST_E_INVALID;
+    if (launch_copy(dst, src, n_bytes, (hipStream_t)stream) != hipSuccess) return LST_E_HIP;
+    return LST_OK;
+}
+
 }  // extern "C"
 
 // Shard counters of every object type, read back from the device.

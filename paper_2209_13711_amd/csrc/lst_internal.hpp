@@ -92,6 +92,7 @@ constexpr int STAGE = 256;           // accepted objects a wave stages in LDS
 constexpr int GRID_MAX = 2048;       // blocks of a grid-stride stage kernel
 
 // launchers (lst_kernels.hip)
+hipError_t launch_copy(void *dst, const void *src, size_t n_bytes, hipStream_t s);
 hipError_t launch_zero(const EvDev &E, void *zero_base, size_t zero_bytes, hipStream_t s);
 hipError_t launch_sort(const EvDev &E, const ModDev &M, hipStream_t s);
 hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s);

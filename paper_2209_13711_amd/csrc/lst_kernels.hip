@@ -150,6 +150,23 @@ hipError_t launch_zero(const EvDev &, void *zero_base, size_t zero_bytes, hipStr
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- calibration copy
+__global__ __launch_bounds__(BLOCK) void k_copy(uint4 *__restrict__ dst,
+                                                const uint4 *__restrict__ src, size_t n16)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n16; i += stride) dst[i] = src[i];
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t n_bytes, hipStream_t s)
+{
+    const size_t n16 = n_bytes / 16;
+    // 8 blocks per CU of the 256 CUs, grid-stride
+    hipLaunchKernelGGL(k_copy, dim3(2048), dim3(BLOCK), 0, s, (uint4 *)dst, (const uint4 *)src, n16);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- a0: hit grouping
 __device__ __forceinline__ int event_of(const int32_t *off, int n_ev, int32_t h)
 {

@@ -71,6 +71,7 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_int64), _P]),
     "lst_get_t5_scores": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64,
                                          ctypes.POINTER(ctypes.c_int64), _P]),
+    "lst_stream_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -112,6 +113,17 @@ def lst_build_map(params, geo_f32, geo_i32):
     if rc != LST_OK:
         raise LSTError(rc, "lst_build_map")
     return ptr, col[:ne.value]
+
+
+def lst_stream_copy(dst: "torch.Tensor", src: "torch.Tensor", stream=None):
+    """Device copy dst <- src through the library's STREAM-like kernel."""
+    lib = load_library()
+    assert dst.is_cuda and src.is_cuda and dst.numel() * dst.element_size() == src.numel() * src.element_size()
+    s = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+    rc = lib.lst_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                             src.numel() * src.element_size(), s)
+    if rc != LST_OK:
+        raise LSTError(rc, "lst_stream_copy")
 
 
 def default_caps(n_events: int, n_hits: int) -> dict:
