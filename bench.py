@@ -101,12 +101,62 @@ def cpu_baseline(params, geo, budget_s=12.0, max_events=200):
                       f"incl. hit grouping and FP64 margins, single thread, {t_total:.1f} s"}
 
 
+def batched(lst, torch, E, G, PR, n_events=64, steps=20):
+    """64 events of uneven pileup (20 x Poisson(U(50, 250)) helices each, barrel
+    toy geometry) in one launch: autotuned launch shape, then the batch timed
+    as one hipGraph replay (per-stage kernels or the persistent kernel, as
+    the tuner chose), the persistent kernel alone, and the same events one at
+    a time through the single-event graph."""
+    geo = G.get("barrel_toy")
+    params = PR.make()
+    evs = [E.generate(3, e) for e in range(n_events)]
+    b = E.concat(evs)
+    ctx = lst.Context(params, geo.f32, geo.i32, device=0)
+    ctx.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+    tuned = ctx.tune(reps=3)
+    stream = torch.cuda.current_stream()
+
+    def timeit(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    ctx.load_hits(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+    t_graph = timeit(lambda: ctx.run_chain_graph(stream), steps)
+    kept = sum(ctx.counts(e)["n_t5_kept"] for e in range(n_events))
+    t_pers = timeit(lambda: ctx.run_chain_persistent(stream), steps)
+    kept_p = sum(ctx.counts(e)["n_t5_kept"] for e in range(n_events))
+    assert kept == kept_p, "persistent chain changed the result"
+    # one event per launch, same events
+    single = lst.Context(params, geo.f32, geo.i32, device=0)
+    single.reserve(dict(ctx.caps, events=1))
+    per_event = []
+    for ev in evs[:8]:
+        single.load_hits(np.array([0, ev.n_hits], np.int32), ev.x, ev.y, ev.z, ev.module, ev.sensor)
+        per_event.append(timeit(lambda: single.run_chain_graph(stream), 5))
+    t_single = float(np.mean(per_event))
+    return {"workload": "64 uneven events (config 3): 20 x Poisson(U(50,250)) helices, "
+                        "barrel toy geometry, plain chain",
+            "hits": int(b.offsets[-1]), "events": n_events,
+            "events_per_s": n_events / t_graph,
+            "ms_per_batch": 1e3 * t_graph,
+            "persistent_events_per_s": n_events / t_pers,
+            "one_event_per_launch_events_per_s": 1.0 / t_single,
+            "tuning": {k: tuned[k] for k in ("grid", "persistent", "blocks_per_cu")},
+            "tuner_report_us": tuned["report_us"], "t5_kept": int(kept)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-event batch figures")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); events are "
@@ -207,6 +257,8 @@ def main():
                      "copy_GBps_measured": copy_gbs,
                      "frac_vs_copy": achieved / copy_gbs},
     }
+    if not args.no_batch:
+        out["batched"] = batched(lst, torch, E, G, PR)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(params, geo)
     print(json.dumps(out), flush=True)

@@ -89,6 +89,7 @@ typedef struct {
     int64_t seg;
     int64_t t3;
     int64_t t5;
+    int32_t features; /* nonzero: also hold the 40 scorer features per quintuplet */
 } lst_caps;
 
 /* per-event result summary.  n_* are the numbers of objects and cand_* the
@@ -178,10 +179,49 @@ int lst_get_counts(lst_ctx *ctx, int32_t event, lst_counts *out, void *stream);
 int lst_get_objects(lst_ctx *ctx, int32_t event, int32_t kind, int32_t *out_host,
                     int64_t cap_tuples, int64_t *n_tuples, void *stream);
 
+/* The 40 FP32 features of every stored quintuplet for the learned scorer
+ * (asynchronous; needs an arena with caps.features set): per mini-doublet
+ * r/100, z/100, bend pull, endcap flag, 2S flag; inner, outer and bridge
+ * curvature over kappa_max; chi2/(1+chi2) in r-phi and r-z; r-phi pulls of
+ * the 2nd and 4th anchors; r-z pulls of the 2nd to 4th; inner and outer
+ * curvature agreement over its tolerance; r-z slope; lever arm/100; a
+ * transverse impact parameter estimate.  lst_get_t5_features copies them
+ * (40 per quintuplet, order of lst_get_objects(LST_T5)). */
+int lst_run_t5_features(lst_ctx *ctx, void *stream);
+int lst_get_t5_features(lst_ctx *ctx, int32_t event, float *out_host, int64_t cap_rows,
+                        int64_t *n_rows, void *stream);
+
 /* Quintuplet scores (chi2_rphi + chi2_rz) of `event`, in the order of
  * lst_get_objects(LST_T5). */
 int lst_get_t5_scores(lst_ctx *ctx, int32_t event, float *out_host, int64_t cap,
                       int64_t *n, void *stream);
+
+/* The whole chain as ONE persistent kernel: every stage runs inside a single
+ * launch, separated by grid-wide barriers (release/acquire at device scope).
+ * The grid is blocks_per_cu x compute units, bounded by the occupancy limit
+ * so that every block is resident; a barrier that does not complete within
+ * about half a second raises error_flags bit 1 and the kernel ends (no hang).
+ * Results are identical to lst_run_chain.  lst_run_chain and
+ * lst_run_chain_graph use this kernel when the tuning selects it. */
+int lst_run_chain_persistent(lst_ctx *ctx, void *stream);
+
+/* Launch shape: grid6 = blocks of 256 threads for the stages (hit grouping,
+ * MD, segments, T3, T5, dedup); persistent = 1 runs the chain as one
+ * persistent kernel of blocks_per_cu x CUs blocks.  lst_get_tuning fills
+ * out9 = grid6, persistent, blocks_per_cu, number of CUs. */
+int lst_set_tuning(lst_ctx *ctx, const int32_t *grid6, int32_t persistent, int32_t blocks_per_cu);
+int lst_get_tuning(const lst_ctx *ctx, int32_t *out9);
+
+/* Autotuner over the loaded batch: for each stage in turn, every candidate
+ * grid is timed (median of `reps` chains, HIP events on `stream`) and its
+ * outputs checksummed against the default launch shape (a candidate that
+ * changes any object fails the call); then the persistent kernel is timed
+ * for every co-resident blocks-per-CU value, and the faster of the per-stage
+ * chain and the persistent chain is selected.  With cache_path, a choice
+ * stored for the same batch shape is reused, and new choices are appended
+ * (one JSON line each).  report (optional, 8 doubles): best per-stage us,
+ * whole-chain us, persistent-chain us; report[0] = -1 when cached. */
+int lst_tune(lst_ctx *ctx, const char *cache_path, int32_t reps, double *report, void *stream);
 
 /* Project-written STREAM-like device copy (no context needed): dst = src for
  * n_bytes (a multiple of 16, 16-byte aligned device pointers), asynchronous

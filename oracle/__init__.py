@@ -63,6 +63,7 @@ def _load():
     lib.orc_t5_scores.argtypes = [P, P]
     lib.orc_t5_keep.argtypes = [P, P]
     lib.orc_t3_curv.argtypes = [P, P]
+    lib.orc_t5_features.argtypes = [P, P]
     lib.orc_near_count.restype = ctypes.c_int64
     lib.orc_near_count.argtypes = [P, ctypes.c_int]
     lib.orc_near.argtypes = [P, ctypes.c_int, P, P, P]
@@ -87,6 +88,7 @@ class Result:
     t5_scores: np.ndarray
     t5_keep: np.ndarray
     t3_curv: np.ndarray
+    t5_features: np.ndarray  # float32 [n_t5, 40]
     cands: np.ndarray       # int64 [4]
     near: dict              # kind -> (tuples, margins, decisions)
 
@@ -152,6 +154,7 @@ class Oracle:
         n3 = lib.orc_count(h, T3)
         k3 = np.zeros(max(n3, 1), np.float32); lib.orc_t3_curv(h, _ptr(k3))
         cands = np.zeros(4, np.int64); lib.orc_cands(h, _ptr(cands))
+        ft = np.zeros((max(n5, 1), 40), np.float32); lib.orc_t5_features(h, _ptr(ft))
         near = {}
         for kind in (MD, SEG, T3, T5):
             nn = lib.orc_near_count(h, kind)
@@ -161,7 +164,7 @@ class Oracle:
             lib.orc_near(h, kind, _ptr(tt), _ptr(mg), _ptr(dc))
             near[kind] = (tt[:nn], mg[:nn], dc[:nn])
         return Result(tuples=tuples, t5_scores=sc[:n5], t5_keep=kp[:n5].astype(bool),
-                      t3_curv=k3[:n3], cands=cands, near=near)
+                      t3_curv=k3[:n3], t5_features=ft[:n5], cands=cands, near=near)
 
     # -- single-candidate evaluation (closed-form checks) -------------------
     def eval_md(self, module: int, lo3, up3):

@@ -51,7 +51,7 @@ typedef struct {
 
 typedef struct {
     float x, y, z, r, a, ca, dx, dy, dn, bend, sv;
-    int barrel, module, hlo, hup;
+    int barrel, is2s, module, hlo, hup;
 } MDREC;
 
 typedef struct {
@@ -60,7 +60,7 @@ typedef struct {
 } CUTREC;
 
 typedef struct {
-    double kbr, resb, resd, pullb, pulld, zpull[3], chi2p, chi2z, score;
+    double kbr, resb, resd, pullb, pulld, zpull[3], chi2p, chi2z, score, tin, tout, sl, lae, kO;
 } T5AUX;
 
 /* float instance: the decisions */
@@ -68,7 +68,9 @@ typedef struct {
 #define FN(name) name##_f
 #define SQRT sqrtf
 #define FABS fabsf
+#define CUTS_FEATURES
 #include "cuts.inc"
+#undef CUTS_FEATURES
 #undef R
 #undef FN
 #undef SQRT
@@ -125,7 +127,7 @@ static void gv_free(gvec *a) { free(a->v); a->v = NULL; a->n = a->cap = 0; }
 
 typedef struct { int32_t i, o; } SEGREC;
 typedef struct { int32_t a, b, c; float k; } T3REC;
-typedef struct { int32_t md[5]; float score; } T5REC;
+typedef struct { int32_t md[5]; float score; float feat[40]; } T5REC;
 typedef struct { int32_t hits[10]; double margin; uint8_t decision; } NEARREC;
 
 struct orc {
@@ -422,6 +424,7 @@ static int make_md(const orc *o, int m, const float *L, const float *U, MDREC *m
     md->dy = U[1] - L[1];
     md->dn = sqrtf((md->dx * md->dx) + (md->dy * md->dy));
     md->barrel = M->barrel;
+    md->is2s = o->mtype[m] == 1;
     md->module = m;
     return pass;
 }
@@ -560,6 +563,7 @@ int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float 
                 T5REC *q = (T5REC *)gv_push(&o->t5);
                 memcpy(q->md, mds, sizeof(mds));
                 q->score = (float)af.score;
+                t5_features_f(&o->K, P, T3[t].k, T3[t2].k, &af, q->feat);
             }
             double mg = cut_margin(&cf, &cd);
             if (mg < NEAR_REL) push_near(o, 3, mds, 5, mg, pass);
@@ -667,6 +671,12 @@ void orc_t5_scores(const orc *o, float *out)
 }
 
 void orc_t5_keep(const orc *o, uint8_t *out) { memcpy(out, o->keep, (size_t)o->t5.n); }
+
+void orc_t5_features(const orc *o, float *out)
+{
+    const T5REC *T5 = (const T5REC *)o->t5.v;
+    for (int64_t i = 0; i < o->t5.n; ++i) memcpy(&out[40 * i], T5[i].feat, sizeof(T5[i].feat));
+}
 
 void orc_t3_curv(const orc *o, float *out)
 {

@@ -65,6 +65,8 @@ void orc_cands(const orc *o, int64_t *out4);
 void orc_t5_scores(const orc *o, float *out);
 void orc_t5_keep(const orc *o, uint8_t *out);
 void orc_t3_curv(const orc *o, float *out);
+/* 40 FP32 features of every quintuplet, in the order of orc_tuples(ORC_T5) */
+void orc_t5_features(const orc *o, float *out40);
 
 /* candidates whose FP64 margin is below 1e-5 (relative): tuple, margin and
  * the FP32 decision; kind 0..3 */

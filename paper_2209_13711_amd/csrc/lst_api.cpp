@@ -52,6 +52,9 @@ struct lst_ctx {
     bool stage_pending = false;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
+    Tuning tune{};
+    int n_cu = 0;
+    bool features_valid = false;
     std::vector<lst_counts> counts;
     bool counts_valid = false;
     int stage = 0;  // 0 nothing, 1 hits loaded, 2 sorted, 3 md, 4 seg, 5 t3, 6 t5, 7 dedup
@@ -135,6 +138,7 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.cap_slots = (int32_t)slots;
     E.cap_keys = (int32_t)keys;
     E.desc = cv.take<int32_t>(D_COUNT);
+    E.bar = cv.take<uint32_t>(64);
     E.cap_hits = k.hits;
     const int64_t caps[OT_COUNT] = {k.md, k.seg, k.t3, k.t5};
     size_t span[OT_COUNT];
@@ -205,6 +209,9 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.t5_md4 = cv.take<int32_t>(nt5);
     E.t5_score = cv.take<float>(nt5);
     E.t5_keep = cv.take<uint8_t>(nt5);
+    E.t5_veto = cv.take<uint8_t>(nt5);
+    E.t5_feat = k.features ? cv.take<float>(nt5 * 40) : nullptr;
+    E.t5_logit = k.features ? cv.take<float>(nt5) : nullptr;
     return (cv.off + 255) & ~(size_t)255;
 }
 }  // namespace
@@ -283,7 +290,7 @@ int lst_load_geometry(lst_ctx *c, int32_t n, const float *f32, const int32_t *i3
 
     // device geometry: 11 float rows, barrel flags, map
     std::vector<float> rows((size_t)11 * n);
-    std::vector<int32_t> barrel(n);
+    std::vector<int32_t> barrel(2 * (size_t)n);   // barrel flags, then 2S flags
     const int src[10] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 14};  // cx..vz, gap
     for (int r = 0; r < 10; ++r)
         std::memcpy(&rows[(size_t)r * n], &f32[(size_t)src[r] * n], sizeof(float) * n);
@@ -292,9 +299,10 @@ int lst_load_geometry(lst_ctx *c, int32_t n, const float *f32, const int32_t *i3
         const float g = f32[14 * n + m];
         rows[(size_t)10 * n + m] = ((cx * wx) + (cy * wy)) - (0.5f * g);  // lower-sensor apothem
         barrel[m] = i32[n + m] == 0 ? 1 : 0;
+        barrel[(size_t)n + m] = i32[3 * n + m] == 1 ? 1 : 0;
     }
     const size_t nf = rows.size() * sizeof(float);
-    const size_t nb = sizeof(int32_t) * n;
+    const size_t nb = sizeof(int32_t) * 2 * n;
     const size_t np = sizeof(int32_t) * (n + 1);
     const size_t nc = sizeof(int32_t) * std::max<size_t>(c->map_col.size(), 1);
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -321,6 +329,7 @@ int lst_load_geometry(lst_ctx *c, int32_t n, const float *f32, const int32_t *i3
     M.cx = r[0]; M.cy = r[1]; M.cz = r[2]; M.ux = r[3]; M.uy = r[4]; M.uz = r[5];
     M.vx = r[6]; M.vy = r[7]; M.vz = r[8]; M.g = r[9]; M.rl = r[10];
     M.barrel = dbar;
+    M.is2s = dbar + n;
     M.map_ptr = dptr;
     M.map_col = dcol;
     M.n_mod = n;
@@ -358,6 +367,22 @@ int lst_get_map(lst_ctx *c, int32_t *row_ptr, int32_t *col, int64_t cap_col, int
 }
 
 // ---------------------------------------------------------------- arena
+
+static int clamp_grid(int64_t g) { return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65535)); }
+
+// Launch shapes before tuning: one wave per work item up to 2048 blocks.
+static void default_tuning(lst_ctx *c)
+{
+    Tuning &t = c->tune;
+    t.grid[ST_SORT] = clamp_grid(std::min<int64_t>((c->caps.hits + BLOCK - 1) / BLOCK, GRID_MAX));
+    t.grid[ST_MD] = clamp_grid(std::min<int64_t>(((int64_t)c->E.cap_slots + WAVES - 1) / WAVES, GRID_MAX));
+    t.grid[ST_SEG] = GRID_MAX;
+    t.grid[ST_T3] = GRID_MAX;
+    t.grid[ST_T5] = GRID_MAX;
+    t.grid[ST_DEDUP] = 512;
+    t.persistent = 0;
+    t.blocks_per_cu = std::max(1, persistent_blocks_per_cu());
+}
 
 int lst_arena_bytes(const lst_ctx *cc, const lst_caps *caps, size_t *bytes)
 {
@@ -399,6 +424,8 @@ int lst_attach_arena(lst_ctx *c, void *dev_ptr, size_t bytes, const lst_caps *ca
     c->arena_bytes = bytes;
     c->caps = *caps;
     carve(c, c->arena, *caps, c->E, &c->zero_base, &c->zero_bytes);
+    if (!c->n_cu) HIPCHK(c, hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+    default_tuning(c);
     c->stage = 0;
     c->n_events = 0;
     return LST_OK;
@@ -458,6 +485,7 @@ static int need_stage(lst_ctx *c, int s, const char *what)
     if (!c) return LST_E_INVALID;
     if (c->stage < s) return fail(c, LST_E_STATE, "%s called out of order", what);
     c->counts_valid = false;
+    if (s <= 6) c->features_valid = false;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, LST_E_HIP, "hipSetDevice");
     return LST_OK;
 }
@@ -468,7 +496,7 @@ int lst_run_sort(lst_ctx *c, void *stream)
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, s));
-    HIPCHK(c, launch_sort(c->E, c->M, s));
+    HIPCHK(c, launch_sort(c->E, c->M, c->tune.grid[ST_SORT], s));
     c->stage = 2;
     return LST_OK;
 }
@@ -477,7 +505,7 @@ int lst_run_md(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 2, "lst_run_md");
     if (rc) return rc;
-    HIPCHK(c, launch_md(c->E, c->M, c->K, (hipStream_t)stream));
+    HIPCHK(c, launch_md(c->E, c->M, c->K, c->tune.grid[ST_MD], (hipStream_t)stream));
     c->stage = 3;
     return LST_OK;
 }
@@ -486,7 +514,7 @@ int lst_run_segments(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 3, "lst_run_segments");
     if (rc) return rc;
-    HIPCHK(c, launch_seg(c->E, c->M, c->K, (hipStream_t)stream));
+    HIPCHK(c, launch_seg(c->E, c->M, c->K, c->tune.grid[ST_SEG], (hipStream_t)stream));
     c->stage = 4;
     return LST_OK;
 }
@@ -495,7 +523,7 @@ int lst_run_triplets(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 4, "lst_run_triplets");
     if (rc) return rc;
-    HIPCHK(c, launch_t3(c->E, c->M, c->K, (hipStream_t)stream));
+    HIPCHK(c, launch_t3(c->E, c->M, c->K, c->tune.grid[ST_T3], (hipStream_t)stream));
     c->stage = 5;
     return LST_OK;
 }
@@ -504,7 +532,7 @@ int lst_run_quintuplets(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 5, "lst_run_quintuplets");
     if (rc) return rc;
-    HIPCHK(c, launch_t5(c->E, c->M, c->K, (hipStream_t)stream));
+    HIPCHK(c, launch_t5(c->E, c->M, c->K, c->tune.grid[ST_T5], (hipStream_t)stream));
     c->stage = 6;
     return LST_OK;
 }
@@ -513,14 +541,17 @@ int lst_run_dedup(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 6, "lst_run_dedup");
     if (rc) return rc;
-    HIPCHK(c, launch_dedup(c->E, c->M, (hipStream_t)stream));
+    HIPCHK(c, launch_dedup(c->E, c->M, c->tune.grid[ST_DEDUP], (hipStream_t)stream));
     c->stage = 7;
     return LST_OK;
 }
 
+int lst_run_chain_persistent(lst_ctx *c, void *stream);
+
 int lst_run_chain(lst_ctx *c, void *stream)
 {
     int rc;
+    if (c && c->tune.persistent) return lst_run_chain_persistent(c, stream);
     if ((rc = lst_run_sort(c, stream))) return rc;
     if ((rc = lst_run_md(c, stream))) return rc;
     if ((rc = lst_run_segments(c, stream))) return rc;
@@ -534,13 +565,66 @@ int lst_run_chain(lst_ctx *c, void *stream)
 // and replayed for every batch.  Only kernel nodes: no memset nodes.
 static int enqueue_chain(lst_ctx *c, hipStream_t s)
 {
+    const Tuning &t = c->tune;
+    if (t.persistent) {
+        HIPCHK(c, launch_chain_persistent(c->E, c->M, c->K, c->zero_base, c->zero_bytes,
+                                          t.blocks_per_cu * c->n_cu, s));
+        return LST_OK;
+    }
     HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, s));
-    HIPCHK(c, launch_sort(c->E, c->M, s));
-    HIPCHK(c, launch_md(c->E, c->M, c->K, s));
-    HIPCHK(c, launch_seg(c->E, c->M, c->K, s));
-    HIPCHK(c, launch_t3(c->E, c->M, c->K, s));
-    HIPCHK(c, launch_t5(c->E, c->M, c->K, s));
-    HIPCHK(c, launch_dedup(c->E, c->M, s));
+    HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], s));
+    HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], s));
+    HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], s));
+    HIPCHK(c, launch_t3(c->E, c->M, c->K, t.grid[ST_T3], s));
+    HIPCHK(c, launch_t5(c->E, c->M, c->K, t.grid[ST_T5], s));
+    HIPCHK(c, launch_dedup(c->E, c->M, t.grid[ST_DEDUP], s));
+    return LST_OK;
+}
+
+int lst_run_chain_persistent(lst_ctx *c, void *stream)
+{
+    int rc = need_stage(c, 1, "lst_run_chain_persistent");
+    if (rc) return rc;
+    const int bpc = std::max(1, std::min(c->tune.blocks_per_cu, persistent_blocks_per_cu()));
+    HIPCHK(c, launch_chain_persistent(c->E, c->M, c->K, c->zero_base, c->zero_bytes,
+                                      bpc * c->n_cu, (hipStream_t)stream));
+    c->stage = 7;
+    return LST_OK;
+}
+
+int lst_run_t5_features(lst_ctx *c, void *stream)
+{
+    int rc = need_stage(c, 6, "lst_run_t5_features");
+    if (rc) return rc;
+    if (!c->E.t5_feat) return fail(c, LST_E_STATE, "arena attached without features");
+    HIPCHK(c, launch_t5_features(c->E, c->K, c->tune.grid[ST_DEDUP], (hipStream_t)stream));
+    c->features_valid = true;
+    return LST_OK;
+}
+
+int lst_set_tuning(lst_ctx *c, const int32_t *grid6, int32_t persistent, int32_t blocks_per_cu)
+{
+    if (!c || !grid6) return LST_E_INVALID;
+    if (!c->arena) return fail(c, LST_E_STATE, "no arena attached");
+    const int occ = persistent_blocks_per_cu();
+    if (blocks_per_cu < 1 || blocks_per_cu > occ)
+        return fail(c, LST_E_INVALID, "blocks_per_cu %d outside 1..%d (co-residency)", blocks_per_cu, occ);
+    for (int i = 0; i < ST_COUNT; ++i)
+        if (grid6[i] < 1 || grid6[i] > 65535) return fail(c, LST_E_INVALID, "grid[%d] = %d", i, grid6[i]);
+    for (int i = 0; i < ST_COUNT; ++i) c->tune.grid[i] = grid6[i];
+    c->tune.persistent = persistent ? 1 : 0;
+    c->tune.blocks_per_cu = blocks_per_cu;
+    drop_graph(c);
+    return LST_OK;
+}
+
+int lst_get_tuning(const lst_ctx *c, int32_t *out9)
+{
+    if (!c || !out9) return LST_E_INVALID;
+    for (int i = 0; i < ST_COUNT; ++i) out9[i] = c->tune.grid[i];
+    out9[6] = c->tune.persistent;
+    out9[7] = c->tune.blocks_per_cu;
+    out9[8] = c->n_cu;
     return LST_OK;
 }
 
@@ -786,6 +870,38 @@ int lst_get_objects(lst_ctx *c, int32_t event, int32_t kind, int32_t *out, int64
     return LST_OK;
 }
 
+int lst_get_t5_features(lst_ctx *c, int32_t event, float *out, int64_t cap, int64_t *n_out,
+                        void *stream)
+{
+    if (!c) return LST_E_INVALID;
+    if (event < 0 || event >= c->n_events) return fail(c, LST_E_INVALID, "event %d", event);
+    if (!c->features_valid) return fail(c, LST_E_STATE, "features have not been computed");
+    int rc = sync_stream(c, stream);
+    if (rc) return rc;
+    const EvDev &E = c->E;
+    ShardCounts S;
+    if ((rc = read_shards(c, S))) return rc;
+    if (S.gc[GC_OVERFLOW])
+        return fail(c, LST_E_CAPACITY, "capacity overflow (mask %u)", S.gc[GC_OVERFLOW]);
+    std::vector<int32_t> m0, slot;
+    std::vector<float> ft;
+    if ((rc = d2h(c, m0, E.t5_md0, S.span(OT_T5))) || (rc = d2h(c, ft, E.t5_feat, S.span(OT_T5) * 40)) ||
+        (rc = d2h(c, slot, E.md_slot, S.span(OT_MD))))
+        return rc;
+    const int lo_slot = event * c->n_mod, hi_slot = (event + 1) * c->n_mod;
+    int64_t k = 0;
+    for (int sh = 0; sh < NSH; ++sh)
+        for (uint32_t q = 0; q < S.n(OT_T5, sh); ++q) {
+            const size_t i = (size_t)sh * S.rc[OT_T5] + q;
+            if (slot[m0[i]] < lo_slot || slot[m0[i]] >= hi_slot) continue;
+            if (out && k < cap) std::memcpy(&out[40 * k], &ft[40 * i], 40 * sizeof(float));
+            ++k;
+        }
+    if (n_out) *n_out = k;
+    if (k > cap) return fail(c, LST_E_CAPACITY, "%lld feature rows, capacity %lld", (long long)k, (long long)cap);
+    return LST_OK;
+}
+
 int lst_get_t5_scores(lst_ctx *c, int32_t event, float *out, int64_t cap, int64_t *n_out,
                       void *stream)
 {
@@ -820,3 +936,223 @@ int lst_get_t5_scores(lst_ctx *c, int32_t event, float *out, int64_t cap, int64_
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- autotuner
+// Order-independent checksum of everything the chain produced (all events):
+// object counts per type and a sum of 64-bit mixes of every quintuplet's
+// (event, hit tuple), separately for the kept ones.
+static uint64_t mix64(uint64_t x)
+{
+    x ^= x >> 33; x *= 0xff51afd7ed558ccdull; x ^= x >> 33; x *= 0xc4ceb9fe1a85ec53ull; x ^= x >> 33;
+    return x;
+}
+
+static int chain_checksum(lst_ctx *c, uint64_t *out)
+{
+    const EvDev &E = c->E;
+    ShardCounts S;
+    int rc = read_shards(c, S);
+    if (rc) return rc;
+    if (S.gc[GC_OVERFLOW] || S.gc[GC_ERROR] & 2)
+        return fail(c, LST_E_CAPACITY, "tuning run overflowed or timed out (%u, %u)", S.gc[GC_OVERFLOW], S.gc[GC_ERROR]);
+    std::vector<int32_t> sorig, hlo, hup, slot, m[5];
+    std::vector<uint8_t> keep;
+    if ((rc = d2h(c, sorig, E.sorig, S.gc[GC_N_SORTED])) || (rc = d2h(c, hlo, E.md_hlo, S.span(OT_MD))) ||
+        (rc = d2h(c, hup, E.md_hup, S.span(OT_MD))) || (rc = d2h(c, slot, E.md_slot, S.span(OT_MD))) ||
+        (rc = d2h(c, keep, E.t5_keep, S.span(OT_T5))))
+        return rc;
+    int32_t *const dm[5] = {E.t5_md0, E.t5_md1, E.t5_md2, E.t5_md3, E.t5_md4};
+    for (int j = 0; j < 5; ++j)
+        if ((rc = d2h(c, m[j], (const int32_t *)dm[j], S.span(OT_T5)))) return rc;
+    uint64_t h_all = 0, h_keep = 0;
+    for (int sh = 0; sh < NSH; ++sh)
+        for (uint32_t q = 0; q < S.n(OT_T5, sh); ++q) {
+            const size_t t = (size_t)sh * S.rc[OT_T5] + q;
+            uint64_t h = mix64((uint64_t)(slot[m[0][t]] / c->n_mod) + 0x9e3779b97f4a7c15ull);
+            for (int j = 0; j < 5; ++j) {
+                h = mix64(h ^ (uint64_t)(uint32_t)sorig[hlo[m[j][t]]]);
+                h = mix64(h ^ (uint64_t)(uint32_t)sorig[hup[m[j][t]]]);
+            }
+            h_all += h;
+            if (keep[t]) h_keep += h;
+        }
+    uint64_t h = 0;
+    for (int t = 0; t < OT_COUNT; ++t) h = mix64(h ^ (uint64_t)S.stored(t));
+    *out = mix64(h ^ h_all) ^ h_keep;
+    return LST_OK;
+}
+
+// one eager chain with an event before and after every stage; per-stage us
+static int timed_chain(lst_ctx *c, hipStream_t s, hipEvent_t *ev, double *stage_us)
+{
+    HIPCHK(c, hipEventRecord(ev[0], s));
+    if (c->tune.persistent) {
+        HIPCHK(c, launch_chain_persistent(c->E, c->M, c->K, c->zero_base, c->zero_bytes,
+                                          c->tune.blocks_per_cu * c->n_cu, s));
+        HIPCHK(c, hipEventRecord(ev[ST_COUNT], s));
+    } else {
+        const Tuning &t = c->tune;
+        HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, s));
+        HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], s));
+        HIPCHK(c, hipEventRecord(ev[1], s));
+        HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], s));
+        HIPCHK(c, hipEventRecord(ev[2], s));
+        HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], s));
+        HIPCHK(c, hipEventRecord(ev[3], s));
+        HIPCHK(c, launch_t3(c->E, c->M, c->K, t.grid[ST_T3], s));
+        HIPCHK(c, hipEventRecord(ev[4], s));
+        HIPCHK(c, launch_t5(c->E, c->M, c->K, t.grid[ST_T5], s));
+        HIPCHK(c, hipEventRecord(ev[5], s));
+        HIPCHK(c, launch_dedup(c->E, c->M, t.grid[ST_DEDUP], s));
+        HIPCHK(c, hipEventRecord(ev[ST_COUNT], s));
+    }
+    HIPCHK(c, hipEventSynchronize(ev[ST_COUNT]));
+    for (int i = 0; i < ST_COUNT; ++i) stage_us[i] = 0.0;
+    float ms = 0.0f;
+    if (c->tune.persistent) {
+        HIPCHK(c, hipEventElapsedTime(&ms, ev[0], ev[ST_COUNT]));
+        stage_us[0] = 1e3 * ms;
+    } else {
+        for (int i = 0; i < ST_COUNT; ++i) {
+            HIPCHK(c, hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            stage_us[i] = 1e3 * ms;
+        }
+    }
+    return LST_OK;
+}
+
+static double median(std::vector<double> v)
+{
+    std::sort(v.begin(), v.end());
+    return v.empty() ? 0.0 : v[v.size() / 2];
+}
+
+// median over `reps` chains of one stage's time (stage < 0: whole chain);
+// the outputs of the last run must carry checksum `want`
+static int measure(lst_ctx *c, hipStream_t s, hipEvent_t *ev, int reps, int stage,
+                   uint64_t want, double *us, bool *valid)
+{
+    std::vector<double> v;
+    double st[ST_COUNT];
+    int rc;
+    for (int r = 0; r <= reps; ++r) {
+        if ((rc = timed_chain(c, s, ev, st))) return rc;
+        double tot = 0.0;
+        for (int i = 0; i < ST_COUNT; ++i) tot += st[i];
+        if (r > 0) v.push_back(stage < 0 ? tot : st[stage]);
+    }
+    uint64_t h = 0;
+    rc = chain_checksum(c, &h);
+    *valid = rc == LST_OK && h == want;
+    *us = median(v);
+    return LST_OK;
+}
+
+static std::string tuning_key(const lst_ctx *c)
+{
+    char buf[160];
+    snprintf(buf, sizeof(buf), "nmod=%d events=%d hits=%d cap_hits=%lld cu=%d", c->n_mod, c->n_events,
+             c->hit_off.empty() ? 0 : c->hit_off.back(), (long long)c->caps.hits, c->n_cu);
+    return buf;
+}
+
+extern "C" int lst_tune(lst_ctx *c, const char *cache_path, int32_t reps, double *report, void *stream)
+{
+    int rc = need_stage(c, 1, "lst_tune");
+    if (rc) return rc;
+    if (reps < 1) reps = 5;
+    hipStream_t s = (hipStream_t)stream;
+    const std::string key = tuning_key(c);
+    // cached choice for this batch shape
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "r");
+        if (f) {
+            char line[1024];
+            while (fgets(line, sizeof(line), f)) {
+                const std::string ln(line);
+                if (ln.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
+                const size_t p = ln.find("\"tuning\": [");
+                int32_t g[9];
+                if (p != std::string::npos &&
+                    sscanf(ln.c_str() + p + 11, "%d, %d, %d, %d, %d, %d, %d, %d", &g[0], &g[1], &g[2], &g[3],
+                           &g[4], &g[5], &g[6], &g[7]) == 8 &&
+                    lst_set_tuning(c, g, g[6], g[7]) == LST_OK) {
+                    fclose(f);
+                    if (report) report[0] = -1.0;  // taken from the cache
+                    return LST_OK;
+                }
+            }
+            fclose(f);
+        }
+    }
+    hipEvent_t ev[ST_COUNT + 1];
+    for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
+    default_tuning(c);
+    drop_graph(c);
+    double st[ST_COUNT];
+    uint64_t ref = 0;
+    bool valid = false;
+    double best_stage[ST_COUNT];
+    if ((rc = timed_chain(c, s, ev, st)) || (rc = chain_checksum(c, &ref))) goto done;
+    {
+        static const int cand[ST_COUNT][6] = {
+            {256, 512, 1024, 2048, 0, 0},        // sort
+            {512, 1024, 2048, 4096, 0, 0},       // md
+            {512, 1024, 2048, 4096, 8192, 0},    // seg
+            {512, 1024, 2048, 4096, 8192, 0},    // t3
+            {512, 1024, 2048, 4096, 8192, 0},    // t5
+            {128, 256, 512, 1024, 2048, 0},      // dedup
+        };
+        for (int stg = 0; stg < ST_COUNT; ++stg) {
+            int best_g = c->tune.grid[stg];
+            double best = 1e30;
+            for (int k = 0; k < 6 && cand[stg][k]; ++k) {
+                c->tune.grid[stg] = cand[stg][k];
+                double us;
+                if ((rc = measure(c, s, ev, reps, stg, ref, &us, &valid))) goto done;
+                if (!valid) {
+                    rc = fail(c, LST_E_HIP, "stage %d with grid %d changed the results", stg, cand[stg][k]);
+                    goto done;
+                }
+                if (us < best) { best = us; best_g = cand[stg][k]; }
+            }
+            c->tune.grid[stg] = best_g;
+            best_stage[stg] = best;
+        }
+        double graph_us = 0.0, pers_us = 1e30;
+        if ((rc = measure(c, s, ev, reps, -1, ref, &graph_us, &valid))) goto done;
+        const int occ = std::max(1, persistent_blocks_per_cu());
+        int best_bpc = 1;
+        c->tune.persistent = 1;
+        for (int bpc = 1; bpc <= occ; ++bpc) {
+            c->tune.blocks_per_cu = bpc;
+            double us;
+            if ((rc = measure(c, s, ev, reps, -1, ref, &us, &valid))) goto done;
+            if (valid && us < pers_us) { pers_us = us; best_bpc = bpc; }
+        }
+        c->tune.blocks_per_cu = best_bpc;
+        c->tune.persistent = pers_us < graph_us ? 1 : 0;
+        if (report) {
+            for (int i = 0; i < ST_COUNT; ++i) report[i] = best_stage[i];
+            report[ST_COUNT] = graph_us;
+            report[ST_COUNT + 1] = pers_us;
+        }
+        if (cache_path) {
+            FILE *f = fopen(cache_path, "a");
+            if (f) {
+                fprintf(f, "{\"key\": \"%s\", \"tuning\": [%d, %d, %d, %d, %d, %d, %d, %d], "
+                           "\"chain_us\": %.2f, \"persistent_us\": %.2f}\n",
+                        key.c_str(), c->tune.grid[0], c->tune.grid[1], c->tune.grid[2], c->tune.grid[3],
+                        c->tune.grid[4], c->tune.grid[5], c->tune.persistent, c->tune.blocks_per_cu,
+                        graph_us, pers_us);
+                fclose(f);
+            }
+        }
+    }
+done:
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    drop_graph(c);
+    c->counts_valid = false;
+    c->stage = 7;
+    return rc;
+}

@@ -40,7 +40,7 @@ __device__ __forceinline__ float arc(float c, float k)
 
 struct ModF {
     float cx, cy, cz, ux, uy, uz, vx, vy, vz, g, rl;
-    int barrel;
+    int barrel, is2s;
 };
 
 struct MdOut {
@@ -103,14 +103,32 @@ struct MdV {
     int barrel;
 };
 
+// the extra MD fields the learned scorer reads
+struct MdX {
+    float bend;
+    int is2s;
+};
+
 __device__ __forceinline__ MdV load_md(const EvDev &E, int32_t i)
 {
     MdV v;
     v.x = E.md_x[i]; v.y = E.md_y[i]; v.z = E.md_z[i]; v.r = E.md_r[i];
     v.a = E.md_a[i]; v.ca = E.md_ca[i]; v.dx = E.md_dx[i]; v.dy = E.md_dy[i];
     v.dn = E.md_dn[i]; v.sv = E.md_sv[i];
-    v.barrel = E.md_bar[i];
+    v.barrel = E.md_bar[i] & 1;
     return v;
+}
+
+__device__ __forceinline__ float tri_curv(const MdV &A, const MdV &B, const MdV &C)
+{
+    float xab = B.x - A.x, yab = B.y - A.y;
+    float xbc = C.x - B.x, ybc = C.y - B.y;
+    float xac = C.x - A.x, yac = C.y - A.y;
+    float lab = sqrtf((xab * xab) + (yab * yab));
+    float lbc = sqrtf((xbc * xbc) + (ybc * ybc));
+    float lac = sqrtf((xac * xac) + (yac * yac));
+    float crs = (xab * yac) - (yab * xac);
+    return (2.0f * crs) / ((lab * lbc) * lac);
 }
 
 // Segment I -> O: azimuthal window (S2), pointing along the prompt circle
@@ -286,6 +304,97 @@ __device__ __forceinline__ bool t5_accept(const Consts &K, const MdV &A, const M
     if (!(chi2z <= K.w2 * K.xrz)) return false;
     score = chi2p + chi2z;
     return true;
+}
+
+// Every quintuplet quantity of t5_accept, without early exits, and the 40
+// features of the learned scorer (same operation order as t5_accept for the
+// shared quantities): per MD r/100, z/100, bend pull, endcap flag, 2S flag;
+// curvatures over kappa_max; chi2/(1+chi2) for r-phi and r-z; r-phi pulls of
+// the 2nd and 4th anchors; r-z pulls of the 2nd..4th; curvature agreement
+// over its tolerance (inner, outer); r-z slope; lever arm/100; transverse
+// impact parameter estimate.
+__device__ __forceinline__ void t5_features(const Consts &K, const MdV *P, const MdX *X, float kin,
+                                            float kout, float *f)
+{
+    const MdV &A = P[0], &B = P[1], &C = P[2], &D = P[3], &Ee = P[4];
+    float xac = C.x - A.x, yac = C.y - A.y;
+    float xce = Ee.x - C.x, yce = Ee.y - C.y;
+    float xae = Ee.x - A.x, yae = Ee.y - A.y;
+    float lac = sqrtf((xac * xac) + (yac * yac));
+    float lce = sqrtf((xce * xce) + (yce * yce));
+    float lae = sqrtf((xae * xae) + (yae * yae));
+    float crs = (xac * yae) - (yac * xae);
+    float den = (lac * lce) * lae;
+    float kbr = (2.0f * crs) / den;
+    float hk = 0.5f * kbr;
+    float v0 = perp_var(K, A, hk), v1 = perp_var(K, B, hk), v2 = perp_var(K, C, hk);
+    float v3 = perp_var(K, D, hk), v4 = perp_var(K, Ee, hk);
+    float ein = mx(mx(v0, v1), v2);
+    float eout = mx(mx(v2, v3), v4);
+    float tin = ((K.tolkc * sqrtf(ein)) / (lac * lac)) + K.epsak;
+    float tout = ((K.tolkc * sqrtf(eout)) / (lce * lce)) + K.epsak;
+    float resb = circ_res(A.x, A.y, C.x, C.y, Ee.x, Ee.y, B.x, B.y, crs, den);
+    float resd = circ_res(A.x, A.y, C.x, C.y, Ee.x, Ee.y, D.x, D.y, crs, den);
+    float xab = B.x - A.x, yab = B.y - A.y;
+    float xbc = C.x - B.x, ybc = C.y - B.y;
+    float xcd = D.x - C.x, ycd = D.y - C.y;
+    float xde = Ee.x - D.x, yde = Ee.y - D.y;
+    float s1 = arc(sqrtf((xab * xab) + (yab * yab)), kbr);
+    float s2 = arc(sqrtf((xbc * xbc) + (ybc * ybc)), kbr);
+    float s3 = arc(sqrtf((xcd * xcd) + (ycd * ycd)), kbr);
+    float s4 = arc(sqrtf((xde * xde) + (yde * yde)), kbr);
+    float S1 = s1, S2 = S1 + s2, S3 = S2 + s3, S4 = S3 + s4;
+    float Lab = ((S1 - S2) * (S1 - S4)) / (S2 * S4);
+    float Lcb = (S1 * (S1 - S4)) / (S2 * (S2 - S4));
+    float Leb = (S1 * (S1 - S2)) / (S4 * (S4 - S2));
+    float Lad = ((S3 - S2) * (S3 - S4)) / (S2 * S4);
+    float Lcd = (S3 * (S3 - S4)) / (S2 * (S2 - S4));
+    float Led = (S3 * (S3 - S2)) / (S4 * (S4 - S2));
+    float Vb = (v1 + (((Lab * Lab) * v0) + ((Lcb * Lcb) * v2))) + ((Leb * Leb) * v4);
+    float Vd = (v3 + (((Lad * Lad) * v0) + ((Lcd * Lcd) * v2))) + ((Led * Led) * v4);
+    float chi2p = ((resb * resb) / Vb) + ((resd * resd) / Vd);
+    float sl = (Ee.z - A.z) / S4;
+    float se = mx(fabsf(sl), 0.05f) * K.sigv;
+    float sza = A.barrel ? K.sigv : se;
+    float sze = Ee.barrel ? K.sigv : se;
+    float Sj[3] = {S1, S2, S3};
+    float zj[3] = {B.z, C.z, D.z};
+    float szj[3] = {B.barrel ? K.sigv : se, C.barrel ? K.sigv : se, D.barrel ? K.sigv : se};
+    float t[3], pull[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        float fr = Sj[j] / S4;
+        float dz = zj[j] - (A.z + (sl * Sj[j]));
+        float g1 = (1.0f - fr) * sza, g2 = fr * sze;
+        float V = ((szj[j] * szj[j]) + (g1 * g1)) + (g2 * g2);
+        t[j] = (dz * dz) / V;
+        pull[j] = dz / sqrtf(V);
+    }
+    float chi2z = (t[0] + t[1]) + t[2];
+    float kO = (2.0f * ((A.x * Ee.y) - (A.y * Ee.x))) / ((A.r * Ee.r) * lae);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        f[5 * j + 0] = P[j].r * 0.01f;
+        f[5 * j + 1] = P[j].z * 0.01f;
+        f[5 * j + 2] = X[j].bend;
+        f[5 * j + 3] = P[j].barrel ? 0.0f : 1.0f;
+        f[5 * j + 4] = X[j].is2s ? 1.0f : 0.0f;
+    }
+    f[25] = kin / K.kmax;
+    f[26] = kout / K.kmax;
+    f[27] = kbr / K.kmax;
+    f[28] = chi2p / (1.0f + chi2p);
+    f[29] = chi2z / (1.0f + chi2z);
+    f[30] = resb / sqrtf(Vb);
+    f[31] = resd / sqrtf(Vd);
+    f[32] = pull[0];
+    f[33] = pull[1];
+    f[34] = pull[2];
+    f[35] = (kin - kbr) / tin;
+    f[36] = (kout - kbr) / tout;
+    f[37] = sl;
+    f[38] = lae * 0.01f;
+    f[39] = ((kbr - kO) * (A.r * Ee.r)) * 0.5f;
 }
 
 }  // namespace lst

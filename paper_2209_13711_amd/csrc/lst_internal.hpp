@@ -37,6 +37,7 @@ enum GlobalCounter {
 struct ModDev {
     const float *cx, *cy, *cz, *ux, *uy, *uz, *vx, *vy, *vz, *g, *rl;
     const int32_t *barrel;   // 1 barrel, 0 endcap
+    const int32_t *is2s;     // 1 for 2S modules
     const int32_t *map_ptr;  // [n_mod + 1]
     const int32_t *map_col;  // [n_edges]
     int32_t n_mod;
@@ -68,7 +69,7 @@ struct EvDev {
     // mini-doublets
     int32_t *md_hlo, *md_hup, *md_slot;
     float *md_x, *md_y, *md_z, *md_r, *md_a, *md_ca, *md_dx, *md_dy, *md_dn, *md_bend, *md_sv;
-    uint8_t *md_bar;                 // 1 when the MD's module is in the barrel
+    uint8_t *md_bar;                 // bit 0: barrel module, bit 1: 2S module
     int32_t *md_start, *md_cnt;      // [n_slots]
     // segments (grouped by inner MD)
     int32_t *seg_in, *seg_out;
@@ -81,8 +82,12 @@ struct EvDev {
     int32_t *t5_md0, *t5_md1, *t5_md2, *t5_md3, *t5_md4;
     float *t5_score;
     uint8_t *t5_keep;
+    uint8_t *t5_veto;                // 1: rejected by the learned scorer
+    float *t5_feat;                  // [span][40] features (learned scorer)
+    float *t5_logit;                 // [span] scorer output
     // counters (zeroed at chain start)
     uint32_t *gc;                    // [GC_COUNT]
+    uint32_t *bar;                   // persistent-chain barrier counters [33]
 };
 
 constexpr int TIE_SLOTS = 8;
@@ -94,11 +99,23 @@ constexpr int GRID_MAX = 2048;       // blocks of a grid-stride stage kernel
 // launchers (lst_kernels.hip)
 hipError_t launch_copy(void *dst, const void *src, size_t n_bytes, hipStream_t s);
 hipError_t launch_zero(const EvDev &E, void *zero_base, size_t zero_bytes, hipStream_t s);
-hipError_t launch_sort(const EvDev &E, const ModDev &M, hipStream_t s);
-hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s);
-hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s);
-hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s);
-hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s);
-hipError_t launch_dedup(const EvDev &E, const ModDev &M, hipStream_t s);
+hipError_t launch_sort(const EvDev &E, const ModDev &M, int grid, hipStream_t s);
+hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s);
+hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s);
+hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s);
+hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s);
+hipError_t launch_dedup(const EvDev &E, const ModDev &M, int grid, hipStream_t s);
+hipError_t launch_chain_persistent(const EvDev &E, const ModDev &M, const Consts &K,
+                                   void *zero_base, size_t zero_bytes, int grid, hipStream_t s);
+int persistent_blocks_per_cu();
+hipError_t launch_t5_features(const EvDev &E, const Consts &K, int grid, hipStream_t s);
+
+// Launch shape of every stage (blocks of BLOCK threads); chosen by the tuner.
+enum StageId { ST_SORT = 0, ST_MD, ST_SEG, ST_T3, ST_T5, ST_DEDUP, ST_COUNT };
+struct Tuning {
+    int grid[ST_COUNT];
+    int persistent;        // 1: the whole chain as one persistent kernel
+    int blocks_per_cu;     // persistent grid = blocks_per_cu x CUs
+};
 
 }  // namespace lst

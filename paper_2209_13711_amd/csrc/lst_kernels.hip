@@ -125,20 +125,15 @@ __device__ __forceinline__ bool upstream_overflow(const EvDev &E)
     return E.gc[GC_OVERFLOW] != 0u;
 }
 
-static int grid_for(uint32_t waves_wanted)
-{
-    uint32_t b = (waves_wanted + WAVES - 1) / WAVES;
-    if (b > (uint32_t)GRID_MAX) b = GRID_MAX;
-    return b < 1 ? 1 : (int)b;
-}
-
 // ---------------------------------------------------------------- zero fill
-__global__ void k_zero(uint4 *p, size_t n16)
+__device__ __forceinline__ void zero_body(uint4 *p, size_t n16)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (; i < n16; i += stride) p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
+
+__global__ void k_zero(uint4 *p, size_t n16) { zero_body(p, n16); }
 
 hipError_t launch_zero(const EvDev &, void *zero_base, size_t zero_bytes, hipStream_t s)
 {
@@ -187,7 +182,7 @@ __device__ __forceinline__ int hit_key(const EvDev &E, int n_mod, int n_ev, int3
     return 2 * (ev * n_mod + m) + s;
 }
 
-__global__ void k_hist(EvDev E, int n_mod)
+__device__ __forceinline__ void hist_body(const EvDev &E, int n_mod)
 {
     const int n_ev = E.desc[D_NEV], n_hits = E.desc[D_NHITS];
     for (int32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < n_hits;
@@ -219,55 +214,67 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t &total)
     return before + incl - v;
 }
 
-__global__ void k_scan_reduce(const uint32_t *in, const int32_t *np, uint32_t *bsum)
+__device__ __forceinline__ int scan_tiles(const EvDev &E)
 {
-    const int n = *np;
-    int base = blockIdx.x * SCAN_TILE + threadIdx.x * 4;
-    uint32_t v = 0;
-    for (int k = 0; k < 4; ++k)
-        if (base + k < n) v += in[base + k];
-    uint32_t tot;
-    block_excl_scan(v, tot);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+    return (E.cap_keys + 1 + SCAN_TILE - 1) / SCAN_TILE;
 }
 
-__global__ void k_scan_top(uint32_t *bsum, int nb)
+// per-tile sums (grid-stride over tiles)
+__device__ __forceinline__ void scan_reduce_body(const EvDev &E)
 {
+    const int n = E.desc[D_NKEYS], nb = scan_tiles(E);
+    for (int tile = blockIdx.x; tile < nb; tile += gridDim.x) {
+        const int base = tile * SCAN_TILE + threadIdx.x * 4;
+        uint32_t v = 0;
+        for (int k = 0; k < 4; ++k)
+            if (base + k < n) v += E.bcnt[base + k];
+        uint32_t tot;
+        block_excl_scan(v, tot);
+        if (threadIdx.x == 0) E.bsum[tile] = tot;
+    }
+}
+
+// exclusive scan of the tile sums by block 0
+__device__ __forceinline__ void scan_top_body(const EvDev &E)
+{
+    if (blockIdx.x != 0) return;
+    const int nb = scan_tiles(E);
     uint32_t carry = 0;
     for (int b0 = 0; b0 < nb; b0 += BLOCK) {
-        int i = b0 + threadIdx.x;
-        uint32_t v = i < nb ? bsum[i] : 0u;
+        const int i = b0 + threadIdx.x;
+        const uint32_t v = i < nb ? E.bsum[i] : 0u;
         uint32_t tot;
-        uint32_t ex = block_excl_scan(v, tot);
-        if (i < nb) bsum[i] = carry + ex;
+        const uint32_t ex = block_excl_scan(v, tot);
+        if (i < nb) E.bsum[i] = carry + ex;
         carry += tot;
     }
 }
 
-__global__ void k_scan_down(const uint32_t *in, const int32_t *np, const uint32_t *bsum,
-                            uint32_t *out, uint32_t *gc)
+__device__ __forceinline__ void scan_down_body(const EvDev &E)
 {
-    const int n = *np;
-    int base = blockIdx.x * SCAN_TILE + threadIdx.x * 4;
-    uint32_t v[4], s = 0;
-    for (int k = 0; k < 4; ++k) {
-        v[k] = (base + k < n) ? in[base + k] : 0u;
-        s += v[k];
-    }
-    uint32_t tot;
-    uint32_t ex = block_excl_scan(s, tot) + bsum[blockIdx.x];
-    for (int k = 0; k < 4; ++k) {
-        const int idx = base + k;
-        if (idx < n) out[idx] = ex;
-        if (idx == n) {   // the total, written by the thread covering index n
-            out[n] = ex;
-            gc[GC_N_SORTED] = ex;
+    const int n = E.desc[D_NKEYS], nb = scan_tiles(E);
+    for (int tile = blockIdx.x; tile < nb; tile += gridDim.x) {
+        const int base = tile * SCAN_TILE + threadIdx.x * 4;
+        uint32_t v[4], sum = 0;
+        for (int k = 0; k < 4; ++k) {
+            v[k] = (base + k < n) ? E.bcnt[base + k] : 0u;
+            sum += v[k];
         }
-        ex += v[k];
+        uint32_t tot;
+        uint32_t ex = block_excl_scan(sum, tot) + E.bsum[tile];
+        for (int k = 0; k < 4; ++k) {
+            const int idx = base + k;
+            if (idx < n) E.boff[idx] = ex;
+            if (idx == n) {   // the total, written by the thread covering index n
+                E.boff[n] = ex;
+                E.gc[GC_N_SORTED] = ex;
+            }
+            ex += v[k];
+        }
     }
 }
 
-__global__ void k_scatter(EvDev E, int n_mod)
+__device__ __forceinline__ void scatter_body(const EvDev &E, int n_mod)
 {
     const int n_ev = E.desc[D_NEV], n_hits = E.desc[D_NHITS];
     for (int32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < n_hits;
@@ -286,21 +293,41 @@ __global__ void k_scatter(EvDev E, int n_mod)
     }
 }
 
+__global__ void k_hist(EvDev E, int n_mod) { hist_body(E, n_mod); }
+__global__ void k_scan_reduce(EvDev E) { scan_reduce_body(E); }
+__global__ void k_scan_top(EvDev E) { scan_top_body(E); }
+__global__ void k_scan_down(EvDev E) { scan_down_body(E); }
+__global__ void k_scatter(EvDev E, int n_mod) { scatter_body(E, n_mod); }
+
 // grids depend on the arena capacities only, never on the batch
-hipError_t launch_sort(const EvDev &E, const ModDev &M, hipStream_t s)
+hipError_t launch_sort(const EvDev &E, const ModDev &M, int grid, hipStream_t s)
 {
-    int hb = (int)((E.cap_hits + BLOCK - 1) / BLOCK);
-    hb = hb < 1 ? 1 : (hb > GRID_MAX ? GRID_MAX : hb);
-    const int32_t *nkeys = E.desc + D_NKEYS;
     const int nb = (E.cap_keys + 1 + SCAN_TILE - 1) / SCAN_TILE;
-    hipLaunchKernelGGL(k_hist, dim3(hb), dim3(BLOCK), 0, s, E, M.n_mod);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(BLOCK), 0, s, E.bcnt, nkeys, E.bsum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, s, E.bsum, nb);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(BLOCK), 0, s, E.bcnt, nkeys, E.bsum, E.boff,
-                       E.gc);
-    hipLaunchKernelGGL(k_scatter, dim3(hb), dim3(BLOCK), 0, s, E, M.n_mod);
+    hipLaunchKernelGGL(k_hist, dim3(grid), dim3(BLOCK), 0, s, E, M.n_mod);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(BLOCK), 0, s, E);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, s, E);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(BLOCK), 0, s, E);
+    hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(BLOCK), 0, s, E, M.n_mod);
     return hipGetLastError();
 }
+
+// ---------------------------------------------------------------- LDS layouts
+struct SmMD { uint32_t lo[WAVES][STAGE]; uint32_t up[WAVES][STAGE]; };
+struct SmSeg { int32_t o[WAVES][STAGE]; };
+struct SmT3 { int32_t b[WAVES][STAGE]; int32_t c[WAVES][STAGE]; float k[WAVES][STAGE]; };
+struct SmT5 {
+    int32_t b[WAVES][STAGE], c[WAVES][STAGE], d[WAVES][STAGE], e[WAVES][STAGE];
+    float s[WAVES][STAGE];
+};
+struct SmChain {
+    union {
+        SmMD md;
+        SmSeg seg;
+        SmT3 t3;
+        SmT5 t5;
+    } u;
+    uint32_t pre[NSH + 1];
+};
 
 // ---------------------------------------------------------------- a1: mini-doublets
 __device__ __forceinline__ ModF load_mod(const ModDev &M, int m)
@@ -311,11 +338,12 @@ __device__ __forceinline__ ModF load_mod(const ModDev &M, int m)
     f.vx = M.vx[m]; f.vy = M.vy[m]; f.vz = M.vz[m];
     f.g = M.g[m]; f.rl = M.rl[m];
     f.barrel = M.barrel[m];
+    f.is2s = M.is2s[m];
     return f;
 }
 
 __device__ __forceinline__ void write_md(const EvDev &E, uint32_t i, int slot, uint32_t hl,
-                                         uint32_t hu, const MdOut &o, int barrel)
+                                         uint32_t hu, const MdOut &o, const ModF &mod)
 {
     const float xL = E.sx[hl], yL = E.sy[hl];
     E.md_hlo[i] = (int32_t)hl;
@@ -333,7 +361,7 @@ __device__ __forceinline__ void write_md(const EvDev &E, uint32_t i, int slot, u
     E.md_dn[i] = sqrtf((dx * dx) + (dy * dy));
     E.md_bend[i] = o.bend;
     E.md_sv[i] = o.sv;
-    E.md_bar[i] = (uint8_t)barrel;
+    E.md_bar[i] = (uint8_t)(mod.barrel | (mod.is2s << 1));
 }
 
 // every lower x upper hit pair of one module slot; sink(ok, hl, hu, pos)
@@ -361,10 +389,8 @@ __device__ __forceinline__ uint32_t enum_md(const EvDev &E, const Consts &K, con
     return cnt;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_md(EvDev E, ModDev M, Consts K)
+__device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const Consts &K, SmMD &sm)
 {
-    __shared__ uint32_t s_lo[WAVES][STAGE];
-    __shared__ uint32_t s_up[WAVES][STAGE];
     const int w = wave_id();
     const int n_slots = E.desc[D_NSLOTS];
     for (int base = blockIdx.x * WAVES; base < n_slots; base += gridDim.x * WAVES) {
@@ -382,8 +408,8 @@ __global__ __launch_bounds__(BLOCK) void k_md(EvDev E, ModDev M, Consts K)
         const uint32_t cnt = enum_md(E, K, mod, lo0, up0, nup, np,
                                      [&](bool ok, uint32_t hl, uint32_t hu, uint32_t pos) {
                                          if (ok && pos < STAGE) {
-                                             s_lo[w][pos] = hl;
-                                             s_up[w][pos] = hu;
+                                             sm.lo[w][pos] = hl;
+                                             sm.up[w][pos] = hu;
                                          }
                                      });
         bool ovf;
@@ -396,10 +422,10 @@ __global__ __launch_bounds__(BLOCK) void k_md(EvDev E, ModDev M, Consts K)
         if (ovf || cnt == 0) continue;
         if (cnt <= STAGE) {
             for (uint32_t k = lane_id(); k < cnt; k += 64) {
-                const uint32_t hl = s_lo[w][k], hu = s_up[w][k];
+                const uint32_t hl = sm.lo[w][k], hu = sm.up[w][k];
                 MdOut o;
                 md_accept(K, mod, E.sx[hl], E.sy[hl], E.sz[hl], E.sx[hu], E.sy[hu], E.sz[hu], o);
-                write_md(E, off + k, slot, hl, hu, o, mod.barrel);
+                write_md(E, off + k, slot, hl, hu, o, mod);
             }
         } else {
             enum_md(E, K, mod, lo0, up0, nup, np,
@@ -408,16 +434,22 @@ __global__ __launch_bounds__(BLOCK) void k_md(EvDev E, ModDev M, Consts K)
                             MdOut o;
                             md_accept(K, mod, E.sx[hl], E.sy[hl], E.sz[hl], E.sx[hu], E.sy[hu],
                                       E.sz[hu], o);
-                            write_md(E, off + pos, slot, hl, hu, o, mod.barrel);
+                            write_md(E, off + pos, slot, hl, hu, o, mod);
                         }
                     });
         }
     }
 }
 
-hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s)
+__global__ __launch_bounds__(BLOCK) void k_md(EvDev E, ModDev M, Consts K)
 {
-    hipLaunchKernelGGL(k_md, dim3(grid_for(E.cap_slots)), dim3(BLOCK), 0, s, E, M, K);
+    __shared__ SmMD sm;
+    md_body(E, M, K, sm);
+}
+
+hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_md, dim3(grid), dim3(BLOCK), 0, s, E, M, K);
     return hipGetLastError();
 }
 
@@ -467,9 +499,8 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
     return cnt;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_seg(EvDev E, ModDev M, Consts K)
+__device__ __forceinline__ void seg_body(const EvDev &E, const ModDev &M, const Consts &K, SmSeg &sm)
 {
-    __shared__ int32_t s_o[WAVES][STAGE];
     if (upstream_overflow(E)) return;
     const int w = wave_id();
     const Regions R = load_regions(E, OT_MD);
@@ -480,7 +511,7 @@ __global__ __launch_bounds__(BLOCK) void k_seg(EvDev E, ModDev M, Consts K)
         uint32_t cnt = 0;
         if (act)
             cnt = enum_seg(E, M, K, i, [&](bool ok, int32_t o, uint32_t pos) {
-                if (ok && pos < STAGE) s_o[w][pos] = o;
+                if (ok && pos < STAGE) sm.o[w][pos] = o;
             });
         bool ovf;
         const uint32_t off = block_reserve(cnt, E, OT_SEG, ovf);
@@ -493,7 +524,7 @@ __global__ __launch_bounds__(BLOCK) void k_seg(EvDev E, ModDev M, Consts K)
         if (cnt <= STAGE) {
             for (uint32_t k = lane_id(); k < cnt; k += 64) {
                 E.seg_in[off + k] = i;
-                E.seg_out[off + k] = s_o[w][k];
+                E.seg_out[off + k] = sm.o[w][k];
             }
         } else {
             enum_seg(E, M, K, i, [&](bool ok, int32_t o, uint32_t pos) {
@@ -506,9 +537,15 @@ __global__ __launch_bounds__(BLOCK) void k_seg(EvDev E, ModDev M, Consts K)
     }
 }
 
-hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s)
+__global__ __launch_bounds__(BLOCK) void k_seg(EvDev E, ModDev M, Consts K)
 {
-    hipLaunchKernelGGL(k_seg, dim3(GRID_MAX), dim3(BLOCK), 0, s, E, M, K);
+    __shared__ SmSeg sm;
+    seg_body(E, M, K, sm);
+}
+
+hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_seg, dim3(grid), dim3(BLOCK), 0, s, E, M, K);
     return hipGetLastError();
 }
 
@@ -556,11 +593,8 @@ __device__ __forceinline__ uint32_t enum_t3(const EvDev &E, const Consts &K, int
     return cnt;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_t3(EvDev E, ModDev M, Consts K)
+__device__ __forceinline__ void t3_body(const EvDev &E, const Consts &K, SmT3 &sm)
 {
-    __shared__ int32_t s_b[WAVES][STAGE];
-    __shared__ int32_t s_c[WAVES][STAGE];
-    __shared__ float s_k[WAVES][STAGE];
     if (upstream_overflow(E)) return;
     const int w = wave_id();
     const Regions R = load_regions(E, OT_MD);
@@ -572,9 +606,9 @@ __global__ __launch_bounds__(BLOCK) void k_t3(EvDev E, ModDev M, Consts K)
         if (act)
             cnt = enum_t3(E, K, a, [&](bool ok, int32_t b, int32_t c, float k, uint32_t pos) {
                 if (ok && pos < STAGE) {
-                    s_b[w][pos] = b;
-                    s_c[w][pos] = c;
-                    s_k[w][pos] = k;
+                    sm.b[w][pos] = b;
+                    sm.c[w][pos] = c;
+                    sm.k[w][pos] = k;
                 }
             });
         bool ovf;
@@ -588,9 +622,9 @@ __global__ __launch_bounds__(BLOCK) void k_t3(EvDev E, ModDev M, Consts K)
         if (cnt <= STAGE) {
             for (uint32_t k = lane_id(); k < cnt; k += 64) {
                 E.t3_a[off + k] = a;
-                E.t3_b[off + k] = s_b[w][k];
-                E.t3_c[off + k] = s_c[w][k];
-                E.t3_k[off + k] = s_k[w][k];
+                E.t3_b[off + k] = sm.b[w][k];
+                E.t3_c[off + k] = sm.c[w][k];
+                E.t3_k[off + k] = sm.k[w][k];
             }
         } else {
             enum_t3(E, K, a, [&](bool ok, int32_t b, int32_t c, float k, uint32_t pos) {
@@ -605,9 +639,16 @@ __global__ __launch_bounds__(BLOCK) void k_t3(EvDev E, ModDev M, Consts K)
     }
 }
 
-hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s)
+__global__ __launch_bounds__(BLOCK) void k_t3(EvDev E, Consts K)
 {
-    hipLaunchKernelGGL(k_t3, dim3(GRID_MAX), dim3(BLOCK), 0, s, E, M, K);
+    __shared__ SmT3 sm;
+    t3_body(E, K, sm);
+}
+
+hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s)
+{
+    (void)M;
+    hipLaunchKernelGGL(k_t3, dim3(grid), dim3(BLOCK), 0, s, E, K);
     return hipGetLastError();
 }
 
@@ -671,13 +712,11 @@ __device__ __forceinline__ void write_t5(const EvDev &E, uint32_t at, int32_t a,
     E.t5_md4[at] = e;
     E.t5_score[at] = score;
     E.t5_keep[at] = 0;
+    E.t5_veto[at] = 0;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_t5(EvDev E, ModDev M, Consts K)
+__device__ __forceinline__ void t5_body(const EvDev &E, const Consts &K, SmT5 &sm)
 {
-    __shared__ int32_t s_b[WAVES][STAGE], s_c[WAVES][STAGE], s_d[WAVES][STAGE],
-        s_e[WAVES][STAGE];
-    __shared__ float s_s[WAVES][STAGE];
     if (upstream_overflow(E)) return;
     const int w = wave_id();
     const Regions R = load_regions(E, OT_MD);
@@ -690,11 +729,11 @@ __global__ __launch_bounds__(BLOCK) void k_t5(EvDev E, ModDev M, Consts K)
             cnt = enum_t5(E, K, a, [&](bool ok, int32_t b, int32_t c, int32_t d, int32_t e,
                                        float sc, uint32_t pos) {
                 if (ok && pos < STAGE) {
-                    s_b[w][pos] = b;
-                    s_c[w][pos] = c;
-                    s_d[w][pos] = d;
-                    s_e[w][pos] = e;
-                    s_s[w][pos] = sc;
+                    sm.b[w][pos] = b;
+                    sm.c[w][pos] = c;
+                    sm.d[w][pos] = d;
+                    sm.e[w][pos] = e;
+                    sm.s[w][pos] = sc;
                 }
             });
         bool ovf;
@@ -702,7 +741,7 @@ __global__ __launch_bounds__(BLOCK) void k_t5(EvDev E, ModDev M, Consts K)
         if (!act || ovf || cnt == 0) continue;
         if (cnt <= STAGE) {
             for (uint32_t k = lane_id(); k < cnt; k += 64)
-                write_t5(E, off + k, a, s_b[w][k], s_c[w][k], s_d[w][k], s_e[w][k], s_s[w][k]);
+                write_t5(E, off + k, a, sm.b[w][k], sm.c[w][k], sm.d[w][k], sm.e[w][k], sm.s[w][k]);
         } else {
             enum_t5(E, K, a, [&](bool ok, int32_t b, int32_t c, int32_t d, int32_t e, float sc,
                                  uint32_t pos) {
@@ -712,9 +751,16 @@ __global__ __launch_bounds__(BLOCK) void k_t5(EvDev E, ModDev M, Consts K)
     }
 }
 
-hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, hipStream_t s)
+__global__ __launch_bounds__(BLOCK) void k_t5(EvDev E, Consts K)
 {
-    hipLaunchKernelGGL(k_t5, dim3(GRID_MAX), dim3(BLOCK), 0, s, E, M, K);
+    __shared__ SmT5 sm;
+    t5_body(E, K, sm);
+}
+
+hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s)
+{
+    (void)M;
+    hipLaunchKernelGGL(k_t5, dim3(grid), dim3(BLOCK), 0, s, E, K);
     return hipGetLastError();
 }
 
@@ -773,24 +819,24 @@ __device__ __forceinline__ int32_t t5_at(const EvDev &E, const uint32_t *s_pre, 
 }
 
 // one thread per (quintuplet, hit)
-__global__ void k_dedup_min(EvDev E)
+__device__ __forceinline__ void dedup_min_body(const EvDev &E, uint32_t *s_pre)
 {
-    __shared__ uint32_t s_pre[NSH + 1];
     if (upstream_overflow(E)) return;
     const uint32_t n = t5_prefix(E, s_pre) * 10u;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const int32_t t = t5_at(E, s_pre, v / 10u);
+        if (E.t5_veto[t]) continue;
         atomicMin(&E.hmin[t5_hit(E, t, (int)(v % 10u))], __float_as_uint(E.t5_score[t]));
     }
 }
 
-__global__ void k_dedup_tie(EvDev E)
+__device__ __forceinline__ void dedup_tie_body(const EvDev &E, uint32_t *s_pre)
 {
-    __shared__ uint32_t s_pre[NSH + 1];
     if (upstream_overflow(E)) return;
     const uint32_t n = t5_prefix(E, s_pre) * 10u;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const int32_t t = t5_at(E, s_pre, v / 10u);
+        if (E.t5_veto[t]) continue;
         const int32_t h = t5_hit(E, t, (int)(v % 10u));
         if (E.hmin[h] == __float_as_uint(E.t5_score[t])) {
             const int k = atomicAdd(&E.htie[h], 1);
@@ -810,13 +856,16 @@ __device__ __forceinline__ bool tuple_less(const EvDev &E, int32_t u, int32_t t)
 }
 
 // one thread per quintuplet; the ten hit lookups are independent loads
-__global__ void k_dedup_keep(EvDev E)
+__device__ __forceinline__ void dedup_keep_body(const EvDev &E, uint32_t *s_pre)
 {
-    __shared__ uint32_t s_pre[NSH + 1];
     if (upstream_overflow(E)) return;
     const uint32_t n = t5_prefix(E, s_pre);
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const int32_t t = t5_at(E, s_pre, v);
+        if (E.t5_veto[t]) {
+            E.t5_keep[t] = 0;
+            continue;
+        }
         const float sc = E.t5_score[t];
         const uint32_t key = __float_as_uint(sc);
         int32_t h[10];
@@ -854,13 +903,161 @@ __global__ void k_dedup_keep(EvDev E)
     }
 }
 
-hipError_t launch_dedup(const EvDev &E, const ModDev &M, hipStream_t s)
+__global__ void k_dedup_min(EvDev E)
+{
+    __shared__ uint32_t s_pre[NSH + 1];
+    dedup_min_body(E, s_pre);
+}
+
+__global__ void k_dedup_tie(EvDev E)
+{
+    __shared__ uint32_t s_pre[NSH + 1];
+    dedup_tie_body(E, s_pre);
+}
+
+__global__ void k_dedup_keep(EvDev E)
+{
+    __shared__ uint32_t s_pre[NSH + 1];
+    dedup_keep_body(E, s_pre);
+}
+
+hipError_t launch_dedup(const EvDev &E, const ModDev &M, int grid, hipStream_t s)
 {
     (void)M;
-    const int blocks = 512;
-    hipLaunchKernelGGL(k_dedup_min, dim3(blocks), dim3(BLOCK), 0, s, E);
-    hipLaunchKernelGGL(k_dedup_tie, dim3(blocks), dim3(BLOCK), 0, s, E);
-    hipLaunchKernelGGL(k_dedup_keep, dim3(blocks), dim3(BLOCK), 0, s, E);
+    hipLaunchKernelGGL(k_dedup_min, dim3(grid), dim3(BLOCK), 0, s, E);
+    hipLaunchKernelGGL(k_dedup_tie, dim3(grid), dim3(BLOCK), 0, s, E);
+    hipLaunchKernelGGL(k_dedup_keep, dim3(grid), dim3(BLOCK), 0, s, E);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- scorer features
+// the 40 features of every stored quintuplet (one thread each)
+__global__ void k_t5_features(EvDev E, Consts K)
+{
+    __shared__ uint32_t s_pre[NSH + 1];
+    if (upstream_overflow(E)) return;
+    const uint32_t n = t5_prefix(E, s_pre);
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int32_t t = t5_at(E, s_pre, v);
+        MdV P[5];
+        MdX X[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int32_t m = t5_md(E, t, j);
+            P[j] = load_md(E, m);
+            X[j].bend = E.md_bend[m];
+            X[j].is2s = E.md_bar[m] >> 1;
+        }
+        const float kin = tri_curv(P[0], P[1], P[2]);
+        const float kout = tri_curv(P[2], P[3], P[4]);
+        float f[40];
+        t5_features(K, P, X, kin, kout, f);
+        float *out = E.t5_feat + (size_t)t * 40;
+#pragma unroll
+        for (int j = 0; j < 40; ++j) out[j] = f[j];
+    }
+}
+
+hipError_t launch_t5_features(const EvDev &E, const Consts &K, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_t5_features, dim3(grid), dim3(BLOCK), 0, s, E, K);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- persistent chain
+// All stages in one launch.  Stages are separated by a grid barrier: blocks
+// arrive on one of BAR_SH shard counters (blockIdx % BAR_SH); the last block
+// of a shard bumps the top counter, which everyone polls.  Release/acquire
+// fences at agent scope make one stage's writes visible to every XCD before
+// the next stage reads them.  The grid must be co-resident (sized from the
+// occupancy query); if it is not, the poll gives up after a bounded time,
+// raises error bit 1 and the blocks leave, so the kernel always terminates.
+constexpr int BAR_SH = 32;
+constexpr uint32_t BAR_SPIN_LIMIT = 1u << 19;   // ~0.5 s of polling
+
+__device__ __forceinline__ bool grid_sync(const EvDev &E, uint32_t gen)
+{
+    __shared__ int s_ok;
+    const uint32_t G = gridDim.x, b = blockIdx.x;
+    const uint32_t nsh = G < (uint32_t)BAR_SH ? G : (uint32_t)BAR_SH;
+    const uint32_t sh = b % BAR_SH;
+    const uint32_t shard_size = (G - sh + BAR_SH - 1) / BAR_SH;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t old = atomicAdd(&E.bar[sh], 1u);
+        if (old + 1u == gen * shard_size) atomicAdd(&E.bar[BAR_SH], 1u);
+        int ok = 1;
+        uint32_t it = 0;
+        while (__hip_atomic_load(&E.bar[BAR_SH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+               gen * nsh) {
+            if (++it > BAR_SPIN_LIMIT) {
+                ok = 0;
+                atomicOr(&E.gc[GC_ERROR], 2u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        s_ok = ok;
+    }
+    __syncthreads();
+    __threadfence();
+    return s_ok != 0;
+}
+
+__global__ void k_bar_reset(uint32_t *bar)
+{
+    if (threadIdx.x <= BAR_SH) bar[threadIdx.x] = 0u;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_chain(EvDev E, ModDev M, Consts K, uint4 *zero_base,
+                                                 size_t zero16)
+{
+    __shared__ SmChain sm;
+    uint32_t gen = 0;
+#define LST_SYNC() \
+    if (!grid_sync(E, ++gen)) return
+    zero_body(zero_base, zero16);
+    LST_SYNC();
+    hist_body(E, M.n_mod);
+    LST_SYNC();
+    scan_reduce_body(E);
+    LST_SYNC();
+    scan_top_body(E);
+    LST_SYNC();
+    scan_down_body(E);
+    LST_SYNC();
+    scatter_body(E, M.n_mod);
+    LST_SYNC();
+    md_body(E, M, K, sm.u.md);
+    LST_SYNC();
+    seg_body(E, M, K, sm.u.seg);
+    LST_SYNC();
+    t3_body(E, K, sm.u.t3);
+    LST_SYNC();
+    t5_body(E, K, sm.u.t5);
+    LST_SYNC();
+    dedup_min_body(E, sm.pre);
+    LST_SYNC();
+    dedup_tie_body(E, sm.pre);
+    LST_SYNC();
+    dedup_keep_body(E, sm.pre);
+#undef LST_SYNC
+}
+
+int persistent_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain, BLOCK, 0) != hipSuccess) return 0;
+    return nb;
+}
+
+hipError_t launch_chain_persistent(const EvDev &E, const ModDev &M, const Consts &K,
+                                   void *zero_base, size_t zero_bytes, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, s, E.bar);
+    hipLaunchKernelGGL(k_chain, dim3(grid), dim3(BLOCK), 0, s, E, M, K, (uint4 *)zero_base,
+                       zero_bytes / 16);
     return hipGetLastError();
 }
 

@@ -26,7 +26,8 @@ LST_MOD_NF, LST_MOD_NI = 21, 4
 
 class lst_caps(ctypes.Structure):
     _fields_ = [("events", ctypes.c_int32), ("hits", ctypes.c_int64), ("md", ctypes.c_int64),
-                ("seg", ctypes.c_int64), ("t3", ctypes.c_int64), ("t5", ctypes.c_int64)]
+                ("seg", ctypes.c_int64), ("t3", ctypes.c_int64), ("t5", ctypes.c_int64),
+                ("features", ctypes.c_int32)]
 
 
 class lst_counts(ctypes.Structure):
@@ -72,6 +73,13 @@ _SIGS = {
     "lst_get_t5_scores": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64,
                                          ctypes.POINTER(ctypes.c_int64), _P]),
     "lst_stream_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+    "lst_run_chain_persistent": (ctypes.c_int, [_P, _P]),
+    "lst_run_t5_features": (ctypes.c_int, [_P, _P]),
+    "lst_get_t5_features": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64,
+                                           ctypes.POINTER(ctypes.c_int64), _P]),
+    "lst_set_tuning": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32]),
+    "lst_get_tuning": (ctypes.c_int, [_P, _P]),
+    "lst_tune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_int32, _P, _P]),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -128,7 +136,8 @@ def lst_stream_copy(dst: "torch.Tensor", src: "torch.Tensor", stream=None):
 
 def default_caps(n_events: int, n_hits: int) -> dict:
     md = max(4096, int(1.5 * n_hits))
-    return dict(events=n_events, hits=max(n_hits, 1), md=md, seg=6 * md, t3=4 * md, t5=4 * md)
+    return dict(events=n_events, hits=max(n_hits, 1), md=md, seg=6 * md, t3=4 * md, t5=4 * md,
+                features=0)
 
 
 class Context:
@@ -172,6 +181,8 @@ class Context:
 
     # -- memory -------------------------------------------------------------
     def reserve(self, caps: dict):
+        caps = dict(caps)
+        caps.setdefault("features", 0)
         c = lst_caps(**caps)
         nbytes = ctypes.c_size_t(0)
         self._check(self.lib.lst_arena_bytes(self.h, ctypes.byref(c), ctypes.byref(nbytes)))
@@ -198,7 +209,10 @@ class Context:
         n_ev = len(offsets) - 1
         n = int(offsets[-1])
         if self.caps is None or self.caps["events"] < n_ev or self.caps["hits"] < n:
-            self.reserve(default_caps(n_ev, n))
+            caps = default_caps(n_ev, n)
+            if self.caps is not None:
+                caps["features"] = self.caps.get("features", 0)
+            self.reserve(caps)
         if isinstance(x, torch.Tensor):
             arrs = [x, y, z, module, sensor]
             for a in arrs:
@@ -241,6 +255,28 @@ class Context:
     def run_chain_graph(self, stream=None):
         self._check(self.lib.lst_run_chain_graph(self.h, self._stream(stream)))
 
+    def run_chain_persistent(self, stream=None):
+        self._check(self.lib.lst_run_chain_persistent(self.h, self._stream(stream)))
+
+    def tuning(self) -> dict:
+        out = np.zeros(9, np.int32)
+        self._check(self.lib.lst_get_tuning(self.h, _np_ptr(out)))
+        return dict(grid=out[:6].tolist(), persistent=int(out[6]), blocks_per_cu=int(out[7]),
+                    n_cu=int(out[8]))
+
+    def set_tuning(self, grid, persistent=0, blocks_per_cu=1):
+        g = np.ascontiguousarray(grid, np.int32)
+        self._check(self.lib.lst_set_tuning(self.h, _np_ptr(g), int(persistent), int(blocks_per_cu)))
+
+    def tune(self, cache_path=None, reps=5, stream=None) -> dict:
+        """Autotune the launch shape on the loaded batch (see lst_tune)."""
+        rep = np.zeros(8, np.float64)
+        cp = cache_path.encode() if cache_path else None
+        self._check(self.lib.lst_tune(self.h, cp, int(reps), _np_ptr(rep), self._stream(stream)))
+        out = self.tuning()
+        out["report_us"] = rep.tolist()
+        return out
+
     # -- outputs ------------------------------------------------------------
     def counts(self, event=0, stream=None, check=True) -> dict:
         c = lst_counts()
@@ -259,6 +295,19 @@ class Context:
         out = np.zeros((max(n.value, 1), WIDTH[kind]), np.int32)
         self._check(self.lib.lst_get_objects(self.h, event, kind, _np_ptr(out), n.value,
                                              ctypes.byref(n), self._stream(stream)))
+        return out[:n.value]
+
+    def run_t5_features(self, stream=None):
+        self._check(self.lib.lst_run_t5_features(self.h, self._stream(stream)))
+
+    def t5_features(self, event, stream=None) -> np.ndarray:
+        n = ctypes.c_int64(0)
+        rc = self.lib.lst_get_t5_features(self.h, event, None, 0, ctypes.byref(n), self._stream(stream))
+        if rc not in (LST_OK, LST_E_CAPACITY):
+            self._check(rc)
+        out = np.zeros((max(n.value, 1), 40), np.float32)
+        self._check(self.lib.lst_get_t5_features(self.h, event, _np_ptr(out), n.value,
+                                                 ctypes.byref(n), self._stream(stream)))
         return out[:n.value]
 
     def t5_scores(self, event, stream=None) -> np.ndarray:

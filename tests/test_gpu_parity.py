@@ -179,3 +179,88 @@ def test_graph_chain_replays_match_eager_and_oracle():
         ctx.run_event(ev1)
     got1 = ctx.run_event(ev1, graph=True)
     assert_parity(got1, orc.run_event(ev1))
+
+
+def _batch_parity(ctx, evs, orc):
+    for e, ev in enumerate(evs):
+        assert_parity({k: ctx.objects(e, k) for k in range(5)}, orc.run_event(ev))
+        assert (ctx.counts(e)["error_flags"] & 2) == 0     # no barrier time-out
+
+
+def test_persistent_chain_matches_oracle():
+    """The whole chain as one persistent kernel (eager launch and inside a
+    hipGraph), on a ragged batch of uneven events and on a PU200-like event."""
+    geo = G.get("barrel_toy")
+    params = PR.make()
+    orc = oracle.Oracle(params, geo.f32, geo.i32)
+    evs = [E.generate(3, e) for e in range(6)] + [E.generate(1, 7)]
+    b = E.concat(evs)
+    print("case persistent batch", b.offsets.tolist(), flush=True)
+    ctx = _ctx(geo, params)
+    ctx.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)      # sizes the arena
+    t = ctx.tuning()
+    for bpc in sorted({1, t["blocks_per_cu"]}):
+        ctx.set_tuning(t["grid"], persistent=1, blocks_per_cu=bpc)
+        ctx.load_hits(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+        ctx.run_chain_persistent()
+        _batch_parity(ctx, evs, orc)
+        ctx.load_hits(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+        ctx.run_chain_graph()
+        _batch_parity(ctx, evs, orc)
+    geo2 = G.get("full")
+    ev = E.generate(2, 0)
+    print("case persistent pu200", flush=True)
+    ctx2 = _ctx(geo2, params)
+    ctx2.run_event(ev)
+    t2 = ctx2.tuning()
+    ctx2.set_tuning(t2["grid"], persistent=1, blocks_per_cu=t2["blocks_per_cu"])
+    got = ctx2.run_event(ev)
+    assert_parity(got, oracle.Oracle(params, geo2.f32, geo2.i32).run_event(ev))
+
+
+def test_autotuner_keeps_results_and_caches(tmp_path):
+    geo = G.get("barrel_toy")
+    params = PR.make()
+    orc = oracle.Oracle(params, geo.f32, geo.i32)
+    evs = [E.generate(3, 10 + e) for e in range(3)]
+    b = E.concat(evs)
+    print("case tuner", b.offsets.tolist(), flush=True)
+    ctx = _ctx(geo, params)
+    ctx.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+    cache = str(tmp_path / "tune.jsonl")
+    res = ctx.tune(cache_path=cache, reps=2)
+    print("tuned", res, flush=True)
+    assert res["report_us"][0] > 0
+    _batch_parity(ctx, evs, orc)
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and '"tuning"' in lines[0]
+    ctx2 = _ctx(geo, params)
+    ctx2.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+    res2 = ctx2.tune(cache_path=cache, reps=2)
+    assert res2["report_us"][0] == -1.0
+    assert res2["grid"] == res["grid"] and res2["persistent"] == res["persistent"]
+    ctx2.load_hits(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+    ctx2.run_chain_graph()
+    _batch_parity(ctx2, evs, orc)
+
+
+@pytest.mark.parametrize("cid,n_tracks", [(2, 1500), (5, 600)])
+def test_t5_features_bitwise(cid, n_tracks):
+    cfg = E.CONFIGS[cid]
+    geo = G.get(cfg.geometry)
+    params = PR.make(w=cfg.window)
+    ev = E.generate(cid, 2, n_tracks=n_tracks)
+    print(f"case features cfg{cid}", ev.n_hits, flush=True)
+    ctx = _ctx(geo, params)
+    caps = dict(ctx.lib and __import__("paper_2209_13711_amd").default_caps(1, ev.n_hits))
+    caps["features"] = 1
+    ctx.reserve(caps)
+    ctx.run_event(ev)
+    ctx.run_t5_features()
+    tup = ctx.objects(0, 3)
+    feat = ctx.t5_features(0)
+    ref = oracle.Oracle(params, geo.f32, geo.i32).run_event(ev)
+    omap = {tuple(t): f for t, f in zip(ref.tuples[3].tolist(), ref.t5_features.view(np.uint32))}
+    assert len(tup) == len(omap) > 50
+    for t, f in zip(tup.tolist(), feat.view(np.uint32)):
+        np.testing.assert_array_equal(f, omap[tuple(t)])
