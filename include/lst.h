@@ -79,6 +79,15 @@ enum lst_param {
 #define LST_MOD_NF 21
 #define LST_MOD_NI 4
 
+/* chain modes (lst_set_mode) */
+#define LST_MODE_CUTS 0 /* the plain cut chain */
+#define LST_MODE_MLP 1  /* cut chain + learned veto of quintuplets before dedup */
+
+/* learned scorer: inputs, and FP32 parameters in the order W1[64][40]
+ * (row = hidden unit), b1[64], W2[64][64], b2[64], w3[64], b3 */
+#define LST_MLP_NFEAT 40
+#define LST_MLP_NPARAM 6849
+
 typedef struct lst_ctx lst_ctx;
 
 /* capacities of one arena (totals over all events of a batch) */
@@ -228,6 +237,75 @@ int lst_tune(lst_ctx *ctx, const char *cache_path, int32_t reps, double *report,
  * on `stream`.  Used to measure the achievable HBM bandwidth and to
  * calibrate the FETCH_SIZE / WRITE_SIZE counters against a known byte count. */
 int lst_stream_copy(void *dst, const void *src, size_t n_bytes, void *stream);
+
+/* ---- Learned quintuplet scorer --------------------------------------------
+ * Not part of the paper.  Its outlook (Sec. 4, Summary and Outlook) plans to
+ * revisit the object selection to raise efficiency and lower the fake rate;
+ * this addition scores every quintuplet passing the cuts with a small network
+ * and vetoes those it rejects before duplicate removal.  The cut chain stays
+ * the fallback (LST_MODE_CUTS) and the reference for its efficiency and fake
+ * rate.
+ *
+ * Network: 40 features -> 64 -> 64 -> 1 logit, ReLU after both hidden layers.
+ * Features are standardised in FP32 as (f - mean) * istd and rounded to BF16
+ * (nearest, ties to even); W1 and W2 are rounded to BF16 and the products
+ * accumulated in FP32 on the matrix cores; the first hidden layer is rounded
+ * to BF16 again before the second; w3, biases and the last layer are FP32.
+ * A quintuplet is accepted iff logit >= threshold. */
+
+/* Copy the scorer (host arrays: LST_MLP_NPARAM parameters, mean[40],
+ * istd[40]) and the logit threshold into the context.  Synchronous; values
+ * must be finite (else LST_E_INVALID). */
+int lst_mlp_load(lst_ctx *ctx, const float *params, int32_t n_params, const float *mean,
+                 const float *istd, float threshold);
+
+/* LST_MODE_CUTS or LST_MODE_MLP (needs lst_mlp_load first, else
+ * LST_E_STATE).  lst_run_chain, lst_run_chain_graph and
+ * lst_run_chain_persistent then include the scoring step. */
+int lst_set_mode(lst_ctx *ctx, int32_t mode);
+
+/* The scoring step on its own, between lst_run_quintuplets and lst_run_dedup
+ * (else LST_E_STATE): features computed on the device for every stored
+ * quintuplet, logit stored, veto set when logit < threshold.  Asynchronous. */
+int lst_run_t5_score(lst_ctx *ctx, void *stream);
+
+/* Logits and vetoes (1 = rejected) of `event`'s quintuplets in the order of
+ * lst_get_objects(LST_T5); host outputs of capacity cap.  Meaningful after a
+ * scoring step. */
+int lst_get_t5_logits(lst_ctx *ctx, int32_t event, float *logits_host, uint8_t *veto_host,
+                      int64_t cap, int64_t *n, void *stream);
+
+/* ---- Training (device pointers, asynchronous on `stream`, ctx's device) ----
+ * A batch of n rows: x [n][64] BF16 bit patterns (uint16; features 0..39
+ * standardised, 40..63 zero), y [n] labels (0/1).  The loss is the mean
+ * binary cross entropy on the logits; gradients flow through the BF16
+ * roundings unchanged.  Every sum runs in a fixed order, so results are
+ * bit-for-bit reproducible. */
+
+/* device workspace lst_mlp_backward needs for n rows */
+size_t lst_mlp_workspace_bytes(int64_t n);
+
+/* x = BF16((feat - mean) * istd), zero padded to 64 columns; feat [n][40] FP32 */
+int lst_mlp_prepare(lst_ctx *ctx, const float *feat, const float *mean, const float *istd,
+                    int64_t n, uint16_t *x, void *stream);
+
+/* logits [n] (FP32) of the network `params` (FP32 master weights, device).
+ * h1 [n][64] (BF16 bits) and h2 [n][64] (FP32), the hidden activations, are
+ * saved for lst_mlp_backward when both are non-null. */
+int lst_mlp_forward(lst_ctx *ctx, const float *params, const uint16_t *x, int64_t n, float *logits,
+                    uint16_t *h1, float *h2, void *stream);
+
+/* grad [LST_MLP_NPARAM] = dL/dparams and *loss (device) for the batch whose
+ * forward saved logits, h1, h2.  work: device scratch of work_bytes >=
+ * lst_mlp_workspace_bytes(n) (else LST_E_CAPACITY). */
+int lst_mlp_backward(lst_ctx *ctx, const float *params, const uint16_t *x, const uint8_t *y,
+                     int64_t n, const float *logits, const uint16_t *h1, const float *h2,
+                     void *work, size_t work_bytes, float *grad, float *loss, void *stream);
+
+/* One Adam step (bias corrected, step >= 1) on params with moments m, v
+ * (device, LST_MLP_NPARAM each, updated in place). */
+int lst_mlp_adam(lst_ctx *ctx, float *params, const float *grad, float *m, float *v, int32_t step,
+                 float lr, float beta1, float beta2, float eps, void *stream);
 
 #ifdef __cplusplus
 }

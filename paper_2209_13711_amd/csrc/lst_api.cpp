@@ -55,6 +55,10 @@ struct lst_ctx {
     Tuning tune{};
     int n_cu = 0;
     bool features_valid = false;
+    // learned scorer
+    int mode = LST_MODE_CUTS;
+    float *mlp_dev = nullptr;   // params [MLP_NPARAM], mean [40], istd [40]
+    float mlp_threshold = 0.0f;
     std::vector<lst_counts> counts;
     bool counts_valid = false;
     int stage = 0;  // 0 nothing, 1 hits loaded, 2 sorted, 3 md, 4 seg, 5 t3, 6 t5, 7 dedup
@@ -211,7 +215,7 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.t5_keep = cv.take<uint8_t>(nt5);
     E.t5_veto = cv.take<uint8_t>(nt5);
     E.t5_feat = k.features ? cv.take<float>(nt5 * 40) : nullptr;
-    E.t5_logit = k.features ? cv.take<float>(nt5) : nullptr;
+    E.t5_logit = cv.take<float>(nt5);
     return (cv.off + 255) & ~(size_t)255;
 }
 }  // namespace
@@ -265,6 +269,7 @@ void lst_destroy(lst_ctx *c)
     if (c->stage_host) (void)hipHostFree(c->stage_host);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->geo_dev) (void)hipFree(c->geo_dev);
+    if (c->mlp_dev) (void)hipFree(c->mlp_dev);
     delete c;
 }
 
@@ -548,6 +553,121 @@ int lst_run_dedup(lst_ctx *c, void *stream)
 
 int lst_run_chain_persistent(lst_ctx *c, void *stream);
 
+// ---------------------------------------------------------------- learned scorer
+static int score_grid(const lst_ctx *c);
+static int enqueue_score(lst_ctx *c, hipStream_t s);
+
+int lst_set_mode(lst_ctx *c, int32_t mode)
+{
+    if (!c) return LST_E_INVALID;
+    if (mode != LST_MODE_CUTS && mode != LST_MODE_MLP) return fail(c, LST_E_INVALID, "mode %d", mode);
+    if (mode == LST_MODE_MLP && !c->mlp_dev)
+        return fail(c, LST_E_STATE, "scorer mode needs weights (lst_mlp_load)");
+    if (mode != c->mode) drop_graph(c);
+    c->mode = mode;
+    return LST_OK;
+}
+
+int lst_mlp_load(lst_ctx *c, const float *params, int32_t n_params, const float *mean,
+                 const float *istd, float threshold)
+{
+    if (!c) return LST_E_INVALID;
+    if (!params || !mean || !istd || n_params != MLP_NPARAM)
+        return fail(c, LST_E_INVALID, "scorer weights: %d parameters, %d expected", n_params,
+                    MLP_NPARAM);
+    for (int i = 0; i < MLP_NPARAM; ++i)
+        if (!std::isfinite(params[i])) return fail(c, LST_E_INVALID, "scorer parameter %d not finite", i);
+    for (int i = 0; i < MLP_NIN; ++i)
+        if (!std::isfinite(mean[i]) || !std::isfinite(istd[i]))
+            return fail(c, LST_E_INVALID, "standardisation of feature %d not finite", i);
+    if (!std::isfinite(threshold)) return fail(c, LST_E_INVALID, "threshold not finite");
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t n = MLP_NPARAM + 2 * MLP_NIN;
+    if (!c->mlp_dev) HIPCHK(c, hipMalloc((void **)&c->mlp_dev, sizeof(float) * n));
+    std::vector<float> h(n);
+    std::memcpy(h.data(), params, sizeof(float) * MLP_NPARAM);
+    std::memcpy(h.data() + MLP_NPARAM, mean, sizeof(float) * MLP_NIN);
+    std::memcpy(h.data() + MLP_NPARAM + MLP_NIN, istd, sizeof(float) * MLP_NIN);
+    // synchronous: a replayed graph reads these weights by address
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, hipMemcpy(c->mlp_dev, h.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+    if (threshold != c->mlp_threshold) drop_graph(c);
+    c->mlp_threshold = threshold;
+    return LST_OK;
+}
+
+int lst_run_t5_score(lst_ctx *c, void *stream)
+{
+    if (!c) return LST_E_INVALID;
+    if (!c->mlp_dev) return fail(c, LST_E_STATE, "scorer weights not loaded");
+    if (c->stage != 6)
+        return fail(c, LST_E_STATE, "lst_run_t5_score runs after quintuplets, before dedup");
+    int rc = need_stage(c, 6, "lst_run_t5_score");
+    if (rc) return rc;
+    return enqueue_score(c, (hipStream_t)stream);
+}
+
+size_t lst_mlp_workspace_bytes(int64_t n) { return n < 0 ? 0 : mlp_workspace_bytes(n); }
+
+static int mlp_args(lst_ctx *c, int64_t n, std::initializer_list<const void *> ptrs)
+{
+    if (!c) return LST_E_INVALID;
+    if (n < 0 || n > ((int64_t)1 << 31)) return fail(c, LST_E_INVALID, "rows %lld", (long long)n);
+    if (n > 0)   // empty batches may come with null pointers
+        for (const void *p : ptrs)
+            if (!p) return fail(c, LST_E_INVALID, "null device pointer");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, LST_E_HIP, "hipSetDevice");
+    return LST_OK;
+}
+
+int lst_mlp_prepare(lst_ctx *c, const float *feat, const float *mean, const float *istd, int64_t n,
+                    uint16_t *x, void *stream)
+{
+    int rc = mlp_args(c, n, {feat, mean, istd, x});
+    if (rc || n == 0) return rc;
+    HIPCHK(c, mlp_prepare(feat, mean, istd, n, x, (hipStream_t)stream));
+    return LST_OK;
+}
+
+int lst_mlp_forward(lst_ctx *c, const float *params, const uint16_t *x, int64_t n, float *logits,
+                    uint16_t *h1, float *h2, void *stream)
+{
+    int rc = mlp_args(c, n, {params, x, logits});
+    if (rc || n == 0) return rc;
+    if (!h1 != !h2) return fail(c, LST_E_INVALID, "h1 and h2 are saved together");
+    HIPCHK(c, mlp_forward(params, x, n, logits, h1, h2, (hipStream_t)stream));
+    return LST_OK;
+}
+
+int lst_mlp_backward(lst_ctx *c, const float *params, const uint16_t *x, const uint8_t *y, int64_t n,
+                     const float *logits, const uint16_t *h1, const float *h2, void *work,
+                     size_t work_bytes, float *grad, float *loss, void *stream)
+{
+    int rc = mlp_args(c, n, {params, x, y, logits, h1, h2, work, grad, loss});
+    if (rc) return rc;
+    if (n == 0) return fail(c, LST_E_INVALID, "empty batch");
+    if (work_bytes < mlp_workspace_bytes(n))
+        return fail(c, LST_E_CAPACITY, "workspace %zu bytes, %zu needed", work_bytes,
+                    mlp_workspace_bytes(n));
+    HIPCHK(c, mlp_backward(params, x, y, n, logits, h1, h2, (float *)work, grad, loss,
+                           (hipStream_t)stream));
+    return LST_OK;
+}
+
+int lst_mlp_adam(lst_ctx *c, float *params, const float *grad, float *m, float *v, int32_t step,
+                 float lr, float beta1, float beta2, float eps, void *stream)
+{
+    int rc = mlp_args(c, MLP_NPARAM, {params, grad, m, v});
+    if (rc) return rc;
+    if (step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+        !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return fail(c, LST_E_INVALID, "Adam hyper-parameters");
+    const float c1 = (float)(1.0 - std::pow((double)beta1, step));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, step));
+    HIPCHK(c, mlp_adam(params, grad, m, v, lr, beta1, beta2, eps, c1, c2, (hipStream_t)stream));
+    return LST_OK;
+}
+
 int lst_run_chain(lst_ctx *c, void *stream)
 {
     int rc;
@@ -557,26 +677,46 @@ int lst_run_chain(lst_ctx *c, void *stream)
     if ((rc = lst_run_segments(c, stream))) return rc;
     if ((rc = lst_run_triplets(c, stream))) return rc;
     if ((rc = lst_run_quintuplets(c, stream))) return rc;
+    if (c->mode == LST_MODE_MLP && (rc = lst_run_t5_score(c, stream))) return rc;
     return lst_run_dedup(c, stream);
 }
 
 // The whole chain as one hipGraph: captured once per arena (kernel grids and
 // arguments depend on the arena only; batch sizes are read on the device)
 // and replayed for every batch.  Only kernel nodes: no memset nodes.
+static int score_grid(const lst_ctx *c)
+{
+    // one block scores 256 quintuplets per pass; grid-stride beyond that
+    const int64_t need = ((int64_t)c->caps.t5 + 255) / 256;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(need, 2 * std::max(c->n_cu, 1)));
+}
+
+static int enqueue_score(lst_ctx *c, hipStream_t s)
+{
+    const float *P = c->mlp_dev;
+    HIPCHK(c, mlp_score(c->E, c->K, P, P + MLP_NPARAM, P + MLP_NPARAM + MLP_NIN, c->mlp_threshold,
+                        score_grid(c), s));
+    return LST_OK;
+}
+
 static int enqueue_chain(lst_ctx *c, hipStream_t s)
 {
     const Tuning &t = c->tune;
+    const bool mlp = c->mode == LST_MODE_MLP;
+    int rc;
     if (t.persistent) {
         HIPCHK(c, launch_chain_persistent(c->E, c->M, c->K, c->zero_base, c->zero_bytes,
-                                          t.blocks_per_cu * c->n_cu, s));
-        return LST_OK;
+                                          t.blocks_per_cu * c->n_cu, mlp, s));
+        if (!mlp) return LST_OK;
+    } else {
+        HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, s));
+        HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], s));
+        HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], s));
+        HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], s));
+        HIPCHK(c, launch_t3(c->E, c->M, c->K, t.grid[ST_T3], s));
+        HIPCHK(c, launch_t5(c->E, c->M, c->K, t.grid[ST_T5], s));
     }
-    HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, s));
-    HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], s));
-    HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], s));
-    HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], s));
-    HIPCHK(c, launch_t3(c->E, c->M, c->K, t.grid[ST_T3], s));
-    HIPCHK(c, launch_t5(c->E, c->M, c->K, t.grid[ST_T5], s));
+    if (mlp && (rc = enqueue_score(c, s))) return rc;
     HIPCHK(c, launch_dedup(c->E, c->M, t.grid[ST_DEDUP], s));
     return LST_OK;
 }
@@ -586,8 +726,14 @@ int lst_run_chain_persistent(lst_ctx *c, void *stream)
     int rc = need_stage(c, 1, "lst_run_chain_persistent");
     if (rc) return rc;
     const int bpc = std::max(1, std::min(c->tune.blocks_per_cu, persistent_blocks_per_cu()));
+    const bool mlp = c->mode == LST_MODE_MLP;
+    hipStream_t s = (hipStream_t)stream;
     HIPCHK(c, launch_chain_persistent(c->E, c->M, c->K, c->zero_base, c->zero_bytes,
-                                      bpc * c->n_cu, (hipStream_t)stream));
+                                      bpc * c->n_cu, mlp, s));
+    if (mlp) {
+        if ((rc = enqueue_score(c, s))) return rc;
+        HIPCHK(c, launch_dedup(c->E, c->M, c->tune.grid[ST_DEDUP], s));
+    }
     c->stage = 7;
     return LST_OK;
 }
@@ -902,8 +1048,12 @@ int lst_get_t5_features(lst_ctx *c, int32_t event, float *out, int64_t cap, int6
     return LST_OK;
 }
 
-int lst_get_t5_scores(lst_ctx *c, int32_t event, float *out, int64_t cap, int64_t *n_out,
-                      void *stream)
+}  // extern "C"
+
+// copy a per-quintuplet device array of `event` in lst_get_objects(LST_T5) order
+template <class T>
+static int t5_field(lst_ctx *c, int32_t event, const T *src, T *out, int64_t cap, int64_t *n_out,
+                    void *stream, const char *what)
 {
     if (!c) return LST_E_INVALID;
     if (event < 0 || event >= c->n_events) return fail(c, LST_E_INVALID, "event %d", event);
@@ -916,8 +1066,8 @@ int lst_get_t5_scores(lst_ctx *c, int32_t event, float *out, int64_t cap, int64_
     if (S.gc[GC_OVERFLOW])
         return fail(c, LST_E_CAPACITY, "capacity overflow (mask %u)", S.gc[GC_OVERFLOW]);
     std::vector<int32_t> m0, slot;
-    std::vector<float> sc;
-    if ((rc = d2h(c, m0, E.t5_md0, S.span(OT_T5))) || (rc = d2h(c, sc, E.t5_score, S.span(OT_T5))) ||
+    std::vector<T> val;
+    if ((rc = d2h(c, m0, E.t5_md0, S.span(OT_T5))) || (rc = d2h(c, val, src, S.span(OT_T5))) ||
         (rc = d2h(c, slot, E.md_slot, S.span(OT_MD))))
         return rc;
     const int lo_slot = event * c->n_mod, hi_slot = (event + 1) * c->n_mod;
@@ -926,13 +1076,31 @@ int lst_get_t5_scores(lst_ctx *c, int32_t event, float *out, int64_t cap, int64_
         for (uint32_t q = 0; q < S.n(OT_T5, s); ++q) {
             const size_t i = (size_t)s * S.rc[OT_T5] + q;
             if (slot[m0[i]] < lo_slot || slot[m0[i]] >= hi_slot) continue;
-            if (out && k < cap) out[k] = sc[i];
+            if (out && k < cap) out[k] = val[i];
             ++k;
         }
     if (n_out) *n_out = k;
     if (k > cap)
-        return fail(c, LST_E_CAPACITY, "%lld scores, capacity %lld", (long long)k, (long long)cap);
+        return fail(c, LST_E_CAPACITY, "%lld %s, capacity %lld", (long long)k, what, (long long)cap);
     return LST_OK;
+}
+
+extern "C" {
+
+int lst_get_t5_scores(lst_ctx *c, int32_t event, float *out, int64_t cap, int64_t *n_out,
+                      void *stream)
+{
+    return t5_field(c, event, c ? c->E.t5_score : nullptr, out, cap, n_out, stream, "scores");
+}
+
+int lst_get_t5_logits(lst_ctx *c, int32_t event, float *logits, uint8_t *veto, int64_t cap,
+                      int64_t *n_out, void *stream)
+{
+    if (!c) return LST_E_INVALID;
+    if (c->stage < 7 && c->stage != 6) return fail(c, LST_E_STATE, "quintuplets have not run");
+    int rc = t5_field(c, event, c->E.t5_logit, logits, cap, n_out, stream, "logits");
+    if (rc) return rc;
+    return t5_field(c, event, c->E.t5_veto, veto, cap, n_out, stream, "vetoes");
 }
 
 }  // extern "C"
@@ -988,7 +1156,7 @@ static int timed_chain(lst_ctx *c, hipStream_t s, hipEvent_t *ev, double *stage_
     HIPCHK(c, hipEventRecord(ev[0], s));
     if (c->tune.persistent) {
         HIPCHK(c, launch_chain_persistent(c->E, c->M, c->K, c->zero_base, c->zero_bytes,
-                                          c->tune.blocks_per_cu * c->n_cu, s));
+                                          c->tune.blocks_per_cu * c->n_cu, false, s));
         HIPCHK(c, hipEventRecord(ev[ST_COUNT], s));
     } else {
         const Tuning &t = c->tune;

@@ -105,10 +105,28 @@ hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, int grid
 hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s);
 hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s);
 hipError_t launch_dedup(const EvDev &E, const ModDev &M, int grid, hipStream_t s);
+// stop_before_dedup: end the persistent kernel after the quintuplet stage
 hipError_t launch_chain_persistent(const EvDev &E, const ModDev &M, const Consts &K,
-                                   void *zero_base, size_t zero_bytes, int grid, hipStream_t s);
+                                   void *zero_base, size_t zero_bytes, int grid,
+                                   bool stop_before_dedup, hipStream_t s);
 int persistent_blocks_per_cu();
 hipError_t launch_t5_features(const EvDev &E, const Consts &K, int grid, hipStream_t s);
+
+// learned quintuplet scorer (lst_mlp.hip)
+constexpr int MLP_NIN = 40, MLP_NH = 64;
+constexpr int MLP_NPARAM = MLP_NH * MLP_NIN + MLP_NH + MLP_NH * MLP_NH + MLP_NH + MLP_NH + 1;
+size_t mlp_workspace_bytes(int64_t n);
+hipError_t mlp_prepare(const float *F, const float *mean, const float *istd, int64_t n, uint16_t *X,
+                       hipStream_t s);
+hipError_t mlp_forward(const float *P, const uint16_t *X, int64_t n, float *logits, uint16_t *h1,
+                       float *h2, hipStream_t s);
+hipError_t mlp_backward(const float *P, const uint16_t *X, const uint8_t *y, int64_t n,
+                        const float *logits, const uint16_t *h1, const float *h2, float *work,
+                        float *grad, float *loss, hipStream_t s);
+hipError_t mlp_adam(float *P, const float *grad, float *m, float *v, float lr, float b1, float b2,
+                    float eps, float c1, float c2, hipStream_t s);
+hipError_t mlp_score(const EvDev &E, const Consts &K, const float *P, const float *mean,
+                     const float *istd, float threshold, int grid, hipStream_t s);
 
 // Launch shape of every stage (blocks of BLOCK threads); chosen by the tuner.
 enum StageId { ST_SORT = 0, ST_MD, ST_SEG, ST_T3, ST_T5, ST_DEDUP, ST_COUNT };

@@ -17,6 +17,7 @@
 // serialised across the chip (measured ~0.1 us apiece through 16 counters),
 // so per-object or per-wave atomics on a shared counter cost more than the
 // whole stage.
+#include "lst_access.hpp"
 #include "lst_cuts.hpp"
 
 namespace lst {
@@ -120,11 +121,6 @@ __device__ __forceinline__ uint32_t block_reserve(uint32_t wave_total, const EvD
     return off;
 }
 
-__device__ __forceinline__ bool upstream_overflow(const EvDev &E)
-{
-    return E.gc[GC_OVERFLOW] != 0u;
-}
-
 // ---------------------------------------------------------------- zero fill
 __device__ __forceinline__ void zero_body(uint4 *p, size_t n16)
 {
@@ -162,7 +158,7 @@ hipError_t launch_copy(void *dst, const void *src, size_t n_bytes, hipStream_t s
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- a0: hit grouping
+// ---------------------------------------------------------------- hit grouping
 __device__ __forceinline__ int event_of(const int32_t *off, int n_ev, int32_t h)
 {
     int lo = 0, hi = n_ev - 1;
@@ -329,7 +325,7 @@ struct SmChain {
     uint32_t pre[NSH + 1];
 };
 
-// ---------------------------------------------------------------- a1: mini-doublets
+// ---------------------------------------------------------------- mini-doublets
 __device__ __forceinline__ ModF load_mod(const ModDev &M, int m)
 {
     ModF f;
@@ -453,7 +449,7 @@ hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, int grid,
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- a2: segments
+// ---------------------------------------------------------------- segments
 // Outer candidates of inner MD i: the MDs of every map edge of its module,
 // in edge order.  sink(ok, o, pos)
 template <class F>
@@ -549,7 +545,7 @@ hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, int grid
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- a3: triplets
+// ---------------------------------------------------------------- triplets
 // Candidates of inner MD a: every segment (a->b) followed by every segment
 // (b->c).  sink(ok, b, c, k, pos)
 template <class F>
@@ -652,7 +648,7 @@ hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, int grid,
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- a4: quintuplets
+// ---------------------------------------------------------------- quintuplets
 // Candidates of inner MD a: every triplet (a,b,c) followed by every triplet
 // (c,d,e).  sink(ok, b, c, d, e, score, pos)
 template <class F>
@@ -764,60 +760,16 @@ hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, int grid,
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- a5: duplicate removal
+// ---------------------------------------------------------------- duplicate removal
 // A quintuplet survives iff for each of its hits it has the smallest key
 // (score, hit tuple) among the quintuplets using that hit.  Scores are
 // non-negative, so their bit patterns order like the floats.  Quintuplets
 // reaching a hit's minimum score are recorded in TIE_SLOTS per-hit slots:
 // exact score ties are common (two quintuplets that differ only in the
 // upper hit of one mini-doublet have the same anchors, hence the same
-// score) and are resolved by the hit tuple.
-__device__ __forceinline__ int32_t t5_md(const EvDev &E, int32_t t, int j)
-{
-    switch (j) {
-    case 0: return E.t5_md0[t];
-    case 1: return E.t5_md1[t];
-    case 2: return E.t5_md2[t];
-    case 3: return E.t5_md3[t];
-    default: return E.t5_md4[t];
-    }
-}
-
-__device__ __forceinline__ int32_t t5_hit(const EvDev &E, int32_t t, int j)
-{
-    const int32_t md = t5_md(E, t, j >> 1);
-    return (j & 1) ? E.md_hup[md] : E.md_hlo[md];
-}
-
-// Compact index over the stored quintuplets: the block keeps the prefix of
-// the NSH region sizes in LDS; a thread maps v to its array index with a
-// binary search over it.
-__device__ __forceinline__ uint32_t t5_prefix(const EvDev &E, uint32_t *s_pre)
-{
-    if (threadIdx.x == 0) {
-        const uint32_t rc = E.rc[OT_T5];
-        uint32_t acc = 0;
-        for (int r = 0; r < NSH; ++r) {
-            s_pre[r] = acc;
-            const uint32_t c = E.gc[GC_SH + OT_T5 * NSH + r];
-            acc += c < rc ? c : rc;
-        }
-        s_pre[NSH] = acc;
-    }
-    __syncthreads();
-    return s_pre[NSH];
-}
-
-__device__ __forceinline__ int32_t t5_at(const EvDev &E, const uint32_t *s_pre, uint32_t v)
-{
-    int lo = 0, hi = NSH - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_pre[mid] <= v) lo = mid; else hi = mid - 1;
-    }
-    return (int32_t)((uint32_t)lo * E.rc[OT_T5] + (v - s_pre[lo]));
-}
-
+// score) and are resolved by the hit tuple.  A quintuplet vetoed by the
+// learned scorer takes no part.
+//
 // one thread per (quintuplet, hit)
 __device__ __forceinline__ void dedup_min_body(const EvDev &E, uint32_t *s_pre)
 {
@@ -1011,7 +963,7 @@ __global__ void k_bar_reset(uint32_t *bar)
 }
 
 __global__ __launch_bounds__(BLOCK) void k_chain(EvDev E, ModDev M, Consts K, uint4 *zero_base,
-                                                 size_t zero16)
+                                                 size_t zero16, int stop_before_dedup)
 {
     __shared__ SmChain sm;
     uint32_t gen = 0;
@@ -1036,6 +988,7 @@ __global__ __launch_bounds__(BLOCK) void k_chain(EvDev E, ModDev M, Consts K, ui
     t3_body(E, K, sm.u.t3);
     LST_SYNC();
     t5_body(E, K, sm.u.t5);
+    if (stop_before_dedup) return;
     LST_SYNC();
     dedup_min_body(E, sm.pre);
     LST_SYNC();
@@ -1053,11 +1006,12 @@ int persistent_blocks_per_cu()
 }
 
 hipError_t launch_chain_persistent(const EvDev &E, const ModDev &M, const Consts &K,
-                                   void *zero_base, size_t zero_bytes, int grid, hipStream_t s)
+                                   void *zero_base, size_t zero_bytes, int grid,
+                                   bool stop_before_dedup, hipStream_t s)
 {
     hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, s, E.bar);
     hipLaunchKernelGGL(k_chain, dim3(grid), dim3(BLOCK), 0, s, E, M, K, (uint4 *)zero_base,
-                       zero_bytes / 16);
+                       zero_bytes / 16, stop_before_dedup ? 1 : 0);
     return hipGetLastError();
 }
 

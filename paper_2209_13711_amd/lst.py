@@ -22,6 +22,8 @@ LST_MD, LST_SEG, LST_T3, LST_T5, LST_T5_KEPT = 0, 1, 2, 3, 4
 WIDTH = {LST_MD: 2, LST_SEG: 4, LST_T3: 6, LST_T5: 10, LST_T5_KEPT: 10}
 LST_N_PARAMS = 14
 LST_MOD_NF, LST_MOD_NI = 21, 4
+LST_MODE_CUTS, LST_MODE_MLP = 0, 1
+LST_MLP_NFEAT, LST_MLP_NPARAM = 40, 6849
 
 
 class lst_caps(ctypes.Structure):
@@ -80,6 +82,18 @@ _SIGS = {
     "lst_set_tuning": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32]),
     "lst_get_tuning": (ctypes.c_int, [_P, _P]),
     "lst_tune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_int32, _P, _P]),
+    "lst_mlp_load": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.c_float]),
+    "lst_set_mode": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "lst_run_t5_score": (ctypes.c_int, [_P, _P]),
+    "lst_get_t5_logits": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_int64), _P]),
+    "lst_mlp_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
+    "lst_mlp_prepare": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, _P, _P]),
+    "lst_mlp_forward": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P, _P, _P]),
+    "lst_mlp_backward": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, _P, _P, _P, _P,
+                                        ctypes.c_size_t, _P, _P, _P]),
+    "lst_mlp_adam": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -319,6 +333,70 @@ class Context:
         self._check(self.lib.lst_get_t5_scores(self.h, event, _np_ptr(out), n.value,
                                                ctypes.byref(n), self._stream(stream)))
         return out[:n.value]
+
+    # -- learned scorer -----------------------------------------------------
+    def mlp_load(self, params, mean, istd, threshold=0.0):
+        p = np.ascontiguousarray(params, np.float32)
+        m = np.ascontiguousarray(mean, np.float32)
+        s = np.ascontiguousarray(istd, np.float32)
+        self._check(self.lib.lst_mlp_load(self.h, _np_ptr(p), len(p), _np_ptr(m), _np_ptr(s),
+                                          float(threshold)))
+
+    def set_mode(self, mode):
+        self._check(self.lib.lst_set_mode(self.h, int(mode)))
+
+    def run_t5_score(self, stream=None):
+        self._check(self.lib.lst_run_t5_score(self.h, self._stream(stream)))
+
+    def t5_logits(self, event, stream=None):
+        """(logits float32, veto bool) in lst_get_objects(LST_T5) order"""
+        n = ctypes.c_int64(0)
+        rc = self.lib.lst_get_t5_logits(self.h, event, None, None, 0, ctypes.byref(n),
+                                        self._stream(stream))
+        if rc not in (LST_OK, LST_E_CAPACITY):
+            self._check(rc)
+        lg = np.zeros(max(n.value, 1), np.float32)
+        vt = np.zeros(max(n.value, 1), np.uint8)
+        self._check(self.lib.lst_get_t5_logits(self.h, event, _np_ptr(lg), _np_ptr(vt), n.value,
+                                               ctypes.byref(n), self._stream(stream)))
+        return lg[:n.value], vt[:n.value].astype(bool)
+
+    # training calls: device tensors, asynchronous on the stream
+    @staticmethod
+    def _dev(t, dtype):
+        assert t.is_cuda and t.is_contiguous() and t.dtype == dtype, (t.dtype, dtype)
+        return ctypes.c_void_p(t.data_ptr())
+
+    def mlp_workspace_bytes(self, n):
+        return int(self.lib.lst_mlp_workspace_bytes(int(n)))
+
+    def mlp_prepare(self, feat, mean, istd, x, stream=None):
+        d = self._dev
+        self._check(self.lib.lst_mlp_prepare(self.h, d(feat, torch.float32), d(mean, torch.float32),
+                                             d(istd, torch.float32), feat.shape[0],
+                                             d(x, torch.int16), self._stream(stream)))
+
+    def mlp_forward(self, params, x, logits, h1=None, h2=None, stream=None):
+        d = self._dev
+        self._check(self.lib.lst_mlp_forward(
+            self.h, d(params, torch.float32), d(x, torch.int16), x.shape[0],
+            d(logits, torch.float32), None if h1 is None else d(h1, torch.int16),
+            None if h2 is None else d(h2, torch.float32), self._stream(stream)))
+
+    def mlp_backward(self, params, x, y, logits, h1, h2, work, grad, loss, stream=None):
+        d = self._dev
+        self._check(self.lib.lst_mlp_backward(
+            self.h, d(params, torch.float32), d(x, torch.int16), d(y, torch.uint8), x.shape[0],
+            d(logits, torch.float32), d(h1, torch.int16), d(h2, torch.float32),
+            d(work, torch.uint8), work.numel(), d(grad, torch.float32), d(loss, torch.float32),
+            self._stream(stream)))
+
+    def mlp_adam(self, params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        d = self._dev
+        self._check(self.lib.lst_mlp_adam(self.h, d(params, torch.float32), d(grad, torch.float32),
+                                          d(m, torch.float32), d(v, torch.float32), int(step),
+                                          float(lr), float(beta1), float(beta2), float(eps),
+                                          self._stream(stream)))
 
     def run_batch(self, offsets, x, y, z, module, sensor, stream=None, max_retry=8, graph=False):
         """Load, run the chain and grow the arena to the reported need on overflow
