@@ -2,8 +2,9 @@
 
 Plain NumPy, FP64 unless stated.  Only the test suite, the smoke check and the
 CPU-baseline leg of the benchmark use it; the HIP library shares no code with
-it.  The scorer is not part of the paper (its outlook only mentions learned
-methods); what it computes is fixed here by its definition:
+it.  The scorer is not part of the paper (its Summary and Outlook section
+plans to revisit the object selection for efficiency and fake rate); what it
+computes is fixed here by its definition:
 
 * network 40 -> 64 -> 64 -> 1, ReLU after both hidden layers, a logit out;
   accept a candidate iff logit >= threshold (probability = sigmoid(logit));
