@@ -24,6 +24,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 30
+# multiply-adds of the scorer per candidate: 64x64 (K padded) + 64x64 + 64
+MLP_FLOPS = 2 * (64 * 64 + 64 * 64 + 64)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_seg_pu200_traffic.txt")
 
 
@@ -32,7 +34,7 @@ def kernel_source_digest():
     source are not reported."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("lst_kernels.hip", "lst_cuts.hpp", "lst_internal.hpp"):
+    for f in ("lst_kernels.hip", "lst_cuts.hpp", "lst_internal.hpp", "lst_access.hpp"):
         with open(os.path.join(ROOT, "paper_2209_13711_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -150,6 +152,101 @@ def batched(lst, torch, E, G, PR, n_events=64, steps=20):
             "tuner_report_us": tuned["report_us"], "t5_kept": int(kept)}
 
 
+def _gen_train(e):
+    from synth import events as E
+    return E.generate(4, e, purpose=E.PURPOSE_TRAIN, cfg=E.scorer_training_config(E.CONFIGS[4]))
+
+
+def _gen_eval(e):
+    from synth import events as E
+    return E.generate(4, e)
+
+
+def scorer_events(n_train=150, n_eval=8):
+    """training and held-out events of the scorer, generated by a pool of
+    CPU workers before this process touches the GPU"""
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        return pool.map(_gen_train, range(n_train)), pool.map(_gen_eval, range(n_eval))
+
+
+def scored(lst, torch, train, evs, steps=50):
+    """Learned scorer end to end on the GPU: quintuplets of the training
+    events (widened windows) labelled by truth, trained by the library's
+    kernels, threshold keeping 99 % of true candidates; then the plain chain
+    at nominal windows against the widened chain + scorer on held-out
+    4000-helix events (efficiency / fake rate by truth, events/s of one
+    event per hipGraph replay)."""
+    from paper_2209_13711_amd import scorer as S
+    from synth import events as E, geometry as G, params as PR, weights as W
+    geo = G.get("barrel_toy")
+    w_train = E.scorer_training_config(E.CONFIGS[4]).window
+    ctx_w = lst.Context(PR.make(w=w_train), geo.f32, geo.i32, device=0)
+    t0 = time.perf_counter()
+    F, y = S.collect(ctx_w, train)
+    t_collect = time.perf_counter() - t0
+    cfg = S.TrainConfig(epochs=10)
+    tr = S.Trainer(ctx_w, F, y, W.random_params(np.random.default_rng(0)), cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = tr.fit()
+    t_train = time.perf_counter() - t0
+    th = S.threshold_for(tr.logits_all(), tr.labels(), 0.99)
+    plain_ctx = lst.Context(PR.make(), geo.f32, geo.i32, device=0)
+    scored_ctx = lst.Context(PR.make(w=w_train), geo.f32, geo.i32, device=0)
+    scored_ctx.mlp_load(tr.params(), tr.mean, tr.istd, th)
+    scored_ctx.set_mode(lst.LST_MODE_MLP)
+    m_plain = S.evaluate(plain_ctx, evs, geo)
+    m_scored = S.evaluate(scored_ctx, evs, geo)
+    stream = torch.cuda.current_stream()
+
+    def rate(ctx):
+        per = []
+        for ev in evs:
+            ctx.load_hits(np.array([0, ev.n_hits], np.int32), ev.x, ev.y, ev.z, ev.module, ev.sensor)
+            for _ in range(3):
+                ctx.run_chain_graph(stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ctx.run_chain_graph(stream)
+            torch.cuda.synchronize()
+            per.append((time.perf_counter() - t0) / steps)
+        return 1.0 / float(np.mean(per))
+
+    # scoring kernel alone: HIP events around the stage on the launch stream
+    ev = evs[0]
+    scored_ctx.load_hits(np.array([0, ev.n_hits], np.int32), ev.x, ev.y, ev.z, ev.module, ev.sensor)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = []
+    for _ in range(20):
+        for fn in (scored_ctx.run_sort, scored_ctx.run_md, scored_ctx.run_segments,
+                   scored_ctx.run_triplets, scored_ctx.run_quintuplets):
+            fn(stream)
+        e0.record(stream)
+        scored_ctx.run_t5_score(stream)
+        e1.record(stream)
+        scored_ctx.run_dedup(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    n_t5 = scored_ctx.counts(0)["n_t5"]
+    score_us = 1e3 * float(np.median(ms[5:]))
+    flops = n_t5 * MLP_FLOPS
+    return {"workload": "scorer trained on quintuplets of 150 training events (barrel toy, "
+                        "20 x Poisson(U(50,250)) helices, windows x1.5), evaluated on 8 held-out "
+                        "4000-helix events (config 4)",
+            "train_candidates": int(len(y)), "train_true_frac": float(y.mean()),
+            "collect_s": t_collect, "train_s": t_train, "epochs": cfg.epochs,
+            "train_candidates_per_s": tr.n_batches * tr.b * cfg.epochs / t_train,
+            "loss_first_last": [losses[0], losses[-1]], "threshold": th,
+            "plain_w1": {k: m_plain[k] for k in ("eff", "fake", "dup", "impure", "n_obj")},
+            "scored_w1.5": {k: m_scored[k] for k in ("eff", "fake", "dup", "impure", "n_obj")},
+            "plain_events_per_s": rate(plain_ctx), "scored_events_per_s": rate(scored_ctx),
+            "score_kernel": {"kernel": "k_mlp_score", "duration_us": score_us, "quintuplets": int(n_t5),
+                             "bound": "mfma", "achieved_TFLOPs": flops / (score_us * 1e-6) / 1e12,
+                             "peak_TFLOPs": 2500.0}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,11 +254,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-event batch figures")
+    ap.add_argument("--no-scorer", action="store_true", help="skip the learned-scorer figures")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); events are "
               "independent, see DESIGN.md for how the batch would shard", file=sys.stderr)
         sys.exit(2)
+
+    if not args.no_scorer:
+        sc_train, sc_eval = scorer_events()
 
     import torch
     import paper_2209_13711_amd as lst
@@ -259,6 +360,8 @@ def main():
     }
     if not args.no_batch:
         out["batched"] = batched(lst, torch, E, G, PR)
+    if not args.no_scorer:
+        out["scored"] = scored(lst, torch, sc_train, sc_eval)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(params, geo)
     print(json.dumps(out), flush=True)

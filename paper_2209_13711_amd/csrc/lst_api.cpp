@@ -175,6 +175,10 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.hmin = cv.take<uint32_t>(k.hits);
     E.htie = cv.take<int32_t>(k.hits);
     E.hslot = cv.take<int32_t>((size_t)k.hits * TIE_SLOTS);
+    E.thead = cv.take<int32_t>(k.hits);
+    E.cap_tpool = (uint32_t)std::max<int64_t>(4096, k.t5 / 8);
+    E.tpool_t5 = cv.take<int32_t>(E.cap_tpool);
+    E.tpool_next = cv.take<int32_t>(E.cap_tpool);
     // MD
     E.md_hlo = cv.take<int32_t>(nmd);
     E.md_hup = cv.take<int32_t>(nmd);

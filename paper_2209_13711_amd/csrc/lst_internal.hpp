@@ -30,6 +30,7 @@ enum GlobalCounter {
     GC_OVERFLOW = 0,   // bit k: object type k ran out of its region
     GC_ERROR,          // bit 0: invalid hit skipped
     GC_N_SORTED,       // number of grouped hits
+    GC_TIEPOOL,        // entries taken from the dedup tie pool
     GC_SH = 8,         // [OT_COUNT][NSH] reservation shards
     GC_COUNT = GC_SH + OT_COUNT * NSH
 };
@@ -66,6 +67,9 @@ struct EvDev {
     uint32_t *hmin;          // dedup: smallest quintuplet score bits per sorted hit
     int32_t *htie;           // dedup: how many quintuplets reach that score
     int32_t *hslot;          // dedup: [n_hits][TIE_SLOTS] quintuplets reaching it
+    int32_t *thead;          // dedup: per hit, 1 + first pool entry of further ties (0: none)
+    int32_t *tpool_t5, *tpool_next;  // dedup tie pool: quintuplet, 1 + next entry
+    uint32_t cap_tpool;
     // mini-doublets
     int32_t *md_hlo, *md_hup, *md_slot;
     float *md_x, *md_y, *md_z, *md_r, *md_a, *md_ca, *md_dx, *md_dy, *md_dn, *md_bend, *md_sv;

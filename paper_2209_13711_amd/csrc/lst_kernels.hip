@@ -286,6 +286,7 @@ __device__ __forceinline__ void scatter_body(const EvDev &E, int n_mod)
         E.sorig[pos] = h - E.hit_off[ev];
         E.hmin[pos] = 0xffffffffu;
         E.htie[pos] = 0;
+        E.thead[pos] = 0;
     }
 }
 
@@ -792,7 +793,16 @@ __device__ __forceinline__ void dedup_tie_body(const EvDev &E, uint32_t *s_pre)
         const int32_t h = t5_hit(E, t, (int)(v % 10u));
         if (E.hmin[h] == __float_as_uint(E.t5_score[t])) {
             const int k = atomicAdd(&E.htie[h], 1);
-            if (k < TIE_SLOTS) E.hslot[(size_t)h * TIE_SLOTS + k] = t;
+            if (k < TIE_SLOTS) {
+                E.hslot[(size_t)h * TIE_SLOTS + k] = t;
+            } else {
+                // further ties: push onto the hit's list in the pool
+                const uint32_t s = atomicAdd(&E.gc[GC_TIEPOOL], 1u);
+                if (s < E.cap_tpool) {
+                    E.tpool_t5[s] = t;
+                    E.tpool_next[s] = atomicExch(&E.thead[h], (int32_t)s + 1);
+                }
+            }
         }
     }
 }
@@ -835,13 +845,20 @@ __device__ __forceinline__ void dedup_keep_body(const EvDev &E, uint32_t *s_pre)
         for (int j = 0; j < 10; ++j) keep = keep && (hm[j] == key);
         for (int j = 0; j < 10 && keep; ++j) {
             if (nt[j] <= 1) continue;
-            if (nt[j] <= TIE_SLOTS) {
-                for (int k = 0; k < nt[j] && keep; ++k) {
-                    const int32_t u = E.hslot[(size_t)h[j] * TIE_SLOTS + k];
-                    if (u != t && tuple_less(E, u, t)) keep = false;
-                }
-            } else {
-                // more tied quintuplets than slots: scan them all (rare)
+            const int ns = nt[j] < TIE_SLOTS ? nt[j] : TIE_SLOTS;
+            for (int k = 0; k < ns && keep; ++k) {
+                const int32_t u = E.hslot[(size_t)h[j] * TIE_SLOTS + k];
+                if (u != t && tuple_less(E, u, t)) keep = false;
+            }
+            if (nt[j] <= TIE_SLOTS || !keep) continue;
+            // further ties are chained in the pool
+            int listed = 0;
+            for (int32_t e = E.thead[h[j]]; e != 0 && keep; e = E.tpool_next[e - 1], ++listed) {
+                const int32_t u = E.tpool_t5[e - 1];
+                if (u != t && tuple_less(E, u, t)) keep = false;
+            }
+            if (keep && listed < nt[j] - TIE_SLOTS) {
+                // the pool ran out: scan every quintuplet (correct, slow)
                 for (uint32_t q = 0; q < n && keep; ++q) {
                     const int32_t u = t5_at(E, s_pre, q);
                     if (u == t || E.t5_score[u] != sc) continue;

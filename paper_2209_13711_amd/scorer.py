@@ -27,7 +27,8 @@ def pure_labels(tuples: np.ndarray, truth: np.ndarray) -> np.ndarray:
 
 def collect(ctx: "L.Context", events, stream=None):
     """Features (FP32 [N, 40], computed by the chain on the GPU) and truth
-    labels of every quintuplet the chain stores for `events`."""
+    labels of every quintuplet the chain stores for `events`, in a
+    reproducible order."""
     feats, labels = [], []
     for ev in events:
         if ctx.caps is None or not ctx.caps.get("features"):
@@ -39,8 +40,11 @@ def collect(ctx: "L.Context", events, stream=None):
         ctx.run_t5_features(stream)
         f = ctx.t5_features(0, stream)
         t5 = ctx.objects(0, L.LST_T5, stream)
-        feats.append(f)
-        labels.append(pure_labels(t5, ev.truth))
+        # canonical order (by hit tuple): the device stores quintuplets in
+        # whatever order its blocks finish, the training set must not depend on it
+        o = np.lexsort(t5.T[::-1]) if len(t5) else np.zeros(0, np.int64)
+        feats.append(f[o])
+        labels.append(pure_labels(t5[o], ev.truth))
     return np.concatenate(feats), np.concatenate(labels)
 
 
@@ -152,10 +156,9 @@ def threshold_for(logits: np.ndarray, labels: np.ndarray, keep_true: float) -> f
 
 
 def training_config(base):
-    """Events of the scorer's training set: the base configuration's
-    detector and spectra, pileup Poisson(U(50, 250)) x 20 helices, windows
-    widened 1.5x so that the chain keeps hard wrong candidates to learn from."""
-    return dataclasses.replace(base, pileup_range=(50, 250), window=1.5)
+    """the training-set recipe (see synth.events.scorer_training_config)"""
+    from synth.events import scorer_training_config
+    return scorer_training_config(base)
 
 
 def evaluate(ctx: "L.Context", events, geo, stream=None) -> dict:

@@ -13,7 +13,7 @@ stream per (config, event, purpose) built with ``SeedSequence``.
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -57,6 +57,13 @@ CONFIGS = {
     5: EventConfig(5, "barrel_toy", 16, 6000, "logu", 1.0, 10.0, 0.8, noise_frac=0.10,
                    displaced_frac=0.05, window=1.5),
 }
+
+
+def scorer_training_config(base: EventConfig) -> EventConfig:
+    """Events of the learned scorer's training set: the base configuration's
+    detector and spectra, pileup Poisson(U(50, 250)) x 20 helices, and cut
+    windows widened 1.5x so that the chain keeps hard wrong candidates."""
+    return replace(base, pileup_range=(50, 250), window=1.5)
 
 
 @dataclass

@@ -264,3 +264,27 @@ def test_t5_features_bitwise(cid, n_tracks):
     assert len(tup) == len(omap) > 50
     for t, f in zip(tup.tolist(), feat.view(np.uint32)):
         np.testing.assert_array_equal(f, omap[tuple(t)])
+
+
+def test_dedup_with_many_score_ties_matches_oracle():
+    """Upper hits of 20 tracks duplicated in place: every mini-doublet of
+    those tracks has two upper-hit choices with identical coordinates, so up
+    to 32 quintuplets share one score and their hits (more ties per hit than
+    the inline slots hold); the survivor is decided by the hit tuple."""
+    import paper_2209_13711_amd as lst
+    geo = G.get("barrel_toy")
+    params = PR.make()
+    ev = E.generate(1, 0)
+    sel = np.flatnonzero((ev.sensor == 1) & (ev.truth >= 0) & (ev.truth < 20))
+    arrs = [np.concatenate([a, a[sel]]) for a in (ev.x, ev.y, ev.z, ev.module, ev.sensor)]
+    print(f"case tie-heavy event hits {len(arrs[0])}", flush=True)
+    ref = oracle.Oracle(params, geo.f32, geo.i32).run(*arrs)
+    ctx = lst.Context(params, geo.f32, geo.i32, device=0)
+    offs = np.array([0, len(arrs[0])], np.int32)
+    for run in ("chain", "persistent"):
+        ctx.run_batch(offs, *arrs)
+        if run == "persistent":
+            ctx.run_chain_persistent()
+        for kind in (lst.LST_T5, lst.LST_T5_KEPT):
+            got = {tuple(t) for t in ctx.objects(0, kind).tolist()}
+            assert got == {tuple(t) for t in ref.tuples[kind].tolist()}, (run, kind)
