@@ -24,8 +24,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 30
-# multiply-adds of the scorer per candidate: 64x64 (K padded) + 64x64 + 64
-MLP_FLOPS = 2 * (64 * 64 + 64 * 64 + 64)
+# algorithmic FLOPs of the scorer per candidate (40x64 + 64x64 + 64 multiply-adds)
+MLP_FLOPS = 2 * (40 * 64 + 64 * 64 + 64)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_seg_pu200_traffic.txt")
 
 
@@ -317,6 +317,17 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
+    # the same chain with the hits handed over from host memory each step
+    # (pageable numpy arrays through lst_load_hits): PCIe-inclusive rate
+    n_pcie = max(args.steps // 4, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n_pcie):
+        ctx.load_hits(offs, ev.x, ev.y, ev.z, ev.module, ev.sensor, stream)
+        ctx.run_chain_graph(stream)
+    torch.cuda.synchronize()
+    pcie_rate = n_pcie / (time.perf_counter() - t0)
+
     stage_ms = {name: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1])
                                      for k in range(args.steps)]))
                 for i, (name, _) in enumerate(stages)}
@@ -349,6 +360,7 @@ def main():
         "candidates_per_s": cands * value,
         "stage_ms": stage_ms,
         "eager_events_per_s": args.steps / dt_eager,
+        "pcie_inclusive_events_per_s": pcie_rate,
         "objects": {k: int(cnt[k]) for k in ("n_md", "n_seg", "n_t3", "n_t5", "n_t5_kept")},
         "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
