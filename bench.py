@@ -148,7 +148,7 @@ def batched(lst, torch, E, G, PR, n_events=64, steps=20):
             "ms_per_batch": 1e3 * t_graph,
             "persistent_events_per_s": n_events / t_pers,
             "one_event_per_launch_events_per_s": 1.0 / t_single,
-            "tuning": {k: tuned[k] for k in ("grid", "persistent", "blocks_per_cu")},
+            "tuning": {k: tuned[k] for k in ("grid", "lanes", "persistent", "blocks_per_cu")},
             "tuner_report_us": tuned["report_us"], "t5_kept": int(kept)}
 
 

@@ -106,7 +106,9 @@ typedef struct {
  * ran out of capacity (LST_E_CAPACITY) the arrays are incomplete and every
  * event reports instead the batch-wide number of MD/SEG/T3/T5 required.  overflow_mask bit k = stage k (MD, SEG,
  * T3, T5) ran out of capacity; error_flags bit 0 = a hit with an invalid
- * module or sensor id was skipped. */
+ * module or sensor id was skipped, bit 1 = a persistent-chain barrier timed
+ * out, bit 2 = the hit-grouping scan timed out waiting for a predecessor tile
+ * (neither should ever happen; the outputs are then unusable). */
 typedef struct {
     int64_t n_hits, n_md, n_seg, n_t3, n_t5, n_t5_kept;
     int64_t cand_md, cand_seg, cand_t3, cand_t5;
@@ -215,14 +217,18 @@ int lst_get_t5_scores(lst_ctx *ctx, int32_t event, float *out_host, int64_t cap,
 int lst_run_chain_persistent(lst_ctx *ctx, void *stream);
 
 /* Launch shape: grid6 = blocks of 256 threads for the stages (hit grouping,
- * MD, segments, T3, T5, dedup); persistent = 1 runs the chain as one
- * persistent kernel of blocks_per_cu x CUs blocks.  lst_get_tuning fills
- * out9 = grid6, persistent, blocks_per_cu, number of CUs. */
-int lst_set_tuning(lst_ctx *ctx, const int32_t *grid6, int32_t persistent, int32_t blocks_per_cu);
-int lst_get_tuning(const lst_ctx *ctx, int32_t *out9);
+ * MD, segments, T3, T5, dedup); lanes6 = lanes of the group that owns one
+ * inner object (8, 16, 32 or 64; used by MD, segments, T3, T5, ignored for
+ * the others; NULL keeps the current values); persistent = 1 runs the chain
+ * as one persistent kernel of blocks_per_cu x CUs blocks, whose object
+ * stages all use the segment stage's group width.  lst_get_tuning fills
+ * out15 = grid6, lanes6, persistent, blocks_per_cu, number of CUs. */
+int lst_set_tuning(lst_ctx *ctx, const int32_t *grid6, const int32_t *lanes6, int32_t persistent,
+                   int32_t blocks_per_cu);
+int lst_get_tuning(const lst_ctx *ctx, int32_t *out15);
 
 /* Autotuner over the loaded batch: for each stage in turn, every candidate
- * grid is timed (median of `reps` chains, HIP events on `stream`) and its
+ * grid (and, for the object stages, group width) is timed (median of `reps` chains, HIP events on `stream`) and its
  * outputs checksummed against the default launch shape (a candidate that
  * changes any object fails the call); then the persistent kernel is timed
  * for every co-resident blocks-per-CU value, and the faster of the per-stage

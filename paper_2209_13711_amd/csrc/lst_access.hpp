@@ -38,7 +38,7 @@ __device__ __forceinline__ uint32_t t5_prefix(const EvDev &E, uint32_t *s_pre)
         uint32_t acc = 0;
         for (int r = 0; r < NSH; ++r) {
             s_pre[r] = acc;
-            const uint32_t c = E.gc[GC_SH + OT_T5 * NSH + r];
+            const uint32_t c = E.gc[gc_shard(OT_T5, r)];
             acc += c < rc ? c : rc;
         }
         s_pre[NSH] = acc;

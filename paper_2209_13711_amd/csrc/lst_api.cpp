@@ -142,7 +142,7 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.cap_slots = (int32_t)slots;
     E.cap_keys = (int32_t)keys;
     E.desc = cv.take<int32_t>(D_COUNT);
-    E.bar = cv.take<uint32_t>(64);
+    E.bar = cv.take<uint32_t>(33 * 64);   // 33 barrier counters, one 256-byte line each
     E.cap_hits = k.hits;
     const int64_t caps[OT_COUNT] = {k.md, k.seg, k.t3, k.t5};
     size_t span[OT_COUNT];
@@ -155,6 +155,7 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     size_t z0 = (cv.off + 255) & ~(size_t)255;
     E.gc = cv.take<uint32_t>(GC_COUNT);
     E.bcnt = cv.take<uint32_t>(keys);
+    E.scan_st = cv.take<unsigned long long>((keys + 1 + SCAN_TILE - 1) / SCAN_TILE);
     size_t z1 = (cv.off + 255) & ~(size_t)255;
     if (zero_base) *zero_base = base ? base + z0 : nullptr;
     if (zero_bytes) *zero_bytes = z1 - z0;
@@ -167,7 +168,6 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.hit_off = cv.take<int32_t>(k.events + 1);
     // grouping
     E.boff = cv.take<uint32_t>(keys + 1);
-    E.bsum = cv.take<uint32_t>((keys + 1023) / 1024 + 1);
     E.sx = cv.take<float>(k.hits);
     E.sy = cv.take<float>(k.hits);
     E.sz = cv.take<float>(k.hits);
@@ -218,6 +218,8 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.t5_score = cv.take<float>(nt5);
     E.t5_keep = cv.take<uint8_t>(nt5);
     E.t5_veto = cv.take<uint8_t>(nt5);
+    E.t5_hs = cv.take<int32_t>(nt5 * 10);
+    E.t5_ho = cv.take<int32_t>(nt5 * 10);
     E.t5_feat = k.features ? cv.take<float>(nt5 * 40) : nullptr;
     E.t5_logit = cv.take<float>(nt5);
     return (cv.off + 255) & ~(size_t)255;
@@ -380,17 +382,23 @@ int lst_get_map(lst_ctx *c, int32_t *row_ptr, int32_t *col, int64_t cap_col, int
 static int clamp_grid(int64_t g) { return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65535)); }
 
 // Launch shapes before tuning: one wave per work item up to 2048 blocks.
+// launch shape before tuning: the best measured on a PU200-like event
 static void default_tuning(lst_ctx *c)
 {
     Tuning &t = c->tune;
     t.grid[ST_SORT] = clamp_grid(std::min<int64_t>((c->caps.hits + BLOCK - 1) / BLOCK, GRID_MAX));
-    t.grid[ST_MD] = clamp_grid(std::min<int64_t>(((int64_t)c->E.cap_slots + WAVES - 1) / WAVES, GRID_MAX));
-    t.grid[ST_SEG] = GRID_MAX;
+    t.grid[ST_MD] = GRID_MAX;
+    t.grid[ST_SEG] = 2 * GRID_MAX;
     t.grid[ST_T3] = GRID_MAX;
-    t.grid[ST_T5] = GRID_MAX;
-    t.grid[ST_DEDUP] = 512;
+    t.grid[ST_T5] = 2 * GRID_MAX;
+    t.grid[ST_DEDUP] = 1024;
+    for (int i = 0; i < ST_COUNT; ++i) t.lanes[i] = 64;
+    t.lanes[ST_MD] = 32;
+    t.lanes[ST_SEG] = 32;
+    t.lanes[ST_T3] = 32;
+    t.lanes[ST_T5] = 16;
     t.persistent = 0;
-    t.blocks_per_cu = std::max(1, persistent_blocks_per_cu());
+    t.blocks_per_cu = std::max(1, std::min(2, persistent_blocks_per_cu(t.lanes[ST_SEG])));
 }
 
 int lst_arena_bytes(const lst_ctx *cc, const lst_caps *caps, size_t *bytes)
@@ -514,7 +522,7 @@ int lst_run_md(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 2, "lst_run_md");
     if (rc) return rc;
-    HIPCHK(c, launch_md(c->E, c->M, c->K, c->tune.grid[ST_MD], (hipStream_t)stream));
+    HIPCHK(c, launch_md(c->E, c->M, c->K, c->tune.grid[ST_MD], c->tune.lanes[ST_MD], (hipStream_t)stream));
     c->stage = 3;
     return LST_OK;
 }
@@ -523,7 +531,7 @@ int lst_run_segments(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 3, "lst_run_segments");
     if (rc) return rc;
-    HIPCHK(c, launch_seg(c->E, c->M, c->K, c->tune.grid[ST_SEG], (hipStream_t)stream));
+    HIPCHK(c, launch_seg(c->E, c->M, c->K, c->tune.grid[ST_SEG], c->tune.lanes[ST_SEG], (hipStream_t)stream));
     c->stage = 4;
     return LST_OK;
 }
@@ -532,7 +540,7 @@ int lst_run_triplets(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 4, "lst_run_triplets");
     if (rc) return rc;
-    HIPCHK(c, launch_t3(c->E, c->M, c->K, c->tune.grid[ST_T3], (hipStream_t)stream));
+    HIPCHK(c, launch_t3(c->E, c->M, c->K, c->tune.grid[ST_T3], c->tune.lanes[ST_T3], (hipStream_t)stream));
     c->stage = 5;
     return LST_OK;
 }
@@ -541,7 +549,7 @@ int lst_run_quintuplets(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 5, "lst_run_quintuplets");
     if (rc) return rc;
-    HIPCHK(c, launch_t5(c->E, c->M, c->K, c->tune.grid[ST_T5], (hipStream_t)stream));
+    HIPCHK(c, launch_t5(c->E, c->M, c->K, c->tune.grid[ST_T5], c->tune.lanes[ST_T5], (hipStream_t)stream));
     c->stage = 6;
     return LST_OK;
 }
@@ -710,15 +718,15 @@ static int enqueue_chain(lst_ctx *c, hipStream_t s)
     int rc;
     if (t.persistent) {
         HIPCHK(c, launch_chain_persistent(c->E, c->M, c->K, c->zero_base, c->zero_bytes,
-                                          t.blocks_per_cu * c->n_cu, mlp, s));
+                                          t.blocks_per_cu * c->n_cu, t.lanes[ST_SEG], mlp, s));
         if (!mlp) return LST_OK;
     } else {
         HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, s));
         HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], s));
-        HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], s));
-        HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], s));
-        HIPCHK(c, launch_t3(c->E, c->M, c->K, t.grid[ST_T3], s));
-        HIPCHK(c, launch_t5(c->E, c->M, c->K, t.grid[ST_T5], s));
+        HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], t.lanes[ST_MD], s));
+        HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], t.lanes[ST_SEG], s));
+        HIPCHK(c, launch_t3(c->E, c->M, c->K, t.grid[ST_T3], t.lanes[ST_T3], s));
+        HIPCHK(c, launch_t5(c->E, c->M, c->K, t.grid[ST_T5], t.lanes[ST_T5], s));
     }
     if (mlp && (rc = enqueue_score(c, s))) return rc;
     HIPCHK(c, launch_dedup(c->E, c->M, t.grid[ST_DEDUP], s));
@@ -729,11 +737,12 @@ int lst_run_chain_persistent(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 1, "lst_run_chain_persistent");
     if (rc) return rc;
-    const int bpc = std::max(1, std::min(c->tune.blocks_per_cu, persistent_blocks_per_cu()));
+    const int bpc =
+        std::max(1, std::min(c->tune.blocks_per_cu, persistent_blocks_per_cu(c->tune.lanes[ST_SEG])));
     const bool mlp = c->mode == LST_MODE_MLP;
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(c, launch_chain_persistent(c->E, c->M, c->K, c->zero_base, c->zero_bytes,
-                                      bpc * c->n_cu, mlp, s));
+                                      bpc * c->n_cu, c->tune.lanes[ST_SEG], mlp, s));
     if (mlp) {
         if ((rc = enqueue_score(c, s))) return rc;
         HIPCHK(c, launch_dedup(c->E, c->M, c->tune.grid[ST_DEDUP], s));
@@ -752,29 +761,41 @@ int lst_run_t5_features(lst_ctx *c, void *stream)
     return LST_OK;
 }
 
-int lst_set_tuning(lst_ctx *c, const int32_t *grid6, int32_t persistent, int32_t blocks_per_cu)
+static bool lanes_ok(int v) { return v == 8 || v == 16 || v == 32 || v == 64; }
+
+int lst_set_tuning(lst_ctx *c, const int32_t *grid6, const int32_t *lanes6, int32_t persistent,
+                   int32_t blocks_per_cu)
 {
     if (!c || !grid6) return LST_E_INVALID;
     if (!c->arena) return fail(c, LST_E_STATE, "no arena attached");
-    const int occ = persistent_blocks_per_cu();
-    if (blocks_per_cu < 1 || blocks_per_cu > occ)
-        return fail(c, LST_E_INVALID, "blocks_per_cu %d outside 1..%d (co-residency)", blocks_per_cu, occ);
     for (int i = 0; i < ST_COUNT; ++i)
         if (grid6[i] < 1 || grid6[i] > 65535) return fail(c, LST_E_INVALID, "grid[%d] = %d", i, grid6[i]);
-    for (int i = 0; i < ST_COUNT; ++i) c->tune.grid[i] = grid6[i];
+    if (lanes6)
+        for (int i = 0; i < ST_COUNT; ++i)
+            if (!lanes_ok(lanes6[i])) return fail(c, LST_E_INVALID, "lanes[%d] = %d", i, lanes6[i]);
+    const int occ = persistent_blocks_per_cu(lanes6 ? lanes6[ST_SEG] : c->tune.lanes[ST_SEG]);
+    if (blocks_per_cu < 1 || blocks_per_cu > occ)
+        return fail(c, LST_E_INVALID, "blocks_per_cu %d outside 1..%d (co-residency)", blocks_per_cu, occ);
+    for (int i = 0; i < ST_COUNT; ++i) {
+        c->tune.grid[i] = grid6[i];
+        if (lanes6) c->tune.lanes[i] = lanes6[i];
+    }
     c->tune.persistent = persistent ? 1 : 0;
     c->tune.blocks_per_cu = blocks_per_cu;
     drop_graph(c);
     return LST_OK;
 }
 
-int lst_get_tuning(const lst_ctx *c, int32_t *out9)
+int lst_get_tuning(const lst_ctx *c, int32_t *out15)
 {
-    if (!c || !out9) return LST_E_INVALID;
-    for (int i = 0; i < ST_COUNT; ++i) out9[i] = c->tune.grid[i];
-    out9[6] = c->tune.persistent;
-    out9[7] = c->tune.blocks_per_cu;
-    out9[8] = c->n_cu;
+    if (!c || !out15) return LST_E_INVALID;
+    for (int i = 0; i < ST_COUNT; ++i) {
+        out15[i] = c->tune.grid[i];
+        out15[ST_COUNT + i] = c->tune.lanes[i];
+    }
+    out15[12] = c->tune.persistent;
+    out15[13] = c->tune.blocks_per_cu;
+    out15[14] = c->n_cu;
     return LST_OK;
 }
 
@@ -828,13 +849,13 @@ int lst_stream_copy(void *dst, const void *src, size_t n_bytes, void *stream)
 struct ShardCounts {
     uint32_t gc[GC_COUNT];
     uint32_t rc[OT_COUNT];
-    uint32_t n(int t, int s) const { return std::min(gc[GC_SH + t * NSH + s], rc[t]); }
+    uint32_t n(int t, int s) const { return std::min(gc[gc_shard(t, s)], rc[t]); }
     size_t span(int t) const { return (size_t)rc[t] * NSH; }
     // capacity that would have let every shard fit
     int64_t required(int t) const
     {
         uint32_t m = 0;
-        for (int s = 0; s < NSH; ++s) m = std::max(m, gc[GC_SH + t * NSH + s]);
+        for (int s = 0; s < NSH; ++s) m = std::max(m, gc[gc_shard(t, s)]);
         return (int64_t)m * NSH;
     }
     int64_t stored(int t) const
@@ -1160,20 +1181,21 @@ static int timed_chain(lst_ctx *c, hipStream_t s, hipEvent_t *ev, double *stage_
     HIPCHK(c, hipEventRecord(ev[0], s));
     if (c->tune.persistent) {
         HIPCHK(c, launch_chain_persistent(c->E, c->M, c->K, c->zero_base, c->zero_bytes,
-                                          c->tune.blocks_per_cu * c->n_cu, false, s));
+                                          c->tune.blocks_per_cu * c->n_cu, c->tune.lanes[ST_SEG],
+                                          false, s));
         HIPCHK(c, hipEventRecord(ev[ST_COUNT], s));
     } else {
         const Tuning &t = c->tune;
         HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, s));
         HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], s));
         HIPCHK(c, hipEventRecord(ev[1], s));
-        HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], s));
+        HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], t.lanes[ST_MD], s));
         HIPCHK(c, hipEventRecord(ev[2], s));
-        HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], s));
+        HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], t.lanes[ST_SEG], s));
         HIPCHK(c, hipEventRecord(ev[3], s));
-        HIPCHK(c, launch_t3(c->E, c->M, c->K, t.grid[ST_T3], s));
+        HIPCHK(c, launch_t3(c->E, c->M, c->K, t.grid[ST_T3], t.lanes[ST_T3], s));
         HIPCHK(c, hipEventRecord(ev[4], s));
-        HIPCHK(c, launch_t5(c->E, c->M, c->K, t.grid[ST_T5], s));
+        HIPCHK(c, launch_t5(c->E, c->M, c->K, t.grid[ST_T5], t.lanes[ST_T5], s));
         HIPCHK(c, hipEventRecord(ev[5], s));
         HIPCHK(c, launch_dedup(c->E, c->M, t.grid[ST_DEDUP], s));
         HIPCHK(c, hipEventRecord(ev[ST_COUNT], s));
@@ -1244,11 +1266,12 @@ extern "C" int lst_tune(lst_ctx *c, const char *cache_path, int32_t reps, double
                 const std::string ln(line);
                 if (ln.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
                 const size_t p = ln.find("\"tuning\": [");
-                int32_t g[9];
+                int32_t g[14];
                 if (p != std::string::npos &&
-                    sscanf(ln.c_str() + p + 11, "%d, %d, %d, %d, %d, %d, %d, %d", &g[0], &g[1], &g[2], &g[3],
-                           &g[4], &g[5], &g[6], &g[7]) == 8 &&
-                    lst_set_tuning(c, g, g[6], g[7]) == LST_OK) {
+                    sscanf(ln.c_str() + p + 11, "%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d",
+                           &g[0], &g[1], &g[2], &g[3], &g[4], &g[5], &g[6], &g[7], &g[8], &g[9],
+                           &g[10], &g[11], &g[12], &g[13]) == 14 &&
+                    lst_set_tuning(c, g, g + 6, g[12], g[13]) == LST_OK) {
                     fclose(f);
                     if (report) report[0] = -1.0;  // taken from the cache
                     return LST_OK;
@@ -1275,25 +1298,37 @@ extern "C" int lst_tune(lst_ctx *c, const char *cache_path, int32_t reps, double
             {512, 1024, 2048, 4096, 8192, 0},    // t5
             {128, 256, 512, 1024, 2048, 0},      // dedup
         };
+        static const int lane_cand[4] = {64, 32, 16, 8};
         for (int stg = 0; stg < ST_COUNT; ++stg) {
-            int best_g = c->tune.grid[stg];
+            const bool grouped = stg >= ST_MD && stg <= ST_T5;
+            int best_g = c->tune.grid[stg], best_l = c->tune.lanes[stg];
             double best = 1e30;
-            for (int k = 0; k < 6 && cand[stg][k]; ++k) {
-                c->tune.grid[stg] = cand[stg][k];
-                double us;
-                if ((rc = measure(c, s, ev, reps, stg, ref, &us, &valid))) goto done;
-                if (!valid) {
-                    rc = fail(c, LST_E_HIP, "stage %d with grid %d changed the results", stg, cand[stg][k]);
-                    goto done;
+            for (int li = 0; li < (grouped ? 4 : 1); ++li) {
+                if (grouped) c->tune.lanes[stg] = lane_cand[li];
+                for (int k = 0; k < 6 && cand[stg][k]; ++k) {
+                    c->tune.grid[stg] = cand[stg][k];
+                    double us;
+                    if ((rc = measure(c, s, ev, reps, stg, ref, &us, &valid))) goto done;
+                    if (!valid) {
+                        rc = fail(c, LST_E_HIP, "stage %d with grid %d, lanes %d changed the results",
+                                  stg, cand[stg][k], c->tune.lanes[stg]);
+                        goto done;
+                    }
+                    if (us < best) {
+                        best = us;
+                        best_g = cand[stg][k];
+                        best_l = c->tune.lanes[stg];
+                    }
                 }
-                if (us < best) { best = us; best_g = cand[stg][k]; }
             }
             c->tune.grid[stg] = best_g;
+            c->tune.lanes[stg] = best_l;
             best_stage[stg] = best;
         }
         double graph_us = 0.0, pers_us = 1e30;
         if ((rc = measure(c, s, ev, reps, -1, ref, &graph_us, &valid))) goto done;
-        const int occ = std::max(1, persistent_blocks_per_cu());
+        // the persistent kernel runs the segment stage's group width everywhere
+        const int occ = std::max(1, persistent_blocks_per_cu(c->tune.lanes[ST_SEG]));
         int best_bpc = 1;
         c->tune.persistent = 1;
         for (int bpc = 1; bpc <= occ; ++bpc) {
@@ -1312,11 +1347,12 @@ extern "C" int lst_tune(lst_ctx *c, const char *cache_path, int32_t reps, double
         if (cache_path) {
             FILE *f = fopen(cache_path, "a");
             if (f) {
-                fprintf(f, "{\"key\": \"%s\", \"tuning\": [%d, %d, %d, %d, %d, %d, %d, %d], "
-                           "\"chain_us\": %.2f, \"persistent_us\": %.2f}\n",
-                        key.c_str(), c->tune.grid[0], c->tune.grid[1], c->tune.grid[2], c->tune.grid[3],
-                        c->tune.grid[4], c->tune.grid[5], c->tune.persistent, c->tune.blocks_per_cu,
-                        graph_us, pers_us);
+                const Tuning &t = c->tune;
+                fprintf(f, "{\"key\": \"%s\", \"tuning\": [%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, "
+                           "%d, %d, %d, %d], \"chain_us\": %.2f, \"persistent_us\": %.2f}\n",
+                        key.c_str(), t.grid[0], t.grid[1], t.grid[2], t.grid[3], t.grid[4], t.grid[5],
+                        t.lanes[0], t.lanes[1], t.lanes[2], t.lanes[3], t.lanes[4], t.lanes[5],
+                        t.persistent, t.blocks_per_cu, graph_us, pers_us);
                 fclose(f);
             }
         }

@@ -25,15 +25,22 @@ struct Consts {
 constexpr int NSH = 32;
 enum ObjType { OT_MD = 0, OT_SEG, OT_T3, OT_T5, OT_COUNT };
 
-// Global counters (int32 / uint32).
+// Global counters (int32 / uint32).  Counters that many blocks update at
+// once sit on their own 256-byte line: device-scope atomics on one line are
+// serialised across the XCDs, so shard counters sharing a line would give
+// no parallelism.
+constexpr int GC_PAD = 64;   // uint32 stride of padded counters
 enum GlobalCounter {
     GC_OVERFLOW = 0,   // bit k: object type k ran out of its region
     GC_ERROR,          // bit 0: invalid hit skipped
     GC_N_SORTED,       // number of grouped hits
     GC_TIEPOOL,        // entries taken from the dedup tie pool
-    GC_SH = 8,         // [OT_COUNT][NSH] reservation shards
-    GC_COUNT = GC_SH + OT_COUNT * NSH
+    GC_SCAN,           // tile tickets of the look-back scan
+    GC_SH = GC_PAD     // [OT_COUNT][NSH] reservation shards, one line each
 };
+__host__ __device__ constexpr int gc_shard(int type, int s) { return GC_SH + (type * NSH + s) * GC_PAD; }
+constexpr int GC_COUNT = GC_SH + OT_COUNT * NSH * GC_PAD;
+
 
 struct ModDev {
     const float *cx, *cy, *cz, *ux, *uy, *uz, *vx, *vy, *vz, *g, *rl;
@@ -61,7 +68,7 @@ struct EvDev {
     // grouping of hits by key = 2 * slot + sensor
     uint32_t *bcnt;          // [n_keys]     (zeroed at chain start)
     uint32_t *boff;          // [n_keys + 1]
-    uint32_t *bsum;          // scan partials
+    unsigned long long *scan_st;  // look-back scan: status per tile (zeroed at chain start)
     float *sx, *sy, *sz;     // sorted hits
     int32_t *sorig;          // per-event index of each sorted hit
     uint32_t *hmin;          // dedup: smallest quintuplet score bits per sorted hit
@@ -87,6 +94,7 @@ struct EvDev {
     float *t5_score;
     uint8_t *t5_keep;
     uint8_t *t5_veto;                // 1: rejected by the learned scorer
+    int32_t *t5_hs, *t5_ho;          // dedup: [span][10] sorted and per-event hit indices
     float *t5_feat;                  // [span][40] features (learned scorer)
     float *t5_logit;                 // [span] scorer output
     // counters (zeroed at chain start)
@@ -99,21 +107,28 @@ constexpr int BLOCK = 256;           // 4 waves of 64
 constexpr int WAVES = BLOCK / 64;
 constexpr int STAGE = 256;           // accepted objects a wave stages in LDS
 constexpr int GRID_MAX = 2048;       // blocks of a grid-stride stage kernel
+constexpr int SCAN_TILE = 1024;      // keys per tile of the look-back scan
 
 // launchers (lst_kernels.hip)
 hipError_t launch_copy(void *dst, const void *src, size_t n_bytes, hipStream_t s);
 hipError_t launch_zero(const EvDev &E, void *zero_base, size_t zero_bytes, hipStream_t s);
 hipError_t launch_sort(const EvDev &E, const ModDev &M, int grid, hipStream_t s);
-hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s);
-hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s);
-hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s);
-hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s);
+// lanes: width of the lane group that owns one inner object (8, 16, 32 or 64)
+hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
+                     hipStream_t s);
+hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
+                      hipStream_t s);
+hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
+                     hipStream_t s);
+hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
+                     hipStream_t s);
 hipError_t launch_dedup(const EvDev &E, const ModDev &M, int grid, hipStream_t s);
-// stop_before_dedup: end the persistent kernel after the quintuplet stage
+// stop_before_dedup: end the persistent kernel after the quintuplet stage;
+// lanes: group width of its four object stages
 hipError_t launch_chain_persistent(const EvDev &E, const ModDev &M, const Consts &K,
-                                   void *zero_base, size_t zero_bytes, int grid,
+                                   void *zero_base, size_t zero_bytes, int grid, int lanes,
                                    bool stop_before_dedup, hipStream_t s);
-int persistent_blocks_per_cu();
+int persistent_blocks_per_cu(int lanes);
 hipError_t launch_t5_features(const EvDev &E, const Consts &K, int grid, hipStream_t s);
 
 // learned quintuplet scorer (lst_mlp.hip)
@@ -136,6 +151,7 @@ hipError_t mlp_score(const EvDev &E, const Consts &K, const float *P, const floa
 enum StageId { ST_SORT = 0, ST_MD, ST_SEG, ST_T3, ST_T5, ST_DEDUP, ST_COUNT };
 struct Tuning {
     int grid[ST_COUNT];
+    int lanes[ST_COUNT];   // group width per stage (MD, SEG, T3, T5; others unused)
     int persistent;        // 1: the whole chain as one persistent kernel
     int blocks_per_cu;     // persistent grid = blocks_per_cu x CUs
 };

@@ -55,6 +55,70 @@ __device__ __forceinline__ int wave_find(uint32_t incl, uint32_t j)
     return lo;
 }
 
+// A wave split into P = 64 / G groups of G lanes; each group works on its
+// own inner object.  Small candidate lists (a few dozen per inner object)
+// then fill the lanes, and P inner objects' loads are in flight per wave.
+template <int G>
+struct Grp {
+    static constexpr int P = 64 / G;
+    static constexpr int LOG = G == 64 ? 6 : G == 32 ? 5 : G == 16 ? 4 : 3;
+    int lane, g;
+    __device__ __forceinline__ Grp() : lane(threadIdx.x & (G - 1)), g((threadIdx.x & 63) / G) {}
+    __device__ __forceinline__ uint32_t incl_scan(uint32_t v) const
+    {
+#pragma unroll
+        for (int d = 1; d < G; d <<= 1) {
+            const uint32_t t = __shfl_up(v, d, G);
+            if (lane >= d) v += t;
+        }
+        return v;
+    }
+    template <class T>
+    __device__ __forceinline__ T bcast(T v, int src) const { return __shfl(v, src, G); }
+    // smallest group lane e with incl[e] > j (incl non-decreasing in the group)
+    __device__ __forceinline__ int find(uint32_t incl, uint32_t j) const
+    {
+        int lo = 0, hi = G - 1;
+#pragma unroll
+        for (int it = 0; it < LOG; ++it) {
+            const int mid = (lo + hi) >> 1;
+            if (__shfl(incl, mid, G) > j) hi = mid; else lo = mid + 1;
+        }
+        return lo;
+    }
+    // accepted lanes of the group below this lane; *tot = accepted in the group
+    __device__ __forceinline__ uint32_t rank(bool ok, uint32_t &tot) const
+    {
+        const unsigned long long m = __ballot(ok);
+        const unsigned long long gm = G == 64 ? m : (m >> (g * G)) & ((1ull << (G & 63)) - 1ull);
+        tot = (uint32_t)__popcll(gm);
+        return (uint32_t)__popcll(gm & ((1ull << lane) - 1ull));
+    }
+    // exclusive prefix of a per-group value over the wave's groups, and the sum
+    __device__ __forceinline__ uint32_t wave_prefix(uint32_t v, uint32_t &sum) const
+    {
+        uint32_t ex = 0;
+        sum = 0;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const uint32_t c = __shfl(v, q * G, 64);
+            if (q < g) ex += c;
+            sum += c;
+        }
+        return ex;
+    }
+};
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t t = __shfl_xor(v, d, 64);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
 // ---------------------------------------------------------------- regions
 // Objects of one type live in NSH regions; n_s = min(counter_s, rc) of them
 // in region s.  A wave maps a compact index v in [0, sum n_s) to its array
@@ -72,7 +136,7 @@ __device__ __forceinline__ Regions load_regions(const EvDev &E, int type)
     R.rc = E.rc[type];
     uint32_t n = 0;
     if (lane_id() < NSH) {
-        uint32_t c = E.gc[GC_SH + type * NSH + lane_id()];
+        uint32_t c = E.gc[gc_shard(type, lane_id())];
         n = c < R.rc ? c : R.rc;
     }
     R.size = n;
@@ -81,7 +145,7 @@ __device__ __forceinline__ Regions load_regions(const EvDev &E, int type)
     return R;
 }
 
-// v must be wave-uniform and < R.total
+// v < R.total (may differ between lanes); every lane of the wave takes part
 __device__ __forceinline__ int32_t region_index(const Regions &R, uint32_t v)
 {
     const int r = wave_find(R.incl, v);
@@ -106,7 +170,7 @@ __device__ __forceinline__ uint32_t block_reserve(uint32_t wave_total, const EvD
         for (int i = 0; i < WAVES; ++i) tot += s_cnt[i];
         const uint32_t shard = blockIdx.x % NSH;
         const uint32_t rc = E.rc[type];
-        const uint32_t base = tot ? atomicAdd(&E.gc[GC_SH + type * NSH + shard], tot) : 0u;
+        const uint32_t base = tot ? atomicAdd(&E.gc[gc_shard(type, shard)], tot) : 0u;
         const int o = ((uint64_t)base + tot) > (uint64_t)rc;
         if (o) atomicOr(&E.gc[GC_OVERFLOW], 1u << type);
         s_base = shard * rc + base;
@@ -190,8 +254,14 @@ __device__ __forceinline__ void hist_body(const EvDev &E, int n_mod)
     }
 }
 
-// exclusive scan of bcnt[0..n) into boff[0..n], three phases over tiles of 1024
-constexpr int SCAN_TILE = 1024;
+// Exclusive scan of bcnt[0..n) into boff[0..n] in one pass (decoupled
+// look-back): a block takes tiles of SCAN_TILE keys in ticket order, publishes
+// its tile sum, then walks back over the predecessors' published sums until
+// it meets an inclusive prefix.  Status words hold flag and value together,
+// so one device-scope atomic load sees both.  A block only ever waits for
+// tiles taken before its own, by blocks that are already running.
+constexpr unsigned long long ST_AGG = 1ull << 62, ST_INC = 2ull << 62;
+constexpr uint32_t SCAN_SPIN_LIMIT = 1u << 20;
 
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t &total)
 {
@@ -210,46 +280,17 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t &total)
     return before + incl - v;
 }
 
-__device__ __forceinline__ int scan_tiles(const EvDev &E)
+__device__ __forceinline__ void scan_body(const EvDev &E)
 {
-    return (E.cap_keys + 1 + SCAN_TILE - 1) / SCAN_TILE;
-}
-
-// per-tile sums (grid-stride over tiles)
-__device__ __forceinline__ void scan_reduce_body(const EvDev &E)
-{
-    const int n = E.desc[D_NKEYS], nb = scan_tiles(E);
-    for (int tile = blockIdx.x; tile < nb; tile += gridDim.x) {
-        const int base = tile * SCAN_TILE + threadIdx.x * 4;
-        uint32_t v = 0;
-        for (int k = 0; k < 4; ++k)
-            if (base + k < n) v += E.bcnt[base + k];
-        uint32_t tot;
-        block_excl_scan(v, tot);
-        if (threadIdx.x == 0) E.bsum[tile] = tot;
-    }
-}
-
-// exclusive scan of the tile sums by block 0
-__device__ __forceinline__ void scan_top_body(const EvDev &E)
-{
-    if (blockIdx.x != 0) return;
-    const int nb = scan_tiles(E);
-    uint32_t carry = 0;
-    for (int b0 = 0; b0 < nb; b0 += BLOCK) {
-        const int i = b0 + threadIdx.x;
-        const uint32_t v = i < nb ? E.bsum[i] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(v, tot);
-        if (i < nb) E.bsum[i] = carry + ex;
-        carry += tot;
-    }
-}
-
-__device__ __forceinline__ void scan_down_body(const EvDev &E)
-{
-    const int n = E.desc[D_NKEYS], nb = scan_tiles(E);
-    for (int tile = blockIdx.x; tile < nb; tile += gridDim.x) {
+    __shared__ int s_tile;
+    __shared__ uint32_t s_prefix;
+    const int n = E.desc[D_NKEYS];
+    const int nb = (n + 1 + SCAN_TILE - 1) / SCAN_TILE;   // index n holds the total
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int)atomicAdd(&E.gc[GC_SCAN], 1u);
+        __syncthreads();
+        const int tile = s_tile;
+        if (tile >= nb) break;
         const int base = tile * SCAN_TILE + threadIdx.x * 4;
         uint32_t v[4], sum = 0;
         for (int k = 0; k < 4; ++k) {
@@ -257,7 +298,40 @@ __device__ __forceinline__ void scan_down_body(const EvDev &E)
             sum += v[k];
         }
         uint32_t tot;
-        uint32_t ex = block_excl_scan(sum, tot) + E.bsum[tile];
+        uint32_t ex = block_excl_scan(sum, tot);
+        if (threadIdx.x == 0) {
+            unsigned long long *st = E.scan_st;
+            uint32_t prefix = 0;
+            if (tile == 0) {
+                __hip_atomic_store(&st[0], ST_INC | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                __hip_atomic_store(&st[tile], ST_AGG | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t it = 0;
+                for (int j = tile - 1; j >= 0;) {
+                    const unsigned long long w =
+                        __hip_atomic_load(&st[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (w & ST_INC) {
+                        prefix += (uint32_t)w;
+                        break;
+                    }
+                    if (w & ST_AGG) {
+                        prefix += (uint32_t)w;
+                        --j;
+                        continue;
+                    }
+                    if (++it > SCAN_SPIN_LIMIT) {   // cannot happen with running predecessors
+                        atomicOr(&E.gc[GC_ERROR], 4u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __hip_atomic_store(&st[tile], ST_INC | (uint32_t)(prefix + tot), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            s_prefix = prefix;
+        }
+        __syncthreads();
+        ex += s_prefix;
         for (int k = 0; k < 4; ++k) {
             const int idx = base + k;
             if (idx < n) E.boff[idx] = ex;
@@ -267,6 +341,7 @@ __device__ __forceinline__ void scan_down_body(const EvDev &E)
             }
             ex += v[k];
         }
+        __syncthreads();   // s_tile is rewritten by the next ticket
     }
 }
 
@@ -291,9 +366,7 @@ __device__ __forceinline__ void scatter_body(const EvDev &E, int n_mod)
 }
 
 __global__ void k_hist(EvDev E, int n_mod) { hist_body(E, n_mod); }
-__global__ void k_scan_reduce(EvDev E) { scan_reduce_body(E); }
-__global__ void k_scan_top(EvDev E) { scan_top_body(E); }
-__global__ void k_scan_down(EvDev E) { scan_down_body(E); }
+__global__ __launch_bounds__(BLOCK) void k_scan(EvDev E) { scan_body(E); }
 __global__ void k_scatter(EvDev E, int n_mod) { scatter_body(E, n_mod); }
 
 // grids depend on the arena capacities only, never on the batch
@@ -301,9 +374,7 @@ hipError_t launch_sort(const EvDev &E, const ModDev &M, int grid, hipStream_t s)
 {
     const int nb = (E.cap_keys + 1 + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(k_hist, dim3(grid), dim3(BLOCK), 0, s, E, M.n_mod);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(BLOCK), 0, s, E);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, s, E);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(BLOCK), 0, s, E);
+    hipLaunchKernelGGL(k_scan, dim3(nb < 1024 ? nb : 1024), dim3(BLOCK), 0, s, E);
     hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(BLOCK), 0, s, E, M.n_mod);
     return hipGetLastError();
 }
@@ -361,15 +432,17 @@ __device__ __forceinline__ void write_md(const EvDev &E, uint32_t i, int slot, u
     E.md_bar[i] = (uint8_t)(mod.barrel | (mod.is2s << 1));
 }
 
-// every lower x upper hit pair of one module slot; sink(ok, hl, hu, pos)
-template <class F>
+// every lower x upper hit pair of one module slot (one group); sink(ok, hl, hu, pos)
+template <int G, class F>
 __device__ __forceinline__ uint32_t enum_md(const EvDev &E, const Consts &K, const ModF &mod,
                                             uint32_t lo0, uint32_t up0, uint32_t nup,
                                             uint32_t np, F &&sink)
 {
+    const Grp<G> gp;
     uint32_t cnt = 0;
-    for (uint32_t b = 0; b < np; b += 64) {
-        const uint32_t p = b + lane_id();
+    const uint32_t np_max = wave_max(np);
+    for (uint32_t b = 0; b < np_max; b += G) {
+        const uint32_t p = b + gp.lane;
         bool ok = false;
         uint32_t hl = 0, hu = 0;
         if (p < np) {
@@ -379,19 +452,24 @@ __device__ __forceinline__ uint32_t enum_md(const EvDev &E, const Consts &K, con
             MdOut o;
             ok = md_accept(K, mod, E.sx[hl], E.sy[hl], E.sz[hl], E.sx[hu], E.sy[hu], E.sz[hu], o);
         }
-        const unsigned long long mask = __ballot(ok);
-        sink(ok, hl, hu, cnt + (uint32_t)__popcll(mask & lanes_below()));
-        cnt += (uint32_t)__popcll(mask);
+        uint32_t t;
+        const uint32_t r = gp.rank(ok, t);
+        sink(ok, hl, hu, cnt + r);
+        cnt += t;
     }
     return cnt;
 }
 
+// one group of G lanes per module slot
+template <int G>
 __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const Consts &K, SmMD &sm)
 {
+    constexpr int P = Grp<G>::P, CAP = STAGE / P;
+    const Grp<G> gp;
     const int w = wave_id();
     const int n_slots = E.desc[D_NSLOTS];
-    for (int base = blockIdx.x * WAVES; base < n_slots; base += gridDim.x * WAVES) {
-        const int slot = base + w;
+    for (int base = blockIdx.x * WAVES * P; base < n_slots; base += gridDim.x * WAVES * P) {
+        const int slot = base + w * P + gp.g;
         const bool act = slot < n_slots;
         uint32_t lo0 = 0, up0 = 0, nup = 0, np = 0;
         if (act) {
@@ -402,72 +480,93 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
         }
         ModF mod = {};
         if (np) mod = load_mod(M, slot % M.n_mod);
-        const uint32_t cnt = enum_md(E, K, mod, lo0, up0, nup, np,
-                                     [&](bool ok, uint32_t hl, uint32_t hu, uint32_t pos) {
-                                         if (ok && pos < STAGE) {
-                                             sm.lo[w][pos] = hl;
-                                             sm.up[w][pos] = hu;
-                                         }
-                                     });
+        const uint32_t cnt = enum_md<G>(E, K, mod, lo0, up0, nup, np,
+                                        [&](bool ok, uint32_t hl, uint32_t hu, uint32_t pos) {
+                                            if (ok && pos < CAP) {
+                                                sm.lo[w][gp.g * CAP + pos] = hl;
+                                                sm.up[w][gp.g * CAP + pos] = hu;
+                                            }
+                                        });
+        uint32_t wtot;
+        const uint32_t gex = gp.wave_prefix(cnt, wtot);
         bool ovf;
-        const uint32_t off = block_reserve(cnt, E, OT_MD, ovf);
-        if (!act) continue;
-        if (lane_id() == 0) {
+        const uint32_t off = block_reserve(wtot, E, OT_MD, ovf) + gex;
+        if (act && gp.lane == 0) {
             E.md_start[slot] = (int32_t)off;
             E.md_cnt[slot] = ovf ? 0 : (int32_t)cnt;
         }
-        if (ovf || cnt == 0) continue;
-        if (cnt <= STAGE) {
-            for (uint32_t k = lane_id(); k < cnt; k += 64) {
-                const uint32_t hl = sm.lo[w][k], hu = sm.up[w][k];
+        if (ovf) continue;
+        if (act && cnt <= CAP) {
+            for (uint32_t k = gp.lane; k < cnt; k += G) {
+                const uint32_t hl = sm.lo[w][gp.g * CAP + k], hu = sm.up[w][gp.g * CAP + k];
                 MdOut o;
                 md_accept(K, mod, E.sx[hl], E.sy[hl], E.sz[hl], E.sx[hu], E.sy[hu], E.sz[hu], o);
                 write_md(E, off + k, slot, hl, hu, o, mod);
             }
-        } else {
-            enum_md(E, K, mod, lo0, up0, nup, np,
-                    [&](bool ok, uint32_t hl, uint32_t hu, uint32_t pos) {
-                        if (ok) {
-                            MdOut o;
-                            md_accept(K, mod, E.sx[hl], E.sy[hl], E.sz[hl], E.sx[hu], E.sy[hu],
-                                      E.sz[hu], o);
-                            write_md(E, off + pos, slot, hl, hu, o, mod);
-                        }
-                    });
+        }
+        if (wave_max(cnt) > CAP) {
+            // groups beyond their staging share enumerate again and write directly
+            const bool redo = act && cnt > CAP;
+            enum_md<G>(E, K, mod, lo0, up0, nup, redo ? np : 0u,
+                       [&](bool ok, uint32_t hl, uint32_t hu, uint32_t pos) {
+                           if (ok) {
+                               MdOut o;
+                               md_accept(K, mod, E.sx[hl], E.sy[hl], E.sz[hl], E.sx[hu], E.sy[hu],
+                                         E.sz[hu], o);
+                               write_md(E, off + pos, slot, hl, hu, o, mod);
+                           }
+                       });
         }
     }
 }
 
+template <int G>
 __global__ __launch_bounds__(BLOCK) void k_md(EvDev E, ModDev M, Consts K)
 {
     __shared__ SmMD sm;
-    md_body(E, M, K, sm);
+    md_body<G>(E, M, K, sm);
 }
 
-hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s)
+// the group widths a stage kernel is built for
+#define LST_BY_LANES(lanes, KERNEL, ...)                                              \
+    switch (lanes) {                                                                  \
+    case 8: hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__); break;                        \
+    case 16: hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__); break;                      \
+    case 32: hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__); break;                      \
+    default: hipLaunchKernelGGL(KERNEL<64>, __VA_ARGS__); break;                      \
+    }
+
+hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
+                     hipStream_t s)
 {
-    hipLaunchKernelGGL(k_md, dim3(grid), dim3(BLOCK), 0, s, E, M, K);
+    LST_BY_LANES(lanes, k_md, dim3(grid), dim3(BLOCK), 0, s, E, M, K);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- segments
 // Outer candidates of inner MD i: the MDs of every map edge of its module,
-// in edge order.  sink(ok, o, pos)
-template <class F>
+// in edge order; one group of G lanes per inner MD.  sink(ok, o, pos)
+template <int G, class F>
 __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, const Consts &K,
-                                             int32_t i, F &&sink)
+                                             int32_t i, bool act, F &&sink)
 {
-    const int lane = lane_id();
-    const MdV I = load_md(E, i);
-    const int slot = E.md_slot[i];
-    const int ev = slot / M.n_mod;
-    const int m = slot - ev * M.n_mod;
-    const int base_slot = ev * M.n_mod;
-    const int32_t e0 = M.map_ptr[m];
-    const int32_t ne = M.map_ptr[m + 1] - e0;
+    const Grp<G> gp;
+    MdV I = {};
+    int base_slot = 0;
+    int32_t e0 = 0, ne = 0;
+    if (act) {
+        I = load_md(E, i);
+        const int slot = E.md_slot[i];
+        const int ev = slot / M.n_mod;
+        const int m = slot - ev * M.n_mod;
+        base_slot = ev * M.n_mod;
+        e0 = M.map_ptr[m];
+        ne = M.map_ptr[m + 1] - e0;
+    }
     uint32_t cnt = 0;
-    for (int32_t ec = 0; ec < ne; ec += 64) {
-        const int32_t e = ec + lane;
+    const int32_t ne_max = (int32_t)wave_max((uint32_t)ne);
+    for (int32_t ec = 0; ec < ne_max; ec += G) {
+        const int32_t e = ec + gp.lane;
         uint32_t bc = 0;
         int32_t bs = 0;
         if (e < ne) {
@@ -475,56 +574,61 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
             bs = E.md_start[b];
             bc = (uint32_t)E.md_cnt[b];
         }
-        const uint32_t incl = wave_incl_scan(bc);
-        const uint32_t tot = __shfl(incl, 63, 64);
-        for (uint32_t jc = 0; jc < tot; jc += 64) {
-            const uint32_t j = jc + lane;
-            const int src = wave_find(incl, j < tot ? j : tot - 1);
-            const uint32_t ex = __shfl(incl, src, 64) - __shfl(bc, src, 64);
-            const int32_t obs = __shfl(bs, src, 64);
+        const uint32_t incl = gp.incl_scan(bc);
+        const uint32_t tot = gp.bcast(incl, G - 1);
+        const uint32_t tot_max = wave_max(tot);
+        for (uint32_t jc = 0; jc < tot_max; jc += G) {
+            const uint32_t j = jc + gp.lane;
+            const int src = gp.find(incl, j < tot ? j : (tot ? tot - 1 : 0));
+            const uint32_t ex = gp.bcast(incl, src) - gp.bcast(bc, src);
+            const int32_t obs = gp.bcast(bs, src);
             bool ok = false;
             int32_t o = 0;
             if (j < tot) {
                 o = obs + (int32_t)(j - ex);
                 ok = seg_accept(K, I, load_md(E, o));
             }
-            const unsigned long long mask = __ballot(ok);
-            sink(ok, o, cnt + (uint32_t)__popcll(mask & lanes_below()));
-            cnt += (uint32_t)__popcll(mask);
+            uint32_t t;
+            const uint32_t r = gp.rank(ok, t);
+            sink(ok, o, cnt + r);
+            cnt += t;
         }
     }
     return cnt;
 }
 
+template <int G>
 __device__ __forceinline__ void seg_body(const EvDev &E, const ModDev &M, const Consts &K, SmSeg &sm)
 {
     if (upstream_overflow(E)) return;
+    constexpr int P = Grp<G>::P, CAP = STAGE / P;
+    const Grp<G> gp;
     const int w = wave_id();
     const Regions R = load_regions(E, OT_MD);
-    for (uint32_t base = blockIdx.x * WAVES; base < R.total; base += gridDim.x * WAVES) {
-        const uint32_t v = base + w;
+    for (uint32_t base = blockIdx.x * WAVES * P; base < R.total; base += gridDim.x * WAVES * P) {
+        const uint32_t v = base + w * P + gp.g;
         const bool act = v < R.total;
         const int32_t i = region_index(R, act ? v : 0);
-        uint32_t cnt = 0;
-        if (act)
-            cnt = enum_seg(E, M, K, i, [&](bool ok, int32_t o, uint32_t pos) {
-                if (ok && pos < STAGE) sm.o[w][pos] = o;
-            });
+        const uint32_t cnt = enum_seg<G>(E, M, K, i, act, [&](bool ok, int32_t o, uint32_t pos) {
+            if (ok && pos < CAP) sm.o[w][gp.g * CAP + pos] = o;
+        });
+        uint32_t wtot;
+        const uint32_t gex = gp.wave_prefix(cnt, wtot);
         bool ovf;
-        const uint32_t off = block_reserve(cnt, E, OT_SEG, ovf);
-        if (!act) continue;
-        if (lane_id() == 0) {
+        const uint32_t off = block_reserve(wtot, E, OT_SEG, ovf) + gex;
+        if (act && gp.lane == 0) {
             E.seg_start[i] = (int32_t)off;
             E.seg_cnt[i] = ovf ? 0 : (int32_t)cnt;
         }
-        if (ovf || cnt == 0) continue;
-        if (cnt <= STAGE) {
-            for (uint32_t k = lane_id(); k < cnt; k += 64) {
+        if (ovf) continue;
+        if (act && cnt <= CAP) {
+            for (uint32_t k = gp.lane; k < cnt; k += G) {
                 E.seg_in[off + k] = i;
-                E.seg_out[off + k] = sm.o[w][k];
+                E.seg_out[off + k] = sm.o[w][gp.g * CAP + k];
             }
-        } else {
-            enum_seg(E, M, K, i, [&](bool ok, int32_t o, uint32_t pos) {
+        }
+        if (wave_max(cnt) > CAP) {
+            enum_seg<G>(E, M, K, i, act && cnt > CAP, [&](bool ok, int32_t o, uint32_t pos) {
                 if (ok) {
                     E.seg_in[off + pos] = i;
                     E.seg_out[off + pos] = o;
@@ -534,32 +638,39 @@ __device__ __forceinline__ void seg_body(const EvDev &E, const ModDev &M, const 
     }
 }
 
+template <int G>
 __global__ __launch_bounds__(BLOCK) void k_seg(EvDev E, ModDev M, Consts K)
 {
     __shared__ SmSeg sm;
-    seg_body(E, M, K, sm);
+    seg_body<G>(E, M, K, sm);
 }
 
-hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s)
+hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
+                      hipStream_t s)
 {
-    hipLaunchKernelGGL(k_seg, dim3(grid), dim3(BLOCK), 0, s, E, M, K);
+    LST_BY_LANES(lanes, k_seg, dim3(grid), dim3(BLOCK), 0, s, E, M, K);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- triplets
 // Candidates of inner MD a: every segment (a->b) followed by every segment
-// (b->c).  sink(ok, b, c, k, pos)
-template <class F>
-__device__ __forceinline__ uint32_t enum_t3(const EvDev &E, const Consts &K, int32_t a, F &&sink)
+// (b->c); one group of G lanes per inner MD.  sink(ok, b, c, k, pos)
+template <int G, class F>
+__device__ __forceinline__ uint32_t enum_t3(const EvDev &E, const Consts &K, int32_t a, bool act,
+                                            F &&sink)
 {
-    const int lane = lane_id();
-    const int32_t ns1 = E.seg_cnt[a];
-    const int32_t s10 = E.seg_start[a];
+    const Grp<G> gp;
+    int32_t ns1 = 0, s10 = 0;
+    if (act) {
+        ns1 = E.seg_cnt[a];
+        s10 = E.seg_start[a];
+    }
+    MdV A = {};
+    if (ns1 > 0) A = load_md(E, a);
     uint32_t cnt = 0;
-    if (ns1 <= 0) return 0;
-    const MdV A = load_md(E, a);
-    for (int32_t c1 = 0; c1 < ns1; c1 += 64) {
-        const int32_t k = c1 + lane;
+    const int32_t ns_max = (int32_t)wave_max((uint32_t)(ns1 > 0 ? ns1 : 0));
+    for (int32_t c1 = 0; c1 < ns_max; c1 += G) {
+        const int32_t k = c1 + gp.lane;
         int32_t b = 0, bs = 0;
         uint32_t nb = 0;
         if (k < ns1) {
@@ -567,14 +678,15 @@ __device__ __forceinline__ uint32_t enum_t3(const EvDev &E, const Consts &K, int
             bs = E.seg_start[b];
             nb = (uint32_t)E.seg_cnt[b];
         }
-        const uint32_t incl = wave_incl_scan(nb);
-        const uint32_t tot = __shfl(incl, 63, 64);
-        for (uint32_t jc = 0; jc < tot; jc += 64) {
-            const uint32_t j = jc + lane;
-            const int src = wave_find(incl, j < tot ? j : tot - 1);
-            const uint32_t ex = __shfl(incl, src, 64) - __shfl(nb, src, 64);
-            const int32_t bb = __shfl(b, src, 64);
-            const int32_t bbs = __shfl(bs, src, 64);
+        const uint32_t incl = gp.incl_scan(nb);
+        const uint32_t tot = gp.bcast(incl, G - 1);
+        const uint32_t tot_max = wave_max(tot);
+        for (uint32_t jc = 0; jc < tot_max; jc += G) {
+            const uint32_t j = jc + gp.lane;
+            const int src = gp.find(incl, j < tot ? j : (tot ? tot - 1 : 0));
+            const uint32_t ex = gp.bcast(incl, src) - gp.bcast(nb, src);
+            const int32_t bb = gp.bcast(b, src);
+            const int32_t bbs = gp.bcast(bs, src);
             bool ok = false;
             int32_t c = 0;
             float kk = 0.0f;
@@ -582,49 +694,55 @@ __device__ __forceinline__ uint32_t enum_t3(const EvDev &E, const Consts &K, int
                 c = E.seg_out[bbs + (int32_t)(j - ex)];
                 ok = t3_accept(K, A, load_md(E, bb), load_md(E, c), kk);
             }
-            const unsigned long long mask = __ballot(ok);
-            sink(ok, bb, c, kk, cnt + (uint32_t)__popcll(mask & lanes_below()));
-            cnt += (uint32_t)__popcll(mask);
+            uint32_t t;
+            const uint32_t r = gp.rank(ok, t);
+            sink(ok, bb, c, kk, cnt + r);
+            cnt += t;
         }
     }
     return cnt;
 }
 
+template <int G>
 __device__ __forceinline__ void t3_body(const EvDev &E, const Consts &K, SmT3 &sm)
 {
     if (upstream_overflow(E)) return;
+    constexpr int P = Grp<G>::P, CAP = STAGE / P;
+    const Grp<G> gp;
     const int w = wave_id();
     const Regions R = load_regions(E, OT_MD);
-    for (uint32_t base = blockIdx.x * WAVES; base < R.total; base += gridDim.x * WAVES) {
-        const uint32_t v = base + w;
+    for (uint32_t base = blockIdx.x * WAVES * P; base < R.total; base += gridDim.x * WAVES * P) {
+        const uint32_t v = base + w * P + gp.g;
         const bool act = v < R.total;
         const int32_t a = region_index(R, act ? v : 0);
-        uint32_t cnt = 0;
-        if (act)
-            cnt = enum_t3(E, K, a, [&](bool ok, int32_t b, int32_t c, float k, uint32_t pos) {
-                if (ok && pos < STAGE) {
-                    sm.b[w][pos] = b;
-                    sm.c[w][pos] = c;
-                    sm.k[w][pos] = k;
-                }
-            });
+        const uint32_t cnt = enum_t3<G>(E, K, a, act, [&](bool ok, int32_t b, int32_t c, float k,
+                                                          uint32_t pos) {
+            if (ok && pos < CAP) {
+                sm.b[w][gp.g * CAP + pos] = b;
+                sm.c[w][gp.g * CAP + pos] = c;
+                sm.k[w][gp.g * CAP + pos] = k;
+            }
+        });
+        uint32_t wtot;
+        const uint32_t gex = gp.wave_prefix(cnt, wtot);
         bool ovf;
-        const uint32_t off = block_reserve(cnt, E, OT_T3, ovf);
-        if (!act) continue;
-        if (lane_id() == 0) {
+        const uint32_t off = block_reserve(wtot, E, OT_T3, ovf) + gex;
+        if (act && gp.lane == 0) {
             E.t3_start[a] = (int32_t)off;
             E.t3_cnt[a] = ovf ? 0 : (int32_t)cnt;
         }
-        if (ovf || cnt == 0) continue;
-        if (cnt <= STAGE) {
-            for (uint32_t k = lane_id(); k < cnt; k += 64) {
+        if (ovf) continue;
+        if (act && cnt <= CAP) {
+            for (uint32_t k = gp.lane; k < cnt; k += G) {
                 E.t3_a[off + k] = a;
-                E.t3_b[off + k] = sm.b[w][k];
-                E.t3_c[off + k] = sm.c[w][k];
-                E.t3_k[off + k] = sm.k[w][k];
+                E.t3_b[off + k] = sm.b[w][gp.g * CAP + k];
+                E.t3_c[off + k] = sm.c[w][gp.g * CAP + k];
+                E.t3_k[off + k] = sm.k[w][gp.g * CAP + k];
             }
-        } else {
-            enum_t3(E, K, a, [&](bool ok, int32_t b, int32_t c, float k, uint32_t pos) {
+        }
+        if (wave_max(cnt) > CAP) {
+            enum_t3<G>(E, K, a, act && cnt > CAP, [&](bool ok, int32_t b, int32_t c, float k,
+                                                      uint32_t pos) {
                 if (ok) {
                     E.t3_a[off + pos] = a;
                     E.t3_b[off + pos] = b;
@@ -636,33 +754,40 @@ __device__ __forceinline__ void t3_body(const EvDev &E, const Consts &K, SmT3 &s
     }
 }
 
+template <int G>
 __global__ __launch_bounds__(BLOCK) void k_t3(EvDev E, Consts K)
 {
     __shared__ SmT3 sm;
-    t3_body(E, K, sm);
+    t3_body<G>(E, K, sm);
 }
 
-hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s)
+hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
+                     hipStream_t s)
 {
     (void)M;
-    hipLaunchKernelGGL(k_t3, dim3(grid), dim3(BLOCK), 0, s, E, K);
+    LST_BY_LANES(lanes, k_t3, dim3(grid), dim3(BLOCK), 0, s, E, K);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- quintuplets
 // Candidates of inner MD a: every triplet (a,b,c) followed by every triplet
-// (c,d,e).  sink(ok, b, c, d, e, score, pos)
-template <class F>
-__device__ __forceinline__ uint32_t enum_t5(const EvDev &E, const Consts &K, int32_t a, F &&sink)
+// (c,d,e); one group of G lanes per inner MD.  sink(ok, b, c, d, e, score, pos)
+template <int G, class F>
+__device__ __forceinline__ uint32_t enum_t5(const EvDev &E, const Consts &K, int32_t a, bool act,
+                                            F &&sink)
 {
-    const int lane = lane_id();
-    const int32_t nt1 = E.t3_cnt[a];
-    const int32_t t10 = E.t3_start[a];
+    const Grp<G> gp;
+    int32_t nt1 = 0, t10 = 0;
+    if (act) {
+        nt1 = E.t3_cnt[a];
+        t10 = E.t3_start[a];
+    }
+    MdV A = {};
+    if (nt1 > 0) A = load_md(E, a);
     uint32_t cnt = 0;
-    if (nt1 <= 0) return 0;
-    const MdV A = load_md(E, a);
-    for (int32_t c1 = 0; c1 < nt1; c1 += 64) {
-        const int32_t k = c1 + lane;
+    const int32_t nt_max = (int32_t)wave_max((uint32_t)(nt1 > 0 ? nt1 : 0));
+    for (int32_t c1 = 0; c1 < nt_max; c1 += G) {
+        const int32_t k = c1 + gp.lane;
         int32_t t1 = 0, cs = 0;
         uint32_t nc = 0;
         if (k < nt1) {
@@ -671,14 +796,15 @@ __device__ __forceinline__ uint32_t enum_t5(const EvDev &E, const Consts &K, int
             cs = E.t3_start[c];
             nc = (uint32_t)E.t3_cnt[c];
         }
-        const uint32_t incl = wave_incl_scan(nc);
-        const uint32_t tot = __shfl(incl, 63, 64);
-        for (uint32_t jc = 0; jc < tot; jc += 64) {
-            const uint32_t j = jc + lane;
-            const int src = wave_find(incl, j < tot ? j : tot - 1);
-            const uint32_t ex = __shfl(incl, src, 64) - __shfl(nc, src, 64);
-            const int32_t tt1 = __shfl(t1, src, 64);
-            const int32_t tcs = __shfl(cs, src, 64);
+        const uint32_t incl = gp.incl_scan(nc);
+        const uint32_t tot = gp.bcast(incl, G - 1);
+        const uint32_t tot_max = wave_max(tot);
+        for (uint32_t jc = 0; jc < tot_max; jc += G) {
+            const uint32_t j = jc + gp.lane;
+            const int src = gp.find(incl, j < tot ? j : (tot ? tot - 1 : 0));
+            const uint32_t ex = gp.bcast(incl, src) - gp.bcast(nc, src);
+            const int32_t tt1 = gp.bcast(t1, src);
+            const int32_t tcs = gp.bcast(cs, src);
             bool ok = false;
             int32_t b = 0, c = 0, d = 0, e = 0;
             float score = 0.0f;
@@ -691,9 +817,10 @@ __device__ __forceinline__ uint32_t enum_t5(const EvDev &E, const Consts &K, int
                 ok = t5_accept(K, A, load_md(E, b), load_md(E, c), load_md(E, d), load_md(E, e),
                                E.t3_k[tt1], E.t3_k[t2], score);
             }
-            const unsigned long long mask = __ballot(ok);
-            sink(ok, b, c, d, e, score, cnt + (uint32_t)__popcll(mask & lanes_below()));
-            cnt += (uint32_t)__popcll(mask);
+            uint32_t t;
+            const uint32_t r = gp.rank(ok, t);
+            sink(ok, b, c, d, e, score, cnt + r);
+            cnt += t;
         }
     }
     return cnt;
@@ -712,52 +839,60 @@ __device__ __forceinline__ void write_t5(const EvDev &E, uint32_t at, int32_t a,
     E.t5_veto[at] = 0;
 }
 
+template <int G>
 __device__ __forceinline__ void t5_body(const EvDev &E, const Consts &K, SmT5 &sm)
 {
     if (upstream_overflow(E)) return;
+    constexpr int P = Grp<G>::P, CAP = STAGE / P;
+    const Grp<G> gp;
     const int w = wave_id();
     const Regions R = load_regions(E, OT_MD);
-    for (uint32_t base = blockIdx.x * WAVES; base < R.total; base += gridDim.x * WAVES) {
-        const uint32_t v = base + w;
+    for (uint32_t base = blockIdx.x * WAVES * P; base < R.total; base += gridDim.x * WAVES * P) {
+        const uint32_t v = base + w * P + gp.g;
         const bool act = v < R.total;
         const int32_t a = region_index(R, act ? v : 0);
-        uint32_t cnt = 0;
-        if (act)
-            cnt = enum_t5(E, K, a, [&](bool ok, int32_t b, int32_t c, int32_t d, int32_t e,
-                                       float sc, uint32_t pos) {
-                if (ok && pos < STAGE) {
-                    sm.b[w][pos] = b;
-                    sm.c[w][pos] = c;
-                    sm.d[w][pos] = d;
-                    sm.e[w][pos] = e;
-                    sm.s[w][pos] = sc;
-                }
-            });
+        const int q0 = gp.g * CAP;
+        const uint32_t cnt = enum_t5<G>(E, K, a, act, [&](bool ok, int32_t b, int32_t c, int32_t d,
+                                                          int32_t e, float sc, uint32_t pos) {
+            if (ok && pos < CAP) {
+                sm.b[w][q0 + pos] = b;
+                sm.c[w][q0 + pos] = c;
+                sm.d[w][q0 + pos] = d;
+                sm.e[w][q0 + pos] = e;
+                sm.s[w][q0 + pos] = sc;
+            }
+        });
+        uint32_t wtot;
+        const uint32_t gex = gp.wave_prefix(cnt, wtot);
         bool ovf;
-        const uint32_t off = block_reserve(cnt, E, OT_T5, ovf);
-        if (!act || ovf || cnt == 0) continue;
-        if (cnt <= STAGE) {
-            for (uint32_t k = lane_id(); k < cnt; k += 64)
-                write_t5(E, off + k, a, sm.b[w][k], sm.c[w][k], sm.d[w][k], sm.e[w][k], sm.s[w][k]);
-        } else {
-            enum_t5(E, K, a, [&](bool ok, int32_t b, int32_t c, int32_t d, int32_t e, float sc,
-                                 uint32_t pos) {
+        const uint32_t off = block_reserve(wtot, E, OT_T5, ovf) + gex;
+        if (ovf) continue;
+        if (act && cnt <= CAP) {
+            for (uint32_t k = gp.lane; k < cnt; k += G)
+                write_t5(E, off + k, a, sm.b[w][q0 + k], sm.c[w][q0 + k], sm.d[w][q0 + k],
+                         sm.e[w][q0 + k], sm.s[w][q0 + k]);
+        }
+        if (wave_max(cnt) > CAP) {
+            enum_t5<G>(E, K, a, act && cnt > CAP, [&](bool ok, int32_t b, int32_t c, int32_t d,
+                                                      int32_t e, float sc, uint32_t pos) {
                 if (ok) write_t5(E, off + pos, a, b, c, d, e, sc);
             });
         }
     }
 }
 
+template <int G>
 __global__ __launch_bounds__(BLOCK) void k_t5(EvDev E, Consts K)
 {
     __shared__ SmT5 sm;
-    t5_body(E, K, sm);
+    t5_body<G>(E, K, sm);
 }
 
-hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, int grid, hipStream_t s)
+hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
+                     hipStream_t s)
 {
     (void)M;
-    hipLaunchKernelGGL(k_t5, dim3(grid), dim3(BLOCK), 0, s, E, K);
+    LST_BY_LANES(lanes, k_t5, dim3(grid), dim3(BLOCK), 0, s, E, K);
     return hipGetLastError();
 }
 
@@ -771,15 +906,20 @@ hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, int grid,
 // score) and are resolved by the hit tuple.  A quintuplet vetoed by the
 // learned scorer takes no part.
 //
-// one thread per (quintuplet, hit)
+// one thread per (quintuplet, hit); the hit indices are cached per
+// quintuplet ([t][10], sorted and per-event) for the two later passes
 __device__ __forceinline__ void dedup_min_body(const EvDev &E, uint32_t *s_pre)
 {
     if (upstream_overflow(E)) return;
     const uint32_t n = t5_prefix(E, s_pre) * 10u;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const int32_t t = t5_at(E, s_pre, v / 10u);
+        const int j = (int)(v % 10u);
+        const int32_t h = t5_hit(E, t, j);
+        E.t5_hs[(size_t)t * 10 + j] = h;
+        E.t5_ho[(size_t)t * 10 + j] = E.sorig[h];
         if (E.t5_veto[t]) continue;
-        atomicMin(&E.hmin[t5_hit(E, t, (int)(v % 10u))], __float_as_uint(E.t5_score[t]));
+        atomicMin(&E.hmin[h], __float_as_uint(E.t5_score[t]));
     }
 }
 
@@ -790,7 +930,7 @@ __device__ __forceinline__ void dedup_tie_body(const EvDev &E, uint32_t *s_pre)
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const int32_t t = t5_at(E, s_pre, v / 10u);
         if (E.t5_veto[t]) continue;
-        const int32_t h = t5_hit(E, t, (int)(v % 10u));
+        const int32_t h = E.t5_hs[(size_t)t * 10 + (v % 10u)];
         if (E.hmin[h] == __float_as_uint(E.t5_score[t])) {
             const int k = atomicAdd(&E.htie[h], 1);
             if (k < TIE_SLOTS) {
@@ -807,17 +947,24 @@ __device__ __forceinline__ void dedup_tie_body(const EvDev &E, uint32_t *s_pre)
     }
 }
 
-// lexicographic order of the (per-event) hit-index tuples
-__device__ __forceinline__ bool tuple_less(const EvDev &E, int32_t u, int32_t t)
+// (score-tied) quintuplet u before the one whose per-event hit tuple is `own`
+__device__ __forceinline__ bool tuple_less(const EvDev &E, int32_t u, const int32_t *own)
 {
-    for (int j = 0; j < 10; ++j) {
-        const int32_t a = E.sorig[t5_hit(E, u, j)], b = E.sorig[t5_hit(E, t, j)];
-        if (a != b) return a < b;
+    const int2 *p = reinterpret_cast<const int2 *>(E.t5_ho + (size_t)u * 10);
+    int32_t o[10];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int2 q = p[k];
+        o[2 * k] = q.x;
+        o[2 * k + 1] = q.y;
     }
+#pragma unroll
+    for (int j = 0; j < 10; ++j)
+        if (o[j] != own[j]) return o[j] < own[j];
     return false;
 }
 
-// one thread per quintuplet; the ten hit lookups are independent loads
+// one thread per quintuplet
 __device__ __forceinline__ void dedup_keep_body(const EvDev &E, uint32_t *s_pre)
 {
     if (upstream_overflow(E)) return;
@@ -830,11 +977,19 @@ __device__ __forceinline__ void dedup_keep_body(const EvDev &E, uint32_t *s_pre)
         }
         const float sc = E.t5_score[t];
         const uint32_t key = __float_as_uint(sc);
-        int32_t h[10];
+        int32_t h[10], own[10];
+        const int2 *ph = reinterpret_cast<const int2 *>(E.t5_hs + (size_t)t * 10);
+        const int2 *po = reinterpret_cast<const int2 *>(E.t5_ho + (size_t)t * 10);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const int2 a = ph[k], b = po[k];
+            h[2 * k] = a.x;
+            h[2 * k + 1] = a.y;
+            own[2 * k] = b.x;
+            own[2 * k + 1] = b.y;
+        }
         uint32_t hm[10];
         int nt[10];
-#pragma unroll
-        for (int j = 0; j < 10; ++j) h[j] = t5_hit(E, t, j);
 #pragma unroll
         for (int j = 0; j < 10; ++j) {
             hm[j] = E.hmin[h[j]];
@@ -848,23 +1003,23 @@ __device__ __forceinline__ void dedup_keep_body(const EvDev &E, uint32_t *s_pre)
             const int ns = nt[j] < TIE_SLOTS ? nt[j] : TIE_SLOTS;
             for (int k = 0; k < ns && keep; ++k) {
                 const int32_t u = E.hslot[(size_t)h[j] * TIE_SLOTS + k];
-                if (u != t && tuple_less(E, u, t)) keep = false;
+                if (u != t && tuple_less(E, u, own)) keep = false;
             }
             if (nt[j] <= TIE_SLOTS || !keep) continue;
             // further ties are chained in the pool
             int listed = 0;
             for (int32_t e = E.thead[h[j]]; e != 0 && keep; e = E.tpool_next[e - 1], ++listed) {
                 const int32_t u = E.tpool_t5[e - 1];
-                if (u != t && tuple_less(E, u, t)) keep = false;
+                if (u != t && tuple_less(E, u, own)) keep = false;
             }
             if (keep && listed < nt[j] - TIE_SLOTS) {
                 // the pool ran out: scan every quintuplet (correct, slow)
                 for (uint32_t q = 0; q < n && keep; ++q) {
                     const int32_t u = t5_at(E, s_pre, q);
-                    if (u == t || E.t5_score[u] != sc) continue;
+                    if (u == t || E.t5_veto[u] || E.t5_score[u] != sc) continue;
                     bool uses = false;
-                    for (int k = 0; k < 10; ++k) uses |= (t5_hit(E, u, k) == h[j]);
-                    if (uses && tuple_less(E, u, t)) keep = false;
+                    for (int k = 0; k < 10; ++k) uses |= (E.t5_hs[(size_t)u * 10 + k] == h[j]);
+                    if (uses && tuple_less(E, u, own)) keep = false;
                 }
             }
         }
@@ -942,6 +1097,7 @@ hipError_t launch_t5_features(const EvDev &E, const Consts &K, int grid, hipStre
 // occupancy query); if it is not, the poll gives up after a bounded time,
 // raises error bit 1 and the blocks leave, so the kernel always terminates.
 constexpr int BAR_SH = 32;
+constexpr int BAR_PAD = 64;   // uint32 stride: each barrier counter on its own 256-byte line
 constexpr uint32_t BAR_SPIN_LIMIT = 1u << 19;   // ~0.5 s of polling
 
 __device__ __forceinline__ bool grid_sync(const EvDev &E, uint32_t gen)
@@ -951,14 +1107,17 @@ __device__ __forceinline__ bool grid_sync(const EvDev &E, uint32_t gen)
     const uint32_t nsh = G < (uint32_t)BAR_SH ? G : (uint32_t)BAR_SH;
     const uint32_t sh = b % BAR_SH;
     const uint32_t shard_size = (G - sh + BAR_SH - 1) / BAR_SH;
-    __threadfence();
+    // the block's stores are complete at the workgroup barrier; one thread
+    // then releases them to the device (L2 write-back) and, once everyone has
+    // arrived, acquires the others' (invalidation) for the whole block
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t old = atomicAdd(&E.bar[sh], 1u);
-        if (old + 1u == gen * shard_size) atomicAdd(&E.bar[BAR_SH], 1u);
+        __threadfence();
+        const uint32_t old = atomicAdd(&E.bar[sh * BAR_PAD], 1u);
+        if (old + 1u == gen * shard_size) atomicAdd(&E.bar[BAR_SH * BAR_PAD], 1u);
         int ok = 1;
         uint32_t it = 0;
-        while (__hip_atomic_load(&E.bar[BAR_SH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+        while (__hip_atomic_load(&E.bar[BAR_SH * BAR_PAD], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
                gen * nsh) {
             if (++it > BAR_SPIN_LIMIT) {
                 ok = 0;
@@ -967,18 +1126,20 @@ __device__ __forceinline__ bool grid_sync(const EvDev &E, uint32_t gen)
             }
             __builtin_amdgcn_s_sleep(2);
         }
+        __threadfence();
         s_ok = ok;
     }
     __syncthreads();
-    __threadfence();
     return s_ok != 0;
 }
 
 __global__ void k_bar_reset(uint32_t *bar)
 {
-    if (threadIdx.x <= BAR_SH) bar[threadIdx.x] = 0u;
+    if (threadIdx.x <= BAR_SH) bar[threadIdx.x * BAR_PAD] = 0u;
 }
 
+// G: group width of the four object stages
+template <int G>
 __global__ __launch_bounds__(BLOCK) void k_chain(EvDev E, ModDev M, Consts K, uint4 *zero_base,
                                                  size_t zero16, int stop_before_dedup)
 {
@@ -990,21 +1151,17 @@ __global__ __launch_bounds__(BLOCK) void k_chain(EvDev E, ModDev M, Consts K, ui
     LST_SYNC();
     hist_body(E, M.n_mod);
     LST_SYNC();
-    scan_reduce_body(E);
-    LST_SYNC();
-    scan_top_body(E);
-    LST_SYNC();
-    scan_down_body(E);
+    scan_body(E);
     LST_SYNC();
     scatter_body(E, M.n_mod);
     LST_SYNC();
-    md_body(E, M, K, sm.u.md);
+    md_body<G>(E, M, K, sm.u.md);
     LST_SYNC();
-    seg_body(E, M, K, sm.u.seg);
+    seg_body<G>(E, M, K, sm.u.seg);
     LST_SYNC();
-    t3_body(E, K, sm.u.t3);
+    t3_body<G>(E, K, sm.u.t3);
     LST_SYNC();
-    t5_body(E, K, sm.u.t5);
+    t5_body<G>(E, K, sm.u.t5);
     if (stop_before_dedup) return;
     LST_SYNC();
     dedup_min_body(E, sm.pre);
@@ -1015,20 +1172,31 @@ __global__ __launch_bounds__(BLOCK) void k_chain(EvDev E, ModDev M, Consts K, ui
 #undef LST_SYNC
 }
 
-int persistent_blocks_per_cu()
+template <int G>
+static int occupancy_of_chain()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain, BLOCK, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<G>, BLOCK, 0) != hipSuccess) return 0;
     return nb;
 }
 
+int persistent_blocks_per_cu(int lanes)
+{
+    switch (lanes) {
+    case 8: return occupancy_of_chain<8>();
+    case 16: return occupancy_of_chain<16>();
+    case 32: return occupancy_of_chain<32>();
+    default: return occupancy_of_chain<64>();
+    }
+}
+
 hipError_t launch_chain_persistent(const EvDev &E, const ModDev &M, const Consts &K,
-                                   void *zero_base, size_t zero_bytes, int grid,
+                                   void *zero_base, size_t zero_bytes, int grid, int lanes,
                                    bool stop_before_dedup, hipStream_t s)
 {
     hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, s, E.bar);
-    hipLaunchKernelGGL(k_chain, dim3(grid), dim3(BLOCK), 0, s, E, M, K, (uint4 *)zero_base,
-                       zero_bytes / 16, stop_before_dedup ? 1 : 0);
+    LST_BY_LANES(lanes, k_chain, dim3(grid), dim3(BLOCK), 0, s, E, M, K, (uint4 *)zero_base,
+                 zero_bytes / 16, stop_before_dedup ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -79,7 +79,7 @@ _SIGS = {
     "lst_run_t5_features": (ctypes.c_int, [_P, _P]),
     "lst_get_t5_features": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64,
                                            ctypes.POINTER(ctypes.c_int64), _P]),
-    "lst_set_tuning": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32]),
+    "lst_set_tuning": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32]),
     "lst_get_tuning": (ctypes.c_int, [_P, _P]),
     "lst_tune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_int32, _P, _P]),
     "lst_mlp_load": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.c_float]),
@@ -273,14 +273,16 @@ class Context:
         self._check(self.lib.lst_run_chain_persistent(self.h, self._stream(stream)))
 
     def tuning(self) -> dict:
-        out = np.zeros(9, np.int32)
+        out = np.zeros(15, np.int32)
         self._check(self.lib.lst_get_tuning(self.h, _np_ptr(out)))
-        return dict(grid=out[:6].tolist(), persistent=int(out[6]), blocks_per_cu=int(out[7]),
-                    n_cu=int(out[8]))
+        return dict(grid=out[:6].tolist(), lanes=out[6:12].tolist(), persistent=int(out[12]),
+                    blocks_per_cu=int(out[13]), n_cu=int(out[14]))
 
-    def set_tuning(self, grid, persistent=0, blocks_per_cu=1):
+    def set_tuning(self, grid, persistent=0, blocks_per_cu=1, lanes=None):
         g = np.ascontiguousarray(grid, np.int32)
-        self._check(self.lib.lst_set_tuning(self.h, _np_ptr(g), int(persistent), int(blocks_per_cu)))
+        ln = None if lanes is None else np.ascontiguousarray(lanes, np.int32)
+        self._check(self.lib.lst_set_tuning(self.h, _np_ptr(g), None if ln is None else _np_ptr(ln),
+                                            int(persistent), int(blocks_per_cu)))
 
     def tune(self, cache_path=None, reps=5, stream=None) -> dict:
         """Autotune the launch shape on the loaded batch (see lst_tune)."""

@@ -218,6 +218,37 @@ def test_persistent_chain_matches_oracle():
     assert_parity(got, oracle.Oracle(params, geo2.f32, geo2.i32).run_event(ev))
 
 
+@pytest.mark.parametrize("lanes", [8, 16, 32, 64])
+def test_group_widths_match_oracle(lanes):
+    """Every group width of the object stages (lanes per inner object), per
+    stage launches and the persistent kernel, on a PU200-like event and a
+    ragged batch."""
+    import paper_2209_13711_amd as lst
+    params = PR.make()
+    geo = G.get("full")
+    ev = E.generate(2, 2, n_tracks=1500)
+    print(f"case lanes {lanes} pu200-1500", flush=True)
+    ref = oracle.Oracle(params, geo.f32, geo.i32).run_event(ev)
+    ctx = _ctx(geo, params)
+    ctx.run_event(ev)
+    t = ctx.tuning()
+    widths = [64, lanes, lanes, lanes, lanes, 64]
+    ctx.set_tuning(t["grid"], persistent=0, blocks_per_cu=1, lanes=widths)
+    assert ctx.tuning()["lanes"] == widths
+    assert_parity(ctx.run_event(ev), ref)
+    ctx.set_tuning(t["grid"], persistent=1, blocks_per_cu=1, lanes=widths)
+    assert_parity(ctx.run_event(ev), ref)
+    geo_b = G.get("barrel_toy")
+    orc = oracle.Oracle(params, geo_b.f32, geo_b.i32)
+    evs = [E.generate(3, 20 + e) for e in range(3)] + [E.generate(1, 3)]
+    b = E.concat(evs)
+    ctx_b = _ctx(geo_b, params)
+    ctx_b.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+    ctx_b.set_tuning(ctx_b.tuning()["grid"], persistent=0, blocks_per_cu=1, lanes=widths)
+    ctx_b.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+    _batch_parity(ctx_b, evs, orc)
+
+
 def test_autotuner_keeps_results_and_caches(tmp_path):
     geo = G.get("barrel_toy")
     params = PR.make()
@@ -239,6 +270,7 @@ def test_autotuner_keeps_results_and_caches(tmp_path):
     res2 = ctx2.tune(cache_path=cache, reps=2)
     assert res2["report_us"][0] == -1.0
     assert res2["grid"] == res["grid"] and res2["persistent"] == res["persistent"]
+    assert res2["lanes"] == res["lanes"]
     ctx2.load_hits(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
     ctx2.run_chain_graph()
     _batch_parity(ctx2, evs, orc)
