@@ -64,6 +64,12 @@ def _load():
     lib.orc_t5_keep.argtypes = [P, P]
     lib.orc_t3_curv.argtypes = [P, P]
     lib.orc_t5_features.argtypes = [P, P]
+    lib.orc_t3_features.argtypes = [P, P]
+    lib.orc_rerun_t5.restype = ctypes.c_int
+    lib.orc_rerun_t5.argtypes = [P, P]
+    for f in ("orc_eval_t3_features", "orc_eval_t5_features"):
+        getattr(lib, f).restype = ctypes.c_int
+        getattr(lib, f).argtypes = [P, P, P, P]
     lib.orc_near_count.restype = ctypes.c_int64
     lib.orc_near_count.argtypes = [P, ctypes.c_int]
     lib.orc_near.argtypes = [P, ctypes.c_int, P, P, P]
@@ -89,6 +95,7 @@ class Result:
     t5_keep: np.ndarray
     t3_curv: np.ndarray
     t5_features: np.ndarray  # float32 [n_t5, 40]
+    t3_features: np.ndarray  # float32 [n_t3, 40]
     cands: np.ndarray       # int64 [4]
     near: dict              # kind -> (tuples, margins, decisions)
 
@@ -140,6 +147,19 @@ class Oracle:
     def run_event(self, ev) -> Result:
         return self.run(ev.x, ev.y, ev.z, ev.module, ev.sensor)
 
+    def rerun_t5(self, t3_veto=None) -> Result:
+        """Quintuplets and duplicate removal again on the last event's
+        triplets, those with t3_veto set (order of the T3 tuples) left out."""
+        if t3_veto is None:
+            rc = self._lib.orc_rerun_t5(self._h, None)
+        else:
+            v = np.ascontiguousarray(t3_veto, np.uint8)
+            assert v.shape[0] == self._lib.orc_count(self._h, T3)
+            rc = self._lib.orc_rerun_t5(self._h, _ptr(v))
+        if rc != 0:
+            raise ValueError("oracle: no event to rerun")
+        return self._collect()
+
     def _collect(self) -> Result:
         lib, h = self._lib, self._h
         tuples = {}
@@ -155,6 +175,7 @@ class Oracle:
         k3 = np.zeros(max(n3, 1), np.float32); lib.orc_t3_curv(h, _ptr(k3))
         cands = np.zeros(4, np.int64); lib.orc_cands(h, _ptr(cands))
         ft = np.zeros((max(n5, 1), 40), np.float32); lib.orc_t5_features(h, _ptr(ft))
+        f3 = np.zeros((max(n3, 1), 40), np.float32); lib.orc_t3_features(h, _ptr(f3))
         near = {}
         for kind in (MD, SEG, T3, T5):
             nn = lib.orc_near_count(h, kind)
@@ -164,7 +185,8 @@ class Oracle:
             lib.orc_near(h, kind, _ptr(tt), _ptr(mg), _ptr(dc))
             near[kind] = (tt[:nn], mg[:nn], dc[:nn])
         return Result(tuples=tuples, t5_scores=sc[:n5], t5_keep=kp[:n5].astype(bool),
-                      t3_curv=k3[:n3], t5_features=ft[:n5], cands=cands, near=near)
+                      t3_curv=k3[:n3], t5_features=ft[:n5], t3_features=f3[:n3], cands=cands,
+                      near=near)
 
     # -- single-candidate evaluation (closed-form checks) -------------------
     def eval_md(self, module: int, lo3, up3):
@@ -189,3 +211,17 @@ class Oracle:
 
     def eval_t5(self, mods, hits):
         return self._eval(self._lib.orc_eval_t5, 5, mods, hits, 18)
+
+    def _eval_f(self, fn, n, mods, hits):
+        mods = np.ascontiguousarray(mods, np.int32)
+        hits = np.ascontiguousarray(hits, np.float32).reshape(-1)
+        assert mods.shape[0] == n and hits.shape[0] == 6 * n
+        out = np.zeros(40, np.float32)
+        p = fn(self._h, _ptr(mods), _ptr(hits), _ptr(out))
+        return bool(p), out
+
+    def eval_t3_features(self, mods, hits):
+        return self._eval_f(self._lib.orc_eval_t3_features, 3, mods, hits)
+
+    def eval_t5_features(self, mods, hits):
+        return self._eval_f(self._lib.orc_eval_t5_features, 5, mods, hits)

@@ -63,6 +63,10 @@ typedef struct {
     double kbr, resb, resd, pullb, pulld, zpull[3], chi2p, chi2z, score, tin, tout, sl, lae, kO;
 } T5AUX;
 
+typedef struct {
+    double k, kO, dz, sl, lac, ra, rc, rhs[3];
+} T3AUX;
+
 /* float instance: the decisions */
 #define R float
 #define FN(name) name##_f
@@ -126,7 +130,7 @@ static void gv_clear(gvec *a) { a->n = 0; }
 static void gv_free(gvec *a) { free(a->v); a->v = NULL; a->n = a->cap = 0; }
 
 typedef struct { int32_t i, o; } SEGREC;
-typedef struct { int32_t a, b, c; float k; } T3REC;
+typedef struct { int32_t a, b, c; float k; float feat[40]; } T3REC;
 typedef struct { int32_t md[5]; float score; float feat[40]; } T5REC;
 typedef struct { int32_t hits[10]; double margin; uint8_t decision; } NEARREC;
 
@@ -141,6 +145,8 @@ struct orc {
     gvec md, seg, t3, t5, near[4];
     int32_t *seg_off, *t3_off;
     uint8_t *keep;
+    uint8_t *t3_veto;   /* triplets excluded from the quintuplet stage (or NULL) */
+    int32_t n_hits;
     int64_t cand[4];
 };
 
@@ -344,7 +350,10 @@ static void free_event(orc *o)
     free(o->seg_off); o->seg_off = NULL;
     free(o->t3_off); o->t3_off = NULL;
     free(o->keep); o->keep = NULL;
+    free(o->t3_veto); o->t3_veto = NULL;
 }
+
+static void run_t5_dedup(orc *o);
 
 void orc_destroy(orc *o)
 {
@@ -529,11 +538,14 @@ int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float 
                     float kf;
                     double kd;
                     o->cand[2]++;
-                    int pass = t3_cut_f(&o->K, &MD[a], &MD[b], &MD[c], &cf, &kf);
-                    t3_cut_d(&o->K, &MD[a], &MD[b], &MD[c], &cd, &kd);
+                    T3AUX ax;
+                    int pass = t3_cut_f(&o->K, &MD[a], &MD[b], &MD[c], &cf, &kf, &ax);
+                    t3_cut_d(&o->K, &MD[a], &MD[b], &MD[c], &cd, &kd, NULL);
                     if (pass) {
                         T3REC *t = (T3REC *)gv_push(&o->t3);
                         t->a = (int32_t)a; t->b = b; t->c = c; t->k = kf;
+                        const MDREC *P3[3] = {&MD[a], &MD[b], &MD[c]};
+                        t3_features_f(&o->K, P3, &ax, t->feat);
                     }
                     double mg = cut_margin(&cf, &cd);
                     if (mg < NEAR_REL) {
@@ -545,6 +557,21 @@ int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float 
         }
         o->t3_off[n_md] = (int32_t)o->t3.n;
     }
+    o->n_hits = n_hits;
+    run_t5_dedup(o);
+    return 0;
+}
+
+/* 4. quintuplets and 5. duplicate removal, on the stored triplets; a
+ * triplet with t3_veto set takes no part in any quintuplet */
+static void run_t5_dedup(orc *o)
+{
+    const MDREC *MD = (const MDREC *)o->md.v;
+    const int32_t n_hits = o->n_hits;
+    gv_clear(&o->t5);
+    gv_clear(&o->near[3]);
+    o->cand[3] = 0;
+    free(o->keep); o->keep = NULL;
     const T3REC *T3 = (const T3REC *)o->t3.v;
 
     /* 4. quintuplets: triplet (a,b,c) with every triplet (c,d,e) */
@@ -553,6 +580,10 @@ int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float 
         for (int32_t t2 = o->t3_off[c]; t2 < o->t3_off[c + 1]; ++t2) {
             const MDREC *P[5] = {&MD[T3[t].a], &MD[T3[t].b], &MD[c], &MD[T3[t2].b],
                                  &MD[T3[t2].c]};
+            if (o->t3_veto && (o->t3_veto[t] || o->t3_veto[t2])) {
+                o->cand[3]++;   /* still a candidate pair of the stage */
+                continue;
+            }
             CUTREC cf, cd;
             T5AUX af, ad;
             o->cand[3]++;
@@ -608,7 +639,6 @@ int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float 
         o->keep[t] = (uint8_t)!removed;
     }
     free(tup); free(hoff); free(hcur); free(hlist);
-    return 0;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -676,6 +706,26 @@ void orc_t5_features(const orc *o, float *out)
 {
     const T5REC *T5 = (const T5REC *)o->t5.v;
     for (int64_t i = 0; i < o->t5.n; ++i) memcpy(&out[40 * i], T5[i].feat, sizeof(T5[i].feat));
+}
+
+void orc_t3_features(const orc *o, float *out)
+{
+    const T3REC *T3 = (const T3REC *)o->t3.v;
+    for (int64_t i = 0; i < o->t3.n; ++i) memcpy(&out[40 * i], T3[i].feat, sizeof(T3[i].feat));
+}
+
+int orc_rerun_t5(orc *o, const uint8_t *t3_veto)
+{
+    if (!o->t3_off) return -1;
+    free(o->t3_veto);
+    o->t3_veto = NULL;
+    if (t3_veto) {
+        o->t3_veto = (uint8_t *)malloc((size_t)(o->t3.n > 0 ? o->t3.n : 1));
+        if (!o->t3_veto) return -1;
+        memcpy(o->t3_veto, t3_veto, (size_t)o->t3.n);
+    }
+    run_t5_dedup(o);
+    return 0;
 }
 
 void orc_t3_curv(const orc *o, float *out)
@@ -748,9 +798,38 @@ int orc_eval_t3(const orc *o, const int32_t *mods3, const float *hits18, double 
     eval_mds(o, 3, mods3, hits18, md);
     CUTREC cf;
     float k;
-    int pass = t3_cut_f(&o->K, &md[0], &md[1], &md[2], &cf, &k);
+    int pass = t3_cut_f(&o->K, &md[0], &md[1], &md[2], &cf, &k, NULL);
     for (int j = 0; j < 3; ++j) { out[2 * j] = cf.lhs[j]; out[2 * j + 1] = cf.rhs[j]; }
     out[6] = k;
+    return pass;
+}
+
+/* the 40 scorer features of one triplet / quintuplet built from the given MDs */
+int orc_eval_t3_features(const orc *o, const int32_t *mods3, const float *hits18, float *out40)
+{
+    MDREC md[3];
+    eval_mds(o, 3, mods3, hits18, md);
+    CUTREC cf;
+    float k;
+    T3AUX ax;
+    int pass = t3_cut_f(&o->K, &md[0], &md[1], &md[2], &cf, &k, &ax);
+    const MDREC *P[3] = {&md[0], &md[1], &md[2]};
+    t3_features_f(&o->K, P, &ax, out40);
+    return pass;
+}
+
+int orc_eval_t5_features(const orc *o, const int32_t *mods5, const float *hits30, float *out40)
+{
+    MDREC md[5];
+    eval_mds(o, 5, mods5, hits30, md);
+    CUTREC c3, cf;
+    float kin, kout;
+    t3_cut_f(&o->K, &md[0], &md[1], &md[2], &c3, &kin, NULL);
+    t3_cut_f(&o->K, &md[2], &md[3], &md[4], &c3, &kout, NULL);
+    const MDREC *P[5] = {&md[0], &md[1], &md[2], &md[3], &md[4]};
+    T5AUX ax;
+    int pass = t5_cut_f(&o->K, P, kin, kout, &cf, &ax);
+    t5_features_f(&o->K, P, kin, kout, &ax, out40);
     return pass;
 }
 
@@ -762,8 +841,8 @@ int orc_eval_t5(const orc *o, const int32_t *mods5, const float *hits30, double 
     eval_mds(o, 5, mods5, hits30, md);
     CUTREC c3;
     float kin, kout;
-    t3_cut_f(&o->K, &md[0], &md[1], &md[2], &c3, &kin);
-    t3_cut_f(&o->K, &md[2], &md[3], &md[4], &c3, &kout);
+    t3_cut_f(&o->K, &md[0], &md[1], &md[2], &c3, &kin, NULL);
+    t3_cut_f(&o->K, &md[2], &md[3], &md[4], &c3, &kout, NULL);
     const MDREC *P[5] = {&md[0], &md[1], &md[2], &md[3], &md[4]};
     CUTREC cf;
     T5AUX ax;

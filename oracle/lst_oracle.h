@@ -65,8 +65,13 @@ void orc_cands(const orc *o, int64_t *out4);
 void orc_t5_scores(const orc *o, float *out);
 void orc_t5_keep(const orc *o, uint8_t *out);
 void orc_t3_curv(const orc *o, float *out);
-/* 40 FP32 features of every quintuplet, in the order of orc_tuples(ORC_T5) */
+/* 40 FP32 features of every quintuplet / triplet, in the order of orc_tuples */
 void orc_t5_features(const orc *o, float *out40);
+void orc_t3_features(const orc *o, float *out40);
+/* quintuplets and duplicate removal again on the stored triplets, with the
+ * triplets whose t3_veto entry is set (orc_tuples(ORC_T3) order; NULL: none)
+ * excluded from every quintuplet */
+int orc_rerun_t5(orc *o, const uint8_t *t3_veto);
 
 /* candidates whose FP64 margin is below 1e-5 (relative): tuple, margin and
  * the FP32 decision; kind 0..3 */
@@ -81,6 +86,8 @@ int orc_eval_md(const orc *o, int module, const float *lo3, const float *up3, do
 int orc_eval_seg(const orc *o, const int32_t *mods2, const float *hits12, double *out);
 int orc_eval_t3(const orc *o, const int32_t *mods3, const float *hits18, double *out);
 int orc_eval_t5(const orc *o, const int32_t *mods5, const float *hits30, double *out);
+int orc_eval_t3_features(const orc *o, const int32_t *mods3, const float *hits18, float *out40);
+int orc_eval_t5_features(const orc *o, const int32_t *mods5, const float *hits30, float *out40);
 
 /* derived FP32 constants (for inspection): kmax, klim, kh, tolu, tolv, tolkc, epsak */
 void orc_consts(const orc *o, float *out7);
