@@ -202,6 +202,16 @@ int lst_run_t5_features(lst_ctx *ctx, void *stream);
 int lst_get_t5_features(lst_ctx *ctx, int32_t event, float *out_host, int64_t cap_rows,
                         int64_t *n_rows, void *stream);
 
+/* The 40 FP32 features of every stored triplet (22 used, the rest zero):
+ * per mini-doublet r/100, z/100, bend pull, endcap flag, 2S flag; curvature
+ * over kappa_max; each triplet cut's left-hand side over its limit (|k|,
+ * signed k - k_origin, signed r-z residual); r-z slope; chord/100; an
+ * impact-parameter estimate.  After lst_run_triplets; order of
+ * lst_get_objects(LST_T3). */
+int lst_run_t3_features(lst_ctx *ctx, void *stream);
+int lst_get_t3_features(lst_ctx *ctx, int32_t event, float *out_host, int64_t cap_rows,
+                        int64_t *n_rows, void *stream);
+
 /* Quintuplet scores (chi2_rphi + chi2_rz) of `event`, in the order of
  * lst_get_objects(LST_T5). */
 int lst_get_t5_scores(lst_ctx *ctx, int32_t event, float *out_host, int64_t cap,
@@ -259,26 +269,37 @@ int lst_stream_copy(void *dst, const void *src, size_t n_bytes, void *stream);
  * to BF16 again before the second; w3, biases and the last layer are FP32.
  * A quintuplet is accepted iff logit >= threshold. */
 
-/* Copy the scorer (host arrays: LST_MLP_NPARAM parameters, mean[40],
- * istd[40]) and the logit threshold into the context.  Synchronous; values
- * must be finite (else LST_E_INVALID). */
-int lst_mlp_load(lst_ctx *ctx, const float *params, int32_t n_params, const float *mean,
-                 const float *istd, float threshold);
+/* Copy the scorer of `kind` (LST_T3: triplets, LST_T5: quintuplets; host
+ * arrays: LST_MLP_NPARAM parameters, mean[40], istd[40]) and its logit
+ * threshold into the context.  Synchronous; values must be finite (else
+ * LST_E_INVALID).  Each kind has its own network; either or both may be
+ * loaded. */
+int lst_mlp_load(lst_ctx *ctx, int32_t kind, const float *params, int32_t n_params,
+                 const float *mean, const float *istd, float threshold);
 
-/* LST_MODE_CUTS or LST_MODE_MLP (needs lst_mlp_load first, else
- * LST_E_STATE).  lst_run_chain, lst_run_chain_graph and
- * lst_run_chain_persistent then include the scoring step. */
+/* LST_MODE_CUTS or LST_MODE_MLP (needs lst_mlp_load of at least one kind,
+ * else LST_E_STATE).  lst_run_chain, lst_run_chain_graph and
+ * lst_run_chain_persistent then include a scoring step for every loaded
+ * kind: triplets are scored before the quintuplet stage (a vetoed triplet
+ * joins no quintuplet), quintuplets before duplicate removal (a vetoed
+ * quintuplet takes no part in it). */
 int lst_set_mode(lst_ctx *ctx, int32_t mode);
 
-/* The scoring step on its own, between lst_run_quintuplets and lst_run_dedup
- * (else LST_E_STATE): features computed on the device for every stored
- * quintuplet, logit stored, veto set when logit < threshold.  Asynchronous. */
+/* The scoring steps on their own (else LST_E_STATE): lst_run_t3_score
+ * between lst_run_triplets and lst_run_quintuplets, lst_run_t5_score between
+ * lst_run_quintuplets and lst_run_dedup.  Features are computed on the device
+ * for every stored object, the logit stored, the veto set when logit <
+ * threshold.  Asynchronous. */
+int lst_run_t3_score(lst_ctx *ctx, void *stream);
 int lst_run_t5_score(lst_ctx *ctx, void *stream);
 
 /* Logits and vetoes (1 = rejected) of `event`'s quintuplets in the order of
  * lst_get_objects(LST_T5); host outputs of capacity cap.  Meaningful after a
  * scoring step. */
 int lst_get_t5_logits(lst_ctx *ctx, int32_t event, float *logits_host, uint8_t *veto_host,
+                      int64_t cap, int64_t *n, void *stream);
+/* the same for triplets, in the order of lst_get_objects(LST_T3) */
+int lst_get_t3_logits(lst_ctx *ctx, int32_t event, float *logits_host, uint8_t *veto_host,
                       int64_t cap, int64_t *n, void *stream);
 
 /* ---- Training (device pointers, asynchronous on `stream`, ctx's device) ----

@@ -28,17 +28,17 @@ __device__ __forceinline__ int32_t t5_hit(const EvDev &E, int32_t t, int j)
     return (j & 1) ? E.md_hup[md] : E.md_hlo[md];
 }
 
-// Compact index over the stored quintuplets: the block keeps the prefix of
-// the NSH region sizes in LDS; a thread maps v to its array index with a
-// binary search over it.
-__device__ __forceinline__ uint32_t t5_prefix(const EvDev &E, uint32_t *s_pre)
+// Compact index over the stored objects of one type: the block keeps the
+// prefix of the NSH region sizes in LDS; a thread maps v to its array index
+// with a binary search over it.
+__device__ __forceinline__ uint32_t obj_prefix(const EvDev &E, int type, uint32_t *s_pre)
 {
     if (threadIdx.x == 0) {
-        const uint32_t rc = E.rc[OT_T5];
+        const uint32_t rc = E.rc[type];
         uint32_t acc = 0;
         for (int r = 0; r < NSH; ++r) {
             s_pre[r] = acc;
-            const uint32_t c = E.gc[gc_shard(OT_T5, r)];
+            const uint32_t c = E.gc[gc_shard(type, r)];
             acc += c < rc ? c : rc;
         }
         s_pre[NSH] = acc;
@@ -47,14 +47,24 @@ __device__ __forceinline__ uint32_t t5_prefix(const EvDev &E, uint32_t *s_pre)
     return s_pre[NSH];
 }
 
-__device__ __forceinline__ int32_t t5_at(const EvDev &E, const uint32_t *s_pre, uint32_t v)
+__device__ __forceinline__ int32_t obj_at(const EvDev &E, int type, const uint32_t *s_pre, uint32_t v)
 {
     int lo = 0, hi = NSH - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (s_pre[mid] <= v) lo = mid; else hi = mid - 1;
     }
-    return (int32_t)((uint32_t)lo * E.rc[OT_T5] + (v - s_pre[lo]));
+    return (int32_t)((uint32_t)lo * E.rc[type] + (v - s_pre[lo]));
+}
+
+__device__ __forceinline__ uint32_t t5_prefix(const EvDev &E, uint32_t *s_pre)
+{
+    return obj_prefix(E, OT_T5, s_pre);
+}
+
+__device__ __forceinline__ int32_t t5_at(const EvDev &E, const uint32_t *s_pre, uint32_t v)
+{
+    return obj_at(E, OT_T5, s_pre, v);
 }
 
 }  // namespace lst

@@ -57,8 +57,10 @@ struct lst_ctx {
     bool features_valid = false;
     // learned scorer
     int mode = LST_MODE_CUTS;
-    float *mlp_dev = nullptr;   // params [MLP_NPARAM], mean [40], istd [40]
-    float mlp_threshold = 0.0f;
+    // per kind (0 triplets, 1 quintuplets): params [MLP_NPARAM], mean [40], istd [40]
+    float *mlp_dev[2] = {nullptr, nullptr};
+    float mlp_threshold[2] = {0.0f, 0.0f};
+    bool t3_features_valid = false;
     std::vector<lst_counts> counts;
     bool counts_valid = false;
     int stage = 0;  // 0 nothing, 1 hits loaded, 2 sorted, 3 md, 4 seg, 5 t3, 6 t5, 7 dedup
@@ -209,6 +211,9 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.t3_k = cv.take<float>(nt3);
     E.t3_start = cv.take<int32_t>(nmd);
     E.t3_cnt = cv.take<int32_t>(nmd);
+    E.t3_veto = cv.take<uint8_t>(nt3);
+    E.t3_logit = cv.take<float>(nt3);
+    E.t3_feat = k.features ? cv.take<float>(nt3 * 40) : nullptr;
     // quintuplets
     E.t5_md0 = cv.take<int32_t>(nt5);
     E.t5_md1 = cv.take<int32_t>(nt5);
@@ -275,7 +280,8 @@ void lst_destroy(lst_ctx *c)
     if (c->stage_host) (void)hipHostFree(c->stage_host);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->geo_dev) (void)hipFree(c->geo_dev);
-    if (c->mlp_dev) (void)hipFree(c->mlp_dev);
+    for (float *p : c->mlp_dev)
+        if (p) (void)hipFree(p);
     delete c;
 }
 
@@ -316,8 +322,23 @@ int lst_load_geometry(lst_ctx *c, int32_t n, const float *f32, const int32_t *i3
     const size_t nb = sizeof(int32_t) * 2 * n;
     const size_t np = sizeof(int32_t) * (n + 1);
     const size_t nc = sizeof(int32_t) * std::max<size_t>(c->map_col.size(), 1);
+    // modules by azimuthal sector (NXCD sectors of the module centre's phi), then layer
+    std::vector<int32_t> order(n), sector(n);
+    int32_t sec_cnt[NXCD] = {};
+    for (int m = 0; m < n; ++m) {
+        const double phi = std::atan2((double)f32[n + m], (double)f32[m]);   // (-pi, pi]
+        int s = (int)std::floor((phi + M_PI) / (2.0 * M_PI) * NXCD);
+        sector[m] = std::min(NXCD - 1, std::max(0, s));
+        ++sec_cnt[sector[m]];
+        order[m] = m;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        if (sector[a] != sector[b]) return sector[a] < sector[b];
+        return i32[a] < i32[b];   // layer
+    });
+    const size_t no = sizeof(int32_t) * n;
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    const size_t total = al(nf) + al(nb) + al(np) + al(nc);
+    const size_t total = al(nf) + al(nb) + al(np) + al(nc) + al(no);
     if (c->geo_dev) {
         HIPCHK(c, hipFree(c->geo_dev));
         c->geo_dev = nullptr;
@@ -328,6 +349,8 @@ int lst_load_geometry(lst_ctx *c, int32_t n, const float *f32, const int32_t *i3
     int32_t *dbar = (int32_t *)(p + al(nf));
     int32_t *dptr = (int32_t *)(p + al(nf) + al(nb));
     int32_t *dcol = (int32_t *)(p + al(nf) + al(nb) + al(np));
+    int32_t *dord = (int32_t *)(p + al(nf) + al(nb) + al(np) + al(nc));
+    HIPCHK(c, hipMemcpy(dord, order.data(), no, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(drows, rows.data(), nf, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(dbar, barrel.data(), nb, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(dptr, c->map_ptr.data(), np, hipMemcpyHostToDevice));
@@ -343,6 +366,9 @@ int lst_load_geometry(lst_ctx *c, int32_t n, const float *f32, const int32_t *i3
     M.is2s = dbar + n;
     M.map_ptr = dptr;
     M.map_col = dcol;
+    M.xorder = dord;
+    M.sec_off[0] = 0;
+    for (int x = 0; x < NXCD; ++x) M.sec_off[x + 1] = M.sec_off[x] + sec_cnt[x];
     M.n_mod = n;
     c->arena = nullptr;  // a new geometry invalidates the arena layout
     drop_graph(c);
@@ -503,6 +529,7 @@ static int need_stage(lst_ctx *c, int s, const char *what)
     if (c->stage < s) return fail(c, LST_E_STATE, "%s called out of order", what);
     c->counts_valid = false;
     if (s <= 6) c->features_valid = false;
+    if (s <= 5) c->t3_features_valid = false;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, LST_E_HIP, "hipSetDevice");
     return LST_OK;
 }
@@ -566,24 +593,28 @@ int lst_run_dedup(lst_ctx *c, void *stream)
 int lst_run_chain_persistent(lst_ctx *c, void *stream);
 
 // ---------------------------------------------------------------- learned scorer
-static int score_grid(const lst_ctx *c);
-static int enqueue_score(lst_ctx *c, hipStream_t s);
+static int score_grid(const lst_ctx *c, int slot);
+static int enqueue_score(lst_ctx *c, int slot, hipStream_t s);
+
+static int mlp_slot(int32_t kind) { return kind == LST_T3 ? 0 : kind == LST_T5 ? 1 : -1; }
 
 int lst_set_mode(lst_ctx *c, int32_t mode)
 {
     if (!c) return LST_E_INVALID;
     if (mode != LST_MODE_CUTS && mode != LST_MODE_MLP) return fail(c, LST_E_INVALID, "mode %d", mode);
-    if (mode == LST_MODE_MLP && !c->mlp_dev)
+    if (mode == LST_MODE_MLP && !c->mlp_dev[0] && !c->mlp_dev[1])
         return fail(c, LST_E_STATE, "scorer mode needs weights (lst_mlp_load)");
     if (mode != c->mode) drop_graph(c);
     c->mode = mode;
     return LST_OK;
 }
 
-int lst_mlp_load(lst_ctx *c, const float *params, int32_t n_params, const float *mean,
+int lst_mlp_load(lst_ctx *c, int32_t kind, const float *params, int32_t n_params, const float *mean,
                  const float *istd, float threshold)
 {
     if (!c) return LST_E_INVALID;
+    const int sl = mlp_slot(kind);
+    if (sl < 0) return fail(c, LST_E_INVALID, "scorer kind %d (LST_T3 or LST_T5)", kind);
     if (!params || !mean || !istd || n_params != MLP_NPARAM)
         return fail(c, LST_E_INVALID, "scorer weights: %d parameters, %d expected", n_params,
                     MLP_NPARAM);
@@ -595,28 +626,40 @@ int lst_mlp_load(lst_ctx *c, const float *params, int32_t n_params, const float 
     if (!std::isfinite(threshold)) return fail(c, LST_E_INVALID, "threshold not finite");
     HIPCHK(c, hipSetDevice(c->device));
     const size_t n = MLP_NPARAM + 2 * MLP_NIN;
-    if (!c->mlp_dev) HIPCHK(c, hipMalloc((void **)&c->mlp_dev, sizeof(float) * n));
+    const bool fresh = !c->mlp_dev[sl];
+    if (fresh) HIPCHK(c, hipMalloc((void **)&c->mlp_dev[sl], sizeof(float) * n));
     std::vector<float> h(n);
     std::memcpy(h.data(), params, sizeof(float) * MLP_NPARAM);
     std::memcpy(h.data() + MLP_NPARAM, mean, sizeof(float) * MLP_NIN);
     std::memcpy(h.data() + MLP_NPARAM + MLP_NIN, istd, sizeof(float) * MLP_NIN);
     // synchronous: a replayed graph reads these weights by address
     HIPCHK(c, hipDeviceSynchronize());
-    HIPCHK(c, hipMemcpy(c->mlp_dev, h.data(), sizeof(float) * n, hipMemcpyHostToDevice));
-    if (threshold != c->mlp_threshold) drop_graph(c);
-    c->mlp_threshold = threshold;
+    HIPCHK(c, hipMemcpy(c->mlp_dev[sl], h.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+    if (fresh || threshold != c->mlp_threshold[sl]) drop_graph(c);
+    c->mlp_threshold[sl] = threshold;
     return LST_OK;
+}
+
+int lst_run_t3_score(lst_ctx *c, void *stream)
+{
+    if (!c) return LST_E_INVALID;
+    if (!c->mlp_dev[0]) return fail(c, LST_E_STATE, "triplet scorer weights not loaded");
+    if (c->stage != 5)
+        return fail(c, LST_E_STATE, "lst_run_t3_score runs after triplets, before quintuplets");
+    int rc = need_stage(c, 5, "lst_run_t3_score");
+    if (rc) return rc;
+    return enqueue_score(c, 0, (hipStream_t)stream);
 }
 
 int lst_run_t5_score(lst_ctx *c, void *stream)
 {
     if (!c) return LST_E_INVALID;
-    if (!c->mlp_dev) return fail(c, LST_E_STATE, "scorer weights not loaded");
+    if (!c->mlp_dev[1]) return fail(c, LST_E_STATE, "quintuplet scorer weights not loaded");
     if (c->stage != 6)
         return fail(c, LST_E_STATE, "lst_run_t5_score runs after quintuplets, before dedup");
     int rc = need_stage(c, 6, "lst_run_t5_score");
     if (rc) return rc;
-    return enqueue_score(c, (hipStream_t)stream);
+    return enqueue_score(c, 1, (hipStream_t)stream);
 }
 
 size_t lst_mlp_workspace_bytes(int64_t n) { return n < 0 ? 0 : mlp_workspace_bytes(n); }
@@ -688,27 +731,50 @@ int lst_run_chain(lst_ctx *c, void *stream)
     if ((rc = lst_run_md(c, stream))) return rc;
     if ((rc = lst_run_segments(c, stream))) return rc;
     if ((rc = lst_run_triplets(c, stream))) return rc;
+    const bool mlp = c->mode == LST_MODE_MLP;
+    if (mlp && c->mlp_dev[0] && (rc = lst_run_t3_score(c, stream))) return rc;
     if ((rc = lst_run_quintuplets(c, stream))) return rc;
-    if (c->mode == LST_MODE_MLP && (rc = lst_run_t5_score(c, stream))) return rc;
+    if (mlp && c->mlp_dev[1] && (rc = lst_run_t5_score(c, stream))) return rc;
     return lst_run_dedup(c, stream);
 }
 
 // The whole chain as one hipGraph: captured once per arena (kernel grids and
 // arguments depend on the arena only; batch sizes are read on the device)
 // and replayed for every batch.  Only kernel nodes: no memset nodes.
-static int score_grid(const lst_ctx *c)
+static int score_grid(const lst_ctx *c, int slot)
 {
-    // one block scores 256 quintuplets per pass; grid-stride beyond that
-    const int64_t need = ((int64_t)c->caps.t5 + 255) / 256;
+    // one block scores 256 objects per pass; grid-stride beyond that
+    const int64_t cap = slot == 0 ? c->caps.t3 : c->caps.t5;
+    const int64_t need = (cap + 255) / 256;
     return (int)std::max<int64_t>(1, std::min<int64_t>(need, 2 * std::max(c->n_cu, 1)));
 }
 
-static int enqueue_score(lst_ctx *c, hipStream_t s)
+static int enqueue_score(lst_ctx *c, int slot, hipStream_t s)
 {
-    const float *P = c->mlp_dev;
-    HIPCHK(c, mlp_score(c->E, c->K, P, P + MLP_NPARAM, P + MLP_NPARAM + MLP_NIN, c->mlp_threshold,
-                        score_grid(c), s));
+    const float *P = c->mlp_dev[slot];
+    HIPCHK(c, mlp_score(c->E, c->K, slot == 0 ? OT_T3 : OT_T5, P, P + MLP_NPARAM,
+                        P + MLP_NPARAM + MLP_NIN, c->mlp_threshold[slot], score_grid(c, slot), s));
     return LST_OK;
+}
+
+// the stages after a persistent launch that stopped early for scoring
+static int enqueue_after_persistent(lst_ctx *c, int stop, hipStream_t s)
+{
+    const Tuning &t = c->tune;
+    int rc;
+    if (stop == PERS_TO_T3) {
+        if ((rc = enqueue_score(c, 0, s))) return rc;
+        HIPCHK(c, launch_t5(c->E, c->M, c->K, t.grid[ST_T5], t.lanes[ST_T5], s));
+    }
+    if (c->mlp_dev[1] && (rc = enqueue_score(c, 1, s))) return rc;
+    HIPCHK(c, launch_dedup(c->E, c->M, t.grid[ST_DEDUP], s));
+    return LST_OK;
+}
+
+static int persistent_stop(const lst_ctx *c)
+{
+    if (c->mode != LST_MODE_MLP) return PERS_FULL;
+    return c->mlp_dev[0] ? PERS_TO_T3 : c->mlp_dev[1] ? PERS_TO_T5 : PERS_FULL;
 }
 
 static int enqueue_chain(lst_ctx *c, hipStream_t s)
@@ -717,18 +783,19 @@ static int enqueue_chain(lst_ctx *c, hipStream_t s)
     const bool mlp = c->mode == LST_MODE_MLP;
     int rc;
     if (t.persistent) {
+        const int stop = persistent_stop(c);
         HIPCHK(c, launch_chain_persistent(c->E, c->M, c->K, c->zero_base, c->zero_bytes,
-                                          t.blocks_per_cu * c->n_cu, t.lanes[ST_SEG], mlp, s));
-        if (!mlp) return LST_OK;
-    } else {
-        HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, s));
-        HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], s));
-        HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], t.lanes[ST_MD], s));
-        HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], t.lanes[ST_SEG], s));
-        HIPCHK(c, launch_t3(c->E, c->M, c->K, t.grid[ST_T3], t.lanes[ST_T3], s));
-        HIPCHK(c, launch_t5(c->E, c->M, c->K, t.grid[ST_T5], t.lanes[ST_T5], s));
+                                          t.blocks_per_cu * c->n_cu, t.lanes[ST_SEG], stop, s));
+        return stop == PERS_FULL ? LST_OK : enqueue_after_persistent(c, stop, s);
     }
-    if (mlp && (rc = enqueue_score(c, s))) return rc;
+    HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, s));
+    HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], s));
+    HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], t.lanes[ST_MD], s));
+    HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], t.lanes[ST_SEG], s));
+    HIPCHK(c, launch_t3(c->E, c->M, c->K, t.grid[ST_T3], t.lanes[ST_T3], s));
+    if (mlp && c->mlp_dev[0] && (rc = enqueue_score(c, 0, s))) return rc;
+    HIPCHK(c, launch_t5(c->E, c->M, c->K, t.grid[ST_T5], t.lanes[ST_T5], s));
+    if (mlp && c->mlp_dev[1] && (rc = enqueue_score(c, 1, s))) return rc;
     HIPCHK(c, launch_dedup(c->E, c->M, t.grid[ST_DEDUP], s));
     return LST_OK;
 }
@@ -739,22 +806,32 @@ int lst_run_chain_persistent(lst_ctx *c, void *stream)
     if (rc) return rc;
     const int bpc =
         std::max(1, std::min(c->tune.blocks_per_cu, persistent_blocks_per_cu(c->tune.lanes[ST_SEG])));
-    const bool mlp = c->mode == LST_MODE_MLP;
     hipStream_t s = (hipStream_t)stream;
+    const int stop = persistent_stop(c);
     HIPCHK(c, launch_chain_persistent(c->E, c->M, c->K, c->zero_base, c->zero_bytes,
-                                      bpc * c->n_cu, c->tune.lanes[ST_SEG], mlp, s));
-    if (mlp) {
-        if ((rc = enqueue_score(c, s))) return rc;
-        HIPCHK(c, launch_dedup(c->E, c->M, c->tune.grid[ST_DEDUP], s));
-    }
+                                      bpc * c->n_cu, c->tune.lanes[ST_SEG], stop, s));
+    if (stop != PERS_FULL && (rc = enqueue_after_persistent(c, stop, s))) return rc;
     c->stage = 7;
+    return LST_OK;
+}
+
+// feature passes read finished stages; they invalidate nothing else
+int lst_run_t3_features(lst_ctx *c, void *stream)
+{
+    if (!c) return LST_E_INVALID;
+    if (c->stage < 5) return fail(c, LST_E_STATE, "lst_run_t3_features called out of order");
+    HIPCHK(c, hipSetDevice(c->device));
+    if (!c->E.t3_feat) return fail(c, LST_E_STATE, "arena attached without features");
+    HIPCHK(c, launch_t3_features(c->E, c->K, c->tune.grid[ST_DEDUP], (hipStream_t)stream));
+    c->t3_features_valid = true;
     return LST_OK;
 }
 
 int lst_run_t5_features(lst_ctx *c, void *stream)
 {
-    int rc = need_stage(c, 6, "lst_run_t5_features");
-    if (rc) return rc;
+    if (!c) return LST_E_INVALID;
+    if (c->stage < 6) return fail(c, LST_E_STATE, "lst_run_t5_features called out of order");
+    HIPCHK(c, hipSetDevice(c->device));
     if (!c->E.t5_feat) return fail(c, LST_E_STATE, "arena attached without features");
     HIPCHK(c, launch_t5_features(c->E, c->K, c->tune.grid[ST_DEDUP], (hipStream_t)stream));
     c->features_valid = true;
@@ -1041,48 +1118,18 @@ int lst_get_objects(lst_ctx *c, int32_t event, int32_t kind, int32_t *out, int64
     return LST_OK;
 }
 
-int lst_get_t5_features(lst_ctx *c, int32_t event, float *out, int64_t cap, int64_t *n_out,
-                        void *stream)
-{
-    if (!c) return LST_E_INVALID;
-    if (event < 0 || event >= c->n_events) return fail(c, LST_E_INVALID, "event %d", event);
-    if (!c->features_valid) return fail(c, LST_E_STATE, "features have not been computed");
-    int rc = sync_stream(c, stream);
-    if (rc) return rc;
-    const EvDev &E = c->E;
-    ShardCounts S;
-    if ((rc = read_shards(c, S))) return rc;
-    if (S.gc[GC_OVERFLOW])
-        return fail(c, LST_E_CAPACITY, "capacity overflow (mask %u)", S.gc[GC_OVERFLOW]);
-    std::vector<int32_t> m0, slot;
-    std::vector<float> ft;
-    if ((rc = d2h(c, m0, E.t5_md0, S.span(OT_T5))) || (rc = d2h(c, ft, E.t5_feat, S.span(OT_T5) * 40)) ||
-        (rc = d2h(c, slot, E.md_slot, S.span(OT_MD))))
-        return rc;
-    const int lo_slot = event * c->n_mod, hi_slot = (event + 1) * c->n_mod;
-    int64_t k = 0;
-    for (int sh = 0; sh < NSH; ++sh)
-        for (uint32_t q = 0; q < S.n(OT_T5, sh); ++q) {
-            const size_t i = (size_t)sh * S.rc[OT_T5] + q;
-            if (slot[m0[i]] < lo_slot || slot[m0[i]] >= hi_slot) continue;
-            if (out && k < cap) std::memcpy(&out[40 * k], &ft[40 * i], 40 * sizeof(float));
-            ++k;
-        }
-    if (n_out) *n_out = k;
-    if (k > cap) return fail(c, LST_E_CAPACITY, "%lld feature rows, capacity %lld", (long long)k, (long long)cap);
-    return LST_OK;
-}
 
 }  // extern "C"
 
-// copy a per-quintuplet device array of `event` in lst_get_objects(LST_T5) order
+// copy a per-object device array (width values per object) of `event` in
+// lst_get_objects order, for triplets (OT_T3) or quintuplets (OT_T5)
 template <class T>
-static int t5_field(lst_ctx *c, int32_t event, const T *src, T *out, int64_t cap, int64_t *n_out,
-                    void *stream, const char *what)
+static int obj_field(lst_ctx *c, int type, int32_t event, const T *src, int width, T *out,
+                     int64_t cap, int64_t *n_out, void *stream, const char *what)
 {
     if (!c) return LST_E_INVALID;
     if (event < 0 || event >= c->n_events) return fail(c, LST_E_INVALID, "event %d", event);
-    if (c->stage < 6) return fail(c, LST_E_STATE, "quintuplets have not run");
+    if (c->stage < (type == OT_T3 ? 5 : 6)) return fail(c, LST_E_STATE, "objects have not been built");
     int rc = sync_stream(c, stream);
     if (rc) return rc;
     const EvDev &E = c->E;
@@ -1092,16 +1139,16 @@ static int t5_field(lst_ctx *c, int32_t event, const T *src, T *out, int64_t cap
         return fail(c, LST_E_CAPACITY, "capacity overflow (mask %u)", S.gc[GC_OVERFLOW]);
     std::vector<int32_t> m0, slot;
     std::vector<T> val;
-    if ((rc = d2h(c, m0, E.t5_md0, S.span(OT_T5))) || (rc = d2h(c, val, src, S.span(OT_T5))) ||
-        (rc = d2h(c, slot, E.md_slot, S.span(OT_MD))))
+    if ((rc = d2h(c, m0, type == OT_T3 ? E.t3_a : E.t5_md0, S.span(type))) ||
+        (rc = d2h(c, val, src, S.span(type) * width)) || (rc = d2h(c, slot, E.md_slot, S.span(OT_MD))))
         return rc;
     const int lo_slot = event * c->n_mod, hi_slot = (event + 1) * c->n_mod;
     int64_t k = 0;
-    for (int s = 0; s < NSH; ++s)
-        for (uint32_t q = 0; q < S.n(OT_T5, s); ++q) {
-            const size_t i = (size_t)s * S.rc[OT_T5] + q;
+    for (int sh = 0; sh < NSH; ++sh)
+        for (uint32_t q = 0; q < S.n(type, sh); ++q) {
+            const size_t i = (size_t)sh * S.rc[type] + q;
             if (slot[m0[i]] < lo_slot || slot[m0[i]] >= hi_slot) continue;
-            if (out && k < cap) out[k] = val[i];
+            if (out && k < cap) std::memcpy(&out[width * k], &val[width * i], width * sizeof(T));
             ++k;
         }
     if (n_out) *n_out = k;
@@ -1115,7 +1162,8 @@ extern "C" {
 int lst_get_t5_scores(lst_ctx *c, int32_t event, float *out, int64_t cap, int64_t *n_out,
                       void *stream)
 {
-    return t5_field(c, event, c ? c->E.t5_score : nullptr, out, cap, n_out, stream, "scores");
+    return obj_field(c, OT_T5, event, c ? c->E.t5_score : nullptr, 1, out, cap, n_out, stream,
+                     "scores");
 }
 
 int lst_get_t5_logits(lst_ctx *c, int32_t event, float *logits, uint8_t *veto, int64_t cap,
@@ -1123,9 +1171,34 @@ int lst_get_t5_logits(lst_ctx *c, int32_t event, float *logits, uint8_t *veto, i
 {
     if (!c) return LST_E_INVALID;
     if (c->stage < 7 && c->stage != 6) return fail(c, LST_E_STATE, "quintuplets have not run");
-    int rc = t5_field(c, event, c->E.t5_logit, logits, cap, n_out, stream, "logits");
+    int rc = obj_field(c, OT_T5, event, c->E.t5_logit, 1, logits, cap, n_out, stream, "logits");
     if (rc) return rc;
-    return t5_field(c, event, c->E.t5_veto, veto, cap, n_out, stream, "vetoes");
+    return obj_field(c, OT_T5, event, c->E.t5_veto, 1, veto, cap, n_out, stream, "vetoes");
+}
+
+int lst_get_t3_logits(lst_ctx *c, int32_t event, float *logits, uint8_t *veto, int64_t cap,
+                      int64_t *n_out, void *stream)
+{
+    if (!c) return LST_E_INVALID;
+    int rc = obj_field(c, OT_T3, event, c->E.t3_logit, 1, logits, cap, n_out, stream, "logits");
+    if (rc) return rc;
+    return obj_field(c, OT_T3, event, c->E.t3_veto, 1, veto, cap, n_out, stream, "vetoes");
+}
+
+int lst_get_t5_features(lst_ctx *c, int32_t event, float *out, int64_t cap, int64_t *n_out,
+                        void *stream)
+{
+    if (!c) return LST_E_INVALID;
+    if (!c->features_valid) return fail(c, LST_E_STATE, "features have not been computed");
+    return obj_field(c, OT_T5, event, c->E.t5_feat, 40, out, cap, n_out, stream, "feature rows");
+}
+
+int lst_get_t3_features(lst_ctx *c, int32_t event, float *out, int64_t cap, int64_t *n_out,
+                        void *stream)
+{
+    if (!c) return LST_E_INVALID;
+    if (!c->t3_features_valid) return fail(c, LST_E_STATE, "features have not been computed");
+    return obj_field(c, OT_T3, event, c->E.t3_feat, 40, out, cap, n_out, stream, "feature rows");
 }
 
 }  // extern "C"
@@ -1182,7 +1255,7 @@ static int timed_chain(lst_ctx *c, hipStream_t s, hipEvent_t *ev, double *stage_
     if (c->tune.persistent) {
         HIPCHK(c, launch_chain_persistent(c->E, c->M, c->K, c->zero_base, c->zero_bytes,
                                           c->tune.blocks_per_cu * c->n_cu, c->tune.lanes[ST_SEG],
-                                          false, s));
+                                          PERS_FULL, s));
         HIPCHK(c, hipEventRecord(ev[ST_COUNT], s));
     } else {
         const Tuning &t = c->tune;

@@ -306,6 +306,62 @@ __device__ __forceinline__ bool t5_accept(const Consts &K, const MdV &A, const M
     return true;
 }
 
+// Every triplet quantity of t3_accept, without early exits, and the 40
+// features of the learned scorer (22 used, the rest zero; same operation
+// order as t3_accept for the shared quantities): per MD r/100, z/100, bend
+// pull, endcap flag, 2S flag; curvature over kappa_max; each cut's left-hand
+// side over its limit (|k|, signed k - k_origin, signed r-z residual); r-z
+// slope; chord/100; impact-parameter estimate (k - k_origin) r_a r_c / 2.
+__device__ __forceinline__ void t3_features(const Consts &K, const MdV *P, const MdX *X, float *f)
+{
+    const MdV &A = P[0], &B = P[1], &C = P[2];
+    float xab = B.x - A.x, yab = B.y - A.y;
+    float xbc = C.x - B.x, ybc = C.y - B.y;
+    float xac = C.x - A.x, yac = C.y - A.y;
+    float lab = sqrtf((xab * xab) + (yab * yab));
+    float lbc = sqrtf((xbc * xbc) + (ybc * ybc));
+    float lac = sqrtf((xac * xac) + (yac * yac));
+    float crs = (xab * yac) - (yab * xac);
+    float k = (2.0f * crs) / ((lab * lbc) * lac);
+    float l2 = lac * lac;
+    float hk = 0.5f * k;
+    float e2 = mx(mx(perp_var(K, A, hk), perp_var(K, B, hk)), perp_var(K, C, hk));
+    float tk = (K.tolkc * sqrtf(e2)) / l2;
+    float rhs0 = K.w * (K.klim + tk);
+    float kO = (2.0f * ((A.x * C.y) - (A.y * C.x))) / ((A.r * C.r) * lac);
+    float rhs1 = K.w * (tk + ((2.0f * K.d0max) / (A.r * C.r)));
+    float sab = arc(lab, k);
+    float sbc = arc(lbc, k);
+    float st = sab + sbc;
+    float fr = sab / st;
+    float sl = (C.z - A.z) / st;
+    float dz = B.z - (A.z + ((C.z - A.z) * fr));
+    float se = mx(fabsf(sl), 0.05f) * K.sigv;
+    float sza = A.barrel ? K.sigv : se;
+    float szb = B.barrel ? K.sigv : se;
+    float szc = C.barrel ? K.sigv : se;
+    float g1 = (1.0f - fr) * sza;
+    float g2 = fr * szc;
+    float rhs2 = K.w * (K.nsig * sqrtf(((szb * szb) + (g1 * g1)) + (g2 * g2)));
+#pragma unroll
+    for (int j = 0; j < 40; ++j) f[j] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        f[5 * j + 0] = P[j].r * 0.01f;
+        f[5 * j + 1] = P[j].z * 0.01f;
+        f[5 * j + 2] = X[j].bend;
+        f[5 * j + 3] = P[j].barrel ? 0.0f : 1.0f;
+        f[5 * j + 4] = X[j].is2s ? 1.0f : 0.0f;
+    }
+    f[15] = k / K.kmax;
+    f[16] = fabsf(k) / rhs0;
+    f[17] = (k - kO) / rhs1;
+    f[18] = dz / rhs2;
+    f[19] = sl;
+    f[20] = lac * 0.01f;
+    f[21] = ((k - kO) * (A.r * C.r)) * 0.5f;
+}
+
 // Every quintuplet quantity of t5_accept, without early exits, and the 40
 // features of the learned scorer (same operation order as t5_accept for the
 // shared quantities): per MD r/100, z/100, bend pull, endcap flag, 2S flag;

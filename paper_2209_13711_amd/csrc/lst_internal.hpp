@@ -42,12 +42,21 @@ __host__ __device__ constexpr int gc_shard(int type, int s) { return GC_SH + (ty
 constexpr int GC_COUNT = GC_SH + OT_COUNT * NSH * GC_PAD;
 
 
+// MI355X dispatches workgroup i to XCD i % 8, and each XCD has its own L2.
+// Object stages split their work into NXCD azimuthal sectors and give
+// sector x to the blocks with blockIdx % NXCD == x, so that the objects a
+// block reads (its module's map neighbours) were mostly produced, and are
+// still cached, on the same XCD.  Correctness never depends on the mapping.
+constexpr int NXCD = 8;
+
 struct ModDev {
     const float *cx, *cy, *cz, *ux, *uy, *uz, *vx, *vy, *vz, *g, *rl;
     const int32_t *barrel;   // 1 barrel, 0 endcap
     const int32_t *is2s;     // 1 for 2S modules
     const int32_t *map_ptr;  // [n_mod + 1]
     const int32_t *map_col;  // [n_edges]
+    const int32_t *xorder;   // modules ordered by azimuthal sector, then layer
+    int32_t sec_off[NXCD + 1];   // sector x = xorder[sec_off[x] .. sec_off[x + 1])
     int32_t n_mod;
 };
 
@@ -89,6 +98,9 @@ struct EvDev {
     int32_t *t3_a, *t3_b, *t3_c;
     float *t3_k;
     int32_t *t3_start, *t3_cnt;      // [cap_md]
+    uint8_t *t3_veto;                // 1: rejected by the learned scorer (no quintuplet uses it)
+    float *t3_feat;                  // [span][40] features (learned scorer)
+    float *t3_logit;                 // [span] scorer output
     // quintuplets
     int32_t *t5_md0, *t5_md1, *t5_md2, *t5_md3, *t5_md4;
     float *t5_score;
@@ -123,13 +135,16 @@ hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, int grid,
 hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
                      hipStream_t s);
 hipError_t launch_dedup(const EvDev &E, const ModDev &M, int grid, hipStream_t s);
-// stop_before_dedup: end the persistent kernel after the quintuplet stage;
-// lanes: group width of its four object stages
+// stop: PERS_FULL runs every stage; PERS_TO_T5 ends after the quintuplets,
+// PERS_TO_T3 after the triplets (learned scoring follows as its own
+// launches); lanes: group width of its four object stages
+enum { PERS_FULL = 0, PERS_TO_T5 = 1, PERS_TO_T3 = 2 };
 hipError_t launch_chain_persistent(const EvDev &E, const ModDev &M, const Consts &K,
                                    void *zero_base, size_t zero_bytes, int grid, int lanes,
-                                   bool stop_before_dedup, hipStream_t s);
+                                   int stop, hipStream_t s);
 int persistent_blocks_per_cu(int lanes);
 hipError_t launch_t5_features(const EvDev &E, const Consts &K, int grid, hipStream_t s);
+hipError_t launch_t3_features(const EvDev &E, const Consts &K, int grid, hipStream_t s);
 
 // learned quintuplet scorer (lst_mlp.hip)
 constexpr int MLP_NIN = 40, MLP_NH = 64;
@@ -144,7 +159,8 @@ hipError_t mlp_backward(const float *P, const uint16_t *X, const uint8_t *y, int
                         float *grad, float *loss, hipStream_t s);
 hipError_t mlp_adam(float *P, const float *grad, float *m, float *v, float lr, float b1, float b2,
                     float eps, float c1, float c2, hipStream_t s);
-hipError_t mlp_score(const EvDev &E, const Consts &K, const float *P, const float *mean,
+// kind: OT_T3 or OT_T5
+hipError_t mlp_score(const EvDev &E, const Consts &K, int kind, const float *P, const float *mean,
                      const float *istd, float threshold, int grid, hipStream_t s);
 
 // Launch shape of every stage (blocks of BLOCK threads); chosen by the tuner.

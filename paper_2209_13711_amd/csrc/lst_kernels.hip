@@ -121,22 +121,24 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v)
 
 // ---------------------------------------------------------------- regions
 // Objects of one type live in NSH regions; n_s = min(counter_s, rc) of them
-// in region s.  A wave maps a compact index v in [0, sum n_s) to its array
-// index with a scan of the region sizes held in lanes 0..NSH-1.
-struct Regions {
-    uint32_t incl;   // inclusive prefix of region sizes (this lane's region)
-    uint32_t size;   // this lane's region size
-    uint32_t total;
-    uint32_t rc;
+// in region s.  A wave maps a compact index v to its array index with a scan
+// of the region sizes held in the first lanes.
+// The regions written by the blocks of XCD sector x (shards x, x + NXCD, ...),
+// as a compact index: the object stages read their inner objects from the
+// sector their own blocks belong to.
+struct XRegions {
+    uint32_t incl, size, total, rc;
+    int x;
 };
 
-__device__ __forceinline__ Regions load_regions(const EvDev &E, int type)
+__device__ __forceinline__ XRegions load_regions_x(const EvDev &E, int type, int x)
 {
-    Regions R;
+    XRegions R;
+    R.x = x;
     R.rc = E.rc[type];
     uint32_t n = 0;
-    if (lane_id() < NSH) {
-        uint32_t c = E.gc[gc_shard(type, lane_id())];
+    if (lane_id() < NSH / NXCD) {
+        const uint32_t c = E.gc[gc_shard(type, x + NXCD * lane_id())];
         n = c < R.rc ? c : R.rc;
     }
     R.size = n;
@@ -146,11 +148,26 @@ __device__ __forceinline__ Regions load_regions(const EvDev &E, int type)
 }
 
 // v < R.total (may differ between lanes); every lane of the wave takes part
-__device__ __forceinline__ int32_t region_index(const Regions &R, uint32_t v)
+__device__ __forceinline__ int32_t region_index_x(const XRegions &R, uint32_t v)
 {
     const int r = wave_find(R.incl, v);
     const uint32_t ex = __shfl(R.incl, r, 64) - __shfl(R.size, r, 64);
-    return (int32_t)((uint32_t)r * R.rc + (v - ex));
+    return (int32_t)((uint32_t)(R.x + NXCD * r) * R.rc + (v - ex));
+}
+
+// this block's sector, its rank among the sector's blocks and their number
+struct XBlock {
+    int x;
+    uint32_t rank, count;
+};
+
+__device__ __forceinline__ XBlock xcd_block()
+{
+    XBlock b;
+    b.x = (int)(blockIdx.x % NXCD);
+    b.rank = blockIdx.x / NXCD;
+    b.count = (gridDim.x - (uint32_t)b.x + NXCD - 1) / NXCD;
+    return b;
 }
 
 // Block-wide reservation in shard blockIdx % NSH; every thread of the block
@@ -467,10 +484,17 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
     constexpr int P = Grp<G>::P, CAP = STAGE / P;
     const Grp<G> gp;
     const int w = wave_id();
-    const int n_slots = E.desc[D_NSLOTS];
-    for (int base = blockIdx.x * WAVES * P; base < n_slots; base += gridDim.x * WAVES * P) {
-        const int slot = base + w * P + gp.g;
-        const bool act = slot < n_slots;
+    const XBlock xb = xcd_block();
+    const int n_x = M.sec_off[xb.x + 1] - M.sec_off[xb.x];   // modules of this sector
+    const int items = E.desc[D_NEV] * n_x;
+    for (int base = (int)xb.rank * WAVES * P; base < items; base += (int)xb.count * WAVES * P) {
+        const int k = base + w * P + gp.g;
+        const bool act = k < items;
+        int slot = 0;
+        if (act) {
+            const int ev = k / n_x;
+            slot = ev * M.n_mod + M.xorder[M.sec_off[xb.x] + (k - ev * n_x)];
+        }
         uint32_t lo0 = 0, up0 = 0, nup = 0, np = 0;
         if (act) {
             lo0 = E.boff[2 * slot];
@@ -528,6 +552,9 @@ __global__ __launch_bounds__(BLOCK) void k_md(EvDev E, ModDev M, Consts K)
 }
 
 // the group widths a stage kernel is built for
+// object-stage grids: at least one block per sector, whole rounds of sectors
+static int xcd_grid(int grid) { return grid < NXCD ? NXCD : (grid + NXCD - 1) / NXCD * NXCD; }
+
 #define LST_BY_LANES(lanes, KERNEL, ...)                                              \
     switch (lanes) {                                                                  \
     case 8: hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__); break;                        \
@@ -539,7 +566,7 @@ __global__ __launch_bounds__(BLOCK) void k_md(EvDev E, ModDev M, Consts K)
 hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
                      hipStream_t s)
 {
-    LST_BY_LANES(lanes, k_md, dim3(grid), dim3(BLOCK), 0, s, E, M, K);
+    LST_BY_LANES(lanes, k_md, dim3(xcd_grid(grid)), dim3(BLOCK), 0, s, E, M, K);
     return hipGetLastError();
 }
 
@@ -604,11 +631,12 @@ __device__ __forceinline__ void seg_body(const EvDev &E, const ModDev &M, const 
     constexpr int P = Grp<G>::P, CAP = STAGE / P;
     const Grp<G> gp;
     const int w = wave_id();
-    const Regions R = load_regions(E, OT_MD);
-    for (uint32_t base = blockIdx.x * WAVES * P; base < R.total; base += gridDim.x * WAVES * P) {
+    const XBlock xb = xcd_block();
+    const XRegions R = load_regions_x(E, OT_MD, xb.x);
+    for (uint32_t base = xb.rank * WAVES * P; base < R.total; base += xb.count * WAVES * P) {
         const uint32_t v = base + w * P + gp.g;
         const bool act = v < R.total;
-        const int32_t i = region_index(R, act ? v : 0);
+        const int32_t i = region_index_x(R, act ? v : 0);
         const uint32_t cnt = enum_seg<G>(E, M, K, i, act, [&](bool ok, int32_t o, uint32_t pos) {
             if (ok && pos < CAP) sm.o[w][gp.g * CAP + pos] = o;
         });
@@ -648,7 +676,7 @@ __global__ __launch_bounds__(BLOCK) void k_seg(EvDev E, ModDev M, Consts K)
 hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
                       hipStream_t s)
 {
-    LST_BY_LANES(lanes, k_seg, dim3(grid), dim3(BLOCK), 0, s, E, M, K);
+    LST_BY_LANES(lanes, k_seg, dim3(xcd_grid(grid)), dim3(BLOCK), 0, s, E, M, K);
     return hipGetLastError();
 }
 
@@ -710,11 +738,12 @@ __device__ __forceinline__ void t3_body(const EvDev &E, const Consts &K, SmT3 &s
     constexpr int P = Grp<G>::P, CAP = STAGE / P;
     const Grp<G> gp;
     const int w = wave_id();
-    const Regions R = load_regions(E, OT_MD);
-    for (uint32_t base = blockIdx.x * WAVES * P; base < R.total; base += gridDim.x * WAVES * P) {
+    const XBlock xb = xcd_block();
+    const XRegions R = load_regions_x(E, OT_MD, xb.x);
+    for (uint32_t base = xb.rank * WAVES * P; base < R.total; base += xb.count * WAVES * P) {
         const uint32_t v = base + w * P + gp.g;
         const bool act = v < R.total;
-        const int32_t a = region_index(R, act ? v : 0);
+        const int32_t a = region_index_x(R, act ? v : 0);
         const uint32_t cnt = enum_t3<G>(E, K, a, act, [&](bool ok, int32_t b, int32_t c, float k,
                                                           uint32_t pos) {
             if (ok && pos < CAP) {
@@ -738,6 +767,7 @@ __device__ __forceinline__ void t3_body(const EvDev &E, const Consts &K, SmT3 &s
                 E.t3_b[off + k] = sm.b[w][gp.g * CAP + k];
                 E.t3_c[off + k] = sm.c[w][gp.g * CAP + k];
                 E.t3_k[off + k] = sm.k[w][gp.g * CAP + k];
+                E.t3_veto[off + k] = 0;
             }
         }
         if (wave_max(cnt) > CAP) {
@@ -748,6 +778,7 @@ __device__ __forceinline__ void t3_body(const EvDev &E, const Consts &K, SmT3 &s
                     E.t3_b[off + pos] = b;
                     E.t3_c[off + pos] = c;
                     E.t3_k[off + pos] = k;
+                    E.t3_veto[off + pos] = 0;
                 }
             });
         }
@@ -765,7 +796,7 @@ hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, int grid,
                      hipStream_t s)
 {
     (void)M;
-    LST_BY_LANES(lanes, k_t3, dim3(grid), dim3(BLOCK), 0, s, E, K);
+    LST_BY_LANES(lanes, k_t3, dim3(xcd_grid(grid)), dim3(BLOCK), 0, s, E, K);
     return hipGetLastError();
 }
 
@@ -814,8 +845,10 @@ __device__ __forceinline__ uint32_t enum_t5(const EvDev &E, const Consts &K, int
                 c = E.t3_c[tt1];
                 d = E.t3_b[t2];
                 e = E.t3_c[t2];
-                ok = t5_accept(K, A, load_md(E, b), load_md(E, c), load_md(E, d), load_md(E, e),
-                               E.t3_k[tt1], E.t3_k[t2], score);
+                // a triplet vetoed by the learned scorer joins no quintuplet
+                if (!(E.t3_veto[tt1] | E.t3_veto[t2]))
+                    ok = t5_accept(K, A, load_md(E, b), load_md(E, c), load_md(E, d), load_md(E, e),
+                                   E.t3_k[tt1], E.t3_k[t2], score);
             }
             uint32_t t;
             const uint32_t r = gp.rank(ok, t);
@@ -846,11 +879,12 @@ __device__ __forceinline__ void t5_body(const EvDev &E, const Consts &K, SmT5 &s
     constexpr int P = Grp<G>::P, CAP = STAGE / P;
     const Grp<G> gp;
     const int w = wave_id();
-    const Regions R = load_regions(E, OT_MD);
-    for (uint32_t base = blockIdx.x * WAVES * P; base < R.total; base += gridDim.x * WAVES * P) {
+    const XBlock xb = xcd_block();
+    const XRegions R = load_regions_x(E, OT_MD, xb.x);
+    for (uint32_t base = xb.rank * WAVES * P; base < R.total; base += xb.count * WAVES * P) {
         const uint32_t v = base + w * P + gp.g;
         const bool act = v < R.total;
-        const int32_t a = region_index(R, act ? v : 0);
+        const int32_t a = region_index_x(R, act ? v : 0);
         const int q0 = gp.g * CAP;
         const uint32_t cnt = enum_t5<G>(E, K, a, act, [&](bool ok, int32_t b, int32_t c, int32_t d,
                                                           int32_t e, float sc, uint32_t pos) {
@@ -892,7 +926,7 @@ hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, int grid,
                      hipStream_t s)
 {
     (void)M;
-    LST_BY_LANES(lanes, k_t5, dim3(grid), dim3(BLOCK), 0, s, E, K);
+    LST_BY_LANES(lanes, k_t5, dim3(xcd_grid(grid)), dim3(BLOCK), 0, s, E, K);
     return hipGetLastError();
 }
 
@@ -1082,6 +1116,37 @@ __global__ void k_t5_features(EvDev E, Consts K)
     }
 }
 
+// the 40 features of every stored triplet (one thread each)
+__global__ void k_t3_features(EvDev E, Consts K)
+{
+    __shared__ uint32_t s_pre[NSH + 1];
+    if (upstream_overflow(E)) return;
+    const uint32_t n = obj_prefix(E, OT_T3, s_pre);
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int32_t t = obj_at(E, OT_T3, s_pre, v);
+        const int32_t m[3] = {E.t3_a[t], E.t3_b[t], E.t3_c[t]};
+        MdV P[3];
+        MdX X[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            P[j] = load_md(E, m[j]);
+            X[j].bend = E.md_bend[m[j]];
+            X[j].is2s = E.md_bar[m[j]] >> 1;
+        }
+        float f[40];
+        t3_features(K, P, X, f);
+        float *out = E.t3_feat + (size_t)t * 40;
+#pragma unroll
+        for (int j = 0; j < 40; ++j) out[j] = f[j];
+    }
+}
+
+hipError_t launch_t3_features(const EvDev &E, const Consts &K, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_t3_features, dim3(grid), dim3(BLOCK), 0, s, E, K);
+    return hipGetLastError();
+}
+
 hipError_t launch_t5_features(const EvDev &E, const Consts &K, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_t5_features, dim3(grid), dim3(BLOCK), 0, s, E, K);
@@ -1141,7 +1206,7 @@ __global__ void k_bar_reset(uint32_t *bar)
 // G: group width of the four object stages
 template <int G>
 __global__ __launch_bounds__(BLOCK) void k_chain(EvDev E, ModDev M, Consts K, uint4 *zero_base,
-                                                 size_t zero16, int stop_before_dedup)
+                                                 size_t zero16, int stop)
 {
     __shared__ SmChain sm;
     uint32_t gen = 0;
@@ -1160,9 +1225,10 @@ __global__ __launch_bounds__(BLOCK) void k_chain(EvDev E, ModDev M, Consts K, ui
     seg_body<G>(E, M, K, sm.u.seg);
     LST_SYNC();
     t3_body<G>(E, K, sm.u.t3);
+    if (stop == PERS_TO_T3) return;
     LST_SYNC();
     t5_body<G>(E, K, sm.u.t5);
-    if (stop_before_dedup) return;
+    if (stop == PERS_TO_T5) return;
     LST_SYNC();
     dedup_min_body(E, sm.pre);
     LST_SYNC();
@@ -1192,11 +1258,14 @@ int persistent_blocks_per_cu(int lanes)
 
 hipError_t launch_chain_persistent(const EvDev &E, const ModDev &M, const Consts &K,
                                    void *zero_base, size_t zero_bytes, int grid, int lanes,
-                                   bool stop_before_dedup, hipStream_t s)
+                                   int stop, hipStream_t s)
 {
+    // whole rounds of sectors (never more blocks than requested: co-residency)
+    grid -= grid % NXCD;
+    if (grid < NXCD) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, s, E.bar);
     LST_BY_LANES(lanes, k_chain, dim3(grid), dim3(BLOCK), 0, s, E, M, K, (uint4 *)zero_base,
-                 zero_bytes / 16, stop_before_dedup ? 1 : 0);
+                 zero_bytes / 16, stop);
     return hipGetLastError();
 }
 

@@ -1,4 +1,5 @@
-// Learned quintuplet scorer: MLP 40 -> 64 -> 64 -> 1 (ReLU, ReLU, logit).
+// Learned scorer of triplets and quintuplets: MLP 40 -> 64 -> 64 -> 1
+// (ReLU, ReLU, logit), one network per object kind.
 //
 // Inference runs on the gfx950 matrix cores.  A wavefront takes 16
 // candidates at a time; layers 1 and 2 are v_mfma_f32_16x16x32_bf16
@@ -315,16 +316,19 @@ struct SmScore {
     uint32_t pre[NSH + 1];
 };
 
-// Every stored quintuplet: features in registers (lane = quintuplet),
-// standardised into the wave's LDS tile, four 16-row MFMA tiles per wave,
-// then logit and veto (logit below the threshold) stored per quintuplet.
+// Every stored object of one kind (triplets or quintuplets): features in
+// registers (lane = object), standardised into the wave's LDS tile, four
+// 16-row MFMA tiles per wave, then logit and veto (logit below the
+// threshold) stored per object.
+template <int KIND>
 __global__ __launch_bounds__(BLOCK) void k_mlp_score(EvDev E, Consts K, const float *P,
                                                      const float *mean, const float *istd,
                                                      float threshold)
 {
+    constexpr int NMD = KIND == OT_T3 ? 3 : 5;
     __shared__ SmScore sm;
     if (upstream_overflow(E)) return;
-    const uint32_t n = t5_prefix(E, sm.pre);
+    const uint32_t n = obj_prefix(E, KIND, sm.pre);
     if (blockIdx.x * (WAVES * 64) >= n) return;   // no rows for this block
     load_weights(P, sm.w);
     for (int i = threadIdx.x; i < NIN; i += blockDim.x) {
@@ -337,19 +341,24 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_score(EvDev E, Consts K, const fl
     for (uint32_t base = blockIdx.x * (WAVES * 64); base < n; base += gridDim.x * (WAVES * 64)) {
         const uint32_t v = base + w * 64 + l;
         const bool live = v < n;
-        const int32_t t = live ? t5_at(E, sm.pre, v) : 0;
+        const int32_t t = live ? obj_at(E, KIND, sm.pre, v) : 0;
         float f[40];
         if (live) {
-            MdV Q[5];
-            MdX X[5];
+            MdV Q[NMD];
+            MdX X[NMD];
 #pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                const int32_t m = t5_md(E, t, j);
+            for (int j = 0; j < NMD; ++j) {
+                int32_t m;
+                if (KIND == OT_T3) m = j == 0 ? E.t3_a[t] : j == 1 ? E.t3_b[t] : E.t3_c[t];
+                else m = t5_md(E, t, j);
                 Q[j] = load_md(E, m);
                 X[j].bend = E.md_bend[m];
                 X[j].is2s = E.md_bar[m] >> 1;
             }
-            t5_features(K, Q, X, tri_curv(Q[0], Q[1], Q[2]), tri_curv(Q[2], Q[3], Q[4]), f);
+            if constexpr (KIND == OT_T3)
+                t3_features(K, Q, X, f);
+            else
+                t5_features(K, Q, X, tri_curv(Q[0], Q[1], Q[2]), tri_curv(Q[2], Q[3], Q[4]), f);
         } else {
 #pragma unroll
             for (int k = 0; k < 40; ++k) f[k] = 0.0f;
@@ -372,8 +381,14 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_score(EvDev E, Consts K, const fl
         __syncthreads();
         if (live) {
             const float lg = sm.logit[w][l];
-            E.t5_logit[t] = lg;
-            E.t5_veto[t] = lg >= threshold ? 0 : 1;
+            const uint8_t veto = lg >= threshold ? 0 : 1;
+            if (KIND == OT_T3) {
+                E.t3_logit[t] = lg;
+                E.t3_veto[t] = veto;
+            } else {
+                E.t5_logit[t] = lg;
+                E.t5_veto[t] = veto;
+            }
         }
     }
 }
@@ -431,10 +446,15 @@ hipError_t mlp_adam(float *P, const float *grad, float *m, float *v, float lr, f
     return hipGetLastError();
 }
 
-hipError_t mlp_score(const EvDev &E, const Consts &K, const float *P, const float *mean,
+hipError_t mlp_score(const EvDev &E, const Consts &K, int kind, const float *P, const float *mean,
                      const float *istd, float threshold, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mlp_score, dim3(grid), dim3(BLOCK), 0, s, E, K, P, mean, istd, threshold);
+    if (kind == OT_T3)
+        hipLaunchKernelGGL(k_mlp_score<OT_T3>, dim3(grid), dim3(BLOCK), 0, s, E, K, P, mean, istd,
+                           threshold);
+    else
+        hipLaunchKernelGGL(k_mlp_score<OT_T5>, dim3(grid), dim3(BLOCK), 0, s, E, K, P, mean, istd,
+                           threshold);
     return hipGetLastError();
 }
 

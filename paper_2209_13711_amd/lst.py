@@ -82,9 +82,15 @@ _SIGS = {
     "lst_set_tuning": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32]),
     "lst_get_tuning": (ctypes.c_int, [_P, _P]),
     "lst_tune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_int32, _P, _P]),
-    "lst_mlp_load": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.c_float]),
+    "lst_mlp_load": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _P, _P, ctypes.c_float]),
     "lst_set_mode": (ctypes.c_int, [_P, ctypes.c_int32]),
     "lst_run_t5_score": (ctypes.c_int, [_P, _P]),
+    "lst_run_t3_score": (ctypes.c_int, [_P, _P]),
+    "lst_get_t3_logits": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_int64), _P]),
+    "lst_run_t3_features": (ctypes.c_int, [_P, _P]),
+    "lst_get_t3_features": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64,
+                                           ctypes.POINTER(ctypes.c_int64), _P]),
     "lst_get_t5_logits": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int64,
                                          ctypes.POINTER(ctypes.c_int64), _P]),
     "lst_mlp_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
@@ -316,15 +322,23 @@ class Context:
     def run_t5_features(self, stream=None):
         self._check(self.lib.lst_run_t5_features(self.h, self._stream(stream)))
 
-    def t5_features(self, event, stream=None) -> np.ndarray:
+    def _features(self, fn, event, stream):
         n = ctypes.c_int64(0)
-        rc = self.lib.lst_get_t5_features(self.h, event, None, 0, ctypes.byref(n), self._stream(stream))
+        rc = fn(self.h, event, None, 0, ctypes.byref(n), self._stream(stream))
         if rc not in (LST_OK, LST_E_CAPACITY):
             self._check(rc)
         out = np.zeros((max(n.value, 1), 40), np.float32)
-        self._check(self.lib.lst_get_t5_features(self.h, event, _np_ptr(out), n.value,
-                                                 ctypes.byref(n), self._stream(stream)))
+        self._check(fn(self.h, event, _np_ptr(out), n.value, ctypes.byref(n), self._stream(stream)))
         return out[:n.value]
+
+    def t5_features(self, event, stream=None) -> np.ndarray:
+        return self._features(self.lib.lst_get_t5_features, event, stream)
+
+    def run_t3_features(self, stream=None):
+        self._check(self.lib.lst_run_t3_features(self.h, self._stream(stream)))
+
+    def t3_features(self, event, stream=None) -> np.ndarray:
+        return self._features(self.lib.lst_get_t3_features, event, stream)
 
     def t5_scores(self, event, stream=None) -> np.ndarray:
         n = ctypes.c_int64(0)
@@ -337,12 +351,13 @@ class Context:
         return out[:n.value]
 
     # -- learned scorer -----------------------------------------------------
-    def mlp_load(self, params, mean, istd, threshold=0.0):
+    def mlp_load(self, params, mean, istd, threshold=0.0, kind=LST_T5):
+        """load the scorer of `kind` (LST_T3 or LST_T5)"""
         p = np.ascontiguousarray(params, np.float32)
         m = np.ascontiguousarray(mean, np.float32)
         s = np.ascontiguousarray(istd, np.float32)
-        self._check(self.lib.lst_mlp_load(self.h, _np_ptr(p), len(p), _np_ptr(m), _np_ptr(s),
-                                          float(threshold)))
+        self._check(self.lib.lst_mlp_load(self.h, int(kind), _np_ptr(p), len(p), _np_ptr(m),
+                                          _np_ptr(s), float(threshold)))
 
     def set_mode(self, mode):
         self._check(self.lib.lst_set_mode(self.h, int(mode)))
@@ -350,18 +365,27 @@ class Context:
     def run_t5_score(self, stream=None):
         self._check(self.lib.lst_run_t5_score(self.h, self._stream(stream)))
 
-    def t5_logits(self, event, stream=None):
-        """(logits float32, veto bool) in lst_get_objects(LST_T5) order"""
+    def run_t3_score(self, stream=None):
+        self._check(self.lib.lst_run_t3_score(self.h, self._stream(stream)))
+
+    def _logits(self, fn, event, stream):
         n = ctypes.c_int64(0)
-        rc = self.lib.lst_get_t5_logits(self.h, event, None, None, 0, ctypes.byref(n),
-                                        self._stream(stream))
+        rc = fn(self.h, event, None, None, 0, ctypes.byref(n), self._stream(stream))
         if rc not in (LST_OK, LST_E_CAPACITY):
             self._check(rc)
         lg = np.zeros(max(n.value, 1), np.float32)
         vt = np.zeros(max(n.value, 1), np.uint8)
-        self._check(self.lib.lst_get_t5_logits(self.h, event, _np_ptr(lg), _np_ptr(vt), n.value,
-                                               ctypes.byref(n), self._stream(stream)))
+        self._check(fn(self.h, event, _np_ptr(lg), _np_ptr(vt), n.value, ctypes.byref(n),
+                       self._stream(stream)))
         return lg[:n.value], vt[:n.value].astype(bool)
+
+    def t5_logits(self, event, stream=None):
+        """(logits float32, veto bool) in lst_get_objects(LST_T5) order"""
+        return self._logits(self.lib.lst_get_t5_logits, event, stream)
+
+    def t3_logits(self, event, stream=None):
+        """(logits float32, veto bool) in lst_get_objects(LST_T3) order"""
+        return self._logits(self.lib.lst_get_t3_logits, event, stream)
 
     # training calls: device tensors, asynchronous on the stream
     @staticmethod

@@ -25,10 +25,12 @@ def pure_labels(tuples: np.ndarray, truth: np.ndarray) -> np.ndarray:
     return ((t[:, 0] >= 0) & np.all(t == t[:, :1], axis=1)).astype(np.uint8)
 
 
-def collect(ctx: "L.Context", events, stream=None):
+def collect(ctx: "L.Context", events, kind=L.LST_T5, stream=None):
     """Features (FP32 [N, 40], computed by the chain on the GPU) and truth
-    labels of every quintuplet the chain stores for `events`, in a
-    reproducible order."""
+    labels of every triplet (kind LST_T3) or quintuplet (LST_T5) the chain
+    stores for `events`, in a reproducible order.  The chain runs in the
+    context's mode (a scored chain gives the objects that survive its
+    earlier vetoes)."""
     feats, labels = [], []
     for ev in events:
         if ctx.caps is None or not ctx.caps.get("features"):
@@ -37,14 +39,18 @@ def collect(ctx: "L.Context", events, stream=None):
             ctx.reserve(caps)
         offs = np.array([0, ev.n_hits], np.int32)
         ctx.run_batch(offs, ev.x, ev.y, ev.z, ev.module, ev.sensor, stream)
-        ctx.run_t5_features(stream)
-        f = ctx.t5_features(0, stream)
-        t5 = ctx.objects(0, L.LST_T5, stream)
-        # canonical order (by hit tuple): the device stores quintuplets in
+        if kind == L.LST_T3:
+            ctx.run_t3_features(stream)
+            f = ctx.t3_features(0, stream)
+        else:
+            ctx.run_t5_features(stream)
+            f = ctx.t5_features(0, stream)
+        obj = ctx.objects(0, kind, stream)
+        # canonical order (by hit tuple): the device stores objects in
         # whatever order its blocks finish, the training set must not depend on it
-        o = np.lexsort(t5.T[::-1]) if len(t5) else np.zeros(0, np.int64)
+        o = np.lexsort(obj.T[::-1]) if len(obj) else np.zeros(0, np.int64)
         feats.append(f[o])
-        labels.append(pure_labels(t5[o], ev.truth))
+        labels.append(pure_labels(obj[o], ev.truth))
     return np.concatenate(feats), np.concatenate(labels)
 
 

@@ -174,12 +174,12 @@ def test_adam_rejects_bad_hyperparameters(ctx_toy):
 
 
 # ---------------------------------------------------------------- scoring in the chain
-def _gap_threshold(lg, bound):
-    """a threshold near the median logit with no logit within twice its
-    bound on either side"""
+def _gap_threshold(lg, bound, q=0.5):
+    """a threshold near the q-quantile of the logits with no logit within
+    twice its bound on either side"""
     order = np.argsort(lg)
     s = lg[order]
-    mid = len(s) // 2
+    mid = int(q * len(s))
     for d in range(len(s)):
         for i in (mid + d, mid - d):
             if 0 < i < len(s):
@@ -277,13 +277,112 @@ def test_scorer_state_errors(ctx_toy):
     assert e.value.code == lst.lst.LST_E_STATE
 
 
+# ---------------------------------------------------------------- triplet scoring
+def _scored_case_both(cid, event=0, n_tracks=None, seed=0):
+    """both scorers: triplet veto before the quintuplet stage, quintuplet veto
+    before dedup; expected values from the oracle's rerun with the triplet veto"""
+    lst = _lst()
+    cfg = E.CONFIGS[cid]
+    geo = G.get(cfg.geometry)
+    params = PR.make(w=cfg.window)
+    ev = E.generate(cid, event, n_tracks=n_tracks)
+    orc = oracle.Oracle(params, geo.f32, geo.i32)
+    ref3 = orc.run_event(ev)
+    m3, s3 = _stats(ref3.t3_features)
+    P3 = W.random_params(np.random.default_rng(seed + 100), bias=0.2)
+    lg3, b3 = M.forward(P3, M.standardise(ref3.t3_features, m3, s3))
+    th3 = _gap_threshold(lg3, b3, q=0.15)   # veto some triplets, keep most quintuplets
+    veto3 = lg3 < th3
+    ref = orc.rerun_t5(veto3)
+    assert len(ref.tuples[oracle.T5]) > 10
+    m5, s5 = _stats(ref.t5_features)
+    P5 = W.random_params(np.random.default_rng(seed), bias=0.2)
+    lg5, b5 = M.forward(P5, M.standardise(ref.t5_features, m5, s5))
+    th5 = _gap_threshold(lg5, b5)
+    veto5 = lg5 < th5
+    keep = M.dedup(ref.tuples[oracle.T5], ref.t5_scores, veto5)
+    ctx = lst.Context(params, geo.f32, geo.i32, device=0)
+    ctx.mlp_load(P3, m3, s3, th3, kind=lst.LST_T3)
+    ctx.mlp_load(P5, m5, s5, th5, kind=lst.LST_T5)
+    ctx.set_mode(lst.LST_MODE_MLP)
+    exp3 = dict(t3=ref3.tuples[oracle.T3], lg=lg3, bound=b3, veto=veto3)
+    exp5 = dict(lg=lg5, bound=b5, veto=veto5, keep=keep)
+    return ctx, ev, ref, exp3, exp5
+
+
+def _check_t3(ctx, exp3):
+    lst = _lst()
+    t3 = ctx.objects(0, lst.LST_T3)
+    lg, veto = ctx.t3_logits(0)
+    idx = {tuple(t): i for i, t in enumerate(exp3["t3"].tolist())}
+    assert len(t3) == len(idx) and all(tuple(t) in idx for t in t3.tolist())
+    j = np.array([idx[tuple(t)] for t in t3.tolist()], np.int64)
+    assert np.all(np.abs(lg.astype(np.float64) - exp3["lg"][j]) <= exp3["bound"][j])
+    assert np.array_equal(veto, exp3["veto"][j])
+
+
+@pytest.mark.parametrize("cid,event,n_tracks", [(1, 0, None), (2, 0, None), (5, 0, 1500)])
+def test_triplet_and_quintuplet_scoring_match_oracle(cid, event, n_tracks):
+    print(f"case scored chain (T3 + T5) cfg{cid} event {event}", flush=True)
+    ctx, ev, ref, exp3, exp5 = _scored_case_both(cid, event, n_tracks)
+    assert 0 < exp3["veto"].sum() < len(exp3["veto"])
+    offs = np.array([0, ev.n_hits], np.int32)
+    ctx.run_batch(offs, ev.x, ev.y, ev.z, ev.module, ev.sensor)
+    _check_t3(ctx, exp3)
+    _check_scored(ctx, ref, exp5)
+
+
+def test_triplet_scoring_stagewise_graph_and_persistent():
+    ctx, ev, ref, exp3, exp5 = _scored_case_both(2, 1, 1500, seed=5)
+    offs = np.array([0, ev.n_hits], np.int32)
+    ctx.run_batch(offs, ev.x, ev.y, ev.z, ev.module, ev.sensor)
+    ctx.load_hits(offs, ev.x, ev.y, ev.z, ev.module, ev.sensor)
+    for fn in (ctx.run_sort, ctx.run_md, ctx.run_segments, ctx.run_triplets, ctx.run_t3_score,
+               ctx.run_quintuplets, ctx.run_t5_score, ctx.run_dedup):
+        fn()
+    _check_t3(ctx, exp3)
+    _check_scored(ctx, ref, exp5)
+    for _ in range(3):
+        ctx.run_chain_graph()
+        _check_t3(ctx, exp3)
+        _check_scored(ctx, ref, exp5)
+    ctx.run_chain_persistent()
+    _check_t3(ctx, exp3)
+    _check_scored(ctx, ref, exp5)
+    t = ctx.tuning()
+    ctx.set_tuning(t["grid"], persistent=1, blocks_per_cu=1)
+    ctx.run_chain_graph()                       # persistent kernel inside the graph
+    _check_scored(ctx, ref, exp5)
+
+
+def test_t3_features_bitwise():
+    lst = _lst()
+    geo = G.get("full")
+    params = PR.make()
+    ev = E.generate(2, 3, n_tracks=1500)
+    ref = oracle.Oracle(params, geo.f32, geo.i32).run_event(ev)
+    ctx = lst.Context(params, geo.f32, geo.i32, device=0)
+    caps = lst.default_caps(1, ev.n_hits)
+    caps["features"] = 1
+    ctx.reserve(caps)
+    ctx.run_event(ev)
+    ctx.run_t3_features()
+    f = ctx.t3_features(0)
+    t3 = ctx.objects(0, lst.LST_T3)
+    want = {tuple(t): r for t, r in zip(ref.tuples[oracle.T3].tolist(), ref.t3_features)}
+    assert len(t3) == len(want)
+    for t, row in zip(t3.tolist(), f):
+        assert np.array_equal(row.view(np.uint32), want[tuple(t)].view(np.uint32))
+
+
 # ---------------------------------------------------------------- training and gain
 def test_training_on_gpu_gains_over_plain_chain():
-    """Train the scorer from scratch on the GPU (quintuplets of 40 widened-
-    window training events, labelled by truth) and compare, on 4 held-out
-    4000-helix events, the plain chain at the nominal windows with the
-    widened chain plus the learned veto: the scored chain must find more
-    tracks at no higher fake rate."""
+    """Train both scorers from scratch on the GPU (triplets, then the
+    quintuplets that survive the trained triplet veto, of 40 widened-window
+    training events, labelled by truth) and compare, on 4 held-out 4000-helix
+    events, the plain chain at the nominal windows with the widened chain plus
+    the learned vetoes: the scored chain must find more tracks at no higher
+    fake rate."""
     lst = _lst()
     from paper_2209_13711_amd import scorer as S
     geo = G.get("barrel_toy")
@@ -291,22 +390,25 @@ def test_training_on_gpu_gains_over_plain_chain():
     train = [E.generate(4, e, purpose=E.PURPOSE_TRAIN, cfg=tcfg) for e in range(40)]
     print("case training: events generated", flush=True)
     ctx_w = lst.Context(PR.make(w=tcfg.window), geo.f32, geo.i32, device=0)
-    F, y = S.collect(ctx_w, train)
-    assert len(y) > 100000 and 0.5 < y.mean() < 0.98
-    tr = S.Trainer(ctx_w, F, y, W.random_params(np.random.default_rng(0)), S.TrainConfig(epochs=8))
-    losses = tr.fit()
-    print("losses", losses, flush=True)
-    assert losses[-1] < 0.8 * losses[0]
-    # the trained forward separates the classes on its own training set
-    lg, lab = tr.logits_all(), tr.labels()
-    th = S.threshold_for(lg, lab, 0.99)
-    assert np.mean(lg[lab == 1] >= th) >= 0.99 and np.mean(lg[lab == 0] < th) > 0.3
+    models = {}
+    for kind in (lst.LST_T3, lst.LST_T5):
+        F, y = S.collect(ctx_w, train, kind=kind)
+        assert len(y) > 50000 and 0.1 < y.mean() < 0.98
+        tr = S.Trainer(ctx_w, F, y, W.random_params(np.random.default_rng(kind)),
+                       S.TrainConfig(epochs=8))
+        losses = tr.fit()
+        print("kind", kind, "losses", losses, flush=True)
+        assert losses[-1] < 0.8 * losses[0]
+        lg, lab = tr.logits_all(), tr.labels()
+        th = S.threshold_for(lg, lab, 0.995 if kind == lst.LST_T3 else 0.99)
+        assert np.mean(lg[lab == 0] < th) > 0.05     # rejects a real share of wrong ones
+        models[kind] = (tr.params(), tr.mean, tr.istd, th)
+        # the quintuplet scorer learns on what survives the triplet veto
+        ctx_w.mlp_load(*models[kind], kind=kind)
+        ctx_w.set_mode(lst.LST_MODE_MLP)
     evs = [E.generate(4, e) for e in range(4)]
     plain = S.evaluate(lst.Context(PR.make(), geo.f32, geo.i32, device=0), evs, geo)
-    ctx_s = lst.Context(PR.make(w=tcfg.window), geo.f32, geo.i32, device=0)
-    ctx_s.mlp_load(tr.params(), tr.mean, tr.istd, th)
-    ctx_s.set_mode(lst.LST_MODE_MLP)
-    scored = S.evaluate(ctx_s, evs, geo)
+    scored = S.evaluate(ctx_w, evs, geo)
     print("plain", plain, "scored", scored, flush=True)
     assert scored["eff"] >= plain["eff"] + 0.003
     assert scored["fake"] <= plain["fake"]
