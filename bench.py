@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 30
 # algorithmic FLOPs of the scorer per candidate (40x64 + 64x64 + 64 multiply-adds)
 MLP_FLOPS = 2 * (40 * 64 + 64 * 64 + 64)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_seg_pu200_traffic.txt")
+TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_digest():
@@ -44,10 +44,11 @@ def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
     when the summary is absent or was taken from other kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = os.path.join(TRAFFIC_DIR, kernel.split("<")[0] + "_pu200_traffic.txt")
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
@@ -103,7 +104,7 @@ def cpu_baseline(params, geo, budget_s=12.0, max_events=200):
                       f"incl. hit grouping and FP64 margins, single thread, {t_total:.1f} s"}
 
 
-def batched(lst, torch, E, G, PR, n_events=64, steps=20):
+def batched(lst, torch, E, G, PR, evs, steps=20):
     """64 events of uneven pileup (20 x Poisson(U(50, 250)) helices each, barrel
     toy geometry) in one launch: autotuned launch shape, then the batch timed
     as one hipGraph replay (per-stage kernels or the persistent kernel, as
@@ -111,7 +112,7 @@ def batched(lst, torch, E, G, PR, n_events=64, steps=20):
     a time through the single-event graph."""
     geo = G.get("barrel_toy")
     params = PR.make()
-    evs = [E.generate(3, e) for e in range(n_events)]
+    n_events = len(evs)
     b = E.concat(evs)
     ctx = lst.Context(params, geo.f32, geo.i32, device=0)
     ctx.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
@@ -141,6 +142,19 @@ def batched(lst, torch, E, G, PR, n_events=64, steps=20):
         single.load_hits(np.array([0, ev.n_hits], np.int32), ev.x, ev.y, ev.z, ev.module, ev.sensor)
         per_event.append(timeit(lambda: single.run_chain_graph(stream), 5))
     t_single = float(np.mean(per_event))
+    # roofline of the segment stage on the batch: algorithmic bytes over the
+    # tuner's per-stage median (HIP events around the stage on the stream)
+    ptr, _ = ctx.module_map()
+    tot = {k: 0 for k in ("n_hits", "n_md", "n_seg", "n_t3", "n_t5")}
+    edges = 0
+    for e, ev in enumerate(evs):
+        c = ctx.counts(e)
+        for k in tot:
+            tot[k] += c[k]
+        mods = np.unique(ev.module[ctx.objects(e, lst.LST_MD)[:, 0]])
+        edges += int(np.sum(ptr[mods + 1] - ptr[mods]))
+    seg_bytes = algorithmic_bytes(tot, n_events * geo.n_mod, edges)["seg"]
+    seg_us = tuned["report_us"][2]
     return {"workload": "64 uneven events (config 3): 20 x Poisson(U(50,250)) helices, "
                         "barrel toy geometry, plain chain",
             "hits": int(b.offsets[-1]), "events": n_events,
@@ -149,7 +163,11 @@ def batched(lst, torch, E, G, PR, n_events=64, steps=20):
             "persistent_events_per_s": n_events / t_pers,
             "one_event_per_launch_events_per_s": 1.0 / t_single,
             "tuning": {k: tuned[k] for k in ("grid", "lanes", "persistent", "blocks_per_cu")},
-            "tuner_report_us": tuned["report_us"], "t5_kept": int(kept)}
+            "tuner_report_us": tuned["report_us"], "t5_kept": int(kept),
+            "roofline_seg": {"bound": "hbm", "achieved": seg_bytes / (seg_us * 1e-6) / 1e9,
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": seg_bytes / (seg_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                             "algorithmic_bytes": int(seg_bytes), "duration_us": seg_us}}
 
 
 def _gen_train(e):
@@ -162,39 +180,98 @@ def _gen_eval(e):
     return E.generate(4, e)
 
 
-def scorer_events(n_train=150, n_eval=8):
-    """training and held-out events of the scorer, generated by a pool of
-    CPU workers before this process touches the GPU"""
+def _gen(args):
+    from synth import events as E
+    cid, e = args
+    return E.generate(cid, e)
+
+
+def pregenerate(scorer=True, batch=True, stress=True, n_train=150, n_eval=8):
+    """every synthetic event the side legs need, generated by a pool of CPU
+    workers before this process touches the GPU"""
     import multiprocessing as mp
+    out = {}
     with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        return pool.map(_gen_train, range(n_train)), pool.map(_gen_eval, range(n_eval))
+        if scorer:
+            out["train"] = pool.map(_gen_train, range(n_train))
+            out["eval"] = pool.map(_gen_eval, range(n_eval))
+        if batch:
+            out["batch"] = pool.map(_gen, [(3, e) for e in range(64)])
+        if stress:
+            out["stress"] = pool.map(_gen, [(5, e) for e in range(16)])
+    return out
+
+
+def _oracle_worker(args):
+    """one CPU process: the oracle on PU200-like events for `budget` seconds"""
+    first, budget = args
+    import oracle
+    from synth import events as E, geometry as G, params as PR
+    geo = G.get("full")
+    orc = oracle.Oracle(PR.make(), geo.f32, geo.i32)
+    n, t = 0, 0.0
+    while t < budget:
+        ev = E.generate(2, first + n)
+        t0 = time.perf_counter()
+        orc.run_event(ev)
+        t += time.perf_counter() - t0
+        n += 1
+    return n, t
+
+
+def cpu_all_cores(budget_s=8.0):
+    """the oracle on every host core at once (one process per core, distinct
+    events), before this process touches the GPU"""
+    import multiprocessing as mp
+    n_proc = min(16, os.cpu_count() or 1)
+    with mp.get_context("fork").Pool(n_proc) as pool:
+        res = pool.map(_oracle_worker, [(5000 + 1000 * k, budget_s) for k in range(n_proc)])
+    return {"value": float(sum(n / t for n, t in res)), "unit": "events/s", "cores": n_proc,
+            "kind": "oracle", "sample": f"{sum(n for n, _ in res)} PU200-like events (config 2), "
+                                        f"one oracle process per core, {budget_s:.0f} s each"}
 
 
 def scored(lst, torch, train, evs, steps=50):
-    """Learned scorer end to end on the GPU: quintuplets of the training
-    events (widened windows) labelled by truth, trained by the library's
-    kernels, threshold keeping 99 % of true candidates; then the plain chain
-    at nominal windows against the widened chain + scorer on held-out
-    4000-helix events (efficiency / fake rate by truth, events/s of one
-    event per hipGraph replay)."""
+    """Learned scorers end to end on the GPU: triplets of the training events
+    (widened windows), then the quintuplets that survive the trained triplet
+    veto, labelled by truth and trained by the library's kernels; thresholds
+    keep 99.5 % (triplets) and 99 % (quintuplets) of the true candidates.
+    Then the plain chain at nominal windows against the widened chain +
+    scorers on held-out 4000-helix events (efficiency / fake rate by truth,
+    events/s of one event per hipGraph replay), and the two scoring kernels
+    timed with HIP events on the launch stream."""
     from paper_2209_13711_amd import scorer as S
     from synth import events as E, geometry as G, params as PR, weights as W
     geo = G.get("barrel_toy")
     w_train = E.scorer_training_config(E.CONFIGS[4]).window
     ctx_w = lst.Context(PR.make(w=w_train), geo.f32, geo.i32, device=0)
-    t0 = time.perf_counter()
-    F, y = S.collect(ctx_w, train)
-    t_collect = time.perf_counter() - t0
-    cfg = S.TrainConfig(epochs=10)
-    tr = S.Trainer(ctx_w, F, y, W.random_params(np.random.default_rng(0)), cfg)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    losses = tr.fit()
-    t_train = time.perf_counter() - t0
-    th = S.threshold_for(tr.logits_all(), tr.labels(), 0.99)
+    models, info = {}, {}
+    for kind, name, keep in ((lst.LST_T3, "t3", 0.995), (lst.LST_T5, "t5", 0.99)):
+        t0 = time.perf_counter()
+        F, y = S.collect(ctx_w, train, kind=kind)
+        t_collect = time.perf_counter() - t0
+        cfg = S.TrainConfig(epochs=10)
+        tr = S.Trainer(ctx_w, F, y, W.random_params(np.random.default_rng(kind)), cfg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = tr.fit()
+        t_train = time.perf_counter() - t0
+        lg, lab = tr.logits_all(), tr.labels()
+        th = S.threshold_for(lg, lab, keep)
+        models[kind] = (tr.params(), tr.mean, tr.istd, th)
+        info[name] = {"train_candidates": int(len(y)), "train_true_frac": float(y.mean()),
+                      "collect_s": t_collect, "train_s": t_train, "epochs": cfg.epochs,
+                      "train_candidates_per_s": tr.n_batches * tr.b * cfg.epochs / t_train,
+                      "loss_first_last": [losses[0], losses[-1]], "threshold": th,
+                      "true_kept": float(np.mean(lg[lab == 1] >= th)),
+                      "false_vetoed": float(np.mean(lg[lab == 0] < th))}
+        # the next kind learns on what survives this veto
+        ctx_w.mlp_load(*models[kind], kind=kind)
+        ctx_w.set_mode(lst.LST_MODE_MLP)
     plain_ctx = lst.Context(PR.make(), geo.f32, geo.i32, device=0)
     scored_ctx = lst.Context(PR.make(w=w_train), geo.f32, geo.i32, device=0)
-    scored_ctx.mlp_load(tr.params(), tr.mean, tr.istd, th)
+    for kind, m in models.items():
+        scored_ctx.mlp_load(*m, kind=kind)
     scored_ctx.set_mode(lst.LST_MODE_MLP)
     m_plain = S.evaluate(plain_ctx, evs, geo)
     m_scored = S.evaluate(scored_ctx, evs, geo)
@@ -214,37 +291,91 @@ def scored(lst, torch, train, evs, steps=50):
             per.append((time.perf_counter() - t0) / steps)
         return 1.0 / float(np.mean(per))
 
-    # scoring kernel alone: HIP events around the stage on the launch stream
+    # scoring kernels alone: HIP events around each scoring step on the launch stream
     ev = evs[0]
-    scored_ctx.load_hits(np.array([0, ev.n_hits], np.int32), ev.x, ev.y, ev.z, ev.module, ev.sensor)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ms = []
+    c = scored_ctx
+    c.load_hits(np.array([0, ev.n_hits], np.int32), ev.x, ev.y, ev.z, ev.module, ev.sensor)
+    ev3 = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ms3, ms5 = [], []
     for _ in range(20):
-        for fn in (scored_ctx.run_sort, scored_ctx.run_md, scored_ctx.run_segments,
-                   scored_ctx.run_triplets, scored_ctx.run_quintuplets):
+        for fn in (c.run_sort, c.run_md, c.run_segments, c.run_triplets):
             fn(stream)
-        e0.record(stream)
-        scored_ctx.run_t5_score(stream)
-        e1.record(stream)
-        scored_ctx.run_dedup(stream)
+        ev3[0].record(stream)
+        c.run_t3_score(stream)
+        ev3[1].record(stream)
+        c.run_quintuplets(stream)
+        ev3[2].record(stream)
+        c.run_t5_score(stream)
+        ev3[3].record(stream)
+        c.run_dedup(stream)
         torch.cuda.synchronize()
-        ms.append(e0.elapsed_time(e1))
-    n_t5 = scored_ctx.counts(0)["n_t5"]
-    score_us = 1e3 * float(np.median(ms[5:]))
-    flops = n_t5 * MLP_FLOPS
-    return {"workload": "scorer trained on quintuplets of 150 training events (barrel toy, "
-                        "20 x Poisson(U(50,250)) helices, windows x1.5), evaluated on 8 held-out "
-                        "4000-helix events (config 4)",
-            "train_candidates": int(len(y)), "train_true_frac": float(y.mean()),
-            "collect_s": t_collect, "train_s": t_train, "epochs": cfg.epochs,
-            "train_candidates_per_s": tr.n_batches * tr.b * cfg.epochs / t_train,
-            "loss_first_last": [losses[0], losses[-1]], "threshold": th,
+        ms3.append(ev3[0].elapsed_time(ev3[1]))
+        ms5.append(ev3[2].elapsed_time(ev3[3]))
+    cnt = c.counts(0)
+
+    def kern(name, ms, n):
+        us = 1e3 * float(np.median(ms[5:]))
+        return {"kernel": name, "duration_us": us, "objects": int(n), "bound": "mfma",
+                "achieved_TFLOPs": n * MLP_FLOPS / (us * 1e-6) / 1e12, "peak_TFLOPs": 2500.0}
+
+    model = models
+    return {"workload": "scorers trained on triplets and quintuplets of 150 training events "
+                        "(barrel toy, 20 x Poisson(U(50,250)) helices, windows x1.5), evaluated on "
+                        "8 held-out 4000-helix events (config 4)",
+            "training": info,
             "plain_w1": {k: m_plain[k] for k in ("eff", "fake", "dup", "impure", "n_obj")},
             "scored_w1.5": {k: m_scored[k] for k in ("eff", "fake", "dup", "impure", "n_obj")},
             "plain_events_per_s": rate(plain_ctx), "scored_events_per_s": rate(scored_ctx),
-            "score_kernel": {"kernel": "k_mlp_score", "duration_us": score_us, "quintuplets": int(n_t5),
-                             "bound": "mfma", "achieved_TFLOPs": flops / (score_us * 1e-6) / 1e12,
-                             "peak_TFLOPs": 2500.0}}
+            "score_kernels": [kern("k_mlp_score<T3>", ms3, cnt["n_t3"]),
+                              kern("k_mlp_score<T5>", ms5, cnt["n_t5"])]}, model
+
+
+def stress(lst, torch, E, G, PR, evs, model=None, steps=10):
+    """16 PU300-like events (6000 helices, 5 % displaced, 10 % noise, windows
+    x1.5) in one tuned launch: events/s and efficiency / fake / duplicate rate
+    by truth, plain and (when a trained scorer is given) scored."""
+    from paper_2209_13711_amd import scorer as S
+    from synth import truth as T
+    geo = G.get("barrel_toy")
+    params = PR.make(w=E.CONFIGS[5].window)
+    b = E.concat(evs)
+    stream = torch.cuda.current_stream()
+
+    def run(ctx):
+        ctx.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+        tuned = ctx.tune(reps=3)
+        ctx.load_hits(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+        ctx.run_chain_graph(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.run_chain_graph(stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        tot = dict(n_obj=0, n_findable=0, n_found=0, n_fake=0, n_dup=0, n_pure=0)
+        for e, ev in enumerate(evs):
+            kept = ctx.objects(e, lst.LST_T5_KEPT)
+            m = T.metrics(kept, ev, geo)
+            for k in ("n_obj", "n_findable", "n_found", "n_fake", "n_dup"):
+                tot[k] += m[k]
+            tot["n_pure"] += int(S.pure_labels(kept, ev.truth).sum())
+        n = max(tot["n_obj"], 1)
+        return {"events_per_s": len(evs) / dt, "ms_per_batch": 1e3 * dt,
+                "eff": tot["n_found"] / max(tot["n_findable"], 1), "fake": tot["n_fake"] / n,
+                "dup": tot["n_dup"] / n, "impure": 1.0 - tot["n_pure"] / n, "n_obj": tot["n_obj"],
+                "tuning": {k: tuned[k] for k in ("grid", "lanes", "persistent", "blocks_per_cu")}}
+
+    out = {"workload": "16 PU300-like events (config 5): 6000 helices, 5 % displaced "
+                       "(d0 up to 10 cm), 10 % noise, windows x1.5, barrel toy geometry, one batch",
+           "hits": int(b.offsets[-1]),
+           "plain": run(lst.Context(params, geo.f32, geo.i32, device=0))}
+    if model is not None:
+        ctx = lst.Context(params, geo.f32, geo.i32, device=0)
+        for kind, m in model.items():
+            ctx.mlp_load(*m, kind=kind)
+        ctx.set_mode(lst.LST_MODE_MLP)
+        out["scored"] = run(ctx)
+    return out
 
 
 def main():
@@ -255,14 +386,18 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-event batch figures")
     ap.add_argument("--no-scorer", action="store_true", help="skip the learned-scorer figures")
+    ap.add_argument("--no-stress", action="store_true", help="skip the config-5 stress figures")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache (JSON lines): reuse a stored launch shape for this event")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); events are "
               "independent, see DESIGN.md for how the batch would shard", file=sys.stderr)
         sys.exit(2)
 
-    if not args.no_scorer:
-        sc_train, sc_eval = scorer_events()
+    pre = pregenerate(scorer=not args.no_scorer, batch=not args.no_batch,
+                      stress=not args.no_stress)
+    cpu_all = None if args.no_cpu else cpu_all_cores()
 
     import torch
     import paper_2209_13711_amd as lst
@@ -275,6 +410,8 @@ def main():
     stream = torch.cuda.current_stream()
     offs = np.array([0, ev.n_hits], np.int32)
     ctx.run_batch(offs, ev.x, ev.y, ev.z, ev.module, ev.sensor)   # sizes the arena
+    # launch shape for this event size (grid, lanes, persistent), tuned or cached
+    tuned = ctx.tune(cache_path=args.tune_cache, reps=5)
     cnt = ctx.counts(0)
     ptr, col = ctx.module_map()
     # map edges actually read: those of modules holding at least one MD
@@ -338,6 +475,8 @@ def main():
     abytes = algorithmic_bytes(cnt, n_slots, n_edges_used)
     dom = max(abytes, key=lambda k: stage_ms[k])
     achieved = abytes[dom] / (stage_ms[dom] * 1e-3) / 1e9
+    lanes_of = {"md": 1, "seg": 2, "t3": 3, "t5": 4}
+    dom_kernel = f"k_{dom}<{tuned['lanes'][lanes_of[dom]]}>"
     cands = cnt["cand_md"] + cnt["cand_seg"] + cnt["cand_t3"] + cnt["cand_t5"]
     value = args.steps / dt
     out = {
@@ -356,26 +495,31 @@ def main():
         "config": {"workload": "PU200-like event (config 2): ~4000 helices, pT^-3 above 0.6 GeV, "
                                "|eta|<2.4, full geometry 6 barrel layers + 2x5 disks, 1% "
                                "inefficiency, 5% noise; plain MD->segment->T3->T5 chain + dedup",
-                   "events_per_step": 1, "hits": int(ev.n_hits)},
+                   "events_per_step": 1, "hits": int(ev.n_hits),
+                   "tuning": {k: tuned[k] for k in ("grid", "lanes", "persistent", "blocks_per_cu")}},
         "candidates_per_s": cands * value,
         "stage_ms": stage_ms,
         "eager_events_per_s": args.steps / dt_eager,
         "pcie_inclusive_events_per_s": pcie_rate,
         "objects": {k: int(cnt[k]) for k in ("n_md", "n_seg", "n_t3", "n_t5", "n_t5_kept")},
-        "roofline": {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": dom_kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(f"k_{dom}"),
+                     "traffic": measured_traffic(dom_kernel),
                      "algorithmic_bytes": int(abytes[dom]),
                      "duration_us": stage_ms[dom] * 1e3,
                      "copy_GBps_measured": copy_gbs,
                      "frac_vs_copy": achieved / copy_gbs},
     }
     if not args.no_batch:
-        out["batched"] = batched(lst, torch, E, G, PR)
+        out["batched"] = batched(lst, torch, E, G, PR, pre["batch"])
+    model = None
     if not args.no_scorer:
-        out["scored"] = scored(lst, torch, sc_train, sc_eval)
+        out["scored"], model = scored(lst, torch, pre["train"], pre["eval"])
+    if not args.no_stress:
+        out["stress"] = stress(lst, torch, E, G, PR, pre["stress"], model)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(params, geo)
+        out["cpu_baseline_all_cores"] = cpu_all
     print(json.dumps(out), flush=True)
 
 
