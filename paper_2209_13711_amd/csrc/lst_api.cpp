@@ -170,10 +170,7 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.hit_off = cv.take<int32_t>(k.events + 1);
     // grouping
     E.boff = cv.take<uint32_t>(keys + 1);
-    E.sx = cv.take<float>(k.hits);
-    E.sy = cv.take<float>(k.hits);
-    E.sz = cv.take<float>(k.hits);
-    E.sorig = cv.take<int32_t>(k.hits);
+    E.hsort = cv.take<float4>(k.hits);
     E.hmin = cv.take<uint32_t>(k.hits);
     E.htie = cv.take<int32_t>(k.hits);
     E.hslot = cv.take<int32_t>((size_t)k.hits * TIE_SLOTS);
@@ -196,6 +193,8 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.md_dn = cv.take<float>(nmd);
     E.md_bend = cv.take<float>(nmd);
     E.md_sv = cv.take<float>(nmd);
+    E.md_ir = cv.take<float>(nmd);
+    E.md_svr = cv.take<float>(nmd);
     E.md_bar = cv.take<uint8_t>(nmd);
     E.md_start = cv.take<int32_t>(slots);
     E.md_cnt = cv.take<int32_t>(slots);
@@ -236,6 +235,17 @@ static int d2h(lst_ctx *c, std::vector<T> &v, const T *src, size_t n)
 {
     v.resize(std::max<size_t>(n, 1));
     if (n) HIPCHK(c, hipMemcpy(v.data(), src, sizeof(T) * n, hipMemcpyDeviceToHost));
+    return LST_OK;
+}
+
+// per-event index of each of the first n sorted hits
+static int sorted_orig(lst_ctx *c, std::vector<int32_t> &out, size_t n)
+{
+    std::vector<float4> h;
+    int rc = d2h(c, h, (const float4 *)c->E.hsort, n);
+    if (rc) return rc;
+    out.resize(std::max<size_t>(n, 1));
+    for (size_t i = 0; i < n; ++i) std::memcpy(&out[i], &h[i].w, sizeof(int32_t));
     return LST_OK;
 }
 
@@ -1066,7 +1076,7 @@ int lst_get_objects(lst_ctx *c, int32_t event, int32_t kind, int32_t *out, int64
     const size_t n_sorted = S.gc[GC_N_SORTED];
     const size_t nmd = S.span(OT_MD);
     std::vector<int32_t> sorig, hlo, hup, slot;
-    if ((rc = d2h(c, sorig, E.sorig, n_sorted)) || (rc = d2h(c, hlo, E.md_hlo, nmd)) ||
+    if ((rc = sorted_orig(c, sorig, n_sorted)) || (rc = d2h(c, hlo, E.md_hlo, nmd)) ||
         (rc = d2h(c, hup, E.md_hup, nmd)) || (rc = d2h(c, slot, E.md_slot, nmd)))
         return rc;
     const int lo_slot = event * c->n_mod, hi_slot = (event + 1) * c->n_mod;
@@ -1223,7 +1233,7 @@ static int chain_checksum(lst_ctx *c, uint64_t *out)
         return fail(c, LST_E_CAPACITY, "tuning run overflowed or timed out (%u, %u)", S.gc[GC_OVERFLOW], S.gc[GC_ERROR]);
     std::vector<int32_t> sorig, hlo, hup, slot, m[5];
     std::vector<uint8_t> keep;
-    if ((rc = d2h(c, sorig, E.sorig, S.gc[GC_N_SORTED])) || (rc = d2h(c, hlo, E.md_hlo, S.span(OT_MD))) ||
+    if ((rc = sorted_orig(c, sorig, S.gc[GC_N_SORTED])) || (rc = d2h(c, hlo, E.md_hlo, S.span(OT_MD))) ||
         (rc = d2h(c, hup, E.md_hup, S.span(OT_MD))) || (rc = d2h(c, slot, E.md_slot, S.span(OT_MD))) ||
         (rc = d2h(c, keep, E.t5_keep, S.span(OT_T5))))
         return rc;

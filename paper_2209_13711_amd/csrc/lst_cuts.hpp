@@ -99,7 +99,7 @@ __device__ __forceinline__ bool md_accept(const Consts &K, const ModF &m, float 
 
 // A mini-doublet as the later stages see it (anchor = lower hit).
 struct MdV {
-    float x, y, z, r, a, ca, dx, dy, dn, sv;
+    float x, y, z, r, a, ca, dx, dy, dn, sv, ir, svr;
     int barrel;
 };
 
@@ -115,6 +115,7 @@ __device__ __forceinline__ MdV load_md(const EvDev &E, int32_t i)
     v.x = E.md_x[i]; v.y = E.md_y[i]; v.z = E.md_z[i]; v.r = E.md_r[i];
     v.a = E.md_a[i]; v.ca = E.md_ca[i]; v.dx = E.md_dx[i]; v.dy = E.md_dy[i];
     v.dn = E.md_dn[i]; v.sv = E.md_sv[i];
+    v.ir = E.md_ir[i]; v.svr = E.md_svr[i];
     v.barrel = E.md_bar[i] & 1;
     return v;
 }
@@ -133,16 +134,37 @@ __device__ __forceinline__ float tri_curv(const MdV &A, const MdV &B, const MdV 
 
 // Segment I -> O: azimuthal window (S2), pointing along the prompt circle
 // (S1), relative angle of each barrel MD direction to the chord (S3).
+// The azimuth window S2 decides exactly as `-(dot / rr) <= 0 && |crs / rr| <=
+// B` would, but divides only when the division-free tests cannot decide:
+//  * dot >= 0 implies -(dot / rr) <= 0 (rr > 0);
+//  * with P = fl(B rr) a normal positive float, |crs| < fl(P (1 - 2^-20))
+//    implies |crs| / rr < B, and |crs| > fl(P (1 + 2^-20)) implies
+//    |crs| / rr > B (1 + 13 2^-24), i.e. above the float after B: the margin
+//    2^-20 exceeds the three FP32 roundings (2^-24 each) between the two
+//    forms, and rounding is monotone, so fl(|crs| / rr) falls on the same
+//    side of B.  NaN and infinities take the exact path or agree with it.
+// The per-MD terms 1 / r and |sv| / r come precomputed from the MD stage,
+// rounded by the same FP32 division.
 __device__ __forceinline__ bool seg_accept(const Consts &K, const MdV &I, const MdV &O)
 {
     float rr = I.r * O.r;
     float crs = (I.x * O.y) - (I.y * O.x);
-    float C = ((I.x * O.x) + (I.y * O.y)) / rr;
-    float S = crs / rr;
+    float dot = (I.x * O.x) + (I.y * O.y);
     float sphi = (O.a * I.ca) - (I.a * O.ca);
-    float tphi = (K.tolu * ((1.0f / I.r) + (1.0f / O.r))) +
-                 (K.tolv * ((fabsf(I.sv) / I.r) + (fabsf(O.sv) / O.r)));
-    if (!((-C <= 0.0f) && (fabsf(S) <= K.w * (sphi + tphi)))) return false;
+    float tphi = (K.tolu * (I.ir + O.ir)) + (K.tolv * (I.svr + O.svr));
+    float B = K.w * (sphi + tphi);
+    bool c_ok = (dot >= 0.0f) || (-(dot / rr) <= 0.0f);
+    float X = fabsf(crs), P = B * rr;
+    bool s_ok;
+    const bool p_ok = P >= 0x1p-100f;              // normal, far from underflow
+    if (p_ok && X < P * 0x1.ffffep-1f)             // 1 - 2^-20
+        s_ok = true;
+    else if (p_ok && X > P * 0x1.00001p+0f)        // 1 + 2^-20
+        s_ok = false;
+    else
+        s_ok = fabsf(crs / rr) <= B;
+    if (!(c_ok && s_ok)) return false;
+    float S = crs / rr;
     float qx = O.x - I.x, qy = O.y - I.y;
     float ql = sqrtf((qx * qx) + (qy * qy));
     float kO = (2.0f * crs) / (rr * ql);

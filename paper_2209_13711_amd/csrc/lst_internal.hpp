@@ -78,8 +78,7 @@ struct EvDev {
     uint32_t *bcnt;          // [n_keys]     (zeroed at chain start)
     uint32_t *boff;          // [n_keys + 1]
     unsigned long long *scan_st;  // look-back scan: status per tile (zeroed at chain start)
-    float *sx, *sy, *sz;     // sorted hits
-    int32_t *sorig;          // per-event index of each sorted hit
+    float4 *hsort;            // sorted hits: x, y, z and (int bits) the hit's per-event index
     uint32_t *hmin;          // dedup: smallest quintuplet score bits per sorted hit
     int32_t *htie;           // dedup: how many quintuplets reach that score
     int32_t *hslot;          // dedup: [n_hits][TIE_SLOTS] quintuplets reaching it
@@ -89,6 +88,7 @@ struct EvDev {
     // mini-doublets
     int32_t *md_hlo, *md_hup, *md_slot;
     float *md_x, *md_y, *md_z, *md_r, *md_a, *md_ca, *md_dx, *md_dy, *md_dn, *md_bend, *md_sv;
+    float *md_ir, *md_svr;           // 1 / r and |sv| / r (the segment window's per-MD terms)
     uint8_t *md_bar;                 // bit 0: barrel module, bit 1: 2S module
     int32_t *md_start, *md_cnt;      // [n_slots]
     // segments (grouped by inner MD)

@@ -372,13 +372,8 @@ __device__ __forceinline__ void scatter_body(const EvDev &E, int n_mod)
         if (key < 0) continue;
         // positions are taken from the top of the bin down; bcnt ends at zero
         const uint32_t pos = E.boff[key] + atomicSub(&E.bcnt[key], 1u) - 1u;
-        E.sx[pos] = E.x[h];
-        E.sy[pos] = E.y[h];
-        E.sz[pos] = E.z[h];
-        E.sorig[pos] = h - E.hit_off[ev];
-        E.hmin[pos] = 0xffffffffu;
-        E.htie[pos] = 0;
-        E.thead[pos] = 0;
+        // one 16-byte store per hit (scattered 4-byte stores cost a line each)
+        E.hsort[pos] = make_float4(E.x[h], E.y[h], E.z[h], __int_as_float(h - E.hit_off[ev]));
     }
 }
 
@@ -430,22 +425,26 @@ __device__ __forceinline__ ModF load_mod(const ModDev &M, int m)
 __device__ __forceinline__ void write_md(const EvDev &E, uint32_t i, int slot, uint32_t hl,
                                          uint32_t hu, const MdOut &o, const ModF &mod)
 {
-    const float xL = E.sx[hl], yL = E.sy[hl];
+    const float4 L = E.hsort[hl], U = E.hsort[hu];
+    const float xL = L.x, yL = L.y;
     E.md_hlo[i] = (int32_t)hl;
     E.md_hup[i] = (int32_t)hu;
     E.md_slot[i] = slot;
     E.md_x[i] = xL;
     E.md_y[i] = yL;
-    E.md_z[i] = E.sz[hl];
+    E.md_z[i] = L.z;
     E.md_r[i] = o.r;
     E.md_a[i] = o.a;
     E.md_ca[i] = o.ca;
-    const float dx = E.sx[hu] - xL, dy = E.sy[hu] - yL;
+    const float dx = U.x - xL, dy = U.y - yL;
     E.md_dx[i] = dx;
     E.md_dy[i] = dy;
     E.md_dn[i] = sqrtf((dx * dx) + (dy * dy));
     E.md_bend[i] = o.bend;
     E.md_sv[i] = o.sv;
+    // the segment window's per-MD terms, rounded exactly as it would round them
+    E.md_ir[i] = 1.0f / o.r;
+    E.md_svr[i] = fabsf(o.sv) / o.r;
     E.md_bar[i] = (uint8_t)(mod.barrel | (mod.is2s << 1));
 }
 
@@ -467,7 +466,8 @@ __device__ __forceinline__ uint32_t enum_md(const EvDev &E, const Consts &K, con
             hl = lo0 + il;
             hu = up0 + iu;
             MdOut o;
-            ok = md_accept(K, mod, E.sx[hl], E.sy[hl], E.sz[hl], E.sx[hu], E.sy[hu], E.sz[hu], o);
+            const float4 L = E.hsort[hl], U = E.hsort[hu];
+            ok = md_accept(K, mod, L.x, L.y, L.z, U.x, U.y, U.z, o);
         }
         uint32_t t;
         const uint32_t r = gp.rank(ok, t);
@@ -502,6 +502,13 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
             nup = E.boff[2 * slot + 2] - up0;
             np = (up0 - lo0) * nup;
         }
+        // per-hit state of duplicate removal for this slot's hits (contiguous)
+        if (act)
+            for (uint32_t h = lo0 + gp.lane; h < up0 + nup; h += G) {
+                E.hmin[h] = 0xffffffffu;
+                E.htie[h] = 0;
+                E.thead[h] = 0;
+            }
         ModF mod = {};
         if (np) mod = load_mod(M, slot % M.n_mod);
         const uint32_t cnt = enum_md<G>(E, K, mod, lo0, up0, nup, np,
@@ -524,7 +531,8 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
             for (uint32_t k = gp.lane; k < cnt; k += G) {
                 const uint32_t hl = sm.lo[w][gp.g * CAP + k], hu = sm.up[w][gp.g * CAP + k];
                 MdOut o;
-                md_accept(K, mod, E.sx[hl], E.sy[hl], E.sz[hl], E.sx[hu], E.sy[hu], E.sz[hu], o);
+                const float4 L = E.hsort[hl], U = E.hsort[hu];
+                md_accept(K, mod, L.x, L.y, L.z, U.x, U.y, U.z, o);
                 write_md(E, off + k, slot, hl, hu, o, mod);
             }
         }
@@ -535,8 +543,8 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
                        [&](bool ok, uint32_t hl, uint32_t hu, uint32_t pos) {
                            if (ok) {
                                MdOut o;
-                               md_accept(K, mod, E.sx[hl], E.sy[hl], E.sz[hl], E.sx[hu], E.sy[hu],
-                                         E.sz[hu], o);
+                               const float4 L = E.hsort[hl], U = E.hsort[hu];
+                               md_accept(K, mod, L.x, L.y, L.z, U.x, U.y, U.z, o);
                                write_md(E, off + pos, slot, hl, hu, o, mod);
                            }
                        });
@@ -951,7 +959,7 @@ __device__ __forceinline__ void dedup_min_body(const EvDev &E, uint32_t *s_pre)
         const int j = (int)(v % 10u);
         const int32_t h = t5_hit(E, t, j);
         E.t5_hs[(size_t)t * 10 + j] = h;
-        E.t5_ho[(size_t)t * 10 + j] = E.sorig[h];
+        E.t5_ho[(size_t)t * 10 + j] = __float_as_int(E.hsort[h].w);
         if (E.t5_veto[t]) continue;
         atomicMin(&E.hmin[h], __float_as_uint(E.t5_score[t]));
     }
