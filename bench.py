@@ -104,19 +104,20 @@ def cpu_baseline(params, geo, budget_s=12.0, max_events=200):
                       f"incl. hit grouping and FP64 margins, single thread, {t_total:.1f} s"}
 
 
-def batched(lst, torch, E, G, PR, evs, steps=20):
+def batched(lst, torch, E, G, PR, evs, steps=20, cache=None, compare=True):
     """64 events of uneven pileup (20 x Poisson(U(50, 250)) helices each, barrel
     toy geometry) in one launch: autotuned launch shape, then the batch timed
     as one hipGraph replay (per-stage kernels or the persistent kernel, as
     the tuner chose), the persistent kernel alone, and the same events one at
-    a time through the single-event graph."""
+    a time through the single-event graph (compare=False: the batch alone,
+    for profiles)."""
     geo = G.get("barrel_toy")
     params = PR.make()
     n_events = len(evs)
     b = E.concat(evs)
     ctx = lst.Context(params, geo.f32, geo.i32, device=0)
     ctx.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
-    tuned = ctx.tune(reps=3)
+    tuned = ctx.tune(cache_path=cache, reps=3)
     stream = torch.cuda.current_stream()
 
     def timeit(fn, n):
@@ -131,17 +132,20 @@ def batched(lst, torch, E, G, PR, evs, steps=20):
     ctx.load_hits(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
     t_graph = timeit(lambda: ctx.run_chain_graph(stream), steps)
     kept = sum(ctx.counts(e)["n_t5_kept"] for e in range(n_events))
-    t_pers = timeit(lambda: ctx.run_chain_persistent(stream), steps)
-    kept_p = sum(ctx.counts(e)["n_t5_kept"] for e in range(n_events))
-    assert kept == kept_p, "persistent chain changed the result"
-    # one event per launch, same events
-    single = lst.Context(params, geo.f32, geo.i32, device=0)
-    single.reserve(dict(ctx.caps, events=1))
-    per_event = []
-    for ev in evs[:8]:
-        single.load_hits(np.array([0, ev.n_hits], np.int32), ev.x, ev.y, ev.z, ev.module, ev.sensor)
-        per_event.append(timeit(lambda: single.run_chain_graph(stream), 5))
-    t_single = float(np.mean(per_event))
+    t_pers = t_single = float("nan")
+    if compare:
+        t_pers = timeit(lambda: ctx.run_chain_persistent(stream), steps)
+        kept_p = sum(ctx.counts(e)["n_t5_kept"] for e in range(n_events))
+        assert kept == kept_p, "persistent chain changed the result"
+        # one event per launch, same events
+        single = lst.Context(params, geo.f32, geo.i32, device=0)
+        single.reserve(dict(ctx.caps, events=1))
+        per_event = []
+        for ev in evs[:8]:
+            single.load_hits(np.array([0, ev.n_hits], np.int32), ev.x, ev.y, ev.z, ev.module,
+                             ev.sensor)
+            per_event.append(timeit(lambda: single.run_chain_graph(stream), 5))
+        t_single = float(np.mean(per_event))
     # roofline of the segment stage on the batch: algorithmic bytes over the
     # tuner's per-stage median (HIP events around the stage on the stream)
     ptr, _ = ctx.module_map()
@@ -154,7 +158,21 @@ def batched(lst, torch, E, G, PR, evs, steps=20):
         mods = np.unique(ev.module[ctx.objects(e, lst.LST_MD)[:, 0]])
         edges += int(np.sum(ptr[mods + 1] - ptr[mods]))
     seg_bytes = algorithmic_bytes(tot, n_events * geo.n_mod, edges)["seg"]
-    seg_us = tuned["report_us"][2]
+    # the segment stage alone: HIP events around it on the launch stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    seg_ms = []
+    for _ in range(6):
+        ctx.load_hits(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+        ctx.run_sort(stream)
+        ctx.run_md(stream)
+        e0.record(stream)
+        ctx.run_segments(stream)
+        e1.record(stream)
+        for fn in (ctx.run_triplets, ctx.run_quintuplets, ctx.run_dedup):
+            fn(stream)
+        torch.cuda.synchronize()
+        seg_ms.append(e0.elapsed_time(e1))
+    seg_us = 1e3 * float(np.median(seg_ms[1:]))
     return {"workload": "64 uneven events (config 3): 20 x Poisson(U(50,250)) helices, "
                         "barrel toy geometry, plain chain",
             "hits": int(b.offsets[-1]), "events": n_events,
@@ -330,6 +348,42 @@ def scored(lst, torch, train, evs, steps=50):
                               kern("k_mlp_score<T5>", ms5, cnt["n_t5"])]}, model
 
 
+def multistream(lst, torch, G, PR, evs, n_streams=8, rounds=3):
+    """The paper's concurrency scheme on this GPU: the same events one per
+    launch, spread over n_streams HIP streams (default priority), each with
+    its own context and hipGraph; hits already in device memory."""
+    geo = G.get("barrel_toy")
+    params = PR.make()
+    dev = []
+    for ev in evs:
+        t = [torch.from_numpy(np.ascontiguousarray(a)).cuda()
+             for a in (ev.x, ev.y, ev.z, ev.module.astype(np.int32), ev.sensor.astype(np.uint8))]
+        dev.append((np.array([0, ev.n_hits], np.int32), t))
+    big = max(evs, key=lambda e: e.n_hits)
+    streams = [torch.cuda.Stream() for _ in range(n_streams)]
+    ctxs = []
+    for k in range(n_streams):
+        c = lst.Context(params, geo.f32, geo.i32, device=0)
+        c.run_batch(np.array([0, big.n_hits], np.int32), big.x, big.y, big.z, big.module,
+                    big.sensor)
+        ctxs.append(c)
+
+    def run_all():
+        for i, (offs, t) in enumerate(dev):
+            k = i % n_streams
+            ctxs[k].load_hits(offs, *t, stream=streams[k])
+            ctxs[k].run_chain_graph(streams[k])
+
+    run_all()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(rounds):
+        run_all()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"streams": n_streams, "events": len(evs), "events_per_s": rounds * len(evs) / dt}
+
+
 def stress(lst, torch, E, G, PR, evs, model=None, steps=10):
     """16 PU300-like events (6000 helices, 5 % displaced, 10 % noise, windows
     x1.5) in one tuned launch: events/s and efficiency / fake / duplicate rate
@@ -387,6 +441,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-event batch figures")
     ap.add_argument("--no-scorer", action="store_true", help="skip the learned-scorer figures")
     ap.add_argument("--no-stress", action="store_true", help="skip the config-5 stress figures")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the 64-event batch leg and print its figures (for profiling)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache (JSON lines): reuse a stored launch shape for this event")
     args = ap.parse_args()
@@ -395,6 +451,14 @@ def main():
               "independent, see DESIGN.md for how the batch would shard", file=sys.stderr)
         sys.exit(2)
 
+    if args.batch_only:
+        pre = pregenerate(scorer=False, batch=True, stress=False)
+        import torch
+        import paper_2209_13711_amd as lst
+        from synth import events as E, geometry as G, params as PR
+        print(json.dumps({"batched": batched(lst, torch, E, G, PR, pre["batch"],
+                                             cache=args.tune_cache, compare=False)}), flush=True)
+        return
     pre = pregenerate(scorer=not args.no_scorer, batch=not args.no_batch,
                       stress=not args.no_stress)
     cpu_all = None if args.no_cpu else cpu_all_cores()
@@ -511,7 +575,8 @@ def main():
                      "frac_vs_copy": achieved / copy_gbs},
     }
     if not args.no_batch:
-        out["batched"] = batched(lst, torch, E, G, PR, pre["batch"])
+        out["batched"] = batched(lst, torch, E, G, PR, pre["batch"], cache=args.tune_cache)
+        out["batched"]["multistream_8"] = multistream(lst, torch, G, PR, pre["batch"])
     model = None
     if not args.no_scorer:
         out["scored"], model = scored(lst, torch, pre["train"], pre["eval"])

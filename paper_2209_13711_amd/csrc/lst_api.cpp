@@ -46,8 +46,10 @@ struct lst_ctx {
     // batch
     int n_events = 0;
     std::vector<int32_t> hit_off;
-    int32_t *stage_host = nullptr;   // pinned: batch descriptor + hit offsets
-    size_t stage_cap = 0;
+    // pinned staging: batch descriptor, hit offsets, then (host inputs) x, y,
+    // z, module, sensor, so that every upload is a DMA from pinned memory
+    int32_t *stage_host = nullptr;
+    size_t stage_cap = 0;   // bytes
     hipEvent_t stage_done = nullptr;
     bool stage_pending = false;
     hipStream_t cap_stream = nullptr;
@@ -182,19 +184,11 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.md_hlo = cv.take<int32_t>(nmd);
     E.md_hup = cv.take<int32_t>(nmd);
     E.md_slot = cv.take<int32_t>(nmd);
-    E.md_x = cv.take<float>(nmd);
-    E.md_y = cv.take<float>(nmd);
-    E.md_z = cv.take<float>(nmd);
-    E.md_r = cv.take<float>(nmd);
-    E.md_a = cv.take<float>(nmd);
-    E.md_ca = cv.take<float>(nmd);
-    E.md_dx = cv.take<float>(nmd);
-    E.md_dy = cv.take<float>(nmd);
-    E.md_dn = cv.take<float>(nmd);
+    E.md_p0 = cv.take<float4>(nmd);
+    E.md_p1 = cv.take<float4>(nmd);
+    E.md_p2 = cv.take<float4>(nmd);
     E.md_bend = cv.take<float>(nmd);
-    E.md_sv = cv.take<float>(nmd);
-    E.md_ir = cv.take<float>(nmd);
-    E.md_svr = cv.take<float>(nmd);
+
     E.md_bar = cv.take<uint8_t>(nmd);
     E.md_start = cv.take<int32_t>(slots);
     E.md_cnt = cv.take<int32_t>(slots);
@@ -247,6 +241,17 @@ static int sorted_orig(lst_ctx *c, std::vector<int32_t> &out, size_t n)
     out.resize(std::max<size_t>(n, 1));
     for (size_t i = 0; i < n; ++i) std::memcpy(&out[i], &h[i].w, sizeof(int32_t));
     return LST_OK;
+}
+
+// pinned staging layout: [descriptor][offsets] then the host hit arrays
+static size_t stage_hits_offset(int64_t events)
+{
+    return ((sizeof(int32_t) * ((size_t)events + 1 + D_COUNT)) + 255) & ~(size_t)255;
+}
+
+static size_t stage_bytes(int64_t events, int64_t hits)
+{
+    return stage_hits_offset(events) + (size_t)hits * (3 * sizeof(float) + sizeof(int32_t) + 1);
 }
 
 extern "C" {
@@ -465,11 +470,11 @@ int lst_attach_arena(lst_ctx *c, void *dev_ptr, size_t bytes, const lst_caps *ca
         HIPCHK(c, hipEventSynchronize(c->stage_done));
         c->stage_pending = false;
     }
-    const size_t want = (size_t)caps->events + 1 + D_COUNT;
+    const size_t want = stage_bytes(caps->events, caps->hits);
     if (c->stage_cap < want) {
         if (c->stage_host) HIPCHK(c, hipHostFree(c->stage_host));
         c->stage_host = nullptr;
-        HIPCHK(c, hipHostMalloc((void **)&c->stage_host, want * sizeof(int32_t), hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->stage_host, want, hipHostMallocDefault));
         c->stage_cap = want;
     }
     if (!c->stage_done) HIPCHK(c, hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming));
@@ -503,19 +508,34 @@ int lst_load_hits(lst_ctx *c, int32_t n_events, const int32_t *hit_offsets, cons
         return fail(c, LST_E_INVALID, "null hit array");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
-    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     EvDev &E = c->E;
-    if (n > 0) {
-        HIPCHK(c, hipMemcpyAsync(E.x, x, sizeof(float) * n, kind, s));
-        HIPCHK(c, hipMemcpyAsync(E.y, y, sizeof(float) * n, kind, s));
-        HIPCHK(c, hipMemcpyAsync(E.z, z, sizeof(float) * n, kind, s));
-        HIPCHK(c, hipMemcpyAsync(E.module, module, sizeof(int32_t) * n, kind, s));
-        HIPCHK(c, hipMemcpyAsync(E.sensor, sensor, n, kind, s));
+    // the pinned buffer is reused: wait until the previous batch's copies have left it
+    if (c->stage_pending) HIPCHK(c, hipEventSynchronize(c->stage_done));
+    if (n > 0 && on_device) {
+        HIPCHK(c, hipMemcpyAsync(E.x, x, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(E.y, y, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(E.z, z, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(E.module, module, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(E.sensor, sensor, n, hipMemcpyDeviceToDevice, s));
+    } else if (n > 0) {
+        // host arrays: one host copy into pinned memory, then DMA (a copy from
+        // pageable memory goes through the runtime's own staging, several
+        // times slower)
+        char *hp = (char *)c->stage_host + stage_hits_offset(c->caps.events);
+        const size_t nb = sizeof(float) * n;
+        char *px = hp, *py = px + nb, *pz = py + nb, *pm = pz + nb, *ps = pm + nb;
+        std::memcpy(px, x, nb);
+        std::memcpy(py, y, nb);
+        std::memcpy(pz, z, nb);
+        std::memcpy(pm, module, sizeof(int32_t) * n);
+        std::memcpy(ps, sensor, n);
+        HIPCHK(c, hipMemcpyAsync(E.x, px, nb, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(E.y, py, nb, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(E.z, pz, nb, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(E.module, pm, sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(E.sensor, ps, n, hipMemcpyHostToDevice, s));
     }
     c->hit_off.assign(hit_offsets, hit_offsets + n_events + 1);
-    // descriptor + offsets go through a pinned buffer; wait until the copy
-    // of the previous batch has left it
-    if (c->stage_pending) HIPCHK(c, hipEventSynchronize(c->stage_done));
     int32_t *st = c->stage_host;
     st[D_NEV] = n_events;
     st[D_NHITS] = (int32_t)n;

@@ -112,10 +112,10 @@ struct MdX {
 __device__ __forceinline__ MdV load_md(const EvDev &E, int32_t i)
 {
     MdV v;
-    v.x = E.md_x[i]; v.y = E.md_y[i]; v.z = E.md_z[i]; v.r = E.md_r[i];
-    v.a = E.md_a[i]; v.ca = E.md_ca[i]; v.dx = E.md_dx[i]; v.dy = E.md_dy[i];
-    v.dn = E.md_dn[i]; v.sv = E.md_sv[i];
-    v.ir = E.md_ir[i]; v.svr = E.md_svr[i];
+    const float4 p0 = E.md_p0[i], p1 = E.md_p1[i], p2 = E.md_p2[i];
+    v.x = p0.x; v.y = p0.y; v.z = p0.z; v.r = p0.w;
+    v.a = p1.x; v.ca = p1.y; v.ir = p1.z; v.svr = p1.w;
+    v.dx = p2.x; v.dy = p2.y; v.dn = p2.z; v.sv = p2.w;
     v.barrel = E.md_bar[i] & 1;
     return v;
 }
@@ -144,9 +144,14 @@ __device__ __forceinline__ float tri_curv(const MdV &A, const MdV &B, const MdV 
 //    forms, and rounding is monotone, so fl(|crs| / rr) falls on the same
 //    side of B.  NaN and infinities take the exact path or agree with it.
 // The per-MD terms 1 / r and |sv| / r come precomputed from the MD stage,
-// rounded by the same FP32 division.
-__device__ __forceinline__ bool seg_accept(const Consts &K, const MdV &I, const MdV &O)
+// rounded by the same FP32 division.  The outer MD o is gathered in two
+// steps: what the window needs first, the rest only for candidates inside it.
+__device__ __forceinline__ bool seg_accept(const Consts &K, const MdV &I, const EvDev &E, int32_t o)
 {
+    MdV O;
+    const float4 p0 = E.md_p0[o], p1 = E.md_p1[o];
+    O.x = p0.x; O.y = p0.y; O.z = p0.z; O.r = p0.w;
+    O.a = p1.x; O.ca = p1.y; O.ir = p1.z; O.svr = p1.w;
     float rr = I.r * O.r;
     float crs = (I.x * O.y) - (I.y * O.x);
     float dot = (I.x * O.x) + (I.y * O.y);
@@ -164,6 +169,9 @@ __device__ __forceinline__ bool seg_accept(const Consts &K, const MdV &I, const 
     else
         s_ok = fabsf(crs / rr) <= B;
     if (!(c_ok && s_ok)) return false;
+    const float4 p2 = E.md_p2[o];
+    O.dx = p2.x; O.dy = p2.y; O.dn = p2.z; O.sv = p2.w;
+    O.barrel = E.md_bar[o] & 1;
     float S = crs / rr;
     float qx = O.x - I.x, qy = O.y - I.y;
     float ql = sqrtf((qx * qx) + (qy * qy));

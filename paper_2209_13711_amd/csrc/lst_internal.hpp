@@ -87,8 +87,11 @@ struct EvDev {
     uint32_t cap_tpool;
     // mini-doublets
     int32_t *md_hlo, *md_hup, *md_slot;
-    float *md_x, *md_y, *md_z, *md_r, *md_a, *md_ca, *md_dx, *md_dy, *md_dn, *md_bend, *md_sv;
-    float *md_ir, *md_svr;           // 1 / r and |sv| / r (the segment window's per-MD terms)
+    // anchor and window terms, three 16-byte records per MD so that a lane
+    // gathers an MD with three loads: (x, y, z, r), (a, ca, 1/r, |sv|/r),
+    // (dx, dy, |d|, sv)
+    float4 *md_p0, *md_p1, *md_p2;
+    float *md_bend;
     uint8_t *md_bar;                 // bit 0: barrel module, bit 1: 2S module
     int32_t *md_start, *md_cnt;      // [n_slots]
     // segments (grouped by inner MD)

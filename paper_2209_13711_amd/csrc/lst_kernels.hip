@@ -430,21 +430,12 @@ __device__ __forceinline__ void write_md(const EvDev &E, uint32_t i, int slot, u
     E.md_hlo[i] = (int32_t)hl;
     E.md_hup[i] = (int32_t)hu;
     E.md_slot[i] = slot;
-    E.md_x[i] = xL;
-    E.md_y[i] = yL;
-    E.md_z[i] = L.z;
-    E.md_r[i] = o.r;
-    E.md_a[i] = o.a;
-    E.md_ca[i] = o.ca;
     const float dx = U.x - xL, dy = U.y - yL;
-    E.md_dx[i] = dx;
-    E.md_dy[i] = dy;
-    E.md_dn[i] = sqrtf((dx * dx) + (dy * dy));
-    E.md_bend[i] = o.bend;
-    E.md_sv[i] = o.sv;
+    E.md_p0[i] = make_float4(xL, yL, L.z, o.r);
     // the segment window's per-MD terms, rounded exactly as it would round them
-    E.md_ir[i] = 1.0f / o.r;
-    E.md_svr[i] = fabsf(o.sv) / o.r;
+    E.md_p1[i] = make_float4(o.a, o.ca, 1.0f / o.r, fabsf(o.sv) / o.r);
+    E.md_p2[i] = make_float4(dx, dy, sqrtf((dx * dx) + (dy * dy)), o.sv);
+    E.md_bend[i] = o.bend;
     E.md_bar[i] = (uint8_t)(mod.barrel | (mod.is2s << 1));
 }
 
@@ -621,7 +612,7 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
             int32_t o = 0;
             if (j < tot) {
                 o = obs + (int32_t)(j - ex);
-                ok = seg_accept(K, I, load_md(E, o));
+                ok = seg_accept(K, I, E, o);
             }
             uint32_t t;
             const uint32_t r = gp.rank(ok, t);
