@@ -204,7 +204,7 @@ def _gen(args):
     return E.generate(cid, e)
 
 
-def pregenerate(scorer=True, batch=True, stress=True, n_train=150, n_eval=8):
+def pregenerate(scorer=True, batch=True, stress=True, pu200=True, n_train=150, n_eval=8):
     """every synthetic event the side legs need, generated by a pool of CPU
     workers before this process touches the GPU"""
     import multiprocessing as mp
@@ -217,6 +217,8 @@ def pregenerate(scorer=True, batch=True, stress=True, n_train=150, n_eval=8):
             out["batch"] = pool.map(_gen, [(3, e) for e in range(64)])
         if stress:
             out["stress"] = pool.map(_gen, [(5, e) for e in range(16)])
+        if pu200:
+            out["pu200"] = pool.map(_gen, [(2, 100 + e) for e in range(16)])
     return out
 
 
@@ -348,11 +350,11 @@ def scored(lst, torch, train, evs, steps=50):
                               kern("k_mlp_score<T5>", ms5, cnt["n_t5"])]}, model
 
 
-def multistream(lst, torch, G, PR, evs, n_streams=8, rounds=3):
+def multistream(lst, torch, G, PR, evs, n_streams=8, rounds=3, geometry="barrel_toy"):
     """The paper's concurrency scheme on this GPU: the same events one per
     launch, spread over n_streams HIP streams (default priority), each with
     its own context and hipGraph; hits already in device memory."""
-    geo = G.get("barrel_toy")
+    geo = G.get(geometry)
     params = PR.make()
     dev = []
     for ev in evs:
@@ -382,6 +384,34 @@ def multistream(lst, torch, G, PR, evs, n_streams=8, rounds=3):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return {"streams": n_streams, "events": len(evs), "events_per_s": rounds * len(evs) / dt}
+
+
+def pu200_concurrent(lst, torch, E, G, PR, evs, steps=20):
+    """Several PU200-like events in flight at once: 16 events (config 2,
+    seeds 100..115) as one batched launch (tuned launch shape, one hipGraph
+    replay per batch), and the same events one per launch over 8 streams."""
+    geo = G.get("full")
+    params = PR.make()
+    b = E.concat(evs)
+    ctx = lst.Context(params, geo.f32, geo.i32, device=0)
+    ctx.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+    tuned = ctx.tune(reps=3)
+    ctx.load_hits(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+    stream = torch.cuda.current_stream()
+    ctx.run_chain_graph(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.run_chain_graph(stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    kept = int(sum(ctx.counts(e)["n_t5_kept"] for e in range(len(evs))))
+    del ctx
+    return {"workload": f"{len(evs)} PU200-like events (config 2, seeds 100..{99 + len(evs)})",
+            "hits": int(b.offsets[-1]), "t5_kept": kept,
+            "batched_events_per_s": len(evs) / dt, "ms_per_batch": 1e3 * dt,
+            "tuning": {k: tuned[k] for k in ("grid", "lanes", "persistent", "blocks_per_cu")},
+            "multistream_8": multistream(lst, torch, G, PR, evs, geometry="full")}
 
 
 def stress(lst, torch, E, G, PR, evs, model=None, steps=10):
@@ -441,6 +471,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-event batch figures")
     ap.add_argument("--no-scorer", action="store_true", help="skip the learned-scorer figures")
     ap.add_argument("--no-stress", action="store_true", help="skip the config-5 stress figures")
+    ap.add_argument("--no-concurrent", action="store_true",
+                    help="skip the figures with several PU200-like events in flight")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the 64-event batch leg and print its figures (for profiling)")
     ap.add_argument("--tune-cache", default=None,
@@ -452,7 +484,7 @@ def main():
         sys.exit(2)
 
     if args.batch_only:
-        pre = pregenerate(scorer=False, batch=True, stress=False)
+        pre = pregenerate(scorer=False, batch=True, stress=False, pu200=False)
         import torch
         import paper_2209_13711_amd as lst
         from synth import events as E, geometry as G, params as PR
@@ -460,7 +492,7 @@ def main():
                                              cache=args.tune_cache, compare=False)}), flush=True)
         return
     pre = pregenerate(scorer=not args.no_scorer, batch=not args.no_batch,
-                      stress=not args.no_stress)
+                      stress=not args.no_stress, pu200=not args.no_concurrent)
     cpu_all = None if args.no_cpu else cpu_all_cores()
 
     import torch
@@ -574,6 +606,8 @@ def main():
                      "copy_GBps_measured": copy_gbs,
                      "frac_vs_copy": achieved / copy_gbs},
     }
+    if not args.no_concurrent:
+        out["pu200_concurrent"] = pu200_concurrent(lst, torch, E, G, PR, pre["pu200"])
     if not args.no_batch:
         out["batched"] = batched(lst, torch, E, G, PR, pre["batch"], cache=args.tune_cache)
         out["batched"]["multistream_8"] = multistream(lst, torch, G, PR, pre["batch"])

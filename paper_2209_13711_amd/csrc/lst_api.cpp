@@ -188,6 +188,7 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.md_p1 = cv.take<float4>(nmd);
     E.md_p2 = cv.take<float4>(nmd);
     E.md_bend = cv.take<float>(nmd);
+    E.md_atol = cv.take<float>(nmd);
 
     E.md_bar = cv.take<uint8_t>(nmd);
     E.md_start = cv.take<int32_t>(slots);

@@ -133,7 +133,11 @@ __device__ __forceinline__ float tri_curv(const MdV &A, const MdV &B, const MdV 
 }
 
 // Segment I -> O: azimuthal window (S2), pointing along the prompt circle
-// (S1), relative angle of each barrel MD direction to the chord (S3).
+// (S1), relative angle of each barrel MD direction to the chord (S3).  The
+// decision is the AND of the three cuts, so it is split in two calls that
+// can run at different times: seg_window (S2, about a third of the pairs
+// pass it) and seg_rest (S1 and S3).  Both compute their shared terms by
+// the same FP32 operations, so the pair gives the single test's result.
 // The azimuth window S2 decides exactly as `-(dot / rr) <= 0 && |crs / rr| <=
 // B` would, but divides only when the division-free tests cannot decide:
 //  * dot >= 0 implies -(dot / rr) <= 0 (rr > 0);
@@ -143,20 +147,17 @@ __device__ __forceinline__ float tri_curv(const MdV &A, const MdV &B, const MdV 
 //    2^-20 exceeds the three FP32 roundings (2^-24 each) between the two
 //    forms, and rounding is monotone, so fl(|crs| / rr) falls on the same
 //    side of B.  NaN and infinities take the exact path or agree with it.
-// The per-MD terms 1 / r and |sv| / r come precomputed from the MD stage,
-// rounded by the same FP32 division.  The outer MD o is gathered in two
-// steps: what the window needs first, the rest only for candidates inside it.
-__device__ __forceinline__ bool seg_accept(const Consts &K, const MdV &I, const EvDev &E, int32_t o)
+// The per-MD terms 1 / r, |sv| / r and the S3 bound w (tol_u / |d|) come
+// precomputed from the MD stage, rounded by the same FP32 operations.
+__device__ __forceinline__ bool seg_window(const Consts &K, float xi, float yi, float ri, float ai,
+                                           float cai, float iri, float svri, const float4 &p0,
+                                           const float4 &p1)
 {
-    MdV O;
-    const float4 p0 = E.md_p0[o], p1 = E.md_p1[o];
-    O.x = p0.x; O.y = p0.y; O.z = p0.z; O.r = p0.w;
-    O.a = p1.x; O.ca = p1.y; O.ir = p1.z; O.svr = p1.w;
-    float rr = I.r * O.r;
-    float crs = (I.x * O.y) - (I.y * O.x);
-    float dot = (I.x * O.x) + (I.y * O.y);
-    float sphi = (O.a * I.ca) - (I.a * O.ca);
-    float tphi = (K.tolu * (I.ir + O.ir)) + (K.tolv * (I.svr + O.svr));
+    float rr = ri * p0.w;
+    float crs = (xi * p0.y) - (yi * p0.x);
+    float dot = (xi * p0.x) + (yi * p0.y);
+    float sphi = (p1.x * cai) - (ai * p1.y);
+    float tphi = (K.tolu * (iri + p1.z)) + (K.tolv * (svri + p1.w));
     float B = K.w * (sphi + tphi);
     bool c_ok = (dot >= 0.0f) || (-(dot / rr) <= 0.0f);
     float X = fabsf(crs), P = B * rr;
@@ -168,32 +169,51 @@ __device__ __forceinline__ bool seg_accept(const Consts &K, const MdV &I, const 
         s_ok = false;
     else
         s_ok = fabsf(crs / rr) <= B;
-    if (!(c_ok && s_ok)) return false;
-    const float4 p2 = E.md_p2[o];
-    O.dx = p2.x; O.dy = p2.y; O.dn = p2.z; O.sv = p2.w;
-    O.barrel = E.md_bar[o] & 1;
+    return c_ok && s_ok;
+}
+
+// the inner MD as seg_rest reads it: anchor (x, y, z, r), direction
+// (dx, dy, |d|, S3 bound), barrel flag
+struct SegIn {
+    float4 p, d;
+    int barrel;
+};
+
+__device__ __forceinline__ bool seg_rest(const Consts &K, const SegIn &I, const EvDev &E, int32_t o)
+{
+    const float4 p0 = E.md_p0[o], p2 = E.md_p2[o];
+    const int ob = E.md_bar[o] & 1;
+    const float xi = I.p.x, yi = I.p.y, zi = I.p.z, ri = I.p.w;
+    float rr = ri * p0.w;
+    float crs = (xi * p0.y) - (yi * p0.x);
     float S = crs / rr;
-    float qx = O.x - I.x, qy = O.y - I.y;
+    float qx = p0.x - xi, qy = p0.y - yi;
     float ql = sqrtf((qx * qx) + (qy * qy));
     float kO = (2.0f * crs) / (rr * ql);
-    float si = arc(I.r, kO);
-    float so = arc(O.r, kO);
+    float si = arc(ri, kO);
+    float so = arc(p0.w, kO);
     float ds = so - si;
-    float z0 = ((I.z * so) - (O.z * si)) / ds;
-    float sl = (O.z - I.z) / ds;
+    float z0 = ((zi * so) - (p0.z * si)) / ds;
+    float sl = (p0.z - zi) / ds;
     float szi = I.barrel ? K.sigv : (fabsf(sl) * K.sigv);
-    float szo = O.barrel ? K.sigv : (fabsf(sl) * K.sigv);
+    float szo = ob ? K.sigv : (fabsf(sl) * K.sigv);
     float tolz = K.nsig * (((so * szi) + (si * szo)) / ds);
     if (!(fabsf(z0) <= K.w * (K.z0max + tolz))) return false;
     if (I.barrel) {
-        float sa = ((I.dx * qy) - (I.dy * qx)) / (I.dn * ql);
-        if (!(fabsf(sa - S) <= K.w * (K.tolu / I.dn))) return false;
+        float sa = ((I.d.x * qy) - (I.d.y * qx)) / (I.d.z * ql);
+        if (!(fabsf(sa - S) <= I.d.w)) return false;
     }
-    if (O.barrel) {
-        float sb = ((qx * O.dy) - (qy * O.dx)) / (ql * O.dn);
-        if (!(fabsf(sb - S) <= K.w * (K.tolu / O.dn))) return false;
+    if (ob) {
+        float sb = ((qx * p2.y) - (qy * p2.x)) / (ql * p2.z);
+        if (!(fabsf(sb - S) <= E.md_atol[o])) return false;
     }
     return true;
+}
+
+// S3 bound of an MD with direction length dn (the MD stage stores it)
+__device__ __forceinline__ float seg_angle_bound(const Consts &K, float dn)
+{
+    return K.w * (K.tolu / dn);
 }
 
 // variance of an anchor along the track normal

@@ -92,6 +92,7 @@ struct EvDev {
     // (dx, dy, |d|, sv)
     float4 *md_p0, *md_p1, *md_p2;
     float *md_bend;
+    float *md_atol;                  // S3 bound w tol_u / |d| of the segment test
     uint8_t *md_bar;                 // bit 0: barrel module, bit 1: 2S module
     int32_t *md_start, *md_cnt;      // [n_slots]
     // segments (grouped by inner MD)

@@ -392,8 +392,21 @@ hipError_t launch_sort(const EvDev &E, const ModDev &M, int grid, hipStream_t s)
 }
 
 // ---------------------------------------------------------------- LDS layouts
+// segment stage: per wave, the queue of window survivors (see enum_seg)
+constexpr int SEGQ = 128;             // ring entries: a full wave plus what is pending
+constexpr int MAXP = 64 / 8;          // groups per wave at the narrowest width
+struct SegQ {
+    float4 ip[MAXP], id[MAXP];        // inner MD of each group (SegIn)
+    int32_t ib[MAXP], idx[MAXP], off[MAXP];
+    int32_t o[SEGQ];
+    uint8_t g[SEGQ];
+};
+
 struct SmMD { uint32_t lo[WAVES][STAGE]; uint32_t up[WAVES][STAGE]; };
-struct SmSeg { int32_t o[WAVES][STAGE]; };
+struct SmSeg {
+    int32_t o[WAVES][STAGE];
+    SegQ q[WAVES];
+};
 struct SmT3 { int32_t b[WAVES][STAGE]; int32_t c[WAVES][STAGE]; float k[WAVES][STAGE]; };
 struct SmT5 {
     int32_t b[WAVES][STAGE], c[WAVES][STAGE], d[WAVES][STAGE], e[WAVES][STAGE];
@@ -422,8 +435,9 @@ __device__ __forceinline__ ModF load_mod(const ModDev &M, int m)
     return f;
 }
 
-__device__ __forceinline__ void write_md(const EvDev &E, uint32_t i, int slot, uint32_t hl,
-                                         uint32_t hu, const MdOut &o, const ModF &mod)
+__device__ __forceinline__ void write_md(const EvDev &E, const Consts &K, uint32_t i, int slot,
+                                         uint32_t hl, uint32_t hu, const MdOut &o,
+                                         const ModF &mod)
 {
     const float4 L = E.hsort[hl], U = E.hsort[hu];
     const float xL = L.x, yL = L.y;
@@ -434,7 +448,9 @@ __device__ __forceinline__ void write_md(const EvDev &E, uint32_t i, int slot, u
     E.md_p0[i] = make_float4(xL, yL, L.z, o.r);
     // the segment window's per-MD terms, rounded exactly as it would round them
     E.md_p1[i] = make_float4(o.a, o.ca, 1.0f / o.r, fabsf(o.sv) / o.r);
-    E.md_p2[i] = make_float4(dx, dy, sqrtf((dx * dx) + (dy * dy)), o.sv);
+    const float dn = sqrtf((dx * dx) + (dy * dy));
+    E.md_p2[i] = make_float4(dx, dy, dn, o.sv);
+    E.md_atol[i] = seg_angle_bound(K, dn);
     E.md_bend[i] = o.bend;
     E.md_bar[i] = (uint8_t)(mod.barrel | (mod.is2s << 1));
 }
@@ -524,7 +540,7 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
                 MdOut o;
                 const float4 L = E.hsort[hl], U = E.hsort[hu];
                 md_accept(K, mod, L.x, L.y, L.z, U.x, U.y, U.z, o);
-                write_md(E, off + k, slot, hl, hu, o, mod);
+                write_md(E, K, off + k, slot, hl, hu, o, mod);
             }
         }
         if (wave_max(cnt) > CAP) {
@@ -536,7 +552,7 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
                                MdOut o;
                                const float4 L = E.hsort[hl], U = E.hsort[hu];
                                md_accept(K, mod, L.x, L.y, L.z, U.x, U.y, U.z, o);
-                               write_md(E, off + pos, slot, hl, hu, o, mod);
+                               write_md(E, K, off + pos, slot, hl, hu, o, mod);
                            }
                        });
         }
@@ -544,7 +560,7 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
 }
 
 template <int G>
-__global__ __launch_bounds__(BLOCK) void k_md(EvDev E, ModDev M, Consts K)
+__global__ __launch_bounds__(BLOCK, 6) void k_md(EvDev E, ModDev M, Consts K)
 {
     __shared__ SmMD sm;
     md_body<G>(E, M, K, sm);
@@ -571,17 +587,41 @@ hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, int grid,
 
 // ---------------------------------------------------------------- segments
 // Outer candidates of inner MD i: the MDs of every map edge of its module,
-// in edge order; one group of G lanes per inner MD.  sink(ok, o, pos)
+// in edge order; one group of G lanes per inner MD.  The pairs inside the
+// azimuth window (about a third of them) go to a ring of the wave in LDS,
+// and the rest of the test runs on full waves of 64 queued pairs, so the
+// costly part of the test runs once per window survivor rather than once
+// per pair.  Accepted pairs get, per inner MD, consecutive positions in
+// enumeration order.  sink(g, ok, o, pos): g is the group of the pair's
+// inner MD.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    // orders the wave's LDS writes before its later LDS reads by other lanes
+    // (a wave's LDS operations complete in issue order)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int G, class F>
 __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, const Consts &K,
-                                             int32_t i, bool act, F &&sink)
+                                             int32_t i, bool act, SegQ &q, F &&sink)
 {
+    constexpr int P = Grp<G>::P;
     const Grp<G> gp;
-    MdV I = {};
+    float xi = 0.0f, yi = 0.0f, ri = 0.0f, ai = 0.0f, cai = 0.0f, iri = 0.0f, svri = 0.0f;
     int base_slot = 0;
     int32_t e0 = 0, ne = 0;
     if (act) {
-        I = load_md(E, i);
+        const float4 p0 = E.md_p0[i], p1 = E.md_p1[i];
+        xi = p0.x; yi = p0.y; ri = p0.w;
+        ai = p1.x; cai = p1.y; iri = p1.z; svri = p1.w;
+        if (gp.lane == 0) {
+            const float4 p2 = E.md_p2[i];
+            q.ip[gp.g] = p0;
+            q.id[gp.g] = make_float4(p2.x, p2.y, p2.z, E.md_atol[i]);
+            q.ib[gp.g] = E.md_bar[i] & 1;
+        }
         const int slot = E.md_slot[i];
         const int ev = slot / M.n_mod;
         const int m = slot - ev * M.n_mod;
@@ -589,7 +629,39 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
         e0 = M.map_ptr[m];
         ne = M.map_ptr[m + 1] - e0;
     }
-    uint32_t cnt = 0;
+    uint32_t cnt[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) cnt[p] = 0;
+    uint32_t head = 0, tail = 0;                  // ring positions (wave-uniform)
+    const unsigned long long below = lanes_below();
+    // the rest of the test on the n (<= 64) oldest queued pairs
+    auto drain = [&](uint32_t n) {
+        wave_lds_sync();
+        const uint32_t l = (uint32_t)lane_id();
+        bool ok = false;
+        int32_t o = 0;
+        int g = 0;
+        if (l < n) {
+            const uint32_t s = (head + l) & (SEGQ - 1);
+            o = q.o[s];
+            g = q.g[s];
+            SegIn I;
+            I.p = q.ip[g];
+            I.d = q.id[g];
+            I.barrel = q.ib[g];
+            ok = seg_rest(K, I, E, o);
+        }
+        head += n;
+        uint32_t pos = 0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const unsigned long long mk = __ballot(ok && g == p);
+            if (g == p) pos = cnt[p] + (uint32_t)__popcll(mk & below);
+            cnt[p] += (uint32_t)__popcll(mk);
+        }
+        sink(g, ok, o, pos);
+        wave_lds_sync();                          // slots are rewritten by later pairs
+    };
     const int32_t ne_max = (int32_t)wave_max((uint32_t)ne);
     for (int32_t ec = 0; ec < ne_max; ec += G) {
         const int32_t e = ec + gp.lane;
@@ -608,19 +680,28 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
             const int src = gp.find(incl, j < tot ? j : (tot ? tot - 1 : 0));
             const uint32_t ex = gp.bcast(incl, src) - gp.bcast(bc, src);
             const int32_t obs = gp.bcast(bs, src);
-            bool ok = false;
+            bool win = false;
             int32_t o = 0;
             if (j < tot) {
                 o = obs + (int32_t)(j - ex);
-                ok = seg_accept(K, I, E, o);
+                win = seg_window(K, xi, yi, ri, ai, cai, iri, svri, E.md_p0[o], E.md_p1[o]);
             }
-            uint32_t t;
-            const uint32_t r = gp.rank(ok, t);
-            sink(ok, o, cnt + r);
-            cnt += t;
+            const unsigned long long mk = __ballot(win);
+            if (win) {
+                const uint32_t s = (tail + (uint32_t)__popcll(mk & below)) & (SEGQ - 1);
+                q.o[s] = o;
+                q.g[s] = (uint8_t)gp.g;
+            }
+            tail += (uint32_t)__popcll(mk);
+            if (tail - head >= 64) drain(64);
         }
     }
-    return cnt;
+    if (tail != head) drain(tail - head);
+    uint32_t c = 0;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+        if (gp.g == p) c = cnt[p];
+    return c;
 }
 
 template <int G>
@@ -630,14 +711,16 @@ __device__ __forceinline__ void seg_body(const EvDev &E, const ModDev &M, const 
     constexpr int P = Grp<G>::P, CAP = STAGE / P;
     const Grp<G> gp;
     const int w = wave_id();
+    SegQ &q = sm.q[w];
     const XBlock xb = xcd_block();
     const XRegions R = load_regions_x(E, OT_MD, xb.x);
     for (uint32_t base = xb.rank * WAVES * P; base < R.total; base += xb.count * WAVES * P) {
         const uint32_t v = base + w * P + gp.g;
         const bool act = v < R.total;
         const int32_t i = region_index_x(R, act ? v : 0);
-        const uint32_t cnt = enum_seg<G>(E, M, K, i, act, [&](bool ok, int32_t o, uint32_t pos) {
-            if (ok && pos < CAP) sm.o[w][gp.g * CAP + pos] = o;
+        const uint32_t cnt = enum_seg<G>(E, M, K, i, act, q,
+                                         [&](int g, bool ok, int32_t o, uint32_t pos) {
+            if (ok && pos < CAP) sm.o[w][g * CAP + pos] = o;
         });
         uint32_t wtot;
         const uint32_t gex = gp.wave_prefix(cnt, wtot);
@@ -655,10 +738,16 @@ __device__ __forceinline__ void seg_body(const EvDev &E, const ModDev &M, const 
             }
         }
         if (wave_max(cnt) > CAP) {
-            enum_seg<G>(E, M, K, i, act && cnt > CAP, [&](bool ok, int32_t o, uint32_t pos) {
+            // groups beyond their staging share enumerate again and write directly
+            if (gp.lane == 0) {
+                q.idx[gp.g] = i;
+                q.off[gp.g] = (int32_t)off;
+            }
+            enum_seg<G>(E, M, K, i, act && cnt > CAP, q,
+                        [&](int g, bool ok, int32_t o, uint32_t pos) {
                 if (ok) {
-                    E.seg_in[off + pos] = i;
-                    E.seg_out[off + pos] = o;
+                    E.seg_in[q.off[g] + pos] = q.idx[g];
+                    E.seg_out[q.off[g] + pos] = o;
                 }
             });
         }
@@ -666,7 +755,7 @@ __device__ __forceinline__ void seg_body(const EvDev &E, const ModDev &M, const 
 }
 
 template <int G>
-__global__ __launch_bounds__(BLOCK) void k_seg(EvDev E, ModDev M, Consts K)
+__global__ __launch_bounds__(BLOCK, 5) void k_seg(EvDev E, ModDev M, Consts K)
 {
     __shared__ SmSeg sm;
     seg_body<G>(E, M, K, sm);
@@ -785,7 +874,7 @@ __device__ __forceinline__ void t3_body(const EvDev &E, const Consts &K, SmT3 &s
 }
 
 template <int G>
-__global__ __launch_bounds__(BLOCK) void k_t3(EvDev E, Consts K)
+__global__ __launch_bounds__(BLOCK, 6) void k_t3(EvDev E, Consts K)
 {
     __shared__ SmT3 sm;
     t3_body<G>(E, K, sm);
@@ -915,7 +1004,7 @@ __device__ __forceinline__ void t5_body(const EvDev &E, const Consts &K, SmT5 &s
 }
 
 template <int G>
-__global__ __launch_bounds__(BLOCK) void k_t5(EvDev E, Consts K)
+__global__ __launch_bounds__(BLOCK, 5) void k_t5(EvDev E, Consts K)
 {
     __shared__ SmT5 sm;
     t5_body<G>(E, K, sm);
@@ -997,66 +1086,71 @@ __device__ __forceinline__ bool tuple_less(const EvDev &E, int32_t u, const int3
     return false;
 }
 
-// one thread per quintuplet
+// one group of 16 lanes per quintuplet: lane j < 10 checks hit j, so the
+// ten hits' tie lists are read side by side; the quintuplet is kept iff no
+// lane of its group finds a smaller key
+constexpr int KEEP_LANES = 16;
+
 __device__ __forceinline__ void dedup_keep_body(const EvDev &E, uint32_t *s_pre)
 {
     if (upstream_overflow(E)) return;
     const uint32_t n = t5_prefix(E, s_pre);
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        const int32_t t = t5_at(E, s_pre, v);
-        if (E.t5_veto[t]) {
-            E.t5_keep[t] = 0;
-            continue;
+    constexpr uint32_t PER_WAVE = 64 / KEEP_LANES, PER_BLOCK = BLOCK / KEEP_LANES;
+    const int gl = lane_id() % KEEP_LANES, gi = lane_id() / KEEP_LANES;
+    for (uint32_t v0 = blockIdx.x * PER_BLOCK + wave_id() * PER_WAVE; v0 < n;
+         v0 += gridDim.x * PER_BLOCK) {
+        const uint32_t v = v0 + gi;
+        bool bad = false, veto = false;
+        int32_t t = 0;
+        if (v < n && gl < 10) {
+            t = t5_at(E, s_pre, v);
+            veto = E.t5_veto[t] != 0;
         }
-        const float sc = E.t5_score[t];
-        const uint32_t key = __float_as_uint(sc);
-        int32_t h[10], own[10];
-        const int2 *ph = reinterpret_cast<const int2 *>(E.t5_hs + (size_t)t * 10);
-        const int2 *po = reinterpret_cast<const int2 *>(E.t5_ho + (size_t)t * 10);
+        if (v < n && gl < 10 && !veto) {
+            const float sc = E.t5_score[t];
+            const int32_t h = E.t5_hs[(size_t)t * 10 + gl];
+            const int nt = E.htie[h];
+            bad = E.hmin[h] != __float_as_uint(sc);
+            if (!bad && nt > 1) {
+                int32_t own[10];
+                const int2 *po = reinterpret_cast<const int2 *>(E.t5_ho + (size_t)t * 10);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            const int2 a = ph[k], b = po[k];
-            h[2 * k] = a.x;
-            h[2 * k + 1] = a.y;
-            own[2 * k] = b.x;
-            own[2 * k + 1] = b.y;
-        }
-        uint32_t hm[10];
-        int nt[10];
+                for (int k = 0; k < 5; ++k) {
+                    const int2 b2 = po[k];
+                    own[2 * k] = b2.x;
+                    own[2 * k + 1] = b2.y;
+                }
+                const int ns = nt < TIE_SLOTS ? nt : TIE_SLOTS;
+                int32_t us[TIE_SLOTS];
 #pragma unroll
-        for (int j = 0; j < 10; ++j) {
-            hm[j] = E.hmin[h[j]];
-            nt[j] = E.htie[h[j]];
-        }
-        bool keep = true;
+                for (int k = 0; k < TIE_SLOTS; ++k)
+                    us[k] = k < ns ? E.hslot[(size_t)h * TIE_SLOTS + k] : t;
 #pragma unroll
-        for (int j = 0; j < 10; ++j) keep = keep && (hm[j] == key);
-        for (int j = 0; j < 10 && keep; ++j) {
-            if (nt[j] <= 1) continue;
-            const int ns = nt[j] < TIE_SLOTS ? nt[j] : TIE_SLOTS;
-            for (int k = 0; k < ns && keep; ++k) {
-                const int32_t u = E.hslot[(size_t)h[j] * TIE_SLOTS + k];
-                if (u != t && tuple_less(E, u, own)) keep = false;
-            }
-            if (nt[j] <= TIE_SLOTS || !keep) continue;
-            // further ties are chained in the pool
-            int listed = 0;
-            for (int32_t e = E.thead[h[j]]; e != 0 && keep; e = E.tpool_next[e - 1], ++listed) {
-                const int32_t u = E.tpool_t5[e - 1];
-                if (u != t && tuple_less(E, u, own)) keep = false;
-            }
-            if (keep && listed < nt[j] - TIE_SLOTS) {
-                // the pool ran out: scan every quintuplet (correct, slow)
-                for (uint32_t q = 0; q < n && keep; ++q) {
-                    const int32_t u = t5_at(E, s_pre, q);
-                    if (u == t || E.t5_veto[u] || E.t5_score[u] != sc) continue;
-                    bool uses = false;
-                    for (int k = 0; k < 10; ++k) uses |= (E.t5_hs[(size_t)u * 10 + k] == h[j]);
-                    if (uses && tuple_less(E, u, own)) keep = false;
+                for (int k = 0; k < TIE_SLOTS; ++k)
+                    if (!bad && us[k] != t && tuple_less(E, us[k], own)) bad = true;
+                if (!bad && nt > TIE_SLOTS) {
+                    // further ties are chained in the pool
+                    int listed = 0;
+                    for (int32_t e = E.thead[h]; e != 0 && !bad; e = E.tpool_next[e - 1], ++listed) {
+                        const int32_t u = E.tpool_t5[e - 1];
+                        if (u != t && tuple_less(E, u, own)) bad = true;
+                    }
+                    if (!bad && listed < nt - TIE_SLOTS) {
+                        // the pool ran out: scan every quintuplet (correct, slow)
+                        for (uint32_t q = 0; q < n && !bad; ++q) {
+                            const int32_t u = t5_at(E, s_pre, q);
+                            if (u == t || E.t5_veto[u] || E.t5_score[u] != sc) continue;
+                            bool uses = false;
+                            for (int k = 0; k < 10; ++k) uses |= (E.t5_hs[(size_t)u * 10 + k] == h);
+                            if (uses && tuple_less(E, u, own)) bad = true;
+                        }
+                    }
                 }
             }
         }
-        E.t5_keep[t] = keep ? 1 : 0;
+        const unsigned long long m = __ballot(bad);
+        const bool any_bad = ((m >> (gi * KEEP_LANES)) & ((1ull << KEEP_LANES) - 1ull)) != 0;
+        if (v < n && gl == 0) E.t5_keep[t] = (veto || any_bad) ? 0 : 1;
     }
 }
 
