@@ -44,7 +44,7 @@ def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
     when the summary is absent or was taken from other kernel source."""
-    path = os.path.join(TRAFFIC_DIR, kernel.split("<")[0] + "_pu200_traffic.txt")
+    path = os.path.join(TRAFFIC_DIR, "chain_pu200_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -52,9 +52,10 @@ def measured_traffic(kernel):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel") != kernel or kv.get("source_digest") != kernel_source_digest():
+    key = f"hbm_bytes_per_launch[{kernel}]"
+    if kv.get("source_digest") != kernel_source_digest() or key not in kv:
         return None
-    return float(kv["hbm_bytes_per_launch"])
+    return float(kv[key])
 
 
 def copy_bandwidth(lst, torch, reps=10):
@@ -76,14 +77,28 @@ def copy_bandwidth(lst, torch, reps=10):
 
 def algorithmic_bytes(c, n_slots, n_edges_used):
     """Minimal bytes per launch of each object kernel: every input read once,
-    every output written once (layouts of the library's SoA arrays)."""
+    every output written once, in the library's layouts.
+    md:  sorted hit (16 B) read and its duplicate-removal state (12 B) set per
+         hit; per slot two bin offsets (8 B), the module frame (52 B) and the
+         slot's MD start and count (8 B); per MD its record written (69 B:
+         hit pair and slot 12, three float4 48, bend 4, S3 bound 4, flags 1)
+    seg: per MD its record read (57 B: window and rest terms, slot) and its
+         segment start and count written (8 B); per slot MD start and count
+         and the map row (12 B); per map edge read its column (4 B); per
+         segment its MD pair written (8 B)
+    t3:  per MD its record (49 B) and segment start/count (8 B) read, triplet
+         start/count written (8 B); per segment its outer MD (4 B); per
+         triplet its MDs and curvature (16 B) and scorer flag (1 B) written
+    t5:  per MD its record (49 B) and triplet start/count (8 B); per triplet
+         its MDs, curvature and flag (17 B); per quintuplet its five MDs,
+         score and flag (25 B) written"""
     H, S = c["n_hits"], n_slots
     md, seg, t3, t5 = c["n_md"], c["n_seg"], c["n_t3"], c["n_t5"]
     return {
-        "md": 12 * H + 16 * S + 57 * md,
-        "seg": 49 * md + 8 * S + 4 * n_edges_used + 8 * seg,
-        "t3": 57 * md + 8 * seg + 16 * t3,
-        "t5": 49 * md + 16 * t3 + 25 * t5,
+        "md": 28 * H + 68 * S + 69 * md,
+        "seg": 65 * md + 12 * S + 4 * n_edges_used + 8 * seg,
+        "t3": 65 * md + 4 * seg + 17 * t3,
+        "t5": 57 * md + 17 * t3 + 25 * t5,
     }
 
 
