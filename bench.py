@@ -495,7 +495,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); events are "
-              "independent, see DESIGN.md for how the batch would shard", file=sys.stderr)
+              "independent, so a batch would shard across GPUs by event with no exchange", file=sys.stderr)
         sys.exit(2)
 
     if args.batch_only:
