@@ -213,13 +213,19 @@ def _gen_eval(e):
     return E.generate(4, e)
 
 
+def _gen_train_full(e):
+    from synth import events as E
+    return E.generate(2, e, purpose=E.PURPOSE_TRAIN, cfg=E.scorer_training_config(E.CONFIGS[2]))
+
+
 def _gen(args):
     from synth import events as E
     cid, e = args
     return E.generate(cid, e)
 
 
-def pregenerate(scorer=True, batch=True, stress=True, pu200=True, n_train=150, n_eval=8):
+def pregenerate(scorer=True, batch=True, stress=True, pu200=True, n_train=150, n_eval=8,
+                n_train_full=80):
     """every synthetic event the side legs need, generated by a pool of CPU
     workers before this process touches the GPU"""
     import multiprocessing as mp
@@ -228,6 +234,8 @@ def pregenerate(scorer=True, batch=True, stress=True, pu200=True, n_train=150, n
         if scorer:
             out["train"] = pool.map(_gen_train, range(n_train))
             out["eval"] = pool.map(_gen_eval, range(n_eval))
+            out["train_full"] = pool.map(_gen_train_full, range(n_train_full))
+            out["eval_full"] = pool.map(_gen, [(2, 200 + e) for e in range(n_eval)])
         if batch:
             out["batch"] = pool.map(_gen, [(3, e) for e in range(64)])
         if stress:
@@ -266,7 +274,7 @@ def cpu_all_cores(budget_s=8.0):
                                         f"one oracle process per core, {budget_s:.0f} s each"}
 
 
-def scored(lst, torch, train, evs, steps=50):
+def scored(lst, torch, train, evs, steps=50, base_cfg=4):
     """Learned scorers end to end on the GPU: triplets of the training events
     (widened windows), then the quintuplets that survive the trained triplet
     veto, labelled by truth and trained by the library's kernels; thresholds
@@ -274,11 +282,12 @@ def scored(lst, torch, train, evs, steps=50):
     Then the plain chain at nominal windows against the widened chain +
     scorers on held-out 4000-helix events (efficiency / fake rate by truth,
     events/s of one event per hipGraph replay), and the two scoring kernels
-    timed with HIP events on the launch stream."""
+    timed with HIP events on the launch stream.  base_cfg 4: barrel toy
+    geometry; 2: the full geometry (barrel and endcap disks, noise hits)."""
     from paper_2209_13711_amd import scorer as S
     from synth import events as E, geometry as G, params as PR, weights as W
-    geo = G.get("barrel_toy")
-    w_train = E.scorer_training_config(E.CONFIGS[4]).window
+    geo = G.get(E.CONFIGS[base_cfg].geometry)
+    w_train = E.scorer_training_config(E.CONFIGS[base_cfg]).window
     ctx_w = lst.Context(PR.make(w=w_train), geo.f32, geo.i32, device=0)
     models, info = {}, {}
     for kind, name, keep in ((lst.LST_T3, "t3", 0.995), (lst.LST_T5, "t5", 0.99)):
@@ -354,9 +363,11 @@ def scored(lst, torch, train, evs, steps=50):
                 "achieved_TFLOPs": n * MLP_FLOPS / (us * 1e-6) / 1e12, "peak_TFLOPs": 2500.0}
 
     model = models
-    return {"workload": "scorers trained on triplets and quintuplets of 150 training events "
-                        "(barrel toy, 20 x Poisson(U(50,250)) helices, windows x1.5), evaluated on "
-                        "8 held-out 4000-helix events (config 4)",
+    where = ("barrel toy" if base_cfg == 4 else
+             "full geometry, 1 % inefficiency, 5 % noise hits")
+    return {"workload": f"scorers trained on triplets and quintuplets of {len(train)} training "
+                        f"events ({where}, 20 x Poisson(U(50,250)) helices, windows x1.5), "
+                        f"evaluated on {len(evs)} held-out 4000-helix events (config {base_cfg})",
             "training": info,
             "plain_w1": {k: m_plain[k] for k in ("eff", "fake", "dup", "impure", "n_obj")},
             "scored_w1.5": {k: m_scored[k] for k in ("eff", "fake", "dup", "impure", "n_obj")},
@@ -629,6 +640,8 @@ def main():
     model = None
     if not args.no_scorer:
         out["scored"], model = scored(lst, torch, pre["train"], pre["eval"])
+        out["scored_full_geometry"], _ = scored(lst, torch, pre["train_full"], pre["eval_full"],
+                                                base_cfg=2)
     if not args.no_stress:
         out["stress"] = stress(lst, torch, E, G, PR, pre["stress"], model)
     if not args.no_cpu:
