@@ -440,6 +440,46 @@ def pu200_concurrent(lst, torch, E, G, PR, evs, steps=20):
             "multistream_8": multistream(lst, torch, G, PR, evs, geometry="full")}
 
 
+def memory(lst, torch, G, PR, evs, quantiles=(0.999, 0.9999)):
+    """Memory of this library's arena against the paper's layout of fixed
+    per-module capacities truncated at an occupancy quantile, on PU200-like
+    events.  Per object type (keyed by the module of its first hit): the
+    per-module capacity at each quantile and at the maximum of the per-module
+    counts over all modules of all events, the arena bytes those capacities
+    imply, and the share of objects that modules above capacity would drop.
+    The library itself sizes its object arrays by the event's counts and
+    drops nothing."""
+    geo = G.get("full")
+    ctx = lst.Context(PR.make(), geo.f32, geo.i32, device=0)
+    kinds = {"md": lst.LST_MD, "seg": lst.LST_SEG, "t3": lst.LST_T3, "t5": lst.LST_T5}
+    per_mod = {k: [] for k in kinds}
+    exact = dict(events=1, hits=1, md=1, seg=1, t3=1, t5=1)
+    for ev in evs:
+        ctx.run_event(ev)
+        exact["hits"] = max(exact["hits"], int(ev.n_hits))
+        for k, kind in kinds.items():
+            t = ctx.objects(0, kind)
+            exact[k] = max(exact[k], len(t))
+            mods = ev.module[t[:, 0]] if len(t) else np.zeros(0, np.int64)
+            per_mod[k].append(np.bincount(mods, minlength=geo.n_mod))
+    counts = {k: np.concatenate(v) for k, v in per_mod.items()}
+    out = {"events": len(evs), "modules": int(geo.n_mod),
+           "exact_arena_MB": ctx.arena_bytes(exact) / 1e6,
+           "grown_arena_MB": ctx.arena_bytes(ctx.caps) / 1e6,
+           "exact_caps": {k: int(exact[k]) for k in kinds}}
+    for name, q in [(f"q{100 * q:g}", q) for q in quantiles] + [("max", None)]:
+        cap = {k: int(np.ceil(np.quantile(c, q))) if q is not None else int(c.max())
+               for k, c in counts.items()}
+        caps = dict(exact, **{k: max(1, cap[k] * geo.n_mod) for k in kinds})
+        out[f"per_module_{name}"] = {
+            "cap_per_module": cap,
+            "arena_MB": ctx.arena_bytes(caps) / 1e6,
+            "dropped_frac": {k: float(np.maximum(counts[k] - cap[k], 0).sum() /
+                                      max(counts[k].sum(), 1)) for k in kinds}}
+    del ctx
+    return out
+
+
 def stress(lst, torch, E, G, PR, evs, model=None, steps=10):
     """16 PU300-like events (6000 helices, 5 % displaced, 10 % noise, windows
     x1.5) in one tuned launch: events/s and efficiency / fake / duplicate rate
@@ -634,6 +674,7 @@ def main():
     }
     if not args.no_concurrent:
         out["pu200_concurrent"] = pu200_concurrent(lst, torch, E, G, PR, pre["pu200"])
+        out["memory"] = memory(lst, torch, G, PR, pre["pu200"])
     if not args.no_batch:
         out["batched"] = batched(lst, torch, E, G, PR, pre["batch"], cache=args.tune_cache)
         out["batched"]["multistream_8"] = multistream(lst, torch, G, PR, pre["batch"])

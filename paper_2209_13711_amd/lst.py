@@ -200,6 +200,15 @@ class Context:
         return ctypes.c_void_p(stream.cuda_stream)
 
     # -- memory -------------------------------------------------------------
+    def arena_bytes(self, caps: dict) -> int:
+        """bytes of the arena the library needs for `caps` (lst_arena_bytes)"""
+        caps = dict(caps)
+        caps.setdefault("features", 0)
+        c = lst_caps(**caps)
+        nbytes = ctypes.c_size_t(0)
+        self._check(self.lib.lst_arena_bytes(self.h, ctypes.byref(c), ctypes.byref(nbytes)))
+        return int(nbytes.value)
+
     def reserve(self, caps: dict):
         caps = dict(caps)
         caps.setdefault("features", 0)
