@@ -397,6 +397,8 @@ constexpr int SEGQ = 128;             // ring entries: a full wave plus what is 
 constexpr int MAXP = 64 / 8;          // groups per wave at the narrowest width
 struct SegQ {
     float4 ip[MAXP], id[MAXP];        // inner MD of each group (SegIn)
+    float4 w0[MAXP], w1[MAXP];        // its window terms (x, y, r, a), (ca, 1/r, |sv|/r, -)
+    int2 eb[MAXP];                    // its module's first map edge, its event's first slot
     int32_t ib[MAXP], idx[MAXP], off[MAXP];
     int32_t o[SEGQ];
     uint8_t g[SEGQ];
@@ -609,35 +611,42 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
 {
     constexpr int P = Grp<G>::P;
     const Grp<G> gp;
-    float xi = 0.0f, yi = 0.0f, ri = 0.0f, ai = 0.0f, cai = 0.0f, iri = 0.0f, svri = 0.0f;
-    int base_slot = 0;
-    int32_t e0 = 0, ne = 0;
+    const Grp<64> gw;
+    const uint32_t l = (uint32_t)lane_id();
+    int32_t ne = 0;
     if (act) {
-        const float4 p0 = E.md_p0[i], p1 = E.md_p1[i];
-        xi = p0.x; yi = p0.y; ri = p0.w;
-        ai = p1.x; cai = p1.y; iri = p1.z; svri = p1.w;
-        if (gp.lane == 0) {
-            const float4 p2 = E.md_p2[i];
-            q.ip[gp.g] = p0;
-            q.id[gp.g] = make_float4(p2.x, p2.y, p2.z, E.md_atol[i]);
-            q.ib[gp.g] = E.md_bar[i] & 1;
-        }
         const int slot = E.md_slot[i];
         const int ev = slot / M.n_mod;
         const int m = slot - ev * M.n_mod;
-        base_slot = ev * M.n_mod;
-        e0 = M.map_ptr[m];
+        const int32_t e0 = M.map_ptr[m];
         ne = M.map_ptr[m + 1] - e0;
+        if (gp.lane == 0) {
+            const float4 p0 = E.md_p0[i], p1 = E.md_p1[i], p2 = E.md_p2[i];
+            q.ip[gp.g] = p0;
+            q.id[gp.g] = make_float4(p2.x, p2.y, p2.z, E.md_atol[i]);
+            q.ib[gp.g] = E.md_bar[i] & 1;
+            q.w0[gp.g] = make_float4(p0.x, p0.y, p0.w, p1.x);
+            q.w1[gp.g] = make_float4(p1.y, p1.z, p1.w, 0.0f);
+            q.eb[gp.g] = make_int2(e0, ev * M.n_mod);
+        }
     }
+    // the wave's (inner MD, map edge) pairs as one list in group order:
+    // pre[g] = edges of the groups before g
+    uint32_t pre[P + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+        pre[p + 1] = pre[p] + (uint32_t)__builtin_amdgcn_readlane(ne, p * G);
+    const uint32_t n_edges = pre[P];
     uint32_t cnt[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) cnt[p] = 0;
     uint32_t head = 0, tail = 0;                  // ring positions (wave-uniform)
     const unsigned long long below = lanes_below();
+    wave_lds_sync();
     // the rest of the test on the n (<= 64) oldest queued pairs
     auto drain = [&](uint32_t n) {
         wave_lds_sync();
-        const uint32_t l = (uint32_t)lane_id();
         bool ok = false;
         int32_t o = 0;
         int g = 0;
@@ -662,35 +671,47 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
         sink(g, ok, o, pos);
         wave_lds_sync();                          // slots are rewritten by later pairs
     };
-    const int32_t ne_max = (int32_t)wave_max((uint32_t)ne);
-    for (int32_t ec = 0; ec < ne_max; ec += G) {
-        const int32_t e = ec + gp.lane;
+    // 64 (MD, edge) pairs at a time: their candidates (the MDs of the edge's
+    // module) as one list the 64 lanes walk 64 at a time
+    for (uint32_t fc = 0; fc < n_edges; fc += 64) {
+        const uint32_t f = fc + l;
+        int ge = 0;
+        uint32_t gpre = 0;
+#pragma unroll
+        for (int p = 1; p < P; ++p)
+            if (f >= pre[p]) {
+                ge = p;
+                gpre = pre[p];
+            }
         uint32_t bc = 0;
         int32_t bs = 0;
-        if (e < ne) {
-            const int b = base_slot + M.map_col[e0 + e];
+        if (f < n_edges) {
+            const int2 eb = q.eb[ge];
+            const int b = eb.y + M.map_col[eb.x + (int32_t)(f - gpre)];
             bs = E.md_start[b];
             bc = (uint32_t)E.md_cnt[b];
         }
-        const uint32_t incl = gp.incl_scan(bc);
-        const uint32_t tot = gp.bcast(incl, G - 1);
-        const uint32_t tot_max = wave_max(tot);
-        for (uint32_t jc = 0; jc < tot_max; jc += G) {
-            const uint32_t j = jc + gp.lane;
-            const int src = gp.find(incl, j < tot ? j : (tot ? tot - 1 : 0));
-            const uint32_t ex = gp.bcast(incl, src) - gp.bcast(bc, src);
-            const int32_t obs = gp.bcast(bs, src);
+        const uint32_t incl = wave_incl_scan(bc);
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        for (uint32_t jc = 0; jc < tot; jc += 64) {
+            const uint32_t j = jc + l;
+            const int src = gw.find(incl, j < tot ? j : tot - 1);
+            const uint32_t ex = gw.bcast(incl, src) - gw.bcast(bc, src);
+            const int32_t obs = gw.bcast(bs, src);
+            const int g = gw.bcast(ge, src);
             bool win = false;
             int32_t o = 0;
             if (j < tot) {
                 o = obs + (int32_t)(j - ex);
-                win = seg_window(K, xi, yi, ri, ai, cai, iri, svri, E.md_p0[o], E.md_p1[o]);
+                const float4 w0 = q.w0[g], w1 = q.w1[g];
+                win = seg_window(K, w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, E.md_p0[o],
+                                 E.md_p1[o]);
             }
             const unsigned long long mk = __ballot(win);
             if (win) {
                 const uint32_t s = (tail + (uint32_t)__popcll(mk & below)) & (SEGQ - 1);
                 q.o[s] = o;
-                q.g[s] = (uint8_t)gp.g;
+                q.g[s] = (uint8_t)g;
             }
             tail += (uint32_t)__popcll(mk);
             if (tail - head >= 64) drain(64);
@@ -755,7 +776,7 @@ __device__ __forceinline__ void seg_body(const EvDev &E, const ModDev &M, const 
 }
 
 template <int G>
-__global__ __launch_bounds__(BLOCK, 5) void k_seg(EvDev E, ModDev M, Consts K)
+__global__ __launch_bounds__(BLOCK, 6) void k_seg(EvDev E, ModDev M, Consts K)
 {
     __shared__ SmSeg sm;
     seg_body<G>(E, M, K, sm);
