@@ -483,6 +483,10 @@ int lst_attach_arena(lst_ctx *c, void *dev_ptr, size_t bytes, const lst_caps *ca
     c->arena_bytes = bytes;
     c->caps = *caps;
     carve(c, c->arena, *caps, c->E, &c->zero_base, &c->zero_bytes);
+    // bin counts start at zero (each sort leaves them at zero again)
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, nullptr));
+    HIPCHK(c, hipDeviceSynchronize());
     if (!c->n_cu) HIPCHK(c, hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
     default_tuning(c);
     c->stage = 0;
@@ -570,7 +574,6 @@ int lst_run_sort(lst_ctx *c, void *stream)
     int rc = need_stage(c, 1, "lst_run_sort");
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, s));
     HIPCHK(c, launch_sort(c->E, c->M, c->tune.grid[ST_SORT], s));
     c->stage = 2;
     return LST_OK;
@@ -819,7 +822,6 @@ static int enqueue_chain(lst_ctx *c, hipStream_t s)
                                           t.blocks_per_cu * c->n_cu, t.lanes[ST_SEG], stop, s));
         return stop == PERS_FULL ? LST_OK : enqueue_after_persistent(c, stop, s);
     }
-    HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, s));
     HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], s));
     HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], t.lanes[ST_MD], s));
     HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], t.lanes[ST_SEG], s));
@@ -1290,7 +1292,6 @@ static int timed_chain(lst_ctx *c, hipStream_t s, hipEvent_t *ev, double *stage_
         HIPCHK(c, hipEventRecord(ev[ST_COUNT], s));
     } else {
         const Tuning &t = c->tune;
-        HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, s));
         HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], s));
         HIPCHK(c, hipEventRecord(ev[1], s));
         HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], t.lanes[ST_MD], s));

@@ -259,15 +259,21 @@ __device__ __forceinline__ int hit_key(const EvDev &E, int n_mod, int n_ev, int3
     return 2 * (ev * n_mod + m) + s;
 }
 
+// Bin counts per key.  The bins are zero on entry: the arena is cleared when
+// it is attached and every scatter takes each count back down to zero.  The
+// same launch clears the chain's counters and the scan's tile status, which
+// only later kernels use.
 __device__ __forceinline__ void hist_body(const EvDev &E, int n_mod)
 {
     const int n_ev = E.desc[D_NEV], n_hits = E.desc[D_NHITS];
-    for (int32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < n_hits;
-         h += gridDim.x * blockDim.x) {
+    const int t0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    for (int i = t0; i < GC_COUNT; i += stride) E.gc[i] = 0u;
+    const int n_tiles = (E.cap_keys + 1 + SCAN_TILE - 1) / SCAN_TILE;
+    for (int i = t0; i < n_tiles; i += stride) E.scan_st[i] = 0ull;
+    for (int32_t h = t0; h < n_hits; h += stride) {
         int ev;
         const int key = hit_key(E, n_mod, n_ev, h, ev);
-        if (key < 0) atomicOr(&E.gc[GC_ERROR], 1u);
-        else atomicAdd(&E.bcnt[key], 1u);
+        if (key >= 0) atomicAdd(&E.bcnt[key], 1u);
     }
 }
 
@@ -369,7 +375,10 @@ __device__ __forceinline__ void scatter_body(const EvDev &E, int n_mod)
          h += gridDim.x * blockDim.x) {
         int ev;
         const int key = hit_key(E, n_mod, n_ev, h, ev);
-        if (key < 0) continue;
+        if (key < 0) {
+            atomicOr(&E.gc[GC_ERROR], 1u);
+            continue;
+        }
         // positions are taken from the top of the bin down; bcnt ends at zero
         const uint32_t pos = E.boff[key] + atomicSub(&E.bcnt[key], 1u) - 1u;
         // one 16-byte store per hit (scattered 4-byte stores cost a line each)
