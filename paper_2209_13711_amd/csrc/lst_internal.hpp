@@ -123,7 +123,7 @@ constexpr int BLOCK = 256;           // 4 waves of 64
 constexpr int WAVES = BLOCK / 64;
 constexpr int STAGE = 256;           // accepted objects a wave stages in LDS
 constexpr int GRID_MAX = 2048;       // blocks of a grid-stride stage kernel
-constexpr int SCAN_TILE = 1024;      // keys per tile of the look-back scan
+constexpr int SCAN_TILE = 4096;      // keys per tile of the look-back scan
 
 // launchers (lst_kernels.hip)
 hipError_t launch_copy(void *dst, const void *src, size_t n_bytes, hipStream_t s);

@@ -314,12 +314,25 @@ __device__ __forceinline__ void scan_body(const EvDev &E)
         __syncthreads();
         const int tile = s_tile;
         if (tile >= nb) break;
-        const int base = tile * SCAN_TILE + threadIdx.x * 4;
-        uint32_t v[4], sum = 0;
-        for (int k = 0; k < 4; ++k) {
-            v[k] = (base + k < n) ? E.bcnt[base + k] : 0u;
-            sum += v[k];
+        constexpr int ITEMS = SCAN_TILE / BLOCK;   // consecutive keys per thread
+        const int base = tile * SCAN_TILE + threadIdx.x * ITEMS;
+        uint32_t v[ITEMS], sum = 0;
+        if (base + ITEMS <= n) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(E.bcnt + base);
+#pragma unroll
+            for (int k = 0; k < ITEMS / 4; ++k) {
+                const uint4 q = src[k];
+                v[4 * k] = q.x;
+                v[4 * k + 1] = q.y;
+                v[4 * k + 2] = q.z;
+                v[4 * k + 3] = q.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) v[k] = (base + k < n) ? E.bcnt[base + k] : 0u;
         }
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) sum += v[k];
         uint32_t tot;
         uint32_t ex = block_excl_scan(sum, tot);
         if (threadIdx.x == 0) {
@@ -355,7 +368,8 @@ __device__ __forceinline__ void scan_body(const EvDev &E)
         }
         __syncthreads();
         ex += s_prefix;
-        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
             const int idx = base + k;
             if (idx < n) E.boff[idx] = ex;
             if (idx == n) {   // the total, written by the thread covering index n
@@ -418,7 +432,18 @@ struct SmSeg {
     int32_t o[WAVES][STAGE];
     SegQ q[WAVES];
 };
-struct SmT3 { int32_t b[WAVES][STAGE]; int32_t c[WAVES][STAGE]; float k[WAVES][STAGE]; };
+// triplet stage: per wave, the inner MDs of the round (one per lane) and the
+// accepted triplets staged until their output offset is known
+constexpr int T3_PMAX = 32;           // most inner MDs a wave takes per round
+struct SmT3 {
+    int32_t b[WAVES][STAGE], c[WAVES][STAGE];
+    float k[WAVES][STAGE];
+    float4 ap[WAVES][T3_PMAX];        // inner MD anchor (x, y, z, r)
+    float asv[WAVES][T3_PMAX];        // its sv
+    int32_t abar[WAVES][T3_PMAX], aidx[WAVES][T3_PMAX];
+    uint32_t cnt[WAVES][T3_PMAX];
+    uint8_t g[WAVES][STAGE];
+};
 struct SmT5 {
     int32_t b[WAVES][STAGE], c[WAVES][STAGE], d[WAVES][STAGE], e[WAVES][STAGE];
     float s[WAVES][STAGE];
@@ -800,99 +825,127 @@ hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, int grid
 
 // ---------------------------------------------------------------- triplets
 // Candidates of inner MD a: every segment (a->b) followed by every segment
-// (b->c); one group of G lanes per inner MD.  sink(ok, b, c, k, pos)
-template <int G, class F>
-__device__ __forceinline__ uint32_t enum_t3(const EvDev &E, const Consts &K, int32_t a, bool act,
+// (b->c).  A wave takes P inner MDs per round, lane l < P holding MD l; their
+// first segments, then the candidates, are walked as one list 64 at a time,
+// so no lane waits for the MD with most candidates.  The list is in MD order,
+// so each MD's accepted triplets are consecutive in the wave's output, in
+// enumeration order.  sink(ok, g, b, c, k, pos): g = lane of the inner MD,
+// pos = rank among the wave's accepted triplets.
+template <class F>
+__device__ __forceinline__ uint32_t enum_t3(const EvDev &E, const Consts &K, const SmT3 &sm,
+                                            int w, int32_t ns1, int32_t s10, uint32_t incl1,
                                             F &&sink)
 {
-    const Grp<G> gp;
-    int32_t ns1 = 0, s10 = 0;
-    if (act) {
-        ns1 = E.seg_cnt[a];
-        s10 = E.seg_start[a];
-    }
-    MdV A = {};
-    if (ns1 > 0) A = load_md(E, a);
-    uint32_t cnt = 0;
-    const int32_t ns_max = (int32_t)wave_max((uint32_t)(ns1 > 0 ? ns1 : 0));
-    for (int32_t c1 = 0; c1 < ns_max; c1 += G) {
-        const int32_t k = c1 + gp.lane;
+    const Grp<64> gw;
+    const uint32_t l = (uint32_t)lane_id();
+    const unsigned long long below = lanes_below();
+    const uint32_t n1 = (uint32_t)__builtin_amdgcn_readlane((int)incl1, 63);
+    uint32_t acc = 0;
+    for (uint32_t fc = 0; fc < n1; fc += 64) {
+        const uint32_t f = fc + l;
+        const int g = gw.find(incl1, f < n1 ? f : n1 - 1);
+        const uint32_t ex1 = gw.bcast(incl1, g) - gw.bcast((uint32_t)ns1, g);
+        const int32_t s10g = gw.bcast(s10, g);
         int32_t b = 0, bs = 0;
         uint32_t nb = 0;
-        if (k < ns1) {
-            b = E.seg_out[s10 + k];
+        if (f < n1) {
+            b = E.seg_out[s10g + (int32_t)(f - ex1)];
             bs = E.seg_start[b];
             nb = (uint32_t)E.seg_cnt[b];
         }
-        const uint32_t incl = gp.incl_scan(nb);
-        const uint32_t tot = gp.bcast(incl, G - 1);
-        const uint32_t tot_max = wave_max(tot);
-        for (uint32_t jc = 0; jc < tot_max; jc += G) {
-            const uint32_t j = jc + gp.lane;
-            const int src = gp.find(incl, j < tot ? j : (tot ? tot - 1 : 0));
-            const uint32_t ex = gp.bcast(incl, src) - gp.bcast(nb, src);
-            const int32_t bb = gp.bcast(b, src);
-            const int32_t bbs = gp.bcast(bs, src);
+        const uint32_t incl2 = wave_incl_scan(nb);
+        const uint32_t n2 = (uint32_t)__builtin_amdgcn_readlane((int)incl2, 63);
+        for (uint32_t jc = 0; jc < n2; jc += 64) {
+            const uint32_t j = jc + l;
+            const int src = gw.find(incl2, j < n2 ? j : n2 - 1);
+            const uint32_t ex2 = gw.bcast(incl2, src) - gw.bcast(nb, src);
+            const int32_t bb = gw.bcast(b, src), bbs = gw.bcast(bs, src);
+            const int gg = gw.bcast(g, src);
             bool ok = false;
             int32_t c = 0;
             float kk = 0.0f;
-            if (j < tot) {
-                c = E.seg_out[bbs + (int32_t)(j - ex)];
+            if (j < n2) {
+                c = E.seg_out[bbs + (int32_t)(j - ex2)];
+                MdV A = {};
+                const float4 ap = sm.ap[w][gg];
+                A.x = ap.x; A.y = ap.y; A.z = ap.z; A.r = ap.w;
+                A.sv = sm.asv[w][gg];
+                A.barrel = sm.abar[w][gg];
                 ok = t3_accept(K, A, load_md(E, bb), load_md(E, c), kk);
             }
-            uint32_t t;
-            const uint32_t r = gp.rank(ok, t);
-            sink(ok, bb, c, kk, cnt + r);
-            cnt += t;
+            const unsigned long long m = __ballot(ok);
+            sink(ok, gg, bb, c, kk, acc + (uint32_t)__popcll(m & below));
+            acc += (uint32_t)__popcll(m);
         }
     }
-    return cnt;
+    return acc;
 }
 
+// G selects P = 256 / G inner MDs per wave and round (G = 8: 32 MDs)
 template <int G>
 __device__ __forceinline__ void t3_body(const EvDev &E, const Consts &K, SmT3 &sm)
 {
     if (upstream_overflow(E)) return;
-    constexpr int P = Grp<G>::P, CAP = STAGE / P;
-    const Grp<G> gp;
+    constexpr int P = 256 / G;
+    static_assert(P <= T3_PMAX, "inner MDs per wave");
     const int w = wave_id();
+    const uint32_t l = (uint32_t)lane_id();
     const XBlock xb = xcd_block();
     const XRegions R = load_regions_x(E, OT_MD, xb.x);
     for (uint32_t base = xb.rank * WAVES * P; base < R.total; base += xb.count * WAVES * P) {
-        const uint32_t v = base + w * P + gp.g;
-        const bool act = v < R.total;
+        const uint32_t v = base + w * P + l;
+        const bool act = l < (uint32_t)P && v < R.total;
         const int32_t a = region_index_x(R, act ? v : 0);
-        const uint32_t cnt = enum_t3<G>(E, K, a, act, [&](bool ok, int32_t b, int32_t c, float k,
-                                                          uint32_t pos) {
-            if (ok && pos < CAP) {
-                sm.b[w][gp.g * CAP + pos] = b;
-                sm.c[w][gp.g * CAP + pos] = c;
-                sm.k[w][gp.g * CAP + pos] = k;
+        int32_t ns1 = 0, s10 = 0;
+        if (act) {
+            ns1 = E.seg_cnt[a];
+            s10 = E.seg_start[a];
+            if (ns1 < 0) ns1 = 0;
+            if (ns1 > 0) {
+                sm.ap[w][l] = E.md_p0[a];
+                sm.asv[w][l] = E.md_p2[a].w;
+                sm.abar[w][l] = E.md_bar[a] & 1;
+            }
+            sm.aidx[w][l] = a;
+        }
+        if (l < (uint32_t)T3_PMAX) sm.cnt[w][l] = 0u;
+        const uint32_t incl1 = wave_incl_scan((uint32_t)ns1);
+        wave_lds_sync();
+        const uint32_t tot = enum_t3(E, K, sm, w, ns1, s10, incl1,
+                                     [&](bool ok, int g, int32_t b, int32_t c, float k, uint32_t pos) {
+            if (ok) {
+                atomicAdd(&sm.cnt[w][g], 1u);
+                if (pos < STAGE) {
+                    sm.b[w][pos] = b;
+                    sm.c[w][pos] = c;
+                    sm.k[w][pos] = k;
+                    sm.g[w][pos] = (uint8_t)g;
+                }
             }
         });
-        uint32_t wtot;
-        const uint32_t gex = gp.wave_prefix(cnt, wtot);
+        wave_lds_sync();
+        const uint32_t cl = l < (uint32_t)T3_PMAX ? sm.cnt[w][l] : 0u;
+        const uint32_t cex = wave_incl_scan(cl) - cl;
         bool ovf;
-        const uint32_t off = block_reserve(wtot, E, OT_T3, ovf) + gex;
-        if (act && gp.lane == 0) {
-            E.t3_start[a] = (int32_t)off;
-            E.t3_cnt[a] = ovf ? 0 : (int32_t)cnt;
+        const uint32_t off = block_reserve(tot, E, OT_T3, ovf);
+        if (act) {
+            E.t3_start[a] = (int32_t)(off + cex);
+            E.t3_cnt[a] = ovf ? 0 : (int32_t)cl;
         }
         if (ovf) continue;
-        if (act && cnt <= CAP) {
-            for (uint32_t k = gp.lane; k < cnt; k += G) {
-                E.t3_a[off + k] = a;
-                E.t3_b[off + k] = sm.b[w][gp.g * CAP + k];
-                E.t3_c[off + k] = sm.c[w][gp.g * CAP + k];
-                E.t3_k[off + k] = sm.k[w][gp.g * CAP + k];
-                E.t3_veto[off + k] = 0;
-            }
+        for (uint32_t q = l; q < tot && q < (uint32_t)STAGE; q += 64) {
+            E.t3_a[off + q] = sm.aidx[w][sm.g[w][q]];
+            E.t3_b[off + q] = sm.b[w][q];
+            E.t3_c[off + q] = sm.c[w][q];
+            E.t3_k[off + q] = sm.k[w][q];
+            E.t3_veto[off + q] = 0;
         }
-        if (wave_max(cnt) > CAP) {
-            enum_t3<G>(E, K, a, act && cnt > CAP, [&](bool ok, int32_t b, int32_t c, float k,
-                                                      uint32_t pos) {
-                if (ok) {
-                    E.t3_a[off + pos] = a;
+        if (tot > (uint32_t)STAGE) {
+            // beyond the staging: enumerate again and write directly
+            enum_t3(E, K, sm, w, ns1, s10, incl1,
+                    [&](bool ok, int g, int32_t b, int32_t c, float k, uint32_t pos) {
+                if (ok && pos >= STAGE) {
+                    E.t3_a[off + pos] = sm.aidx[w][g];
                     E.t3_b[off + pos] = b;
                     E.t3_c[off + pos] = c;
                     E.t3_k[off + pos] = k;
@@ -900,6 +953,7 @@ __device__ __forceinline__ void t3_body(const EvDev &E, const Consts &K, SmT3 &s
                 }
             });
         }
+        wave_lds_sync();
     }
 }
 
