@@ -444,9 +444,15 @@ struct SmT3 {
     uint32_t cnt[WAVES][T3_PMAX];
     uint8_t g[WAVES][STAGE];
 };
+// quintuplet stage: the same per-wave table of inner MDs and staging
+constexpr int T5_PMAX = 32;
 struct SmT5 {
     int32_t b[WAVES][STAGE], c[WAVES][STAGE], d[WAVES][STAGE], e[WAVES][STAGE];
     float s[WAVES][STAGE];
+    float4 ap[WAVES][T5_PMAX];
+    float asv[WAVES][T5_PMAX];
+    int32_t abar[WAVES][T5_PMAX], aidx[WAVES][T5_PMAX];
+    uint8_t g[WAVES][STAGE];
 };
 struct SmChain {
     union {
@@ -974,61 +980,67 @@ hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, int grid,
 
 // ---------------------------------------------------------------- quintuplets
 // Candidates of inner MD a: every triplet (a,b,c) followed by every triplet
-// (c,d,e); one group of G lanes per inner MD.  sink(ok, b, c, d, e, score, pos)
-template <int G, class F>
-__device__ __forceinline__ uint32_t enum_t5(const EvDev &E, const Consts &K, int32_t a, bool act,
+// (c,d,e).  As for triplets, a wave takes P inner MDs per round (lane l < P
+// holds MD l) and walks their first triplets, then the candidates, as one
+// list 64 at a time.  sink(ok, g, b, c, d, e, score, pos): g = lane of the
+// inner MD, pos = rank among the wave's accepted quintuplets.
+template <class F>
+__device__ __forceinline__ uint32_t enum_t5(const EvDev &E, const Consts &K, const SmT5 &sm,
+                                            int w, int32_t nt1, int32_t t10, uint32_t incl1,
                                             F &&sink)
 {
-    const Grp<G> gp;
-    int32_t nt1 = 0, t10 = 0;
-    if (act) {
-        nt1 = E.t3_cnt[a];
-        t10 = E.t3_start[a];
-    }
-    MdV A = {};
-    if (nt1 > 0) A = load_md(E, a);
-    uint32_t cnt = 0;
-    const int32_t nt_max = (int32_t)wave_max((uint32_t)(nt1 > 0 ? nt1 : 0));
-    for (int32_t c1 = 0; c1 < nt_max; c1 += G) {
-        const int32_t k = c1 + gp.lane;
+    const Grp<64> gw;
+    const uint32_t l = (uint32_t)lane_id();
+    const unsigned long long below = lanes_below();
+    const uint32_t n1 = (uint32_t)__builtin_amdgcn_readlane((int)incl1, 63);
+    uint32_t acc = 0;
+    for (uint32_t fc = 0; fc < n1; fc += 64) {
+        const uint32_t f = fc + l;
+        const int g = gw.find(incl1, f < n1 ? f : n1 - 1);
+        const uint32_t ex1 = gw.bcast(incl1, g) - gw.bcast((uint32_t)nt1, g);
+        const int32_t t10g = gw.bcast(t10, g);
         int32_t t1 = 0, cs = 0;
         uint32_t nc = 0;
-        if (k < nt1) {
-            t1 = t10 + k;
+        if (f < n1) {
+            t1 = t10g + (int32_t)(f - ex1);
             const int32_t c = E.t3_c[t1];
             cs = E.t3_start[c];
             nc = (uint32_t)E.t3_cnt[c];
         }
-        const uint32_t incl = gp.incl_scan(nc);
-        const uint32_t tot = gp.bcast(incl, G - 1);
-        const uint32_t tot_max = wave_max(tot);
-        for (uint32_t jc = 0; jc < tot_max; jc += G) {
-            const uint32_t j = jc + gp.lane;
-            const int src = gp.find(incl, j < tot ? j : (tot ? tot - 1 : 0));
-            const uint32_t ex = gp.bcast(incl, src) - gp.bcast(nc, src);
-            const int32_t tt1 = gp.bcast(t1, src);
-            const int32_t tcs = gp.bcast(cs, src);
+        const uint32_t incl2 = wave_incl_scan(nc);
+        const uint32_t n2 = (uint32_t)__builtin_amdgcn_readlane((int)incl2, 63);
+        for (uint32_t jc = 0; jc < n2; jc += 64) {
+            const uint32_t j = jc + l;
+            const int src = gw.find(incl2, j < n2 ? j : n2 - 1);
+            const uint32_t ex2 = gw.bcast(incl2, src) - gw.bcast(nc, src);
+            const int32_t tt1 = gw.bcast(t1, src), tcs = gw.bcast(cs, src);
+            const int gg = gw.bcast(g, src);
             bool ok = false;
             int32_t b = 0, c = 0, d = 0, e = 0;
             float score = 0.0f;
-            if (j < tot) {
-                const int32_t t2 = tcs + (int32_t)(j - ex);
+            if (j < n2) {
+                const int32_t t2 = tcs + (int32_t)(j - ex2);
                 b = E.t3_b[tt1];
                 c = E.t3_c[tt1];
                 d = E.t3_b[t2];
                 e = E.t3_c[t2];
                 // a triplet vetoed by the learned scorer joins no quintuplet
-                if (!(E.t3_veto[tt1] | E.t3_veto[t2]))
+                if (!(E.t3_veto[tt1] | E.t3_veto[t2])) {
+                    MdV A = {};
+                    const float4 ap = sm.ap[w][gg];
+                    A.x = ap.x; A.y = ap.y; A.z = ap.z; A.r = ap.w;
+                    A.sv = sm.asv[w][gg];
+                    A.barrel = sm.abar[w][gg];
                     ok = t5_accept(K, A, load_md(E, b), load_md(E, c), load_md(E, d), load_md(E, e),
                                    E.t3_k[tt1], E.t3_k[t2], score);
+                }
             }
-            uint32_t t;
-            const uint32_t r = gp.rank(ok, t);
-            sink(ok, b, c, d, e, score, cnt + r);
-            cnt += t;
+            const unsigned long long m = __ballot(ok);
+            sink(ok, gg, b, c, d, e, score, acc + (uint32_t)__popcll(m & below));
+            acc += (uint32_t)__popcll(m);
         }
     }
-    return cnt;
+    return acc;
 }
 
 __device__ __forceinline__ void write_t5(const EvDev &E, uint32_t at, int32_t a, int32_t b,
@@ -1044,46 +1056,63 @@ __device__ __forceinline__ void write_t5(const EvDev &E, uint32_t at, int32_t a,
     E.t5_veto[at] = 0;
 }
 
+// G selects P = 256 / G inner MDs per wave and round
 template <int G>
 __device__ __forceinline__ void t5_body(const EvDev &E, const Consts &K, SmT5 &sm)
 {
     if (upstream_overflow(E)) return;
-    constexpr int P = Grp<G>::P, CAP = STAGE / P;
-    const Grp<G> gp;
+    constexpr int P = 256 / G;
+    static_assert(P <= T5_PMAX, "inner MDs per wave");
     const int w = wave_id();
+    const uint32_t l = (uint32_t)lane_id();
     const XBlock xb = xcd_block();
     const XRegions R = load_regions_x(E, OT_MD, xb.x);
     for (uint32_t base = xb.rank * WAVES * P; base < R.total; base += xb.count * WAVES * P) {
-        const uint32_t v = base + w * P + gp.g;
-        const bool act = v < R.total;
+        const uint32_t v = base + w * P + l;
+        const bool act = l < (uint32_t)P && v < R.total;
         const int32_t a = region_index_x(R, act ? v : 0);
-        const int q0 = gp.g * CAP;
-        const uint32_t cnt = enum_t5<G>(E, K, a, act, [&](bool ok, int32_t b, int32_t c, int32_t d,
-                                                          int32_t e, float sc, uint32_t pos) {
-            if (ok && pos < CAP) {
-                sm.b[w][q0 + pos] = b;
-                sm.c[w][q0 + pos] = c;
-                sm.d[w][q0 + pos] = d;
-                sm.e[w][q0 + pos] = e;
-                sm.s[w][q0 + pos] = sc;
+        int32_t nt1 = 0, t10 = 0;
+        if (act) {
+            nt1 = E.t3_cnt[a];
+            t10 = E.t3_start[a];
+            if (nt1 < 0) nt1 = 0;
+            if (nt1 > 0) {
+                sm.ap[w][l] = E.md_p0[a];
+                sm.asv[w][l] = E.md_p2[a].w;
+                sm.abar[w][l] = E.md_bar[a] & 1;
+                sm.aidx[w][l] = a;
+            }
+        }
+        const uint32_t incl1 = wave_incl_scan((uint32_t)nt1);
+        wave_lds_sync();
+        const uint32_t tot = enum_t5(E, K, sm, w, nt1, t10, incl1,
+                                     [&](bool ok, int g, int32_t b, int32_t c, int32_t d,
+                                         int32_t e, float sc, uint32_t pos) {
+            if (ok && pos < STAGE) {
+                sm.b[w][pos] = b;
+                sm.c[w][pos] = c;
+                sm.d[w][pos] = d;
+                sm.e[w][pos] = e;
+                sm.s[w][pos] = sc;
+                sm.g[w][pos] = (uint8_t)g;
             }
         });
-        uint32_t wtot;
-        const uint32_t gex = gp.wave_prefix(cnt, wtot);
+        wave_lds_sync();
         bool ovf;
-        const uint32_t off = block_reserve(wtot, E, OT_T5, ovf) + gex;
+        const uint32_t off = block_reserve(tot, E, OT_T5, ovf);
         if (ovf) continue;
-        if (act && cnt <= CAP) {
-            for (uint32_t k = gp.lane; k < cnt; k += G)
-                write_t5(E, off + k, a, sm.b[w][q0 + k], sm.c[w][q0 + k], sm.d[w][q0 + k],
-                         sm.e[w][q0 + k], sm.s[w][q0 + k]);
-        }
-        if (wave_max(cnt) > CAP) {
-            enum_t5<G>(E, K, a, act && cnt > CAP, [&](bool ok, int32_t b, int32_t c, int32_t d,
-                                                      int32_t e, float sc, uint32_t pos) {
-                if (ok) write_t5(E, off + pos, a, b, c, d, e, sc);
+        for (uint32_t q = l; q < tot && q < (uint32_t)STAGE; q += 64)
+            write_t5(E, off + q, sm.aidx[w][sm.g[w][q]], sm.b[w][q], sm.c[w][q], sm.d[w][q],
+                     sm.e[w][q], sm.s[w][q]);
+        if (tot > (uint32_t)STAGE) {
+            // beyond the staging: enumerate again and write directly
+            enum_t5(E, K, sm, w, nt1, t10, incl1,
+                    [&](bool ok, int g, int32_t b, int32_t c, int32_t d, int32_t e, float sc,
+                        uint32_t pos) {
+                if (ok && pos >= STAGE) write_t5(E, off + pos, sm.aidx[w][g], b, c, d, e, sc);
             });
         }
+        wave_lds_sync();
     }
 }
 
