@@ -47,6 +47,15 @@ struct MdOut {
     float r, a, ca, bend, sv;
 };
 
+// radius of the lower hit and the sine / cosine of the threshold track's
+// angle to the radius there
+__device__ __forceinline__ void md_anchor(const Consts &K, float xL, float yL, MdOut &o)
+{
+    o.r = sqrtf((xL * xL) + (yL * yL));
+    o.a = mn(o.r * K.kh, 0.999f);
+    o.ca = sqrtf(1.0f - (o.a * o.a));
+}
+
 // Mini-doublet (stub) window for lower hit L and upper hit U of a module.
 __device__ __forceinline__ bool md_accept(const Consts &K, const ModF &m, float xL, float yL,
                                           float zL, float xU, float yU, float zU, MdOut &o)
@@ -57,9 +66,8 @@ __device__ __forceinline__ bool md_accept(const Consts &K, const ModF &m, float 
     float vU = (((xU - m.cx) * m.vx) + ((yU - m.cy) * m.vy)) + ((zU - m.cz) * m.vz);
     float du = uU - uL;
     float dv = vU - vL;
-    float rL = sqrtf((xL * xL) + (yL * yL));
-    float a = mn(rL * K.kh, 0.999f);
-    float ca = sqrtf(1.0f - (a * a));
+    md_anchor(K, xL, yL, o);
+    const float rL = o.r, a = o.a, ca = o.ca;
     float g = m.g;
     float hi, lo, zc, hz, sv;
     if (m.barrel) {
@@ -89,9 +97,6 @@ __device__ __forceinline__ bool md_accept(const Consts &K, const ModF &m, float 
     }
     float c0 = 0.5f * (hi + lo);
     float h0 = (0.5f * (hi - lo)) + K.tolu;
-    o.r = rL;
-    o.a = a;
-    o.ca = ca;
     o.bend = (du - c0) / h0;
     o.sv = sv;
     return (fabsf(du - c0) <= K.w * h0) && (fabsf(dv - zc) <= K.w * hz);

@@ -427,7 +427,12 @@ struct SegQ {
     uint8_t g[SEGQ];
 };
 
-struct SmMD { uint32_t lo[WAVES][STAGE]; uint32_t up[WAVES][STAGE]; };
+// mini-doublet stage: accepted pairs and their window outputs staged until
+// the output offset is known
+struct SmMD {
+    uint32_t lo[WAVES][STAGE], up[WAVES][STAGE];
+    float bend[WAVES][STAGE], sv[WAVES][STAGE];
+};
 struct SmSeg {
     int32_t o[WAVES][STAGE];
     SegQ q[WAVES];
@@ -497,7 +502,8 @@ __device__ __forceinline__ void write_md(const EvDev &E, const Consts &K, uint32
     E.md_bar[i] = (uint8_t)(mod.barrel | (mod.is2s << 1));
 }
 
-// every lower x upper hit pair of one module slot (one group); sink(ok, hl, hu, pos)
+// every lower x upper hit pair of one module slot (one group);
+// sink(ok, hl, hu, o, pos) with o the window's outputs for the pair
 template <int G, class F>
 __device__ __forceinline__ uint32_t enum_md(const EvDev &E, const Consts &K, const ModF &mod,
                                             uint32_t lo0, uint32_t up0, uint32_t nup,
@@ -510,17 +516,17 @@ __device__ __forceinline__ uint32_t enum_md(const EvDev &E, const Consts &K, con
         const uint32_t p = b + gp.lane;
         bool ok = false;
         uint32_t hl = 0, hu = 0;
+        MdOut o = {};
         if (p < np) {
             const uint32_t il = p / nup, iu = p - il * nup;
             hl = lo0 + il;
             hu = up0 + iu;
-            MdOut o;
             const float4 L = E.hsort[hl], U = E.hsort[hu];
             ok = md_accept(K, mod, L.x, L.y, L.z, U.x, U.y, U.z, o);
         }
         uint32_t t;
         const uint32_t r = gp.rank(ok, t);
-        sink(ok, hl, hu, cnt + r);
+        sink(ok, hl, hu, o, cnt + r);
         cnt += t;
     }
     return cnt;
@@ -561,10 +567,14 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
         ModF mod = {};
         if (np) mod = load_mod(M, slot % M.n_mod);
         const uint32_t cnt = enum_md<G>(E, K, mod, lo0, up0, nup, np,
-                                        [&](bool ok, uint32_t hl, uint32_t hu, uint32_t pos) {
+                                        [&](bool ok, uint32_t hl, uint32_t hu, const MdOut &o,
+                                            uint32_t pos) {
                                             if (ok && pos < CAP) {
-                                                sm.lo[w][gp.g * CAP + pos] = hl;
-                                                sm.up[w][gp.g * CAP + pos] = hu;
+                                                const int q = gp.g * CAP + pos;
+                                                sm.lo[w][q] = hl;
+                                                sm.up[w][q] = hu;
+                                                sm.bend[w][q] = o.bend;
+                                                sm.sv[w][q] = o.sv;
                                             }
                                         });
         uint32_t wtot;
@@ -578,24 +588,22 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
         if (ovf) continue;
         if (act && cnt <= CAP) {
             for (uint32_t k = gp.lane; k < cnt; k += G) {
-                const uint32_t hl = sm.lo[w][gp.g * CAP + k], hu = sm.up[w][gp.g * CAP + k];
+                const int q = gp.g * CAP + k;
+                const uint32_t hl = sm.lo[w][q];
+                const float4 L = E.hsort[hl];
                 MdOut o;
-                const float4 L = E.hsort[hl], U = E.hsort[hu];
-                md_accept(K, mod, L.x, L.y, L.z, U.x, U.y, U.z, o);
-                write_md(E, K, off + k, slot, hl, hu, o, mod);
+                md_anchor(K, L.x, L.y, o);
+                o.bend = sm.bend[w][q];
+                o.sv = sm.sv[w][q];
+                write_md(E, K, off + k, slot, hl, sm.up[w][q], o, mod);
             }
         }
         if (wave_max(cnt) > CAP) {
             // groups beyond their staging share enumerate again and write directly
             const bool redo = act && cnt > CAP;
             enum_md<G>(E, K, mod, lo0, up0, nup, redo ? np : 0u,
-                       [&](bool ok, uint32_t hl, uint32_t hu, uint32_t pos) {
-                           if (ok) {
-                               MdOut o;
-                               const float4 L = E.hsort[hl], U = E.hsort[hu];
-                               md_accept(K, mod, L.x, L.y, L.z, U.x, U.y, U.z, o);
-                               write_md(E, K, off + pos, slot, hl, hu, o, mod);
-                           }
+                       [&](bool ok, uint32_t hl, uint32_t hu, const MdOut &o, uint32_t pos) {
+                           if (ok) write_md(E, K, off + pos, slot, hl, hu, o, mod);
                        });
         }
     }
