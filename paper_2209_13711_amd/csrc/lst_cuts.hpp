@@ -139,10 +139,11 @@ __device__ __forceinline__ float tri_curv(const MdV &A, const MdV &B, const MdV 
 
 // Segment I -> O: azimuthal window (S2), pointing along the prompt circle
 // (S1), relative angle of each barrel MD direction to the chord (S3).  The
-// decision is the AND of the three cuts, so it is split in two calls that
-// can run at different times: seg_window (S2, about a third of the pairs
-// pass it) and seg_rest (S1 and S3).  Both compute their shared terms by
-// the same FP32 operations, so the pair gives the single test's result.
+// decision is the AND of the three cuts, so it is split in three calls that
+// can run at different times, cheapest and most selective first:
+// seg_window (S2, about a third of the pairs pass it), seg_angle (S3) and
+// seg_point (S1).  They compute their shared terms by the same FP32
+// operations, so together they give the single test's result.
 // The azimuth window S2 decides exactly as `-(dot / rr) <= 0 && |crs / rr| <=
 // B` would, but divides only when the division-free tests cannot decide:
 //  * dot >= 0 implies -(dot / rr) <= 0 (rr > 0);
@@ -177,21 +178,46 @@ __device__ __forceinline__ bool seg_window(const Consts &K, float xi, float yi, 
     return c_ok && s_ok;
 }
 
-// the inner MD as seg_rest reads it: anchor (x, y, z, r), direction
-// (dx, dy, |d|, S3 bound), barrel flag
+// the inner MD as seg_angle and seg_point read it: anchor (x, y, z, r),
+// direction (dx, dy, |d|, S3 bound), barrel flag
 struct SegIn {
     float4 p, d;
     int barrel;
 };
 
-__device__ __forceinline__ bool seg_rest(const Consts &K, const SegIn &I, const EvDev &E, int32_t o)
+// S3: relative angle of each barrel MD's direction to the chord (about a
+// fifth of the window survivors pass)
+__device__ __forceinline__ bool seg_angle(const SegIn &I, const EvDev &E, int32_t o)
 {
-    const float4 p0 = E.md_p0[o], p2 = E.md_p2[o];
+    const int ob = E.md_bar[o] & 1;
+    if (!I.barrel && !ob) return true;
+    const float4 p0 = E.md_p0[o];
+    const float xi = I.p.x, yi = I.p.y, ri = I.p.w;
+    float rr = ri * p0.w;
+    float crs = (xi * p0.y) - (yi * p0.x);
+    float S = crs / rr;
+    float qx = p0.x - xi, qy = p0.y - yi;
+    float ql = sqrtf((qx * qx) + (qy * qy));
+    if (I.barrel) {
+        float sa = ((I.d.x * qy) - (I.d.y * qx)) / (I.d.z * ql);
+        if (!(fabsf(sa - S) <= I.d.w)) return false;
+    }
+    if (ob) {
+        const float4 p2 = E.md_p2[o];
+        float sb = ((qx * p2.y) - (qy * p2.x)) / (ql * p2.z);
+        if (!(fabsf(sb - S) <= E.md_atol[o])) return false;
+    }
+    return true;
+}
+
+// S1: pointing of the r-z line along the prompt circle through both anchors
+__device__ __forceinline__ bool seg_point(const Consts &K, const SegIn &I, const EvDev &E, int32_t o)
+{
+    const float4 p0 = E.md_p0[o];
     const int ob = E.md_bar[o] & 1;
     const float xi = I.p.x, yi = I.p.y, zi = I.p.z, ri = I.p.w;
     float rr = ri * p0.w;
     float crs = (xi * p0.y) - (yi * p0.x);
-    float S = crs / rr;
     float qx = p0.x - xi, qy = p0.y - yi;
     float ql = sqrtf((qx * qx) + (qy * qy));
     float kO = (2.0f * crs) / (rr * ql);
@@ -203,16 +229,7 @@ __device__ __forceinline__ bool seg_rest(const Consts &K, const SegIn &I, const 
     float szi = I.barrel ? K.sigv : (fabsf(sl) * K.sigv);
     float szo = ob ? K.sigv : (fabsf(sl) * K.sigv);
     float tolz = K.nsig * (((so * szi) + (si * szo)) / ds);
-    if (!(fabsf(z0) <= K.w * (K.z0max + tolz))) return false;
-    if (I.barrel) {
-        float sa = ((I.d.x * qy) - (I.d.y * qx)) / (I.d.z * ql);
-        if (!(fabsf(sa - S) <= I.d.w)) return false;
-    }
-    if (ob) {
-        float sb = ((qx * p2.y) - (qy * p2.x)) / (ql * p2.z);
-        if (!(fabsf(sb - S) <= E.md_atol[o])) return false;
-    }
-    return true;
+    return fabsf(z0) <= K.w * (K.z0max + tolz);
 }
 
 // S3 bound of an MD with direction length dn (the MD stage stores it)

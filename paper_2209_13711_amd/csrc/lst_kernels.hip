@@ -29,6 +29,15 @@ __device__ __forceinline__ unsigned long long lanes_below()
     return (1ull << lane_id()) - 1ull;
 }
 
+__device__ __forceinline__ void wave_lds_sync()
+{
+    // orders the wave's LDS writes before its later LDS reads by other lanes
+    // (a wave's LDS operations complete in issue order)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // inclusive scan over the 64 lanes of a wave
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
@@ -423,8 +432,8 @@ struct SegQ {
     float4 w0[MAXP], w1[MAXP];        // its window terms (x, y, r, a), (ca, 1/r, |sv|/r, -)
     int2 eb[MAXP];                    // its module's first map edge, its event's first slot
     int32_t ib[MAXP], idx[MAXP], off[MAXP];
-    int32_t o[SEGQ];
-    uint8_t g[SEGQ];
+    int32_t o[SEGQ], o2[SEGQ];        // window survivors; angle survivors
+    uint8_t g[SEGQ], g2[SEGQ];
 };
 
 // mini-doublet stage: accepted pairs and their window outputs staged until
@@ -636,23 +645,16 @@ hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, int grid,
 }
 
 // ---------------------------------------------------------------- segments
-// Outer candidates of inner MD i: the MDs of every map edge of its module,
-// in edge order; one group of G lanes per inner MD.  The pairs inside the
-// azimuth window (about a third of them) go to a ring of the wave in LDS,
-// and the rest of the test runs on full waves of 64 queued pairs, so the
-// costly part of the test runs once per window survivor rather than once
-// per pair.  Accepted pairs get, per inner MD, consecutive positions in
-// enumeration order.  sink(g, ok, o, pos): g is the group of the pair's
-// inner MD.
-__device__ __forceinline__ void wave_lds_sync()
-{
-    // orders the wave's LDS writes before its later LDS reads by other lanes
-    // (a wave's LDS operations complete in issue order)
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
+// Outer candidates of inner MD i: the MDs of every map edge of its module,
+// in edge order; the candidates of the wave's inner MDs are walked as one
+// list.  The pairs inside the azimuth window (about a third of them) go to a
+// ring of the wave in LDS; 64 queued pairs at a time take the angle cut,
+// whose survivors queue again for the pointing cut, so each costly part of
+// the test runs on full waves of the pairs that reached it.  The rings keep
+// the enumeration order, so accepted pairs get, per inner MD, consecutive
+// positions in that order.  sink(g, ok, o, pos): g is the group of the
+// pair's inner MD.
 template <int G, class F>
 __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, const Consts &K,
                                              int32_t i, bool act, SegQ &q, F &&sink)
@@ -692,7 +694,36 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
     uint32_t head = 0, tail = 0;                  // ring positions (wave-uniform)
     const unsigned long long below = lanes_below();
     wave_lds_sync();
-    // the rest of the test on the n (<= 64) oldest queued pairs
+    uint32_t head2 = 0, tail2 = 0;
+    // the pointing cut on the n (<= 64) oldest angle survivors: final decision
+    auto drain2 = [&](uint32_t n) {
+        wave_lds_sync();
+        bool ok = false;
+        int32_t o = 0;
+        int g = 0;
+        if (l < n) {
+            const uint32_t s = (head2 + l) & (SEGQ - 1);
+            o = q.o2[s];
+            g = q.g2[s];
+            SegIn I;
+            I.p = q.ip[g];
+            I.d = q.id[g];
+            I.barrel = q.ib[g];
+            ok = seg_point(K, I, E, o);
+        }
+        head2 += n;
+        uint32_t pos = 0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const unsigned long long mk = __ballot(ok && g == p);
+            if (g == p) pos = cnt[p] + (uint32_t)__popcll(mk & below);
+            cnt[p] += (uint32_t)__popcll(mk);
+        }
+        sink(g, ok, o, pos);
+        wave_lds_sync();                          // slots are rewritten by later pairs
+    };
+    // the angle cut on the n (<= 64) oldest window survivors; its survivors
+    // queue for the pointing cut in the same order
     auto drain = [&](uint32_t n) {
         wave_lds_sync();
         bool ok = false;
@@ -706,18 +737,18 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
             I.p = q.ip[g];
             I.d = q.id[g];
             I.barrel = q.ib[g];
-            ok = seg_rest(K, I, E, o);
+            ok = seg_angle(I, E, o);
         }
         head += n;
-        uint32_t pos = 0;
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const unsigned long long mk = __ballot(ok && g == p);
-            if (g == p) pos = cnt[p] + (uint32_t)__popcll(mk & below);
-            cnt[p] += (uint32_t)__popcll(mk);
+        const unsigned long long mk = __ballot(ok);
+        if (ok) {
+            const uint32_t s = (tail2 + (uint32_t)__popcll(mk & below)) & (SEGQ - 1);
+            q.o2[s] = o;
+            q.g2[s] = (uint8_t)g;
         }
-        sink(g, ok, o, pos);
-        wave_lds_sync();                          // slots are rewritten by later pairs
+        tail2 += (uint32_t)__popcll(mk);
+        if (tail2 - head2 >= 64) drain2(64);
+        wave_lds_sync();
     };
     // 64 (MD, edge) pairs at a time: their candidates (the MDs of the edge's
     // module) as one list the 64 lanes walk 64 at a time
@@ -766,6 +797,7 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
         }
     }
     if (tail != head) drain(tail - head);
+    if (tail2 != head2) drain2(tail2 - head2);
     uint32_t c = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p)
