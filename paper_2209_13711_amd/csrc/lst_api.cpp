@@ -66,6 +66,7 @@ struct lst_ctx {
     std::vector<lst_counts> counts;
     bool counts_valid = false;
     int stage = 0;  // 0 nothing, 1 hits loaded, 2 sorted, 3 md, 4 seg, 5 t3, 6 t5, 7 dedup
+    bool sort_ev_ok = false;   // the per-event LDS sort can run on this geometry
 };
 
 static int fail(lst_ctx *c, int code, const char *fmt, ...)
@@ -386,10 +387,19 @@ int lst_load_geometry(lst_ctx *c, int32_t n, const float *f32, const int32_t *i3
     M.sec_off[0] = 0;
     for (int x = 0; x < NXCD; ++x) M.sec_off[x + 1] = M.sec_off[x] + sec_cnt[x];
     M.n_mod = n;
+    // batches sort each event's hits in LDS when its bins fit there
+    c->sort_ev_ok = sort_ev_lds_bytes(n) <= SORT_EV_LDS_MAX && sort_ev_prepare(n) == hipSuccess;
+    (void)hipGetLastError();
     c->arena = nullptr;  // a new geometry invalidates the arena layout
     drop_graph(c);
     c->stage = 0;
     return LST_OK;
+}
+
+// the per-event sort for batches of at least SORT_EV_MIN_EVENTS events
+static bool sort_per_event(const lst_ctx *c)
+{
+    return c->sort_ev_ok && c->caps.events >= SORT_EV_MIN_EVENTS;
 }
 
 int lst_build_map(const double *params, int32_t n_params, int32_t n, const float *f32,
@@ -574,7 +584,7 @@ int lst_run_sort(lst_ctx *c, void *stream)
     int rc = need_stage(c, 1, "lst_run_sort");
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(c, launch_sort(c->E, c->M, c->tune.grid[ST_SORT], s));
+    HIPCHK(c, launch_sort(c->E, c->M, c->tune.grid[ST_SORT], sort_per_event(c), s));
     c->stage = 2;
     return LST_OK;
 }
@@ -822,7 +832,7 @@ static int enqueue_chain(lst_ctx *c, hipStream_t s)
                                           t.blocks_per_cu * c->n_cu, t.lanes[ST_SEG], stop, s));
         return stop == PERS_FULL ? LST_OK : enqueue_after_persistent(c, stop, s);
     }
-    HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], s));
+    HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], sort_per_event(c), s));
     HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], t.lanes[ST_MD], s));
     HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], t.lanes[ST_SEG], s));
     HIPCHK(c, launch_t3(c->E, c->M, c->K, t.grid[ST_T3], t.lanes[ST_T3], s));
@@ -1292,7 +1302,7 @@ static int timed_chain(lst_ctx *c, hipStream_t s, hipEvent_t *ev, double *stage_
         HIPCHK(c, hipEventRecord(ev[ST_COUNT], s));
     } else {
         const Tuning &t = c->tune;
-        HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], s));
+        HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], sort_per_event(c), s));
         HIPCHK(c, hipEventRecord(ev[1], s));
         HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], t.lanes[ST_MD], s));
         HIPCHK(c, hipEventRecord(ev[2], s));

@@ -413,10 +413,114 @@ __global__ void k_hist(EvDev E, int n_mod) { hist_body(E, n_mod); }
 __global__ __launch_bounds__(BLOCK) void k_scan(EvDev E) { scan_body(E); }
 __global__ void k_scatter(EvDev E, int n_mod) { scatter_body(E, n_mod); }
 
+// Batches: one block per event keeps the event's 2 x n_mod bins in LDS, so
+// the histogram and the scatter take LDS atomics instead of device-scope
+// ones.  Same results as the kernels above (bin counts, then the same
+// look-back scan, then each hit to a slot of its bin), and the bins end at
+// zero as they do there.
+constexpr int SORT_EV_BLOCK = 1024;
+constexpr int SORT_EV_ILP = 4;
+
+__global__ __launch_bounds__(SORT_EV_BLOCK) void k_hist_ev(EvDev E, int n_mod)
+{
+    extern __shared__ uint32_t s_bin[];     // [2 * n_mod]
+    const int n_ev = E.desc[D_NEV], nk = 2 * n_mod;
+    const int t0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    for (int i = t0; i < GC_COUNT; i += stride) E.gc[i] = 0u;
+    const int n_tiles = (E.cap_keys + 1 + SCAN_TILE - 1) / SCAN_TILE;
+    for (int i = t0; i < n_tiles; i += stride) E.scan_st[i] = 0ull;
+    for (int ev = blockIdx.x; ev < n_ev; ev += gridDim.x) {
+        for (int k = threadIdx.x; k < nk; k += blockDim.x) s_bin[k] = 0u;
+        __syncthreads();
+        const int h1 = E.hit_off[ev + 1];
+        // SORT_EV_ILP hits per thread and step: their loads are issued together
+        for (int hb = E.hit_off[ev] + threadIdx.x; hb < h1; hb += SORT_EV_ILP * blockDim.x) {
+            int32_t m[SORT_EV_ILP];
+            uint8_t sn[SORT_EV_ILP];
+#pragma unroll
+            for (int u = 0; u < SORT_EV_ILP; ++u) {
+                const int h = hb + u * (int)blockDim.x;
+                m[u] = h < h1 ? E.module[h] : -1;
+                sn[u] = h < h1 ? E.sensor[h] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < SORT_EV_ILP; ++u)
+                if (m[u] >= 0 && m[u] < n_mod && sn[u] <= 1) atomicAdd(&s_bin[2 * m[u] + sn[u]], 1u);
+        }
+        __syncthreads();
+        uint32_t *dst = E.bcnt + (size_t)nk * ev;
+        for (int k = threadIdx.x; k < nk; k += blockDim.x) dst[k] = s_bin[k];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(SORT_EV_BLOCK) void k_scatter_ev(EvDev E, int n_mod)
+{
+    extern __shared__ uint32_t s_cur[];     // [2 * n_mod]: next free slot of each bin
+    const int n_ev = E.desc[D_NEV], nk = 2 * n_mod;
+    for (int ev = blockIdx.x; ev < n_ev; ev += gridDim.x) {
+        const uint32_t *off = E.boff + (size_t)nk * ev;
+        for (int k = threadIdx.x; k < nk; k += blockDim.x) s_cur[k] = off[k];
+        __syncthreads();
+        const int h0 = E.hit_off[ev], h1 = E.hit_off[ev + 1];
+        for (int hb = h0 + threadIdx.x; hb < h1; hb += SORT_EV_ILP * blockDim.x) {
+            int32_t m[SORT_EV_ILP];
+            uint8_t sn[SORT_EV_ILP];
+            float4 v[SORT_EV_ILP];
+#pragma unroll
+            for (int u = 0; u < SORT_EV_ILP; ++u) {
+                const int h = hb + u * (int)blockDim.x;
+                m[u] = -1;
+                sn[u] = 0;
+                if (h < h1) {
+                    m[u] = E.module[h];
+                    sn[u] = E.sensor[h];
+                    v[u] = make_float4(E.x[h], E.y[h], E.z[h], __int_as_float(h - h0));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SORT_EV_ILP; ++u) {
+                const int h = hb + u * (int)blockDim.x;
+                if (h >= h1) continue;
+                if (m[u] < 0 || m[u] >= n_mod || sn[u] > 1) {
+                    atomicOr(&E.gc[GC_ERROR], 1u);
+                    continue;
+                }
+                const uint32_t pos = atomicAdd(&s_cur[2 * m[u] + sn[u]], 1u);
+                E.hsort[pos] = v[u];
+            }
+        }
+        // the bins end at zero, as the device-wide scatter leaves them
+        uint32_t *bc = E.bcnt + (size_t)nk * ev;
+        for (int k = threadIdx.x; k < nk; k += blockDim.x) bc[k] = 0u;
+        __syncthreads();
+    }
+}
+
+size_t sort_ev_lds_bytes(int n_mod) { return (size_t)2 * n_mod * sizeof(uint32_t); }
+
+hipError_t sort_ev_prepare(int n_mod)
+{
+    const int bytes = (int)sort_ev_lds_bytes(n_mod);
+    hipError_t e = hipFuncSetAttribute((const void *)k_hist_ev,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_scatter_ev,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
 // grids depend on the arena capacities only, never on the batch
-hipError_t launch_sort(const EvDev &E, const ModDev &M, int grid, hipStream_t s)
+hipError_t launch_sort(const EvDev &E, const ModDev &M, int grid, bool per_event, hipStream_t s)
 {
     const int nb = (E.cap_keys + 1 + SCAN_TILE - 1) / SCAN_TILE;
+    if (per_event) {
+        const int eg = E.cap_ev < GRID_MAX ? E.cap_ev : GRID_MAX;
+        const size_t lds = sort_ev_lds_bytes(M.n_mod);
+        hipLaunchKernelGGL(k_hist_ev, dim3(eg), dim3(SORT_EV_BLOCK), lds, s, E, M.n_mod);
+        hipLaunchKernelGGL(k_scan, dim3(nb < 1024 ? nb : 1024), dim3(BLOCK), 0, s, E);
+        hipLaunchKernelGGL(k_scatter_ev, dim3(eg), dim3(SORT_EV_BLOCK), lds, s, E, M.n_mod);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_hist, dim3(grid), dim3(BLOCK), 0, s, E, M.n_mod);
     hipLaunchKernelGGL(k_scan, dim3(nb < 1024 ? nb : 1024), dim3(BLOCK), 0, s, E);
     hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(BLOCK), 0, s, E, M.n_mod);
