@@ -542,9 +542,16 @@ struct SegQ {
 
 // mini-doublet stage: accepted pairs and their window outputs staged until
 // the output offset is known
+struct ModL {
+    float4 c, u, v;                   // (cx, cy, cz, g), (ux, uy, uz, rl), (vx, vy, vz, flags)
+};
 struct SmMD {
     uint32_t lo[WAVES][STAGE], up[WAVES][STAGE];
     float bend[WAVES][STAGE], sv[WAVES][STAGE];
+    ModL mod[WAVES][MAXP];            // module frame of each group's slot
+    int4 sl[WAVES][MAXP];             // slot, first lower hit, first upper hit, upper hits
+    uint32_t cnt[WAVES][MAXP];
+    uint8_t g[WAVES][STAGE];
 };
 struct SmSeg {
     int32_t o[WAVES][STAGE];
@@ -615,43 +622,77 @@ __device__ __forceinline__ void write_md(const EvDev &E, const Consts &K, uint32
     E.md_bar[i] = (uint8_t)(mod.barrel | (mod.is2s << 1));
 }
 
-// every lower x upper hit pair of one module slot (one group);
-// sink(ok, hl, hu, o, pos) with o the window's outputs for the pair
+__device__ __forceinline__ ModF mod_from(const ModL &r)
+{
+    ModF f;
+    f.cx = r.c.x; f.cy = r.c.y; f.cz = r.c.z; f.g = r.c.w;
+    f.ux = r.u.x; f.uy = r.u.y; f.uz = r.u.z; f.rl = r.u.w;
+    f.vx = r.v.x; f.vy = r.v.y; f.vz = r.v.z;
+    const int fl = __float_as_int(r.v.w);
+    f.barrel = fl & 1;
+    f.is2s = fl >> 1;
+    return f;
+}
+
+// Every lower x upper hit pair of the wave's P module slots (one per group,
+// its frame and hit ranges in the LDS table), walked as one list 64 pairs at
+// a time, so a slot with many hits is shared by all lanes of the wave.  The
+// list is in slot order, so each slot's accepted pairs are consecutive in
+// the wave's output, in lower-major pair order.
+// sink(ok, g, hl, hu, o, pos): g = group of the slot, pos = rank among the
+// wave's accepted pairs, o the window's outputs for the pair.
 template <int G, class F>
-__device__ __forceinline__ uint32_t enum_md(const EvDev &E, const Consts &K, const ModF &mod,
-                                            uint32_t lo0, uint32_t up0, uint32_t nup,
+__device__ __forceinline__ uint32_t enum_md(const EvDev &E, const Consts &K, const SmMD &sm, int w,
                                             uint32_t np, F &&sink)
 {
-    const Grp<G> gp;
-    uint32_t cnt = 0;
-    const uint32_t np_max = wave_max(np);
-    for (uint32_t b = 0; b < np_max; b += G) {
-        const uint32_t p = b + gp.lane;
+    constexpr int P = Grp<G>::P;
+    const uint32_t l = (uint32_t)lane_id();
+    const unsigned long long below = lanes_below();
+    uint32_t pre[P + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+        pre[p + 1] = pre[p] + (uint32_t)__builtin_amdgcn_readlane((int)np, p * G);
+    const uint32_t tot = pre[P];
+    uint32_t acc = 0;
+    for (uint32_t jc = 0; jc < tot; jc += 64) {
+        const uint32_t j = jc + l;
+        int g = 0;
+        uint32_t gpre = 0;
+#pragma unroll
+        for (int p = 1; p < P; ++p)
+            if (j >= pre[p]) {
+                g = p;
+                gpre = pre[p];
+            }
         bool ok = false;
         uint32_t hl = 0, hu = 0;
         MdOut o = {};
-        if (p < np) {
+        if (j < tot) {
+            const int4 sl = sm.sl[w][g];
+            const uint32_t p = j - gpre, nup = (uint32_t)sl.w;
             const uint32_t il = p / nup, iu = p - il * nup;
-            hl = lo0 + il;
-            hu = up0 + iu;
+            hl = (uint32_t)sl.y + il;
+            hu = (uint32_t)sl.z + iu;
             const float4 L = E.hsort[hl], U = E.hsort[hu];
-            ok = md_accept(K, mod, L.x, L.y, L.z, U.x, U.y, U.z, o);
+            ok = md_accept(K, mod_from(sm.mod[w][g]), L.x, L.y, L.z, U.x, U.y, U.z, o);
         }
-        uint32_t t;
-        const uint32_t r = gp.rank(ok, t);
-        sink(ok, hl, hu, o, cnt + r);
-        cnt += t;
+        const unsigned long long m = __ballot(ok);
+        sink(ok, g, hl, hu, o, acc + (uint32_t)__popcll(m & below));
+        acc += (uint32_t)__popcll(m);
     }
-    return cnt;
+    return acc;
 }
 
-// one group of G lanes per module slot
+// one group of G lanes per module slot sets it up; the pairs are walked by
+// the whole wave
 template <int G>
 __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const Consts &K, SmMD &sm)
 {
-    constexpr int P = Grp<G>::P, CAP = STAGE / P;
+    constexpr int P = Grp<G>::P;
     const Grp<G> gp;
     const int w = wave_id();
+    const uint32_t l = (uint32_t)lane_id();
     const XBlock xb = xcd_block();
     const int n_x = M.sec_off[xb.x + 1] - M.sec_off[xb.x];   // modules of this sector
     const int items = E.desc[D_NEV] * n_x;
@@ -659,66 +700,80 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
         const int k = base + w * P + gp.g;
         const bool act = k < items;
         int slot = 0;
-        if (act) {
-            const int ev = k / n_x;
-            slot = ev * M.n_mod + M.xorder[M.sec_off[xb.x] + (k - ev * n_x)];
-        }
         uint32_t lo0 = 0, up0 = 0, nup = 0, np = 0;
         if (act) {
+            const int ev = k / n_x;
+            const int m = M.xorder[M.sec_off[xb.x] + (k - ev * n_x)];
+            slot = ev * M.n_mod + m;
             lo0 = E.boff[2 * slot];
             up0 = E.boff[2 * slot + 1];
             nup = E.boff[2 * slot + 2] - up0;
             np = (up0 - lo0) * nup;
-        }
-        // per-hit state of duplicate removal for this slot's hits (contiguous)
-        if (act)
+            // per-hit state of duplicate removal for this slot's hits (contiguous)
             for (uint32_t h = lo0 + gp.lane; h < up0 + nup; h += G) {
                 E.hmin[h] = 0xffffffffu;
                 E.htie[h] = 0;
                 E.thead[h] = 0;
             }
-        ModF mod = {};
-        if (np) mod = load_mod(M, slot % M.n_mod);
-        const uint32_t cnt = enum_md<G>(E, K, mod, lo0, up0, nup, np,
-                                        [&](bool ok, uint32_t hl, uint32_t hu, const MdOut &o,
+            if (gp.lane == 0) {
+                sm.sl[w][gp.g] = make_int4(slot, (int)lo0, (int)up0, (int)nup);
+                if (np) {
+                    ModL r;
+                    r.c = make_float4(M.cx[m], M.cy[m], M.cz[m], M.g[m]);
+                    r.u = make_float4(M.ux[m], M.uy[m], M.uz[m], M.rl[m]);
+                    r.v = make_float4(M.vx[m], M.vy[m], M.vz[m],
+                                      __int_as_float(M.barrel[m] | (M.is2s[m] << 1)));
+                    sm.mod[w][gp.g] = r;
+                }
+            }
+        }
+        if (l < (uint32_t)MAXP) sm.cnt[w][l] = 0u;
+        wave_lds_sync();
+        const uint32_t tot = enum_md<G>(E, K, sm, w, np,
+                                        [&](bool ok, int g, uint32_t hl, uint32_t hu, const MdOut &o,
                                             uint32_t pos) {
-                                            if (ok && pos < CAP) {
-                                                const int q = gp.g * CAP + pos;
-                                                sm.lo[w][q] = hl;
-                                                sm.up[w][q] = hu;
-                                                sm.bend[w][q] = o.bend;
-                                                sm.sv[w][q] = o.sv;
-                                            }
-                                        });
+            if (ok) {
+                atomicAdd(&sm.cnt[w][g], 1u);
+                if (pos < STAGE) {
+                    sm.lo[w][pos] = hl;
+                    sm.up[w][pos] = hu;
+                    sm.bend[w][pos] = o.bend;
+                    sm.sv[w][pos] = o.sv;
+                    sm.g[w][pos] = (uint8_t)g;
+                }
+            }
+        });
+        wave_lds_sync();
+        // each slot's MDs follow those of the groups before it
+        const uint32_t cnt = act ? sm.cnt[w][gp.g] : 0u;
         uint32_t wtot;
         const uint32_t gex = gp.wave_prefix(cnt, wtot);
         bool ovf;
-        const uint32_t off = block_reserve(wtot, E, OT_MD, ovf) + gex;
+        const uint32_t off = block_reserve(tot, E, OT_MD, ovf);
         if (act && gp.lane == 0) {
-            E.md_start[slot] = (int32_t)off;
+            E.md_start[slot] = (int32_t)(off + gex);
             E.md_cnt[slot] = ovf ? 0 : (int32_t)cnt;
         }
         if (ovf) continue;
-        if (act && cnt <= CAP) {
-            for (uint32_t k = gp.lane; k < cnt; k += G) {
-                const int q = gp.g * CAP + k;
-                const uint32_t hl = sm.lo[w][q];
-                const float4 L = E.hsort[hl];
-                MdOut o;
-                md_anchor(K, L.x, L.y, o);
-                o.bend = sm.bend[w][q];
-                o.sv = sm.sv[w][q];
-                write_md(E, K, off + k, slot, hl, sm.up[w][q], o, mod);
-            }
+        for (uint32_t q = l; q < tot && q < (uint32_t)STAGE; q += 64) {
+            const int g = sm.g[w][q];
+            const uint32_t hl = sm.lo[w][q];
+            const float4 L = E.hsort[hl];
+            MdOut o;
+            md_anchor(K, L.x, L.y, o);
+            o.bend = sm.bend[w][q];
+            o.sv = sm.sv[w][q];
+            write_md(E, K, off + q, sm.sl[w][g].x, hl, sm.up[w][q], o, mod_from(sm.mod[w][g]));
         }
-        if (wave_max(cnt) > CAP) {
-            // groups beyond their staging share enumerate again and write directly
-            const bool redo = act && cnt > CAP;
-            enum_md<G>(E, K, mod, lo0, up0, nup, redo ? np : 0u,
-                       [&](bool ok, uint32_t hl, uint32_t hu, const MdOut &o, uint32_t pos) {
-                           if (ok) write_md(E, K, off + pos, slot, hl, hu, o, mod);
-                       });
+        if (tot > (uint32_t)STAGE) {
+            // beyond the staging: enumerate again and write directly
+            enum_md<G>(E, K, sm, w, np,
+                       [&](bool ok, int g, uint32_t hl, uint32_t hu, const MdOut &o, uint32_t pos) {
+                if (ok && pos >= STAGE)
+                    write_md(E, K, off + pos, sm.sl[w][g].x, hl, hu, o, mod_from(sm.mod[w][g]));
+            });
         }
+        wave_lds_sync();
     }
 }
 
