@@ -179,36 +179,28 @@ __device__ __forceinline__ XBlock xcd_block()
     return b;
 }
 
-// Block-wide reservation in shard blockIdx % NSH; every thread of the block
-// must call it.  Returns the first output index of the calling wave; `ovf`
-// is set for the whole block when the range does not fit the shard's region.
-__device__ __forceinline__ uint32_t block_reserve(uint32_t wave_total, const EvDev &E, int type,
-                                                  bool &ovf)
+// Wave-wide reservation: lane 0 takes the wave's output range from one of
+// the NSH / NXCD shards of the block's XCD sector, picked by the wave's
+// position so that the sector's waves spread over them.  No block barrier:
+// the waves of a block go on independently.  Every lane of the wave calls it
+// with the same total; returns the wave's first output index, `ovf` when the
+// range does not fit the shard's region.
+__device__ __forceinline__ uint32_t wave_reserve(uint32_t wave_total, const EvDev &E, int type,
+                                                 bool &ovf)
 {
-    __shared__ uint32_t s_cnt[WAVES];
-    __shared__ uint32_t s_base;
-    __shared__ int s_ovf;
-    const int w = wave_id();
-    if (lane_id() == 0) s_cnt[w] = wave_total;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t tot = 0;
-        for (int i = 0; i < WAVES; ++i) tot += s_cnt[i];
-        const uint32_t shard = blockIdx.x % NSH;
-        const uint32_t rc = E.rc[type];
-        const uint32_t base = tot ? atomicAdd(&E.gc[gc_shard(type, shard)], tot) : 0u;
-        const int o = ((uint64_t)base + tot) > (uint64_t)rc;
+    const uint32_t x = blockIdx.x % NXCD;
+    const uint32_t r = ((blockIdx.x / NXCD) * WAVES + (uint32_t)wave_id()) % (NSH / NXCD);
+    const uint32_t shard = x + NXCD * r;
+    uint32_t base = 0;
+    int o = 0;
+    if (lane_id() == 0 && wave_total) {
+        base = atomicAdd(&E.gc[gc_shard(type, shard)], wave_total);
+        o = ((uint64_t)base + wave_total) > (uint64_t)E.rc[type];
         if (o) atomicOr(&E.gc[GC_OVERFLOW], 1u << type);
-        s_base = shard * rc + base;
-        s_ovf = o;
     }
-    __syncthreads();
-    uint32_t off = s_base;
-    for (int i = 0; i < w; ++i) off += s_cnt[i];
-    ovf = s_ovf != 0;
-    // the next grid-stride round rewrites s_cnt: every wave must have read it
-    __syncthreads();
-    return off;
+    base = __shfl(base, 0, 64);
+    ovf = __shfl(o, 0, 64) != 0;
+    return shard * E.rc[type] + base;
 }
 
 // ---------------------------------------------------------------- zero fill
@@ -749,7 +741,7 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
         uint32_t wtot;
         const uint32_t gex = gp.wave_prefix(cnt, wtot);
         bool ovf;
-        const uint32_t off = block_reserve(tot, E, OT_MD, ovf);
+        const uint32_t off = wave_reserve(tot, E, OT_MD, ovf);
         if (act && gp.lane == 0) {
             E.md_start[slot] = (int32_t)(off + gex);
             E.md_cnt[slot] = ovf ? 0 : (int32_t)cnt;
@@ -985,7 +977,7 @@ __device__ __forceinline__ void seg_body(const EvDev &E, const ModDev &M, const 
         uint32_t wtot;
         const uint32_t gex = gp.wave_prefix(cnt, wtot);
         bool ovf;
-        const uint32_t off = block_reserve(wtot, E, OT_SEG, ovf) + gex;
+        const uint32_t off = wave_reserve(wtot, E, OT_SEG, ovf) + gex;
         if (act && gp.lane == 0) {
             E.seg_start[i] = (int32_t)off;
             E.seg_cnt[i] = ovf ? 0 : (int32_t)cnt;
@@ -1132,7 +1124,7 @@ __device__ __forceinline__ void t3_body(const EvDev &E, const Consts &K, SmT3 &s
         const uint32_t cl = l < (uint32_t)T3_PMAX ? sm.cnt[w][l] : 0u;
         const uint32_t cex = wave_incl_scan(cl) - cl;
         bool ovf;
-        const uint32_t off = block_reserve(tot, E, OT_T3, ovf);
+        const uint32_t off = wave_reserve(tot, E, OT_T3, ovf);
         if (act) {
             E.t3_start[a] = (int32_t)(off + cex);
             E.t3_cnt[a] = ovf ? 0 : (int32_t)cl;
@@ -1298,7 +1290,7 @@ __device__ __forceinline__ void t5_body(const EvDev &E, const Consts &K, SmT5 &s
         });
         wave_lds_sync();
         bool ovf;
-        const uint32_t off = block_reserve(tot, E, OT_T5, ovf);
+        const uint32_t off = wave_reserve(tot, E, OT_T5, ovf);
         if (ovf) continue;
         for (uint32_t q = l; q < tot && q < (uint32_t)STAGE; q += 64)
             write_t5(E, off + q, sm.aidx[w][sm.g[w][q]], sm.b[w][q], sm.c[w][q], sm.d[w][q],
