@@ -227,9 +227,11 @@ int lst_get_t5_scores(lst_ctx *ctx, int32_t event, float *out_host, int64_t cap,
 int lst_run_chain_persistent(lst_ctx *ctx, void *stream);
 
 /* Launch shape: grid6 = blocks of 256 threads for the stages (hit grouping,
- * MD, segments, T3, T5, dedup); lanes6 = lanes of the group that owns one
- * inner object (8, 16, 32 or 64; used by MD, segments, T3, T5, ignored for
- * the others; NULL keeps the current values); persistent = 1 runs the chain
+ * MD, segments, T3, T5, dedup); lanes6 = group width G (8, 16, 32 or 64;
+ * used by MD, segments, T3, T5, ignored for the others; NULL keeps the
+ * current values), which sets the inner objects a wave takes per round:
+ * 64 / G module slots (MD) or inner MDs (segments), 256 / G inner MDs (T3,
+ * T5); the wave walks their candidates together.  persistent = 1 runs the chain
  * as one persistent kernel of blocks_per_cu x CUs blocks, whose object
  * stages all use the segment stage's group width.  lst_get_tuning fills
  * out15 = grid6, lanes6, persistent, blocks_per_cu, number of CUs. */
