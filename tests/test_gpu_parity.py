@@ -73,6 +73,47 @@ def test_batch_of_uneven_events_matches_per_event_oracle():
         assert [cnt["cand_md"], cnt["cand_seg"], cnt["cand_t3"], cnt["cand_t5"]] == ref.cands.tolist()
 
 
+@pytest.mark.parametrize("geometry,cid,n_tracks", [("barrel_toy", 1, None), ("full", 2, 300)])
+def test_batch_sorted_per_event_matches_oracle(geometry, cid, n_tracks):
+    """Batches of 8 or more events group their hits per event in LDS (bins
+    of the barrel toy: 66 KB, of the full geometry: 102 KB); the batch holds
+    an empty event and a hit with a bad module id, and a second batch on the
+    same context checks that the first one left every bin at zero."""
+    geo = G.get(geometry)
+    params = PR.make()
+    orc = oracle.Oracle(params, geo.f32, geo.i32)
+    ctx = _ctx(geo, params)
+    for first in (0, 20):
+        evs = [E.generate(cid, first + e, n_tracks=n_tracks) for e in range(9)]
+        evs[3] = E.generate(cid, first + 3, n_tracks=0)
+        b = E.concat(evs)
+        mod = b.module.copy()
+        bad = int(b.offsets[5]) + 1            # second hit of event 5
+        mod[bad] = geo.n_mod + 3
+        print(f"case per-event sort {geometry} first {first} hits {b.offsets.tolist()}", flush=True)
+        ctx.run_batch(b.offsets, b.x, b.y, b.z, mod, b.sensor)
+        assert ctx.caps["events"] >= 8
+        for e, ev in enumerate(evs):
+            cnt = ctx.counts(e)
+            assert cnt["error_flags"] & 1
+            if e == 5:
+                keep = np.ones(ev.n_hits, bool)
+                keep[1] = False
+                ref = orc.run(ev.x[keep], ev.y[keep], ev.z[keep], ev.module[keep], ev.sensor[keep])
+                back = np.nonzero(keep)[0]
+                for k in range(5):
+                    ref.tuples[k] = back[ref.tuples[k]] if len(ref.tuples[k]) else ref.tuples[k]
+                for k in range(4):
+                    if len(ref.near[k][0]):
+                        ref.near[k] = (back[ref.near[k][0]], ref.near[k][1], ref.near[k][2])
+            else:
+                ref = orc.run_event(ev)
+                assert [cnt["cand_md"], cnt["cand_seg"], cnt["cand_t3"],
+                        cnt["cand_t5"]] == ref.cands.tolist()
+            assert_parity({k: ctx.objects(e, k) for k in range(5)}, ref)
+        assert len(ctx.objects(3, 0)) == 0
+
+
 def test_empty_and_degenerate_events():
     geo = G.get("barrel_toy")
     params = PR.make()
