@@ -80,12 +80,13 @@ def algorithmic_bytes(c, n_slots, n_edges_used):
     every output written once, in the library's layouts.
     md:  sorted hit (16 B) read and its duplicate-removal state (12 B) set per
          hit; per slot two bin offsets (8 B), the module frame (52 B) and the
-         slot's MD start and count (8 B); per MD its record written (69 B:
-         hit pair and slot 12, three float4 48, bend 4, S3 bound 4, flags 1)
-    seg: per MD its record read (57 B: window and rest terms, slot) and its
-         segment start and count written (8 B); per slot MD start and count
-         and the map row (12 B); per map edge read its column (4 B); per
-         segment its MD pair written (8 B)
+         slot's MD start and count (8 B); per MD its record written (85 B:
+         hit pair and slot 12, three float4 48, map row 16, bend 4, S3 bound
+         4, flags 1)
+    seg: per MD its record read (69 B: window and cut terms, map row) and
+         its segment start and count written (8 B); per slot MD start and
+         count (8 B); per map edge read its column (4 B); per segment its MD
+         pair written (8 B)
     t3:  per MD its record (49 B) and segment start/count (8 B) read, triplet
          start/count written (8 B); per segment its outer MD (4 B); per
          triplet its MDs and curvature (16 B) and scorer flag (1 B) written
@@ -95,8 +96,8 @@ def algorithmic_bytes(c, n_slots, n_edges_used):
     H, S = c["n_hits"], n_slots
     md, seg, t3, t5 = c["n_md"], c["n_seg"], c["n_t3"], c["n_t5"]
     return {
-        "md": 28 * H + 68 * S + 69 * md,
-        "seg": 65 * md + 12 * S + 4 * n_edges_used + 8 * seg,
+        "md": 28 * H + 68 * S + 85 * md,
+        "seg": 77 * md + 8 * S + 4 * n_edges_used + 8 * seg,
         "t3": 65 * md + 4 * seg + 17 * t3,
         "t5": 57 * md + 17 * t3 + 25 * t5,
     }

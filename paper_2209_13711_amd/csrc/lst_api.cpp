@@ -185,6 +185,7 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.md_hlo = cv.take<int32_t>(nmd);
     E.md_hup = cv.take<int32_t>(nmd);
     E.md_slot = cv.take<int32_t>(nmd);
+    E.md_nbr = cv.take<int4>(nmd);
     E.md_p0 = cv.take<float4>(nmd);
     E.md_p1 = cv.take<float4>(nmd);
     E.md_p2 = cv.take<float4>(nmd);

@@ -87,6 +87,7 @@ struct EvDev {
     uint32_t cap_tpool;
     // mini-doublets
     int32_t *md_hlo, *md_hup, *md_slot;
+    int4 *md_nbr;                    // module's first map edge, its edge count, event's first slot
     // anchor and window terms, three 16-byte records per MD so that a lane
     // gathers an MD with three loads: (x, y, z, r), (a, ca, 1/r, |sv|/r),
     // (dx, dy, |d|, sv)

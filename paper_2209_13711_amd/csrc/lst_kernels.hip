@@ -542,6 +542,7 @@ struct SmMD {
     float bend[WAVES][STAGE], sv[WAVES][STAGE];
     ModL mod[WAVES][MAXP];            // module frame of each group's slot
     int4 sl[WAVES][MAXP];             // slot, first lower hit, first upper hit, upper hits
+    int4 nb[WAVES][MAXP];             // the slot's map row and its event's first slot
     uint32_t cnt[WAVES][MAXP];
     uint8_t g[WAVES][STAGE];
 };
@@ -596,13 +597,14 @@ __device__ __forceinline__ ModF load_mod(const ModDev &M, int m)
 
 __device__ __forceinline__ void write_md(const EvDev &E, const Consts &K, uint32_t i, int slot,
                                          uint32_t hl, uint32_t hu, const MdOut &o,
-                                         const ModF &mod)
+                                         const ModF &mod, const int4 &nbr)
 {
     const float4 L = E.hsort[hl], U = E.hsort[hu];
     const float xL = L.x, yL = L.y;
     E.md_hlo[i] = (int32_t)hl;
     E.md_hup[i] = (int32_t)hu;
     E.md_slot[i] = slot;
+    E.md_nbr[i] = nbr;
     const float dx = U.x - xL, dy = U.y - yL;
     E.md_p0[i] = make_float4(xL, yL, L.z, o.r);
     // the segment window's per-MD terms, rounded exactly as it would round them
@@ -709,6 +711,8 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
             }
             if (gp.lane == 0) {
                 sm.sl[w][gp.g] = make_int4(slot, (int)lo0, (int)up0, (int)nup);
+                const int e0 = M.map_ptr[m];
+                sm.nb[w][gp.g] = make_int4(e0, M.map_ptr[m + 1] - e0, ev * M.n_mod, 0);
                 if (np) {
                     ModL r;
                     r.c = make_float4(M.cx[m], M.cy[m], M.cz[m], M.g[m]);
@@ -755,14 +759,14 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
             md_anchor(K, L.x, L.y, o);
             o.bend = sm.bend[w][q];
             o.sv = sm.sv[w][q];
-            write_md(E, K, off + q, sm.sl[w][g].x, hl, sm.up[w][q], o, mod_from(sm.mod[w][g]));
+            write_md(E, K, off + q, sm.sl[w][g].x, hl, sm.up[w][q], o, mod_from(sm.mod[w][g]), sm.nb[w][g]);
         }
         if (tot > (uint32_t)STAGE) {
             // beyond the staging: enumerate again and write directly
             enum_md<G>(E, K, sm, w, np,
                        [&](bool ok, int g, uint32_t hl, uint32_t hu, const MdOut &o, uint32_t pos) {
                 if (ok && pos >= STAGE)
-                    write_md(E, K, off + pos, sm.sl[w][g].x, hl, hu, o, mod_from(sm.mod[w][g]));
+                    write_md(E, K, off + pos, sm.sl[w][g].x, hl, hu, o, mod_from(sm.mod[w][g]), sm.nb[w][g]);
             });
         }
         wave_lds_sync();
@@ -816,11 +820,9 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
     const uint32_t l = (uint32_t)lane_id();
     int32_t ne = 0;
     if (act) {
-        const int slot = E.md_slot[i];
-        const int ev = slot / M.n_mod;
-        const int m = slot - ev * M.n_mod;
-        const int32_t e0 = M.map_ptr[m];
-        ne = M.map_ptr[m + 1] - e0;
+        const int4 nb = E.md_nbr[i];
+        const int32_t e0 = nb.x;
+        ne = nb.y;
         if (gp.lane == 0) {
             const float4 p0 = E.md_p0[i], p1 = E.md_p1[i], p2 = E.md_p2[i];
             q.ip[gp.g] = p0;
@@ -828,7 +830,7 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
             q.ib[gp.g] = E.md_bar[i] & 1;
             q.w0[gp.g] = make_float4(p0.x, p0.y, p0.w, p1.x);
             q.w1[gp.g] = make_float4(p1.y, p1.z, p1.w, 0.0f);
-            q.eb[gp.g] = make_int2(e0, ev * M.n_mod);
+            q.eb[gp.g] = make_int2(e0, nb.z);
         }
     }
     // the wave's (inner MD, map edge) pairs as one list in group order:
