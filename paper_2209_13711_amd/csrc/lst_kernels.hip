@@ -64,9 +64,10 @@ __device__ __forceinline__ int wave_find(uint32_t incl, uint32_t j)
     return lo;
 }
 
-// A wave split into P = 64 / G groups of G lanes; each group works on its
-// own inner object.  Small candidate lists (a few dozen per inner object)
-// then fill the lanes, and P inner objects' loads are in flight per wave.
+// A wave split into P = 64 / G groups of G lanes: each group sets up its
+// own inner object, so P objects' loads are in flight per wave; Grp<64>
+// gives the whole-wave scan, broadcast and search the stages use to walk
+// their candidates as one list.
 template <int G>
 struct Grp {
     static constexpr int P = 64 / G;
@@ -94,14 +95,6 @@ struct Grp {
             if (__shfl(incl, mid, G) > j) hi = mid; else lo = mid + 1;
         }
         return lo;
-    }
-    // accepted lanes of the group below this lane; *tot = accepted in the group
-    __device__ __forceinline__ uint32_t rank(bool ok, uint32_t &tot) const
-    {
-        const unsigned long long m = __ballot(ok);
-        const unsigned long long gm = G == 64 ? m : (m >> (g * G)) & ((1ull << (G & 63)) - 1ull);
-        tot = (uint32_t)__popcll(gm);
-        return (uint32_t)__popcll(gm & ((1ull << lane) - 1ull));
     }
     // exclusive prefix of a per-group value over the wave's groups, and the sum
     __device__ __forceinline__ uint32_t wave_prefix(uint32_t v, uint32_t &sum) const
@@ -583,18 +576,6 @@ struct SmChain {
 };
 
 // ---------------------------------------------------------------- mini-doublets
-__device__ __forceinline__ ModF load_mod(const ModDev &M, int m)
-{
-    ModF f;
-    f.cx = M.cx[m]; f.cy = M.cy[m]; f.cz = M.cz[m];
-    f.ux = M.ux[m]; f.uy = M.uy[m]; f.uz = M.uz[m];
-    f.vx = M.vx[m]; f.vy = M.vy[m]; f.vz = M.vz[m];
-    f.g = M.g[m]; f.rl = M.rl[m];
-    f.barrel = M.barrel[m];
-    f.is2s = M.is2s[m];
-    return f;
-}
-
 __device__ __forceinline__ void write_md(const EvDev &E, const Consts &K, uint32_t i, int slot,
                                          uint32_t hl, uint32_t hu, const MdOut &o,
                                          const ModF &mod, const int4 &nbr)
