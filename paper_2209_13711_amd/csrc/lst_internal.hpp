@@ -129,7 +129,7 @@ constexpr int SCAN_TILE = 4096;      // keys per tile of the look-back scan
 // launchers (lst_kernels.hip)
 hipError_t launch_copy(void *dst, const void *src, size_t n_bytes, hipStream_t s);
 hipError_t launch_zero(const EvDev &E, void *zero_base, size_t zero_bytes, hipStream_t s);
-// per_event: one block per event with the event's bins in LDS (batches)
+// per_event: one block per (event, quarter of its bins), bins in LDS (batches)
 hipError_t launch_sort(const EvDev &E, const ModDev &M, int grid, bool per_event, hipStream_t s);
 size_t sort_ev_lds_bytes(int n_mod);
 constexpr size_t SORT_EV_LDS_MAX = 160 * 1024;   // LDS of one gfx950 workgroup

@@ -398,24 +398,30 @@ __global__ void k_hist(EvDev E, int n_mod) { hist_body(E, n_mod); }
 __global__ __launch_bounds__(BLOCK) void k_scan(EvDev E) { scan_body(E); }
 __global__ void k_scatter(EvDev E, int n_mod) { scatter_body(E, n_mod); }
 
-// Batches: one block per event keeps the event's 2 x n_mod bins in LDS, so
-// the histogram and the scatter take LDS atomics instead of device-scope
-// ones.  Same results as the kernels above (bin counts, then the same
-// look-back scan, then each hit to a slot of its bin), and the bins end at
-// zero as they do there.
+// Batches: each event's 2 x n_mod bins are split in SORT_EV_PARTS ranges of
+// consecutive keys; one block per (event, range) keeps its bins in LDS and
+// takes the event's hits whose key falls in its range, so the histogram and
+// the scatter use LDS atomics instead of device-scope ones.  Same results as
+// the kernels above (bin counts, then the same look-back scan, then each hit
+// to a slot of its bin), and the bins end at zero as they do there.
 constexpr int SORT_EV_BLOCK = 1024;
 constexpr int SORT_EV_ILP = 4;
+constexpr int SORT_EV_PARTS = 4;
+
+__device__ __forceinline__ int sort_ev_span(int nk) { return (nk + SORT_EV_PARTS - 1) / SORT_EV_PARTS; }
 
 __global__ __launch_bounds__(SORT_EV_BLOCK) void k_hist_ev(EvDev E, int n_mod)
 {
-    extern __shared__ uint32_t s_bin[];     // [2 * n_mod]
-    const int n_ev = E.desc[D_NEV], nk = 2 * n_mod;
+    extern __shared__ uint32_t s_bin[];     // [sort_ev_span(2 n_mod)]
+    const int n_ev = E.desc[D_NEV], nk = 2 * n_mod, kp = sort_ev_span(nk);
     const int t0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
     for (int i = t0; i < GC_COUNT; i += stride) E.gc[i] = 0u;
     const int n_tiles = (E.cap_keys + 1 + SCAN_TILE - 1) / SCAN_TILE;
     for (int i = t0; i < n_tiles; i += stride) E.scan_st[i] = 0ull;
-    for (int ev = blockIdx.x; ev < n_ev; ev += gridDim.x) {
-        for (int k = threadIdx.x; k < nk; k += blockDim.x) s_bin[k] = 0u;
+    for (int item = blockIdx.x; item < n_ev * SORT_EV_PARTS; item += gridDim.x) {
+        const int ev = item / SORT_EV_PARTS, k0 = (item - ev * SORT_EV_PARTS) * kp;
+        const int k1 = k0 + kp < nk ? k0 + kp : nk;
+        for (int k = threadIdx.x; k < k1 - k0; k += blockDim.x) s_bin[k] = 0u;
         __syncthreads();
         const int h1 = E.hit_off[ev + 1];
         // SORT_EV_ILP hits per thread and step: their loads are issued together
@@ -429,60 +435,72 @@ __global__ __launch_bounds__(SORT_EV_BLOCK) void k_hist_ev(EvDev E, int n_mod)
                 sn[u] = h < h1 ? E.sensor[h] : 0;
             }
 #pragma unroll
-            for (int u = 0; u < SORT_EV_ILP; ++u)
-                if (m[u] >= 0 && m[u] < n_mod && sn[u] <= 1) atomicAdd(&s_bin[2 * m[u] + sn[u]], 1u);
+            for (int u = 0; u < SORT_EV_ILP; ++u) {
+                const int key = 2 * m[u] + sn[u];
+                if (m[u] >= 0 && m[u] < n_mod && sn[u] <= 1 && key >= k0 && key < k1)
+                    atomicAdd(&s_bin[key - k0], 1u);
+            }
         }
         __syncthreads();
         uint32_t *dst = E.bcnt + (size_t)nk * ev;
-        for (int k = threadIdx.x; k < nk; k += blockDim.x) dst[k] = s_bin[k];
+        for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) dst[k] = s_bin[k - k0];
         __syncthreads();
     }
 }
 
 __global__ __launch_bounds__(SORT_EV_BLOCK) void k_scatter_ev(EvDev E, int n_mod)
 {
-    extern __shared__ uint32_t s_cur[];     // [2 * n_mod]: next free slot of each bin
-    const int n_ev = E.desc[D_NEV], nk = 2 * n_mod;
-    for (int ev = blockIdx.x; ev < n_ev; ev += gridDim.x) {
+    extern __shared__ uint32_t s_cur[];     // next free slot of each bin of the range
+    const int n_ev = E.desc[D_NEV], nk = 2 * n_mod, kp = sort_ev_span(nk);
+    for (int item = blockIdx.x; item < n_ev * SORT_EV_PARTS; item += gridDim.x) {
+        const int ev = item / SORT_EV_PARTS, part = item - ev * SORT_EV_PARTS, k0 = part * kp;
+        const int k1 = k0 + kp < nk ? k0 + kp : nk;
         const uint32_t *off = E.boff + (size_t)nk * ev;
-        for (int k = threadIdx.x; k < nk; k += blockDim.x) s_cur[k] = off[k];
+        for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) s_cur[k - k0] = off[k];
         __syncthreads();
         const int h0 = E.hit_off[ev], h1 = E.hit_off[ev + 1];
         for (int hb = h0 + threadIdx.x; hb < h1; hb += SORT_EV_ILP * blockDim.x) {
-            int32_t m[SORT_EV_ILP];
-            uint8_t sn[SORT_EV_ILP];
+            int key[SORT_EV_ILP];
+#pragma unroll
+            for (int u = 0; u < SORT_EV_ILP; ++u) {
+                const int h = hb + u * (int)blockDim.x;
+                key[u] = -1;
+                if (h < h1) {
+                    const int32_t m = E.module[h];
+                    const uint8_t sn = E.sensor[h];
+                    if (m < 0 || m >= n_mod || sn > 1) {
+                        if (part == 0) atomicOr(&E.gc[GC_ERROR], 1u);
+                    } else {
+                        key[u] = 2 * m + sn;
+                    }
+                }
+            }
             float4 v[SORT_EV_ILP];
 #pragma unroll
             for (int u = 0; u < SORT_EV_ILP; ++u) {
                 const int h = hb + u * (int)blockDim.x;
-                m[u] = -1;
-                sn[u] = 0;
-                if (h < h1) {
-                    m[u] = E.module[h];
-                    sn[u] = E.sensor[h];
+                if (key[u] >= k0 && key[u] < k1)
                     v[u] = make_float4(E.x[h], E.y[h], E.z[h], __int_as_float(h - h0));
-                }
             }
 #pragma unroll
             for (int u = 0; u < SORT_EV_ILP; ++u) {
-                const int h = hb + u * (int)blockDim.x;
-                if (h >= h1) continue;
-                if (m[u] < 0 || m[u] >= n_mod || sn[u] > 1) {
-                    atomicOr(&E.gc[GC_ERROR], 1u);
-                    continue;
+                if (key[u] >= k0 && key[u] < k1) {
+                    const uint32_t pos = atomicAdd(&s_cur[key[u] - k0], 1u);
+                    E.hsort[pos] = v[u];
                 }
-                const uint32_t pos = atomicAdd(&s_cur[2 * m[u] + sn[u]], 1u);
-                E.hsort[pos] = v[u];
             }
         }
         // the bins end at zero, as the device-wide scatter leaves them
         uint32_t *bc = E.bcnt + (size_t)nk * ev;
-        for (int k = threadIdx.x; k < nk; k += blockDim.x) bc[k] = 0u;
+        for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) bc[k] = 0u;
         __syncthreads();
     }
 }
 
-size_t sort_ev_lds_bytes(int n_mod) { return (size_t)2 * n_mod * sizeof(uint32_t); }
+size_t sort_ev_lds_bytes(int n_mod)
+{
+    return (size_t)((2 * n_mod + SORT_EV_PARTS - 1) / SORT_EV_PARTS) * sizeof(uint32_t);
+}
 
 hipError_t sort_ev_prepare(int n_mod)
 {
@@ -499,7 +517,8 @@ hipError_t launch_sort(const EvDev &E, const ModDev &M, int grid, bool per_event
 {
     const int nb = (E.cap_keys + 1 + SCAN_TILE - 1) / SCAN_TILE;
     if (per_event) {
-        const int eg = E.cap_ev < GRID_MAX ? E.cap_ev : GRID_MAX;
+        const int items = E.cap_ev * SORT_EV_PARTS;
+        const int eg = items < GRID_MAX ? items : GRID_MAX;
         const size_t lds = sort_ev_lds_bytes(M.n_mod);
         hipLaunchKernelGGL(k_hist_ev, dim3(eg), dim3(SORT_EV_BLOCK), lds, s, E, M.n_mod);
         hipLaunchKernelGGL(k_scan, dim3(nb < 1024 ? nb : 1024), dim3(BLOCK), 0, s, E);

@@ -75,8 +75,8 @@ def test_batch_of_uneven_events_matches_per_event_oracle():
 
 @pytest.mark.parametrize("geometry,cid,n_tracks", [("barrel_toy", 1, None), ("full", 2, 300)])
 def test_batch_sorted_per_event_matches_oracle(geometry, cid, n_tracks):
-    """Batches of 8 or more events group their hits per event in LDS (bins
-    of the barrel toy: 66 KB, of the full geometry: 102 KB); the batch holds
+    """Batches of 8 or more events group their hits per event in LDS (a
+    quarter of the event's bins per block); the batch holds
     an empty event and a hit with a bad module id, and a second batch on the
     same context checks that the first one left every bin at zero."""
     geo = G.get(geometry)
