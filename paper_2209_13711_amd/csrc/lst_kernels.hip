@@ -38,6 +38,41 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// inclusive max-scan of non-negative values over the 64 lanes: shifts within
+// rows of 16 lanes, then the last lane of a row broadcast to the next rows
+// (DPP row_shr:1,2,4,8, row_bcast:15, row_bcast:31)
+__device__ __forceinline__ int wave_max_scan(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false));
+    return v;
+}
+
+// Lane l owns c consecutive positions of a list, ending at its inclusive
+// prefix incl.  Returns the owner of position jc + lane (positions past the
+// end map to the last owner): each owner marks where its range enters the
+// window [jc, jc + 64) in the wave's LDS row `mark`, and a max-scan fills
+// the gaps.
+__device__ __forceinline__ int chunk_src(uint32_t incl, uint32_t c, uint32_t jc, int *mark)
+{
+    const int l = lane_id();
+    mark[l] = 0;
+    wave_lds_sync();
+    const uint32_t ex = incl - c;
+    if (c > 0) {
+        if (ex >= jc && ex < jc + 64u) mark[ex - jc] = l + 1;
+        else if (ex < jc && incl > jc) mark[0] = l + 1;
+    }
+    wave_lds_sync();
+    const int v = mark[l];
+    wave_lds_sync();
+    return wave_max_scan(v) - 1;
+}
+
 // inclusive scan over the 64 lanes of a wave
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
@@ -541,6 +576,7 @@ struct SegQ {
     int2 eb[MAXP];                    // its module's first map edge, its event's first slot
     int32_t ib[MAXP], idx[MAXP], off[MAXP];
     int32_t o[SEGQ], o2[SEGQ];        // window survivors; angle survivors
+    int32_t mark[64];                 // chunk_src
     uint8_t g[SEGQ], g2[SEGQ];
 };
 
@@ -572,6 +608,7 @@ struct SmT3 {
     float asv[WAVES][T3_PMAX];        // its sv
     int32_t abar[WAVES][T3_PMAX], aidx[WAVES][T3_PMAX];
     uint32_t cnt[WAVES][T3_PMAX];
+    int32_t mark[WAVES][64];          // chunk_src
     uint8_t g[WAVES][STAGE];
 };
 // quintuplet stage: the same per-wave table of inner MDs and staging
@@ -582,6 +619,7 @@ struct SmT5 {
     float4 ap[WAVES][T5_PMAX];
     float asv[WAVES][T5_PMAX];
     int32_t abar[WAVES][T5_PMAX], aidx[WAVES][T5_PMAX];
+    int32_t mark[WAVES][64];          // chunk_src
     uint8_t g[WAVES][STAGE];
 };
 struct SmChain {
@@ -927,7 +965,7 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
         const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
         for (uint32_t jc = 0; jc < tot; jc += 64) {
             const uint32_t j = jc + l;
-            const int src = gw.find(incl, j < tot ? j : tot - 1);
+            const int src = chunk_src(incl, bc, jc, q.mark);
             const uint32_t ex = gw.bcast(incl, src) - gw.bcast(bc, src);
             const int32_t obs = gw.bcast(bs, src);
             const int g = gw.bcast(ge, src);
@@ -1031,7 +1069,7 @@ hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, int grid
 // enumeration order.  sink(ok, g, b, c, k, pos): g = lane of the inner MD,
 // pos = rank among the wave's accepted triplets.
 template <class F>
-__device__ __forceinline__ uint32_t enum_t3(const EvDev &E, const Consts &K, const SmT3 &sm,
+__device__ __forceinline__ uint32_t enum_t3(const EvDev &E, const Consts &K, SmT3 &sm,
                                             int w, int32_t ns1, int32_t s10, uint32_t incl1,
                                             F &&sink)
 {
@@ -1042,7 +1080,7 @@ __device__ __forceinline__ uint32_t enum_t3(const EvDev &E, const Consts &K, con
     uint32_t acc = 0;
     for (uint32_t fc = 0; fc < n1; fc += 64) {
         const uint32_t f = fc + l;
-        const int g = gw.find(incl1, f < n1 ? f : n1 - 1);
+        const int g = chunk_src(incl1, (uint32_t)ns1, fc, sm.mark[w]);
         const uint32_t ex1 = gw.bcast(incl1, g) - gw.bcast((uint32_t)ns1, g);
         const int32_t s10g = gw.bcast(s10, g);
         int32_t b = 0, bs = 0;
@@ -1056,7 +1094,7 @@ __device__ __forceinline__ uint32_t enum_t3(const EvDev &E, const Consts &K, con
         const uint32_t n2 = (uint32_t)__builtin_amdgcn_readlane((int)incl2, 63);
         for (uint32_t jc = 0; jc < n2; jc += 64) {
             const uint32_t j = jc + l;
-            const int src = gw.find(incl2, j < n2 ? j : n2 - 1);
+            const int src = chunk_src(incl2, nb, jc, sm.mark[w]);
             const uint32_t ex2 = gw.bcast(incl2, src) - gw.bcast(nb, src);
             const int32_t bb = gw.bcast(b, src), bbs = gw.bcast(bs, src);
             const int gg = gw.bcast(g, src);
@@ -1178,7 +1216,7 @@ hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, int grid,
 // list 64 at a time.  sink(ok, g, b, c, d, e, score, pos): g = lane of the
 // inner MD, pos = rank among the wave's accepted quintuplets.
 template <class F>
-__device__ __forceinline__ uint32_t enum_t5(const EvDev &E, const Consts &K, const SmT5 &sm,
+__device__ __forceinline__ uint32_t enum_t5(const EvDev &E, const Consts &K, SmT5 &sm,
                                             int w, int32_t nt1, int32_t t10, uint32_t incl1,
                                             F &&sink)
 {
@@ -1189,7 +1227,7 @@ __device__ __forceinline__ uint32_t enum_t5(const EvDev &E, const Consts &K, con
     uint32_t acc = 0;
     for (uint32_t fc = 0; fc < n1; fc += 64) {
         const uint32_t f = fc + l;
-        const int g = gw.find(incl1, f < n1 ? f : n1 - 1);
+        const int g = chunk_src(incl1, (uint32_t)nt1, fc, sm.mark[w]);
         const uint32_t ex1 = gw.bcast(incl1, g) - gw.bcast((uint32_t)nt1, g);
         const int32_t t10g = gw.bcast(t10, g);
         int32_t t1 = 0, cs = 0;
@@ -1204,7 +1242,7 @@ __device__ __forceinline__ uint32_t enum_t5(const EvDev &E, const Consts &K, con
         const uint32_t n2 = (uint32_t)__builtin_amdgcn_readlane((int)incl2, 63);
         for (uint32_t jc = 0; jc < n2; jc += 64) {
             const uint32_t j = jc + l;
-            const int src = gw.find(incl2, j < n2 ? j : n2 - 1);
+            const int src = chunk_src(incl2, nc, jc, sm.mark[w]);
             const uint32_t ex2 = gw.bcast(incl2, src) - gw.bcast(nc, src);
             const int32_t tt1 = gw.bcast(t1, src), tcs = gw.bcast(cs, src);
             const int gg = gw.bcast(g, src);
