@@ -73,16 +73,18 @@ __device__ __forceinline__ int chunk_src(uint32_t incl, uint32_t c, uint32_t jc,
     return wave_max_scan(v) - 1;
 }
 
-// inclusive scan over the 64 lanes of a wave
+// inclusive scan over the 64 lanes of a wave (the same DPP pattern as
+// wave_max_scan, adding; lanes outside a shift or a broadcast add zero)
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
-    const int l = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, 64);
-        if (l >= d) v += t;
-    }
-    return v;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);
+    return (uint32_t)x;
 }
 
 // smallest lane e with incl[e] > j (incl non-decreasing, j < incl[63]);
