@@ -108,31 +108,10 @@ __device__ __forceinline__ int wave_find(uint32_t incl, uint32_t j)
 template <int G>
 struct Grp {
     static constexpr int P = 64 / G;
-    static constexpr int LOG = G == 64 ? 6 : G == 32 ? 5 : G == 16 ? 4 : 3;
     int lane, g;
     __device__ __forceinline__ Grp() : lane(threadIdx.x & (G - 1)), g((threadIdx.x & 63) / G) {}
-    __device__ __forceinline__ uint32_t incl_scan(uint32_t v) const
-    {
-#pragma unroll
-        for (int d = 1; d < G; d <<= 1) {
-            const uint32_t t = __shfl_up(v, d, G);
-            if (lane >= d) v += t;
-        }
-        return v;
-    }
     template <class T>
     __device__ __forceinline__ T bcast(T v, int src) const { return __shfl(v, src, G); }
-    // smallest group lane e with incl[e] > j (incl non-decreasing in the group)
-    __device__ __forceinline__ int find(uint32_t incl, uint32_t j) const
-    {
-        int lo = 0, hi = G - 1;
-#pragma unroll
-        for (int it = 0; it < LOG; ++it) {
-            const int mid = (lo + hi) >> 1;
-            if (__shfl(incl, mid, G) > j) hi = mid; else lo = mid + 1;
-        }
-        return lo;
-    }
     // exclusive prefix of a per-group value over the wave's groups, and the sum
     __device__ __forceinline__ uint32_t wave_prefix(uint32_t v, uint32_t &sum) const
     {
