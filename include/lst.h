@@ -336,6 +336,23 @@ int lst_mlp_backward(lst_ctx *ctx, const float *params, const uint16_t *x, const
 int lst_mlp_adam(lst_ctx *ctx, float *params, const float *grad, float *m, float *v, int32_t step,
                  float lr, float beta1, float beta2, float eps, void *stream);
 
+/* n_steps Adam steps in one call.  Step i takes rows [order[i] * batch,
+ * (order[i] + 1) * batch) of x [n_rows][64] and y [n_rows] through
+ * lst_mlp_forward, lst_mlp_backward (its loss into losses[order[i]]) and
+ * lst_mlp_adam with step number first_step + 1 + i: the same kernels in the
+ * same order as those calls, hence the same results, with no return to the
+ * caller between steps.  order: host array of n_steps batch indices, each in
+ * 0 .. n_rows / batch - 1 (checked before anything is launched, else
+ * LST_E_INVALID).  Device buffers: logits [batch], h1 [batch][64] (BF16
+ * bits), h2 [batch][64], work (work_bytes >= lst_mlp_workspace_bytes(batch),
+ * else LST_E_CAPACITY), grad, m, v [LST_MLP_NPARAM], losses [n_rows / batch].
+ * Hyper-parameters as for lst_mlp_adam. */
+int lst_mlp_train_steps(lst_ctx *ctx, float *params, const uint16_t *x, const uint8_t *y,
+                        int64_t n_rows, int64_t batch, const int32_t *order, int32_t n_steps,
+                        int32_t first_step, float *logits, uint16_t *h1, float *h2, void *work,
+                        size_t work_bytes, float *grad, float *m, float *v, float *losses,
+                        float lr, float beta1, float beta2, float eps, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -768,6 +768,45 @@ int lst_mlp_adam(lst_ctx *c, float *params, const float *grad, float *m, float *
     return LST_OK;
 }
 
+int lst_mlp_train_steps(lst_ctx *c, float *params, const uint16_t *x, const uint8_t *y,
+                        int64_t n_rows, int64_t batch, const int32_t *order, int32_t n_steps,
+                        int32_t first_step, float *logits, uint16_t *h1, float *h2, void *work,
+                        size_t work_bytes, float *grad, float *m, float *v, float *losses,
+                        float lr, float beta1, float beta2, float eps, void *stream)
+{
+    int rc = mlp_args(c, batch, {params, x, y, logits, h1, h2, work, grad, m, v, losses});
+    if (rc) return rc;
+    if (batch < 1 || n_rows < batch || n_steps < 0 || first_step < 0 || (n_steps > 0 && !order))
+        return fail(c, LST_E_INVALID, "rows %lld, batch %lld, steps %d from %d", (long long)n_rows,
+                    (long long)batch, n_steps, first_step);
+    if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps > 0.0f))
+        return fail(c, LST_E_INVALID, "Adam hyper-parameters");
+    if (work_bytes < mlp_workspace_bytes(batch))
+        return fail(c, LST_E_CAPACITY, "workspace %zu bytes, %zu needed", work_bytes,
+                    mlp_workspace_bytes(batch));
+    const int64_t n_batches = n_rows / batch;
+    for (int32_t i = 0; i < n_steps; ++i)
+        if (order[i] < 0 || order[i] >= n_batches)
+            return fail(c, LST_E_INVALID, "order[%d] = %d outside 0..%lld", i, order[i],
+                        (long long)n_batches - 1);
+    const hipStream_t s = (hipStream_t)stream;
+    for (int32_t i = 0; i < n_steps; ++i) {
+        const int64_t r0 = (int64_t)order[i] * batch;
+        const uint16_t *xb = x + r0 * 64;
+        const uint8_t *yb = y + r0;
+        HIPCHK(c, mlp_forward(params, xb, batch, logits, h1, h2, s));
+        HIPCHK(c, mlp_backward(params, xb, yb, batch, logits, h1, h2, (float *)work, grad,
+                               losses + order[i], s));
+        // bias corrections exactly as lst_mlp_adam computes them
+        const int32_t step = first_step + 1 + i;
+        const float c1 = (float)(1.0 - std::pow((double)beta1, step));
+        const float c2 = (float)(1.0 - std::pow((double)beta2, step));
+        HIPCHK(c, mlp_adam(params, grad, m, v, lr, beta1, beta2, eps, c1, c2, s));
+    }
+    return LST_OK;
+}
+
 int lst_run_chain(lst_ctx *c, void *stream)
 {
     int rc;

@@ -100,6 +100,10 @@ _SIGS = {
                                         ctypes.c_size_t, _P, _P, _P]),
     "lst_mlp_adam": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_float,
                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
+    "lst_mlp_train_steps": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int64, _P,
+                                           ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P,
+                                           ctypes.c_size_t, _P, _P, _P, _P, ctypes.c_float,
+                                           ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -432,6 +436,19 @@ class Context:
                                           d(m, torch.float32), d(v, torch.float32), int(step),
                                           float(lr), float(beta1), float(beta2), float(eps),
                                           self._stream(stream)))
+
+    def mlp_train_steps(self, params, x, y, batch, order, first_step, logits, h1, h2, work, grad,
+                        m, v, losses, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        """len(order) Adam steps on the batches order[i] of x, y (see lst_mlp_train_steps)"""
+        d = self._dev
+        order = np.ascontiguousarray(order, np.int32)
+        self._check(self.lib.lst_mlp_train_steps(
+            self.h, d(params, torch.float32), d(x, torch.int16), d(y, torch.uint8), x.shape[0],
+            int(batch), _np_ptr(order) if len(order) else None, len(order), int(first_step),
+            d(logits, torch.float32), d(h1, torch.int16), d(h2, torch.float32),
+            d(work, torch.uint8), work.numel(), d(grad, torch.float32), d(m, torch.float32),
+            d(v, torch.float32), d(losses, torch.float32), float(lr), float(beta1), float(beta2),
+            float(eps), self._stream(stream)))
 
     def run_batch(self, offsets, x, y, z, module, sensor, stream=None, max_retry=8, graph=False):
         """Load, run the chain and grow the arena to the reported need on overflow

@@ -127,9 +127,20 @@ class Trainer:
         c.mlp_adam(self.P, self.grad, self.m, self.v, self.step_no, cf.lr, cf.beta1, cf.beta2,
                    cf.eps, s)
 
-    def epoch(self) -> float:
-        for k in self.rng.permutation(self.n_batches):
-            self.step(int(k))
+    def epoch(self, per_step: bool = False) -> float:
+        """one pass over the batches in a random order: all its steps in one
+        library call (per_step: one call per step, same results)"""
+        order = self.rng.permutation(self.n_batches)
+        if per_step:
+            for k in order:
+                self.step(int(k))
+        else:
+            cf = self.cfg
+            self.ctx.mlp_train_steps(self.P, self.x, self.y, self.b, order, self.step_no,
+                                     self.logits, self.h1, self.h2, self.work, self.grad, self.m,
+                                     self.v, self.losses, cf.lr, cf.beta1, cf.beta2, cf.eps,
+                                     self.stream)
+            self.step_no += len(order)
         self.stream.synchronize()
         return float(np.mean(self.losses.cpu().numpy()))
 

@@ -173,6 +173,48 @@ def test_adam_rejects_bad_hyperparameters(ctx_toy):
         ctx_toy.mlp_adam(P, P, P.clone(), P.clone(), 1, -1.0)
 
 
+def test_train_steps_in_one_call_equal_per_step_calls(ctx_toy):
+    """lst_mlp_train_steps runs the same kernels in the same order as one
+    forward, backward and Adam call per step: parameters, moments and losses
+    equal bit for bit after two epochs over a ragged training set (its tail
+    is left out), then the argument checks"""
+    from paper_2209_13711_amd import scorer as S
+    lst = _lst()
+    rng = np.random.default_rng(11)
+    n = 3 * 1024 + 517
+    F = _features(rng, n)
+    y = (rng.random(n) < 0.4).astype(np.uint8)
+    P0 = W.random_params(rng, bias=0.05)
+    cfg = S.TrainConfig(epochs=2, batch=1024, lr=3e-3, seed=5)
+    runs = []
+    for per_step in (True, False):
+        tr = S.Trainer(ctx_toy, F, y, P0, cfg)
+        losses = [tr.epoch(per_step=per_step) for _ in range(cfg.epochs)]
+        torch.cuda.synchronize()
+        runs.append((losses, tr.step_no, [t.cpu().numpy().view(np.uint32)
+                                          for t in (tr.P, tr.m, tr.v, tr.losses)]))
+    (l1, s1, a1), (l2, s2, a2) = runs
+    assert s1 == s2 == 2 * (n // 1024)
+    assert l1 == l2
+    assert all(np.array_equal(a, b) for a, b in zip(a1, a2))
+    assert not np.array_equal(a1[0], P0.view(np.uint32))
+    # order outside the batches, empty workspace, bad hyper-parameters
+    tr = S.Trainer(ctx_toy, F, y, P0, cfg)
+    args = (tr.P, tr.x, tr.y, tr.b)
+    rest = (tr.logits, tr.h1, tr.h2, tr.work, tr.grad, tr.m, tr.v, tr.losses)
+    with pytest.raises(lst.LSTError):
+        ctx_toy.mlp_train_steps(*args, [0, n // 1024], 0, *rest, 1e-3)
+    with pytest.raises(lst.LSTError):
+        ctx_toy.mlp_train_steps(*args, [-1], 0, *rest, 1e-3)
+    with pytest.raises(lst.LSTError):
+        ctx_toy.mlp_train_steps(*args, [0], 0, *rest[:3], tr.work[:16], *rest[4:], 1e-3)
+    with pytest.raises(lst.LSTError):
+        ctx_toy.mlp_train_steps(*args, [0], 0, *rest, -1.0)
+    ctx_toy.mlp_train_steps(*args, [], 0, *rest, 1e-3)      # no step: nothing happens
+    torch.cuda.synchronize()
+    assert np.array_equal(tr.P.cpu().numpy(), P0)
+
+
 # ---------------------------------------------------------------- scoring in the chain
 def _gap_threshold(lg, bound, q=0.5):
     """a threshold near the q-quantile of the logits with no logit within
