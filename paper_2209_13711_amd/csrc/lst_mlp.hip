@@ -202,6 +202,11 @@ __global__ void k_mlp_prepare(const float *F, const float *mean, const float *is
 // Row-local terms of the gradient of the mean BCE-with-logits loss:
 // g = (sigmoid(z) - y) / n, dz2 = g w3 [h2 > 0], dz1 = (dz2 W2) [h1 > 0],
 // with W2 the BF16-rounded weights the forward used; also the per-row loss.
+// A block takes ROWS_PER_BLOCK rows, ROW_GROUPS at a time: 64 lanes per row,
+// lane j writes dz2[r][j] and lane k sums dz1[r][k] over j = 0..63 in order,
+// so every output is coalesced and the sums run in a fixed order.
+constexpr int ROW_GROUPS = BLOCK / NH, ROWS_PER_BLOCK = 4 * ROW_GROUPS;
+
 __global__ __launch_bounds__(BLOCK) void k_mlp_rows(const float *P, const float *logits,
                                                     const uint8_t *y, int64_t n, const uint16_t *h1,
                                                     const float *h2, float *g, float *dz2,
@@ -209,27 +214,35 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_rows(const float *P, const float 
 {
     __shared__ float w2[NH][NH + 1];
     __shared__ float w3[NH];
+    __shared__ float d2[ROW_GROUPS][NH];
     for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) w2[i / NH][i % NH] = bf2f(f2bf(P[OFF_W2 + i]));
     for (int i = threadIdx.x; i < NH; i += blockDim.x) w3[i] = P[OFF_W3 + i];
-    __syncthreads();
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        const float z = logits[r];
-        const float yv = y[r] ? 1.0f : 0.0f;
-        loss_rows[r] = (z > 0.0f ? z : 0.0f) - z * yv + log1pf(expf(-fabsf(z)));
-        const float gr = (1.0f / (1.0f + expf(-z)) - yv) / (float)n;
-        g[r] = gr;
-        float d2[NH];
+    const int grp = threadIdx.x / NH, lane = threadIdx.x % NH;
+    for (int64_t b = (int64_t)blockIdx.x * ROWS_PER_BLOCK; b < n;
+         b += (int64_t)gridDim.x * ROWS_PER_BLOCK) {
+        __syncthreads();                     // weights loaded; d2 of the last rows consumed
+        for (int q = 0; q < ROWS_PER_BLOCK; q += ROW_GROUPS) {
+            const int64_t r = b + q + grp;
+            if (r < n) {
+                const float z = logits[r];
+                const float yv = y[r] ? 1.0f : 0.0f;
+                const float gr = (1.0f / (1.0f + expf(-z)) - yv) / (float)n;
+                if (lane == 0) {
+                    loss_rows[r] = (z > 0.0f ? z : 0.0f) - z * yv + log1pf(expf(-fabsf(z)));
+                    g[r] = gr;
+                }
+                const float dj = h2[r * NH + lane] > 0.0f ? gr * w3[lane] : 0.0f;
+                d2[grp][lane] = dj;
+                dz2[r * NH + lane] = dj;
+            }
+            __syncthreads();
+            if (r < n) {
+                float acc = 0.0f;
 #pragma unroll
-        for (int j = 0; j < NH; ++j) {
-            d2[j] = h2[r * NH + j] > 0.0f ? gr * w3[j] : 0.0f;
-            dz2[r * NH + j] = d2[j];
-        }
-        for (int k = 0; k < NH; ++k) {
-            float acc = 0.0f;
-#pragma unroll
-            for (int j = 0; j < NH; ++j) acc += d2[j] * w2[j][k];
-            dz1[r * NH + k] = h1[r * KP + k] != 0 ? acc : 0.0f;
+                for (int j = 0; j < NH; ++j) acc += d2[grp][j] * w2[j][lane];
+                dz1[r * NH + lane] = h1[r * KP + lane] != 0 ? acc : 0.0f;
+            }
+            __syncthreads();                 // d2 is rewritten by the next rows
         }
     }
 }
@@ -428,8 +441,8 @@ hipError_t mlp_backward(const float *P, const uint16_t *X, const uint8_t *y, int
                         float *grad, float *loss, hipStream_t s)
 {
     float *g = work, *lrow = g + n, *dz2 = lrow + n, *dz1 = dz2 + n * NH, *part = dz1 + n * NH;
-    hipLaunchKernelGGL(k_mlp_rows, dim3(grid_of(n, BLOCK)), dim3(BLOCK), 0, s, P, logits, y, n, h1,
-                       h2, g, dz2, dz1, lrow);
+    hipLaunchKernelGGL(k_mlp_rows, dim3(grid_of(n, ROWS_PER_BLOCK)), dim3(BLOCK), 0, s, P, logits, y,
+                       n, h1, h2, g, dz2, dz1, lrow);
     hipLaunchKernelGGL(k_mlp_grad_parts, dim3((NPARAM + BLOCK - 1) / BLOCK, GRAD_CHUNKS), dim3(BLOCK),
                        0, s, X, n, h1, h2, g, dz2, dz1, part);
     hipLaunchKernelGGL(k_mlp_grad_reduce, dim3((NPARAM + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s,
