@@ -247,6 +247,45 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_rows(const float *P, const float 
     }
 }
 
+// Sums over the rows r0..r1-1 in row order of a(r) b(r) (or of a(r)):
+// GP_U rows' operands are loaded before they are added, so GP_U loads are in
+// flight at once; the additions keep the row order.
+constexpr int GP_U = 16;
+
+template <class A, class B>
+__device__ __forceinline__ float rows_dot(int64_t r0, int64_t r1, A a, B b)
+{
+    float acc = 0.0f;
+    for (int64_t rb = r0; rb < r1; rb += GP_U) {
+        float x[GP_U], y[GP_U];
+#pragma unroll
+        for (int u = 0; u < GP_U; ++u) {
+            const int64_t r = rb + u < r1 ? rb + u : r1 - 1;   // rows past the end: not added
+            x[u] = a(r);
+            y[u] = b(r);
+        }
+#pragma unroll
+        for (int u = 0; u < GP_U; ++u)
+            if (rb + u < r1) acc += x[u] * y[u];
+    }
+    return acc;
+}
+
+template <class A>
+__device__ __forceinline__ float rows_sum(int64_t r0, int64_t r1, A a)
+{
+    float acc = 0.0f;
+    for (int64_t rb = r0; rb < r1; rb += GP_U) {
+        float x[GP_U];
+#pragma unroll
+        for (int u = 0; u < GP_U; ++u) x[u] = a(rb + u < r1 ? rb + u : r1 - 1);
+#pragma unroll
+        for (int u = 0; u < GP_U; ++u)
+            if (rb + u < r1) acc += x[u];
+    }
+    return acc;
+}
+
 // part[c][p] = sum over the rows of chunk c (in row order) of parameter p's terms
 __global__ __launch_bounds__(BLOCK) void k_mlp_grad_parts(const uint16_t *X, int64_t n,
                                                           const uint16_t *h1, const float *h2,
@@ -259,24 +298,27 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_grad_parts(const uint16_t *X, int
     const int64_t len = (n + GRAD_CHUNKS - 1) / GRAD_CHUNKS;
     const int64_t r0 = c * len < n ? c * len : n;
     const int64_t r1 = r0 + len < n ? r0 + len : n;
-    float acc = 0.0f;
+    float acc;
     if (p < OFF_B1) {                       // dW1[j][k] = sum dz1[j] x[k]
         const int j = p / NIN, k = p % NIN;
-        for (int64_t r = r0; r < r1; ++r) acc += dz1[r * NH + j] * bf2f(X[r * KP + k]);
+        acc = rows_dot(r0, r1, [&](int64_t r) { return dz1[r * NH + j]; },
+                       [&](int64_t r) { return bf2f(X[r * KP + k]); });
     } else if (p < OFF_W2) {                // db1[j] = sum dz1[j]
         const int j = p - OFF_B1;
-        for (int64_t r = r0; r < r1; ++r) acc += dz1[r * NH + j];
+        acc = rows_sum(r0, r1, [&](int64_t r) { return dz1[r * NH + j]; });
     } else if (p < OFF_B2) {                // dW2[j][k] = sum dz2[j] h1[k]
         const int j = (p - OFF_W2) / NH, k = (p - OFF_W2) % NH;
-        for (int64_t r = r0; r < r1; ++r) acc += dz2[r * NH + j] * bf2f(h1[r * KP + k]);
+        acc = rows_dot(r0, r1, [&](int64_t r) { return dz2[r * NH + j]; },
+                       [&](int64_t r) { return bf2f(h1[r * KP + k]); });
     } else if (p < OFF_W3) {                // db2[j] = sum dz2[j]
         const int j = p - OFF_B2;
-        for (int64_t r = r0; r < r1; ++r) acc += dz2[r * NH + j];
+        acc = rows_sum(r0, r1, [&](int64_t r) { return dz2[r * NH + j]; });
     } else if (p < OFF_B3) {                // dw3[j] = sum g h2[j]
         const int j = p - OFF_W3;
-        for (int64_t r = r0; r < r1; ++r) acc += g[r] * h2[r * NH + j];
+        acc = rows_dot(r0, r1, [&](int64_t r) { return g[r]; },
+                       [&](int64_t r) { return h2[r * NH + j]; });
     } else {                                // db3 = sum g
-        for (int64_t r = r0; r < r1; ++r) acc += g[r];
+        acc = rows_sum(r0, r1, [&](int64_t r) { return g[r]; });
     }
     part[(int64_t)c * NPARAM + p] = acc;
 }
