@@ -61,12 +61,26 @@ struct MlpW {
     float b3;
 };
 
+// Every kernel that stages the weights runs BLOCK threads: each thread loads
+// its WPT elements of each matrix before it converts them, so the loads are
+// in flight together rather than one after the other.
+constexpr int WPT = NH * KP / BLOCK;
+static_assert(NH * KP % BLOCK == 0 && NH * NH == NH * KP, "weight staging");
+
 __device__ __forceinline__ void load_weights(const float *P, MlpW &w)
 {
-    for (int i = threadIdx.x; i < NH * KP; i += blockDim.x) {
-        const int o = i / KP, k = i % KP;
-        w.w1[o][k] = k < NIN ? f2bf(P[OFF_W1 + o * NIN + k]) : (uint16_t)0;
-        w.w2[o][k] = f2bf(P[OFF_W2 + o * NH + k]);
+    float a[WPT], b[WPT];
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+        const int i = threadIdx.x + u * BLOCK, o = i / KP, k = i % KP;
+        a[u] = k < NIN ? P[OFF_W1 + o * NIN + k] : 0.0f;
+        b[u] = P[OFF_W2 + o * NH + k];
+    }
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+        const int i = threadIdx.x + u * BLOCK, o = i / KP, k = i % KP;
+        w.w1[o][k] = k < NIN ? f2bf(a[u]) : (uint16_t)0;
+        w.w2[o][k] = f2bf(b[u]);
     }
     for (int i = threadIdx.x; i < NH; i += blockDim.x) {
         w.b1[i] = P[OFF_B1 + i];
@@ -215,7 +229,16 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_rows(const float *P, const float 
     __shared__ float w2[NH][NH + 1];
     __shared__ float w3[NH];
     __shared__ float d2[ROW_GROUPS][NH];
-    for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) w2[i / NH][i % NH] = bf2f(f2bf(P[OFF_W2 + i]));
+    {
+        float b[WPT];   // all loads in flight, then the BF16 rounding
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) b[u] = P[OFF_W2 + threadIdx.x + u * BLOCK];
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            const int i = threadIdx.x + u * BLOCK;
+            w2[i / NH][i % NH] = bf2f(f2bf(b[u]));
+        }
+    }
     for (int i = threadIdx.x; i < NH; i += blockDim.x) w3[i] = P[OFF_W3 + i];
     const int grp = threadIdx.x / NH, lane = threadIdx.x % NH;
     for (int64_t b = (int64_t)blockIdx.x * ROWS_PER_BLOCK; b < n;
