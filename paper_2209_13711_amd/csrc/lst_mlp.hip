@@ -219,7 +219,7 @@ __global__ void k_mlp_prepare(const float *F, const float *mean, const float *is
 // A block takes ROWS_PER_BLOCK rows, ROW_GROUPS at a time: 64 lanes per row,
 // lane j writes dz2[r][j] and lane k sums dz1[r][k] over j = 0..63 in order,
 // so every output is coalesced and the sums run in a fixed order.
-constexpr int ROW_GROUPS = BLOCK / NH, ROWS_PER_BLOCK = 4 * ROW_GROUPS;
+constexpr int ROW_GROUPS = BLOCK / NH, ROWS_PER_BLOCK = 2 * ROW_GROUPS;
 
 __global__ __launch_bounds__(BLOCK) void k_mlp_rows(const float *P, const float *logits,
                                                     const uint8_t *y, int64_t n, const uint16_t *h1,
@@ -350,8 +350,12 @@ __global__ void k_mlp_grad_reduce(const float *part, float *grad)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= NPARAM) return;
+    float v[GRAD_CHUNKS];   // all chunks' partials in flight, then added in chunk order
+#pragma unroll
+    for (int c = 0; c < GRAD_CHUNKS; ++c) v[c] = part[c * NPARAM + p];
     float acc = 0.0f;
-    for (int c = 0; c < GRAD_CHUNKS; ++c) acc += part[c * NPARAM + p];
+#pragma unroll
+    for (int c = 0; c < GRAD_CHUNKS; ++c) acc += v[c];
     grad[p] = acc;
 }
 
@@ -360,7 +364,18 @@ __global__ void k_mlp_loss(const float *loss_rows, int64_t n, float *loss)
 {
     __shared__ float part[BLOCK];
     float acc = 0.0f;
-    for (int64_t r = threadIdx.x; r < n; r += blockDim.x) acc += loss_rows[r];
+    // GP_U rows per thread in flight at once, added in row order
+    for (int64_t rb = threadIdx.x; rb < n; rb += (int64_t)GP_U * blockDim.x) {
+        float v[GP_U];
+#pragma unroll
+        for (int u = 0; u < GP_U; ++u) {
+            const int64_t r = rb + (int64_t)u * blockDim.x;
+            v[u] = r < n ? loss_rows[r] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < GP_U; ++u)
+            if (rb + (int64_t)u * blockDim.x < n) acc += v[u];
+    }
     part[threadIdx.x] = acc;
     __syncthreads();
     for (int s = BLOCK / 2; s > 0; s >>= 1) {
