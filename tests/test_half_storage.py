@@ -9,7 +9,8 @@ each FP16 coordinate is within half an ulp of 2^-8 cm (19.5 um) of its
 FP32 value.  Rounding the global coordinates to FP16 instead costs up to
 2^-6 cm per coordinate at r = 110 cm and is shown for contrast.
 
-Measured (8 events, seeds 300..307): FP16 local storage changes 0.7 % of
+Measured on 8 events (seeds 300..307; the tests run the first four): FP16
+local storage changes 0.7 % of
 the mini-doublets, 2.4 % of the segments, 1 % of the triplets, 0.7 % of the
 quintuplets and 6 % of the kept quintuplets (mostly which of two near-equal
 duplicates survives); efficiency 97.01 % -> 96.93 %, fake rate unchanged.
