@@ -80,6 +80,8 @@ def _load():
         getattr(lib, f).restype = ctypes.c_int
         getattr(lib, f).argtypes = [P, P, P, P]
     lib.orc_consts.argtypes = [P, P]
+    lib.orc_eval_margin.restype = ctypes.c_double
+    lib.orc_eval_margin.argtypes = [P, ctypes.c_int, P, P]
     _lib = lib
     return lib
 
@@ -225,3 +227,13 @@ class Oracle:
 
     def eval_t5_features(self, mods, hits):
         return self._eval_f(self._lib.orc_eval_t5_features, 5, mods, hits)
+
+    def eval_margin(self, kind: int, mods, hits) -> float:
+        """FP64 margin the chain records for one candidate of ``kind`` (MD,
+        SEG, T3, T5) built from the given MDs: the relative distance to
+        threshold of the cut that decides it (infinite when two cuts fail)."""
+        n = {MD: 1, SEG: 2, T3: 3, T5: 5}[kind]
+        mods = np.ascontiguousarray(np.atleast_1d(mods), np.int32)
+        hits = np.ascontiguousarray(hits, np.float32).reshape(-1)
+        assert mods.shape[0] == n and hits.shape[0] == 6 * n
+        return float(self._lib.orc_eval_margin(self._h, int(kind), _ptr(mods), _ptr(hits)))

@@ -852,3 +852,48 @@ int orc_eval_t5(const orc *o, const int32_t *mods5, const float *hits30, double 
     out[15] = ax.chi2p; out[16] = ax.chi2z; out[17] = ax.score;
     return pass;
 }
+
+/* FP64 margin (cut_margin) of one candidate of kind ORC_MD..ORC_T5 built from
+ * the given MDs, as the chain would record it: the FP32 decision picks which
+ * cuts can flip the outcome, the FP64 re-evaluation measures their relative
+ * distance to threshold (infinite when two or more cuts fail).  For ORC_MD,
+ * mods has one entry and hits six floats (lower, upper hit). */
+double orc_eval_margin(const orc *o, int kind, const int32_t *mods, const float *hits)
+{
+    CUTREC cf, cd;
+    if (kind == ORC_MD) {
+        MDREC md;
+        make_md(o, mods[0], &hits[0], &hits[3], &md, &cf, &cd);
+        return cut_margin(&cf, &cd);
+    }
+    MDREC md[5];
+    if (kind == ORC_SEG) {
+        eval_mds(o, 2, mods, hits, md);
+        float z0f, kOf;
+        double z0d, kOd;
+        seg_cut_f(&o->K, &md[0], &md[1], &cf, &z0f, &kOf);
+        seg_cut_d(&o->K, &md[0], &md[1], &cd, &z0d, &kOd);
+        return cut_margin(&cf, &cd);
+    }
+    if (kind == ORC_T3) {
+        eval_mds(o, 3, mods, hits, md);
+        float kf;
+        double kd;
+        t3_cut_f(&o->K, &md[0], &md[1], &md[2], &cf, &kf, NULL);
+        t3_cut_d(&o->K, &md[0], &md[1], &md[2], &cd, &kd, NULL);
+        return cut_margin(&cf, &cd);
+    }
+    if (kind == ORC_T5) {
+        eval_mds(o, 5, mods, hits, md);
+        CUTREC c3;
+        float kin, kout;
+        t3_cut_f(&o->K, &md[0], &md[1], &md[2], &c3, &kin, NULL);
+        t3_cut_f(&o->K, &md[2], &md[3], &md[4], &c3, &kout, NULL);
+        const MDREC *P[5] = {&md[0], &md[1], &md[2], &md[3], &md[4]};
+        T5AUX af, ad;
+        t5_cut_f(&o->K, P, kin, kout, &cf, &af);
+        t5_cut_d(&o->K, P, kin, kout, &cd, &ad);
+        return cut_margin(&cf, &cd);
+    }
+    return NAN;
+}

@@ -89,6 +89,11 @@ int orc_eval_t5(const orc *o, const int32_t *mods5, const float *hits30, double 
 int orc_eval_t3_features(const orc *o, const int32_t *mods3, const float *hits18, float *out40);
 int orc_eval_t5_features(const orc *o, const int32_t *mods5, const float *hits30, float *out40);
 
+/* FP64 decision margin of one candidate (kind ORC_MD..ORC_T5; ORC_MD takes one
+ * module and six floats): relative distance to threshold of the cut that
+ * decides it, infinite when two or more cuts fail */
+double orc_eval_margin(const orc *o, int kind, const int32_t *mods, const float *hits);
+
 /* derived FP32 constants (for inspection): kmax, klim, kh, tolu, tolv, tolkc, epsak */
 void orc_consts(const orc *o, float *out7);
 

@@ -91,8 +91,9 @@ __device__ __forceinline__ bool md_accept(const Consts &K, const ModF &m, float 
         float Sm = (sp * ca) - (cp * a);
         hi = mx(Dlo * Sp, Dhi * Sp);
         lo = mn(Dlo * Sm, Dhi * Sm);
+        // the step's coarse (radial) component lies between Dlo cp and Dhi cp
         zc = (0.5f * (Dlo + Dhi)) * cp;
-        hz = (0.5f * (Dhi - Dlo)) + K.tolv;
+        hz = ((0.5f * (Dhi - Dlo)) * cp) + K.tolv;
         sv = sp;
     }
     float c0 = 0.5f * (hi + lo);

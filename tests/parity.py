@@ -29,8 +29,13 @@ def compare(gpu: dict, ref, verbose=True):
             for t in d:
                 if any(tuple(t[a:b]) in diffs[up] for a, b in parts):
                     casc.add(t)
-        if kind == 4 and (diffs[3] or d):
-            casc = set(d) if diffs[3] else set()
+        if kind == 4:
+            # duplicate removal decides a quintuplet from the quintuplets that
+            # share one of its hits (one pass), so a kept-set difference is a
+            # cascade only when the quintuplet itself, or one sharing a hit
+            # with it, differs between the two sides
+            dhits = {h for q in diffs[3] for h in q}
+            casc = {t for t in d if t in diffs[3] or (set(t) & dhits)}
         near_d = {t for t in d if t in near}
         unexplained = d - near_d - casc
         report[KINDS[kind]] = dict(gpu=len(g), oracle=len(o), mismatch=len(d), near=len(near_d),
