@@ -58,6 +58,15 @@ def measured_traffic(kernel):
     return float(kv[key])
 
 
+def assert_clean(ctx, n_events=None):
+    """After a timed leg: every event's counts come back without an error
+    (a time-out of a kernel-side wait raises LST_E_FAULT from the getter) and
+    with no error flag raised, so no figure is taken from broken outputs."""
+    for e in range(ctx.n_events if n_events is None else n_events):
+        c = ctx.counts(e)
+        assert c["error_flags"] == 0 and c["overflow_mask"] == 0, (e, c)
+
+
 def copy_bandwidth(lst, torch, reps=10):
     """Achievable HBM bandwidth of the library's STREAM-like copy (read+write)."""
     src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
@@ -147,10 +156,12 @@ def batched(lst, torch, E, G, PR, evs, steps=20, cache=None, compare=True):
 
     ctx.load_hits(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
     t_graph = timeit(lambda: ctx.run_chain_graph(stream), steps)
+    assert_clean(ctx)
     kept = sum(ctx.counts(e)["n_t5_kept"] for e in range(n_events))
     t_pers = t_single = float("nan")
     if compare:
         t_pers = timeit(lambda: ctx.run_chain_persistent(stream), steps)
+        assert_clean(ctx)
         kept_p = sum(ctx.counts(e)["n_t5_kept"] for e in range(n_events))
         assert kept == kept_p, "persistent chain changed the result"
         # one event per launch, same events
@@ -161,6 +172,7 @@ def batched(lst, torch, E, G, PR, evs, steps=20, cache=None, compare=True):
             single.load_hits(np.array([0, ev.n_hits], np.int32), ev.x, ev.y, ev.z, ev.module,
                              ev.sensor)
             per_event.append(timeit(lambda: single.run_chain_graph(stream), 5))
+            assert_clean(single)
         t_single = float(np.mean(per_event))
     # roofline of the segment stage on the batch: algorithmic bytes over the
     # tuner's per-stage median (HIP events around the stage on the stream)
@@ -334,6 +346,7 @@ def scored(lst, torch, train, evs, steps=50, base_cfg=4):
                 ctx.run_chain_graph(stream)
             torch.cuda.synchronize()
             per.append((time.perf_counter() - t0) / steps)
+            assert_clean(ctx)
         return 1.0 / float(np.mean(per))
 
     # scoring kernels alone: HIP events around each scoring step on the launch stream
@@ -410,6 +423,8 @@ def multistream(lst, torch, G, PR, evs, n_streams=8, rounds=3, geometry="barrel_
         run_all()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    for c in ctxs:
+        assert_clean(c)
     return {"streams": n_streams, "events": len(evs), "events_per_s": rounds * len(evs) / dt}
 
 
@@ -432,6 +447,7 @@ def pu200_concurrent(lst, torch, E, G, PR, evs, steps=20):
         ctx.run_chain_graph(stream)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    assert_clean(ctx)
     kept = int(sum(ctx.counts(e)["n_t5_kept"] for e in range(len(evs))))
     del ctx
     return {"workload": f"{len(evs)} PU200-like events (config 2, seeds 100..{99 + len(evs)})",
@@ -503,6 +519,7 @@ def stress(lst, torch, E, G, PR, evs, model=None, steps=10):
             ctx.run_chain_graph(stream)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
+        assert_clean(ctx)
         tot = dict(n_obj=0, n_findable=0, n_found=0, n_fake=0, n_dup=0, n_pure=0)
         for e, ev in enumerate(evs):
             kept = ctx.objects(e, lst.LST_T5_KEPT)
@@ -631,6 +648,7 @@ def main():
     stage_ms = {name: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1])
                                      for k in range(args.steps)]))
                 for i, (name, _) in enumerate(stages)}
+    assert_clean(ctx)
     c2 = ctx.counts(0)   # after the graph replays
     assert c2["n_t5_kept"] == cnt["n_t5_kept"], "result changed between runs"
 

@@ -39,6 +39,8 @@ extern "C" {
 #define LST_E_CAPACITY (-3) /* an output did not fit its capacity; counts report the need */
 #define LST_E_HIP (-4)      /* HIP runtime error */
 #define LST_E_NOMEM (-5)    /* host or device allocation failed */
+#define LST_E_FAULT (-6)    /* a kernel-side wait timed out (error_flags bit 1 or 2):
+                               the chain's outputs are unusable */
 
 /* object kinds and their tuple widths (hit indices per object) */
 enum lst_kind {
@@ -108,7 +110,11 @@ typedef struct {
  * T3, T5) ran out of capacity; error_flags bit 0 = a hit with an invalid
  * module or sensor id was skipped, bit 1 = a persistent-chain barrier timed
  * out, bit 2 = the hit-grouping scan timed out waiting for a predecessor tile
- * (neither should ever happen; the outputs are then unusable). */
+ * (neither should ever happen).  With bit 1 or 2 set the outputs are unusable:
+ * lst_get_counts fills *out (so the flags can be read) and returns
+ * LST_E_FAULT, and every getter of objects, scores, logits or features
+ * returns LST_E_FAULT; the bin counts are cleared so that the next chain
+ * starts from a clean state. */
 typedef struct {
     int64_t n_hits, n_md, n_seg, n_t3, n_t5, n_t5_kept;
     int64_t cand_md, cand_seg, cand_t3, cand_t5;
@@ -165,7 +171,10 @@ int lst_load_hits(lst_ctx *ctx, int32_t n_events, const int32_t *hit_offsets, co
  * lst_run_dedup     removal of quintuplets sharing hits (Sec. 2.1: objects
  *                   must not share hits): a quintuplet survives when, for each
  *                   of its hits, it has the smallest (score, hit tuple) key
- * lst_run_chain     all of the above in one call. */
+ * lst_run_chain     all of the above in one call.
+ * lst_run_sort may start a chain at any point after lst_load_hits; every
+ * other stage runs exactly once, right after its predecessor (a repeated or
+ * skipped stage returns LST_E_STATE and changes nothing). */
 int lst_run_sort(lst_ctx *ctx, void *stream);
 int lst_run_md(lst_ctx *ctx, void *stream);
 int lst_run_segments(lst_ctx *ctx, void *stream);
@@ -181,8 +190,15 @@ int lst_run_chain(lst_ctx *ctx, void *stream);
 int lst_run_chain_graph(lst_ctx *ctx, void *stream);
 
 /* Synchronise `stream`, then report event `event` (0..n_events-1).  Returns
- * LST_E_CAPACITY when any stage overflowed (counts still filled). */
+ * LST_E_FAULT when a kernel-side wait timed out and LST_E_CAPACITY when any
+ * stage overflowed (counts still filled in both cases). */
 int lst_get_counts(lst_ctx *ctx, int32_t event, lst_counts *out, void *stream);
+
+/* Error-path hook for tests of the callers' handling of LST_E_FAULT: ORs
+ * `bits` (error_flags bits 1 and 2 only) into the context's device error
+ * word with a host-to-device copy after synchronising `stream`; no kernel
+ * runs.  The next chain clears the word.  Needs a chain to have run. */
+int lst_raise_error_flags(lst_ctx *ctx, int32_t bits, void *stream);
 
 /* Synchronise `stream` and copy the objects of `kind` of `event` to out_host
  * (int32, width per lst_kind, capacity cap_tuples tuples).  *n_tuples is set

@@ -569,10 +569,17 @@ int lst_load_hits(lst_ctx *c, int32_t n_events, const int32_t *hit_offsets, cons
 }
 
 // ---------------------------------------------------------------- stages
+// Stage calls run in chain order.  Hit grouping (s = 1) may start a chain at
+// any point after hits are loaded: it clears every object counter.  Each
+// object stage and duplicate removal (s = 2..6) runs exactly once, right after
+// its predecessor: running one again would append to the output ranges
+// its first run reserved, and running it after a later stage would mix two
+// chains' objects.
 static int need_stage(lst_ctx *c, int s, const char *what)
 {
     if (!c) return LST_E_INVALID;
-    if (c->stage < s) return fail(c, LST_E_STATE, "%s called out of order", what);
+    if (c->stage < s || (s >= 2 && c->stage != s))
+        return fail(c, LST_E_STATE, "%s called out of order (chain at step %d)", what, c->stage);
     c->counts_valid = false;
     if (s <= 6) c->features_valid = false;
     if (s <= 5) c->t3_features_valid = false;
@@ -1033,6 +1040,23 @@ static int read_shards(lst_ctx *c, ShardCounts &S)
     return LST_OK;
 }
 
+// Error bits 1 (a persistent-chain grid barrier timed out) and 2 (the
+// grouping scan timed out) make the outputs unusable and can leave bin
+// counts non-zero, while the grouping of the next chain relies on them being
+// zero: the bins are cleared here.  The error word itself stays set until the
+// next chain clears it, so every getter keeps refusing until then.
+static int check_fault(lst_ctx *c, uint32_t err)
+{
+    if (!(err & 6u)) return LST_OK;
+    char *b = (char *)c->E.bcnt;
+    const size_t n = (size_t)((char *)c->zero_base + c->zero_bytes - b);
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, launch_zero(c->E, b, n, nullptr));
+    HIPCHK(c, hipDeviceSynchronize());
+    return fail(c, LST_E_FAULT, "a kernel-side wait timed out (error flags %u): the outputs are unusable",
+                err);
+}
+
 // Per-event statistics, reduced on the host from the device arrays (the
 // reporting path; the stage kernels carry no statistics atomics).
 static int compute_counts(lst_ctx *c)
@@ -1123,11 +1147,27 @@ int lst_get_counts(lst_ctx *c, int32_t event, lst_counts *out, void *stream)
     if (rc) return rc;
     if (!c->counts_valid && (rc = compute_counts(c))) return rc;
     *out = c->counts[event];
+    if ((rc = check_fault(c, (uint32_t)out->error_flags))) return rc;
     if (out->overflow_mask)
         return fail(c, LST_E_CAPACITY,
                     "capacity overflow (mask %d): MD %lld SEG %lld T3 %lld T5 %lld needed",
                     out->overflow_mask, (long long)out->n_md, (long long)out->n_seg,
                     (long long)out->n_t3, (long long)out->n_t5);
+    return LST_OK;
+}
+
+int lst_raise_error_flags(lst_ctx *c, int32_t bits, void *stream)
+{
+    if (!c) return LST_E_INVALID;
+    if (bits & ~6) return fail(c, LST_E_INVALID, "only error bits 1 and 2 may be raised (%d)", bits);
+    if (c->stage < 2) return fail(c, LST_E_STATE, "no chain has run");
+    int rc = sync_stream(c, stream);
+    if (rc) return rc;
+    uint32_t w = 0;
+    HIPCHK(c, hipMemcpy(&w, &c->E.gc[GC_ERROR], sizeof(w), hipMemcpyDeviceToHost));
+    w |= (uint32_t)bits;
+    HIPCHK(c, hipMemcpy(&c->E.gc[GC_ERROR], &w, sizeof(w), hipMemcpyHostToDevice));
+    c->counts_valid = false;
     return LST_OK;
 }
 
@@ -1143,7 +1183,7 @@ int lst_get_objects(lst_ctx *c, int32_t event, int32_t kind, int32_t *out, int64
     if (rc) return rc;
     const EvDev &E = c->E;
     ShardCounts S;
-    if ((rc = read_shards(c, S))) return rc;
+    if ((rc = read_shards(c, S)) || (rc = check_fault(c, S.gc[GC_ERROR]))) return rc;
     if (S.gc[GC_OVERFLOW])
         return fail(c, LST_E_CAPACITY, "capacity overflow (mask %u)", S.gc[GC_OVERFLOW]);
     const size_t n_sorted = S.gc[GC_N_SORTED];
@@ -1217,7 +1257,7 @@ static int obj_field(lst_ctx *c, int type, int32_t event, const T *src, int widt
     if (rc) return rc;
     const EvDev &E = c->E;
     ShardCounts S;
-    if ((rc = read_shards(c, S))) return rc;
+    if ((rc = read_shards(c, S)) || (rc = check_fault(c, S.gc[GC_ERROR]))) return rc;
     if (S.gc[GC_OVERFLOW])
         return fail(c, LST_E_CAPACITY, "capacity overflow (mask %u)", S.gc[GC_OVERFLOW]);
     std::vector<int32_t> m0, slot;
@@ -1302,7 +1342,7 @@ static int chain_checksum(lst_ctx *c, uint64_t *out)
     ShardCounts S;
     int rc = read_shards(c, S);
     if (rc) return rc;
-    if (S.gc[GC_OVERFLOW] || S.gc[GC_ERROR] & 2)
+    if (S.gc[GC_OVERFLOW] || S.gc[GC_ERROR] & 6)
         return fail(c, LST_E_CAPACITY, "tuning run overflowed or timed out (%u, %u)", S.gc[GC_OVERFLOW], S.gc[GC_ERROR]);
     std::vector<int32_t> sorig, hlo, hup, slot, m[5];
     std::vector<uint8_t> keep;

@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "liblst.so")
 
 LST_OK, LST_E_INVALID, LST_E_STATE, LST_E_CAPACITY, LST_E_HIP, LST_E_NOMEM = 0, -1, -2, -3, -4, -5
+LST_E_FAULT = -6
 LST_MD, LST_SEG, LST_T3, LST_T5, LST_T5_KEPT = 0, 1, 2, 3, 4
 WIDTH = {LST_MD: 2, LST_SEG: 4, LST_T3: 6, LST_T5: 10, LST_T5_KEPT: 10}
 LST_N_PARAMS = 14
@@ -70,6 +71,7 @@ _SIGS = {
     "lst_run_chain": (ctypes.c_int, [_P, _P]),
     "lst_run_chain_graph": (ctypes.c_int, [_P, _P]),
     "lst_get_counts": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(lst_counts), _P]),
+    "lst_raise_error_flags": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "lst_get_objects": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64,
                                        ctypes.POINTER(ctypes.c_int64), _P]),
     "lst_get_t5_scores": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64,
@@ -321,6 +323,10 @@ class Context:
         d = c.as_dict()
         d["rc"] = rc
         return d
+
+    def raise_error_flags(self, bits, stream=None):
+        """test hook: OR error bits 1/2 into the device error word (lst_raise_error_flags)"""
+        self._check(self.lib.lst_raise_error_flags(self.h, int(bits), self._stream(stream)))
 
     def objects(self, event, kind, stream=None) -> np.ndarray:
         n = ctypes.c_int64(0)

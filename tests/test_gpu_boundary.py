@@ -1,0 +1,122 @@
+"""Boundary behaviour of the library on the GPU: non-finite hit coordinates,
+stage calls out of chain order, and the error path of kernel-side
+time-outs (raised from the host; no kernel is made to time out)."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import events as E
+from synth import geometry as G
+from synth import params as PR
+from tests.parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(cid=1, event=0):
+    import paper_2209_13711_amd as lst
+    cfg = E.CONFIGS[cid]
+    geo = G.get(cfg.geometry)
+    params = PR.make(w=cfg.window)
+    ev = E.generate(cid, event)
+    ctx = lst.Context(params, geo.f32, geo.i32, device=0)
+    return lst, ctx, oracle.Oracle(params, geo.f32, geo.i32), ev
+
+
+@pytest.mark.parametrize("cid", [1, 2])
+def test_non_finite_hits_match_oracle(cid):
+    """NaN and +-Inf coordinates fail every comparison they enter, on both
+    sides alike: the chain equals the oracle's, and no object of any kind
+    holds a non-finite hit."""
+    lst, ctx, orc, ev = _setup(cid, 3)
+    rng = np.random.default_rng(11)
+    x, y, z = ev.x.copy(), ev.y.copy(), ev.z.copy()
+    idx = rng.choice(ev.n_hits, 90, replace=False)
+    x[idx[:30]] = np.nan
+    y[idx[30:60]] = np.inf
+    z[idx[60:75]] = -np.inf
+    x[idx[75:]] = np.nan
+    z[idx[75:]] = np.inf
+    print(f"case non-finite cfg{cid} hits {ev.n_hits}", flush=True)
+    ctx.run_batch(np.array([0, ev.n_hits], np.int32), x, y, z, ev.module, ev.sensor)
+    got = {k: ctx.objects(0, k) for k in range(5)}
+    ref = orc.run(x, y, z, ev.module, ev.sensor)
+    assert_parity(got, ref)
+    bad = set(idx.tolist())
+    for k in range(5):
+        assert not any(h in bad for h in got[k].reshape(-1).tolist()), k
+    assert ctx.counts(0)["error_flags"] == 0
+
+
+def test_stage_calls_out_of_order_are_refused():
+    """Each object stage runs once, right after its predecessor; a call out
+    of that order returns LST_E_STATE and changes nothing, so the chain that
+    finally runs in order equals the oracle's."""
+    lst, ctx, orc, ev = _setup(1, 2)
+    ctx.run_event(ev)                        # sizes the arena
+    ctx.load_hits(np.array([0, ev.n_hits], np.int32), ev.x, ev.y, ev.z, ev.module, ev.sensor)
+    print("case out-of-order calls", flush=True)
+
+    def refused(fn):
+        with pytest.raises(lst.LSTError) as ei:
+            fn()
+        assert ei.value.code == lst.LST_E_STATE, ei.value
+
+    refused(ctx.run_md)                      # before grouping
+    ctx.run_sort()
+    refused(ctx.run_segments)
+    refused(ctx.run_dedup)
+    ctx.run_md()
+    refused(ctx.run_md)                      # twice
+    refused(ctx.run_triplets)                # skips segments
+    refused(lambda: ctx.objects(0, lst.LST_SEG))
+    ctx.run_segments()
+    ctx.run_triplets()
+    refused(ctx.run_segments)                # after a later stage
+    refused(ctx.run_dedup)
+    refused(lambda: ctx.objects(0, lst.LST_T5))
+    ctx.run_quintuplets()
+    refused(ctx.run_quintuplets)
+    refused(lambda: ctx.objects(0, lst.LST_T5_KEPT))
+    ctx.run_dedup()
+    refused(ctx.run_dedup)
+    refused(ctx.run_md)
+    got = {k: ctx.objects(0, k) for k in range(5)}
+    ref = orc.run_event(ev)
+    assert_parity(got, ref)
+    assert ctx.counts(0)["cand_seg"] == ref.cands[1]
+    # grouping restarts the chain at any point
+    ctx.run_sort()
+    for fn in (ctx.run_md, ctx.run_segments, ctx.run_triplets, ctx.run_quintuplets, ctx.run_dedup):
+        fn()
+    assert_parity({k: ctx.objects(0, k) for k in range(5)}, ref)
+
+
+@pytest.mark.parametrize("bits", [2, 4])
+def test_fault_flags_make_every_getter_refuse(bits):
+    """Error bit 1 (persistent barrier time-out) or 2 (grouping scan
+    time-out), written into the device error word from the host: counts come
+    back filled with LST_E_FAULT, every object, score and feature getter
+    refuses with LST_E_FAULT, and the next chain runs clean and equals the
+    oracle (the bins were cleared)."""
+    lst, ctx, orc, ev = _setup(1, 4)
+    ref = orc.run_event(ev)
+    ctx.reserve(dict(lst.default_caps(1, ev.n_hits), features=1))
+    print(f"case fault bits {bits}", flush=True)
+    assert_parity(ctx.run_event(ev), ref)
+    ctx.run_t5_features()
+    ctx.raise_error_flags(bits)
+    c = ctx.counts(0, check=False)
+    assert c["rc"] == lst.LST_E_FAULT and c["error_flags"] & bits
+    for fn in (lambda: ctx.counts(0), lambda: ctx.objects(0, lst.LST_MD),
+               lambda: ctx.objects(0, lst.LST_T5_KEPT), lambda: ctx.t5_scores(0),
+               lambda: ctx.t5_logits(0), lambda: ctx.t3_logits(0),
+               lambda: ctx.t5_features(0)):
+        with pytest.raises(lst.LSTError) as ei:
+            fn()
+        assert ei.value.code == lst.LST_E_FAULT, ei.value
+    with pytest.raises(lst.LSTError) as ei:
+        ctx.raise_error_flags(1)
+    assert ei.value.code == lst.LST_E_INVALID
+    assert_parity(ctx.run_event(ev), ref)
+    assert ctx.counts(0)["error_flags"] == 0
