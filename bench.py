@@ -231,14 +231,19 @@ def _gen_train_full(e):
     return E.generate(2, e, purpose=E.PURPOSE_TRAIN, cfg=E.scorer_training_config(E.CONFIGS[2]))
 
 
+def _gen_train_stress(e):
+    from synth import events as E
+    return E.generate(5, e, purpose=E.PURPOSE_TRAIN, cfg=E.scorer_training_config(E.CONFIGS[5]))
+
+
 def _gen(args):
     from synth import events as E
     cid, e = args
     return E.generate(cid, e)
 
 
-def pregenerate(scorer=True, batch=True, stress=True, pu200=True, n_train=150, n_eval=8,
-                n_train_full=80):
+def pregenerate(scorer=True, batch=True, stress=True, pu200=True, n_train=150, n_eval=16,
+                n_train_full=80, n_train_stress=100):
     """every synthetic event the side legs need, generated by a pool of CPU
     workers before this process touches the GPU"""
     import multiprocessing as mp
@@ -253,6 +258,8 @@ def pregenerate(scorer=True, batch=True, stress=True, pu200=True, n_train=150, n
             out["batch"] = pool.map(_gen, [(3, e) for e in range(64)])
         if stress:
             out["stress"] = pool.map(_gen, [(5, e) for e in range(16)])
+            if scorer:
+                out["train_stress"] = pool.map(_gen_train_stress, range(n_train_stress))
         if pu200:
             out["pu200"] = pool.map(_gen, [(2, 100 + e) for e in range(16)])
     return out
@@ -325,18 +332,26 @@ def scored(lst, torch, train, evs, steps=50, base_cfg=4):
         # the next kind learns on what survives this veto
         ctx_w.mlp_load(*models[kind], kind=kind)
         ctx_w.set_mode(lst.LST_MODE_MLP)
+    # three arms on the same held-out events, each as one batched launch:
+    # the plain chain at nominal windows, the plain chain at the widened
+    # training windows (what widening alone does), and the widened chain with
+    # both learned vetoes (what the networks add on top of the widening)
     plain_ctx = lst.Context(PR.make(), geo.f32, geo.i32, device=0)
+    wide_ctx = lst.Context(PR.make(w=w_train), geo.f32, geo.i32, device=0)
     scored_ctx = lst.Context(PR.make(w=w_train), geo.f32, geo.i32, device=0)
     for kind, m in models.items():
         scored_ctx.mlp_load(*m, kind=kind)
     scored_ctx.set_mode(lst.LST_MODE_MLP)
     m_plain = S.evaluate(plain_ctx, evs, geo)
+    m_wide = S.evaluate(wide_ctx, evs, geo)
     m_scored = S.evaluate(scored_ctx, evs, geo)
+    for c in (plain_ctx, wide_ctx, scored_ctx):
+        assert_clean(c)
     stream = torch.cuda.current_stream()
 
     def rate(ctx):
         per = []
-        for ev in evs:
+        for ev in evs[:8]:
             ctx.load_hits(np.array([0, ev.n_hits], np.int32), ev.x, ev.y, ev.z, ev.module, ev.sensor)
             for _ in range(3):
                 ctx.run_chain_graph(stream)
@@ -377,14 +392,21 @@ def scored(lst, torch, train, evs, steps=50, base_cfg=4):
                 "achieved_TFLOPs": n * MLP_FLOPS / (us * 1e-6) / 1e12, "peak_TFLOPs": 2500.0}
 
     model = models
-    where = ("barrel toy" if base_cfg == 4 else
-             "full geometry, 1 % inefficiency, 5 % noise hits")
+    where = {4: "barrel toy", 2: "full geometry, 1 % inefficiency, 5 % noise hits",
+             5: "barrel toy, 5 % displaced, 10 % noise hits"}[base_cfg]
+    keys = ("eff", "fake", "dup", "impure", "n_obj")
     return {"workload": f"scorers trained on triplets and quintuplets of {len(train)} training "
                         f"events ({where}, 20 x Poisson(U(50,250)) helices, windows x1.5), "
-                        f"evaluated on {len(evs)} held-out 4000-helix events (config {base_cfg})",
+                        f"evaluated on {len(evs)} held-out events (config {base_cfg}) in one "
+                        f"batched launch per arm",
             "training": info,
-            "plain_w1": {k: m_plain[k] for k in ("eff", "fake", "dup", "impure", "n_obj")},
-            "scored_w1.5": {k: m_scored[k] for k in ("eff", "fake", "dup", "impure", "n_obj")},
+            "plain_w1": {k: m_plain[k] for k in keys},
+            "plain_w1.5": {k: m_wide[k] for k in keys},
+            "scored_w1.5": {k: m_scored[k] for k in keys},
+            "network_gain_vs_plain_w1.5": {
+                "eff_points": 100 * (m_scored["eff"] - m_wide["eff"]),
+                "fake_ratio": m_scored["fake"] / m_wide["fake"] if m_wide["fake"] else None,
+                "impure_points": 100 * (m_scored["impure"] - m_wide["impure"])},
             "plain_events_per_s": rate(plain_ctx), "scored_events_per_s": rate(scored_ctx),
             "score_kernels": [kern("k_mlp_score<T3>", ms3, cnt["n_t3"]),
                               kern("k_mlp_score<T5>", ms5, cnt["n_t5"])]}, model
@@ -497,10 +519,12 @@ def memory(lst, torch, G, PR, evs, quantiles=(0.999, 0.9999)):
     return out
 
 
-def stress(lst, torch, E, G, PR, evs, model=None, steps=10):
+def stress(lst, torch, E, G, PR, evs, model=None, model_transfer=None, steps=10):
     """16 PU300-like events (6000 helices, 5 % displaced, 10 % noise, windows
     x1.5) in one tuned launch: events/s and efficiency / fake / duplicate rate
-    by truth, plain and (when a trained scorer is given) scored."""
+    by truth, plain and (when trained scorers are given) scored: `model`
+    trained on events of the stress recipe (displaced tracks and noise hits
+    included), `model_transfer` trained on prompt, noise-free barrel events."""
     from paper_2209_13711_amd import scorer as S
     from synth import truth as T
     geo = G.get("barrel_toy")
@@ -537,12 +561,14 @@ def stress(lst, torch, E, G, PR, evs, model=None, steps=10):
                        "(d0 up to 10 cm), 10 % noise, windows x1.5, barrel toy geometry, one batch",
            "hits": int(b.offsets[-1]),
            "plain": run(lst.Context(params, geo.f32, geo.i32, device=0))}
-    if model is not None:
+    for name, mdl in (("scored", model), ("scored_prompt_model", model_transfer)):
+        if mdl is None:
+            continue
         ctx = lst.Context(params, geo.f32, geo.i32, device=0)
-        for kind, m in model.items():
+        for kind, m in mdl.items():
             ctx.mlp_load(*m, kind=kind)
         ctx.set_mode(lst.LST_MODE_MLP)
-        out["scored"] = run(ctx)
+        out[name] = run(ctx)
     return out
 
 
@@ -698,12 +724,16 @@ def main():
         out["batched"] = batched(lst, torch, E, G, PR, pre["batch"], cache=args.tune_cache)
         out["batched"]["multistream_8"] = multistream(lst, torch, G, PR, pre["batch"])
     model = None
+    model = model_stress = None
     if not args.no_scorer:
         out["scored"], model = scored(lst, torch, pre["train"], pre["eval"])
         out["scored_full_geometry"], _ = scored(lst, torch, pre["train_full"], pre["eval_full"],
                                                 base_cfg=2)
+        if not args.no_stress:
+            out["scored_stress"], model_stress = scored(lst, torch, pre["train_stress"],
+                                                        pre["stress"], base_cfg=5)
     if not args.no_stress:
-        out["stress"] = stress(lst, torch, E, G, PR, pre["stress"], model)
+        out["stress"] = stress(lst, torch, E, G, PR, pre["stress"], model_stress, model)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(params, geo)
         out["cpu_baseline_all_cores"] = cpu_all

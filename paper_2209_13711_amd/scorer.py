@@ -181,13 +181,16 @@ def training_config(base):
 def evaluate(ctx: "L.Context", events, geo, stream=None) -> dict:
     """Efficiency, fake and duplicate rate of the kept quintuplets (truth
     definitions of synth.truth) and the fraction of kept quintuplets whose ten
-    hits all come from one track, summed over `events`."""
+    hits all come from one track, summed over `events`, which run as one
+    batched launch."""
     from synth import truth as T
     tot = dict(n_obj=0, n_findable=0, n_found=0, n_fake=0, n_dup=0, n_pure=0)
-    for ev in events:
-        offs = np.array([0, ev.n_hits], np.int32)
-        ctx.run_batch(offs, ev.x, ev.y, ev.z, ev.module, ev.sensor, stream)
-        kept = ctx.objects(0, L.LST_T5_KEPT, stream)
+    offs = np.zeros(len(events) + 1, np.int32)
+    offs[1:] = np.cumsum([ev.n_hits for ev in events])
+    cat = [np.concatenate([getattr(ev, a) for ev in events]) for a in ("x", "y", "z", "module", "sensor")]
+    ctx.run_batch(offs, *cat, stream)
+    for e, ev in enumerate(events):
+        kept = ctx.objects(e, L.LST_T5_KEPT, stream)
         m = T.metrics(kept, ev, geo)
         for k in ("n_obj", "n_findable", "n_found", "n_fake", "n_dup"):
             tot[k] += m[k]

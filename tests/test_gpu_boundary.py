@@ -120,3 +120,44 @@ def test_fault_flags_make_every_getter_refuse(bits):
     assert ei.value.code == lst.LST_E_INVALID
     assert_parity(ctx.run_event(ev), ref)
     assert ctx.counts(0)["error_flags"] == 0
+
+
+@pytest.mark.parametrize("cid,n_events", [(2, 16), (3, 16)])
+def test_eight_streams_match_oracle(cid, n_events):
+    """The paper's concurrency scheme on one GPU (Sec. 3: events overlapped
+    on 8 streams): one context and one hipGraph per stream, hits already in
+    device memory, eight events in flight at a time.  Every event's objects
+    must equal the oracle's."""
+    import torch
+    import paper_2209_13711_amd as lst
+    cfg = E.CONFIGS[cid]
+    geo = G.get(cfg.geometry)
+    params = PR.make(w=cfg.window)
+    evs = [E.generate(cid, 300 + e) for e in range(n_events)]
+    orc = oracle.Oracle(params, geo.f32, geo.i32)
+    refs = [orc.run_event(ev) for ev in evs]
+    streams = [torch.cuda.Stream() for _ in range(8)]
+    # arena sizes that fit every event (grown by run_batch on overflow)
+    sizer = lst.Context(params, geo.f32, geo.i32, device=0)
+    for ev in evs:
+        sizer.run_batch(np.array([0, ev.n_hits], np.int32), ev.x, ev.y, ev.z, ev.module, ev.sensor)
+    ctxs = []
+    for k in range(8):
+        c = lst.Context(params, geo.f32, geo.i32, device=0)
+        c.reserve(sizer.caps)
+        ctxs.append(c)
+    dev = [[torch.from_numpy(np.ascontiguousarray(a)).cuda()
+            for a in (ev.x, ev.y, ev.z, ev.module.astype(np.int32), ev.sensor.astype(np.uint8))]
+           for ev in evs]
+    torch.cuda.synchronize()
+    print(f"case 8 streams cfg{cid} x{n_events}", flush=True)
+    for w0 in range(0, n_events, 8):
+        for k in range(8):
+            ev = evs[w0 + k]
+            ctxs[k].load_hits(np.array([0, ev.n_hits], np.int32), *dev[w0 + k], stream=streams[k])
+            ctxs[k].run_chain_graph(streams[k])
+        torch.cuda.synchronize()
+        for k in range(8):
+            got = {kind: ctxs[k].objects(0, kind, stream=streams[k]) for kind in range(5)}
+            assert_parity(got, refs[w0 + k])
+            assert ctxs[k].counts(0, stream=streams[k])["error_flags"] == 0
