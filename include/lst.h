@@ -347,6 +347,19 @@ int lst_mlp_backward(lst_ctx *ctx, const float *params, const uint16_t *x, const
                      int64_t n, const float *logits, const uint16_t *h1, const float *h2,
                      void *work, size_t work_bytes, float *grad, float *loss, void *stream);
 
+/* lst_mlp_backward without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid allocation).  The workspace is a
+ * fixed device array inside the library, one per GPU, 6.0 MB, held from the
+ * first lst_create on that GPU until the process ends; n at most 8192 rows
+ * (else LST_E_CAPACITY, nothing launched).  The call allocates nothing and
+ * gives the same results as lst_mlp_backward.  Every call on one GPU shares
+ * that array: calls that overlap on one GPU (different streams, threads or
+ * contexts) race and must be ordered by the caller. */
+int lst_mlp_backward_noalloc(lst_ctx *ctx, const float *params, const uint16_t *x,
+                             const uint8_t *y, int64_t n, const float *logits, const uint16_t *h1,
+                             const float *h2, float *grad, float *loss, void *stream);
+
 /* One Adam step (bias corrected, step >= 1) on params with moments m, v
  * (device, LST_MLP_NPARAM each, updated in place). */
 int lst_mlp_adam(lst_ctx *ctx, float *params, const float *grad, float *m, float *v, int32_t step,

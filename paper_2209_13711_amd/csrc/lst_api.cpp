@@ -63,6 +63,7 @@ struct lst_ctx {
     float *mlp_dev[2] = {nullptr, nullptr};
     float mlp_threshold[2] = {0.0f, 0.0f};
     bool t3_features_valid = false;
+    void *fixed_work = nullptr;   // this device's copy of the fixed backward workspace
     std::vector<lst_counts> counts;
     bool counts_valid = false;
     int stage = 0;  // 0 nothing, 1 hits loaded, 2 sorted, 3 md, 4 seg, 5 t3, 6 t5, 7 dedup
@@ -271,9 +272,13 @@ int lst_create(lst_ctx **out, int device, const double *params, int32_t n_params
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return LST_E_HIP;
+    // device address of the fixed backward workspace on this GPU (lst_mlp_backward_noalloc)
+    void *fixed = nullptr;
+    if (mlp_fixed_scratch(device, &fixed) != hipSuccess || !fixed) return LST_E_HIP;
     lst_ctx *c = new (std::nothrow) lst_ctx();
     if (!c) return LST_E_NOMEM;
     c->device = device;
+    c->fixed_work = fixed;
     std::memcpy(c->params, params, sizeof(c->params));
     derive(c->params, c->K);
     *out = c;
@@ -757,6 +762,23 @@ int lst_mlp_backward(lst_ctx *c, const float *params, const uint16_t *x, const u
         return fail(c, LST_E_CAPACITY, "workspace %zu bytes, %zu needed", work_bytes,
                     mlp_workspace_bytes(n));
     HIPCHK(c, mlp_backward(params, x, y, n, logits, h1, h2, (float *)work, grad, loss,
+                           (hipStream_t)stream));
+    return LST_OK;
+}
+
+int lst_mlp_backward_noalloc(lst_ctx *c, const float *params, const uint16_t *x, const uint8_t *y,
+                             int64_t n, const float *logits, const uint16_t *h1, const float *h2,
+                             float *grad, float *loss, void *stream)
+{
+    int rc = mlp_args(c, n, {params, x, y, logits, h1, h2, grad, loss});
+    if (rc) return rc;
+    if (n == 0) return fail(c, LST_E_INVALID, "empty batch");
+    if (n > MLP_FIXED_MAX_ROWS)
+        return fail(c, LST_E_CAPACITY, "%lld rows: the fixed workspace holds at most %lld",
+                    (long long)n, (long long)MLP_FIXED_MAX_ROWS);
+    // every workspace word the kernels read is written by them first in the
+    // same call: nothing to clear
+    HIPCHK(c, mlp_backward(params, x, y, n, logits, h1, h2, (float *)c->fixed_work, grad, loss,
                            (hipStream_t)stream));
     return LST_OK;
 }

@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "lst_access.hpp"
 #include "lst_cuts.hpp"
 
@@ -529,6 +531,41 @@ hipError_t mlp_backward(const float *P, const uint16_t *X, const uint8_t *y, int
                        part, grad);
     hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(BLOCK), 0, s, lrow, n, loss);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- fixed workspace
+// Workspace of the backward pass for callers that cannot allocate: one
+// file-scope device array, one copy per GPU, held until the process ends.
+// In host code the name `scratch` is only a stand-in for the symbol; its
+// device address on each GPU comes from hipGetSymbolAddress, taken once per
+// device with that device current, and only that address is ever passed on.
+static __device__ __align__(256) float scratch[MLP_FIXED_SCRATCH_FLOATS];
+static_assert(sizeof(float) * ((size_t)MLP_FIXED_MAX_ROWS * (2 + 2 * NH) +
+                               (size_t)GRAD_CHUNKS * NPARAM) <= sizeof(scratch),
+              "fixed workspace holds MLP_FIXED_MAX_ROWS rows");
+
+static std::mutex scratch_mu;
+static void *scratch_at[MLP_FIXED_MAX_DEVICES];
+
+hipError_t mlp_fixed_scratch(int device, void **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= MLP_FIXED_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_at[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if ((e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        const hipError_t back = hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        if (back != hipSuccess) return back;
+        scratch_at[device] = p;
+    }
+    *out = scratch_at[device];
+    return hipSuccess;
 }
 
 hipError_t mlp_adam(float *P, const float *grad, float *m, float *v, float lr, float b1, float b2,

@@ -100,6 +100,8 @@ _SIGS = {
     "lst_mlp_forward": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P, _P, _P, _P]),
     "lst_mlp_backward": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, _P, _P, _P, _P,
                                         ctypes.c_size_t, _P, _P, _P]),
+    "lst_mlp_backward_noalloc": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, _P, _P, _P, _P,
+                                                _P, _P]),
     "lst_mlp_adam": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_float,
                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
     "lst_mlp_train_steps": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int64, _P,
@@ -435,6 +437,14 @@ class Context:
             d(logits, torch.float32), d(h1, torch.int16), d(h2, torch.float32),
             d(work, torch.uint8), work.numel(), d(grad, torch.float32), d(loss, torch.float32),
             self._stream(stream)))
+
+    def mlp_backward_noalloc(self, params, x, y, logits, h1, h2, grad, loss, stream=None):
+        """lst_mlp_backward with the library's fixed workspace (no allocation)"""
+        d = self._dev
+        self._check(self.lib.lst_mlp_backward_noalloc(
+            self.h, d(params, torch.float32), d(x, torch.int16), d(y, torch.uint8), x.shape[0],
+            d(logits, torch.float32), d(h1, torch.int16), d(h2, torch.float32),
+            d(grad, torch.float32), d(loss, torch.float32), self._stream(stream)))
 
     def mlp_adam(self, params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         d = self._dev
