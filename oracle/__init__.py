@@ -80,6 +80,17 @@ def _load():
         getattr(lib, f).restype = ctypes.c_int
         getattr(lib, f).argtypes = [P, P, P, P]
     lib.orc_consts.argtypes = [P, P]
+    lib.orc_run_pixel.restype = ctypes.c_int
+    lib.orc_run_pixel.argtypes = [P, P, ctypes.c_int, ctypes.c_int32, P, P, P, ctypes.c_int32, P]
+    lib.orc_px_count.restype = ctypes.c_int64
+    lib.orc_px_count.argtypes = [P, ctypes.c_int]
+    lib.orc_px_candidates.argtypes = [P, ctypes.c_int, P]
+    lib.orc_tc.argtypes = [P, P]
+    lib.orc_eval_link.restype = ctypes.c_int
+    lib.orc_eval_link.argtypes = [P, P, P, ctypes.c_int, P, P, P]
+    lib.orc_set_truncation.restype = ctypes.c_int
+    lib.orc_set_truncation.argtypes = [P, P]
+    lib.orc_dropped.argtypes = [P, P]
     lib.orc_eval_margin.restype = ctypes.c_double
     lib.orc_eval_margin.argtypes = [P, ctypes.c_int, P, P]
     _lib = lib
@@ -100,6 +111,17 @@ class Result:
     t3_features: np.ndarray  # float32 [n_t3, 40]
     cands: np.ndarray       # int64 [4]
     near: dict              # kind -> (tuples, margins, decisions)
+
+
+@dataclass
+class PixelResult:
+    pt5: np.ndarray         # int32 [n, 13]: seed, 10 hits, score bits, kept
+    pt3: np.ndarray         # int32 [n, 13]: seed, 6 hits + 4 x -1, score bits, kept
+    tc: np.ndarray          # int32 [n, 12]: type, seed, 10 hits (-1 padded)
+    near: int               # pixel decisions within 1e-5 (relative) of a threshold
+
+
+TC_PT5, TC_PT3, TC_T5, TC_PLS = 0, 1, 2, 3
 
 
 class Oracle:
@@ -134,6 +156,47 @@ class Oracle:
         out = np.zeros(7, np.float32)
         self._lib.orc_consts(self._h, _ptr(out))
         return dict(zip(("kmax", "klim", "kh", "tolu", "tolv", "tolkc", "epsak"), out))
+
+    def set_truncation(self, caps=None):
+        """per-module capacities (MD, SEG, T3, T5; 0 = none) for later events"""
+        if caps is None:
+            rc = self._lib.orc_set_truncation(self._h, None)
+        else:
+            c = np.ascontiguousarray(caps, np.int32)
+            assert c.shape == (4,)
+            rc = self._lib.orc_set_truncation(self._h, _ptr(c))
+        if rc != 0:
+            raise ValueError("oracle: negative capacity")
+
+    def dropped(self) -> np.ndarray:
+        """objects removed by the capacities in the last event, per kind"""
+        out = np.zeros(4, np.int64)
+        self._lib.orc_dropped(self._h, _ptr(out))
+        return out
+
+    def run_pixel(self, pix_params, px):
+        """Pixel objects and track candidates of the last event (run / run_event
+        first): px has x, y, z (pixel hits) and seeds [n, 4].  Returns a
+        PixelResult."""
+        pp = np.ascontiguousarray(pix_params, np.float64)
+        x = np.ascontiguousarray(px.x, np.float32); y = np.ascontiguousarray(px.y, np.float32)
+        z = np.ascontiguousarray(px.z, np.float32)
+        sd = np.ascontiguousarray(px.seeds, np.int32).reshape(-1, 4)
+        rc = self._lib.orc_run_pixel(self._h, _ptr(pp), len(pp), int(x.shape[0]), _ptr(x),
+                                     _ptr(y), _ptr(z), int(sd.shape[0]), _ptr(sd))
+        if rc != 0:
+            raise ValueError("oracle: bad pixel input or no event")
+        lib, h = self._lib, self._h
+        cand = {}
+        for what in (0, 2):
+            n = lib.orc_px_count(h, what)
+            out = np.zeros((max(n, 1), 13), np.int32)
+            lib.orc_px_candidates(h, what, _ptr(out))
+            cand[what] = out[:n]
+        n = lib.orc_px_count(h, 4)
+        tc = np.zeros((max(n, 1), 12), np.int32)
+        lib.orc_tc(h, _ptr(tc))
+        return PixelResult(pt5=cand[0], pt3=cand[2], tc=tc[:n], near=int(lib.orc_px_count(h, 5)))
 
     def run(self, x, y, z, module, sensor) -> Result:
         x = np.ascontiguousarray(x, np.float32); y = np.ascontiguousarray(y, np.float32)
@@ -227,6 +290,23 @@ class Oracle:
 
     def eval_t5_features(self, mods, hits):
         return self._eval_f(self._lib.orc_eval_t5_features, 5, mods, hits)
+
+    def eval_link(self, pix_params, pix12, mods, hits):
+        """one pixel link: four pixel hits (12 floats) with a quintuplet (5 MDs)
+        or a triplet (3 MDs); returns (decision, out[12]): pLS tx, ty, cot,
+        object tx, ty, cot, window cos-term, sin^2, polar term, chi2_rphi,
+        chi2_rz, score"""
+        pp = np.ascontiguousarray(pix_params, np.float64)
+        p12 = np.ascontiguousarray(pix12, np.float32).reshape(-1)
+        mods = np.ascontiguousarray(mods, np.int32)
+        hits = np.ascontiguousarray(hits, np.float32).reshape(-1)
+        assert p12.shape[0] == 12 and hits.shape[0] == 6 * mods.shape[0]
+        out = np.zeros(12)
+        d = self._lib.orc_eval_link(self._h, _ptr(pp), _ptr(p12), int(mods.shape[0]), _ptr(mods),
+                                    _ptr(hits), _ptr(out))
+        if d < 0:
+            raise ValueError("oracle: 3 or 5 MDs")
+        return bool(d), out
 
     def eval_margin(self, kind: int, mods, hits) -> float:
         """FP64 margin the chain records for one candidate of ``kind`` (MD,

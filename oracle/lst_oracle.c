@@ -37,6 +37,7 @@
 #define ARC_A6 (231.0f / 13312.0f)
 
 #define NEAR_REL 1e-5
+#define LINK_MAXP 9     /* points of a linked chain: 4 pixel hits + 5 anchors */
 
 /* ------------------------------------------------------------------------- */
 typedef struct {
@@ -133,6 +134,10 @@ typedef struct { int32_t i, o; } SEGREC;
 typedef struct { int32_t a, b, c; float k; float feat[40]; } T3REC;
 typedef struct { int32_t md[5]; float score; float feat[40]; } T5REC;
 typedef struct { int32_t hits[10]; double margin; uint8_t decision; } NEARREC;
+/* a pixel-linked candidate: seed (pLS), outer object (T5 or T3 index), score */
+typedef struct { int32_t seed, obj; float score; } PXREC;
+/* a track candidate: type (ORC_TC_*), seed or -1, outer hits (-1 padded) */
+typedef struct { int32_t type, seed, hits[10]; } TCREC;
 
 struct orc {
     KCONST K;
@@ -148,6 +153,15 @@ struct orc {
     uint8_t *t3_veto;   /* triplets excluded from the quintuplet stage (or NULL) */
     int32_t n_hits;
     int64_t cand[4];
+    int32_t cap[4];     /* per-module capacity of MD, SEG, T3, T5 (0: none) */
+    int64_t dropped[4]; /* objects the capacities removed in the last event */
+    /* pixel objects of the last orc_run_pixel */
+    gvec pt5, pt3;      /* PXREC candidates */
+    uint8_t *pt5_keep, *pt3_keep, *t5_clean, *pls_keep;
+    int32_t *seeds;     /* copy of the last seeds (4 pixel hits each) */
+    int32_t n_seeds, n_px;
+    int64_t px_near;    /* pixel decisions within NEAR_REL of a threshold */
+    gvec tc;            /* TCREC */
 };
 
 /* ------------------------------------------------------------------------- */
@@ -341,6 +355,9 @@ orc *orc_create(const double *params, int n_params, int n_mod, const float *f32,
     o->t3.sz = sizeof(T3REC);
     o->t5.sz = sizeof(T5REC);
     for (int k = 0; k < 4; ++k) o->near[k].sz = sizeof(NEARREC);
+    o->pt5.sz = sizeof(PXREC);
+    o->pt3.sz = sizeof(PXREC);
+    o->tc.sz = sizeof(TCREC);
     if (build_map(o, params, f32, i32) != 0) { orc_destroy(o); return NULL; }
     return o;
 }
@@ -361,6 +378,8 @@ void orc_destroy(orc *o)
     free_event(o);
     gv_free(&o->md); gv_free(&o->seg); gv_free(&o->t3); gv_free(&o->t5);
     for (int k = 0; k < 4; ++k) gv_free(&o->near[k]);
+    gv_free(&o->pt5); gv_free(&o->pt3); gv_free(&o->tc);
+    free(o->pt5_keep); free(o->pt3_keep); free(o->t5_clean); free(o->pls_keep); free(o->seeds);
     free(o->mod); free(o->layer); free(o->subdet); free(o->mtype);
     free(o->map_ptr); free(o->map_col);
     free(o);
@@ -439,6 +458,98 @@ static int make_md(const orc *o, int m, const float *L, const float *U, MDREC *m
 }
 
 
+/* ------------------------------------------------------------------------- */
+/* Per-module capacities (Sec. 3: every object kind lives in arrays of a fixed
+ * capacity per module, set at a high quantile of the per-module occupancy, so
+ * that a fuller module loses objects).  Which objects the paper's GPU loses
+ * depends on thread timing; the rule here is fixed so that it can be
+ * reproduced: a module holding more than `cap` objects of one kind keeps the
+ * `cap` with the smallest tuples of caller hit indices (lexicographic), the
+ * module of an object being that of its first mini-doublet.  keys: n rows of
+ * w hit indices (all distinct); keep[i] = 1 iff fewer than cap rows are
+ * smaller than row i.  Returns the number of rows dropped. */
+static int64_t cap_keep(const int32_t *keys, int w, int64_t n, int64_t cap, uint8_t *keep)
+{
+    int64_t dropped = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t smaller = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            int c = 0;   /* sign of (row j - row i) at the first differing hit */
+            for (int k = 0; k < w && c == 0; ++k)
+                c = (keys[j * w + k] > keys[i * w + k]) - (keys[j * w + k] < keys[i * w + k]);
+            smaller += c < 0;
+        }
+        keep[i] = (uint8_t)(smaller < cap);
+        dropped += !keep[i];
+    }
+    return dropped;
+}
+
+/* hit tuples of objects [lo, hi) of kind 1..3 (SEG, T3, T5) */
+static int32_t *object_keys(const orc *o, int kind, int64_t lo, int64_t hi)
+{
+    const int w = kind == 1 ? 4 : kind == 2 ? 6 : 10;
+    int32_t *k = (int32_t *)malloc((size_t)((hi - lo) > 0 ? (hi - lo) : 1) * w * sizeof(int32_t));
+    for (int64_t i = lo; i < hi; ++i) {
+        int32_t *r = &k[(i - lo) * w];
+        if (kind == 1) {
+            const SEGREC *S = &((const SEGREC *)o->seg.v)[i];
+            md_hits(o, S->i, &r[0]); md_hits(o, S->o, &r[2]);
+        } else if (kind == 2) {
+            const T3REC *T = &((const T3REC *)o->t3.v)[i];
+            md_hits(o, T->a, &r[0]); md_hits(o, T->b, &r[2]); md_hits(o, T->c, &r[4]);
+        } else {
+            const T5REC *T = &((const T5REC *)o->t5.v)[i];
+            for (int j = 0; j < 5; ++j) md_hits(o, T->md[j], &r[2 * j]);
+        }
+    }
+    return k;
+}
+
+/* Applies the capacity of `kind` (1..3) to objects grouped by inner MD:
+ * off[md] .. off[md + 1] are the objects of MD md, md_off[m] .. md_off[m + 1]
+ * the MDs of module m.  Compacts the kind's array in place (enumeration
+ * order kept) and rewrites off. */
+static void cap_grouped(orc *o, int kind, gvec *v, int32_t *off, const int32_t *md_off)
+{
+    const int64_t cap = o->cap[kind];
+    if (cap <= 0) return;
+    uint8_t *keep = (uint8_t *)malloc((size_t)(v->n > 0 ? v->n : 1));
+    memset(keep, 1, (size_t)(v->n > 0 ? v->n : 1));
+    for (int m = 0; m < o->n_mod; ++m) {
+        const int64_t lo = off[md_off[m]], hi = off[md_off[m + 1]];
+        if (hi - lo <= cap) continue;
+        int32_t *keys = object_keys(o, kind, lo, hi);
+        o->dropped[kind] += cap_keep(keys, kind == 1 ? 4 : 6, hi - lo, cap, &keep[lo]);
+        free(keys);
+    }
+    const int64_t n_md = o->md.n;
+    int64_t w = 0, r = 0;
+    char *base = (char *)v->v;
+    for (int64_t md = 0; md < n_md; ++md) {
+        const int64_t end = off[md + 1];
+        off[md] = (int32_t)w;
+        for (; r < end; ++r)
+            if (keep[r]) {
+                if (w != r) memcpy(base + w * v->sz, base + r * v->sz, v->sz);
+                ++w;
+            }
+    }
+    off[n_md] = (int32_t)w;
+    v->n = w;
+    free(keep);
+}
+
+int orc_set_truncation(orc *o, const int32_t *caps4)
+{
+    for (int k = 0; k < 4; ++k)
+        if (caps4 && caps4[k] < 0) return -1;
+    for (int k = 0; k < 4; ++k) o->cap[k] = caps4 ? caps4[k] : 0;
+    return 0;
+}
+
+void orc_dropped(const orc *o, int64_t *out4) { memcpy(out4, o->dropped, sizeof(o->dropped)); }
+
 int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float *z,
             const int32_t *module, const uint8_t *sensor)
 {
@@ -449,6 +560,7 @@ int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float 
     gv_clear(&o->md); gv_clear(&o->seg); gv_clear(&o->t3); gv_clear(&o->t5);
     for (int k = 0; k < 4; ++k) gv_clear(&o->near[k]);
     memset(o->cand, 0, sizeof(o->cand));
+    memset(o->dropped, 0, sizeof(o->dropped));
     int nm = o->n_mod;
 
     /* hits grouped by (module, sensor), original order kept inside a group */
@@ -484,6 +596,12 @@ int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float 
                     r->margin = mg; r->decision = (uint8_t)pass;
                 }
             }
+        }
+        /* the module's MDs are enumerated in (lower, upper) hit order, so its
+         * capacity keeps the first cap of them */
+        if (o->cap[0] > 0 && o->md.n - md_off[m] > o->cap[0]) {
+            o->dropped[0] += o->md.n - md_off[m] - o->cap[0];
+            o->md.n = md_off[m] + o->cap[0];
         }
     }
     md_off[nm] = (int32_t)o->md.n;
@@ -521,7 +639,7 @@ int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float 
         }
     }
     o->seg_off[n_md] = (int32_t)o->seg.n;
-    free(md_off);
+    cap_grouped(o, 1, &o->seg, o->seg_off, md_off);
     const SEGREC *SG = (const SEGREC *)o->seg.v;
 
     /* 3. triplets: segment (a->b) with every segment (b->c) */
@@ -557,6 +675,8 @@ int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float 
         }
         o->t3_off[n_md] = (int32_t)o->t3.n;
     }
+    cap_grouped(o, 2, &o->t3, o->t3_off, md_off);
+    free(md_off);
     o->n_hits = n_hits;
     run_t5_dedup(o);
     return 0;
@@ -571,6 +691,7 @@ static void run_t5_dedup(orc *o)
     gv_clear(&o->t5);
     gv_clear(&o->near[3]);
     o->cand[3] = 0;
+    o->dropped[3] = 0;
     free(o->keep); o->keep = NULL;
     const T3REC *T3 = (const T3REC *)o->t3.v;
 
@@ -599,6 +720,34 @@ static void run_t5_dedup(orc *o)
             double mg = cut_margin(&cf, &cd);
             if (mg < NEAR_REL) push_near(o, 3, mds, 5, mg, pass);
         }
+    }
+
+    /* capacity per module of the first MD: the quintuplets come grouped by
+     * their first triplet, hence by first MD and by its module */
+    if (o->cap[3] > 0 && o->t5.n > 0) {
+        T5REC *Q = (T5REC *)o->t5.v;
+        uint8_t *keep = (uint8_t *)malloc((size_t)o->t5.n);
+        int64_t lo = 0;
+        while (lo < o->t5.n) {
+            const int m = MD[Q[lo].md[0]].module;
+            int64_t hi = lo + 1;
+            while (hi < o->t5.n && MD[Q[hi].md[0]].module == m) ++hi;
+            memset(&keep[lo], 1, (size_t)(hi - lo));
+            if (hi - lo > o->cap[3]) {
+                int32_t *keys = object_keys(o, 3, lo, hi);
+                o->dropped[3] += cap_keep(keys, 10, hi - lo, o->cap[3], &keep[lo]);
+                free(keys);
+            }
+            lo = hi;
+        }
+        int64_t w = 0;
+        for (int64_t r = 0; r < o->t5.n; ++r)
+            if (keep[r]) {
+                if (w != r) Q[w] = Q[r];
+                ++w;
+            }
+        o->t5.n = w;
+        free(keep);
     }
 
     /* 5. duplicate removal over shared hits */
@@ -896,4 +1045,455 @@ double orc_eval_margin(const orc *o, int kind, const int32_t *mods, const float 
         return cut_margin(&cf, &cd);
     }
     return NAN;
+}
+
+/* ========================================================================= */
+/* Pixel objects (Sec. 2.1 and the kernel-flow figure of Sec. 3): pixel line
+ * segments (pLS, seeds of four pixel hits) linked to quintuplets (pT5) and
+ * to triplets (pT3), cross-cleaning, track candidates (TC).  Runs on the
+ * objects of the last orc_run.  The steps, in the paper's order:
+ *   1. pT5: every (pLS, kept quintuplet) pair inside the linking window whose
+ *      nine points pass the link chi2 cuts; within the collection a candidate
+ *      survives iff no candidate sharing one of its hits (pixel or outer) has
+ *      a smaller (score, seed, hit tuple) key;
+ *   2. pT3: the same for pLS not used by a surviving pT5, with every triplet;
+ *   3. pT3 near a surviving pT5 in eta-phi, or sharing a hit with one, are
+ *      duplicates;
+ *   4. kept quintuplets near a surviving pT5 or cleaned pT3, or sharing a hit
+ *      with one, are duplicates;
+ *   5. pLS used by neither are cleaned against all of the above (near, or
+ *      sharing a pixel hit); among the rest a pLS sharing a pixel hit with a
+ *      remaining pLS of smaller index is a duplicate;
+ *   6. TC = surviving pT5, cleaned pT3, cleaned T5, cleaned pLS. */
+
+static void pix_dir(const float *x, const float *y, const float *z, const int32_t *sd,
+                    float *tx, float *ty, float *c)
+{
+    float x1 = x[sd[0]], y1 = y[sd[0]], z1 = z[sd[0]];
+    float x4 = x[sd[3]], y4 = y[sd[3]], z4 = z[sd[3]];
+    dir2_f(x1, y1, x4, y4, tx, ty);
+    float dx = x4 - x1, dy = y4 - y1;
+    *c = (z4 - z1) / sqrtf((dx * dx) + (dy * dy));
+}
+
+/* direction of an outer object from its first and last anchors A, E and its
+ * curvature k: polar slope = dz / arc length */
+static void obj_dir(const MDREC *A, const MDREC *E, float k, float *tx, float *ty, float *c)
+{
+    dir2_f(A->x, A->y, E->x, E->y, tx, ty);
+    float dx = E->x - A->x, dy = E->y - A->y;
+    *c = (E->z - A->z) / arc_f(sqrtf((dx * dx) + (dy * dy)), k);
+}
+
+/* bridge curvature of a quintuplet (its first, middle and last anchors) */
+static float t5_kbr(const MDREC *A, const MDREC *C, const MDREC *E)
+{
+    float xac = C->x - A->x, yac = C->y - A->y;
+    float xce = E->x - C->x, yce = E->y - C->y;
+    float xae = E->x - A->x, yae = E->y - A->y;
+    float lac = sqrtf((xac * xac) + (yac * yac));
+    float lce = sqrtf((xce * xce) + (yce * yce));
+    float lae = sqrtf((xae * xae) + (yae * yae));
+    float crs = (xac * yae) - (yac * xae);
+    return (2.0f * crs) / ((lac * lce) * lae);
+}
+
+static void lpt_md(const MDREC *m, lpt_f *p, lpt_d *q)
+{
+    p->x = m->x; p->y = m->y; p->z = m->z; p->sv = m->sv; p->r = m->r;
+    p->kind = m->barrel ? 1 : 2;
+    q->x = m->x; q->y = m->y; q->z = m->z; q->sv = m->sv; q->r = m->r; q->kind = p->kind;
+}
+
+static void lpt_px(float x, float y, float z, lpt_f *p, lpt_d *q)
+{
+    p->x = x; p->y = y; p->z = z; p->sv = 0.0f; p->r = 0.0f; p->kind = 0;
+    q->x = x; q->y = y; q->z = z; q->sv = 0.0; q->r = 0.0; q->kind = 0;
+}
+
+/* hits of a candidate, as (kind, id): 4 pixel hits (kind 0), then the outer
+ * hits of its object (kind 1) */
+typedef struct { int n; int32_t id[14]; uint8_t kind[14]; } HITSET;
+
+/* key order: score, then seed, then the outer hit tuple */
+static int px_less(const PXREC *a, const int32_t *ta, const PXREC *b, const int32_t *tb, int w)
+{
+    if (a->score != b->score) return a->score < b->score;
+    if (a->seed != b->seed) return a->seed < b->seed;
+    for (int k = 0; k < w; ++k)
+        if (ta[k] != tb[k]) return ta[k] < tb[k];
+    return 0;
+}
+
+static int hits_share(const HITSET *a, const HITSET *b)
+{
+    for (int i = 0; i < a->n; ++i)
+        for (int j = 0; j < b->n; ++j)
+            if (a->kind[i] == b->kind[j] && a->id[i] == b->id[j]) return 1;
+    return 0;
+}
+
+static void px_hits(const orc *o, const int32_t *seeds, const PXREC *c, int w, HITSET *h,
+                    int32_t *tup)
+{
+    h->n = 0;
+    for (int k = 0; k < 4; ++k) { h->id[h->n] = seeds[4 * c->seed + k]; h->kind[h->n++] = 0; }
+    if (w == 10) {
+        const T5REC *T = &((const T5REC *)o->t5.v)[c->obj];
+        for (int j = 0; j < 5; ++j) md_hits(o, T->md[j], &tup[2 * j]);
+    } else {
+        const T3REC *T = &((const T3REC *)o->t3.v)[c->obj];
+        md_hits(o, T->a, &tup[0]); md_hits(o, T->b, &tup[2]); md_hits(o, T->c, &tup[4]);
+    }
+    for (int k = 0; k < w; ++k) { h->id[h->n] = tup[k]; h->kind[h->n++] = 1; }
+}
+
+/* within a collection: keep[i] iff no candidate sharing a hit has a smaller
+ * key (all pairs; collections are small) */
+static void px_dedup(const orc *o, const int32_t *seeds, const gvec *v, int w, uint8_t *keep)
+{
+    const PXREC *C = (const PXREC *)v->v;
+    int64_t n = v->n;
+    HITSET *H = (HITSET *)malloc((size_t)(n > 0 ? n : 1) * sizeof(HITSET));
+    int32_t *T = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * 10 * sizeof(int32_t));
+    for (int64_t i = 0; i < n; ++i) px_hits(o, seeds, &C[i], w, &H[i], &T[10 * i]);
+    for (int64_t i = 0; i < n; ++i) {
+        keep[i] = 1;
+        for (int64_t j = 0; j < n && keep[i]; ++j)
+            if (j != i && hits_share(&H[i], &H[j]) &&
+                px_less(&C[j], &T[10 * j], &C[i], &T[10 * i], w))
+                keep[i] = 0;
+    }
+    free(H); free(T);
+}
+
+int orc_run_pixel(orc *o, const double *pp, int n_pp, int32_t n_px, const float *x,
+                  const float *y, const float *z, int32_t n_seeds, const int32_t *seeds)
+{
+    if (!o->keep || n_pp < ORC_PX_N_PARAMS || n_px < 0 || n_seeds < 0) return -1;
+    for (int64_t i = 0; i < 4 * (int64_t)n_seeds; ++i)
+        if (seeds[i] < 0 || seeds[i] >= n_px) return -1;
+    gv_clear(&o->pt5); gv_clear(&o->pt3); gv_clear(&o->tc);
+    free(o->pt5_keep); free(o->pt3_keep); free(o->t5_clean); free(o->pls_keep); free(o->seeds);
+    o->n_seeds = n_seeds; o->n_px = n_px; o->px_near = 0;
+    o->seeds = (int32_t *)malloc((size_t)(n_seeds > 0 ? n_seeds : 1) * 4 * sizeof(int32_t));
+    memcpy(o->seeds, seeds, (size_t)n_seeds * 4 * sizeof(int32_t));
+    const KCONST *K = &o->K;
+    /* pixel constants, each rounded once to FP32 */
+    const float sig2p = (float)(pp[ORC_PX_SIGRPHI] * pp[ORC_PX_SIGRPHI]);
+    const float sigz = (float)pp[ORC_PX_SIGZ];
+    const double wl = pp[ORC_PX_WLINK] * (double)K->w;
+    const float wl2 = (float)(wl * wl);
+    const float dr2 = (float)pp[ORC_PX_DR2];
+    const float x5p = (float)pp[ORC_PX_X5P], x5z = (float)pp[ORC_PX_X5Z];
+    const float x3p = (float)pp[ORC_PX_X3P], x3z = (float)pp[ORC_PX_X3Z];
+    const MDREC *MD = (const MDREC *)o->md.v;
+    const T3REC *T3 = (const T3REC *)o->t3.v;
+    const T5REC *T5 = (const T5REC *)o->t5.v;
+    const int64_t n3 = o->t3.n, n5 = o->t5.n;
+
+    /* directions: pLS from its first and last pixel hits, outer objects from
+     * their first and last anchors */
+    float *sd = (float *)malloc((size_t)(n_seeds > 0 ? n_seeds : 1) * 3 * sizeof(float));
+    for (int32_t i = 0; i < n_seeds; ++i)
+        pix_dir(x, y, z, &seeds[4 * i], &sd[3 * i], &sd[3 * i + 1], &sd[3 * i + 2]);
+    float *d5 = (float *)malloc((size_t)(n5 > 0 ? n5 : 1) * 3 * sizeof(float));
+    for (int64_t t = 0; t < n5; ++t) {
+        const MDREC *A = &MD[T5[t].md[0]], *C = &MD[T5[t].md[2]], *E = &MD[T5[t].md[4]];
+        obj_dir(A, E, t5_kbr(A, C, E), &d5[3 * t], &d5[3 * t + 1], &d5[3 * t + 2]);
+    }
+    float *d3 = (float *)malloc((size_t)(n3 > 0 ? n3 : 1) * 3 * sizeof(float));
+    for (int64_t t = 0; t < n3; ++t)
+        obj_dir(&MD[T3[t].a], &MD[T3[t].c], T3[t].k, &d3[3 * t], &d3[3 * t + 1], &d3[3 * t + 2]);
+
+    /* 1. pT5 */
+    for (int32_t i = 0; i < n_seeds; ++i) {
+        const int32_t *h = &seeds[4 * i];
+        for (int64_t t = 0; t < n5; ++t) {
+            if (!o->keep[t]) continue;
+            CUTREC wf, wd;
+            int pw = link_window_f(sd[3 * i], sd[3 * i + 1], sd[3 * i + 2], d5[3 * t],
+                                   d5[3 * t + 1], d5[3 * t + 2], wl2, &wf);
+            link_window_d(sd[3 * i], sd[3 * i + 1], sd[3 * i + 2], d5[3 * t], d5[3 * t + 1],
+                          d5[3 * t + 2], wl2, &wd);
+            if (cut_margin(&wf, &wd) < NEAR_REL) o->px_near++;
+            if (!pw) continue;
+            lpt_f pf[9]; lpt_d pd[9];
+            for (int k = 0; k < 4; ++k) lpt_px(x[h[k]], y[h[k]], z[h[k]], &pf[k], &pd[k]);
+            for (int j = 0; j < 5; ++j) lpt_md(&MD[T5[t].md[j]], &pf[4 + j], &pd[4 + j]);
+            CUTREC cf, cd;
+            float sc;
+            double scd;
+            int pass = link_cut_f(K, pf, 9, 6, sig2p, sigz, x5p, x5z, &cf, &sc);
+            link_cut_d(K, pd, 9, 6, sig2p, sigz, x5p, x5z, &cd, &scd);
+            if (cut_margin(&cf, &cd) < NEAR_REL) o->px_near++;
+            if (pass) {
+                PXREC *r = (PXREC *)gv_push(&o->pt5);
+                r->seed = i; r->obj = (int32_t)t; r->score = sc;
+            }
+        }
+    }
+    o->pt5_keep = (uint8_t *)malloc((size_t)(o->pt5.n > 0 ? o->pt5.n : 1));
+    px_dedup(o, seeds, &o->pt5, 10, o->pt5_keep);
+    uint8_t *used = (uint8_t *)calloc((size_t)(n_seeds > 0 ? n_seeds : 1), 1);
+    const PXREC *P5 = (const PXREC *)o->pt5.v;
+    for (int64_t c = 0; c < o->pt5.n; ++c)
+        if (o->pt5_keep[c]) used[P5[c].seed] = 1;
+
+    /* 2. pT3 from the unused pLS */
+    for (int32_t i = 0; i < n_seeds; ++i) {
+        if (used[i]) continue;
+        const int32_t *h = &seeds[4 * i];
+        for (int64_t t = 0; t < n3; ++t) {
+            CUTREC wf, wd;
+            int pw = link_window_f(sd[3 * i], sd[3 * i + 1], sd[3 * i + 2], d3[3 * t],
+                                   d3[3 * t + 1], d3[3 * t + 2], wl2, &wf);
+            link_window_d(sd[3 * i], sd[3 * i + 1], sd[3 * i + 2], d3[3 * t], d3[3 * t + 1],
+                          d3[3 * t + 2], wl2, &wd);
+            if (cut_margin(&wf, &wd) < NEAR_REL) o->px_near++;
+            if (!pw) continue;
+            lpt_f pf[7]; lpt_d pd[7];
+            for (int k = 0; k < 4; ++k) lpt_px(x[h[k]], y[h[k]], z[h[k]], &pf[k], &pd[k]);
+            lpt_md(&MD[T3[t].a], &pf[4], &pd[4]);
+            lpt_md(&MD[T3[t].b], &pf[5], &pd[5]);
+            lpt_md(&MD[T3[t].c], &pf[6], &pd[6]);
+            CUTREC cf, cd;
+            float sc;
+            double scd;
+            int pass = link_cut_f(K, pf, 7, 4, sig2p, sigz, x3p, x3z, &cf, &sc);
+            link_cut_d(K, pd, 7, 4, sig2p, sigz, x3p, x3z, &cd, &scd);
+            if (cut_margin(&cf, &cd) < NEAR_REL) o->px_near++;
+            if (pass) {
+                PXREC *r = (PXREC *)gv_push(&o->pt3);
+                r->seed = i; r->obj = (int32_t)t; r->score = sc;
+            }
+        }
+    }
+    o->pt3_keep = (uint8_t *)malloc((size_t)(o->pt3.n > 0 ? o->pt3.n : 1));
+    px_dedup(o, seeds, &o->pt3, 6, o->pt3_keep);
+    const PXREC *P3 = (const PXREC *)o->pt3.v;
+
+    /* hit sets of the surviving pT5 */
+    HITSET hs;
+    int32_t tup[10];
+    int64_t np5 = o->pt5.n, np3 = o->pt3.n;
+
+    /* 3. pT3 against the surviving pT5 */
+    for (int64_t c = 0; c < np3; ++c) {
+        if (!o->pt3_keep[c]) continue;
+        HITSET hc;
+        int32_t tc[10];
+        px_hits(o, seeds, &P3[c], 6, &hc, tc);
+        const float *a = &sd[3 * P3[c].seed];
+        for (int64_t u = 0; u < np5 && o->pt3_keep[c]; ++u) {
+            if (!o->pt5_keep[u]) continue;
+            px_hits(o, seeds, &P5[u], 10, &hs, tup);
+            const float *b = &sd[3 * P5[u].seed];
+            CUTREC ff, fd;
+            int near = close_cut_f(a[0], a[1], a[2], b[0], b[1], b[2], dr2, &ff);
+            close_cut_d(a[0], a[1], a[2], b[0], b[1], b[2], dr2, &fd);
+            if (cut_margin(&ff, &fd) < NEAR_REL) o->px_near++;
+            if (near || hits_share(&hc, &hs)) o->pt3_keep[c] = 0;
+        }
+    }
+
+    /* 4. kept quintuplets against the surviving pT5 and cleaned pT3 */
+    o->t5_clean = (uint8_t *)malloc((size_t)(n5 > 0 ? n5 : 1));
+    for (int64_t t = 0; t < n5; ++t) {
+        o->t5_clean[t] = o->keep[t];
+        if (!o->keep[t]) continue;
+        HITSET ht;
+        ht.n = 0;
+        for (int j = 0; j < 5; ++j) {
+            md_hits(o, T5[t].md[j], &tup[2 * j]);
+        }
+        for (int k = 0; k < 10; ++k) { ht.id[ht.n] = tup[k]; ht.kind[ht.n++] = 1; }
+        const float *a = &d5[3 * t];
+        for (int pass = 0; pass < 2 && o->t5_clean[t]; ++pass) {
+            const gvec *v = pass ? &o->pt3 : &o->pt5;
+            const uint8_t *kp = pass ? o->pt3_keep : o->pt5_keep;
+            const PXREC *Q = (const PXREC *)v->v;
+            for (int64_t u = 0; u < v->n && o->t5_clean[t]; ++u) {
+                if (!kp[u]) continue;
+                int32_t tu[10];
+                px_hits(o, seeds, &Q[u], pass ? 6 : 10, &hs, tu);
+                const float *b = &sd[3 * Q[u].seed];
+                CUTREC ff, fd;
+                int near = close_cut_f(a[0], a[1], a[2], b[0], b[1], b[2], dr2, &ff);
+                close_cut_d(a[0], a[1], a[2], b[0], b[1], b[2], dr2, &fd);
+                if (cut_margin(&ff, &fd) < NEAR_REL) o->px_near++;
+                if (near || hits_share(&ht, &hs)) o->t5_clean[t] = 0;
+            }
+        }
+    }
+
+    /* 5. pLS used by neither, against everything above, then among themselves */
+    for (int64_t c = 0; c < np3; ++c)
+        if (o->pt3_keep[c]) used[P3[c].seed] = 1;
+    o->pls_keep = (uint8_t *)malloc((size_t)(n_seeds > 0 ? n_seeds : 1));
+    for (int32_t i = 0; i < n_seeds; ++i) {
+        o->pls_keep[i] = !used[i];
+        if (used[i]) continue;
+        HITSET hi;
+        hi.n = 4;
+        for (int k = 0; k < 4; ++k) { hi.id[k] = seeds[4 * i + k]; hi.kind[k] = 0; }
+        const float *a = &sd[3 * i];
+        for (int pass = 0; pass < 3 && o->pls_keep[i]; ++pass) {
+            int64_t n = pass == 0 ? np5 : pass == 1 ? np3 : n5;
+            for (int64_t u = 0; u < n && o->pls_keep[i]; ++u) {
+                const float *b;
+                int share = 0;
+                if (pass < 2) {
+                    const PXREC *Q = pass ? &P3[u] : &P5[u];
+                    if (!(pass ? o->pt3_keep[u] : o->pt5_keep[u])) continue;
+                    HITSET hq;
+                    hq.n = 4;
+                    for (int k = 0; k < 4; ++k) { hq.id[k] = seeds[4 * Q->seed + k]; hq.kind[k] = 0; }
+                    share = hits_share(&hi, &hq);
+                    b = &sd[3 * Q->seed];
+                } else {
+                    if (!o->t5_clean[u]) continue;
+                    b = &d5[3 * u];
+                }
+                CUTREC ff, fd;
+                int near = close_cut_f(a[0], a[1], a[2], b[0], b[1], b[2], dr2, &ff);
+                close_cut_d(a[0], a[1], a[2], b[0], b[1], b[2], dr2, &fd);
+                if (cut_margin(&ff, &fd) < NEAR_REL) o->px_near++;
+                if (near || share) o->pls_keep[i] = 0;
+            }
+        }
+    }
+    /* among the remaining pLS: a smaller index sharing a pixel hit wins */
+    uint8_t *rem = (uint8_t *)malloc((size_t)(n_seeds > 0 ? n_seeds : 1));
+    memcpy(rem, o->pls_keep, (size_t)(n_seeds > 0 ? n_seeds : 1));
+    for (int32_t i = 0; i < n_seeds; ++i) {
+        if (!rem[i]) continue;
+        for (int32_t j = 0; j < i && o->pls_keep[i]; ++j) {
+            if (!rem[j]) continue;
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b)
+                    if (seeds[4 * i + a] == seeds[4 * j + b]) o->pls_keep[i] = 0;
+        }
+    }
+    free(rem);
+
+    /* 6. track candidates */
+    for (int64_t c = 0; c < np5; ++c) {
+        if (!o->pt5_keep[c]) continue;
+        TCREC *r = (TCREC *)gv_push(&o->tc);
+        r->type = ORC_TC_PT5; r->seed = P5[c].seed;
+        for (int j = 0; j < 5; ++j) md_hits(o, T5[P5[c].obj].md[j], &r->hits[2 * j]);
+    }
+    for (int64_t c = 0; c < np3; ++c) {
+        if (!o->pt3_keep[c]) continue;
+        TCREC *r = (TCREC *)gv_push(&o->tc);
+        r->type = ORC_TC_PT3; r->seed = P3[c].seed;
+        const T3REC *T = &T3[P3[c].obj];
+        md_hits(o, T->a, &r->hits[0]); md_hits(o, T->b, &r->hits[2]); md_hits(o, T->c, &r->hits[4]);
+        for (int k = 6; k < 10; ++k) r->hits[k] = -1;
+    }
+    for (int64_t t = 0; t < n5; ++t) {
+        if (!o->t5_clean[t]) continue;
+        TCREC *r = (TCREC *)gv_push(&o->tc);
+        r->type = ORC_TC_T5; r->seed = -1;
+        for (int j = 0; j < 5; ++j) md_hits(o, T5[t].md[j], &r->hits[2 * j]);
+    }
+    for (int32_t i = 0; i < n_seeds; ++i) {
+        if (!o->pls_keep[i]) continue;
+        TCREC *r = (TCREC *)gv_push(&o->tc);
+        r->type = ORC_TC_PLS; r->seed = i;
+        for (int k = 0; k < 10; ++k) r->hits[k] = -1;
+    }
+    free(used); free(sd); free(d5); free(d3);
+    return 0;
+}
+
+int64_t orc_px_count(const orc *o, int what)
+{
+    int64_t c = 0;
+    switch (what) {
+    case 0: return o->pt5.n;
+    case 1: for (int64_t i = 0; i < o->pt5.n; ++i) c += o->pt5_keep[i]; return c;
+    case 2: return o->pt3.n;
+    case 3: for (int64_t i = 0; i < o->pt3.n; ++i) c += o->pt3_keep[i]; return c;
+    case 4: return o->tc.n;
+    case 5: return o->px_near;
+    }
+    return -1;
+}
+
+/* candidates of pT5 (what 0) or pT3 (what 2): seed, object tuple (10 or 6
+ * hits, -1 padded), score bits, survived the collection's dedup */
+void orc_px_candidates(const orc *o, int what, int32_t *out13)
+{
+    const gvec *v = what == 0 ? &o->pt5 : &o->pt3;
+    const PXREC *C = (const PXREC *)v->v;
+    const uint8_t *kp = what == 0 ? o->pt5_keep : o->pt3_keep;
+    for (int64_t i = 0; i < v->n; ++i) {
+        int32_t *r = &out13[13 * i];
+        HITSET h;
+        int32_t tup[10];
+        for (int k = 0; k < 10; ++k) tup[k] = -1;
+        px_hits(o, o->seeds, &C[i], what == 0 ? 10 : 6, &h, tup);
+        r[0] = C[i].seed;
+        memcpy(&r[1], tup, sizeof(tup));
+        memcpy(&r[11], &C[i].score, sizeof(float));
+        r[12] = kp[i];
+    }
+}
+
+void orc_tc(const orc *o, int32_t *out12)
+{
+    const TCREC *T = (const TCREC *)o->tc.v;
+    for (int64_t i = 0; i < o->tc.n; ++i) {
+        out12[12 * i] = T[i].type;
+        out12[12 * i + 1] = T[i].seed;
+        memcpy(&out12[12 * i + 2], T[i].hits, sizeof(T[i].hits));
+    }
+}
+
+/* Single-candidate evaluation of a pixel link (closed-form checks): a pLS of
+ * four pixel hits (pix12: x, y, z of each, inner to outer) with the outer
+ * object built from n_md = 5 (quintuplet) or 3 (triplet) MDs given as
+ * (module, lower hit, upper hit).  out: pLS tx, ty, cot; object tx, ty, cot;
+ * window dot, sin^2, polar term; chi2_rphi, chi2_rz, score.  Returns the
+ * FP32 decision of window and chi2 cuts together. */
+int orc_eval_link(const orc *o, const double *pp, const float *pix12, int n_md,
+                  const int32_t *mods, const float *hits, double *out)
+{
+    if (n_md != 3 && n_md != 5) return -1;
+    MDREC md[5];
+    eval_mds(o, n_md, mods, hits, md);
+    const KCONST *K = &o->K;
+    float x[4], y[4], z[4];
+    for (int k = 0; k < 4; ++k) { x[k] = pix12[3 * k]; y[k] = pix12[3 * k + 1]; z[k] = pix12[3 * k + 2]; }
+    const int32_t sd[4] = {0, 1, 2, 3};
+    float ptx, pty, pc, otx, oty, oc;
+    pix_dir(x, y, z, sd, &ptx, &pty, &pc);
+    float k = 0.0f;
+    if (n_md == 5) {
+        k = t5_kbr(&md[0], &md[2], &md[4]);
+    } else {
+        CUTREC c3;
+        t3_cut_f(K, &md[0], &md[1], &md[2], &c3, &k, NULL);
+    }
+    obj_dir(&md[0], &md[n_md - 1], k, &otx, &oty, &oc);
+    const double wl = pp[ORC_PX_WLINK] * (double)K->w;
+    CUTREC wf;
+    int pw = link_window_f(ptx, pty, pc, otx, oty, oc, (float)(wl * wl), &wf);
+    lpt_f pf[9]; lpt_d pd[9];
+    for (int j = 0; j < 4; ++j) lpt_px(x[j], y[j], z[j], &pf[j], &pd[j]);
+    for (int j = 0; j < n_md; ++j) lpt_md(&md[j], &pf[4 + j], &pd[4 + j]);
+    CUTREC cf;
+    float sc;
+    const float sig2p = (float)(pp[ORC_PX_SIGRPHI] * pp[ORC_PX_SIGRPHI]);
+    int pass = n_md == 5
+        ? link_cut_f(K, pf, 9, 6, sig2p, (float)pp[ORC_PX_SIGZ], (float)pp[ORC_PX_X5P],
+                     (float)pp[ORC_PX_X5Z], &cf, &sc)
+        : link_cut_f(K, pf, 7, 4, sig2p, (float)pp[ORC_PX_SIGZ], (float)pp[ORC_PX_X3P],
+                     (float)pp[ORC_PX_X3Z], &cf, &sc);
+    out[0] = ptx; out[1] = pty; out[2] = pc; out[3] = otx; out[4] = oty; out[5] = oc;
+    out[6] = -wf.lhs[0]; out[7] = wf.lhs[1]; out[8] = wf.lhs[2];
+    out[9] = cf.lhs[0]; out[10] = cf.lhs[1]; out[11] = sc;
+    return pw && pass;
 }

@@ -94,6 +94,50 @@ int orc_eval_t5_features(const orc *o, const int32_t *mods5, const float *hits30
  * decides it, infinite when two or more cuts fail */
 double orc_eval_margin(const orc *o, int kind, const int32_t *mods, const float *hits);
 
+/* Per-module capacities (Sec. 3: fixed per-module output arrays truncated at
+ * an occupancy quantile) of MD, SEG, T3, T5 (caps4; 0 or NULL: none), applied
+ * from the next orc_run on: a module (that of an object's first MD) holding
+ * more objects of a kind than its capacity keeps those with the smallest hit
+ * tuples; later stages are built from the kept objects only.  orc_dropped:
+ * objects removed per kind in the last event.  Returns -1 on a negative cap. */
+int orc_set_truncation(orc *o, const int32_t *caps4);
+void orc_dropped(const orc *o, int64_t *out4);
+
+/* ---- pixel objects (Sec. 2.1; kernel-flow figure of Sec. 3) ----
+ * Pixel parameter vector (double): pixel hit resolution across the track and
+ * along z (cm), linking window (sine of the angle, scaled by the window scale
+ * W), cross-cleaning distance (squared, eta-phi), chi2 limits of pT5 (r-phi
+ * 6 dof, r-z 7 dof) and pT3 (r-phi 4 dof, r-z 5 dof). */
+enum {
+    ORC_PX_SIGRPHI = 0, ORC_PX_SIGZ, ORC_PX_WLINK, ORC_PX_DR2, ORC_PX_X5P, ORC_PX_X5Z,
+    ORC_PX_X3P, ORC_PX_X3Z, ORC_PX_N_PARAMS
+};
+/* track-candidate types */
+enum { ORC_TC_PT5 = 0, ORC_TC_PT3 = 1, ORC_TC_T5 = 2, ORC_TC_PLS = 3 };
+
+/* pixel objects of the last orc_run: pixel hits (x, y, z, n_px) and seeds
+ * (4 pixel hit indices each, inner to outer).  -1 on bad input or when no
+ * event ran. */
+int orc_run_pixel(orc *o, const double *pix_params, int n_pp, int32_t n_px, const float *x,
+                  const float *y, const float *z, int32_t n_seeds, const int32_t *seeds);
+/* what: 0 pT5 candidates, 1 surviving pT5, 2 pT3 candidates, 3 surviving
+ * pT3 (after cross-cleaning), 4 track candidates, 5 near-threshold pixel
+ * decisions */
+int64_t orc_px_count(const orc *o, int what);
+/* candidates (what 0: pT5, 2: pT3), 13 ints each: seed, 10 outer hits (-1
+ * padded), score bits, survived the collection's duplicate removal */
+void orc_px_candidates(const orc *o, int what, int32_t *out13);
+/* track candidates, 12 ints each: type, seed (-1 for T5), 10 outer hits
+ * (-1 padded) */
+void orc_tc(const orc *o, int32_t *out12);
+
+/* single pixel link for closed-form checks: pix12 = four pixel hits (x, y,
+ * z), n_md = 5 or 3 MDs (mods, hits as for orc_eval_t5); out12: pLS tx, ty,
+ * cot, object tx, ty, cot, window cos-term, sin^2, polar term, chi2_rphi,
+ * chi2_rz, score; returns the FP32 decision (window and chi2 cuts) */
+int orc_eval_link(const orc *o, const double *pix_params, const float *pix12, int n_md,
+                  const int32_t *mods, const float *hits, double *out12);
+
 /* derived FP32 constants (for inspection): kmax, klim, kh, tolu, tolv, tolkc, epsak */
 void orc_consts(const orc *o, float *out7);
 

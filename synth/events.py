@@ -340,3 +340,86 @@ def generate_batch(cid: int, n_events: int | None = None, purpose: int = PURPOSE
     cfg = CONFIGS[cid]
     n = cfg.n_events if n_events is None else n_events
     return concat([generate(cid, first_event + e, purpose) for e in range(n)])
+
+
+# ----------------------------------------------------------------------------
+# pixel detector and pixel seeds (input of the pixel line segments, Sec. 2.1)
+# ----------------------------------------------------------------------------
+PURPOSE_PIXEL = 3
+PIXEL_RADII = (3.0, 6.8, 10.9, 16.0)   # cm, four idealised barrel cylinders
+SIGMA_PIX_RPHI = 0.0010                # cm (10 um)
+SIGMA_PIX_Z = 0.0020                   # cm (20 um)
+PIXEL_SEED_PT = 0.8                    # GeV: seeds of simulated tracks above it
+PIXEL_FAKE_FRAC = 0.05                 # fake seeds per real seed
+
+
+@dataclass
+class PixelSeeds:
+    """Pixel hits of one event and its seeds (four hit indices each, inner to
+    outer).  Stand-in for the pixel tracking that feeds the method: every
+    simulated track above PIXEL_SEED_PT crossing all four layers (each hit
+    kept with probability 1 - ineff) gives a seed, and PIXEL_FAKE_FRAC fake
+    seeds join the two inner hits of one track to the two outer hits of
+    another track close to it in azimuth."""
+    x: np.ndarray            # float32 [n_px]
+    y: np.ndarray
+    z: np.ndarray
+    truth: np.ndarray        # int32 track id of each pixel hit
+    seeds: np.ndarray        # int32 [n_seeds, 4] pixel hit indices
+
+    @property
+    def n_hits(self) -> int:
+        return int(self.x.shape[0])
+
+    @property
+    def n_seeds(self) -> int:
+        return int(self.seeds.shape[0])
+
+
+def pixel_seeds(ev: Event, cid: int, event: int, cfg: EventConfig | None = None) -> PixelSeeds:
+    """Pixel hits and seeds of event `event` of configuration `cid` (its own
+    random stream: the outer-tracker hits of the event are unchanged)."""
+    cfg = cfg or CONFIGS[cid]
+    rng = rng_for(cfg.cid, event, PURPOSE_PIXEL)
+    trk = ev.tracks
+    hel = Helices(trk["pt"], trk["eta"], trk["phi0"], trk["q"], trk["z0"], trk["d0"])
+    n = hel.pt.shape[0]
+    pos = np.full((n, 4, 3), np.nan)
+    for j, r in enumerate(PIXEL_RADII):
+        s = hel.s_at_radius(r)
+        ok = np.isfinite(s)
+        x, y, z = hel.pos(np.where(ok, s, 0.0))
+        # smearing along the azimuthal direction and along z
+        d = rng.normal(0.0, SIGMA_PIX_RPHI, n)
+        dz = rng.normal(0.0, SIGMA_PIX_Z, n)
+        rr = np.maximum(np.hypot(x, y), 1e-9)
+        x, y, z = x - d * y / rr, y + d * x / rr, z + dz
+        hit = ok & (rng.uniform(0.0, 1.0, n) >= cfg.ineff)
+        pos[hit, j] = np.stack([x[hit], y[hit], z[hit]], axis=1)
+    has = np.all(np.isfinite(pos[:, :, 0]), axis=1)
+    # every pixel hit, track-major, then shuffled
+    tr_of, lay_of = np.nonzero(np.isfinite(pos[:, :, 0]))
+    px = pos[tr_of, lay_of]
+    perm = rng.permutation(tr_of.shape[0])
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.shape[0])
+    index = np.full((n, 4), -1, np.int64)
+    index[tr_of, lay_of] = inv
+    real = np.nonzero(has & (hel.pt >= PIXEL_SEED_PT))[0]
+    seeds = [index[t] for t in real]
+    n_fake = int(round(PIXEL_FAKE_FRAC * real.shape[0]))
+    if n_fake and real.shape[0] > 1:
+        phi = np.arctan2(pos[real, 3, 1], pos[real, 3, 0])
+        order = np.argsort(phi)
+        for _ in range(n_fake):
+            i = int(rng.integers(0, real.shape[0]))
+            k = int(np.searchsorted(phi[order], phi[i]))
+            j = order[(k + int(rng.choice([-2, -1, 1, 2]))) % real.shape[0]]
+            a, b = real[i], real[j]
+            if a != b:
+                seeds.append(np.r_[index[a, :2], index[b, 2:]])
+    seeds = np.array(seeds, np.int64).reshape(-1, 4)
+    seeds = seeds[rng.permutation(seeds.shape[0])]
+    return PixelSeeds(x=px[perm, 0].astype(np.float32), y=px[perm, 1].astype(np.float32),
+                      z=px[perm, 2].astype(np.float32), truth=tr_of[perm].astype(np.int32),
+                      seeds=seeds.astype(np.int32))

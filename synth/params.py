@@ -39,3 +39,28 @@ def make(**over) -> np.ndarray:
             raise KeyError(k)
         d[k] = v
     return np.array([d[n] for n in NAMES], dtype=np.float64)
+
+
+# pixel objects (pLS, pT3, pT5, cross-cleaning): the synthetic pixel
+# detector's resolutions and this project's window, cleaning distance and
+# chi2 limits at p = 1e-3 (the paper prints none)
+PIX_NAMES = ("sig_rphi", "sig_z", "wlink", "dr2", "x5p", "x5z", "x3p", "x3z")
+PIX_DEFAULTS = dict(
+    sig_rphi=0.0010,    # cm, pixel hit resolution across the track
+    sig_z=0.0020,       # cm, along z
+    wlink=0.05,         # sine of the largest angle between a pLS and an object it links to
+    dr2=1e-3,           # squared eta-phi distance of duplicates in cross-cleaning
+    x5p=22.46,          # pT5 r-phi chi2 (6 dof)
+    x5z=24.32,          # pT5 r-z chi2 (7 dof)
+    x3p=18.47,          # pT3 r-phi chi2 (4 dof)
+    x3z=20.52,          # pT3 r-z chi2 (5 dof)
+)
+
+
+def make_pixel(**over) -> np.ndarray:
+    d = dict(PIX_DEFAULTS)
+    for k, v in over.items():
+        if k not in d:
+            raise KeyError(k)
+        d[k] = v
+    return np.array([d[n] for n in PIX_NAMES], dtype=np.float64)
