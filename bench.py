@@ -487,7 +487,10 @@ def memory(lst, torch, G, PR, evs, quantiles=(0.999, 0.9999)):
     counts over all modules of all events, the arena bytes those capacities
     imply, and the share of objects that modules above capacity would drop.
     The library itself sizes its object arrays by the event's counts and
-    drops nothing."""
+    drops nothing; with the same capacities set in the chain
+    (lst_set_capacities) each stage drops what a full module cannot hold, and
+    the leg reports the resulting efficiency and fake rate (one batched
+    launch of the 16 events) against the uncapped chain."""
     geo = G.get("full")
     ctx = lst.Context(PR.make(), geo.f32, geo.i32, device=0)
     kinds = {"md": lst.LST_MD, "seg": lst.LST_SEG, "t3": lst.LST_T3, "t5": lst.LST_T5}
@@ -506,15 +509,39 @@ def memory(lst, torch, G, PR, evs, quantiles=(0.999, 0.9999)):
            "exact_arena_MB": ctx.arena_bytes(exact) / 1e6,
            "grown_arena_MB": ctx.arena_bytes(ctx.caps) / 1e6,
            "exact_caps": {k: int(exact[k]) for k in kinds}}
+    from paper_2209_13711_amd import scorer as S
+    keys = ("eff", "fake", "dup", "n_obj")
+    m_exact = S.evaluate(ctx, evs, geo)
+    out["chain_exact"] = {k: m_exact[k] for k in keys}
+    stream = torch.cuda.current_stream()
     for name, q in [(f"q{100 * q:g}", q) for q in quantiles] + [("max", None)]:
         cap = {k: int(np.ceil(np.quantile(c, q))) if q is not None else int(c.max())
                for k, c in counts.items()}
         caps = dict(exact, **{k: max(1, cap[k] * geo.n_mod) for k in kinds})
+        # the capacities applied in the chain (lst_set_capacities): what each
+        # stage removes, and the efficiency / fake rate of what is left
+        cctx = lst.Context(PR.make(), geo.f32, geo.i32, device=0)
+        cctx.set_capacities([max(1, cap[k]) for k in kinds])
+        m = S.evaluate(cctx, evs, geo)
+        dropped = np.sum([cctx.counts(e)["dropped"] for e in range(len(evs))], axis=0)
+        assert_clean(cctx)
+        cctx.run_chain_graph(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            cctx.run_chain_graph(stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 10
+        del cctx
         out[f"per_module_{name}"] = {
             "cap_per_module": cap,
             "arena_MB": ctx.arena_bytes(caps) / 1e6,
             "dropped_frac": {k: float(np.maximum(counts[k] - cap[k], 0).sum() /
-                                      max(counts[k].sum(), 1)) for k in kinds}}
+                                      max(counts[k].sum(), 1)) for k in kinds},
+            "chain_capped": dict({k: m[k] for k in keys},
+                                 dropped={k: int(d) for k, d in zip(kinds, dropped)},
+                                 eff_loss_points=100 * (m_exact["eff"] - m["eff"]),
+                                 events_per_s=len(evs) / dt)}
     del ctx
     return out
 

@@ -101,6 +101,9 @@ typedef struct {
     int64_t t3;
     int64_t t5;
     int32_t features; /* nonzero: also hold the 40 scorer features per quintuplet */
+    int64_t px_hits;  /* pixel hits (lst_load_pixel; 0: no pixel objects) */
+    int64_t seeds;    /* pixel seeds (pLS) */
+    int64_t px_cand;  /* link candidates of each kind (pT5, pT3) */
 } lst_caps;
 
 /* per-event result summary.  n_* are the numbers of objects and cand_* the
@@ -119,6 +122,12 @@ typedef struct {
     int64_t n_hits, n_md, n_seg, n_t3, n_t5, n_t5_kept;
     int64_t cand_md, cand_seg, cand_t3, cand_t5;
     int32_t overflow_mask, error_flags;
+    int64_t dropped[4]; /* MD, SEG, T3, T5 removed by per-module capacities
+                           (lst_set_capacities; 0 without them) */
+    /* after lst_run_pixel: pixel seeds; pT5 link candidates and survivors;
+     * pT3 link candidates and those left after cross-cleaning; track
+     * candidates (pT5 + pT3 + T5 + pLS); 0 before */
+    int64_t n_pls, cand_pt5, n_pt5, cand_pt3, n_pt3, n_tc;
 } lst_counts;
 
 /* Create a context on HIP device `device`.  params: LST_N_PARAMS doubles. */
@@ -162,6 +171,23 @@ int lst_load_hits(lst_ctx *ctx, int32_t n_events, const int32_t *hit_offsets, co
                   const float *y, const float *z, const int32_t *module, const uint8_t *sensor,
                   int on_device, void *stream);
 
+/* Per-module capacities (Sec. 3: every object kind held in arrays of a fixed
+ * capacity per module, set at the 99.9 % or 99.99 % quantile of the
+ * per-module occupancy, at a cost of 1-2 % in efficiency).  caps4 = the
+ * capacity of MD, SEG, T3, T5 per module (0: none; NULL: all off), applied by
+ * every later chain: right after a stage, a module (that of an object's first
+ * mini-doublet) holding more objects of the stage's kind than its capacity
+ * keeps the ones whose tuples of per-event hit indices are smallest
+ * (lexicographic order) and the others are removed before the next stage
+ * runs; lst_counts.dropped reports how many per kind.  The rule is
+ * deterministic (the paper's GPU keeps whichever objects arrive first).  The
+ * arrays stay compact: the mode reproduces the paper's selection, and the
+ * memory its fixed per-module layout would take is caps x modules.  Runs
+ * with the per-stage chain (lst_run_chain, lst_run_chain_graph); the
+ * persistent kernel returns LST_E_STATE while capacities are set.
+ * LST_E_INVALID for a negative capacity. */
+int lst_set_capacities(lst_ctx *ctx, const int32_t *caps4);
+
 /* Stages (asynchronous on `stream`), each requiring the previous one:
  * lst_run_sort      hits grouped by (event, module, sensor)
  * lst_run_md        mini-doublets (stubs), Sec. 2
@@ -193,6 +219,62 @@ int lst_run_chain_graph(lst_ctx *ctx, void *stream);
  * LST_E_FAULT when a kernel-side wait timed out and LST_E_CAPACITY when any
  * stage overflowed (counts still filled in both cases). */
 int lst_get_counts(lst_ctx *ctx, int32_t event, lst_counts *out, void *stream);
+
+/* ---- pixel objects and track candidates (Sec. 2.1; kernel-flow figure of
+ * Sec. 3) ------------------------------------------------------------------
+ * Pixel parameters (double, in this order): pixel hit resolution across the
+ * track and along z (cm); linking window (sine of the largest angle between
+ * a pLS and an object it links to, times the window scale); squared eta-phi
+ * distance under which cross-cleaning calls two objects duplicates; chi2
+ * limits of pT5 (r-phi, r-z) and pT3 (r-phi, r-z). */
+enum lst_pix_param {
+    LST_PX_SIGRPHI = 0, LST_PX_SIGZ, LST_PX_WLINK, LST_PX_DR2, LST_PX_X5P, LST_PX_X5Z,
+    LST_PX_X3P, LST_PX_X3Z, LST_PX_N_PARAMS
+};
+/* track-candidate types */
+enum lst_tc_type { LST_TC_PT5 = 0, LST_TC_PT3 = 1, LST_TC_T5 = 2, LST_TC_PLS = 3 };
+
+/* Pixel hits and seeds of the batch loaded by lst_load_hits (same n_events;
+ * host arrays, copied, asynchronous on `stream` like lst_load_hits):
+ * px_offsets[n_events + 1] first pixel hit of each event in x, y, z;
+ * seed_offsets[n_events + 1] first seed of each event; seeds: four pixel hit
+ * indices per seed, inner to outer, counted inside the seed's event.  A seed
+ * index is its position inside its event.  Needs an arena whose caps hold
+ * the pixel hits, seeds and link candidates (LST_E_CAPACITY otherwise);
+ * LST_E_INVALID for a hit index outside its event or bad parameters. */
+int lst_load_pixel(lst_ctx *ctx, int32_t n_events, const int32_t *px_offsets, const float *x,
+                   const float *y, const float *z, const int32_t *seed_offsets,
+                   const int32_t *seeds, const double *pix_params, int32_t n_pix_params,
+                   void *stream);
+
+/* The pixel stage after a whole chain (duplicate removal done) of the same
+ * batch: each pLS linked to the kept quintuplets of its event (pT5) when
+ * their directions lie inside the linking window and the chain of its four
+ * pixel hits and five anchors passes the r-phi chi2 (circle through its
+ * first hit and the 3rd and 5th anchors) and r-z chi2 (line in arc length)
+ * cuts, score = their sum; inside the collection a pT5 survives iff no pT5
+ * sharing one of its hits (pixel or outer) has a smaller (score, seed, hit
+ * tuple) key.  The pLS no surviving pT5 uses link to the triplets (pT3, the
+ * same way, circle through its first hit and the 1st and 3rd anchors).
+ * Cross-cleaning in the paper's order: pT3 near a pT5 in eta-phi or sharing
+ * a hit with one are duplicates; then kept quintuplets near or sharing a hit
+ * with a pT5 or cleaned pT3; then the pLS used by neither, against all of
+ * them, and among themselves the smaller seed index keeps a shared pixel
+ * hit.  Asynchronous; per-stage chain, graph and persistent runs alike. */
+int lst_run_pixel(lst_ctx *ctx, void *stream);
+
+/* Track candidates of `event` (synchronises): 12 int32 per candidate: type
+ * (lst_tc_type), seed index (-1 for T5), the outer hit tuple (10 hits for pT5
+ * and T5, 6 for pT3, -1 padded).  *n set even when cap is too small
+ * (LST_E_CAPACITY).  Order: pT5, pT3, T5, pLS. */
+int lst_get_track_candidates(lst_ctx *ctx, int32_t event, int32_t *out12, int64_t cap,
+                             int64_t *n, void *stream);
+
+/* Link candidates of `event` (what 0: pT5, 1: pT3), 13 int32 each: seed,
+ * outer hit tuple (-1 padded to 10), score bits, kept (pT5: survived the
+ * collection's duplicate removal; pT3: also the cross-cleaning). */
+int lst_get_pixel_candidates(lst_ctx *ctx, int32_t event, int32_t what, int32_t *out13,
+                             int64_t cap, int64_t *n, void *stream);
 
 /* Error-path hook for tests of the callers' handling of LST_E_FAULT: ORs
  * `bits` (error_flags bits 1 and 2 only) into the context's device error

@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 SO = os.path.join(LIBDIR, "liblst.so")
-SOURCES = ["lst_api.cpp", "lst_map.cpp", "lst_kernels.hip", "lst_mlp.hip"]
+SOURCES = ["lst_api.cpp", "lst_map.cpp", "lst_kernels.hip", "lst_mlp.hip", "lst_cap.hip",
+           "lst_pixel.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -64,6 +65,12 @@ struct lst_ctx {
     float mlp_threshold[2] = {0.0f, 0.0f};
     bool t3_features_valid = false;
     void *fixed_work = nullptr;   // this device's copy of the fixed backward workspace
+    int32_t cap[OT_COUNT] = {0, 0, 0, 0};   // per-module capacities (0: none)
+    // pixel objects: constants of the loaded pixel parameters, host copy of
+    // the batch's seed and pixel offsets, loaded for the current hits
+    PixConsts pxk{};
+    std::vector<int32_t> px_off, sd_off;
+    bool px_loaded = false;
     std::vector<lst_counts> counts;
     bool counts_valid = false;
     int stage = 0;  // 0 nothing, 1 hits loaded, 2 sorted, 3 md, 4 seg, 5 t3, 6 t5, 7 dedup
@@ -133,7 +140,9 @@ bool caps_ok(const lst_caps *k)
 {
     return k && k->events > 0 && k->hits >= 0 && k->md >= 0 && k->seg >= 0 && k->t3 >= 0 &&
            k->t5 >= 0 && k->hits < (1ll << 31) && k->md < (1ll << 31) &&
-           k->seg < (1ll << 31) && k->t3 < (1ll << 31) && k->t5 < (1ll << 31);
+           k->seg < (1ll << 31) && k->t3 < (1ll << 31) && k->t5 < (1ll << 31) &&
+           k->px_hits >= 0 && k->seeds >= 0 && k->px_cand >= 0 && k->px_hits < (1ll << 31) &&
+           k->seeds < (1ll << 29) && k->px_cand < (1ll << 31);
 }
 
 // Lay the arrays out; with base == nullptr only the size is computed.
@@ -224,6 +233,56 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.t5_ho = cv.take<int32_t>(nt5 * 10);
     E.t5_feat = k.features ? cv.take<float>(nt5 * 40) : nullptr;
     E.t5_logit = cv.take<float>(nt5);
+    E.t5_start = cv.take<int32_t>(nmd);
+    E.t5_cnt = cv.take<int32_t>(nmd);
+    // per-module capacities
+    const size_t span_max = std::max(std::max(nmd, nseg), std::max(nt3, nt5));
+    uint32_t rc_max = 0;
+    for (int t = 0; t < OT_COUNT; ++t) rc_max = std::max(rc_max, E.rc[t]);
+    E.cap_drop = cv.take<uint8_t>((span_max + 15) & ~(size_t)15);
+    E.cap_pre = cv.take<int32_t>((size_t)NSH * (rc_max + 1));
+    E.cap_nd = cv.take<uint32_t>(((size_t)k.events * OT_COUNT + 3) & ~(size_t)3);
+    // pixel objects (only with pixel capacities)
+    E.cap_px = (int32_t)k.px_hits;
+    E.cap_seeds = (int32_t)k.seeds;
+    E.cap_pxc = (int32_t)k.px_cand;
+    if (k.seeds > 0) {
+        E.px_x = cv.take<float>(k.px_hits);
+        E.px_y = cv.take<float>(k.px_hits);
+        E.px_z = cv.take<float>(k.px_hits);
+        E.px_off = cv.take<int32_t>(k.events + 1);
+        E.sd_off = cv.take<int32_t>(k.events + 1);
+        E.sd_hits = cv.take<int32_t>((size_t)k.seeds * 4);
+        E.sd_ev = cv.take<int32_t>(k.seeds);
+        E.sd_local = cv.take<int32_t>(k.seeds);
+        E.sd_dir = cv.take<float4>(k.seeds);
+        E.sd_used = cv.take<uint8_t>(k.seeds);
+        E.sd_keep = cv.take<uint8_t>(k.seeds);
+        E.t5_dir = cv.take<float4>(nt5);
+        E.t3_dir = cv.take<float4>(nt3);
+        E.t5_clean = cv.take<uint8_t>(nt5);
+        E.pl_cnt = cv.take<int32_t>((size_t)PXL_COUNT * k.events);
+        E.pl_fill = cv.take<int32_t>((size_t)PXL_COUNT * k.events);
+        E.pl_off = cv.take<int32_t>((size_t)PXL_COUNT * (k.events + 1));
+        E.pl_k5 = cv.take<int32_t>(nt5);
+        E.pl_k3 = cv.take<int32_t>(nt3);
+        E.pl_d5 = cv.take<float4>(k.px_cand);
+        E.pl_d3 = cv.take<float4>(k.px_cand);
+        E.pl_dt = cv.take<float4>(nt5);
+        E.c5_seed = cv.take<int32_t>(k.px_cand);
+        E.c5_obj = cv.take<int32_t>(k.px_cand);
+        E.c5_score = cv.take<float>(k.px_cand);
+        E.c5_keep = cv.take<uint8_t>(k.px_cand);
+        E.c3_seed = cv.take<int32_t>(k.px_cand);
+        E.c3_obj = cv.take<int32_t>(k.px_cand);
+        E.c3_score = cv.take<float>(k.px_cand);
+        E.c3_keep = cv.take<uint8_t>(k.px_cand);
+        E.hmin_o = cv.take<unsigned long long>(k.hits);
+        E.hmin_p = cv.take<unsigned long long>(k.px_hits);
+        E.htie_p = cv.take<uint32_t>(k.px_hits);
+        E.hflag_o = cv.take<uint8_t>(k.hits);
+        E.hflag_p = cv.take<uint8_t>(k.px_hits);
+    }
     return (cv.off + 255) & ~(size_t)255;
 }
 }  // namespace
@@ -502,6 +561,12 @@ int lst_attach_arena(lst_ctx *c, void *dev_ptr, size_t bytes, const lst_caps *ca
     // bin counts start at zero (each sort leaves them at zero again)
     HIPCHK(c, hipDeviceSynchronize());
     HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, nullptr));
+    // capacity drop flags start at zero (each compaction leaves them at zero)
+    {
+        const size_t span_max = std::max(std::max(c->E.rc[OT_MD], c->E.rc[OT_SEG]),
+                                         std::max(c->E.rc[OT_T3], c->E.rc[OT_T5])) * (size_t)NSH;
+        HIPCHK(c, launch_zero(c->E, c->E.cap_drop, (span_max + 15) & ~(size_t)15, nullptr));
+    }
     HIPCHK(c, hipDeviceSynchronize());
     if (!c->n_cu) HIPCHK(c, hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
     default_tuning(c);
@@ -562,6 +627,9 @@ int lst_load_hits(lst_ctx *c, int32_t n_events, const int32_t *hit_offsets, cons
     st[D_NHITS] = (int32_t)n;
     st[D_NSLOTS] = n_events * c->n_mod;
     st[D_NKEYS] = 2 * n_events * c->n_mod;
+    st[D_NPX] = 0;      // pixel objects belong to one batch: load them after the hits
+    st[D_NSEEDS] = 0;
+    c->px_loaded = false;
     std::memcpy(st + D_COUNT, hit_offsets, sizeof(int32_t) * (n_events + 1));
     HIPCHK(c, hipMemcpyAsync((void *)E.desc, st, sizeof(int32_t) * D_COUNT, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(E.hit_off, st + D_COUNT, sizeof(int32_t) * (n_events + 1),
@@ -570,6 +638,83 @@ int lst_load_hits(lst_ctx *c, int32_t n_events, const int32_t *hit_offsets, cons
     c->stage_pending = true;
     c->n_events = n_events;
     c->stage = 1;
+    return LST_OK;
+}
+
+int lst_load_pixel(lst_ctx *c, int32_t n_events, const int32_t *px_offsets, const float *x,
+                   const float *y, const float *z, const int32_t *seed_offsets,
+                   const int32_t *seeds, const double *pp, int32_t n_pp, void *stream)
+{
+    if (!c) return LST_E_INVALID;
+    if (c->stage < 1) return fail(c, LST_E_STATE, "load the hits of the batch first");
+    if (n_events != c->n_events || !px_offsets || !seed_offsets)
+        return fail(c, LST_E_INVALID, "pixel batch of %d events, hits of %d", n_events, c->n_events);
+    if (c->caps.seeds < 1 || c->caps.px_cand < 1 || !c->E.sd_hits)
+        return fail(c, LST_E_CAPACITY, "the arena holds no pixel objects (caps.seeds, caps.px_cand)");
+    if (!pp || n_pp < LST_PX_N_PARAMS) return fail(c, LST_E_INVALID, "pixel parameters");
+    for (int i = 0; i < LST_PX_N_PARAMS; ++i)
+        if (!std::isfinite(pp[i]) || pp[i] < 0) return fail(c, LST_E_INVALID, "pixel parameter %d", i);
+    if (px_offsets[0] != 0 || seed_offsets[0] != 0)
+        return fail(c, LST_E_INVALID, "pixel and seed offsets start at 0");
+    for (int e = 0; e < n_events; ++e)
+        if (px_offsets[e + 1] < px_offsets[e] || seed_offsets[e + 1] < seed_offsets[e])
+            return fail(c, LST_E_INVALID, "pixel or seed offsets not sorted");
+    const int64_t n_px = px_offsets[n_events], n_sd = seed_offsets[n_events];
+    if (n_px > c->caps.px_hits || n_sd > c->caps.seeds)
+        return fail(c, LST_E_CAPACITY, "%lld pixel hits and %lld seeds exceed capacities %lld, %lld",
+                    (long long)n_px, (long long)n_sd, (long long)c->caps.px_hits,
+                    (long long)c->caps.seeds);
+    if ((n_px > 0 && (!x || !y || !z)) || (n_sd > 0 && !seeds))
+        return fail(c, LST_E_INVALID, "null pixel array");
+    std::vector<int32_t> hits((size_t)n_sd * 4), ev((size_t)n_sd), loc((size_t)n_sd);
+    for (int e = 0; e < n_events; ++e)
+        for (int32_t q = seed_offsets[e]; q < seed_offsets[e + 1]; ++q) {
+            const int32_t n_e = px_offsets[e + 1] - px_offsets[e];
+            for (int k = 0; k < 4; ++k) {
+                const int32_t h = seeds[4 * (size_t)q + k];
+                if (h < 0 || h >= n_e)
+                    return fail(c, LST_E_INVALID, "seed %d of event %d: pixel hit %d outside 0..%d",
+                                q - seed_offsets[e], e, h, n_e - 1);
+                hits[4 * (size_t)q + k] = px_offsets[e] + h;
+            }
+            ev[q] = e;
+            loc[q] = q - seed_offsets[e];
+        }
+    HIPCHK(c, hipSetDevice(c->device));
+    // the stream may still read the previous pixel batch: copy after it
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    const EvDev &E = c->E;
+    if (n_px > 0) {
+        HIPCHK(c, hipMemcpy(E.px_x, x, sizeof(float) * n_px, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(E.px_y, y, sizeof(float) * n_px, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(E.px_z, z, sizeof(float) * n_px, hipMemcpyHostToDevice));
+    }
+    if (n_sd > 0) {
+        HIPCHK(c, hipMemcpy(E.sd_hits, hits.data(), sizeof(int32_t) * hits.size(), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(E.sd_ev, ev.data(), sizeof(int32_t) * ev.size(), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(E.sd_local, loc.data(), sizeof(int32_t) * loc.size(), hipMemcpyHostToDevice));
+    }
+    if (E.px_off) {
+        HIPCHK(c, hipMemcpy(E.px_off, px_offsets, sizeof(int32_t) * (n_events + 1), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(E.sd_off, seed_offsets, sizeof(int32_t) * (n_events + 1), hipMemcpyHostToDevice));
+    }
+    const int32_t d[2] = {(int32_t)n_px, (int32_t)n_sd};
+    HIPCHK(c, hipMemcpy((void *)(E.desc + D_NPX), d, sizeof(d), hipMemcpyHostToDevice));
+    c->px_off.assign(px_offsets, px_offsets + n_events + 1);
+    c->sd_off.assign(seed_offsets, seed_offsets + n_events + 1);
+    // pixel constants, each rounded once from the double parameters
+    PixConsts &P = c->pxk;
+    const double wl = pp[LST_PX_WLINK] * c->params[LST_P_W];
+    P.sig2p = (float)(pp[LST_PX_SIGRPHI] * pp[LST_PX_SIGRPHI]);
+    P.sigz = (float)pp[LST_PX_SIGZ];
+    P.wl2 = (float)(wl * wl);
+    P.dr2 = (float)pp[LST_PX_DR2];
+    P.x5p = (float)pp[LST_PX_X5P];
+    P.x5z = (float)pp[LST_PX_X5Z];
+    P.x3p = (float)pp[LST_PX_X3P];
+    P.x3z = (float)pp[LST_PX_X3Z];
+    c->px_loaded = true;
+    c->counts_valid = false;
     return LST_OK;
 }
 
@@ -592,6 +737,35 @@ static int need_stage(lst_ctx *c, int s, const char *what)
     return LST_OK;
 }
 
+static bool capped(const lst_ctx *c)
+{
+    return c->cap[OT_MD] > 0 || c->cap[OT_SEG] > 0 || c->cap[OT_T3] > 0 || c->cap[OT_T5] > 0;
+}
+
+// the capacity passes of one object type after its stage; the per-event drop
+// counts are cleared before the first pass of a chain
+static int enqueue_cap(lst_ctx *c, int type, hipStream_t s)
+{
+    if (!capped(c)) return LST_OK;
+    if (type == OT_MD)
+        HIPCHK(c, launch_zero(c->E, c->E.cap_nd,
+                              (((size_t)c->E.cap_ev * OT_COUNT + 3) & ~(size_t)3) * sizeof(uint32_t), s));
+    HIPCHK(c, launch_cap(c->E, type, c->cap[type], s));
+    return LST_OK;
+}
+
+int lst_set_capacities(lst_ctx *c, const int32_t *caps4)
+{
+    if (!c) return LST_E_INVALID;
+    if (caps4)
+        for (int t = 0; t < OT_COUNT; ++t)
+            if (caps4[t] < 0) return fail(c, LST_E_INVALID, "capacity %d of kind %d", caps4[t], t);
+    for (int t = 0; t < OT_COUNT; ++t) c->cap[t] = caps4 ? caps4[t] : 0;
+    drop_graph(c);
+    c->counts_valid = false;
+    return LST_OK;
+}
+
 int lst_run_sort(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 1, "lst_run_sort");
@@ -607,6 +781,7 @@ int lst_run_md(lst_ctx *c, void *stream)
     int rc = need_stage(c, 2, "lst_run_md");
     if (rc) return rc;
     HIPCHK(c, launch_md(c->E, c->M, c->K, c->tune.grid[ST_MD], c->tune.lanes[ST_MD], (hipStream_t)stream));
+    if ((rc = enqueue_cap(c, OT_MD, (hipStream_t)stream))) return rc;
     c->stage = 3;
     return LST_OK;
 }
@@ -616,6 +791,7 @@ int lst_run_segments(lst_ctx *c, void *stream)
     int rc = need_stage(c, 3, "lst_run_segments");
     if (rc) return rc;
     HIPCHK(c, launch_seg(c->E, c->M, c->K, c->tune.grid[ST_SEG], c->tune.lanes[ST_SEG], (hipStream_t)stream));
+    if ((rc = enqueue_cap(c, OT_SEG, (hipStream_t)stream))) return rc;
     c->stage = 4;
     return LST_OK;
 }
@@ -625,6 +801,7 @@ int lst_run_triplets(lst_ctx *c, void *stream)
     int rc = need_stage(c, 4, "lst_run_triplets");
     if (rc) return rc;
     HIPCHK(c, launch_t3(c->E, c->M, c->K, c->tune.grid[ST_T3], c->tune.lanes[ST_T3], (hipStream_t)stream));
+    if ((rc = enqueue_cap(c, OT_T3, (hipStream_t)stream))) return rc;
     c->stage = 5;
     return LST_OK;
 }
@@ -634,6 +811,7 @@ int lst_run_quintuplets(lst_ctx *c, void *stream)
     int rc = need_stage(c, 5, "lst_run_quintuplets");
     if (rc) return rc;
     HIPCHK(c, launch_t5(c->E, c->M, c->K, c->tune.grid[ST_T5], c->tune.lanes[ST_T5], (hipStream_t)stream));
+    if ((rc = enqueue_cap(c, OT_T5, (hipStream_t)stream))) return rc;
     c->stage = 6;
     return LST_OK;
 }
@@ -648,6 +826,16 @@ int lst_run_dedup(lst_ctx *c, void *stream)
 }
 
 int lst_run_chain_persistent(lst_ctx *c, void *stream);
+
+int lst_run_pixel(lst_ctx *c, void *stream)
+{
+    int rc = need_stage(c, 7, "lst_run_pixel");
+    if (rc) return rc;
+    if (!c->px_loaded) return fail(c, LST_E_STATE, "no pixel seeds loaded for this batch");
+    HIPCHK(c, launch_pixel(c->E, c->K, c->pxk, (hipStream_t)stream));
+    c->stage = 8;
+    return LST_OK;
+}
 
 // ---------------------------------------------------------------- learned scorer
 static int score_grid(const lst_ctx *c, int slot);
@@ -839,7 +1027,7 @@ int lst_mlp_train_steps(lst_ctx *c, float *params, const uint16_t *x, const uint
 int lst_run_chain(lst_ctx *c, void *stream)
 {
     int rc;
-    if (c && c->tune.persistent) return lst_run_chain_persistent(c, stream);
+    if (c && c->tune.persistent && !capped(c)) return lst_run_chain_persistent(c, stream);
     if ((rc = lst_run_sort(c, stream))) return rc;
     if ((rc = lst_run_md(c, stream))) return rc;
     if ((rc = lst_run_segments(c, stream))) return rc;
@@ -895,7 +1083,7 @@ static int enqueue_chain(lst_ctx *c, hipStream_t s)
     const Tuning &t = c->tune;
     const bool mlp = c->mode == LST_MODE_MLP;
     int rc;
-    if (t.persistent) {
+    if (t.persistent && !capped(c)) {
         const int stop = persistent_stop(c);
         HIPCHK(c, launch_chain_persistent(c->E, c->M, c->K, c->zero_base, c->zero_bytes,
                                           t.blocks_per_cu * c->n_cu, t.lanes[ST_SEG], stop, s));
@@ -903,10 +1091,14 @@ static int enqueue_chain(lst_ctx *c, hipStream_t s)
     }
     HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], sort_per_event(c), s));
     HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], t.lanes[ST_MD], s));
+    if ((rc = enqueue_cap(c, OT_MD, s))) return rc;
     HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], t.lanes[ST_SEG], s));
+    if ((rc = enqueue_cap(c, OT_SEG, s))) return rc;
     HIPCHK(c, launch_t3(c->E, c->M, c->K, t.grid[ST_T3], t.lanes[ST_T3], s));
+    if ((rc = enqueue_cap(c, OT_T3, s))) return rc;
     if (mlp && c->mlp_dev[0] && (rc = enqueue_score(c, 0, s))) return rc;
     HIPCHK(c, launch_t5(c->E, c->M, c->K, t.grid[ST_T5], t.lanes[ST_T5], s));
+    if ((rc = enqueue_cap(c, OT_T5, s))) return rc;
     if (mlp && c->mlp_dev[1] && (rc = enqueue_score(c, 1, s))) return rc;
     HIPCHK(c, launch_dedup(c->E, c->M, t.grid[ST_DEDUP], s));
     return LST_OK;
@@ -916,6 +1108,8 @@ int lst_run_chain_persistent(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 1, "lst_run_chain_persistent");
     if (rc) return rc;
+    if (capped(c))
+        return fail(c, LST_E_STATE, "per-module capacities run with the per-stage chain only");
     const int bpc =
         std::max(1, std::min(c->tune.blocks_per_cu, persistent_blocks_per_cu(c->tune.lanes[ST_SEG])));
     hipStream_t s = (hipStream_t)stream;
@@ -1094,6 +1288,14 @@ static int compute_counts(lst_ctx *c)
         c->counts[e].overflow_mask = (int32_t)S.gc[GC_OVERFLOW];
         c->counts[e].error_flags = (int32_t)S.gc[GC_ERROR];
     }
+    if (capped(c) && c->stage >= 3) {
+        std::vector<uint32_t> nd;
+        if ((rc = d2h(c, nd, E.cap_nd, (size_t)n_ev * OT_COUNT))) return rc;
+        // a kind's counts are only meaningful once its stage (and pass) ran
+        for (int e = 0; e < n_ev; ++e)
+            for (int t = 0; t < OT_COUNT; ++t)
+                c->counts[e].dropped[t] = c->stage >= 3 + t ? nd[(size_t)e * OT_COUNT + t] : 0;
+    }
     if (S.gc[GC_OVERFLOW]) {
         // arrays are incomplete: report the batch-wide requirement instead
         for (auto &k : c->counts) {
@@ -1145,6 +1347,8 @@ static int compute_counts(lst_ctx *c)
             }
         }
     }
+    std::vector<uint8_t> clean;
+    if (c->stage >= 8 && (rc = d2h(c, clean, E.t5_clean, nt5))) return rc;
     if (c->stage >= 6) {
         for (int s = 0; s < NSH; ++s)
             for (uint32_t q = 0; q < S.n(OT_T5, s); ++q) {
@@ -1152,7 +1356,33 @@ static int compute_counts(lst_ctx *c)
                 const int e = mslot[t50[t]] / nm;
                 c->counts[e].n_t5++;
                 if (c->stage >= 7) c->counts[e].n_t5_kept += keep[t];
+                if (c->stage >= 8) c->counts[e].n_tc += clean[t];
             }
+    }
+    if (c->stage >= 8) {
+        const uint32_t n5 = std::min<uint32_t>(S.gc[GC_PX5], (uint32_t)E.cap_pxc);
+        const uint32_t n3 = std::min<uint32_t>(S.gc[GC_PX3], (uint32_t)E.cap_pxc);
+        const int64_t n_sd = c->sd_off[n_ev];
+        std::vector<int32_t> s5, s3, sev;
+        std::vector<uint8_t> k5, k3, sk;
+        if ((rc = d2h(c, s5, E.c5_seed, n5)) || (rc = d2h(c, k5, E.c5_keep, n5)) ||
+            (rc = d2h(c, s3, E.c3_seed, n3)) || (rc = d2h(c, k3, E.c3_keep, n3)) ||
+            (rc = d2h(c, sev, E.sd_ev, n_sd)) || (rc = d2h(c, sk, E.sd_keep, n_sd)))
+            return rc;
+        for (int e = 0; e < n_ev; ++e) c->counts[e].n_pls = c->sd_off[e + 1] - c->sd_off[e];
+        for (uint32_t i = 0; i < n5; ++i) {
+            lst_counts &k = c->counts[sev[s5[i]]];
+            k.cand_pt5++;
+            k.n_pt5 += k5[i];
+            k.n_tc += k5[i];
+        }
+        for (uint32_t i = 0; i < n3; ++i) {
+            lst_counts &k = c->counts[sev[s3[i]]];
+            k.cand_pt3++;
+            k.n_pt3 += k3[i];
+            k.n_tc += k3[i];
+        }
+        for (int64_t q = 0; q < n_sd; ++q) c->counts[sev[q]].n_tc += sk[q];
     }
     c->counts_valid = true;
     return LST_OK;
@@ -1336,6 +1566,137 @@ int lst_get_t5_features(lst_ctx *c, int32_t event, float *out, int64_t cap, int6
     if (!c) return LST_E_INVALID;
     if (!c->features_valid) return fail(c, LST_E_STATE, "features have not been computed");
     return obj_field(c, OT_T5, event, c->E.t5_feat, 40, out, cap, n_out, stream, "feature rows");
+}
+
+// the pixel stage's device arrays, read back for one event's getters
+struct PixRead {
+    std::vector<int32_t> sorig, hlo, hup, slot, t5m[5], t3a, t3b, t3c;
+    std::vector<int32_t> s5, o5, s3, o3, sev, sloc;
+    std::vector<float> f5, f3;
+    std::vector<uint8_t> k5, k3, clean, sk, keep;
+    ShardCounts S;
+};
+
+static int pix_read(lst_ctx *c, void *stream, PixRead &R)
+{
+    if (c->stage < 8) return fail(c, LST_E_STATE, "the pixel stage has not run");
+    int rc = sync_stream(c, stream);
+    if (rc) return rc;
+    const EvDev &E = c->E;
+    ShardCounts &S = R.S;
+    if ((rc = read_shards(c, S)) || (rc = check_fault(c, S.gc[GC_ERROR]))) return rc;
+    if (S.gc[GC_OVERFLOW])
+        return fail(c, LST_E_CAPACITY, "capacity overflow (mask %u)", S.gc[GC_OVERFLOW]);
+    const uint32_t n5 = std::min<uint32_t>(S.gc[GC_PX5], (uint32_t)E.cap_pxc);
+    const uint32_t n3 = std::min<uint32_t>(S.gc[GC_PX3], (uint32_t)E.cap_pxc);
+    const int64_t n_sd = c->sd_off[c->n_events];
+    const size_t nmd = S.span(OT_MD), nt3 = S.span(OT_T3), nt5 = S.span(OT_T5);
+    if ((rc = sorted_orig(c, R.sorig, S.gc[GC_N_SORTED])) || (rc = d2h(c, R.hlo, E.md_hlo, nmd)) ||
+        (rc = d2h(c, R.hup, E.md_hup, nmd)) || (rc = d2h(c, R.slot, E.md_slot, nmd)) ||
+        (rc = d2h(c, R.t5m[0], E.t5_md0, nt5)) || (rc = d2h(c, R.t5m[1], E.t5_md1, nt5)) ||
+        (rc = d2h(c, R.t5m[2], E.t5_md2, nt5)) || (rc = d2h(c, R.t5m[3], E.t5_md3, nt5)) ||
+        (rc = d2h(c, R.t5m[4], E.t5_md4, nt5)) || (rc = d2h(c, R.t3a, E.t3_a, nt3)) ||
+        (rc = d2h(c, R.t3b, E.t3_b, nt3)) || (rc = d2h(c, R.t3c, E.t3_c, nt3)) ||
+        (rc = d2h(c, R.s5, E.c5_seed, n5)) || (rc = d2h(c, R.o5, E.c5_obj, n5)) ||
+        (rc = d2h(c, R.f5, E.c5_score, n5)) || (rc = d2h(c, R.k5, E.c5_keep, n5)) ||
+        (rc = d2h(c, R.s3, E.c3_seed, n3)) || (rc = d2h(c, R.o3, E.c3_obj, n3)) ||
+        (rc = d2h(c, R.f3, E.c3_score, n3)) || (rc = d2h(c, R.k3, E.c3_keep, n3)) ||
+        (rc = d2h(c, R.clean, E.t5_clean, nt5)) || (rc = d2h(c, R.keep, E.t5_keep, nt5)) ||
+        (rc = d2h(c, R.sev, E.sd_ev, n_sd)) || (rc = d2h(c, R.sloc, E.sd_local, n_sd)) ||
+        (rc = d2h(c, R.sk, E.sd_keep, n_sd)))
+        return rc;
+    R.s5.resize(n5); R.s3.resize(n3);
+    return LST_OK;
+}
+
+// outer hit tuple (per-event indices) of a quintuplet (w 10) or triplet (w 6)
+static void pix_tuple(const PixRead &R, int w, int32_t t, int32_t *out)
+{
+    for (int j = 0; j < w / 2; ++j) {
+        const int32_t m = w == 10 ? R.t5m[j][t] : j == 0 ? R.t3a[t] : j == 1 ? R.t3b[t] : R.t3c[t];
+        out[2 * j] = R.sorig[R.hlo[m]];
+        out[2 * j + 1] = R.sorig[R.hup[m]];
+    }
+    for (int k = w; k < 10; ++k) out[k] = -1;
+}
+
+static int put_rows(lst_ctx *c, std::vector<std::array<int32_t, 13>> &rows, int width,
+                    int32_t *out, int64_t cap, int64_t *n)
+{
+    std::sort(rows.begin(), rows.end());
+    if (n) *n = (int64_t)rows.size();
+    if ((int64_t)rows.size() > cap)
+        return fail(c, LST_E_CAPACITY, "%lld rows, capacity %lld", (long long)rows.size(), (long long)cap);
+    if (out)
+        for (size_t i = 0; i < rows.size(); ++i)
+            std::memcpy(&out[(size_t)width * i], rows[i].data(), sizeof(int32_t) * width);
+    return LST_OK;
+}
+
+int lst_get_track_candidates(lst_ctx *c, int32_t event, int32_t *out, int64_t cap, int64_t *n,
+                             void *stream)
+{
+    if (!c) return LST_E_INVALID;
+    if (event < 0 || event >= c->n_events) return fail(c, LST_E_INVALID, "event %d", event);
+    PixRead R;
+    int rc = pix_read(c, stream, R);
+    if (rc) return rc;
+    std::vector<std::array<int32_t, 13>> rows;
+    std::array<int32_t, 13> r{};
+    for (size_t i = 0; i < R.s5.size(); ++i)
+        if (R.k5[i] && R.sev[R.s5[i]] == event) {
+            r[0] = LST_TC_PT5; r[1] = R.sloc[R.s5[i]];
+            pix_tuple(R, 10, R.o5[i], &r[2]);
+            rows.push_back(r);
+        }
+    for (size_t i = 0; i < R.s3.size(); ++i)
+        if (R.k3[i] && R.sev[R.s3[i]] == event) {
+            r[0] = LST_TC_PT3; r[1] = R.sloc[R.s3[i]];
+            pix_tuple(R, 6, R.o3[i], &r[2]);
+            rows.push_back(r);
+        }
+    const int lo_slot = event * c->n_mod, hi_slot = (event + 1) * c->n_mod;
+    for (int sh = 0; sh < NSH; ++sh)
+        for (uint32_t q = 0; q < R.S.n(OT_T5, sh); ++q) {
+            const size_t t = (size_t)sh * R.S.rc[OT_T5] + q;
+            const int32_t sl = R.slot[R.t5m[0][t]];
+            if (!R.clean[t] || sl < lo_slot || sl >= hi_slot) continue;
+            r[0] = LST_TC_T5; r[1] = -1;
+            pix_tuple(R, 10, (int32_t)t, &r[2]);
+            rows.push_back(r);
+        }
+    for (int32_t q = c->sd_off[event]; q < c->sd_off[event + 1]; ++q)
+        if (R.sk[q]) {
+            r[0] = LST_TC_PLS; r[1] = R.sloc[q];
+            for (int k = 0; k < 10; ++k) r[2 + k] = -1;
+            rows.push_back(r);
+        }
+    return put_rows(c, rows, 12, out, cap, n);
+}
+
+int lst_get_pixel_candidates(lst_ctx *c, int32_t event, int32_t what, int32_t *out, int64_t cap,
+                             int64_t *n, void *stream)
+{
+    if (!c) return LST_E_INVALID;
+    if (event < 0 || event >= c->n_events) return fail(c, LST_E_INVALID, "event %d", event);
+    if (what != 0 && what != 1) return fail(c, LST_E_INVALID, "what %d (0 pT5, 1 pT3)", what);
+    PixRead R;
+    int rc = pix_read(c, stream, R);
+    if (rc) return rc;
+    const std::vector<int32_t> &sd = what ? R.s3 : R.s5, &ob = what ? R.o3 : R.o5;
+    const std::vector<float> &sc = what ? R.f3 : R.f5;
+    const std::vector<uint8_t> &kp = what ? R.k3 : R.k5;
+    std::vector<std::array<int32_t, 13>> rows;
+    std::array<int32_t, 13> r{};
+    for (size_t i = 0; i < sd.size(); ++i) {
+        if (R.sev[sd[i]] != event) continue;
+        r[0] = R.sloc[sd[i]];
+        pix_tuple(R, what ? 6 : 10, ob[i], &r[1]);
+        std::memcpy(&r[11], &sc[i], sizeof(float));
+        r[12] = kp[i];
+        rows.push_back(r);
+    }
+    return put_rows(c, rows, 13, out, cap, n);
 }
 
 int lst_get_t3_features(lst_ctx *c, int32_t event, float *out, int64_t cap, int64_t *n_out,

@@ -379,6 +379,173 @@ __device__ __forceinline__ bool t5_accept(const Consts &K, const MdV &A, const M
     return true;
 }
 
+// ---------------------------------------------------------------- pixel objects
+// Direction of an object without transcendental functions: the circle
+// through the beam line and points A (inner) and E (outer) has its tangent at
+// the beam line along A/|A|^2 - E/|E|^2 (the image of the circle under
+// inversion about the origin is the line through the images of A and E).
+__device__ __forceinline__ void dir2(float xa, float ya, float xe, float ye, float &tx, float &ty)
+{
+    float ra2 = (xa * xa) + (ya * ya);
+    float re2 = (xe * xe) + (ye * ye);
+    tx = (xa / ra2) - (xe / re2);
+    ty = (ya / ra2) - (ye / re2);
+}
+
+// pLS direction: tangent from its first and last pixel hits, polar slope of
+// their chord
+__device__ __forceinline__ float4 pls_dir(float x1, float y1, float z1, float x4, float y4, float z4)
+{
+    float tx, ty;
+    dir2(x1, y1, x4, y4, tx, ty);
+    float dx = x4 - x1, dy = y4 - y1;
+    return make_float4(tx, ty, (z4 - z1) / sqrtf((dx * dx) + (dy * dy)), 0.0f);
+}
+
+// outer object direction from its first and last anchors and curvature k:
+// polar slope = dz over the arc length
+__device__ __forceinline__ float4 obj_dir(const MdV &A, const MdV &E, float k)
+{
+    float tx, ty;
+    dir2(A.x, A.y, E.x, E.y, tx, ty);
+    float dx = E.x - A.x, dy = E.y - A.y;
+    return make_float4(tx, ty, (E.z - A.z) / arc(sqrtf((dx * dx) + (dy * dy)), k), 0.0f);
+}
+
+// bridge curvature of a quintuplet from its anchors A, C, E
+__device__ __forceinline__ float bridge_curv(const MdV &A, const MdV &C, const MdV &E)
+{
+    float xac = C.x - A.x, yac = C.y - A.y;
+    float xce = E.x - C.x, yce = E.y - C.y;
+    float xae = E.x - A.x, yae = E.y - A.y;
+    float lac = sqrtf((xac * xac) + (yac * yac));
+    float lce = sqrtf((xce * xce) + (yce * yce));
+    float lae = sqrtf((xae * xae) + (yae * yae));
+    float crs = (xac * yae) - (yac * xae);
+    return (2.0f * crs) / ((lac * lce) * lae);
+}
+
+// azimuthal and polar separation of two directions: cos-term, sin^2(dphi),
+// (dcot)^2 / (1 + (c1^2 + c2^2) / 2)
+__device__ __forceinline__ void dir_sep(const float4 &a, const float4 &b, float &dot, float &sp2,
+                                        float &se2)
+{
+    dot = (a.x * b.x) + (a.y * b.y);
+    float crs = (a.x * b.y) - (a.y * b.x);
+    float nn = ((a.x * a.x) + (a.y * a.y)) * ((b.x * b.x) + (b.y * b.y));
+    sp2 = (crs * crs) / nn;
+    float dc = a.z - b.z;
+    se2 = (dc * dc) / (1.0f + (0.5f * ((a.z * a.z) + (b.z * b.z))));
+}
+
+// linking window: same hemisphere, sin^2(dphi) and polar term within wl2
+__device__ __forceinline__ bool link_window(const float4 &a, const float4 &b, float wl2)
+{
+    float dot, sp2, se2;
+    dir_sep(a, b, dot, sp2, se2);
+    return (-dot <= 0.0f) && (sp2 <= wl2) && (se2 <= wl2);
+}
+
+// cross-cleaning: same hemisphere and sin^2(dphi) + polar term within dr2
+__device__ __forceinline__ bool close_dir(const float4 &a, const float4 &b, float dr2)
+{
+    float dot, sp2, se2;
+    dir_sep(a, b, dot, sp2, se2);
+    return (-dot <= 0.0f) && ((sp2 + se2) <= dr2);
+}
+
+// a point of a linked chain: pixel hit (kind 0) or anchor (1 barrel, 2 endcap)
+struct LPt {
+    float x, y, z, sv, r;
+    int kind;
+};
+
+__device__ __forceinline__ LPt lpt_md(const MdV &m)
+{
+    LPt p;
+    p.x = m.x; p.y = m.y; p.z = m.z; p.sv = m.sv; p.r = m.r;
+    p.kind = m.barrel ? 1 : 2;
+    return p;
+}
+
+__device__ __forceinline__ LPt lpt_px(float x, float y, float z)
+{
+    LPt p;
+    p.x = x; p.y = y; p.z = z; p.sv = 0.0f; p.r = 0.0f; p.kind = 0;
+    return p;
+}
+
+// Link chi2 of a chain of N points (pLS hits then anchors): circle through
+// points 0, IC and N-1; r-phi chi2 of the others with Lagrange-propagated
+// node variances; r-z chi2 of points 1..N-2 about the line in arc length
+// through 0 and N-1; both sums taken in point order.  Cuts against
+// w^2 x2p and w^2 x2z; score = chi2_rphi + chi2_rz.
+template <int N, int IC>
+__device__ __forceinline__ bool link_accept(const Consts &K, const LPt *p, float sig2p,
+                                            float sigz, float x2p, float x2z, float &score)
+{
+    const float xa = p[0].x, ya = p[0].y, za = p[0].z;
+    const float xc = p[IC].x, yc = p[IC].y;
+    const float xe = p[N - 1].x, ye = p[N - 1].y, ze = p[N - 1].z;
+    float xac = xc - xa, yac = yc - ya;
+    float xce = xe - xc, yce = ye - yc;
+    float xae = xe - xa, yae = ye - ya;
+    float lac = sqrtf((xac * xac) + (yac * yac));
+    float lce = sqrtf((xce * xce) + (yce * yce));
+    float lae = sqrtf((xae * xae) + (yae * yae));
+    float crs = (xac * yae) - (yac * xae);
+    float den = (lac * lce) * lae;
+    float k = (2.0f * crs) / den;
+    float hk = 0.5f * k;
+    float s[N], vp[N];
+    s[0] = 0.0f;
+#pragma unroll
+    for (int j = 1; j < N; ++j) {
+        float dx = p[j].x - p[j - 1].x, dy = p[j].y - p[j - 1].y;
+        s[j] = s[j - 1] + arc(sqrtf((dx * dx) + (dy * dy)), k);
+    }
+    const float su2 = K.sigu * K.sigu;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (p[j].kind == 0) {
+            vp[j] = sig2p;
+        } else {
+            float e = K.sigv * (p[j].sv + (hk * p[j].r));
+            vp[j] = p[j].kind == 1 ? su2 : (su2 + (e * e));
+        }
+    }
+    const float sc = s[IC], se = s[N - 1];
+    float chi2p = 0.0f;
+#pragma unroll
+    for (int j = 1; j < N - 1; ++j) {
+        if (j == IC) continue;
+        float res = circ_res(xa, ya, xc, yc, xe, ye, p[j].x, p[j].y, crs, den);
+        float sj = s[j];
+        float L0 = ((sj - sc) * (sj - se)) / (sc * se);
+        float Lc = (sj * (sj - se)) / (sc * (sc - se));
+        float Le = (sj * (sj - sc)) / (se * (se - sc));
+        float V = (vp[j] + (((L0 * L0) * vp[0]) + ((Lc * Lc) * vp[IC]))) + ((Le * Le) * vp[N - 1]);
+        chi2p = chi2p + ((res * res) / V);
+    }
+    float sl = (ze - za) / se;
+    float sev = mx(fabsf(sl), 0.05f) * K.sigv;
+    float sz0 = p[0].kind == 0 ? sigz : p[0].kind == 1 ? K.sigv : sev;
+    float sze = p[N - 1].kind == 0 ? sigz : p[N - 1].kind == 1 ? K.sigv : sev;
+    float chi2z = 0.0f;
+#pragma unroll
+    for (int j = 1; j < N - 1; ++j) {
+        float szj = p[j].kind == 0 ? sigz : p[j].kind == 1 ? K.sigv : sev;
+        float f = s[j] / se;
+        float dz = p[j].z - (za + (sl * s[j]));
+        float g1 = (1.0f - f) * sz0;
+        float g2 = f * sze;
+        float V = ((szj * szj) + (g1 * g1)) + (g2 * g2);
+        chi2z = chi2z + ((dz * dz) / V);
+    }
+    score = chi2p + chi2z;
+    return (chi2p <= K.w2 * x2p) && (chi2z <= K.w2 * x2z);
+}
+
 // Every triplet quantity of t3_accept, without early exits, and the 40
 // features of the learned scorer (22 used, the rest zero; same operation
 // order as t3_accept for the shared quantities): per MD r/100, z/100, bend

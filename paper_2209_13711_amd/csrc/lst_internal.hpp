@@ -36,6 +36,9 @@ enum GlobalCounter {
     GC_N_SORTED,       // number of grouped hits
     GC_TIEPOOL,        // entries taken from the dedup tie pool
     GC_SCAN,           // tile tickets of the look-back scan
+    GC_DROP,           // [OT_COUNT] objects removed by per-module capacities
+    GC_PX5 = GC_DROP + OT_COUNT,   // pT5 link candidates
+    GC_PX3,            // pT3 link candidates
     GC_SH = GC_PAD     // [OT_COUNT][NSH] reservation shards, one line each
 };
 __host__ __device__ constexpr int gc_shard(int type, int s) { return GC_SH + (type * NSH + s) * GC_PAD; }
@@ -62,7 +65,7 @@ struct ModDev {
 
 // Batch descriptor, device resident so that a captured chain stays valid for
 // any batch that fits the arena: [n_events, n_hits, n_slots, n_keys].
-enum { D_NEV = 0, D_NHITS, D_NSLOTS, D_NKEYS, D_COUNT };
+enum { D_NEV = 0, D_NHITS, D_NSLOTS, D_NKEYS, D_NPX, D_NSEEDS, D_COUNT };
 
 struct EvDev {
     const int32_t *desc;             // [D_COUNT]
@@ -106,7 +109,8 @@ struct EvDev {
     uint8_t *t3_veto;                // 1: rejected by the learned scorer (no quintuplet uses it)
     float *t3_feat;                  // [span][40] features (learned scorer)
     float *t3_logit;                 // [span] scorer output
-    // quintuplets
+    // quintuplets (grouped by first MD)
+    int32_t *t5_start, *t5_cnt;      // [cap_md]
     int32_t *t5_md0, *t5_md1, *t5_md2, *t5_md3, *t5_md4;
     float *t5_score;
     uint8_t *t5_keep;
@@ -114,6 +118,35 @@ struct EvDev {
     int32_t *t5_hs, *t5_ho;          // dedup: [span][10] sorted and per-event hit indices
     float *t5_feat;                  // [span][40] features (learned scorer)
     float *t5_logit;                 // [span] scorer output
+    // per-module capacities: drop flags (one byte per object, zero between
+    // passes), each shard's prefix of kept objects (NSH x (largest rc + 1)),
+    // objects removed per event and kind [cap_ev][OT_COUNT]
+    uint8_t *cap_drop;
+    int32_t *cap_pre;
+    uint32_t *cap_nd;
+    // pixel objects: pixel hits and seeds of the batch (pLS), object
+    // directions, per-event lists, link candidates, cross-cleaning state
+    int32_t cap_px, cap_seeds, cap_pxc;
+    float *px_x, *px_y, *px_z;       // [cap_px]
+    int32_t *px_off, *sd_off;        // [cap_ev + 1] first pixel hit / seed of each event
+    int32_t *sd_hits;                // [cap_seeds][4] batch-wide pixel hit indices, inner to outer
+    int32_t *sd_ev, *sd_local;       // [cap_seeds] event, index inside the event
+    float4 *sd_dir;                  // [cap_seeds] tangent at the beam line, cot(theta)
+    uint8_t *sd_used, *sd_keep;      // [cap_seeds] linked by a kept pT5/pT3; a track candidate
+    float4 *t5_dir, *t3_dir;         // [span] directions of kept quintuplets, of triplets
+    uint8_t *t5_clean;               // [span] kept quintuplet left after cross-cleaning
+    // per-event lists (PXL_*): counts, offsets, fill counters, entries
+    int32_t *pl_cnt, *pl_off, *pl_fill;  // [PXL_COUNT][cap_ev (+1)]
+    int32_t *pl_k5, *pl_k3;          // kept quintuplets, triplets
+    float4 *pl_d5, *pl_d3, *pl_dt;   // directions of kept pT5, cleaned pT3, cleaned T5
+    // link candidates of pT5 (c5) and pT3 (c3): seed, object, score, kept
+    int32_t *c5_seed, *c5_obj, *c3_seed, *c3_obj;   // [cap_pxc]
+    float *c5_score, *c3_score;
+    uint8_t *c5_keep, *c3_keep;
+    unsigned long long *hmin_o;      // [cap_hits] smallest key per grouped outer hit
+    unsigned long long *hmin_p;      // [cap_px]   smallest key per pixel hit
+    uint32_t *htie_p;                // [cap_px]   candidates reaching it on their first pixel hit
+    uint8_t *hflag_o, *hflag_p;      // hits held by track candidates so far
     // counters (zeroed at chain start)
     uint32_t *gc;                    // [GC_COUNT]
     uint32_t *bar;                   // persistent-chain barrier counters [33]
@@ -145,6 +178,15 @@ hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, int grid,
 hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
                      hipStream_t s);
 hipError_t launch_dedup(const EvDev &E, const ModDev &M, int grid, hipStream_t s);
+// pixel objects (lst_pixel.hip)
+enum { PXL_K5 = 0, PXL_K3, PXL_D5, PXL_D3, PXL_DT, PXL_COUNT };
+struct PixConsts {
+    float sig2p, sigz, wl2, dr2, x5p, x5z, x3p, x3z;
+};
+hipError_t launch_pixel(const EvDev &E, const Consts &K, const PixConsts &P, hipStream_t s);
+// per-module capacity `cap` of object type `type` (lst_cap.hip): objects of
+// a module beyond it removed, the type's arrays compacted in place
+hipError_t launch_cap(const EvDev &E, int type, int32_t cap, hipStream_t s);
 // stop: PERS_FULL runs every stage; PERS_TO_T5 ends after the quintuplets,
 // PERS_TO_T3 after the triplets (learned scoring follows as its own
 // launches); lanes: group width of its four object stages

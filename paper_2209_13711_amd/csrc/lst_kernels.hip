@@ -600,6 +600,7 @@ struct SmT5 {
     float4 ap[WAVES][T5_PMAX];
     float asv[WAVES][T5_PMAX];
     int32_t abar[WAVES][T5_PMAX], aidx[WAVES][T5_PMAX];
+    uint32_t cnt[WAVES][T5_PMAX];     // accepted quintuplets per inner MD
     int32_t mark[WAVES][64];          // chunk_src
     uint8_t g[WAVES][STAGE];
 };
@@ -1296,22 +1297,33 @@ __device__ __forceinline__ void t5_body(const EvDev &E, const Consts &K, SmT5 &s
             }
         }
         const uint32_t incl1 = wave_incl_scan((uint32_t)nt1);
+        if (l < (uint32_t)T5_PMAX) sm.cnt[w][l] = 0u;
         wave_lds_sync();
         const uint32_t tot = enum_t5(E, K, sm, w, nt1, t10, incl1,
                                      [&](bool ok, int g, int32_t b, int32_t c, int32_t d,
                                          int32_t e, float sc, uint32_t pos) {
-            if (ok && pos < STAGE) {
-                sm.b[w][pos] = b;
-                sm.c[w][pos] = c;
-                sm.d[w][pos] = d;
-                sm.e[w][pos] = e;
-                sm.s[w][pos] = sc;
-                sm.g[w][pos] = (uint8_t)g;
+            if (ok) {
+                atomicAdd(&sm.cnt[w][g], 1u);
+                if (pos < STAGE) {
+                    sm.b[w][pos] = b;
+                    sm.c[w][pos] = c;
+                    sm.d[w][pos] = d;
+                    sm.e[w][pos] = e;
+                    sm.s[w][pos] = sc;
+                    sm.g[w][pos] = (uint8_t)g;
+                }
             }
         });
         wave_lds_sync();
+        // each inner MD's quintuplets are consecutive, in the list's order
+        const uint32_t cl = l < (uint32_t)T5_PMAX ? sm.cnt[w][l] : 0u;
+        const uint32_t cex = wave_incl_scan(cl) - cl;
         bool ovf;
         const uint32_t off = wave_reserve(tot, E, OT_T5, ovf);
+        if (act) {
+            E.t5_start[a] = (int32_t)(off + cex);
+            E.t5_cnt[a] = ovf ? 0 : (int32_t)cl;
+        }
         if (ovf) continue;
         for (uint32_t q = l; q < tot && q < (uint32_t)STAGE; q += 64)
             write_t5(E, off + q, sm.aidx[w][sm.g[w][q]], sm.b[w][q], sm.c[w][q], sm.d[w][q],

@@ -25,22 +25,30 @@ LST_N_PARAMS = 14
 LST_MOD_NF, LST_MOD_NI = 21, 4
 LST_MODE_CUTS, LST_MODE_MLP = 0, 1
 LST_MLP_NFEAT, LST_MLP_NPARAM = 40, 6849
+LST_PX_N_PARAMS = 8
+LST_TC_PT5, LST_TC_PT3, LST_TC_T5, LST_TC_PLS = 0, 1, 2, 3
 
 
 class lst_caps(ctypes.Structure):
     _fields_ = [("events", ctypes.c_int32), ("hits", ctypes.c_int64), ("md", ctypes.c_int64),
                 ("seg", ctypes.c_int64), ("t3", ctypes.c_int64), ("t5", ctypes.c_int64),
-                ("features", ctypes.c_int32)]
+                ("features", ctypes.c_int32), ("px_hits", ctypes.c_int64),
+                ("seeds", ctypes.c_int64), ("px_cand", ctypes.c_int64)]
 
 
 class lst_counts(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("n_hits", "n_md", "n_seg", "n_t3", "n_t5",
                                                "n_t5_kept", "cand_md", "cand_seg", "cand_t3",
                                                "cand_t5")] + \
-               [("overflow_mask", ctypes.c_int32), ("error_flags", ctypes.c_int32)]
+               [("overflow_mask", ctypes.c_int32), ("error_flags", ctypes.c_int32),
+                ("dropped", ctypes.c_int64 * 4)] + \
+               [(n, ctypes.c_int64) for n in ("n_pls", "cand_pt5", "n_pt5", "cand_pt3", "n_pt3",
+                                               "n_tc")]
 
     def as_dict(self):
-        return {n: getattr(self, n) for n, _ in self._fields_}
+        d = {n: getattr(self, n) for n, _ in self._fields_}
+        d["dropped"] = list(self.dropped)
+        return d
 
 
 class LSTError(RuntimeError):
@@ -72,6 +80,14 @@ _SIGS = {
     "lst_run_chain_graph": (ctypes.c_int, [_P, _P]),
     "lst_get_counts": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(lst_counts), _P]),
     "lst_raise_error_flags": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
+    "lst_set_capacities": (ctypes.c_int, [_P, _P]),
+    "lst_load_pixel": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P,
+                                      ctypes.c_int32, _P]),
+    "lst_run_pixel": (ctypes.c_int, [_P, _P]),
+    "lst_get_track_candidates": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64,
+                                                ctypes.POINTER(ctypes.c_int64), _P]),
+    "lst_get_pixel_candidates": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P,
+                                                ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _P]),
     "lst_get_objects": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64,
                                        ctypes.POINTER(ctypes.c_int64), _P]),
     "lst_get_t5_scores": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64,
@@ -165,7 +181,7 @@ def lst_stream_copy(dst: "torch.Tensor", src: "torch.Tensor", stream=None):
 def default_caps(n_events: int, n_hits: int) -> dict:
     md = max(4096, int(1.5 * n_hits))
     return dict(events=n_events, hits=max(n_hits, 1), md=md, seg=6 * md, t3=4 * md, t5=4 * md,
-                features=0)
+                features=0, px_hits=0, seeds=0, px_cand=0)
 
 
 class Context:
@@ -211,7 +227,8 @@ class Context:
     def arena_bytes(self, caps: dict) -> int:
         """bytes of the arena the library needs for `caps` (lst_arena_bytes)"""
         caps = dict(caps)
-        caps.setdefault("features", 0)
+        for k in ("features", "px_hits", "seeds", "px_cand"):
+            caps.setdefault(k, 0)
         c = lst_caps(**caps)
         nbytes = ctypes.c_size_t(0)
         self._check(self.lib.lst_arena_bytes(self.h, ctypes.byref(c), ctypes.byref(nbytes)))
@@ -219,7 +236,8 @@ class Context:
 
     def reserve(self, caps: dict):
         caps = dict(caps)
-        caps.setdefault("features", 0)
+        for k in ("features", "px_hits", "seeds", "px_cand"):
+            caps.setdefault(k, 0)
         c = lst_caps(**caps)
         nbytes = ctypes.c_size_t(0)
         self._check(self.lib.lst_arena_bytes(self.h, ctypes.byref(c), ctypes.byref(nbytes)))
@@ -248,7 +266,8 @@ class Context:
         if self.caps is None or self.caps["events"] < n_ev or self.caps["hits"] < n:
             caps = default_caps(n_ev, n)
             if self.caps is not None:
-                caps["features"] = self.caps.get("features", 0)
+                for k in ("features", "px_hits", "seeds", "px_cand"):
+                    caps[k] = self.caps.get(k, 0)
             self.reserve(caps)
         if isinstance(x, torch.Tensor):
             arrs = [x, y, z, module, sensor]
@@ -325,6 +344,76 @@ class Context:
         d = c.as_dict()
         d["rc"] = rc
         return d
+
+    def set_capacities(self, caps=None):
+        """per-module capacities of MD, SEG, T3, T5 (0 = none; None = off)"""
+        if caps is None:
+            self._check(self.lib.lst_set_capacities(self.h, None))
+        else:
+            c = np.ascontiguousarray(caps, np.int32)
+            assert c.shape == (4,)
+            self._keep_caps = c
+            self._check(self.lib.lst_set_capacities(self.h, _np_ptr(c)))
+
+    # -- pixel objects and track candidates ----------------------------------
+    def load_pixel(self, px_offsets, x, y, z, seed_offsets, seeds, pix_params, stream=None):
+        """pixel hits and seeds of the loaded batch (host arrays); grows the
+        arena's pixel capacities when needed (which needs the hits loaded
+        again: call before the chain)"""
+        px_offsets = np.ascontiguousarray(px_offsets, np.int32)
+        seed_offsets = np.ascontiguousarray(seed_offsets, np.int32)
+        n_px, n_sd = int(px_offsets[-1]), int(seed_offsets[-1])
+        need = dict(px_hits=max(n_px, 1), seeds=max(n_sd, 1), px_cand=max(4096, 8 * n_sd))
+        if any(self.caps.get(k, 0) < v for k, v in need.items()):
+            raise LSTError(LST_E_CAPACITY, f"reserve pixel capacities first: {need}")
+        arrs = [np.ascontiguousarray(a, np.float32) for a in (x, y, z)]
+        sd = np.ascontiguousarray(seeds, np.int32).reshape(-1)
+        pp = np.ascontiguousarray(pix_params, np.float64)
+        self._keep_px = [px_offsets, seed_offsets, sd, pp] + arrs
+        self._check(self.lib.lst_load_pixel(self.h, len(px_offsets) - 1, _np_ptr(px_offsets),
+                                            *[_np_ptr(a) for a in arrs], _np_ptr(seed_offsets),
+                                            _np_ptr(sd), _np_ptr(pp), len(pp), self._stream(stream)))
+
+    def pixel_caps(self, n_px, n_seeds):
+        """reserve an arena that also holds n_px pixel hits and n_seeds seeds"""
+        caps = dict(self.caps)
+        caps.update(px_hits=max(n_px, 1, caps.get("px_hits", 0)),
+                    seeds=max(n_seeds, 1, caps.get("seeds", 0)),
+                    px_cand=max(4096, 8 * n_seeds, caps.get("px_cand", 0)))
+        if caps != self.caps:
+            self.reserve(caps)
+
+    def run_pixel(self, stream=None):
+        self._check(self.lib.lst_run_pixel(self.h, self._stream(stream)))
+
+    def _rows(self, fn, width, *args, stream=None):
+        n = ctypes.c_int64(0)
+        rc = fn(self.h, *args, None, 0, ctypes.byref(n), self._stream(stream))
+        if rc not in (LST_OK, LST_E_CAPACITY):
+            self._check(rc)
+        out = np.zeros((max(n.value, 1), width), np.int32)
+        self._check(fn(self.h, *args, _np_ptr(out), n.value, ctypes.byref(n), self._stream(stream)))
+        return out[:n.value]
+
+    def track_candidates(self, event, stream=None) -> np.ndarray:
+        """[n, 12]: type, seed (-1 for T5), outer hits (-1 padded)"""
+        return self._rows(self.lib.lst_get_track_candidates, 12, event, stream=stream)
+
+    def pixel_candidates(self, event, what, stream=None) -> np.ndarray:
+        """[n, 13]: seed, outer hits (-1 padded), score bits, kept (what 0 pT5, 1 pT3)"""
+        return self._rows(self.lib.lst_get_pixel_candidates, 13, event, int(what), stream=stream)
+
+    def run_event_pixel(self, ev, px, pix_params, stream=None, graph=False):
+        """one event through the chain and the pixel stage"""
+        offs = np.array([0, ev.n_hits], np.int32)
+        if self.caps is None:
+            self.reserve(default_caps(1, ev.n_hits))
+        self.pixel_caps(px.n_hits, px.n_seeds)
+        self.run_batch(offs, ev.x, ev.y, ev.z, ev.module, ev.sensor, stream, graph=graph)
+        self.load_pixel(np.array([0, px.n_hits], np.int32), px.x, px.y, px.z,
+                        np.array([0, px.n_seeds], np.int32), px.seeds, pix_params, stream)
+        self.run_pixel(stream)
+        return self.track_candidates(0, stream)
 
     def raise_error_flags(self, bits, stream=None):
         """test hook: OR error bits 1/2 into the device error word (lst_raise_error_flags)"""

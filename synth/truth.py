@@ -73,3 +73,37 @@ def metrics(t5_tuples: np.ndarray, ev, geo: G.Geometry) -> dict:
     return dict(n_obj=n, n_findable=int(len(fnd)), n_found=found,
                 eff=found / max(len(fnd), 1), fake=n_fake / max(n, 1), dup=n_dup / max(n, 1),
                 n_fake=n_fake, n_dup=n_dup)
+
+
+def tc_metrics(tc, ev, px, geo: G.Geometry) -> dict:
+    """Track candidates (rows: type, seed, 10 outer hits -1 padded) against
+    the simulated tracks.  A candidate matches a track when at least 75 % of
+    its hits (outer hits and its seed's four pixel hits) come from it;
+    findable = p_T >= 0.8 GeV and either quintuplet-findable (five
+    consecutive layers with a hit pair) or with a hit on all four pixel
+    layers."""
+    tc = np.asarray(tc).reshape(-1, 12)
+    ptr = ev.tracks["pt"]
+    fnd = set(findable(ev, geo).tolist())
+    px_tr = {}
+    for h, t in enumerate(px.truth.tolist()):
+        px_tr[t] = px_tr.get(t, 0) + 1
+    fnd |= {t for t, n in px_tr.items() if n == 4 and ptr[t] >= 0.8}
+    match = []
+    for row in tc:
+        hits = [int(ev.truth[h]) for h in row[2:] if h >= 0]
+        if row[1] >= 0:
+            hits += [int(px.truth[h]) for h in px.seeds[row[1]]]
+        ids, cnt = np.unique([h for h in hits if h >= 0], return_counts=True)
+        ok = len(cnt) and cnt.max() >= 0.75 * len(hits)
+        match.append(int(ids[np.argmax(cnt)]) if ok else -1)
+    match = np.array(match, np.int64)
+    matched = set(match[match >= 0].tolist())
+    n = len(tc)
+    n_fake = int(np.sum(match < 0))
+    n_dup = int(np.sum(match >= 0) - len(matched))
+    found = len(fnd & matched)
+    by_type = {int(t): int(np.sum(tc[:, 0] == t)) for t in range(4)}
+    return dict(n_obj=n, n_findable=len(fnd), n_found=found, eff=found / max(len(fnd), 1),
+                fake=n_fake / max(n, 1), dup=n_dup / max(n, 1), n_fake=n_fake, n_dup=n_dup,
+                by_type=by_type)
