@@ -88,6 +88,11 @@ def _load():
     lib.orc_tc.argtypes = [P, P]
     lib.orc_eval_link.restype = ctypes.c_int
     lib.orc_eval_link.argtypes = [P, P, P, ctypes.c_int, P, P, P]
+    lib.orc_set_hit_storage.argtypes = [P, ctypes.c_int]
+    lib.orc_f32_to_f16.restype = ctypes.c_uint16
+    lib.orc_f32_to_f16.argtypes = [ctypes.c_float]
+    lib.orc_f16_to_f32.restype = ctypes.c_float
+    lib.orc_f16_to_f32.argtypes = [ctypes.c_uint16]
     lib.orc_set_truncation.restype = ctypes.c_int
     lib.orc_set_truncation.argtypes = [P, P]
     lib.orc_dropped.argtypes = [P, P]
@@ -111,6 +116,19 @@ class Result:
     t3_features: np.ndarray  # float32 [n_t3, 40]
     cands: np.ndarray       # int64 [4]
     near: dict              # kind -> (tuples, margins, decisions)
+
+
+def f32_to_f16_bits(values) -> np.ndarray:
+    """the oracle's binary32 -> binary16 conversion (nearest even), as bits"""
+    lib = _load()
+    return np.array([lib.orc_f32_to_f16(float(v)) for v in np.asarray(values, np.float32)],
+                    np.uint16)
+
+
+def f16_bits_to_f32(bits) -> np.ndarray:
+    lib = _load()
+    return np.array([lib.orc_f16_to_f32(int(b)) for b in np.asarray(bits, np.uint16)],
+                    np.float32)
 
 
 @dataclass
@@ -156,6 +174,10 @@ class Oracle:
         out = np.zeros(7, np.float32)
         self._lib.orc_consts(self._h, _ptr(out))
         return dict(zip(("kmax", "klim", "kh", "tolu", "tolv", "tolkc", "epsak"), out))
+
+    def set_hit_storage(self, fp16: bool):
+        """hits stored as module-local FP16 (u, v) for later events"""
+        self._lib.orc_set_hit_storage(self._h, int(bool(fp16)))
 
     def set_truncation(self, caps=None):
         """per-module capacities (MD, SEG, T3, T5; 0 = none) for later events"""

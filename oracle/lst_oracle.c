@@ -48,6 +48,7 @@ typedef struct {
 typedef struct {
     float cx, cy, cz, ux, uy, uz, vx, vy, vz, g, rl;
     int barrel;
+    float wx, wy, wz;   /* sensor normal (hit storage rebuild) */
 } MODF;
 
 typedef struct {
@@ -153,6 +154,7 @@ struct orc {
     uint8_t *t3_veto;   /* triplets excluded from the quintuplet stage (or NULL) */
     int32_t n_hits;
     int64_t cand[4];
+    int hit_fp16;       /* hits stored as module-local FP16 (u, v) before the chain */
     int32_t cap[4];     /* per-module capacity of MD, SEG, T3, T5 (0: none) */
     int64_t dropped[4]; /* objects the capacities removed in the last event */
     /* pixel objects of the last orc_run_pixel */
@@ -342,6 +344,7 @@ orc *orc_create(const double *params, int n_params, int n_mod, const float *f32,
         M->ux = f32[3 * n_mod + m]; M->uy = f32[4 * n_mod + m]; M->uz = f32[5 * n_mod + m];
         M->vx = f32[6 * n_mod + m]; M->vy = f32[7 * n_mod + m]; M->vz = f32[8 * n_mod + m];
         float wx = f32[9 * n_mod + m], wy = f32[10 * n_mod + m];
+        M->wx = wx; M->wy = wy; M->wz = f32[11 * n_mod + m];
         M->g = f32[14 * n_mod + m];
         M->barrel = i32[1 * n_mod + m] == 0;
         /* apothem of the lower sensor plane (barrel) */
@@ -540,6 +543,77 @@ static void cap_grouped(orc *o, int kind, gvec *v, int32_t *off, const int32_t *
     free(keep);
 }
 
+/* ---- half-precision hit storage (Sec. 4 outlook: half-precision data
+ * types) ----
+ * A hit is kept as its in-plane coordinates in its module's frame, relative
+ * to the module centre, each rounded to binary16 (round to nearest, ties to
+ * even), and its sensor; the chain then works on the FP32 position rebuilt
+ * from them.  Every FP32 operation in the fixed order below. */
+
+/* binary32 -> binary16 bits, round to nearest even (no NaN inputs here:
+ * the coordinates are differences of finite positions) */
+uint16_t orc_f32_to_f16(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    const uint32_t sign = (u >> 16) & 0x8000u;
+    const uint32_t a = u & 0x7fffffffu;
+    if (a >= 0x7f800000u) return (uint16_t)(sign | 0x7c00u | (a > 0x7f800000u ? 0x200u : 0u));
+    if (a >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u);    /* rounds past 65504 */
+    const int e = (int)(a >> 23) - 127;
+    uint32_t mant = (a & 0x7fffffu) | 0x800000u;                 /* 24 bits, implicit one */
+    int shift;                                                   /* bits dropped */
+    uint32_t base;
+    if (e >= -14) {                                              /* normal binary16 */
+        shift = 13;
+        base = ((uint32_t)(e + 15) << 10);
+        mant &= 0x7fffffu;                                       /* fraction only */
+        uint32_t q = mant >> shift, rem = mant & ((1u << shift) - 1u), half = 1u << (shift - 1);
+        uint32_t r = base + q;
+        if (rem > half || (rem == half && (q & 1u))) r += 1u;  /* carries into the exponent */
+        return (uint16_t)(sign | r);
+    }
+    if (e < -25) return (uint16_t)sign;                          /* below half the smallest subnormal */
+    shift = -e - 1;                                              /* subnormal: value = q 2^-24 */
+    uint32_t q = mant >> shift, rem = mant & ((1u << shift) - 1u), half = 1u << (shift - 1);
+    if (rem > half || (rem == half && (q & 1u))) q += 1u;
+    return (uint16_t)(sign | q);
+}
+
+float orc_f16_to_f32(uint16_t h)
+{
+    const uint32_t sign = (uint32_t)(h & 0x8000u) << 16;
+    const uint32_t e = (h >> 10) & 0x1fu, m = h & 0x3ffu;
+    float v;
+    if (e == 0) {
+        v = (float)m * 0x1p-24f;                                 /* exact: m < 2^10 */
+    } else if (e == 31) {
+        uint32_t u = sign | 0x7f800000u | (m << 13);
+        memcpy(&v, &u, 4);
+        return v;
+    } else {
+        uint32_t u = ((e + 112u) << 23) | (m << 13);
+        memcpy(&v, &u, 4);
+    }
+    return sign ? -v : v;
+}
+
+/* the FP32 position a hit has after half-precision storage */
+static void stored_hit(const MODF *M, int sensor, float x, float y, float z, float *out)
+{
+    float dx = x - M->cx, dy = y - M->cy, dz = z - M->cz;
+    float u = ((dx * M->ux) + (dy * M->uy)) + (dz * M->uz);
+    float v = ((dx * M->vx) + (dy * M->vy)) + (dz * M->vz);
+    float uh = orc_f16_to_f32(orc_f32_to_f16(u));
+    float vh = orc_f16_to_f32(orc_f32_to_f16(v));
+    float w = (sensor ? 0.5f : -0.5f) * M->g;
+    out[0] = ((M->cx + (uh * M->ux)) + (vh * M->vx)) + (w * M->wx);
+    out[1] = ((M->cy + (uh * M->uy)) + (vh * M->vy)) + (w * M->wy);
+    out[2] = ((M->cz + (uh * M->uz)) + (vh * M->vz)) + (w * M->wz);
+}
+
+void orc_set_hit_storage(orc *o, int fp16) { o->hit_fp16 = fp16 != 0; }
+
 int orc_set_truncation(orc *o, const int32_t *caps4)
 {
     for (int k = 0; k < 4; ++k)
@@ -556,6 +630,19 @@ int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float 
     if (n_hits < 0) return -1;
     for (int32_t h = 0; h < n_hits; ++h)
         if (module[h] < 0 || module[h] >= o->n_mod || sensor[h] > 1) return -1;
+    float *xs = NULL, *ys = NULL, *zs = NULL;
+    if (o->hit_fp16) {
+        /* the chain runs on the positions half-precision storage gives back */
+        xs = (float *)malloc((size_t)(n_hits > 0 ? n_hits : 1) * sizeof(float));
+        ys = (float *)malloc((size_t)(n_hits > 0 ? n_hits : 1) * sizeof(float));
+        zs = (float *)malloc((size_t)(n_hits > 0 ? n_hits : 1) * sizeof(float));
+        for (int32_t h = 0; h < n_hits; ++h) {
+            float p[3];
+            stored_hit(&o->mod[module[h]], sensor[h], x[h], y[h], z[h], p);
+            xs[h] = p[0]; ys[h] = p[1]; zs[h] = p[2];
+        }
+        x = xs; y = ys; z = zs;
+    }
     free_event(o);
     gv_clear(&o->md); gv_clear(&o->seg); gv_clear(&o->t3); gv_clear(&o->t5);
     for (int k = 0; k < 4; ++k) gv_clear(&o->near[k]);
@@ -679,6 +766,7 @@ int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float 
     free(md_off);
     o->n_hits = n_hits;
     run_t5_dedup(o);
+    free(xs); free(ys); free(zs);
     return 0;
 }
 

@@ -94,6 +94,16 @@ int orc_eval_t5_features(const orc *o, const int32_t *mods5, const float *hits30
  * decides it, infinite when two or more cuts fail */
 double orc_eval_margin(const orc *o, int kind, const int32_t *mods, const float *hits);
 
+/* Half-precision hit storage (Sec. 4 outlook): with fp16 set, every hit of
+ * the next events is stored as its module-local in-plane coordinates (FP32
+ * u, v relative to the module centre, each rounded to binary16, nearest
+ * even) and rebuilt as centre + u U + v V + (sensor ? +g/2 : -g/2) W in FP32
+ * before the chain runs on it.  orc_f32_to_f16 / orc_f16_to_f32: the
+ * conversions it uses. */
+void orc_set_hit_storage(orc *o, int fp16);
+uint16_t orc_f32_to_f16(float f);
+float orc_f16_to_f32(uint16_t h);
+
 /* Per-module capacities (Sec. 3: fixed per-module output arrays truncated at
  * an occupancy quantile) of MD, SEG, T3, T5 (caps4; 0 or NULL: none), applied
  * from the next orc_run on: a module (that of an object's first MD) holding

@@ -15,6 +15,11 @@ the mini-doublets, 2.4 % of the segments, 1 % of the triplets, 0.7 % of the
 quintuplets and 6 % of the kept quintuplets (mostly which of two near-equal
 duplicates survives); efficiency 97.01 % -> 96.93 %, fake rate unchanged.
 Global FP16: efficiency 67 %.
+
+The module-local storage is built: the oracle's storage mode
+(`Oracle.set_hit_storage`) is pinned here against NumPy's FP16 conversion
+and the positions rebuilt below, and the library's mode
+(`lst_set_hit_storage`) is compared with it on the GPU.
 """
 import numpy as np
 import pytest
@@ -117,3 +122,47 @@ def test_local_fp16_costs_little_efficiency(study):
 def test_global_fp16_is_far_too_coarse(study):
     assert study["global_f16"]["err"] > 0.05        # > 0.5 mm at the outer layers
     assert study["global_f16"]["eff"] < study["ref"]["eff"] - 0.1
+
+
+# ---------------------------------------------------------------- the storage mode
+def test_oracle_fp16_conversion_is_numpys():
+    """the oracle's binary32 -> binary16 rounding (nearest, ties to even) and
+    its inverse against NumPy's own conversion: random values over every
+    exponent a module coordinate can take and beyond, exact ties between two
+    binary16 values, subnormals, and every binary16 bit pattern back"""
+    rng = np.random.default_rng(71)
+    v = (rng.uniform(-1, 1, 60000) * 2.0 ** rng.integers(-28, 17, 60000)).astype(np.float32)
+    h16 = np.arange(0, 0x7c00, 7, dtype=np.uint16)            # finite positive patterns
+    lo = h16[:-1].view(np.float16).astype(np.float64)
+    hi = (h16[:-1] + 1).view(np.float16).astype(np.float64)
+    ties = (0.5 * (lo + hi)).astype(np.float32)                # exact in binary32
+    vals = np.concatenate([v, ties, -ties, np.float32([0.0, -0.0, 65504.0, 1e-8])])
+    assert np.array_equal(oracle.f32_to_f16_bits(vals), vals.astype(np.float16).view(np.uint16))
+    allh = np.arange(0, 0x10000, dtype=np.uint32).astype(np.uint16)
+    allh = allh[(allh & 0x7c00) != 0x7c00]                     # no Inf/NaN
+    assert np.array_equal(oracle.f16_bits_to_f32(allh).view(np.uint32),
+                          allh.view(np.float16).astype(np.float32).view(np.uint32))
+
+
+@pytest.mark.parametrize("cid,event", [(1, 0), (2, 300)])
+def test_oracle_storage_mode_is_the_rebuilt_positions(cid, event):
+    """the oracle with half-precision hit storage equals the plain oracle run
+    on the positions rebuilt here from NumPy's FP16 rounding of the
+    module-local coordinates (same FP32 operation order)"""
+    cfg = E.CONFIGS[cid]
+    geo = G.get(cfg.geometry)
+    params = PR.make(w=cfg.window)
+    ev = E.generate(cid, event)
+    plain = oracle.Oracle(params, geo.f32, geo.i32)
+    x, y, z = _rebuild(geo, ev, _half)
+    want = plain.run(x, y, z, ev.module, ev.sensor)
+    half = oracle.Oracle(params, geo.f32, geo.i32)
+    half.set_hit_storage(True)
+    got = half.run_event(ev)
+    tup = lambda a: set(map(tuple, a.tolist()))
+    for k in range(5):
+        assert tup(got.tuples[k]) == tup(want.tuples[k]), k
+    assert np.array_equal(got.cands, want.cands)
+    # and the mode does change the chain (the rounding is not a no-op)
+    ref = plain.run_event(ev)
+    assert any(tup(ref.tuples[k]) != tup(got.tuples[k]) for k in range(4))
