@@ -89,6 +89,7 @@ def _load():
     lib.orc_eval_link.restype = ctypes.c_int
     lib.orc_eval_link.argtypes = [P, P, P, ctypes.c_int, P, P, P]
     lib.orc_set_hit_storage.argtypes = [P, ctypes.c_int]
+    lib.orc_set_margins.argtypes = [P, ctypes.c_int]
     lib.orc_f32_to_f16.restype = ctypes.c_uint16
     lib.orc_f32_to_f16.argtypes = [ctypes.c_float]
     lib.orc_f16_to_f32.restype = ctypes.c_float
@@ -178,6 +179,11 @@ class Oracle:
     def set_hit_storage(self, fp16: bool):
         """hits stored as module-local FP16 (u, v) for later events"""
         self._lib.orc_set_hit_storage(self._h, int(bool(fp16)))
+
+    def set_margins(self, on: bool):
+        """FP64 margins on (default) or off (FP32 decisions only, no
+        near-threshold records; objects unchanged)"""
+        self._lib.orc_set_margins(self._h, int(bool(on)))
 
     def set_truncation(self, caps=None):
         """per-module capacities (MD, SEG, T3, T5; 0 = none) for later events"""

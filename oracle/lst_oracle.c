@@ -155,6 +155,7 @@ struct orc {
     int32_t n_hits;
     int64_t cand[4];
     int hit_fp16;       /* hits stored as module-local FP16 (u, v) before the chain */
+    int no_margin;      /* skip the FP64 instance (no near-threshold records) */
     int32_t cap[4];     /* per-module capacity of MD, SEG, T3, T5 (0: none) */
     int64_t dropped[4]; /* objects the capacities removed in the last event */
     /* pixel objects of the last orc_run_pixel */
@@ -614,6 +615,11 @@ static void stored_hit(const MODF *M, int sensor, float x, float y, float z, flo
 
 void orc_set_hit_storage(orc *o, int fp16) { o->hit_fp16 = fp16 != 0; }
 
+/* FP64 margins on (default) or off: off leaves every decision and object as
+ * it is and records no near-threshold candidate; for timing the FP32
+ * decisions alone */
+void orc_set_margins(orc *o, int on) { o->no_margin = on == 0; }
+
 int orc_set_truncation(orc *o, const int32_t *caps4)
 {
     for (int k = 0; k < 4; ++k)
@@ -672,9 +678,9 @@ int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float 
                 MDREC md;
                 CUTREC cf, cd;
                 o->cand[0]++;
-                int pass = make_md(o, m, L, U, &md, &cf, &cd);
+                int pass = make_md(o, m, L, U, &md, &cf, o->no_margin ? NULL : &cd);
                 md.hlo = hl; md.hup = hu;
-                double mg = cut_margin(&cf, &cd);
+                double mg = o->no_margin ? INFINITY : cut_margin(&cf, &cd);
                 if (pass) *(MDREC *)gv_push(&o->md) = md;
                 if (mg < NEAR_REL) {
                     NEARREC *r = (NEARREC *)gv_push(&o->near[0]);
@@ -711,12 +717,12 @@ int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float 
                     double z0d, kOd;
                     o->cand[1]++;
                     int pass = seg_cut_f(&o->K, &MD[i], &MD[j], &cf, &z0f, &kOf);
-                    seg_cut_d(&o->K, &MD[i], &MD[j], &cd, &z0d, &kOd);
+                    if (!o->no_margin) seg_cut_d(&o->K, &MD[i], &MD[j], &cd, &z0d, &kOd);
                     if (pass) {
                         SEGREC *s = (SEGREC *)gv_push(&o->seg);
                         s->i = i; s->o = j;
                     }
-                    double mg = cut_margin(&cf, &cd);
+                    double mg = o->no_margin ? INFINITY : cut_margin(&cf, &cd);
                     if (mg < NEAR_REL) {
                         int32_t mds[2] = {i, j};
                         push_near(o, 1, mds, 2, mg, pass);
@@ -745,14 +751,14 @@ int orc_run(orc *o, int32_t n_hits, const float *x, const float *y, const float 
                     o->cand[2]++;
                     T3AUX ax;
                     int pass = t3_cut_f(&o->K, &MD[a], &MD[b], &MD[c], &cf, &kf, &ax);
-                    t3_cut_d(&o->K, &MD[a], &MD[b], &MD[c], &cd, &kd, NULL);
+                    if (!o->no_margin) t3_cut_d(&o->K, &MD[a], &MD[b], &MD[c], &cd, &kd, NULL);
                     if (pass) {
                         T3REC *t = (T3REC *)gv_push(&o->t3);
                         t->a = (int32_t)a; t->b = b; t->c = c; t->k = kf;
                         const MDREC *P3[3] = {&MD[a], &MD[b], &MD[c]};
                         t3_features_f(&o->K, P3, &ax, t->feat);
                     }
-                    double mg = cut_margin(&cf, &cd);
+                    double mg = o->no_margin ? INFINITY : cut_margin(&cf, &cd);
                     if (mg < NEAR_REL) {
                         int32_t mds[3] = {(int32_t)a, b, c};
                         push_near(o, 2, mds, 3, mg, pass);
@@ -797,7 +803,7 @@ static void run_t5_dedup(orc *o)
             T5AUX af, ad;
             o->cand[3]++;
             int pass = t5_cut_f(&o->K, P, T3[t].k, T3[t2].k, &cf, &af);
-            t5_cut_d(&o->K, P, T3[t].k, T3[t2].k, &cd, &ad);
+            if (!o->no_margin) t5_cut_d(&o->K, P, T3[t].k, T3[t2].k, &cd, &ad);
             int32_t mds[5] = {T3[t].a, T3[t].b, c, T3[t2].b, T3[t2].c};
             if (pass) {
                 T5REC *q = (T5REC *)gv_push(&o->t5);
@@ -805,7 +811,7 @@ static void run_t5_dedup(orc *o)
                 q->score = (float)af.score;
                 t5_features_f(&o->K, P, T3[t].k, T3[t2].k, &af, q->feat);
             }
-            double mg = cut_margin(&cf, &cd);
+            double mg = o->no_margin ? INFINITY : cut_margin(&cf, &cd);
             if (mg < NEAR_REL) push_near(o, 3, mds, 5, mg, pass);
         }
     }

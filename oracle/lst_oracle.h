@@ -101,6 +101,10 @@ double orc_eval_margin(const orc *o, int kind, const int32_t *mods, const float 
  * before the chain runs on it.  orc_f32_to_f16 / orc_f16_to_f32: the
  * conversions it uses. */
 void orc_set_hit_storage(orc *o, int fp16);
+/* FP64 margins on (1, default) or off (0).  Off: the chain evaluates only
+ * the FP32 instance of each cut; objects, candidates and scores are
+ * unchanged and no near-threshold candidate is recorded. */
+void orc_set_margins(orc *o, int on);
 uint16_t orc_f32_to_f16(float f);
 float orc_f16_to_f32(uint16_t h);
 

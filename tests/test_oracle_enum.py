@@ -164,6 +164,24 @@ def test_invariants_pu200_event():
         assert np.all(res.near[kind][1] < 1e-5)
 
 
+def test_margins_off_changes_no_object():
+    """the FP64 instance only records near-threshold candidates: switched off,
+    every object, candidate count and score is the same and no near record
+    is left"""
+    geo = G.get("full")
+    ev = E.generate(2, 3, n_tracks=600)
+    on = oracle.Oracle(PR.make(), geo.f32, geo.i32)
+    off = oracle.Oracle(PR.make(), geo.f32, geo.i32)
+    off.set_margins(False)
+    a, b = on.run_event(ev), off.run_event(ev)
+    for k in range(5):
+        assert np.array_equal(a.tuples[k], b.tuples[k])
+    assert np.array_equal(a.cands, b.cands)
+    assert np.array_equal(a.t5_scores.view(np.uint32), b.t5_scores.view(np.uint32))
+    assert sum(len(a.near[k][1]) for k in range(4)) > 0
+    assert all(len(b.near[k][1]) == 0 for k in range(4))
+
+
 def test_noise_free_isolated_tracks_are_all_built():
     geo = G.get("barrel_toy")
     orc = oracle.Oracle(PR.make(), geo.f32, geo.i32)
