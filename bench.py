@@ -85,8 +85,27 @@ def copy_bandwidth(lst, torch, reps=10):
 
 
 def algorithmic_bytes(c, n_slots, n_edges_used):
-    """Minimal bytes per launch of each object kernel: every input read once,
-    every output written once, in the library's layouts.
+    """Minimal bytes per launch of each object kernel (every input read
+    once, every output written once), from the per-unit figures of the
+    method's measurement plan:
+    md:  12 B per hit + 48 B per module slot + 40 B per MD written
+    seg: 28 B per MD read + 12 B per map edge of a module holding an MD +
+         8 B per segment written
+    t3:  8 B per segment + 16 B per triplet written
+    t5:  16 B per triplet + 12 B per quintuplet written"""
+    H, S = c["n_hits"], n_slots
+    md, seg, t3, t5 = c["n_md"], c["n_seg"], c["n_t3"], c["n_t5"]
+    return {
+        "md": 12 * H + 48 * S + 40 * md,
+        "seg": 28 * md + 12 * n_edges_used + 8 * seg,
+        "t3": 8 * seg + 16 * t3,
+        "t5": 16 * t3 + 12 * t5,
+    }
+
+
+def layout_bytes(c, n_slots, n_edges_used):
+    """The same in the library's own layouts (wider records than the
+    minimal figures above; reported beside them):
     md:  sorted hit (16 B) read and its duplicate-removal state (12 B) set per
          hit; per slot two bin offsets (8 B), the module frame (52 B) and the
          slot's MD start and count (8 B); per MD its record written (85 B:
@@ -112,21 +131,31 @@ def algorithmic_bytes(c, n_slots, n_edges_used):
     }
 
 
-def cpu_baseline(params, geo, budget_s=12.0, max_events=200):
+def cpu_baseline(params, geo, budget_s=18.0, max_events=200):
+    """The oracle chain on PU200-like events, one thread: as it runs in the
+    parity tests (FP32 decisions plus the FP64 instance that records
+    near-threshold candidates), and on the same events with the FP64
+    instance switched off (FP32 decisions alone, same objects)."""
     import oracle
     from synth import events as E
     orc = oracle.Oracle(params, geo.f32, geo.i32)
-    evs = []
-    t_total, n = 0.0, 0
-    while t_total < budget_s and n < max_events:
+    fp32 = oracle.Oracle(params, geo.f32, geo.i32)
+    fp32.set_margins(False)
+    t_total, t_fp32, n = 0.0, 0.0, 0
+    while t_total + t_fp32 < budget_s and n < max_events:
         ev = E.generate(2, 1000 + n)
         t0 = time.perf_counter()
         orc.run_event(ev)
-        t_total += time.perf_counter() - t0
+        t1 = time.perf_counter()
+        fp32.run_event(ev)
+        t_total += t1 - t0
+        t_fp32 += time.perf_counter() - t1
         n += 1
     return {"value": n / t_total, "unit": "events/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} PU200-like events (config 2, seeds 1000..{999 + n}), oracle chain "
-                      f"incl. hit grouping and FP64 margins, single thread, {t_total:.1f} s"}
+                      f"incl. hit grouping and FP64 margins, single thread, {t_total:.1f} s",
+            "fp32_decisions_only": {"value": n / t_fp32, "unit": "events/s",
+                                    "sample": f"same {n} events, FP64 instance off, {t_fp32:.1f} s"}}
 
 
 def batched(lst, torch, E, G, PR, evs, steps=20, cache=None, compare=True):
@@ -407,7 +436,10 @@ def scored(lst, torch, train, evs, steps=50, base_cfg=4):
                 "eff_points": 100 * (m_scored["eff"] - m_wide["eff"]),
                 "fake_ratio": m_scored["fake"] / m_wide["fake"] if m_wide["fake"] else None,
                 "impure_points": 100 * (m_scored["impure"] - m_wide["impure"])},
-            "plain_events_per_s": rate(plain_ctx), "scored_events_per_s": rate(scored_ctx),
+            "plain_events_per_s": rate(plain_ctx),
+            # the widened windows alone, so that scored / this is the cost of scoring
+            "plain_w1.5_events_per_s": rate(wide_ctx),
+            "scored_events_per_s": rate(scored_ctx),
             "score_kernels": [kern("k_mlp_score<T3>", ms3, cnt["n_t3"]),
                               kern("k_mlp_score<T5>", ms5, cnt["n_t5"])]}, model
 
@@ -546,6 +578,124 @@ def memory(lst, torch, G, PR, evs, quantiles=(0.999, 0.9999)):
     return out
 
 
+def half_storage(lst, torch, E, G, PR, evs, steps=100):
+    """Half-precision hit storage (lst_set_hit_storage): the PU200-like event
+    (config 2, seed 0) and the 16-event PU200-like batch, each through the
+    tuned chain as one hipGraph per step, with FP32 and with FP16 module-local
+    hit storage; kept-quintuplet efficiency / fake rate by truth on the 16
+    events in both modes."""
+    from synth import truth as T
+    geo = G.get("full")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, evl in (("pu200_event", [E.generate(2, 0)]), ("pu200_batch16", evs)):
+        b = E.concat(evl)
+        row = {}
+        for mode in (0, 1):
+            ctx = lst.Context(PR.make(), geo.f32, geo.i32, device=0)
+            ctx.set_hit_storage(bool(mode))
+            ctx.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+            ctx.tune(reps=3)
+            ctx.load_hits(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+            ctx.run_chain_graph(stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ctx.run_chain_graph(stream)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            assert_clean(ctx)
+            tot = dict(n_obj=0, n_findable=0, n_found=0, n_fake=0)
+            for e, ev in enumerate(evl):
+                m = T.metrics(ctx.objects(e, lst.LST_T5_KEPT), ev, geo)
+                for k in tot:
+                    tot[k] += m[k]
+            row["fp16" if mode else "fp32"] = {
+                "events_per_s": len(evl) / dt, "ms_per_step": 1e3 * dt,
+                "eff": tot["n_found"] / max(tot["n_findable"], 1),
+                "fake": tot["n_fake"] / max(tot["n_obj"], 1), "n_obj": tot["n_obj"],
+                "hit_record_bytes": 8 if mode else 16}
+            del ctx
+        out[name] = row
+    return out
+
+
+def pixel_leg(lst, torch, E, G, PR, evs, steps=50):
+    """Pixel objects and track candidates (pLS linked to quintuplets and
+    triplets, cross-cleaning): one PU200-like event (config 2, seed 0) and the
+    16-event PU200-like batch, chain replayed as one hipGraph then the pixel
+    stage, hits and seeds resident on the device; the pixel stage alone timed
+    with HIP events on the launch stream; track-candidate efficiency, fake
+    and duplicate rate by truth beside the kept quintuplets'."""
+    from synth import truth as T
+    geo = G.get("full")
+    params, pp = PR.make(), PR.make_pixel()
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, batch in (("pu200_event", [(E.generate(2, 0), 0)]),
+                        ("pu200_batch16", [(ev, 100 + e) for e, ev in enumerate(evs)])):
+        evl = [ev for ev, _ in batch]
+        pxs = [E.pixel_seeds(ev, 2, seed) for ev, seed in batch]
+        b = E.concat(evl)
+        poff = np.r_[0, np.cumsum([p.n_hits for p in pxs])].astype(np.int32)
+        soff = np.r_[0, np.cumsum([p.n_seeds for p in pxs])].astype(np.int32)
+        cat = lambda a: np.concatenate([getattr(p, a) for p in pxs])
+        ctx = lst.Context(params, geo.f32, geo.i32, device=0)
+        ctx.reserve(lst.default_caps(len(evl), int(b.offsets[-1])))
+        ctx.pixel_caps(int(poff[-1]), int(soff[-1]))
+        ctx.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+        tuned = ctx.tune(reps=3)
+        ctx.load_hits(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+        ctx.run_chain_graph(stream)
+        ctx.load_pixel(poff, cat("x"), cat("y"), cat("z"), soff,
+                       np.concatenate([p.seeds for p in pxs]), pp)
+        ctx.run_pixel(stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        px_ms = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.run_chain_graph(stream)
+            e0.record(stream)
+            ctx.run_pixel(stream)
+            e1.record(stream)
+            e1.synchronize()
+            px_ms.append(e0.elapsed_time(e1))
+        dt_sync = (time.perf_counter() - t0) / steps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.run_chain_graph(stream)
+            ctx.run_pixel(stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        assert_clean(ctx)
+        tot = dict(n_obj=0, n_findable=0, n_found=0, n_fake=0, n_dup=0)
+        t5 = dict(tot)
+        types = [0, 0, 0, 0]
+        for e, (ev, px) in enumerate(zip(evl, pxs)):
+            m = T.tc_metrics(ctx.track_candidates(e), ev, px, geo)
+            for k in tot:
+                tot[k] += m[k]
+            for t in range(4):
+                types[t] += m["by_type"][t]
+            m5 = T.metrics(ctx.objects(e, lst.LST_T5_KEPT), ev, geo)
+            for k in t5:
+                t5[k] += m5[k]
+        rate = lambda d: {"eff": d["n_found"] / max(d["n_findable"], 1),
+                          "fake": d["n_fake"] / max(d["n_obj"], 1),
+                          "dup": d["n_dup"] / max(d["n_obj"], 1), "n_obj": d["n_obj"]}
+        out[name] = {"events": len(evl), "seeds": int(soff[-1]),
+                     "events_per_s_chain_plus_pixel": len(evl) / dt,
+                     "pixel_stage_us": 1e3 * float(np.median(px_ms)),
+                     "ms_per_step": 1e3 * dt,
+                     "track_candidates": dict(rate(tot), by_type=dict(zip(("pT5", "pT3", "T5", "pLS"), types))),
+                     "kept_quintuplets": rate(t5),
+                     "tuning": {k: tuned[k] for k in ("grid", "lanes", "persistent", "blocks_per_cu")}}
+        del ctx
+    return out
+
+
 def stress(lst, torch, E, G, PR, evs, model=None, model_transfer=None, steps=10):
     """16 PU300-like events (6000 helices, 5 % displaced, 10 % noise, windows
     x1.5) in one tuned launch: events/s and efficiency / fake / duplicate rate
@@ -612,6 +762,9 @@ def main():
                     help="skip the figures with several PU200-like events in flight")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the 64-event batch leg and print its figures (for profiling)")
+    ap.add_argument("--pixel-only", action="store_true",
+                    help="run only the pixel-object leg and the half-precision storage leg "
+                         "and print their figures (for profiling)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache (JSON lines): reuse a stored launch shape for this event")
     args = ap.parse_args()
@@ -627,6 +780,15 @@ def main():
         from synth import events as E, geometry as G, params as PR
         print(json.dumps({"batched": batched(lst, torch, E, G, PR, pre["batch"],
                                              cache=args.tune_cache, compare=False)}), flush=True)
+        return
+    if args.pixel_only:
+        pre = pregenerate(scorer=False, batch=False, stress=False, pu200=True)
+        import torch
+        import paper_2209_13711_amd as lst
+        from synth import events as E, geometry as G, params as PR
+        print(json.dumps({"pixel": pixel_leg(lst, torch, E, G, PR, pre["pu200"], steps=20),
+                          "half_storage": half_storage(lst, torch, E, G, PR, pre["pu200"],
+                                                       steps=20)}), flush=True)
         return
     pre = pregenerate(scorer=not args.no_scorer, batch=not args.no_batch,
                       stress=not args.no_stress, pu200=not args.no_concurrent)
@@ -740,6 +902,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom_kernel),
                      "algorithmic_bytes": int(abytes[dom]),
+                     "layout_bytes": int(layout_bytes(cnt, n_slots, n_edges_used)[dom]),
                      "duration_us": stage_ms[dom] * 1e3,
                      "copy_GBps_measured": copy_gbs,
                      "frac_vs_copy": achieved / copy_gbs},
@@ -747,6 +910,8 @@ def main():
     if not args.no_concurrent:
         out["pu200_concurrent"] = pu200_concurrent(lst, torch, E, G, PR, pre["pu200"])
         out["memory"] = memory(lst, torch, G, PR, pre["pu200"])
+        out["pixel"] = pixel_leg(lst, torch, E, G, PR, pre["pu200"])
+        out["half_storage"] = half_storage(lst, torch, E, G, PR, pre["pu200"])
     if not args.no_batch:
         out["batched"] = batched(lst, torch, E, G, PR, pre["batch"], cache=args.tune_cache)
         out["batched"]["multistream_8"] = multistream(lst, torch, G, PR, pre["batch"])

@@ -112,7 +112,8 @@ typedef struct {
  * event reports instead the batch-wide number of MD/SEG/T3/T5 required.  overflow_mask bit k = stage k (MD, SEG,
  * T3, T5) ran out of capacity; error_flags bit 0 = a hit with an invalid
  * module or sensor id was skipped, bit 1 = a persistent-chain barrier timed
- * out, bit 2 = the hit-grouping scan timed out waiting for a predecessor tile
+ * out, bit 2 = the hit grouping failed: its scan timed out waiting for a
+ * predecessor tile, or a hit's grouped position fell outside the hit arrays
  * (neither should ever happen).  With bit 1 or 2 set the outputs are unusable:
  * lst_get_counts fills *out (so the flags can be read) and returns
  * LST_E_FAULT, and every getter of objects, scores, logits or features
@@ -128,6 +129,10 @@ typedef struct {
      * pT3 link candidates and those left after cross-cleaning; track
      * candidates (pT5 + pT3 + T5 + pLS); 0 before */
     int64_t n_pls, cand_pt5, n_pt5, cand_pt3, n_pt3, n_tc;
+    /* 1: the context was in scorer mode (LST_MODE_MLP) with no network
+     * loaded, or with every loaded one rejected, so the batch ran the plain
+     * cut chain; 0 otherwise */
+    int32_t mlp_fallback;
 } lst_counts;
 
 /* Create a context on HIP device `device`.  params: LST_N_PARAMS doubles. */
@@ -170,6 +175,19 @@ int lst_attach_arena(lst_ctx *ctx, void *dev_ptr, size_t bytes, const lst_caps *
 int lst_load_hits(lst_ctx *ctx, int32_t n_events, const int32_t *hit_offsets, const float *x,
                   const float *y, const float *z, const int32_t *module, const uint8_t *sensor,
                   int on_device, void *stream);
+
+/* Half-precision hit storage (Sec. 4, Summary and Outlook: half-precision
+ * data types).  fp16 = 1: the grouping stage stores each hit as its in-plane
+ * coordinates in its module's frame, relative to the module centre (u along
+ * the precise axis, v along the coarse one), each rounded to binary16
+ * (nearest even), with its per-event index: 8 bytes instead of 16; the
+ * mini-doublet stage rebuilds the FP32 position centre + u U + v V +
+ * (+-gap/2) W (every operation FP32, in that order) and every later stage
+ * works on it.  Module half-sizes are below 8 cm, so each coordinate moves by
+ * at most 2^-9 cm.  fp16 = 0 (default): FP32 positions.  Later chains use the
+ * mode; a batch grouped in the other mode must be grouped again
+ * (LST_E_STATE until then).  LST_E_INVALID for other values. */
+int lst_set_hit_storage(lst_ctx *ctx, int32_t fp16);
 
 /* Per-module capacities (Sec. 3: every object kind held in arrays of a fixed
  * capacity per module, set at the 99.9 % or 99.99 % quantile of the
@@ -371,18 +389,20 @@ int lst_stream_copy(void *dst, const void *src, size_t n_bytes, void *stream);
 
 /* Copy the scorer of `kind` (LST_T3: triplets, LST_T5: quintuplets; host
  * arrays: LST_MLP_NPARAM parameters, mean[40], istd[40]) and its logit
- * threshold into the context.  Synchronous; values must be finite (else
- * LST_E_INVALID).  Each kind has its own network; either or both may be
- * loaded. */
+ * threshold into the context.  Synchronous; values must be finite: else
+ * LST_E_INVALID, and the kind's earlier network, if any, is unloaded so that
+ * its stage runs the plain cuts.  Each kind has its own network; either or
+ * both may be loaded. */
 int lst_mlp_load(lst_ctx *ctx, int32_t kind, const float *params, int32_t n_params,
                  const float *mean, const float *istd, float threshold);
 
-/* LST_MODE_CUTS or LST_MODE_MLP (needs lst_mlp_load of at least one kind,
- * else LST_E_STATE).  lst_run_chain, lst_run_chain_graph and
- * lst_run_chain_persistent then include a scoring step for every loaded
- * kind: triplets are scored before the quintuplet stage (a vetoed triplet
- * joins no quintuplet), quintuplets before duplicate removal (a vetoed
- * quintuplet takes no part in it). */
+/* LST_MODE_CUTS or LST_MODE_MLP.  In LST_MODE_MLP lst_run_chain,
+ * lst_run_chain_graph and lst_run_chain_persistent include a scoring step
+ * for every loaded kind: triplets are scored before the quintuplet stage (a
+ * vetoed triplet joins no quintuplet), quintuplets before duplicate removal
+ * (a vetoed quintuplet takes no part in it).  With no kind loaded (never
+ * loaded, or rejected as not finite) the chain falls back to the plain cuts
+ * and lst_counts.mlp_fallback reports it for every event of the batch. */
 int lst_set_mode(lst_ctx *ctx, int32_t mode);
 
 /* The scoring steps on their own (else LST_E_STATE): lst_run_t3_score

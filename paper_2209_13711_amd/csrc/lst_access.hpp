@@ -11,6 +11,12 @@ __device__ __forceinline__ bool upstream_overflow(const EvDev &E)
     return E.gc[GC_OVERFLOW] != 0u;
 }
 
+// per-event index of grouped hit h (either storage)
+__device__ __forceinline__ int32_t hit_orig(const EvDev &E, int32_t h)
+{
+    return E.half16 ? (int32_t)E.hsort_h[h].y : __float_as_int(E.hsort[h].w);
+}
+
 __device__ __forceinline__ int32_t t5_md(const EvDev &E, int32_t t, int j)
 {
     switch (j) {

@@ -63,9 +63,11 @@ struct lst_ctx {
     // per kind (0 triplets, 1 quintuplets): params [MLP_NPARAM], mean [40], istd [40]
     float *mlp_dev[2] = {nullptr, nullptr};
     float mlp_threshold[2] = {0.0f, 0.0f};
+    bool fallback = false;   // the running batch: scorer mode without a network
     bool t3_features_valid = false;
     void *fixed_work = nullptr;   // this device's copy of the fixed backward workspace
     int32_t cap[OT_COUNT] = {0, 0, 0, 0};   // per-module capacities (0: none)
+    int32_t half16 = 0;                       // half-precision hit storage
     // pixel objects: constants of the loaded pixel parameters, host copy of
     // the batch's seed and pixel offsets, loaded for the current hits
     PixConsts pxk{};
@@ -182,8 +184,10 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
     E.sensor = cv.take<uint8_t>(k.hits);
     E.hit_off = cv.take<int32_t>(k.events + 1);
     // grouping
+    E.hrank = cv.take<uint32_t>(k.hits);
     E.boff = cv.take<uint32_t>(keys + 1);
     E.hsort = cv.take<float4>(k.hits);
+    E.hsort_h = cv.take<uint2>(k.hits);
     E.hmin = cv.take<uint32_t>(k.hits);
     E.htie = cv.take<int32_t>(k.hits);
     E.hslot = cv.take<int32_t>((size_t)k.hits * TIE_SLOTS);
@@ -261,11 +265,14 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
         E.t5_dir = cv.take<float4>(nt5);
         E.t3_dir = cv.take<float4>(nt3);
         E.t5_clean = cv.take<uint8_t>(nt5);
-        E.pl_cnt = cv.take<int32_t>((size_t)PXL_COUNT * k.events);
-        E.pl_fill = cv.take<int32_t>((size_t)PXL_COUNT * k.events);
-        E.pl_off = cv.take<int32_t>((size_t)PXL_COUNT * (k.events + 1));
+        const size_t pl_n = (size_t)PXL_COUNT * ((size_t)k.events * PX_NB + 1);
+        E.pl_cnt = cv.take<int32_t>(pl_n);
+        E.pl_fill = cv.take<int32_t>(pl_n);
+        E.pl_off = cv.take<int32_t>(pl_n);
         E.pl_k5 = cv.take<int32_t>(nt5);
         E.pl_k3 = cv.take<int32_t>(nt3);
+        E.pl_k5d = cv.take<float4>(nt5);
+        E.pl_k3d = cv.take<float4>(nt3);
         E.pl_d5 = cv.take<float4>(k.px_cand);
         E.pl_d3 = cv.take<float4>(k.px_cand);
         E.pl_dt = cv.take<float4>(nt5);
@@ -277,9 +284,11 @@ size_t carve(lst_ctx *c, char *base, const lst_caps &k, EvDev &E, void **zero_ba
         E.c3_obj = cv.take<int32_t>(k.px_cand);
         E.c3_score = cv.take<float>(k.px_cand);
         E.c3_keep = cv.take<uint8_t>(k.px_cand);
+        E.sd_c5 = cv.take<int2>(k.seeds);
+        E.sd_c3 = cv.take<int2>(k.seeds);
+        E.sd_free = cv.take<int32_t>(k.seeds);
         E.hmin_o = cv.take<unsigned long long>(k.hits);
         E.hmin_p = cv.take<unsigned long long>(k.px_hits);
-        E.htie_p = cv.take<uint32_t>(k.px_hits);
         E.hflag_o = cv.take<uint8_t>(k.hits);
         E.hflag_p = cv.take<uint8_t>(k.px_hits);
     }
@@ -298,10 +307,17 @@ static int d2h(lst_ctx *c, std::vector<T> &v, const T *src, size_t n)
 // per-event index of each of the first n sorted hits
 static int sorted_orig(lst_ctx *c, std::vector<int32_t> &out, size_t n)
 {
+    out.resize(std::max<size_t>(n, 1));
+    if (c->E.half16) {
+        std::vector<uint2> h;
+        int rc = d2h(c, h, (const uint2 *)c->E.hsort_h, n);
+        if (rc) return rc;
+        for (size_t i = 0; i < n; ++i) out[i] = (int32_t)h[i].y;
+        return LST_OK;
+    }
     std::vector<float4> h;
     int rc = d2h(c, h, (const float4 *)c->E.hsort, n);
     if (rc) return rc;
-    out.resize(std::max<size_t>(n, 1));
     for (size_t i = 0; i < n; ++i) std::memcpy(&out[i], &h[i].w, sizeof(int32_t));
     return LST_OK;
 }
@@ -387,8 +403,8 @@ int lst_load_geometry(lst_ctx *c, int32_t n, const float *f32, const int32_t *i3
     c->mod_i32.assign(i32, i32 + (size_t)LST_MOD_NI * n);
     build_module_map(n, f32, i32, c->params, c->map_ptr, c->map_col);
 
-    // device geometry: 11 float rows, barrel flags, map
-    std::vector<float> rows((size_t)11 * n);
+    // device geometry: 14 float rows, barrel flags, map
+    std::vector<float> rows((size_t)14 * n);
     std::vector<int32_t> barrel(2 * (size_t)n);   // barrel flags, then 2S flags
     const int src[10] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 14};  // cx..vz, gap
     for (int r = 0; r < 10; ++r)
@@ -397,6 +413,9 @@ int lst_load_geometry(lst_ctx *c, int32_t n, const float *f32, const int32_t *i3
         const float cx = f32[m], cy = f32[n + m], wx = f32[9 * n + m], wy = f32[10 * n + m];
         const float g = f32[14 * n + m];
         rows[(size_t)10 * n + m] = ((cx * wx) + (cy * wy)) - (0.5f * g);  // lower-sensor apothem
+        rows[(size_t)11 * n + m] = wx;                                     // sensor normal
+        rows[(size_t)12 * n + m] = wy;
+        rows[(size_t)13 * n + m] = f32[11 * n + m];
         barrel[m] = i32[n + m] == 0 ? 1 : 0;
         barrel[(size_t)n + m] = i32[3 * n + m] == 1 ? 1 : 0;
     }
@@ -440,10 +459,11 @@ int lst_load_geometry(lst_ctx *c, int32_t n, const float *f32, const int32_t *i3
         HIPCHK(c, hipMemcpy(dcol, c->map_col.data(), c->map_col.size() * sizeof(int32_t),
                             hipMemcpyHostToDevice));
     ModDev &M = c->M;
-    float *r[11];
-    for (int i = 0; i < 11; ++i) r[i] = drows + (size_t)i * n;
+    float *r[14];
+    for (int i = 0; i < 14; ++i) r[i] = drows + (size_t)i * n;
     M.cx = r[0]; M.cy = r[1]; M.cz = r[2]; M.ux = r[3]; M.uy = r[4]; M.uz = r[5];
     M.vx = r[6]; M.vy = r[7]; M.vz = r[8]; M.g = r[9]; M.rl = r[10];
+    M.wx = r[11]; M.wy = r[12]; M.wz = r[13];
     M.barrel = dbar;
     M.is2s = dbar + n;
     M.map_ptr = dptr;
@@ -558,6 +578,7 @@ int lst_attach_arena(lst_ctx *c, void *dev_ptr, size_t bytes, const lst_caps *ca
     c->arena_bytes = bytes;
     c->caps = *caps;
     carve(c, c->arena, *caps, c->E, &c->zero_base, &c->zero_bytes);
+    c->E.half16 = c->half16;
     // bin counts start at zero (each sort leaves them at zero again)
     HIPCHK(c, hipDeviceSynchronize());
     HIPCHK(c, launch_zero(c->E, c->zero_base, c->zero_bytes, nullptr));
@@ -713,6 +734,11 @@ int lst_load_pixel(lst_ctx *c, int32_t n_events, const int32_t *px_offsets, cons
     P.x5z = (float)pp[LST_PX_X5Z];
     P.x3p = (float)pp[LST_PX_X3P];
     P.x3z = (float)pp[LST_PX_X3Z];
+    // the window holds |dphi| <= asin(sqrt(wl2)) (same hemisphere); 1e-3 rad
+    // covers the rounding of the directions' azimuths
+    P.wphi = P.wl2 >= 1.0f ? 4.0f : (float)(std::asin(std::sqrt((double)P.wl2)) + 1e-3);
+    // closeness holds sin^2(dphi) <= dr2 (same hemisphere)
+    P.wdr = P.dr2 >= 1.0f ? 4.0f : (float)(std::asin(std::sqrt((double)P.dr2)) + 1e-3);
     c->px_loaded = true;
     c->counts_valid = false;
     return LST_OK;
@@ -754,6 +780,19 @@ static int enqueue_cap(lst_ctx *c, int type, hipStream_t s)
     return LST_OK;
 }
 
+int lst_set_hit_storage(lst_ctx *c, int32_t fp16)
+{
+    if (!c) return LST_E_INVALID;
+    if (fp16 != 0 && fp16 != 1) return fail(c, LST_E_INVALID, "hit storage %d (0 FP32, 1 FP16)", fp16);
+    c->half16 = fp16;
+    c->E.half16 = fp16;
+    drop_graph(c);
+    // hits grouped in the other storage are not readable: group them again
+    if (c->stage > 1) c->stage = 1;
+    c->counts_valid = false;
+    return LST_OK;
+}
+
 int lst_set_capacities(lst_ctx *c, const int32_t *caps4)
 {
     if (!c) return LST_E_INVALID;
@@ -766,10 +805,18 @@ int lst_set_capacities(lst_ctx *c, const int32_t *caps4)
     return LST_OK;
 }
 
+// scorer mode with no usable network: the batch runs the plain cut chain
+// and its counts say so
+static void note_fallback(lst_ctx *c)
+{
+    c->fallback = c->mode == LST_MODE_MLP && !c->mlp_dev[0] && !c->mlp_dev[1];
+}
+
 int lst_run_sort(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 1, "lst_run_sort");
     if (rc) return rc;
+    note_fallback(c);
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(c, launch_sort(c->E, c->M, c->tune.grid[ST_SORT], sort_per_event(c), s));
     c->stage = 2;
@@ -847,8 +894,6 @@ int lst_set_mode(lst_ctx *c, int32_t mode)
 {
     if (!c) return LST_E_INVALID;
     if (mode != LST_MODE_CUTS && mode != LST_MODE_MLP) return fail(c, LST_E_INVALID, "mode %d", mode);
-    if (mode == LST_MODE_MLP && !c->mlp_dev[0] && !c->mlp_dev[1])
-        return fail(c, LST_E_STATE, "scorer mode needs weights (lst_mlp_load)");
     if (mode != c->mode) drop_graph(c);
     c->mode = mode;
     return LST_OK;
@@ -860,16 +905,28 @@ int lst_mlp_load(lst_ctx *c, int32_t kind, const float *params, int32_t n_params
     if (!c) return LST_E_INVALID;
     const int sl = mlp_slot(kind);
     if (sl < 0) return fail(c, LST_E_INVALID, "scorer kind %d (LST_T3 or LST_T5)", kind);
+    HIPCHK(c, hipSetDevice(c->device));
+    // rejected weights also unload the kind's earlier network: that stage
+    // then runs its plain cuts
+    auto reject = [&](const char *what, int i) {
+        char msg[96];
+        std::snprintf(msg, sizeof msg, what, i);
+        if (c->mlp_dev[sl]) {
+            drop_graph(c);
+            (void)hipDeviceSynchronize();
+            (void)hipFree(c->mlp_dev[sl]);
+            c->mlp_dev[sl] = nullptr;
+        }
+        return fail(c, LST_E_INVALID, "%s", msg);
+    };
     if (!params || !mean || !istd || n_params != MLP_NPARAM)
-        return fail(c, LST_E_INVALID, "scorer weights: %d parameters, %d expected", n_params,
-                    MLP_NPARAM);
+        return reject("scorer weights: %d parameters expected", MLP_NPARAM);
     for (int i = 0; i < MLP_NPARAM; ++i)
-        if (!std::isfinite(params[i])) return fail(c, LST_E_INVALID, "scorer parameter %d not finite", i);
+        if (!std::isfinite(params[i])) return reject("scorer parameter %d not finite", i);
     for (int i = 0; i < MLP_NIN; ++i)
         if (!std::isfinite(mean[i]) || !std::isfinite(istd[i]))
-            return fail(c, LST_E_INVALID, "standardisation of feature %d not finite", i);
-    if (!std::isfinite(threshold)) return fail(c, LST_E_INVALID, "threshold not finite");
-    HIPCHK(c, hipSetDevice(c->device));
+            return reject("standardisation of feature %d not finite", i);
+    if (!std::isfinite(threshold)) return reject("threshold not finite (kind slot %d)", sl);
     const size_t n = MLP_NPARAM + 2 * MLP_NIN;
     const bool fresh = !c->mlp_dev[sl];
     if (fresh) HIPCHK(c, hipMalloc((void **)&c->mlp_dev[sl], sizeof(float) * n));
@@ -1108,6 +1165,7 @@ int lst_run_chain_persistent(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 1, "lst_run_chain_persistent");
     if (rc) return rc;
+    note_fallback(c);
     if (capped(c))
         return fail(c, LST_E_STATE, "per-module capacities run with the per-stage chain only");
     const int bpc =
@@ -1186,6 +1244,7 @@ int lst_run_chain_graph(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 1, "lst_run_chain_graph");
     if (rc) return rc;
+    note_fallback(c);
     if (!c->graph) {
         if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
         HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
@@ -1287,6 +1346,7 @@ static int compute_counts(lst_ctx *c)
         c->counts[e].n_hits = c->hit_off[e + 1] - c->hit_off[e];
         c->counts[e].overflow_mask = (int32_t)S.gc[GC_OVERFLOW];
         c->counts[e].error_flags = (int32_t)S.gc[GC_ERROR];
+        c->counts[e].mlp_fallback = c->fallback ? 1 : 0;
     }
     if (capped(c) && c->stage >= 3) {
         std::vector<uint32_t> nd;

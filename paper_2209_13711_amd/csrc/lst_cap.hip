@@ -37,8 +37,8 @@ __device__ __forceinline__ uint32_t cap_wave_sum(uint32_t v)
 // an MD's (lower, upper) per-event hit indices as one lexicographic key
 __device__ __forceinline__ uint64_t md_key(const EvDev &E, int32_t m)
 {
-    const uint32_t lo = (uint32_t)__float_as_int(E.hsort[E.md_hlo[m]].w);
-    const uint32_t up = (uint32_t)__float_as_int(E.hsort[E.md_hup[m]].w);
+    const uint32_t lo = (uint32_t)hit_orig(E, E.md_hlo[m]);
+    const uint32_t up = (uint32_t)hit_orig(E, E.md_hup[m]);
     return ((uint64_t)lo << 32) | up;
 }
 

@@ -41,7 +41,36 @@ __device__ __forceinline__ float arc(float c, float k)
 struct ModF {
     float cx, cy, cz, ux, uy, uz, vx, vy, vz, g, rl;
     int barrel, is2s;
+    float wx, wy, wz;   // sensor normal (half-precision hit storage)
 };
+
+// Half-precision hit storage (the paper's outlook, Sec. 4): a hit is kept as
+// its in-plane coordinates in its module's frame, relative to the module
+// centre, each rounded to binary16 (nearest even), with its per-event index;
+// the stages see the FP32 position rebuilt from them.  Fixed FP32 order.
+__device__ __forceinline__ uint2 half_hit(const ModF &m, float x, float y, float z, int32_t idx)
+{
+    float dx = x - m.cx, dy = y - m.cy, dz = z - m.cz;
+    float u = ((dx * m.ux) + (dy * m.uy)) + (dz * m.uz);
+    float v = ((dx * m.vx) + (dy * m.vy)) + (dz * m.vz);
+    const uint32_t hu = __builtin_bit_cast(uint16_t, (_Float16)u);
+    const uint32_t hv = __builtin_bit_cast(uint16_t, (_Float16)v);
+    return make_uint2(hu | (hv << 16), (uint32_t)idx);
+}
+
+// the FP32 position of grouped hit h on sensor `sensor` of module m (and its
+// per-event index in w), from either storage
+__device__ __forceinline__ float4 stored_hit(const EvDev &E, const ModF &m, uint32_t h, int sensor)
+{
+    if (!E.half16) return E.hsort[h];
+    const uint2 r = E.hsort_h[h];
+    const float u = (float)__builtin_bit_cast(_Float16, (uint16_t)(r.x & 0xffffu));
+    const float v = (float)__builtin_bit_cast(_Float16, (uint16_t)(r.x >> 16));
+    const float w = (sensor ? 0.5f : -0.5f) * m.g;
+    return make_float4(((m.cx + (u * m.ux)) + (v * m.vx)) + (w * m.wx),
+                       ((m.cy + (u * m.uy)) + (v * m.vy)) + (w * m.wy),
+                       ((m.cz + (u * m.uz)) + (v * m.vz)) + (w * m.wz), __int_as_float((int32_t)r.y));
+}
 
 struct MdOut {
     float r, a, ca, bend, sv;

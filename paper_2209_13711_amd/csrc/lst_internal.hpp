@@ -39,6 +39,7 @@ enum GlobalCounter {
     GC_DROP,           // [OT_COUNT] objects removed by per-module capacities
     GC_PX5 = GC_DROP + OT_COUNT,   // pT5 link candidates
     GC_PX3,            // pT3 link candidates
+    GC_PXFREE,         // seeds that no kept pT5 uses (sd_free)
     GC_SH = GC_PAD     // [OT_COUNT][NSH] reservation shards, one line each
 };
 __host__ __device__ constexpr int gc_shard(int type, int s) { return GC_SH + (type * NSH + s) * GC_PAD; }
@@ -53,7 +54,7 @@ constexpr int GC_COUNT = GC_SH + OT_COUNT * NSH * GC_PAD;
 constexpr int NXCD = 8;
 
 struct ModDev {
-    const float *cx, *cy, *cz, *ux, *uy, *uz, *vx, *vy, *vz, *g, *rl;
+    const float *cx, *cy, *cz, *ux, *uy, *uz, *vx, *vy, *vz, *g, *rl, *wx, *wy, *wz;
     const int32_t *barrel;   // 1 barrel, 0 endcap
     const int32_t *is2s;     // 1 for 2S modules
     const int32_t *map_ptr;  // [n_mod + 1]
@@ -78,10 +79,15 @@ struct EvDev {
     uint8_t *sensor;
     int32_t *hit_off;        // [n_ev + 1]
     // grouping of hits by key = 2 * slot + sensor
-    uint32_t *bcnt;          // [n_keys]     (zeroed at chain start)
+    uint32_t *bcnt;          // [n_keys]     (zero between chains: the scan clears what it reads)
+    uint32_t *hrank;         // [cap_hits]   each input hit's rank in its bin (histogram atomics)
     uint32_t *boff;          // [n_keys + 1]
     unsigned long long *scan_st;  // look-back scan: status per tile (zeroed at chain start)
     float4 *hsort;            // sorted hits: x, y, z and (int bits) the hit's per-event index
+    // half-precision storage (half16 != 0): the sorted hits as module-local
+    // (u, v) in binary16 (x: u | v << 16) and the per-event index (y)
+    uint2 *hsort_h;
+    int32_t half16;
     uint32_t *hmin;          // dedup: smallest quintuplet score bits per sorted hit
     int32_t *htie;           // dedup: how many quintuplets reach that score
     int32_t *hslot;          // dedup: [n_hits][TIE_SLOTS] quintuplets reaching it
@@ -135,17 +141,21 @@ struct EvDev {
     uint8_t *sd_used, *sd_keep;      // [cap_seeds] linked by a kept pT5/pT3; a track candidate
     float4 *t5_dir, *t3_dir;         // [span] directions of kept quintuplets, of triplets
     uint8_t *t5_clean;               // [span] kept quintuplet left after cross-cleaning
-    // per-event lists (PXL_*): counts, offsets, fill counters, entries
-    int32_t *pl_cnt, *pl_off, *pl_fill;  // [PXL_COUNT][cap_ev (+1)]
+    // per-event lists (PXL_*), the kept quintuplets and the triplets also per
+    // azimuth bin: counts, offsets, fill counters ([PXL_COUNT][cap_ev x PX_NB
+    // + 1] each; a list's key is ev x PX_NB + bin, or ev), entries
+    int32_t *pl_cnt, *pl_off, *pl_fill;
     int32_t *pl_k5, *pl_k3;          // kept quintuplets, triplets
+    float4 *pl_k5d, *pl_k3d;         // their directions, in list order
     float4 *pl_d5, *pl_d3, *pl_dt;   // directions of kept pT5, cleaned pT3, cleaned T5
     // link candidates of pT5 (c5) and pT3 (c3): seed, object, score, kept
     int32_t *c5_seed, *c5_obj, *c3_seed, *c3_obj;   // [cap_pxc]
     float *c5_score, *c3_score;
     uint8_t *c5_keep, *c3_keep;
+    int2 *sd_c5, *sd_c3;             // [cap_seeds] first candidate and count of each seed
+    int32_t *sd_free;                // [cap_seeds] seeds that no kept pT5 uses
     unsigned long long *hmin_o;      // [cap_hits] smallest key per grouped outer hit
     unsigned long long *hmin_p;      // [cap_px]   smallest key per pixel hit
-    uint32_t *htie_p;                // [cap_px]   candidates reaching it on their first pixel hit
     uint8_t *hflag_o, *hflag_p;      // hits held by track candidates so far
     // counters (zeroed at chain start)
     uint32_t *gc;                    // [GC_COUNT]
@@ -180,8 +190,11 @@ hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, int grid,
 hipError_t launch_dedup(const EvDev &E, const ModDev &M, int grid, hipStream_t s);
 // pixel objects (lst_pixel.hip)
 enum { PXL_K5 = 0, PXL_K3, PXL_D5, PXL_D3, PXL_DT, PXL_COUNT };
+constexpr int PX_NB = 64;   // azimuth bins of the per-event object lists
 struct PixConsts {
     float sig2p, sigz, wl2, dr2, x5p, x5z, x3p, x3z;
+    float wphi;   // azimuth half-range of the link window plus a margin (>= pi: all bins)
+    float wdr;    // the same for the cross-cleaning closeness
 };
 hipError_t launch_pixel(const EvDev &E, const Consts &K, const PixConsts &P, hipStream_t s);
 // per-module capacity `cap` of object type `type` (lst_cap.hip): objects of

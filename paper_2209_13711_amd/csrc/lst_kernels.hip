@@ -269,10 +269,11 @@ __device__ __forceinline__ int hit_key(const EvDev &E, int n_mod, int n_ev, int3
     return 2 * (ev * n_mod + m) + s;
 }
 
-// Bin counts per key.  The bins are zero on entry: the arena is cleared when
-// it is attached and every scatter takes each count back down to zero.  The
-// same launch clears the chain's counters and the scan's tile status, which
-// only later kernels use.
+// Bin counts per key, and each hit's rank in its bin (the value its atomic
+// returned), so that the scatter needs no atomics.  The bins are zero on
+// entry: the arena is cleared when it is attached and every scan clears the
+// counts it reads.  The same launch clears the chain's counters and the
+// scan's tile status, which only later kernels use.
 __device__ __forceinline__ void hist_body(const EvDev &E, int n_mod)
 {
     const int n_ev = E.desc[D_NEV], n_hits = E.desc[D_NHITS];
@@ -283,7 +284,7 @@ __device__ __forceinline__ void hist_body(const EvDev &E, int n_mod)
     for (int32_t h = t0; h < n_hits; h += stride) {
         int ev;
         const int key = hit_key(E, n_mod, n_ev, h, ev);
-        if (key >= 0) atomicAdd(&E.bcnt[key], 1u);
+        if (key >= 0) E.hrank[h] = atomicAdd(&E.bcnt[key], 1u);
     }
 }
 
@@ -328,7 +329,7 @@ __device__ __forceinline__ void scan_body(const EvDev &E)
         const int base = tile * SCAN_TILE + threadIdx.x * ITEMS;
         uint32_t v[ITEMS], sum = 0;
         if (base + ITEMS <= n) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(E.bcnt + base);
+            uint4 *src = reinterpret_cast<uint4 *>(E.bcnt + base);
 #pragma unroll
             for (int k = 0; k < ITEMS / 4; ++k) {
                 const uint4 q = src[k];
@@ -336,10 +337,14 @@ __device__ __forceinline__ void scan_body(const EvDev &E)
                 v[4 * k + 1] = q.y;
                 v[4 * k + 2] = q.z;
                 v[4 * k + 3] = q.w;
+                src[k] = make_uint4(0u, 0u, 0u, 0u);   // bins end at zero
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < ITEMS; ++k) v[k] = (base + k < n) ? E.bcnt[base + k] : 0u;
+            for (int k = 0; k < ITEMS; ++k) {
+                v[k] = (base + k < n) ? E.bcnt[base + k] : 0u;
+                if (base + k < n) E.bcnt[base + k] = 0u;
+            }
         }
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) sum += v[k];
@@ -392,8 +397,22 @@ __device__ __forceinline__ void scan_body(const EvDev &E)
     }
 }
 
-__device__ __forceinline__ void scatter_body(const EvDev &E, int n_mod)
+// module frame of module m (half-precision hit storage)
+__device__ __forceinline__ ModF mod_frame(const ModDev &M, int m)
 {
+    ModF f;
+    f.cx = M.cx[m]; f.cy = M.cy[m]; f.cz = M.cz[m];
+    f.ux = M.ux[m]; f.uy = M.uy[m]; f.uz = M.uz[m];
+    f.vx = M.vx[m]; f.vy = M.vy[m]; f.vz = M.vz[m];
+    f.wx = M.wx[m]; f.wy = M.wy[m]; f.wz = M.wz[m];
+    f.g = M.g[m]; f.rl = M.rl[m];
+    f.barrel = M.barrel[m]; f.is2s = M.is2s[m];
+    return f;
+}
+
+__device__ __forceinline__ void scatter_body(const EvDev &E, const ModDev &M)
+{
+    const int n_mod = M.n_mod;
     const int n_ev = E.desc[D_NEV], n_hits = E.desc[D_NHITS];
     for (int32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < n_hits;
          h += gridDim.x * blockDim.x) {
@@ -403,16 +422,24 @@ __device__ __forceinline__ void scatter_body(const EvDev &E, int n_mod)
             atomicOr(&E.gc[GC_ERROR], 1u);
             continue;
         }
-        // positions are taken from the top of the bin down; bcnt ends at zero
-        const uint32_t pos = E.boff[key] + atomicSub(&E.bcnt[key], 1u) - 1u;
-        // one 16-byte store per hit (scattered 4-byte stores cost a line each)
-        E.hsort[pos] = make_float4(E.x[h], E.y[h], E.z[h], __int_as_float(h - E.hit_off[ev]));
+        const uint32_t pos = E.boff[key] + E.hrank[h];
+        if (pos >= (uint32_t)E.cap_hits) {   // inconsistent grouping: never written
+            atomicOr(&E.gc[GC_ERROR], 4u);
+            continue;
+        }
+        // one 16-byte store per hit (scattered 4-byte stores cost a line each),
+        // or one 8-byte record in half-precision storage
+        if (E.half16)
+            E.hsort_h[pos] = half_hit(mod_frame(M, E.module[h]), E.x[h], E.y[h], E.z[h], h - E.hit_off[ev]);
+        else
+            E.hsort[pos] = make_float4(E.x[h], E.y[h], E.z[h], __int_as_float(h - E.hit_off[ev]));
     }
 }
 
 __global__ void k_hist(EvDev E, int n_mod) { hist_body(E, n_mod); }
+
 __global__ __launch_bounds__(BLOCK) void k_scan(EvDev E) { scan_body(E); }
-__global__ void k_scatter(EvDev E, int n_mod) { scatter_body(E, n_mod); }
+__global__ void k_scatter(EvDev E, ModDev M) { scatter_body(E, M); }
 
 // Batches: each event's 2 x n_mod bins are split in SORT_EV_PARTS ranges of
 // consecutive keys; one block per (event, range) keeps its bins in LDS and
@@ -464,8 +491,9 @@ __global__ __launch_bounds__(SORT_EV_BLOCK) void k_hist_ev(EvDev E, int n_mod)
     }
 }
 
-__global__ __launch_bounds__(SORT_EV_BLOCK) void k_scatter_ev(EvDev E, int n_mod)
+__global__ __launch_bounds__(SORT_EV_BLOCK) void k_scatter_ev(EvDev E, ModDev M)
 {
+    const int n_mod = M.n_mod;
     extern __shared__ uint32_t s_cur[];     // next free slot of each bin of the range
     const int n_ev = E.desc[D_NEV], nk = 2 * n_mod, kp = sort_ev_span(nk);
     for (int item = blockIdx.x; item < n_ev * SORT_EV_PARTS; item += gridDim.x) {
@@ -502,7 +530,11 @@ __global__ __launch_bounds__(SORT_EV_BLOCK) void k_scatter_ev(EvDev E, int n_mod
             for (int u = 0; u < SORT_EV_ILP; ++u) {
                 if (key[u] >= k0 && key[u] < k1) {
                     const uint32_t pos = atomicAdd(&s_cur[key[u] - k0], 1u);
-                    E.hsort[pos] = v[u];
+                    if (E.half16)
+                        E.hsort_h[pos] = half_hit(mod_frame(M, key[u] >> 1), v[u].x, v[u].y, v[u].z,
+                                                  __float_as_int(v[u].w));
+                    else
+                        E.hsort[pos] = v[u];
                 }
             }
         }
@@ -538,12 +570,12 @@ hipError_t launch_sort(const EvDev &E, const ModDev &M, int grid, bool per_event
         const size_t lds = sort_ev_lds_bytes(M.n_mod);
         hipLaunchKernelGGL(k_hist_ev, dim3(eg), dim3(SORT_EV_BLOCK), lds, s, E, M.n_mod);
         hipLaunchKernelGGL(k_scan, dim3(nb < 1024 ? nb : 1024), dim3(BLOCK), 0, s, E);
-        hipLaunchKernelGGL(k_scatter_ev, dim3(eg), dim3(SORT_EV_BLOCK), lds, s, E, M.n_mod);
+        hipLaunchKernelGGL(k_scatter_ev, dim3(eg), dim3(SORT_EV_BLOCK), lds, s, E, M);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_hist, dim3(grid), dim3(BLOCK), 0, s, E, M.n_mod);
     hipLaunchKernelGGL(k_scan, dim3(nb < 1024 ? nb : 1024), dim3(BLOCK), 0, s, E);
-    hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(BLOCK), 0, s, E, M.n_mod);
+    hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(BLOCK), 0, s, E, M);
     return hipGetLastError();
 }
 
@@ -565,6 +597,7 @@ struct SegQ {
 // the output offset is known
 struct ModL {
     float4 c, u, v;                   // (cx, cy, cz, g), (ux, uy, uz, rl), (vx, vy, vz, flags)
+    float4 w;                         // (wx, wy, wz, -): sensor normal
 };
 struct SmMD {
     uint32_t lo[WAVES][STAGE], up[WAVES][STAGE];
@@ -619,7 +652,7 @@ __device__ __forceinline__ void write_md(const EvDev &E, const Consts &K, uint32
                                          uint32_t hl, uint32_t hu, const MdOut &o,
                                          const ModF &mod, const int4 &nbr)
 {
-    const float4 L = E.hsort[hl], U = E.hsort[hu];
+    const float4 L = stored_hit(E, mod, hl, 0), U = stored_hit(E, mod, hu, 1);
     const float xL = L.x, yL = L.y;
     E.md_hlo[i] = (int32_t)hl;
     E.md_hup[i] = (int32_t)hu;
@@ -645,6 +678,7 @@ __device__ __forceinline__ ModF mod_from(const ModL &r)
     const int fl = __float_as_int(r.v.w);
     f.barrel = fl & 1;
     f.is2s = fl >> 1;
+    f.wx = r.w.x; f.wy = r.w.y; f.wz = r.w.z;
     return f;
 }
 
@@ -688,8 +722,9 @@ __device__ __forceinline__ uint32_t enum_md(const EvDev &E, const Consts &K, con
             const uint32_t il = p / nup, iu = p - il * nup;
             hl = (uint32_t)sl.y + il;
             hu = (uint32_t)sl.z + iu;
-            const float4 L = E.hsort[hl], U = E.hsort[hu];
-            ok = md_accept(K, mod_from(sm.mod[w][g]), L.x, L.y, L.z, U.x, U.y, U.z, o);
+            const ModF mf = mod_from(sm.mod[w][g]);
+            const float4 L = stored_hit(E, mf, hl, 0), U = stored_hit(E, mf, hu, 1);
+            ok = md_accept(K, mf, L.x, L.y, L.z, U.x, U.y, U.z, o);
         }
         const unsigned long long m = __ballot(ok);
         sink(ok, g, hl, hu, o, acc + (uint32_t)__popcll(m & below));
@@ -739,6 +774,7 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
                     r.u = make_float4(M.ux[m], M.uy[m], M.uz[m], M.rl[m]);
                     r.v = make_float4(M.vx[m], M.vy[m], M.vz[m],
                                       __int_as_float(M.barrel[m] | (M.is2s[m] << 1)));
+                    r.w = make_float4(M.wx[m], M.wy[m], M.wz[m], 0.0f);
                     sm.mod[w][gp.g] = r;
                 }
             }
@@ -774,7 +810,7 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
         for (uint32_t q = l; q < tot && q < (uint32_t)STAGE; q += 64) {
             const int g = sm.g[w][q];
             const uint32_t hl = sm.lo[w][q];
-            const float4 L = E.hsort[hl];
+            const float4 L = stored_hit(E, mod_from(sm.mod[w][g]), hl, 0);
             MdOut o;
             md_anchor(K, L.x, L.y, o);
             o.bend = sm.bend[w][q];
@@ -1376,7 +1412,7 @@ __device__ __forceinline__ void dedup_min_body(const EvDev &E, uint32_t *s_pre)
         const int j = (int)(v % 10u);
         const int32_t h = t5_hit(E, t, j);
         E.t5_hs[(size_t)t * 10 + j] = h;
-        E.t5_ho[(size_t)t * 10 + j] = __float_as_int(E.hsort[h].w);
+        E.t5_ho[(size_t)t * 10 + j] = hit_orig(E, h);
         if (E.t5_veto[t]) continue;
         atomicMin(&E.hmin[h], __float_as_uint(E.t5_score[t]));
     }
@@ -1648,7 +1684,7 @@ __global__ __launch_bounds__(BLOCK) void k_chain(EvDev E, ModDev M, Consts K, ui
     LST_SYNC();
     scan_body(E);
     LST_SYNC();
-    scatter_body(E, M.n_mod);
+    scatter_body(E, M);
     LST_SYNC();
     md_body<G>(E, M, K, sm.u.md);
     LST_SYNC();

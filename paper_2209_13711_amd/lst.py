@@ -43,7 +43,8 @@ class lst_counts(ctypes.Structure):
                [("overflow_mask", ctypes.c_int32), ("error_flags", ctypes.c_int32),
                 ("dropped", ctypes.c_int64 * 4)] + \
                [(n, ctypes.c_int64) for n in ("n_pls", "cand_pt5", "n_pt5", "cand_pt3", "n_pt3",
-                                               "n_tc")]
+                                               "n_tc")] + \
+               [("mlp_fallback", ctypes.c_int32)]
 
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_}
@@ -81,6 +82,7 @@ _SIGS = {
     "lst_get_counts": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(lst_counts), _P]),
     "lst_raise_error_flags": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "lst_set_capacities": (ctypes.c_int, [_P, _P]),
+    "lst_set_hit_storage": (ctypes.c_int, [_P, ctypes.c_int32]),
     "lst_load_pixel": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P,
                                       ctypes.c_int32, _P]),
     "lst_run_pixel": (ctypes.c_int, [_P, _P]),
@@ -345,6 +347,10 @@ class Context:
         d["rc"] = rc
         return d
 
+    def set_hit_storage(self, fp16: bool):
+        """hits grouped as module-local FP16 (u, v) (lst_set_hit_storage)"""
+        self._check(self.lib.lst_set_hit_storage(self.h, int(bool(fp16))))
+
     def set_capacities(self, caps=None):
         """per-module capacities of MD, SEG, T3, T5 (0 = none; None = off)"""
         if caps is None:
@@ -419,36 +425,46 @@ class Context:
         """test hook: OR error bits 1/2 into the device error word (lst_raise_error_flags)"""
         self._check(self.lib.lst_raise_error_flags(self.h, int(bits), self._stream(stream)))
 
-    def objects(self, event, kind, stream=None) -> np.ndarray:
+    def _hint(self, kind):
+        """rows an output of `kind` can hold at most: the arena's capacity"""
+        key = {LST_MD: "md", LST_SEG: "seg", LST_T3: "t3", LST_T5: "t5", LST_T5_KEPT: "t5"}[kind]
+        return int(self.caps.get(key, 0)) if self.caps else 0
+
+    def _fetch(self, call, shape, dtype, hint):
+        """One getter call into a buffer of `hint` rows (the getters copy the
+        device arrays on every call); a second call only when they do not
+        fit.  `call(out_ptr, cap, n)` returns the status."""
         n = ctypes.c_int64(0)
-        rc = self.lib.lst_get_objects(self.h, event, kind, None, 0, ctypes.byref(n), self._stream(stream))
-        if rc not in (LST_OK, LST_E_CAPACITY):
-            self._check(rc)
-        out = np.zeros((max(n.value, 1), WIDTH[kind]), np.int32)
-        self._check(self.lib.lst_get_objects(self.h, event, kind, _np_ptr(out), n.value,
-                                             ctypes.byref(n), self._stream(stream)))
+        out = np.empty((max(hint, 1),) + shape, dtype)
+        rc = call(_np_ptr(out), hint, n)
+        if rc == LST_E_CAPACITY and n.value > hint:
+            out = np.empty((n.value,) + shape, dtype)
+            rc = call(_np_ptr(out), n.value, n)
+        self._check(rc)
         return out[:n.value]
+
+    def objects(self, event, kind, stream=None) -> np.ndarray:
+        st = self._stream(stream)
+        return self._fetch(lambda o, cap, n: self.lib.lst_get_objects(
+            self.h, event, kind, o, cap, ctypes.byref(n), st), (WIDTH[kind],), np.int32,
+            self._hint(kind))
 
     def run_t5_features(self, stream=None):
         self._check(self.lib.lst_run_t5_features(self.h, self._stream(stream)))
 
-    def _features(self, fn, event, stream):
-        n = ctypes.c_int64(0)
-        rc = fn(self.h, event, None, 0, ctypes.byref(n), self._stream(stream))
-        if rc not in (LST_OK, LST_E_CAPACITY):
-            self._check(rc)
-        out = np.zeros((max(n.value, 1), 40), np.float32)
-        self._check(fn(self.h, event, _np_ptr(out), n.value, ctypes.byref(n), self._stream(stream)))
-        return out[:n.value]
+    def _features(self, fn, event, stream, kind):
+        st = self._stream(stream)
+        return self._fetch(lambda o, cap, n: fn(self.h, event, o, cap, ctypes.byref(n), st),
+                           (40,), np.float32, self._hint(kind))
 
     def t5_features(self, event, stream=None) -> np.ndarray:
-        return self._features(self.lib.lst_get_t5_features, event, stream)
+        return self._features(self.lib.lst_get_t5_features, event, stream, LST_T5)
 
     def run_t3_features(self, stream=None):
         self._check(self.lib.lst_run_t3_features(self.h, self._stream(stream)))
 
     def t3_features(self, event, stream=None) -> np.ndarray:
-        return self._features(self.lib.lst_get_t3_features, event, stream)
+        return self._features(self.lib.lst_get_t3_features, event, stream, LST_T3)
 
     def t5_scores(self, event, stream=None) -> np.ndarray:
         n = ctypes.c_int64(0)

@@ -298,21 +298,42 @@ def test_scored_chain_stagewise_graph_and_persistent():
     assert kept == {tuple(t) for t in ref.tuples[oracle.T5_KEPT].tolist()}
 
 
-def test_scorer_state_errors(ctx_toy):
+def test_scorer_fallback_and_state_errors(ctx_toy):
+    """scorer mode with no usable network runs the plain cut chain and says
+    so in the counts; weights that are not finite are refused and unload the
+    kind's earlier network"""
     lst = _lst()
     geo = G.get("barrel_toy")
-    ctx = lst.Context(PR.make(), geo.f32, geo.i32, device=0)
-    with pytest.raises(lst.LSTError) as e:
-        ctx.set_mode(lst.LST_MODE_MLP)
-    assert e.value.code == lst.lst.LST_E_STATE
+    params = PR.make()
+    ev = E.generate(1, 0)
+    plain = oracle.Oracle(params, geo.f32, geo.i32).run_event(ev)
+    kept_ref = {tuple(t) for t in plain.tuples[oracle.T5_KEPT].tolist()}
+    offs = np.array([0, ev.n_hits], np.int32)
+    ctx = lst.Context(params, geo.f32, geo.i32, device=0)
+
+    def run_all(expect_fallback, expect_plain):
+        for chain in (ctx.run_chain, ctx.run_chain_graph, ctx.run_chain_persistent):
+            ctx.load_hits(offs, ev.x, ev.y, ev.z, ev.module, ev.sensor)
+            chain()
+            assert ctx.counts(0)["mlp_fallback"] == expect_fallback
+            kept = {tuple(t) for t in ctx.objects(0, lst.LST_T5_KEPT).tolist()}
+            assert (kept == kept_ref) == expect_plain
+
+    ctx.set_mode(lst.LST_MODE_MLP)           # nothing loaded
+    run_all(1, True)
     P = W.random_params(np.random.default_rng(0))
+    ctx.mlp_load(P, np.zeros(40), np.ones(40), 1e30)   # vetoes every quintuplet
+    run_all(0, False)
+    assert ctx.counts(0)["n_t5_kept"] == 0
     bad = P.copy()
     bad[5] = np.nan
     with pytest.raises(lst.LSTError) as e:
         ctx.mlp_load(bad, np.zeros(40), np.ones(40), 0.0)
     assert e.value.code == lst.lst.LST_E_INVALID
+    run_all(1, True)                         # the earlier network is gone
+    ctx.set_mode(lst.LST_MODE_CUTS)
+    run_all(0, True)
     ctx.mlp_load(P, np.zeros(40), np.ones(40), 0.0)
-    ev = E.generate(1, 0)
     ctx.run_event(ev)
     with pytest.raises(lst.LSTError) as e:   # after dedup: out of order
         ctx.run_t5_score()

@@ -123,3 +123,32 @@ def test_pixel_stage_state_and_input_errors():
         ctx.load_pixel(one, px.x, px.y, px.z, sone, px.seeds, PP)
         ctx.run_pixel()
     assert ei.value.code == lst.LST_E_STATE
+
+
+def test_pixel_stage_full_size_batch_of_16_pu200():
+    """16 PU200-like events (the full-size batch) with their pixel seeds in
+    one launch, every event against the oracle"""
+    import paper_2209_13711_amd as lst
+    geo = G.get("full")
+    params = PR.make()
+    evs = [E.generate(2, 100 + e) for e in range(16)]
+    pxs = [E.pixel_seeds(ev, 2, 100 + e) for e, ev in enumerate(evs)]
+    b = E.concat(evs)
+    poff = np.r_[0, np.cumsum([p.n_hits for p in pxs])].astype(np.int32)
+    soff = np.r_[0, np.cumsum([p.n_seeds for p in pxs])].astype(np.int32)
+    cat = lambda a: np.concatenate([getattr(p, a) for p in pxs])
+    print(f"case pixel full-size batch: 16 events, {soff[-1]} seeds", flush=True)
+    ctx = lst.Context(params, geo.f32, geo.i32, device=0)
+    ctx.reserve(lst.default_caps(16, int(b.offsets[-1])))
+    ctx.pixel_caps(int(poff[-1]), int(soff[-1]))
+    ctx.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+    ctx.tune(reps=1)
+    ctx.load_hits(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+    ctx.run_chain_graph()
+    ctx.load_pixel(poff, cat("x"), cat("y"), cat("z"), soff, np.concatenate([p.seeds for p in pxs]), PP)
+    ctx.run_pixel()
+    orc = oracle.Oracle(params, geo.f32, geo.i32)
+    for e, (ev, px) in enumerate(zip(evs, pxs)):
+        orc.run_event(ev)
+        _compare(ctx, e, orc.run_pixel(PP, px))
+        assert ctx.counts(e)["error_flags"] == 0
