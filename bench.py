@@ -58,6 +58,11 @@ def measured_traffic(kernel):
     return float(kv[key])
 
 
+def step_done(name, t0):
+    """one line on stderr per finished leg (the JSON line stays alone on stdout)"""
+    print(f"bench: {name} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+
+
 def assert_clean(ctx, n_events=None):
     """After a timed leg: every event's counts come back without an error
     (a time-out of a kernel-side wait raises LST_E_FAULT from the getter) and
@@ -907,28 +912,39 @@ def main():
                      "copy_GBps_measured": copy_gbs,
                      "frac_vs_copy": achieved / copy_gbs},
     }
+    t0 = time.perf_counter()
+    step_done("headline", t0)
     if not args.no_concurrent:
         out["pu200_concurrent"] = pu200_concurrent(lst, torch, E, G, PR, pre["pu200"])
+        step_done("pu200_concurrent", t0)
         out["memory"] = memory(lst, torch, G, PR, pre["pu200"])
+        step_done("memory", t0)
         out["pixel"] = pixel_leg(lst, torch, E, G, PR, pre["pu200"])
+        step_done("pixel", t0)
         out["half_storage"] = half_storage(lst, torch, E, G, PR, pre["pu200"])
+        step_done("half_storage", t0)
     if not args.no_batch:
         out["batched"] = batched(lst, torch, E, G, PR, pre["batch"], cache=args.tune_cache)
         out["batched"]["multistream_8"] = multistream(lst, torch, G, PR, pre["batch"])
-    model = None
+        step_done("batched", t0)
     model = model_stress = None
     if not args.no_scorer:
         out["scored"], model = scored(lst, torch, pre["train"], pre["eval"])
+        step_done("scored", t0)
         out["scored_full_geometry"], _ = scored(lst, torch, pre["train_full"], pre["eval_full"],
                                                 base_cfg=2)
+        step_done("scored_full_geometry", t0)
         if not args.no_stress:
             out["scored_stress"], model_stress = scored(lst, torch, pre["train_stress"],
                                                         pre["stress"], base_cfg=5)
+            step_done("scored_stress", t0)
     if not args.no_stress:
         out["stress"] = stress(lst, torch, E, G, PR, pre["stress"], model_stress, model)
+        step_done("stress", t0)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(params, geo)
         out["cpu_baseline_all_cores"] = cpu_all
+        step_done("cpu_baseline", t0)
     print(json.dumps(out), flush=True)
 
 

@@ -92,6 +92,16 @@ __device__ __forceinline__ void load_weights(const float *P, MlpW &w)
     if (threadIdx.x == 0) w.b3 = P[OFF_B3];
 }
 
+// orders a wave's LDS writes before later LDS reads by other lanes of the
+// same wave (a wave's LDS operations complete in issue order): the operand
+// and hidden tiles are wave-private, so no block barrier is needed for them
+__device__ __forceinline__ void wave_tile_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // acc[nt] = A(16 x 64) * W(rows 16 nt .. 16 nt + 15)^T.  Operand layouts of
 // v_mfma_f32_16x16x32_bf16 on a wave64: lane l supplies row l%16 of A and
 // column l%16 of B, each with the eight k values 8 (l/16) .. +7 of the
@@ -118,7 +128,7 @@ __device__ __forceinline__ void mfma_layer(const uint16_t (*A)[LD], const uint16
 // scratch tile.  Lanes with l%16 == 0 return the logits of rows
 // 4 (l/16) + r in logit[r].  If h1_out / h2_out are given, rows row0 + i < n
 // of the first (BF16, stride KP) and second (FP32, stride NH) hidden layers
-// are stored.  Must be called by every wave of the block (block barrier).
+// are stored.  A and H are the calling wave's own tiles.
 __device__ __forceinline__ void mlp_tile(const MlpW &w, const uint16_t (*A)[LD], uint16_t (*H)[LD],
                                          float logit[4], uint16_t *h1_out, float *h2_out,
                                          int64_t row0, int64_t n)
@@ -137,7 +147,7 @@ __device__ __forceinline__ void mlp_tile(const MlpW &w, const uint16_t (*A)[LD],
             H[rq + r][j] = hb;
             if (h1_out && row0 + rq + r < n) h1_out[(row0 + rq + r) * KP + j] = hb;
         }
-    __syncthreads();
+    wave_tile_sync();
     mfma_layer(H, w.w2, acc);
     float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -160,7 +170,7 @@ __device__ __forceinline__ void mlp_tile(const MlpW &w, const uint16_t (*A)[LD],
         v += __shfl_xor(v, 1, 16);
         logit[r] = v + w.b3;
     }
-    __syncthreads();   // H is reused by the next tile
+    wave_tile_sync();   // H is reused by the next tile
 }
 
 // ---------------------------------------------------------------- training forward
@@ -176,6 +186,7 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_forward(const float *P, const uin
 {
     __shared__ SmFwd sm;
     load_weights(P, sm.w);
+    __syncthreads();   // weights staged
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int64_t tiles = (n + 15) / 16;
     for (int64_t base = (int64_t)blockIdx.x * WAVES; base < tiles; base += (int64_t)gridDim.x * WAVES) {
@@ -189,7 +200,7 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_forward(const float *P, const uin
             if (live && row0 + r < n) v = *reinterpret_cast<const uint4 *>(&X[(row0 + r) * KP + c8]);
             *reinterpret_cast<uint4 *>(&sm.x[w][r][c8]) = v;
         }
-        __syncthreads();
+        wave_tile_sync();
         float lg[4];
         mlp_tile(sm.w, sm.x[w], sm.h[w], lg, live ? h1 : nullptr, live ? h2 : nullptr, row0, n);
         if ((l & 15) == 0 && live)
@@ -464,7 +475,7 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_score(EvDev E, Consts K, const fl
             const uint32_t hi = f2bf((f[k + 1] - sm.mean[k + 1]) * sm.istd[k + 1]);
             *reinterpret_cast<uint32_t *>(&sm.x[w][l][k]) = lo | (hi << 16);
         }
-        __syncthreads();
+        wave_tile_sync();
 #pragma unroll 1
         for (int sub = 0; sub < 4; ++sub) {
             float lg[4];
@@ -473,7 +484,7 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_score(EvDev E, Consts K, const fl
 #pragma unroll
                 for (int r = 0; r < 4; ++r) sm.logit[w][16 * sub + 4 * (l >> 4) + r] = lg[r];
         }
-        __syncthreads();
+        wave_tile_sync();
         if (live) {
             const float lg = sm.logit[w][l];
             const uint8_t veto = lg >= threshold ? 0 : 1;

@@ -143,7 +143,8 @@ struct EvRun {
 };
 
 // ---------------------------------------------------------------- setup
-// every per-event list count, the per-hit minima and flags, seed state
+// every per-event list count, the per-hit minima and flags, seed state and
+// direction
 __global__ __launch_bounds__(BLOCK) void k_px_init(EvDev E)
 {
     if (upstream_overflow(E)) return;
@@ -171,14 +172,17 @@ __global__ __launch_bounds__(BLOCK) void k_px_init(EvDev E)
     for (int i = t0; i < n_sd; i += st) {
         E.sd_used[i] = 0;
         E.sd_keep[i] = 0;
+        // seed direction
+        const int32_t a = E.sd_hits[4 * i], d = E.sd_hits[4 * i + 3];
+        E.sd_dir[i] = pls_dir(E.px_x[a], E.px_y[a], E.px_z[a], E.px_x[d], E.px_y[d], E.px_z[d]);
     }
 }
 
 // reset of the per-hit minima between two duplicate removals; with
-// list_free, also the list of the seeds that no kept pT5 uses
-__global__ __launch_bounds__(BLOCK) void k_px_rekey(EvDev E, int list_free)
+// list_free, also the list of the seeds that no kept pT5 uses (run inside
+// the kernels that precede the next users)
+__device__ __forceinline__ void rekey_body(const EvDev &E, bool list_free)
 {
-    if (upstream_overflow(E)) return;
     const int t0 = blockIdx.x * BLOCK + threadIdx.x, st = gridDim.x * BLOCK;
     const int n_px = E.desc[D_NPX], n_hits = (int)E.gc[GC_N_SORTED], n_sd = E.desc[D_NSEEDS];
     for (int i = t0; i < n_hits; i += st) E.hmin_o[i] = KEY_NONE;
@@ -189,17 +193,6 @@ __global__ __launch_bounds__(BLOCK) void k_px_rekey(EvDev E, int list_free)
         const bool act = s < n_sd && !E.sd_used[s];
         const int32_t at = agg_add(reinterpret_cast<int32_t *>(E.gc + GC_PXFREE), 0, act);
         if (act) E.sd_free[at] = s;
-    }
-}
-
-// seed directions
-__global__ __launch_bounds__(BLOCK) void k_sd_dir(EvDev E)
-{
-    if (upstream_overflow(E)) return;
-    const int n_sd = E.desc[D_NSEEDS];
-    for (int s = blockIdx.x * BLOCK + threadIdx.x; s < n_sd; s += gridDim.x * BLOCK) {
-        const int32_t a = E.sd_hits[4 * s], d = E.sd_hits[4 * s + 3];
-        E.sd_dir[s] = pls_dir(E.px_x[a], E.px_y[a], E.px_z[a], E.px_x[d], E.px_y[d], E.px_z[d]);
     }
 }
 
@@ -331,6 +324,27 @@ __device__ __forceinline__ int32_t obj_md(const EvDev &E, int32_t t, int j)
     else return j == 0 ? E.t3_a[t] : j == 1 ? E.t3_b[t] : E.t3_c[t];
 }
 
+// grouped position of outer hit j (0 .. 2 KIND - 1) of candidate c's object
+template <int KIND>
+__device__ __forceinline__ int32_t c_ohit(const EvDev &E, int32_t obj, int j)
+{
+    const int32_t m = obj_md<KIND>(E, obj, j >> 1);
+    return (j & 1) ? E.md_hup[m] : E.md_hlo[m];
+}
+
+// A new candidate's key (score bits, seed's index in its event) into the
+// per-hit minima of its duplicate removal, taken as the candidate is written
+template <int KIND>
+__device__ __forceinline__ void cand_min(const EvDev &E, int32_t s, int32_t o, float score)
+{
+    const unsigned long long key =
+        ((unsigned long long)__float_as_uint(score) << 32) | (uint32_t)E.sd_local[s];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) atomicMin(&E.hmin_p[E.sd_hits[4 * s + k]], key);
+#pragma unroll
+    for (int j = 0; j < 2 * KIND; ++j) atomicMin(&E.hmin_o[c_ohit<KIND>(E, o, j)], key);
+}
+
 // WPS waves per seed: the objects of its event in the azimuth bins of its
 // link window, 64 at a time (wave q of the seed takes every WPS-th chunk);
 // window, then the link chi2 on the lanes inside it.  A block of PX_LW
@@ -402,6 +416,7 @@ __device__ __forceinline__ void link_scan(const EvDev &E, const Consts &K, const
                         (KIND == 5 ? E.c5_seed : E.c3_seed)[at] = s;
                         (KIND == 5 ? E.c5_obj : E.c3_obj)[at] = t;
                         (KIND == 5 ? E.c5_score : E.c3_score)[at] = score;
+                        cand_min<KIND>(E, s, t, score);
                     }
                 }
             }
@@ -469,6 +484,7 @@ __global__ __launch_bounds__(PX_LW * 64) void k_px_link(EvDev E, Consts K, PixCo
                     c_seed[at] = s;
                     c_obj[at] = sm.obj[w][k];
                     c_score[at] = sm.score[w][k];
+                    cand_min<KIND>(E, s, sm.obj[w][k], sm.score[w][k]);
                 }
             }
             if (n_acc > PX_STAGE) {
@@ -496,29 +512,6 @@ __device__ __forceinline__ uint32_t n_cand(const EvDev &E)
     return n < (uint32_t)E.cap_pxc ? n : (uint32_t)E.cap_pxc;
 }
 
-// grouped position of outer hit j (0 .. 2 KIND - 1) of candidate c's object
-template <int KIND>
-__device__ __forceinline__ int32_t c_ohit(const EvDev &E, int32_t obj, int j)
-{
-    const int32_t m = obj_md<KIND>(E, obj, j >> 1);
-    return (j & 1) ? E.md_hup[m] : E.md_hlo[m];
-}
-
-template <int KIND>
-__global__ __launch_bounds__(BLOCK) void k_pxd_min(EvDev E)
-{
-    if (upstream_overflow(E)) return;
-    const uint32_t n = n_cand<KIND>(E);
-    for (uint32_t c = blockIdx.x * BLOCK + threadIdx.x; c < n; c += gridDim.x * BLOCK) {
-        const unsigned long long key = c_key<KIND>(E, c);
-        const int32_t s = KIND == 5 ? E.c5_seed[c] : E.c3_seed[c];
-        const int32_t o = KIND == 5 ? E.c5_obj[c] : E.c3_obj[c];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) atomicMin(&E.hmin_p[E.sd_hits[4 * s + k]], key);
-#pragma unroll
-        for (int j = 0; j < 2 * KIND; ++j) atomicMin(&E.hmin_o[c_ohit<KIND>(E, o, j)], key);
-    }
-}
 
 // per-event hit index of outer hit j of an object
 template <int KIND>
@@ -626,6 +619,8 @@ __global__ __launch_bounds__(BLOCK) void k_pt5_mark(EvDev E)
         for (int k = 0; k < 4; ++k) E.hflag_p[E.sd_hits[4 * s + k]] = 1;
         for (int j = 0; j < 10; ++j) E.hflag_o[c_ohit<5>(E, o, j)] = 1;
     }
+    // the pT5 minima are read no more: reset for the pT3 duplicate removal
+    rekey_body(E, true);
 }
 
 // pT3 near a pT5 or sharing a hit with one are duplicates (one wave per
@@ -733,6 +728,8 @@ __global__ __launch_bounds__(BLOCK) void k_t5_clean_fill(EvDev E, int n_mod)
         const int32_t at = agg_add(fill, ev, act);
         if (act) E.pl_dt[off[ev] + at] = E.t5_dir[t];
     }
+    // the pT3 minima are read no more: reset for the pLS cleaning
+    rekey_body(E, false);
 }
 
 // unlinked pLS: a pixel hit held by a candidate, or near one, is a
@@ -800,20 +797,16 @@ hipError_t launch_pixel(const EvDev &E, const Consts &K, const PixConsts &P, hip
     const int g_objw = px_grid((int64_t)E.rc[OT_T5] * NSH, WAVES * PX_WCHUNK);
     const int g_sdc = px_grid(E.cap_seeds, WAVES * PX_WCHUNK);
     hipLaunchKernelGGL(k_px_init, dim3(g_hits), dim3(BLOCK), 0, s, E);
-    hipLaunchKernelGGL(k_sd_dir, dim3(g_sd), dim3(BLOCK), 0, s, E);
     hipLaunchKernelGGL(k_obj_dir, dim3(g_obj), dim3(BLOCK), 0, s, E, n_mod);
     hipLaunchKernelGGL(k_pl_scan, dim3(2), dim3(1024), 0, s, E, (int)PXL_K5, (int)PXL_K3, PX_NB);
     hipLaunchKernelGGL(k_obj_fill, dim3(g_obj), dim3(BLOCK), 0, s, E, n_mod);
     // pT5
     hipLaunchKernelGGL((k_px_link<5, PX_WPS5>), dim3(g_link5), dim3(PX_LW * 64), 0, s, E, K, P);
-    hipLaunchKernelGGL(k_pxd_min<5>, dim3(g_c), dim3(BLOCK), 0, s, E);
     hipLaunchKernelGGL(k_pxd_keep<5>, dim3(g_c), dim3(BLOCK), 0, s, E, n_mod);
     hipLaunchKernelGGL(k_pl_scan, dim3(1), dim3(1024), 0, s, E, (int)PXL_D5, (int)PXL_D5, PX_NB);
     hipLaunchKernelGGL(k_pt5_mark, dim3(g_c), dim3(BLOCK), 0, s, E);
     // pT3 from the seeds no pT5 uses
-    hipLaunchKernelGGL(k_px_rekey, dim3(g_hits), dim3(BLOCK), 0, s, E, 1);
     hipLaunchKernelGGL((k_px_link<3, PX_WPS3>), dim3(g_link3), dim3(PX_LW * 64), 0, s, E, K, P);
-    hipLaunchKernelGGL(k_pxd_min<3>, dim3(g_c), dim3(BLOCK), 0, s, E);
     hipLaunchKernelGGL(k_pxd_keep<3>, dim3(g_c), dim3(BLOCK), 0, s, E, n_mod);
     // cross-cleaning
     hipLaunchKernelGGL(k_pt3_clean, dim3(g_cw), dim3(BLOCK), 0, s, E, P);
@@ -822,7 +815,6 @@ hipError_t launch_pixel(const EvDev &E, const Consts &K, const PixConsts &P, hip
     hipLaunchKernelGGL(k_t5_clean, dim3(g_objw), dim3(BLOCK), 0, s, E, P, n_mod);
     hipLaunchKernelGGL(k_pl_scan, dim3(1), dim3(1024), 0, s, E, (int)PXL_DT, (int)PXL_DT, PX_NB);
     hipLaunchKernelGGL(k_t5_clean_fill, dim3(g_obj), dim3(BLOCK), 0, s, E, n_mod);
-    hipLaunchKernelGGL(k_px_rekey, dim3(g_hits), dim3(BLOCK), 0, s, E, 0);
     hipLaunchKernelGGL(k_pls_clean, dim3(g_sdc), dim3(BLOCK), 0, s, E, P);
     hipLaunchKernelGGL(k_pls_keep, dim3(g_sd), dim3(BLOCK), 0, s, E);
     return hipGetLastError();
