@@ -602,7 +602,8 @@ def half_storage(lst, torch, E, G, PR, evs, steps=100):
             ctx.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
             ctx.tune(reps=3)
             ctx.load_hits(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
-            ctx.run_chain_graph(stream)
+            for _ in range(10):          # capture, then warm replays
+                ctx.run_chain_graph(stream)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(steps):

@@ -332,19 +332,6 @@ __device__ __forceinline__ int32_t c_ohit(const EvDev &E, int32_t obj, int j)
     return (j & 1) ? E.md_hup[m] : E.md_hlo[m];
 }
 
-// A new candidate's key (score bits, seed's index in its event) into the
-// per-hit minima of its duplicate removal, taken as the candidate is written
-template <int KIND>
-__device__ __forceinline__ void cand_min(const EvDev &E, int32_t s, int32_t o, float score)
-{
-    const unsigned long long key =
-        ((unsigned long long)__float_as_uint(score) << 32) | (uint32_t)E.sd_local[s];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) atomicMin(&E.hmin_p[E.sd_hits[4 * s + k]], key);
-#pragma unroll
-    for (int j = 0; j < 2 * KIND; ++j) atomicMin(&E.hmin_o[c_ohit<KIND>(E, o, j)], key);
-}
-
 // WPS waves per seed: the objects of its event in the azimuth bins of its
 // link window, 64 at a time (wave q of the seed takes every WPS-th chunk);
 // window, then the link chi2 on the lanes inside it.  A block of PX_LW
@@ -416,7 +403,6 @@ __device__ __forceinline__ void link_scan(const EvDev &E, const Consts &K, const
                         (KIND == 5 ? E.c5_seed : E.c3_seed)[at] = s;
                         (KIND == 5 ? E.c5_obj : E.c3_obj)[at] = t;
                         (KIND == 5 ? E.c5_score : E.c3_score)[at] = score;
-                        cand_min<KIND>(E, s, t, score);
                     }
                 }
             }
@@ -484,7 +470,6 @@ __global__ __launch_bounds__(PX_LW * 64) void k_px_link(EvDev E, Consts K, PixCo
                     c_seed[at] = s;
                     c_obj[at] = sm.obj[w][k];
                     c_score[at] = sm.score[w][k];
-                    cand_min<KIND>(E, s, sm.obj[w][k], sm.score[w][k]);
                 }
             }
             if (n_acc > PX_STAGE) {
@@ -512,6 +497,24 @@ __device__ __forceinline__ uint32_t n_cand(const EvDev &E)
     return n < (uint32_t)E.cap_pxc ? n : (uint32_t)E.cap_pxc;
 }
 
+
+// every candidate's key (score bits, seed's index in its event) into the
+// per-hit minima of its collection
+template <int KIND>
+__global__ __launch_bounds__(BLOCK) void k_pxd_min(EvDev E)
+{
+    if (upstream_overflow(E)) return;
+    const uint32_t n = n_cand<KIND>(E);
+    for (uint32_t c = blockIdx.x * BLOCK + threadIdx.x; c < n; c += gridDim.x * BLOCK) {
+        const unsigned long long key = c_key<KIND>(E, c);
+        const int32_t s = KIND == 5 ? E.c5_seed[c] : E.c3_seed[c];
+        const int32_t o = KIND == 5 ? E.c5_obj[c] : E.c3_obj[c];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) atomicMin(&E.hmin_p[E.sd_hits[4 * s + k]], key);
+#pragma unroll
+        for (int j = 0; j < 2 * KIND; ++j) atomicMin(&E.hmin_o[c_ohit<KIND>(E, o, j)], key);
+    }
+}
 
 // per-event hit index of outer hit j of an object
 template <int KIND>
@@ -802,11 +805,13 @@ hipError_t launch_pixel(const EvDev &E, const Consts &K, const PixConsts &P, hip
     hipLaunchKernelGGL(k_obj_fill, dim3(g_obj), dim3(BLOCK), 0, s, E, n_mod);
     // pT5
     hipLaunchKernelGGL((k_px_link<5, PX_WPS5>), dim3(g_link5), dim3(PX_LW * 64), 0, s, E, K, P);
+    hipLaunchKernelGGL(k_pxd_min<5>, dim3(g_c), dim3(BLOCK), 0, s, E);
     hipLaunchKernelGGL(k_pxd_keep<5>, dim3(g_c), dim3(BLOCK), 0, s, E, n_mod);
     hipLaunchKernelGGL(k_pl_scan, dim3(1), dim3(1024), 0, s, E, (int)PXL_D5, (int)PXL_D5, PX_NB);
-    hipLaunchKernelGGL(k_pt5_mark, dim3(g_c), dim3(BLOCK), 0, s, E);
+    hipLaunchKernelGGL(k_pt5_mark, dim3(std::max(g_c, g_hits)), dim3(BLOCK), 0, s, E);
     // pT3 from the seeds no pT5 uses
     hipLaunchKernelGGL((k_px_link<3, PX_WPS3>), dim3(g_link3), dim3(PX_LW * 64), 0, s, E, K, P);
+    hipLaunchKernelGGL(k_pxd_min<3>, dim3(g_c), dim3(BLOCK), 0, s, E);
     hipLaunchKernelGGL(k_pxd_keep<3>, dim3(g_c), dim3(BLOCK), 0, s, E, n_mod);
     // cross-cleaning
     hipLaunchKernelGGL(k_pt3_clean, dim3(g_cw), dim3(BLOCK), 0, s, E, P);
@@ -814,7 +819,7 @@ hipError_t launch_pixel(const EvDev &E, const Consts &K, const PixConsts &P, hip
     hipLaunchKernelGGL(k_pt3_mark, dim3(g_c), dim3(BLOCK), 0, s, E);
     hipLaunchKernelGGL(k_t5_clean, dim3(g_objw), dim3(BLOCK), 0, s, E, P, n_mod);
     hipLaunchKernelGGL(k_pl_scan, dim3(1), dim3(1024), 0, s, E, (int)PXL_DT, (int)PXL_DT, PX_NB);
-    hipLaunchKernelGGL(k_t5_clean_fill, dim3(g_obj), dim3(BLOCK), 0, s, E, n_mod);
+    hipLaunchKernelGGL(k_t5_clean_fill, dim3(std::max(g_obj, g_hits)), dim3(BLOCK), 0, s, E, n_mod);
     hipLaunchKernelGGL(k_pls_clean, dim3(g_sdc), dim3(BLOCK), 0, s, E, P);
     hipLaunchKernelGGL(k_pls_keep, dim3(g_sd), dim3(BLOCK), 0, s, E);
     return hipGetLastError();
