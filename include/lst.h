@@ -429,7 +429,9 @@ int lst_get_t3_logits(lst_ctx *ctx, int32_t event, float *logits_host, uint8_t *
  * roundings unchanged.  Every sum runs in a fixed order, so results are
  * bit-for-bit reproducible. */
 
-/* device workspace lst_mlp_backward needs for n rows */
+/* device workspace lst_mlp_backward needs for n rows: 4 (n + 64 x
+ * LST_MLP_NPARAM) bytes (per-row losses, partial gradients of up to 64 row
+ * chunks) */
 size_t lst_mlp_workspace_bytes(int64_t n);
 
 /* x = BF16((feat - mean) * istd), zero padded to 64 columns; feat [n][40] FP32 */
@@ -452,7 +454,7 @@ int lst_mlp_backward(lst_ctx *ctx, const float *params, const uint16_t *x, const
 /* lst_mlp_backward without a workspace argument, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving or
  * training loops, harnesses that forbid allocation).  The workspace is a
- * fixed device array inside the library, one per GPU, 6.0 MB, held from the
+ * fixed device array inside the library, one per GPU, 1.8 MB, held from the
  * first lst_create on that GPU until the process ends; n at most 8192 rows
  * (else LST_E_CAPACITY, nothing launched).  The call allocates nothing and
  * gives the same results as lst_mlp_backward.  Every call on one GPU shares
@@ -468,15 +470,17 @@ int lst_mlp_adam(lst_ctx *ctx, float *params, const float *grad, float *m, float
                  float lr, float beta1, float beta2, float eps, void *stream);
 
 /* n_steps Adam steps in one call.  Step i takes rows [order[i] * batch,
- * (order[i] + 1) * batch) of x [n_rows][64] and y [n_rows] through
- * lst_mlp_forward, lst_mlp_backward (its loss into losses[order[i]]) and
- * lst_mlp_adam with step number first_step + 1 + i: the same kernels in the
- * same order as those calls, hence the same results, with no return to the
- * caller between steps.  order: host array of n_steps batch indices, each in
- * 0 .. n_rows / batch - 1 (checked before anything is launched, else
- * LST_E_INVALID).  Device buffers: logits [batch], h1 [batch][64] (BF16
- * bits), h2 [batch][64], work (work_bytes >= lst_mlp_workspace_bytes(batch),
- * else LST_E_CAPACITY), grad, m, v [LST_MLP_NPARAM], losses [n_rows / batch].
+ * (order[i] + 1) * batch) of x [n_rows][64] and y [n_rows] through the
+ * arithmetic of lst_mlp_forward, lst_mlp_backward (its loss into
+ * losses[order[i]]) and lst_mlp_adam with step number first_step + 1 + i, in
+ * the same order as those calls, hence the same results, in two launches per
+ * step (the forward runs inside the gradient kernel, the Adam update inside
+ * the chunk reduction) with no return to the caller between steps.  order:
+ * host array of n_steps batch indices, each in 0 .. n_rows / batch - 1
+ * (checked before anything is launched, else LST_E_INVALID).  logits, h1
+ * and h2 are not used (kept for the signature; may be NULL).  Device
+ * buffers: work (work_bytes >= lst_mlp_workspace_bytes(batch), else
+ * LST_E_CAPACITY), grad, m, v [LST_MLP_NPARAM], losses [n_rows / batch].
  * Hyper-parameters as for lst_mlp_adam. */
 int lst_mlp_train_steps(lst_ctx *ctx, float *params, const uint16_t *x, const uint8_t *y,
                         int64_t n_rows, int64_t batch, const int32_t *order, int32_t n_steps,

@@ -1048,7 +1048,10 @@ int lst_mlp_train_steps(lst_ctx *c, float *params, const uint16_t *x, const uint
                         size_t work_bytes, float *grad, float *m, float *v, float *losses,
                         float lr, float beta1, float beta2, float eps, void *stream)
 {
-    int rc = mlp_args(c, batch, {params, x, y, logits, h1, h2, work, grad, m, v, losses});
+    (void)logits;   // the forward runs inside the gradient kernel
+    (void)h1;
+    (void)h2;
+    int rc = mlp_args(c, batch, {params, x, y, work, grad, m, v, losses});
     if (rc) return rc;
     if (batch < 1 || n_rows < batch || n_steps < 0 || first_step < 0 || (n_steps > 0 && !order))
         return fail(c, LST_E_INVALID, "rows %lld, batch %lld, steps %d from %d", (long long)n_rows,
@@ -1069,14 +1072,13 @@ int lst_mlp_train_steps(lst_ctx *c, float *params, const uint16_t *x, const uint
         const int64_t r0 = (int64_t)order[i] * batch;
         const uint16_t *xb = x + r0 * 64;
         const uint8_t *yb = y + r0;
-        HIPCHK(c, mlp_forward(params, xb, batch, logits, h1, h2, s));
-        HIPCHK(c, mlp_backward(params, xb, yb, batch, logits, h1, h2, (float *)work, grad,
-                               losses + order[i], s));
         // bias corrections exactly as lst_mlp_adam computes them
         const int32_t step = first_step + 1 + i;
         const float c1 = (float)(1.0 - std::pow((double)beta1, step));
         const float c2 = (float)(1.0 - std::pow((double)beta2, step));
-        HIPCHK(c, mlp_adam(params, grad, m, v, lr, beta1, beta2, eps, c1, c2, s));
+        // forward, backward and Adam in two launches with the same arithmetic
+        HIPCHK(c, mlp_train_step(params, xb, yb, batch, (float *)work, grad, losses + order[i], m,
+                                 v, lr, beta1, beta2, eps, c1, c2, s));
     }
     return LST_OK;
 }

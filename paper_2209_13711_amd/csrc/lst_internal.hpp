@@ -224,12 +224,14 @@ hipError_t mlp_backward(const float *P, const uint16_t *X, const uint8_t *y, int
                         float *grad, float *loss, hipStream_t s);
 hipError_t mlp_adam(float *P, const float *grad, float *m, float *v, float lr, float b1, float b2,
                     float eps, float c1, float c2, hipStream_t s);
+hipError_t mlp_train_step(float *P, const uint16_t *X, const uint8_t *y, int64_t n, float *work,
+                          float *grad, float *loss, float *m, float *v, float lr, float b1, float b2,
+                          float eps, float c1, float c2, hipStream_t s);
 // fixed backward workspace (no allocation): rows it holds, its size in floats
-// (n (2 + 2 x 64) + 64 chunks x MLP_NPARAM at n = MLP_FIXED_MAX_ROWS), and its
+// (n loss rows + 64 chunks x MLP_NPARAM at n = MLP_FIXED_MAX_ROWS), and its
 // device address on `device` (looked up once per device, then cached)
 constexpr int64_t MLP_FIXED_MAX_ROWS = 8192;
-constexpr size_t MLP_FIXED_SCRATCH_FLOATS =
-    (size_t)MLP_FIXED_MAX_ROWS * (2 + 2 * MLP_NH) + (size_t)64 * MLP_NPARAM;
+constexpr size_t MLP_FIXED_SCRATCH_FLOATS = (size_t)MLP_FIXED_MAX_ROWS + (size_t)64 * MLP_NPARAM;
 constexpr int MLP_FIXED_MAX_DEVICES = 64;
 hipError_t mlp_fixed_scratch(int device, void **out);
 // kind: OT_T3 or OT_T5

@@ -1024,9 +1024,20 @@ __device__ __forceinline__ void seg_body(const EvDev &E, const ModDev &M, const 
     SegQ &q = sm.q[w];
     const XBlock xb = xcd_block();
     const XRegions R = load_regions_x(E, OT_MD, xb.x);
-    for (uint32_t base = xb.rank * WAVES * P; base < R.total; base += xb.count * WAVES * P) {
-        const uint32_t v = base + w * P + gp.g;
-        const bool act = v < R.total;
+    // MDs of one module (same map edges, same candidate count) sit next to
+    // each other in the regions, so P consecutive MDs in one wave add up a
+    // dense module's load P times.  When the grid covers the sector in one
+    // pass, the longest wave sets the kernel's duration: the sector's MDs are
+    // then split into P equal runs and group g of wave slot u takes the u-th
+    // MD of run g, which evens out the waves' lengths.  Over several passes
+    // the lengths average out and consecutive MDs keep their shared
+    // candidates in the caches.
+    const uint32_t nslot = (R.total + P - 1) / P;
+    const bool spread = nslot <= xb.count * WAVES;
+    for (uint32_t base = xb.rank * WAVES; base < nslot; base += xb.count * WAVES) {
+        const uint32_t u = base + (uint32_t)w;
+        const uint32_t v = spread ? (uint32_t)gp.g * nslot + u : u * P + (uint32_t)gp.g;
+        const bool act = u < nslot && v < R.total;
         const int32_t i = region_index_x(R, act ? v : 0);
         const uint32_t cnt = enum_seg<G>(E, M, K, i, act, q,
                                          [&](int g, bool ok, int32_t o, uint32_t pos) {
@@ -1147,9 +1158,14 @@ __device__ __forceinline__ void t3_body(const EvDev &E, const Consts &K, SmT3 &s
     const uint32_t l = (uint32_t)lane_id();
     const XBlock xb = xcd_block();
     const XRegions R = load_regions_x(E, OT_MD, xb.x);
-    for (uint32_t base = xb.rank * WAVES * P; base < R.total; base += xb.count * WAVES * P) {
-        const uint32_t v = base + w * P + l;
-        const bool act = l < (uint32_t)P && v < R.total;
+    // one pass over the sector: lane l of wave slot u takes the u-th MD of the
+    // sector's l-th run (as in the segment stage), else consecutive MDs
+    const uint32_t nslot = (R.total + P - 1) / P;
+    const bool spread = nslot <= xb.count * WAVES;
+    for (uint32_t base = xb.rank * WAVES; base < nslot; base += xb.count * WAVES) {
+        const uint32_t u = base + (uint32_t)w;
+        const uint32_t v = spread ? l * nslot + u : u * P + l;
+        const bool act = l < (uint32_t)P && u < nslot && v < R.total;
         const int32_t a = region_index_x(R, act ? v : 0);
         int32_t ns1 = 0, s10 = 0;
         if (act) {
@@ -1316,9 +1332,14 @@ __device__ __forceinline__ void t5_body(const EvDev &E, const Consts &K, SmT5 &s
     const uint32_t l = (uint32_t)lane_id();
     const XBlock xb = xcd_block();
     const XRegions R = load_regions_x(E, OT_MD, xb.x);
-    for (uint32_t base = xb.rank * WAVES * P; base < R.total; base += xb.count * WAVES * P) {
-        const uint32_t v = base + w * P + l;
-        const bool act = l < (uint32_t)P && v < R.total;
+    // one pass over the sector: lane l of wave slot u takes the u-th MD of the
+    // sector's l-th run (as in the segment stage), else consecutive MDs
+    const uint32_t nslot = (R.total + P - 1) / P;
+    const bool spread = nslot <= xb.count * WAVES;
+    for (uint32_t base = xb.rank * WAVES; base < nslot; base += xb.count * WAVES) {
+        const uint32_t u = base + (uint32_t)w;
+        const uint32_t v = spread ? l * nslot + u : u * P + l;
+        const bool act = l < (uint32_t)P && u < nslot && v < R.total;
         const int32_t a = region_index_x(R, act ? v : 0);
         int32_t nt1 = 0, t10 = 0;
         if (act) {

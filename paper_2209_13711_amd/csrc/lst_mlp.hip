@@ -10,10 +10,10 @@
 // computed in registers by the lane that owns it, standardised and written
 // straight into the LDS operand tile, so they never travel through HBM.
 //
-// Training uses the same forward tile (saving the hidden activations), a
-// backward pass in FP32 with one thread per row for the row-local terms and
-// one thread per parameter and row chunk for the batch sums, followed by a
-// reduction over the chunks in a fixed order (gradients are bit-for-bit
+// Training uses the same forward tile (saving the hidden activations, or
+// fused into the gradient kernel), a backward pass whose products run on the
+// matrix cores in FP32 (v_mfma_f32_16x16x4_f32) per chunk of rows, followed
+// by a reduction over the chunks in a fixed order (gradients are bit-for-bit
 // deterministic), and Adam on FP32 master weights.
 //
 // Parameter vector (FP32): W1[64][40] (row = hidden unit), b1[64],
@@ -128,10 +128,12 @@ __device__ __forceinline__ void mfma_layer(const uint16_t (*A)[LD], const uint16
 // scratch tile.  Lanes with l%16 == 0 return the logits of rows
 // 4 (l/16) + r in logit[r].  If h1_out / h2_out are given, rows row0 + i < n
 // of the first (BF16, stride KP) and second (FP32, stride NH) hidden layers
-// are stored.  A and H are the calling wave's own tiles.
+// are stored.  A and H are the calling wave's own tiles.  If h2v is given,
+// lane l receives the second hidden layer's units 16 nt + l%16 of rows
+// 4 (l/16) + r in h2v[nt][r], and every lane the logits of its rows.
 __device__ __forceinline__ void mlp_tile(const MlpW &w, const uint16_t (*A)[LD], uint16_t (*H)[LD],
                                          float logit[4], uint16_t *h1_out, float *h2_out,
-                                         int64_t row0, int64_t n)
+                                         int64_t row0, int64_t n, float (*h2v)[4] = nullptr)
 {
     const int l = threadIdx.x & 63;
     const int col = l & 15, rq = 4 * (l >> 4);
@@ -158,6 +160,7 @@ __device__ __forceinline__ void mlp_tile(const MlpW &w, const uint16_t (*A)[LD],
             const float z = acc[nt][r] + w.b2[j];
             const float h2 = z > 0.0f ? z : 0.0f;
             if (h2_out && row0 + rq + r < n) h2_out[(row0 + rq + r) * NH + j] = h2;
+            if (h2v) h2v[nt][r] = h2;
             part[r] += h2 * w.w3[j];
         }
     // sum over the 16 lanes that hold one row's hidden units
@@ -226,154 +229,226 @@ __global__ void k_mlp_prepare(const float *F, const float *mean, const float *is
 }
 
 // ---------------------------------------------------------------- training backward
-// Row-local terms of the gradient of the mean BCE-with-logits loss:
-// g = (sigmoid(z) - y) / n, dz2 = g w3 [h2 > 0], dz1 = (dz2 W2) [h1 > 0],
-// with W2 the BF16-rounded weights the forward used; also the per-row loss.
-// A block takes ROWS_PER_BLOCK rows, ROW_GROUPS at a time: 64 lanes per row,
-// lane j writes dz2[r][j] and lane k sums dz1[r][k] over j = 0..63 in order,
-// so every output is coalesced and the sums run in a fixed order.
-constexpr int ROW_GROUPS = BLOCK / NH, ROWS_PER_BLOCK = 2 * ROW_GROUPS;
+// Gradient of the mean BCE-with-logits loss from the row terms
+//   g = (sigmoid(z) - y) / n,  dz2 = g w3 [h2 > 0],  dz1 = (dz2 W2) [h1 > 0]
+// (W2 the BF16-rounded weights the forward used), summed over the rows:
+//   dW1 = dz1^T X, db1 = sum dz1, dW2 = dz2^T h1, db2 = sum dz2,
+//   dw3 = h2^T g, db3 = sum g.
+// The rows split into at most GRAD_CHUNKS chunks of whole 64-row batches,
+// one block per chunk.  In each batch a wave takes 16 rows: their forward
+// (FWD) or the stored logits and hidden layers, the row terms into LDS, and
+// dz1 as a 16 x 64 x 64 FP32 matrix product.  The block's waves then share
+// the 28 16 x 16 tiles of dW1 (64 x 48, inputs zero padded) and dW2
+// (64 x 64), each a product over the batch's 64 rows; their accumulators
+// stay in registers over the chunk's batches.  Products are FP32 matrix-core
+// steps (v_mfma_f32_16x16x4_f32: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16], receives D rows 4 (l/16) + r, column l%16).  The vector
+// sums are kept per lane over its rows and combined in a fixed order at the
+// end.  A block writes its chunk's partial gradient; k_mlp_reduce adds the
+// chunks in chunk order.  Every sum runs in an order fixed by n alone, so the
+// gradient is bit-for-bit reproducible, and the forward-fused and the
+// stored-activation variants give the same bits.
+constexpr int RB = WAVES * 16;     // rows per batch of a block
+constexpr int DS = NH + 4;         // row stride of the FP32 row-term tiles
+constexpr int GT = 28;             // gradient tiles: 12 of dW1, 16 of dW2
+constexpr int GT_W = GT / WAVES;   // per wave
+static_assert(GT % WAVES == 0 && NIN <= 48, "gradient tiles");
 
-__global__ __launch_bounds__(BLOCK) void k_mlp_rows(const float *P, const float *logits,
-                                                    const uint8_t *y, int64_t n, const uint16_t *h1,
-                                                    const float *h2, float *g, float *dz2,
-                                                    float *dz1, float *loss_rows)
+struct SmGrad {
+    MlpW w;
+    uint16_t x[WAVES][16][LD];     // inputs (BF16)
+    uint16_t h[WAVES][16][LD];     // first hidden layer (BF16)
+    float d2[WAVES][16][DS];       // dz2
+    float d1[WAVES][16][DS];       // dz1
+    float vs[WAVES][3][NH];        // the waves' db1, db2, dw3
+    float gs[WAVES];               // the waves' db3
+};
+
+__device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c)
 {
-    __shared__ float w2[NH][NH + 1];
-    __shared__ float w3[NH];
-    __shared__ float d2[ROW_GROUPS][NH];
-    {
-        float b[WPT];   // all loads in flight, then the BF16 rounding
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// rows of the chunk c: [c clen, min((c + 1) clen, n)), clen a multiple of RB
+static void grad_chunks(int64_t n, int &nch, int64_t &clen)
+{
+    int64_t b = (n + RB - 1) / RB;
+    if (b < 1) b = 1;
+    nch = (int)(b < GRAD_CHUNKS ? b : GRAD_CHUNKS);
+    clen = (b + nch - 1) / nch * RB;
+}
+
+template <bool FWD>
+__global__ __launch_bounds__(BLOCK) void k_mlp_grad(const float *P, const uint16_t *X,
+                                                    const uint8_t *y, int64_t n, int64_t clen,
+                                                    const float *logits, const uint16_t *h1,
+                                                    const float *h2, float *loss_rows, float *part)
+{
+    __shared__ SmGrad sm;
+    load_weights(P, sm.w);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int col = l & 15, q = l >> 4, rq = 4 * q;
+    const int64_t r0 = (int64_t)blockIdx.x * clen;
+    const int64_t r1 = r0 + clen < n ? r0 + clen : n;
+    f32x4 acc[GT_W];
 #pragma unroll
-        for (int u = 0; u < WPT; ++u) b[u] = P[OFF_W2 + threadIdx.x + u * BLOCK];
+    for (int i = 0; i < GT_W; ++i) acc[i] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float sb1[4] = {0.0f, 0.0f, 0.0f, 0.0f}, sb2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float sw3[4] = {0.0f, 0.0f, 0.0f, 0.0f}, sg = 0.0f;
+    // operands of the wave's gradient tiles: column 16 jt + l%16 of dz1 (dW1)
+    // or dz2 (dW2) and column 16 kt + l%16 of the inputs or h1, at row 0
+    const float *ta[GT_W];
+    const uint16_t *tb[GT_W];
 #pragma unroll
-        for (int u = 0; u < WPT; ++u) {
-            const int i = threadIdx.x + u * BLOCK;
-            w2[i / NH][i % NH] = bf2f(f2bf(b[u]));
+    for (int i = 0; i < GT_W; ++i) {
+        const int t = w + WAVES * i;
+        const bool first = t < 12;
+        const int jt = first ? t / 3 : (t - 12) / 4, kt = first ? t % 3 : (t - 12) % 4;
+        ta[i] = (first ? &sm.d1[0][0][0] : &sm.d2[0][0][0]) + 16 * jt + col;
+        tb[i] = (first ? &sm.x[0][0][0] : &sm.h[0][0][0]) + 16 * kt + col;
+    }
+    __syncthreads();   // weights staged
+    for (int64_t b0 = r0; b0 < r1; b0 += RB) {
+        const int64_t row0 = b0 + 16 * w;
+        // the wave's 16 input rows (and stored first hidden layer), zero past the chunk
+        for (int i = l; i < 16 * (KP / 8); i += 64) {
+            const int r = i / (KP / 8), c8 = (i % (KP / 8)) * 8;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u), u = v;
+            if (row0 + r < r1) {
+                v = *reinterpret_cast<const uint4 *>(&X[(row0 + r) * KP + c8]);
+                if (!FWD) u = *reinterpret_cast<const uint4 *>(&h1[(row0 + r) * KP + c8]);
+            }
+            *reinterpret_cast<uint4 *>(&sm.x[w][r][c8]) = v;
+            if (!FWD) *reinterpret_cast<uint4 *>(&sm.h[w][r][c8]) = u;
+        }
+        wave_tile_sync();
+        float lg[4], h2v[4][4];
+        if (FWD) {
+            mlp_tile(sm.w, sm.x[w], sm.h[w], lg, nullptr, nullptr, row0, r1, h2v);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = row0 + rq + r;
+                const bool live = row < r1;
+                lg[r] = live ? logits[row] : 0.0f;
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) h2v[nt][r] = live ? h2[row * NH + 16 * nt + col] : 0.0f;
+            }
+        }
+        // row terms: g, the loss per row, dz2 (lane: units 16 nt + col of rows rq + r)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = row0 + rq + r;
+            const bool live = row < r1;
+            const float z = lg[r];
+            const float yv = live && y[row] ? 1.0f : 0.0f;
+            const float gr = live ? (1.0f / (1.0f + expf(-z)) - yv) / (float)n : 0.0f;
+            if (live && col == 0)
+                loss_rows[row] = (z > 0.0f ? z : 0.0f) - z * yv + log1pf(expf(-fabsf(z)));
+            if (col == 0) sg += gr;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int j = 16 * nt + col;
+                const float dj = h2v[nt][r] > 0.0f ? gr * sm.w.w3[j] : 0.0f;
+                sm.d2[w][rq + r][j] = dj;
+                sb2[nt] += dj;
+                sw3[nt] += gr * h2v[nt][r];
+            }
+        }
+        wave_tile_sync();
+        // dz1 (16 x 64) = dz2 (16 x 64) W2 (64 x 64), masked where h1 is zero
+        {
+            f32x4 d[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) d[nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ks = 0; ks < NH / 4; ++ks) {
+                const float a = sm.d2[w][col][4 * ks + q];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    d[nt] = mfma_f32(a, bf2f(sm.w.w2[4 * ks + q][16 * nt + col]), d[nt]);
+            }
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j = 16 * nt + col;
+                    const float v = sm.h[w][rq + r][j] != 0 ? d[nt][r] : 0.0f;
+                    sm.d1[w][rq + r][j] = v;
+                    sb1[nt] += v;
+                }
+        }
+        __syncthreads();   // every wave's rows in LDS
+        // the wave's gradient tiles t = w + WAVES i over the batch's 64 rows,
+        // four rows per step; the tiles' products of one step are independent
+#pragma unroll 2
+        for (int s = 0; s < RB / 4; ++s) {
+            const int row = 4 * s + q;
+#pragma unroll
+            for (int i = 0; i < GT_W; ++i)
+                acc[i] = mfma_f32(ta[i][row * DS], bf2f(tb[i][row * LD]), acc[i]);
+        }
+        __syncthreads();   // the tiles are rewritten by the next batch
+    }
+    // the chunk's partial gradient
+    float *pc = part + (int64_t)blockIdx.x * NPARAM;
+#pragma unroll
+    for (int i = 0; i < GT_W; ++i) {
+        const int t = w + WAVES * i;
+        const bool first = t < 12;
+        const int jt = first ? t / 3 : (t - 12) / 4, kt = first ? t % 3 : (t - 12) % 4;
+        const int k = 16 * kt + col;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = 16 * jt + rq + r;
+            if (first) {
+                if (k < NIN) pc[OFF_W1 + j * NIN + k] = acc[i][r];
+            } else {
+                pc[OFF_W2 + j * NH + k] = acc[i][r];
+            }
         }
     }
-    for (int i = threadIdx.x; i < NH; i += blockDim.x) w3[i] = P[OFF_W3 + i];
-    const int grp = threadIdx.x / NH, lane = threadIdx.x % NH;
-    for (int64_t b = (int64_t)blockIdx.x * ROWS_PER_BLOCK; b < n;
-         b += (int64_t)gridDim.x * ROWS_PER_BLOCK) {
-        __syncthreads();                     // weights loaded; d2 of the last rows consumed
-        for (int q = 0; q < ROWS_PER_BLOCK; q += ROW_GROUPS) {
-            const int64_t r = b + q + grp;
-            if (r < n) {
-                const float z = logits[r];
-                const float yv = y[r] ? 1.0f : 0.0f;
-                const float gr = (1.0f / (1.0f + expf(-z)) - yv) / (float)n;
-                if (lane == 0) {
-                    loss_rows[r] = (z > 0.0f ? z : 0.0f) - z * yv + log1pf(expf(-fabsf(z)));
-                    g[r] = gr;
-                }
-                const float dj = h2[r * NH + lane] > 0.0f ? gr * w3[lane] : 0.0f;
-                d2[grp][lane] = dj;
-                dz2[r * NH + lane] = dj;
-            }
-            __syncthreads();
-            if (r < n) {
-                float acc = 0.0f;
+    // vector sums: the four row quarters of the wave, then the waves in order
 #pragma unroll
-                for (int j = 0; j < NH; ++j) acc += d2[grp][j] * w2[j][lane];
-                dz1[r * NH + lane] = h1[r * KP + lane] != 0 ? acc : 0.0f;
-            }
-            __syncthreads();                 // d2 is rewritten by the next rows
+    for (int nt = 0; nt < 4; ++nt) {
+        float a = sb1[nt], b = sb2[nt], c = sw3[nt];
+        a += __shfl_xor(a, 16, 64);
+        b += __shfl_xor(b, 16, 64);
+        c += __shfl_xor(c, 16, 64);
+        a += __shfl_xor(a, 32, 64);
+        b += __shfl_xor(b, 32, 64);
+        c += __shfl_xor(c, 32, 64);
+        if (q == 0) {
+            sm.vs[w][0][16 * nt + col] = a;
+            sm.vs[w][1][16 * nt + col] = b;
+            sm.vs[w][2][16 * nt + col] = c;
         }
+    }
+    sg += __shfl_xor(sg, 16, 64);
+    sg += __shfl_xor(sg, 32, 64);
+    if (l == 0) sm.gs[w] = sg;
+    __syncthreads();
+    const int tid = threadIdx.x;
+    if (tid < 3 * NH) {
+        const int v = tid / NH, j = tid % NH;
+        float a = 0.0f;
+#pragma unroll
+        for (int ww = 0; ww < WAVES; ++ww) a += sm.vs[ww][v][j];
+        pc[(v == 0 ? OFF_B1 : v == 1 ? OFF_B2 : OFF_W3) + j] = a;
+    } else if (tid == 3 * NH) {
+        float a = 0.0f;
+#pragma unroll
+        for (int ww = 0; ww < WAVES; ++ww) a += sm.gs[ww];
+        pc[OFF_B3] = a;
     }
 }
 
-// Sums over the rows r0..r1-1 in row order of a(r) b(r) (or of a(r)):
-// GP_U rows' operands are loaded before they are added, so GP_U loads are in
-// flight at once; the additions keep the row order.
+// mean of the per-row losses: one block, fixed-order partials and tree;
+// GP_U rows per thread are loaded before they are added
 constexpr int GP_U = 16;
 
-template <class A, class B>
-__device__ __forceinline__ float rows_dot(int64_t r0, int64_t r1, A a, B b)
-{
-    float acc = 0.0f;
-    for (int64_t rb = r0; rb < r1; rb += GP_U) {
-        float x[GP_U], y[GP_U];
-#pragma unroll
-        for (int u = 0; u < GP_U; ++u) {
-            const int64_t r = rb + u < r1 ? rb + u : r1 - 1;   // rows past the end: not added
-            x[u] = a(r);
-            y[u] = b(r);
-        }
-#pragma unroll
-        for (int u = 0; u < GP_U; ++u)
-            if (rb + u < r1) acc += x[u] * y[u];
-    }
-    return acc;
-}
-
-template <class A>
-__device__ __forceinline__ float rows_sum(int64_t r0, int64_t r1, A a)
-{
-    float acc = 0.0f;
-    for (int64_t rb = r0; rb < r1; rb += GP_U) {
-        float x[GP_U];
-#pragma unroll
-        for (int u = 0; u < GP_U; ++u) x[u] = a(rb + u < r1 ? rb + u : r1 - 1);
-#pragma unroll
-        for (int u = 0; u < GP_U; ++u)
-            if (rb + u < r1) acc += x[u];
-    }
-    return acc;
-}
-
-// part[c][p] = sum over the rows of chunk c (in row order) of parameter p's terms
-__global__ __launch_bounds__(BLOCK) void k_mlp_grad_parts(const uint16_t *X, int64_t n,
-                                                          const uint16_t *h1, const float *h2,
-                                                          const float *g, const float *dz2,
-                                                          const float *dz1, float *part)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y;
-    if (p >= NPARAM) return;
-    const int64_t len = (n + GRAD_CHUNKS - 1) / GRAD_CHUNKS;
-    const int64_t r0 = c * len < n ? c * len : n;
-    const int64_t r1 = r0 + len < n ? r0 + len : n;
-    float acc;
-    if (p < OFF_B1) {                       // dW1[j][k] = sum dz1[j] x[k]
-        const int j = p / NIN, k = p % NIN;
-        acc = rows_dot(r0, r1, [&](int64_t r) { return dz1[r * NH + j]; },
-                       [&](int64_t r) { return bf2f(X[r * KP + k]); });
-    } else if (p < OFF_W2) {                // db1[j] = sum dz1[j]
-        const int j = p - OFF_B1;
-        acc = rows_sum(r0, r1, [&](int64_t r) { return dz1[r * NH + j]; });
-    } else if (p < OFF_B2) {                // dW2[j][k] = sum dz2[j] h1[k]
-        const int j = (p - OFF_W2) / NH, k = (p - OFF_W2) % NH;
-        acc = rows_dot(r0, r1, [&](int64_t r) { return dz2[r * NH + j]; },
-                       [&](int64_t r) { return bf2f(h1[r * KP + k]); });
-    } else if (p < OFF_W3) {                // db2[j] = sum dz2[j]
-        const int j = p - OFF_B2;
-        acc = rows_sum(r0, r1, [&](int64_t r) { return dz2[r * NH + j]; });
-    } else if (p < OFF_B3) {                // dw3[j] = sum g h2[j]
-        const int j = p - OFF_W3;
-        acc = rows_dot(r0, r1, [&](int64_t r) { return g[r]; },
-                       [&](int64_t r) { return h2[r * NH + j]; });
-    } else {                                // db3 = sum g
-        acc = rows_sum(r0, r1, [&](int64_t r) { return g[r]; });
-    }
-    part[(int64_t)c * NPARAM + p] = acc;
-}
-
-__global__ void k_mlp_grad_reduce(const float *part, float *grad)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= NPARAM) return;
-    float v[GRAD_CHUNKS];   // all chunks' partials in flight, then added in chunk order
-#pragma unroll
-    for (int c = 0; c < GRAD_CHUNKS; ++c) v[c] = part[c * NPARAM + p];
-    float acc = 0.0f;
-#pragma unroll
-    for (int c = 0; c < GRAD_CHUNKS; ++c) acc += v[c];
-    grad[p] = acc;
-}
-
 // mean of the per-row losses: one block, fixed-order partials and tree
-__global__ void k_mlp_loss(const float *loss_rows, int64_t n, float *loss)
+__device__ __forceinline__ void loss_body(const float *loss_rows, int64_t n, float *loss)
 {
     __shared__ float part[BLOCK];
     float acc = 0.0f;
@@ -399,17 +474,50 @@ __global__ void k_mlp_loss(const float *loss_rows, int64_t n, float *loss)
 }
 
 // Adam with bias correction; c1 = 1 - beta1^t, c2 = 1 - beta2^t
-__global__ void k_mlp_adam(float *P, const float *grad, float *m, float *v, float lr, float b1,
-                           float b2, float eps, float c1, float c2)
+struct AdamArgs {
+    float *m, *v;
+    float lr, b1, b2, eps, c1, c2;
+};
+
+__device__ __forceinline__ void adam_one(float *P, int p, float gr, const AdamArgs &a)
+{
+    const float mp = a.b1 * a.m[p] + (1.0f - a.b1) * gr;
+    const float vp = a.b2 * a.v[p] + (1.0f - a.b2) * gr * gr;
+    a.m[p] = mp;
+    a.v[p] = vp;
+    P[p] -= a.lr * (mp / a.c1) / (sqrtf(vp / a.c2) + a.eps);
+}
+
+__global__ void k_mlp_adam(float *P, const float *grad, AdamArgs a)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= NPARAM) return;
-    const float gr = grad[p];
-    const float mp = b1 * m[p] + (1.0f - b1) * gr;
-    const float vp = b2 * v[p] + (1.0f - b2) * gr * gr;
-    m[p] = mp;
-    v[p] = vp;
-    P[p] -= lr * (mp / c1) / (sqrtf(vp / c2) + eps);
+    adam_one(P, p, grad[p], a);
+}
+
+// The end of a backward pass in one launch: grad[p] is the sum of the
+// chunks' partials in chunk order, followed (ADAM) by the Adam update of
+// parameter p with the same operations as k_mlp_adam; the block past the
+// parameters takes the mean loss (loss_body).
+template <bool ADAM>
+__global__ void k_mlp_reduce(const float *part, int nch, float *grad, const float *loss_rows,
+                             int64_t n, float *loss, float *P, AdamArgs a)
+{
+    if (blockIdx.x == gridDim.x - 1) {
+        loss_body(loss_rows, n, loss);
+        return;
+    }
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= NPARAM) return;
+    float v[GRAD_CHUNKS];   // all chunks' partials in flight, then added in chunk order
+#pragma unroll
+    for (int c = 0; c < GRAD_CHUNKS; ++c) v[c] = c < nch ? part[c * NPARAM + p] : 0.0f;
+    float acc = 0.0f;
+#pragma unroll
+    for (int c = 0; c < GRAD_CHUNKS; ++c)
+        if (c < nch) acc += v[c];
+    grad[p] = acc;
+    if (ADAM) adam_one(P, p, acc, a);
 }
 
 // ---------------------------------------------------------------- scoring in the chain
@@ -508,9 +616,10 @@ static int grid_of(int64_t work, int per_block)
     return (int)g;
 }
 
+// backward workspace: the per-row losses, then the chunks' partial gradients
 size_t mlp_workspace_bytes(int64_t n)
 {
-    return sizeof(float) * ((size_t)n * (2 + 2 * NH) + (size_t)GRAD_CHUNKS * NPARAM);
+    return sizeof(float) * ((size_t)n + (size_t)GRAD_CHUNKS * NPARAM);
 }
 
 hipError_t mlp_prepare(const float *F, const float *mean, const float *istd, int64_t n, uint16_t *X,
@@ -533,14 +642,34 @@ hipError_t mlp_backward(const float *P, const uint16_t *X, const uint8_t *y, int
                         const float *logits, const uint16_t *h1, const float *h2, float *work,
                         float *grad, float *loss, hipStream_t s)
 {
-    float *g = work, *lrow = g + n, *dz2 = lrow + n, *dz1 = dz2 + n * NH, *part = dz1 + n * NH;
-    hipLaunchKernelGGL(k_mlp_rows, dim3(grid_of(n, ROWS_PER_BLOCK)), dim3(BLOCK), 0, s, P, logits, y,
-                       n, h1, h2, g, dz2, dz1, lrow);
-    hipLaunchKernelGGL(k_mlp_grad_parts, dim3((NPARAM + BLOCK - 1) / BLOCK, GRAD_CHUNKS), dim3(BLOCK),
-                       0, s, X, n, h1, h2, g, dz2, dz1, part);
-    hipLaunchKernelGGL(k_mlp_grad_reduce, dim3((NPARAM + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s,
-                       part, grad);
-    hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(BLOCK), 0, s, lrow, n, loss);
+    float *lrow = work, *part = work + n;
+    int nch;
+    int64_t clen;
+    grad_chunks(n, nch, clen);
+    hipLaunchKernelGGL(k_mlp_grad<false>, dim3(nch), dim3(BLOCK), 0, s, P, X, y, n, clen, logits, h1,
+                       h2, lrow, part);
+    // the chunk sums and the mean loss in one launch (the loss in the last block)
+    hipLaunchKernelGGL(k_mlp_reduce<false>, dim3((NPARAM + BLOCK - 1) / BLOCK + 1), dim3(BLOCK), 0, s,
+                       part, nch, grad, lrow, n, loss, nullptr, AdamArgs{});
+    return hipGetLastError();
+}
+
+// One Adam step on n rows in two launches, with the same operations in the
+// same order as mlp_forward, mlp_backward and mlp_adam one after the other:
+// the forward fused with the per-chunk gradient products, then the chunk
+// reduction with the Adam update and the mean loss.
+hipError_t mlp_train_step(float *P, const uint16_t *X, const uint8_t *y, int64_t n, float *work,
+                          float *grad, float *loss, float *m, float *v, float lr, float b1, float b2,
+                          float eps, float c1, float c2, hipStream_t s)
+{
+    float *lrow = work, *part = work + n;
+    int nch;
+    int64_t clen;
+    grad_chunks(n, nch, clen);
+    hipLaunchKernelGGL(k_mlp_grad<true>, dim3(nch), dim3(BLOCK), 0, s, P, X, y, n, clen, nullptr,
+                       nullptr, nullptr, lrow, part);
+    hipLaunchKernelGGL(k_mlp_reduce<true>, dim3((NPARAM + BLOCK - 1) / BLOCK + 1), dim3(BLOCK), 0, s,
+                       part, nch, grad, lrow, n, loss, P, AdamArgs{m, v, lr, b1, b2, eps, c1, c2});
     return hipGetLastError();
 }
 
@@ -551,8 +680,8 @@ hipError_t mlp_backward(const float *P, const uint16_t *X, const uint8_t *y, int
 // device address on each GPU comes from hipGetSymbolAddress, taken once per
 // device with that device current, and only that address is ever passed on.
 static __device__ __align__(256) float scratch[MLP_FIXED_SCRATCH_FLOATS];
-static_assert(sizeof(float) * ((size_t)MLP_FIXED_MAX_ROWS * (2 + 2 * NH) +
-                               (size_t)GRAD_CHUNKS * NPARAM) <= sizeof(scratch),
+static_assert(sizeof(float) * ((size_t)MLP_FIXED_MAX_ROWS + (size_t)GRAD_CHUNKS * NPARAM) <=
+                  sizeof(scratch),
               "fixed workspace holds MLP_FIXED_MAX_ROWS rows");
 
 static std::mutex scratch_mu;
@@ -583,7 +712,7 @@ hipError_t mlp_adam(float *P, const float *grad, float *m, float *v, float lr, f
                     float eps, float c1, float c2, hipStream_t s)
 {
     hipLaunchKernelGGL(k_mlp_adam, dim3((NPARAM + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, P, grad,
-                       m, v, lr, b1, b2, eps, c1, c2);
+                       AdamArgs{m, v, lr, b1, b2, eps, c1, c2});
     return hipGetLastError();
 }
 
