@@ -745,9 +745,15 @@ __device__ __forceinline__ void md_body(const EvDev &E, const ModDev &M, const C
     const XBlock xb = xcd_block();
     const int n_x = M.sec_off[xb.x + 1] - M.sec_off[xb.x];   // modules of this sector
     const int items = E.desc[D_NEV] * n_x;
-    for (int base = (int)xb.rank * WAVES * P; base < items; base += (int)xb.count * WAVES * P) {
-        const int k = base + w * P + gp.g;
-        const bool act = k < items;
+    // one pass over the sector: group g of wave slot u takes the u-th module
+    // of the sector's g-th run (spreads the dense modules over the waves, as
+    // in the segment stage), else consecutive modules
+    const int nslot = (items + P - 1) / P;
+    const bool spread = nslot <= (int)xb.count * WAVES;
+    for (int base = (int)xb.rank * WAVES; base < nslot; base += (int)xb.count * WAVES) {
+        const int u = base + w;
+        const int k = spread ? gp.g * nslot + u : u * P + gp.g;
+        const bool act = u < nslot && k < items;
         int slot = 0;
         uint32_t lo0 = 0, up0 = 0, nup = 0, np = 0;
         if (act) {
