@@ -249,7 +249,10 @@ __global__ void k_mlp_prepare(const float *F, const float *mean, const float *is
 // gradient is bit-for-bit reproducible, and the forward-fused and the
 // stored-activation variants give the same bits.
 constexpr int RB = WAVES * 16;     // rows per batch of a block
-constexpr int DS = NH + 4;         // row stride of the FP32 row-term tiles
+// row stride of the FP32 row-term tiles: the gradient products read 16
+// consecutive columns of 4 consecutive rows per instruction, which a stride
+// of 16 banks (mod 64) spreads over distinct banks
+constexpr int DS = NH + 16;
 constexpr int GT = 28;             // gradient tiles: 12 of dW1, 16 of dW2
 constexpr int GT_W = GT / WAVES;   // per wave
 static_assert(GT % WAVES == 0 && NIN <= 48, "gradient tiles");
