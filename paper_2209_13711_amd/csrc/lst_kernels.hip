@@ -987,19 +987,44 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
         }
         const uint32_t incl = wave_incl_scan(bc);
         const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-        for (uint32_t jc = 0; jc < tot; jc += 64) {
-            const uint32_t j = jc + l;
+        // candidate jc + l of the list: its outer MD o and the group g of its
+        // inner MD; the outer anchors are loaded one chunk of 64 ahead, so
+        // their latency overlaps the window test and queueing of the chunk
+        // before
+        auto locate = [&](uint32_t jc, int32_t &o, int &g) {
             const int src = chunk_src(incl, bc, jc, q.mark);
             const uint32_t ex = gw.bcast(incl, src) - gw.bcast(bc, src);
-            const int32_t obs = gw.bcast(bs, src);
-            const int g = gw.bcast(ge, src);
+            o = gw.bcast(bs, src) + (int32_t)(jc + l - ex);
+            g = gw.bcast(ge, src);
+            return jc + l < tot;
+        };
+        int32_t o = 0;
+        int g = 0;
+        bool live = false;
+        float4 a0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), a1 = a0;
+        if (tot > 0) {
+            live = locate(0, o, g);
+            if (live) {
+                a0 = E.md_p0[o];
+                a1 = E.md_p1[o];
+            }
+        }
+        for (uint32_t jc = 0; jc < tot; jc += 64) {
+            int32_t on = 0;
+            int gn = 0;
+            bool ln = false;
+            float4 b0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b1 = b0;
+            if (jc + 64 < tot) {
+                ln = locate(jc + 64, on, gn);
+                if (ln) {
+                    b0 = E.md_p0[on];
+                    b1 = E.md_p1[on];
+                }
+            }
             bool win = false;
-            int32_t o = 0;
-            if (j < tot) {
-                o = obs + (int32_t)(j - ex);
+            if (live) {
                 const float4 w0 = q.w0[g], w1 = q.w1[g];
-                win = seg_window(K, w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, E.md_p0[o],
-                                 E.md_p1[o]);
+                win = seg_window(K, w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, a0, a1);
             }
             const unsigned long long mk = __ballot(win);
             if (win) {
@@ -1009,6 +1034,11 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
             }
             tail += (uint32_t)__popcll(mk);
             if (tail - head >= 64) drain(64);
+            o = on;
+            g = gn;
+            live = ln;
+            a0 = b0;
+            a1 = b1;
         }
     }
     if (tail != head) drain(tail - head);
