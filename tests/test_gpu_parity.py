@@ -290,6 +290,29 @@ def test_group_widths_match_oracle(lanes):
     _batch_parity(ctx_b, evs, orc)
 
 
+@pytest.mark.parametrize("lanes", [16, 32])
+def test_one_pass_and_many_pass_orders_match_oracle(lanes):
+    """The MD, segment, triplet and quintuplet stages spread a sector's inner
+    objects over the waves when the grid covers the sector in one pass, and
+    keep their consecutive order when each wave makes several passes: both
+    orders (grids of 8192 and 8 blocks) give the oracle's objects on the same
+    PU200-like event."""
+    params = PR.make()
+    geo = G.get("full")
+    ev = E.generate(2, 4)
+    ref = oracle.Oracle(params, geo.f32, geo.i32).run_event(ev)
+    ctx = _ctx(geo, params)
+    ctx.run_event(ev)
+    t = ctx.tuning()
+    widths = [64, lanes, lanes, lanes, lanes, 64]
+    for g in (8192, 8):
+        print(f"case lanes {lanes} object-stage grid {g}", flush=True)
+        ctx.set_tuning([t["grid"][0], g, g, g, g, t["grid"][5]], persistent=0, blocks_per_cu=1,
+                       lanes=widths)
+        assert ctx.tuning()["grid"][1:5] == [g] * 4
+        assert_parity(ctx.run_event(ev), ref)
+
+
 def test_autotuner_keeps_results_and_caches(tmp_path):
     geo = G.get("barrel_toy")
     params = PR.make()
