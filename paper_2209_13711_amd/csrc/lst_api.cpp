@@ -487,6 +487,11 @@ static bool sort_per_event(const lst_ctx *c)
     return c->sort_ev_ok && c->caps.events >= SORT_EV_MIN_EVENTS;
 }
 
+// the segment kernel whose runs of inner MDs of one module share their
+// candidate enumeration, for arenas that hold more than one event (a wave
+// then takes consecutive MDs); one event spreads its MDs over the waves
+static bool seg_share(const lst_ctx *c) { return c->caps.events > 1; }
+
 int lst_build_map(const double *params, int32_t n_params, int32_t n, const float *f32,
                   const int32_t *i32, int32_t *row_ptr, int32_t *col, int64_t cap_col,
                   int64_t *n_edges)
@@ -837,7 +842,8 @@ int lst_run_segments(lst_ctx *c, void *stream)
 {
     int rc = need_stage(c, 3, "lst_run_segments");
     if (rc) return rc;
-    HIPCHK(c, launch_seg(c->E, c->M, c->K, c->tune.grid[ST_SEG], c->tune.lanes[ST_SEG], (hipStream_t)stream));
+    HIPCHK(c, launch_seg(c->E, c->M, c->K, c->tune.grid[ST_SEG], c->tune.lanes[ST_SEG],
+                         seg_share(c), (hipStream_t)stream));
     if ((rc = enqueue_cap(c, OT_SEG, (hipStream_t)stream))) return rc;
     c->stage = 4;
     return LST_OK;
@@ -1151,7 +1157,7 @@ static int enqueue_chain(lst_ctx *c, hipStream_t s)
     HIPCHK(c, launch_sort(c->E, c->M, t.grid[ST_SORT], sort_per_event(c), s));
     HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], t.lanes[ST_MD], s));
     if ((rc = enqueue_cap(c, OT_MD, s))) return rc;
-    HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], t.lanes[ST_SEG], s));
+    HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], t.lanes[ST_SEG], seg_share(c), s));
     if ((rc = enqueue_cap(c, OT_SEG, s))) return rc;
     HIPCHK(c, launch_t3(c->E, c->M, c->K, t.grid[ST_T3], t.lanes[ST_T3], s));
     if ((rc = enqueue_cap(c, OT_T3, s))) return rc;
@@ -1831,7 +1837,7 @@ static int timed_chain(lst_ctx *c, hipStream_t s, hipEvent_t *ev, double *stage_
         HIPCHK(c, hipEventRecord(ev[1], s));
         HIPCHK(c, launch_md(c->E, c->M, c->K, t.grid[ST_MD], t.lanes[ST_MD], s));
         HIPCHK(c, hipEventRecord(ev[2], s));
-        HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], t.lanes[ST_SEG], s));
+        HIPCHK(c, launch_seg(c->E, c->M, c->K, t.grid[ST_SEG], t.lanes[ST_SEG], seg_share(c), s));
         HIPCHK(c, hipEventRecord(ev[3], s));
         HIPCHK(c, launch_t3(c->E, c->M, c->K, t.grid[ST_T3], t.lanes[ST_T3], s));
         HIPCHK(c, hipEventRecord(ev[4], s));

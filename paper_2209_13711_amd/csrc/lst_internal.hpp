@@ -181,8 +181,11 @@ hipError_t sort_ev_prepare(int n_mod);   // allows the per-event sort's LDS size
 // lanes: width of the lane group that owns one inner object (8, 16, 32 or 64)
 hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
                      hipStream_t s);
+// share: the kernel whose runs of inner MDs of one module share their
+// candidate enumeration when a wave takes consecutive MDs (batches); the
+// other enumerates per MD (one event, whose one-pass order spreads the MDs)
 hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
-                      hipStream_t s);
+                      bool share, hipStream_t s);
 hipError_t launch_t3(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
                      hipStream_t s);
 hipError_t launch_t5(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,

@@ -591,6 +591,7 @@ struct SegQ {
     int32_t o[SEGQ], o2[SEGQ];        // window survivors; angle survivors
     int32_t mark[64];                 // chunk_src
     uint8_t g[SEGQ], g2[SEGQ];
+    uint8_t nf[MAXP];                 // groups sharing a leading group's candidates
 };
 
 // mini-doublet stage: accepted pairs and their window outputs staged until
@@ -872,7 +873,7 @@ hipError_t launch_md(const EvDev &E, const ModDev &M, const Consts &K, int grid,
 // the enumeration order, so accepted pairs get, per inner MD, consecutive
 // positions in that order.  sink(g, ok, o, pos): g is the group of the
 // pair's inner MD.
-template <int G, class F>
+template <int G, bool SHARE, class F>
 __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, const Consts &K,
                                              int32_t i, bool act, SegQ &q, F &&sink)
 {
@@ -880,11 +881,10 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
     const Grp<G> gp;
     const Grp<64> gw;
     const uint32_t l = (uint32_t)lane_id();
-    int32_t ne = 0;
+    int4 nb = make_int4(-1, 0, -1, 0);
     if (act) {
-        const int4 nb = E.md_nbr[i];
+        nb = E.md_nbr[i];
         const int32_t e0 = nb.x;
-        ne = nb.y;
         if (gp.lane == 0) {
             const float4 p0 = E.md_p0[i], p1 = E.md_p1[i], p2 = E.md_p2[i];
             q.ip[gp.g] = p0;
@@ -895,13 +895,47 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
             q.eb[gp.g] = make_int2(e0, nb.z);
         }
     }
-    // the wave's (inner MD, map edge) pairs as one list in group order:
-    // pre[g] = edges of the groups before g
+    // Groups whose inner MDs lie in one module (next to each other in the
+    // regions) have the same candidates: the first of a run of such groups
+    // enumerates them and each candidate is tested against every MD of the
+    // run.  A module is keyed by its map row and its event.
+    // (SHARE: the wave's inner MDs are consecutive in their region, else
+    // they come from distant parts of it and every group leads)
+    uint32_t ne_of[P];
+    int nmax = 1;
+    if constexpr (SHARE) {
+        int lead[P], nfol[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int32_t kx = __builtin_amdgcn_readlane(nb.x, p * G);
+            const int32_t ky = __builtin_amdgcn_readlane(nb.y, p * G);
+            const int32_t kz = __builtin_amdgcn_readlane(nb.z, p * G);
+            lead[p] = p;
+            if (p > 0 && kx >= 0 && kx == __builtin_amdgcn_readlane(nb.x, (p - 1) * G) &&
+                ky == __builtin_amdgcn_readlane(nb.y, (p - 1) * G) &&
+                kz == __builtin_amdgcn_readlane(nb.z, (p - 1) * G))
+                lead[p] = lead[p - 1];
+            ne_of[p] = lead[p] == p ? (uint32_t)ky : 0u;
+            nfol[p] = 0;
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+#pragma unroll
+            for (int r = 0; r < P; ++r)
+                if (lead[r] == p) ++nfol[p];
+            nmax = nfol[p] > nmax ? nfol[p] : nmax;
+            if (l == 0) q.nf[p] = (uint8_t)nfol[p];
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < P; ++p) ne_of[p] = (uint32_t)__builtin_amdgcn_readlane(nb.y, p * G);
+    }
+    // the wave's (leading inner MD, map edge) pairs as one list in group
+    // order: pre[g] = edges of the groups before g
     uint32_t pre[P + 1];
     pre[0] = 0;
 #pragma unroll
-    for (int p = 0; p < P; ++p)
-        pre[p + 1] = pre[p] + (uint32_t)__builtin_amdgcn_readlane(ne, p * G);
+    for (int p = 0; p < P; ++p) pre[p + 1] = pre[p] + ne_of[p];
     const uint32_t n_edges = pre[P];
     uint32_t cnt[P];
 #pragma unroll
@@ -1021,19 +1055,23 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
                     b1 = E.md_p1[on];
                 }
             }
-            bool win = false;
-            if (live) {
-                const float4 w0 = q.w0[g], w1 = q.w1[g];
-                win = seg_window(K, w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, a0, a1);
+            // the candidate against each inner MD of its run of groups
+            const int nf = live ? (SHARE ? (int)q.nf[g] : 1) : 0;
+            for (int k = 0; k < (SHARE ? nmax : 1); ++k) {
+                bool win = false;
+                if (k < nf) {
+                    const float4 w0 = q.w0[g + k], w1 = q.w1[g + k];
+                    win = seg_window(K, w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, a0, a1);
+                }
+                const unsigned long long mk = __ballot(win);
+                if (win) {
+                    const uint32_t s = (tail + (uint32_t)__popcll(mk & below)) & (SEGQ - 1);
+                    q.o[s] = o;
+                    q.g[s] = (uint8_t)(g + k);
+                }
+                tail += (uint32_t)__popcll(mk);
+                if (tail - head >= 64) drain(64);
             }
-            const unsigned long long mk = __ballot(win);
-            if (win) {
-                const uint32_t s = (tail + (uint32_t)__popcll(mk & below)) & (SEGQ - 1);
-                q.o[s] = o;
-                q.g[s] = (uint8_t)g;
-            }
-            tail += (uint32_t)__popcll(mk);
-            if (tail - head >= 64) drain(64);
             o = on;
             g = gn;
             live = ln;
@@ -1050,7 +1088,10 @@ __device__ __forceinline__ uint32_t enum_seg(const EvDev &E, const ModDev &M, co
     return c;
 }
 
-template <int G>
+// SHARE: runs of inner MDs of one module may share their candidate
+// enumeration (when the order is consecutive); else every group enumerates
+// its own (the single-event kernel, whose one-pass order spreads the MDs)
+template <int G, bool SHARE>
 __device__ __forceinline__ void seg_body(const EvDev &E, const ModDev &M, const Consts &K, SmSeg &sm)
 {
     if (upstream_overflow(E)) return;
@@ -1075,10 +1116,17 @@ __device__ __forceinline__ void seg_body(const EvDev &E, const ModDev &M, const 
         const uint32_t v = spread ? (uint32_t)gp.g * nslot + u : u * P + (uint32_t)gp.g;
         const bool act = u < nslot && v < R.total;
         const int32_t i = region_index_x(R, act ? v : 0);
-        const uint32_t cnt = enum_seg<G>(E, M, K, i, act, q,
-                                         [&](int g, bool ok, int32_t o, uint32_t pos) {
+        auto stage = [&](int g, bool ok, int32_t o, uint32_t pos) {
             if (ok && pos < CAP) sm.o[w][g * CAP + pos] = o;
-        });
+        };
+        // consecutive inner MDs (several passes): runs of one module share
+        // their candidate enumeration
+        uint32_t cnt;
+        if constexpr (SHARE)
+            cnt = spread ? enum_seg<G, false>(E, M, K, i, act, q, stage)
+                         : enum_seg<G, true>(E, M, K, i, act, q, stage);
+        else
+            cnt = enum_seg<G, false>(E, M, K, i, act, q, stage);
         uint32_t wtot;
         const uint32_t gex = gp.wave_prefix(cnt, wtot);
         bool ovf;
@@ -1100,13 +1148,20 @@ __device__ __forceinline__ void seg_body(const EvDev &E, const ModDev &M, const 
                 q.idx[gp.g] = i;
                 q.off[gp.g] = (int32_t)off;
             }
-            enum_seg<G>(E, M, K, i, act && cnt > CAP, q,
-                        [&](int g, bool ok, int32_t o, uint32_t pos) {
+            auto direct = [&](int g, bool ok, int32_t o, uint32_t pos) {
                 if (ok) {
                     E.seg_in[q.off[g] + pos] = q.idx[g];
                     E.seg_out[q.off[g] + pos] = o;
                 }
-            });
+            };
+            if constexpr (SHARE) {
+                if (spread)
+                    enum_seg<G, false>(E, M, K, i, act && cnt > CAP, q, direct);
+                else
+                    enum_seg<G, true>(E, M, K, i, act && cnt > CAP, q, direct);
+            } else {
+                enum_seg<G, false>(E, M, K, i, act && cnt > CAP, q, direct);
+            }
         }
     }
 }
@@ -1115,13 +1170,24 @@ template <int G>
 __global__ __launch_bounds__(BLOCK, 6) void k_seg(EvDev E, ModDev M, Consts K)
 {
     __shared__ SmSeg sm;
-    seg_body<G>(E, M, K, sm);
+    seg_body<G, false>(E, M, K, sm);
+}
+
+template <int G>
+__global__ __launch_bounds__(BLOCK, 6) void k_seg_share(EvDev E, ModDev M, Consts K)
+{
+    __shared__ SmSeg sm;
+    seg_body<G, true>(E, M, K, sm);
 }
 
 hipError_t launch_seg(const EvDev &E, const ModDev &M, const Consts &K, int grid, int lanes,
-                      hipStream_t s)
+                      bool share, hipStream_t s)
 {
-    LST_BY_LANES(lanes, k_seg, dim3(xcd_grid(grid)), dim3(BLOCK), 0, s, E, M, K);
+    if (share) {
+        LST_BY_LANES(lanes, k_seg_share, dim3(xcd_grid(grid)), dim3(BLOCK), 0, s, E, M, K);
+    } else {
+        LST_BY_LANES(lanes, k_seg, dim3(xcd_grid(grid)), dim3(BLOCK), 0, s, E, M, K);
+    }
     return hipGetLastError();
 }
 
@@ -1745,7 +1811,7 @@ __global__ __launch_bounds__(BLOCK) void k_chain(EvDev E, ModDev M, Consts K, ui
     LST_SYNC();
     md_body<G>(E, M, K, sm.u.md);
     LST_SYNC();
-    seg_body<G>(E, M, K, sm.u.seg);
+    seg_body<G, false>(E, M, K, sm.u.seg);
     LST_SYNC();
     t3_body<G>(E, K, sm.u.t3);
     if (stop == PERS_TO_T3) return;
