@@ -29,15 +29,32 @@ MLP_FLOPS = 2 * (40 * 64 + 64 * 64 + 64)
 TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 
 
-def kernel_source_digest():
-    """Digest of the kernel sources; counter figures taken from an older
-    source are not reported."""
+KERNEL_SOURCES = ("lst_kernels.hip", "lst_cuts.hpp", "lst_internal.hpp", "lst_access.hpp")
+
+
+def code_digest(texts):
+    """Digest of C++ sources with comments, trailing blanks and empty lines
+    removed: a comment edit keeps it, any code edit changes it."""
     import hashlib
+    import re
     h = hashlib.sha256()
-    for f in ("lst_kernels.hip", "lst_cuts.hpp", "lst_internal.hpp", "lst_access.hpp"):
-        with open(os.path.join(ROOT, "paper_2209_13711_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for text in texts:
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+        h.update(code.encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
+
+
+def kernel_source_digest():
+    """Digest of the kernel code; counter figures taken from other kernel
+    code are not reported."""
+    texts = []
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2209_13711_amd", "csrc", f), encoding="utf-8") as fh:
+            texts.append(fh.read())
+    return code_digest(texts)
 
 
 def measured_traffic(kernel):

@@ -1,17 +1,22 @@
 // Stage kernels of the Segment Linking chain for gfx950 (wave64).
 //
-// Work decomposition of the object stages: one wavefront owns one inner
-// object (a module slot for mini-doublets, an inner mini-doublet for
-// segments, triplets and quintuplets) and evaluates that object's candidate
-// combinations 64 at a time, one per lane.  Candidate lists that are
-// concatenations of several groups (map edges, outgoing segments, outgoing
-// triplets) are flattened with a wave-wide inclusive scan of the group sizes;
-// a lane finds its group by a binary search over that scan held in
-// registers (cross-lane reads, no LDS).  Accepted objects are compacted with
-// ballot + popcount into an LDS staging buffer; the block then reserves its
-// whole output range with one atomic on one of NSH shard counters, and each
-// wave copies its staged objects out.  Kernels are grid-stride over the inner
-// objects, whose number is only known on the device.
+// Work decomposition of the object stages: a wavefront takes P inner
+// objects per round (module slots for mini-doublets, inner mini-doublets for
+// segments, triplets and quintuplets; a group of G = 64 / P lanes, or one
+// lane, sets each up) and walks all their candidate combinations as one
+// list, 64 at a time, one per lane.  Candidate lists that are
+// concatenations of several ranges (map edges, outgoing segments, outgoing
+// triplets) are flattened with a wave-wide inclusive scan of the range
+// sizes, and a lane finds its range from that scan with cross-lane reads.
+// Accepted objects are compacted with ballot + popcount into an LDS staging
+// buffer; the wave then reserves its output range with one atomic on one of
+// the shard counters of its XCD sector and copies its staged objects out.
+// Kernels are grid-stride over the inner objects, whose number is only
+// known on the device.  When the grid covers a sector in one pass the
+// sector's inner objects are spread over the waves (heavy modules do not
+// pile up in one wave); otherwise consecutive objects go together, and on
+// batches the segment stage enumerates the candidates of a run of MDs of
+// one module once.
 //
 // Why not one global counter: device-scope atomics on one address are
 // serialised across the chip (measured ~0.1 us apiece through 16 counters),

@@ -55,6 +55,14 @@ def test_layout_bytes_follow_the_library_layouts():
                "n_t3": (0, 0, 17, 17), "n_t5": (0, 0, 0, 25)}, (68, 8), 4)
 
 
+def test_code_digest_ignores_comments_only():
+    src = "int f(int x)\n{\n    return x + 1;   // one more\n}\n"
+    d = bench.code_digest([src])
+    assert bench.code_digest(["/* a note */\nint f(int x)\n{\n\n    return x + 1;\n}\n"]) == d
+    assert bench.code_digest([src.replace("x + 1", "x + 2")]) != d
+    assert bench.code_digest([src, ""]) != d                  # file boundaries count
+
+
 def test_traffic_is_read_only_for_the_current_kernel_source(tmp_path, monkeypatch):
     digest = bench.kernel_source_digest()
     assert len(digest) == 16
