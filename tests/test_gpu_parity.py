@@ -313,6 +313,31 @@ def test_one_pass_and_many_pass_orders_match_oracle(lanes):
         assert_parity(ctx.run_event(ev), ref)
 
 
+@pytest.mark.parametrize("lanes", [8, 16])
+def test_batch_shared_segment_enumeration_matches_oracle(lanes):
+    """Arenas of several events use the segment kernel whose runs of inner MDs
+    of one module share their candidates; with a grid of 8 blocks every wave
+    takes consecutive MDs, so runs of one module are common.  Two PU200-like
+    events (one of them with 2500 tracks) in one batch against the oracle,
+    then the same batch with a one-pass grid (spread order, nothing
+    shared)."""
+    params = PR.make()
+    geo = G.get("full")
+    orc = oracle.Oracle(params, geo.f32, geo.i32)
+    evs = [E.generate(2, 6), E.generate(2, 7, n_tracks=2500)]
+    b = E.concat(evs)
+    ctx = _ctx(geo, params)
+    ctx.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+    t = ctx.tuning()
+    widths = [64, lanes, lanes, lanes, lanes, 64]
+    for g in (8, 8192):
+        print(f"case lanes {lanes} batch of 2 object-stage grid {g}", flush=True)
+        ctx.set_tuning([t["grid"][0], g, g, g, g, t["grid"][5]], persistent=0, blocks_per_cu=1,
+                       lanes=widths)
+        ctx.run_batch(b.offsets, b.x, b.y, b.z, b.module, b.sensor)
+        _batch_parity(ctx, evs, orc)
+
+
 def test_autotuner_keeps_results_and_caches(tmp_path):
     geo = G.get("barrel_toy")
     params = PR.make()
