@@ -114,7 +114,9 @@ def _grads_gpu(ctx, P, x, y):
     return grad.cpu().numpy(), float(loss.cpu().numpy()[0])
 
 
-@pytest.mark.parametrize("n", [1, 1000, 4096])
+# 5000 rows: 79 batches of 64 in 64 chunks of two batches each (the last
+# batch ragged, the last 24 chunks empty)
+@pytest.mark.parametrize("n", [1, 1000, 4096, 5000])
 def test_backward_matches_oracle(ctx_toy, n):
     print(f"case backward n={n}", flush=True)
     rng = np.random.default_rng(200 + n)
