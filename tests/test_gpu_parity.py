@@ -313,7 +313,7 @@ def test_one_pass_and_many_pass_orders_match_oracle(lanes):
         assert_parity(ctx.run_event(ev), ref)
 
 
-@pytest.mark.parametrize("lanes", [8, 16])
+@pytest.mark.parametrize("lanes", [8, 16, 32])
 def test_batch_shared_segment_enumeration_matches_oracle(lanes):
     """Arenas of several events use the segment kernel whose runs of inner MDs
     of one module share their candidates; with a grid of 8 blocks every wave
